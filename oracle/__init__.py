@@ -1,0 +1,272 @@
+"""ctypes wrapper of the FP64 CPU oracle (oracle/pic_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by __graft_entry__.smoke() and by the
+CPU-baseline leg of bench.py.  The product package never imports it.  Parity unpinned
+items are listed in the header of pic_oracle.c's companion notes in the design document.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "libpic_oracle.so")
+
+FIELDS = ["Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "Exo", "Eyo", "Ezo",
+          "Exb", "Eyb", "Ezb", "Byx", "Eyx", "Bxo", "Byo", "Bzo"]
+FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
+
+
+def build(force: bool = False) -> str:
+    src = os.path.join(_HERE, "pic_oracle.c")
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(src):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Cfg(C.Structure):
+    _fields_ = [("nx", C.c_int), ("nz", C.c_int), ("dx_um", C.c_double), ("dz_um", C.c_double),
+                ("pml_cells", C.c_int), ("periodic_x", C.c_int), ("periodic_z", C.c_int),
+                ("ck_alpha", C.c_double), ("ck_beta", C.c_double), ("ck_gamma", C.c_double),
+                ("theta", C.c_double), ("cfl_fraction", C.c_double), ("filter_npass", C.c_int),
+                ("filter_compensate", C.c_int), ("gamma_boost", C.c_double),
+                ("moving_window", C.c_int), ("seed", C.c_uint64)]
+
+
+class _Plasma(C.Structure):
+    _fields_ = [("n0_cm3", C.c_double), ("ramp_um", C.c_double), ("start_um", C.c_double),
+                ("ppc", C.c_int), ("ion_mode", C.c_int)]
+
+
+class _Laser(C.Structure):
+    _fields_ = [("lambda_um", C.c_double), ("a0", C.c_double), ("waist_um", C.c_double),
+                ("fwhm_fs", C.c_double), ("z_antenna_um", C.c_double)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("dt", C.c_double), ("dt_crit", C.c_double), ("beta", C.c_double),
+                ("gamma", C.c_double), ("v_window", C.c_double), ("n0_norm", C.c_double),
+                ("e0_norm", C.c_double), ("omega", C.c_double), ("alpha2", C.c_double),
+                ("beta2", C.c_double), ("antenna_weight", C.c_double), ("stored_x", C.c_int),
+                ("stored_z", C.c_int), ("pml_x", C.c_int), ("pml_z", C.c_int),
+                ("step", C.c_long), ("time", C.c_double), ("shift", C.c_long),
+                ("next_row", C.c_long)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        P = C.c_void_p
+        D = C.POINTER(C.c_double)
+        U = C.POINTER(C.c_uint32)
+        _lib.orc_create.restype = P
+        _lib.orc_create.argtypes = [C.POINTER(_Cfg)]
+        _lib.orc_destroy.argtypes = [P]
+        _lib.orc_init_plasma.argtypes = [P, C.POINTER(_Plasma)]
+        _lib.orc_init_laser.argtypes = [P, C.POINTER(_Laser)]
+        _lib.orc_add_station.argtypes = [P, C.c_double, C.c_int]
+        _lib.orc_step.argtypes = [P, C.c_int]
+        for n in ["faraday", "stations", "particles", "filter", "ampere", "advance"]:
+            getattr(_lib, "orc_stage_" + n).argtypes = [P]
+        _lib.orc_get_info.argtypes = [P, C.POINTER(_Info)]
+        _lib.orc_cfl_2d.restype = C.c_double
+        _lib.orc_cfl_2d.argtypes = [C.c_double] * 6
+        _lib.orc_cfl_3d.restype = C.c_double
+        _lib.orc_cfl_3d.argtypes = [C.c_double] * 7
+        _lib.orc_get_field.argtypes = [P, C.c_int, D]
+        _lib.orc_set_field.argtypes = [P, C.c_int, D]
+        _lib.orc_num_particles.restype = C.c_long
+        _lib.orc_num_particles.argtypes = [P, C.c_int]
+        _lib.orc_get_particles.argtypes = [P, C.c_int, U, D, D, D, D, D, D]
+        _lib.orc_set_electrons.argtypes = [P, C.c_long, U, D, D, D, D, D, D]
+        _lib.orc_set_ions.argtypes = [P, C.c_long, U, D, D, D]
+        _lib.orc_get_antenna.argtypes = [P, D]
+        _lib.orc_set_antenna.argtypes = [P, D]
+        _lib.orc_set_clock.argtypes = [P, C.c_long, C.c_double, C.c_long, C.c_long]
+        _lib.orc_energy.argtypes = [P, D]
+        _lib.orc_gauss_residual.argtypes = [P, D]
+        _lib.orc_charge_density.argtypes = [P, D]
+        _lib.orc_station_samples.restype = C.c_long
+        _lib.orc_station_samples.argtypes = [P, C.c_int, D, C.c_long]
+        _lib.orc_shape3.restype = C.c_double
+        _lib.orc_shape3.argtypes = [C.c_double]
+        _lib.orc_boris.argtypes = [C.c_double, C.c_double, D, D, D]
+        _lib.orc_deposit_one.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_double,
+                                         C.c_double, C.c_double, C.c_double]
+        _lib.orc_splitmix64.restype = C.c_uint64
+        _lib.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _up(a):
+    return a.ctypes.data_as(C.POINTER(C.c_uint32))
+
+
+class Oracle:
+    """One FP64 reference simulation."""
+
+    def __init__(self, config: dict):
+        L = lib()
+        c = _Cfg(**{k: config[k] for k, _ in _Cfg._fields_})
+        self._h = L.orc_create(C.byref(c))
+        if not self._h:
+            raise ValueError("oracle rejected the configuration")
+        self.config = dict(config)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().orc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- set-up -------------------------------------------------------------------
+    def init_plasma(self, p: dict):
+        if lib().orc_init_plasma(self._h, C.byref(_Plasma(**p))) != 0:
+            raise ValueError("bad plasma")
+
+    def init_laser(self, l: dict):
+        if lib().orc_init_laser(self._h, C.byref(_Laser(**l))) != 0:
+            raise ValueError("bad laser")
+
+    def add_station(self, z_lab_um: float, capacity: int = 100000) -> int:
+        return lib().orc_add_station(self._h, z_lab_um, capacity)
+
+    @classmethod
+    def from_workload(cls, w: dict, laser=True, plasma=True, stations=()):
+        o = cls(w["config"])
+        if plasma and w.get("plasma"):
+            o.init_plasma(w["plasma"])
+        if laser and w.get("laser"):
+            o.init_laser(w["laser"])
+        for z in stations:
+            o.add_station(z)
+        return o
+
+    # ---- stepping -----------------------------------------------------------------
+    def step(self, n: int = 1):
+        lib().orc_step(self._h, n)
+
+    def stage(self, name: str):
+        getattr(lib(), "orc_stage_" + name)(self._h)
+
+    # ---- access -------------------------------------------------------------------
+    def info(self) -> dict:
+        i = _Info()
+        lib().orc_get_info(self._h, C.byref(i))
+        return {k: getattr(i, k) for k, _ in _Info._fields_}
+
+    @property
+    def shape(self):
+        i = self.info()
+        return (i["stored_z"], i["stored_x"])
+
+    def field(self, name: str) -> np.ndarray:
+        out = np.zeros(self.shape, dtype=np.float64)
+        lib().orc_get_field(self._h, FIELD_ID[name], _dp(out))
+        return out
+
+    def set_field(self, name: str, arr: np.ndarray):
+        a = np.ascontiguousarray(arr, dtype=np.float64).reshape(self.shape)
+        lib().orc_set_field(self._h, FIELD_ID[name], _dp(a))
+
+    def num_particles(self, species: int = 0) -> int:
+        return lib().orc_num_particles(self._h, species)
+
+    def particles(self, species: int = 0) -> dict:
+        n = self.num_particles(species)
+        d = {k: np.zeros(n, dtype=np.float64) for k in ["x", "z", "ux", "uy", "uz", "w"]}
+        d["id"] = np.zeros(n, dtype=np.uint32)
+        lib().orc_get_particles(self._h, species, _up(d["id"]), _dp(d["x"]), _dp(d["z"]),
+                                _dp(d["ux"]), _dp(d["uy"]), _dp(d["uz"]), _dp(d["w"]))
+        return d
+
+    def set_electrons(self, p: dict):
+        n = len(p["x"])
+        arr = {k: np.ascontiguousarray(p[k], dtype=np.float64) for k in ["x", "z", "ux", "uy", "uz", "w"]}
+        ids = np.ascontiguousarray(p["id"], dtype=np.uint32)
+        lib().orc_set_electrons(self._h, n, _up(ids), _dp(arr["x"]), _dp(arr["z"]), _dp(arr["ux"]),
+                                _dp(arr["uy"]), _dp(arr["uz"]), _dp(arr["w"]))
+
+    def set_ions(self, ids, x, z0, w):
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        x, z0, w = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, z0, w))
+        lib().orc_set_ions(self._h, len(x), _up(ids), _dp(x), _dp(z0), _dp(w))
+
+    def antenna(self) -> np.ndarray:
+        out = np.zeros(self.config["nx"], dtype=np.float64)
+        lib().orc_get_antenna(self._h, _dp(out))
+        return out
+
+    def set_antenna(self, xm):
+        a = np.ascontiguousarray(xm, dtype=np.float64)
+        lib().orc_set_antenna(self._h, _dp(a))
+
+    def set_clock(self, step, time, shift, next_row):
+        lib().orc_set_clock(self._h, step, time, shift, next_row)
+
+    def energy(self) -> np.ndarray:
+        out = np.zeros(3)
+        lib().orc_energy(self._h, _dp(out))
+        return out
+
+    def gauss_residual(self) -> np.ndarray:
+        out = np.zeros(self.shape)
+        lib().orc_gauss_residual(self._h, _dp(out))
+        return out
+
+    def charge_density(self) -> np.ndarray:
+        out = np.zeros(self.shape)
+        lib().orc_charge_density(self._h, _dp(out))
+        return out
+
+    def station(self, q: int) -> np.ndarray:
+        n = lib().orc_station_samples(self._h, q, None, 0)
+        out = np.zeros((max(n, 0), 7))
+        if n > 0:
+            lib().orc_station_samples(self._h, q, _dp(out), n)
+        return out
+
+    def deposit_one(self, q, w, x0, z0, x1, z1, vy):
+        lib().orc_deposit_one(self._h, q, w, x0, z0, x1, z1, vy)
+
+
+def shape3(r: float) -> float:
+    return lib().orc_shape3(r)
+
+
+def boris(qm, dt, E, B, u):
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    u = np.array(u, dtype=np.float64)
+    lib().orc_boris(qm, dt, _dp(E), _dp(B), _dp(u))
+    return u
+
+
+def cfl_2d(a, b, g, dx, dz, theta=0.0):
+    return lib().orc_cfl_2d(a, b, g, dx, dz, theta)
+
+
+def cfl_3d(a, b, g, dx, dy, dz, theta=0.0):
+    return lib().orc_cfl_3d(a, b, g, dx, dy, dz, theta)
+
+
+def splitmix64(seed, k):
+    return lib().orc_splitmix64(seed, k)

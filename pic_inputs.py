@@ -1,0 +1,148 @@
+"""Workload recipes and seeded input generators shared by the tests, the benchmark, the
+HIP binding and the oracle wrapper.
+
+This module holds parameters only -- sizes, physical inputs, coefficient sets supplied by
+the user, and seeded random states for unit tests.  It contains none of the PIC method's
+arithmetic; both implementations derive everything else (time step, window speed,
+normalisation, loading) themselves.
+
+Physical inputs are in the units the C interfaces take: um, fs, cm^-3, Lorentz factor.
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+# Coefficient sets of the tunable solver, Table "CKcoefs" of Sec. 4.2.1 (alpha, beta, gamma).
+CK_SETS = {
+    "yee": (1.0, 0.0, 0.0),
+    "ck": (7.0 / 12.0, 1.0 / 12.0, 1.0 / 48.0),
+    "ck2": (19.0 / 24.0, 1.0 / 24.0, 1.0 / 96.0),
+    "ck3": (11.0 / 12.0, 1.0 / 24.0, -1.0 / 48.0),
+    "ck4": (3.0 / 4.0, 1.0 / 16.0, 0.0),
+    "ck5": (5.0 / 8.0, 3.0 / 40.0, 3.0 / 160.0),
+}
+
+LAMBDA_UM = 0.8
+
+
+def _beta(gamma: float) -> float:
+    return math.sqrt(1.0 - 1.0 / (gamma * gamma))
+
+
+def boosted_cell(gamma: float, frac: float = 1.0 / 32.0, lam: float = LAMBDA_UM) -> float:
+    """Cell size as a fixed fraction of the Doppler-stretched wavelength (1+beta) gamma lambda
+    (Sec. 5.1 keeps dz a constant fraction of the boosted laser wavelength)."""
+    return frac * (1.0 + _beta(gamma)) * gamma * lam
+
+
+def make_config(nx, nz, dx_um, dz_um, *, pml_cells=10, periodic_x=0, periodic_z=0, ck="yee",
+                theta=0.0, cfl_fraction=0.95, filter_npass=0, filter_compensate=0,
+                gamma_boost=1.0, moving_window=0, seed=1009, real="f64"):
+    a, b, g = CK_SETS[ck] if isinstance(ck, str) else ck
+    return dict(nx=int(nx), nz=int(nz), dx_um=float(dx_um), dz_um=float(dz_um),
+                pml_cells=int(pml_cells), periodic_x=int(periodic_x), periodic_z=int(periodic_z),
+                ck_alpha=a, ck_beta=b, ck_gamma=g, theta=float(theta),
+                cfl_fraction=float(cfl_fraction), filter_npass=int(filter_npass),
+                filter_compensate=int(filter_compensate), gamma_boost=float(gamma_boost),
+                moving_window=int(moving_window), seed=int(seed), real=real)
+
+
+def plasma(n0_cm3, ppc, *, ramp_um=0.0, start_um=0.0, ion_mode=0):
+    return dict(n0_cm3=float(n0_cm3), ramp_um=float(ramp_um), start_um=float(start_um),
+                ppc=int(ppc), ion_mode=int(ion_mode))
+
+
+def laser(a0, waist_um, fwhm_fs, z_antenna_um, lambda_um=LAMBDA_UM):
+    return dict(lambda_um=float(lambda_um), a0=float(a0), waist_um=float(waist_um),
+                fwhm_fs=float(fwhm_fs), z_antenna_um=float(z_antenna_um))
+
+
+# ---------------------------------------------------------------------------------------
+# Workloads
+# ---------------------------------------------------------------------------------------
+
+def c1(real="f64", nx=64, nz=512, ppc=4):
+    """2D lab frame: 64x512 Yee grid, 0.05 um cells, 4 ppc at 1e19 cm^-3 flat from z=1 um,
+    immobile ions, laser 0.8 um a0=1 waist 8 um 10 fs from z=0.5 um, CFL 0.95, one bilinear
+    pass, x periodic, 10-cell PML at the z ends, 200 steps."""
+    return dict(
+        name=f"2D lab frame {nx}x{nz}, {ppc} ppc, 1e19 cm^-3, a0=1, Yee, 1-pass bilinear",
+        config=make_config(nx, nz, 0.05, 0.05, pml_cells=10, periodic_x=1, ck="yee",
+                           theta=0.0, cfl_fraction=0.95, filter_npass=1, filter_compensate=0,
+                           gamma_boost=1.0, moving_window=0, seed=1010, real=real),
+        plasma=plasma(1e19, ppc, start_um=1.0, ion_mode=0),
+        laser=laser(1.0, 8.0, 10.0, 0.5),
+        steps=200,
+    )
+
+
+def c2(real="f32", nx=256, nz=4096, ppc=16, preload=False, gamma=13.0):
+    """2D boosted frame gamma=13: 256x4096, 16 ppc, lab density 1e18 cm^-3 with a 20 um
+    linear up-ramp starting 2 um ahead of the antenna, laser a0=2 waist 20 um, CK2 solver,
+    Friedman theta=0.1, 4 bilinear passes + compensation, 10-cell PML on every face, moving
+    window, rigid ions, 20000 steps.  preload=True fills the whole window with the plateau
+    density (throughput runs start from the filled state)."""
+    d = boosted_cell(gamma)
+    z_ant = gamma * 0.6 * nz * d              # lab position whose boosted image sits at 60%
+    start = -1e30 if preload else z_ant + 2.0
+    ramp = 0.0 if preload else 20.0
+    # laser FWHM = half a plasma wavelength at 1e18 cm^-3 (lambda_p = 33.39 um)
+    fwhm = 0.5 * 33.39 / 0.299792458
+    return dict(
+        name=(f"2D boosted gamma={gamma:g} {nx}x{nz}, {ppc} ppc, 1e18 cm^-3"
+              f"{' (pre-loaded window)' if preload else ''}, a0=2, CK2 + Friedman 0.1,"
+              " 4-pass bilinear + compensation, 10-cell PML, moving window"),
+        config=make_config(nx, nz, d, d, pml_cells=10, periodic_x=0, ck="ck2", theta=0.1,
+                           cfl_fraction=0.95, filter_npass=4, filter_compensate=1,
+                           gamma_boost=gamma, moving_window=1, seed=1011, real=real),
+        plasma=plasma(1e18, ppc, ramp_um=ramp, start_um=start, ion_mode=1),
+        laser=laser(2.0, 20.0, fwhm, z_ant),
+        steps=20000,
+    )
+
+
+def small_lab(real="f64", nx=24, nz=96, ppc=4, seed=77, npass=1, comp=0, ck="yee", theta=0.0):
+    """A C1-shaped lab-frame case the oracle finishes in seconds (several tiles + ragged tail)."""
+    w = c1(real, nx=nx, nz=nz, ppc=ppc)
+    w["config"].update(make_config(nx, nz, 0.05, 0.05, pml_cells=10, periodic_x=1, ck=ck,
+                                   theta=theta, filter_npass=npass, filter_compensate=comp,
+                                   seed=seed, real=real))
+    w["name"] = f"small lab {nx}x{nz}"
+    return w
+
+
+def small_boosted(real="f64", nx=40, nz=150, ppc=4, seed=78, gamma=13.0, preload=False):
+    """A C2-shaped boosted case (window, PML on all faces, CK2 + Friedman, 4+comp filter,
+    rigid ions, antenna) small enough for the oracle."""
+    w = c2(real, nx=nx, nz=nz, ppc=ppc, preload=preload, gamma=gamma)
+    w["config"]["seed"] = seed
+    w["name"] = f"small boosted {nx}x{nz}"
+    return w
+
+
+def copy_workload(w):
+    return copy.deepcopy(w)
+
+
+# ---------------------------------------------------------------------------------------
+# Seeded random states for unit tests
+# ---------------------------------------------------------------------------------------
+
+def random_electrons(n, nx, nz, dx, dz, seed, umax=1.0, margin=3.0):
+    """n electrons uniformly placed at least `margin` cells inside the interior, with
+    momenta uniform in [-umax, umax]^3 and weights in [0.5, 1.5] x 1e-3."""
+    r = np.random.default_rng(seed)
+    x = (margin + r.random(n) * (nx - 2 * margin)) * dx
+    z = (margin + r.random(n) * (nz - 2 * margin)) * dz
+    u = (2.0 * r.random((3, n)) - 1.0) * umax
+    w = (0.5 + r.random(n)) * 1e-3
+    ids = np.arange(n, dtype=np.uint32)
+    return dict(id=ids, x=x, z=z, ux=u[0], uy=u[1], uz=u[2], w=w)
+
+
+def random_field(shape, seed, amp=0.1):
+    r = np.random.default_rng(seed)
+    return amp * (2.0 * r.random(shape) - 1.0)
