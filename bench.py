@@ -1,0 +1,213 @@
+#!/usr/bin/env python
+"""Throughput of the boosted-frame laser-wakefield PIC step on one MI355X.
+
+Workload (default): 2D boosted frame gamma = 13, 256 x 4096 cells, 16 macro-electrons per
+cell at 1e18 cm^-3 (lab) with rigid ions, window pre-loaded with plasma (steady state of the
+moving window), laser a0 = 2 w0 = 20 um through the lab-fixed antenna, CK2 solver with
+Friedman theta = 0.1, 4 bilinear passes + compensation, 10-cell PML on every face, moving
+window, FP32 fields/momenta with FP64 positions.  Inputs are synthetic and seeded.
+
+One step = the whole PIC step of the library (Faraday, push, ions, antenna, filter, Ampere,
+window/injection, periodic tile sort).  Prints ONE JSON line with the metric, the roofline of
+the dominant kernel (gather/push/deposit, timed with HIP events on the library's stream) and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
+PMC_FILE = os.path.join(ROOT, "profiles", "gpd_c2_pmc.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1009_2727_amd", "csrc", "bf_particles.hip")
+
+
+def src_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1009_2727_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def bytes_model(ne: int, ni: int, nx: int, nz: int, real: int = 4):
+    """Algorithmic HBM bytes.  Per electron (2D, FP32 momenta, FP64 positions): read x,z
+    (16) + u (12) + w (4), write x,z,u (28) = 60 B.  Per rigid ion: read x, z0 (16) + w (4) =
+    20 B.  Per interior cell and step: 51 words (Faraday+Friedman 12 read / 6 write, gather 9
+    read, deposit flush 3 write, J clear 3, filter 3+3, Ampere 9 read / 3 write).  The
+    gather/push/deposit kernel alone moves its particles plus the 9 staged field words and
+    the 3 flushed current words per cell."""
+    cells = nx * nz
+    gpd = ne * (32 + 28) + cells * 12 * real
+    step = ne * 60 + ni * 20 + cells * 51 * real
+    return gpd, step
+
+
+def cpu_baseline(args):
+    """FP64 oracle on a bounded sample of the workload: a 256 x 256 slab of the same
+    physics (16 ppc, pre-loaded), a few steps, single thread."""
+    import pic_inputs as pi
+    from oracle import Oracle
+    w = pi.c2(real="f64", nx=256, nz=256, ppc=16, preload=True)
+    o = Oracle.from_workload(w)
+    ne = o.num_particles(0)
+    o.step(1)       # first step outside the timing (allocations)
+    t0 = time.perf_counter()
+    o.step(args.cpu_steps)
+    dt = time.perf_counter() - t0
+    return {"value": ne * args.cpu_steps / dt, "unit": "particle pushes/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"256x256 slab of the same workload, 16 ppc pre-loaded ({ne} electrons), "
+                      f"{args.cpu_steps} steps after one untimed step, FP64, single thread"}
+
+
+def read_pmc():
+    if not os.path.exists(PMC_FILE):
+        return None
+    try:
+        d = json.load(open(PMC_FILE))
+    except Exception:
+        return None
+    if d.get("source_hash") != src_hash():
+        return None          # kernels changed since the counters were taken
+    return d
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, copy_bytes: int, out: str):
+    """Reduces two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) to per-launch HBM bytes
+    of the gather/push/deposit kernel, scaled by what the counters read for a plain device
+    copy of copy_bytes in the same process."""
+    import csv
+
+    def load(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r.get("Counter_Name") == counter:
+                        rows.append((r.get("Kernel_Name", ""), float(r["Counter_Value"])))
+        return rows
+
+    res = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = load(d, counter)
+        gpd = [v for k, v in rows if "k_gpd" in k]
+        copies = [v for k, v in rows if ("copy" in k.lower() or "elementwise" in k.lower()) and v > 0]
+        if not gpd or not copies:
+            raise SystemExit(f"no {counter} rows for k_gpd / copy in {d}")
+        cal = max(copies) * 1024.0 / copy_bytes     # counter KiB vs true bytes
+        res[counter] = {"gpd_kib_per_launch": sum(gpd) / len(gpd), "copy_kib": max(copies),
+                        "calibration": cal,
+                        "gpd_bytes_per_launch": sum(gpd) / len(gpd) * 1024.0 / cal}
+    res["source_hash"] = src_hash()
+    res["traffic_bytes_per_launch"] = (res["FETCH_SIZE"]["gpd_bytes_per_launch"]
+                                       + res["WRITE_SIZE"]["gpd_bytes_per_launch"])
+    json.dump(res, open(out, "w"), indent=1)
+    print(json.dumps(res))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--sort-every", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="run a plain device copy of this size first (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_GIB"))
+    args = ap.parse_args()
+
+    if args.summarize_pmc:
+        f, wdir, gib = args.summarize_pmc
+        summarize_pmc(f, wdir, int(float(gib) * 2 ** 30), PMC_FILE)
+        return
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU: the boosted-frame PIC hot path is "
+                          "measured on one MI355X (multi-GPU sharding is described, not built)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import pic_inputs as pi
+    from paper_1009_2727_amd import Sim
+
+    if args.calib_copy_gib > 0:
+        n = int(args.calib_copy_gib * 2 ** 30)
+        src = torch.empty(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    w = pi.c2(real="f32", preload=True)
+    cfg = w["config"]
+    sim = Sim.from_workload(w, sort_every=args.sort_every, timers=True)
+    stream = sim.stream
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    c0 = sim.counts()
+    sim.timers(reset=True)
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    sim.step(args.steps)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms = t_start.elapsed_time(t_end)
+    status = sim.sync_status()
+    c1 = sim.counts()
+    timers = sim.timers(reset=True)
+    ne = 0.5 * (c0[0] + c1[0])
+    ni = 0.5 * (c0[1] + c1[1])
+    ms_step = ms / args.steps
+    value = ne * args.steps / (ms / 1e3)
+    gpd_bytes, step_bytes = bytes_model(int(ne), int(ni), cfg["nx"], cfg["nz"])
+    push_ms, push_n = timers["push"]
+    gpd_ms = push_ms / max(push_n, 1)
+    achieved = gpd_bytes / (gpd_ms / 1e3) / 1e9
+    pmc = read_pmc()
+    traffic = pmc["traffic_bytes_per_launch"] if pmc else None
+
+    out = {
+        "metric": "particle pushes/s",
+        "value": value,
+        "unit": "electron pushes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "grid": f"{cfg['nx']}x{cfg['nz']}", "ppc": 16,
+                   "gamma_boost": cfg["gamma_boost"], "electrons": int(ne), "rigid_ions": int(ni),
+                   "positions": "f64", "sort_every": sim.info()["sort_every"],
+                   "status": status},
+        "hbm_gbps_per_step": step_bytes / (ms_step / 1e3) / 1e9,
+        "phases_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in timers.items()},
+        "roofline": {"bound": "hbm", "kernel": "k_gpd (gather + push + deposit)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": gpd_bytes, "avg_launch_ms": gpd_ms},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,232 @@
+/*
+ * bfpic.h -- C ABI of the MI355X (gfx950) boosted-frame laser-wakefield PIC library.
+ *
+ * The calls follow the way the paper (Vay, Geddes, Cormier-Michel, Grote, arXiv:1009.2727)
+ * states the problem: choose the frame (Sec. 2, boosted quantities), give the plasma
+ * (Table "Tablephyspar2d": density, length, entrance ramp) and the laser emitted through a
+ * plane (Sec. 3.1.2), give the numerical parameters (tunable solver Table "CKcoefs",
+ * Friedman theta Sec. 4.3, filter passes and compensation Sec. 4.1, PML Appendix II, time
+ * step at a fraction of the CFL limit Eq. cfl), step, and collect lab-frame outputs through
+ * stations (Sec. 3.2), fields and particles.
+ *
+ * Conventions
+ *  - Geometry: 2-1/2D, the plane (x, z), z the boost and laser axis.  Interior cells
+ *    nx * nz; every non-periodic face carries a split-field PML of pml_cells cells.
+ *  - Units at the boundary: lengths in um, durations in fs, densities in cm^-3, laser and
+ *    plasma always given in the LAB frame (the library applies the boost).
+ *  - Ownership: the caller owns every device byte.  bf_query_buffers() lists the device
+ *    buffers a configuration needs (name, size, alignment); the caller allocates each
+ *    (e.g. torch.empty on the HIP device) and passes them to bf_create().  The library never
+ *    allocates or frees device memory; bf_destroy() frees host metadata only.  Buffers must
+ *    stay valid until bf_destroy().  Host pointers passed to the other calls are only read
+ *    or written during the call.
+ *  - Streams: every launch goes to the hipStream_t given to bf_create(); bf_step() is
+ *    asynchronous.  bf_diagnose(), bf_sync_status(), bf_get_state() and the particle/field
+ *    copies synchronise the stream.  A handle is not thread-safe.
+ *  - Errors: status codes only, no exceptions or aborts cross the ABI.  Device-side
+ *    conditions (particle capacity exceeded, non-finite momentum) are sticky bits reported
+ *    by the next synchronising call; after such an error the handle accepts only
+ *    bf_diagnose(), bf_get_state(), bf_last_error() and bf_destroy() (BF_ESTATE otherwise).
+ */
+#ifndef BFPIC_H
+#define BFPIC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BF_ABI_VERSION 1u
+
+typedef enum {
+    BF_OK = 0,
+    BF_EINVAL = -1,        /* malformed argument or configuration                          */
+    BF_ECFL = -2,          /* time step above the (Friedman-corrected) CFL limit           */
+    BF_ECAPACITY = -3,     /* particle or segment capacity exceeded on the device          */
+    BF_ENONFINITE = -4,    /* non-finite particle momentum detected                        */
+    BF_EDEVICE = -5,       /* HIP runtime error                                            */
+    BF_ESTATE = -6,        /* call not allowed in the handle's current state               */
+    BF_EUNSUPPORTED = -7   /* valid request this build does not implement                  */
+} bf_status;
+
+typedef struct bf_sim bf_sim;
+
+/* Simulation configuration.  abi_version must be BF_ABI_VERSION and struct_size
+   sizeof(bf_config). */
+typedef struct {
+    uint32_t abi_version, struct_size;
+    int dim;                   /* 2 (x, z plane)                                               */
+    int nx, ny, nz;            /* interior cells (ny unused in 2D)                             */
+    double dx_um, dy_um, dz_um;/* cell sizes in the calculation frame                          */
+    int real_bytes;            /* 4: FP32 fields/momenta, 8: FP64 throughout                   */
+    int shape_order;           /* 3: cubic B-spline gather and deposit (Sec. 4)                */
+    double ck_alpha, ck_beta, ck_gamma; /* tunable-solver coefficients, 3D values of Table
+                                           CKcoefs; 2D folds the y neighbours in            */
+    double friedman_theta;     /* 0 <= theta <= 1 (Sec. 4.3)                                    */
+    double cfl_fraction;       /* dt = cfl_fraction * dt*_c (Eq. cfl x sqrt((2+t)/(2+3t)))      */
+    int filter_npass;          /* bilinear passes per axis (Sec. 4.1)                          */
+    int filter_compensate;     /* 1: one extra pass with alpha_c = n/2 + 1                     */
+    int pml_cells;             /* PML depth on non-periodic faces (Appendix II)                */
+    int periodic_mask;         /* bit 0: x periodic, bit 2: z periodic (no moving window)      */
+    double gamma_boost;        /* Lorentz factor of the calculation frame (>= 1)              */
+    int moving_window;         /* 1: window follows the wake at beta_w* c (Sec. 2)             */
+    int64_t particle_capacity; /* slots per species (electrons; rigid ions alike)              */
+    int sort_every;            /* steps between tile sorts (0: library default)                */
+    int tile_x, tile_z;        /* particle tile in cells (0: library default)                  */
+    int max_stations;          /* lab-frame stations that may be added                         */
+    int station_capacity;      /* samples kept per station                                     */
+    int phase_timers;          /* 1: record HIP events around every phase of bf_step          */
+    uint64_t seed;             /* counter-based RNG seed for plasma loading                    */
+} bf_config;
+
+/* Plasma given in the lab frame: zero density before start_um, linear up-ramp of ramp_um
+   (0: step), then the plateau n0_cm3.  ppc macro-electrons per cell, placed uniformly at
+   random in each cell by SplitMix64 keyed by (seed, lattice row, cell, index).
+   ion_mode 0: immobile neutralising background (lab frame), 1: ions at rest in the lab,
+   i.e. drifting rigidly at -beta c in the calculation frame and depositing current. */
+typedef struct {
+    double n0_cm3, ramp_um, start_um;
+    int ppc;
+    int ion_mode;
+} bf_plasma;
+
+/* Laser given in the lab frame (Sec. 3.1.2): wavelength, normalised amplitude a0, 1/e
+   field waist, intensity FWHM duration, lab position of the emitting plane.  Linear
+   polarisation along x; the pulse peak crosses the plane 3 sigma_t after t = 0. */
+typedef struct {
+    double lambda_um, a0, waist_um, fwhm_fs, z_antenna_um;
+} bf_laser;
+
+/* Lab-frame station: fields sampled on axis at the lab position z_lab_um, back-transformed
+   to the lab frame (Sec. 3.2). */
+typedef struct {
+    double z_lab_um;
+} bf_station;
+
+/* Device buffer descriptor / binding.  dtype is informational (0: raw bytes). */
+typedef struct { const char* name; size_t bytes; size_t align; int dtype; } bf_buffer_desc;
+typedef struct { const char* name; void* ptr; size_t bytes; } bf_buffer_binding;
+
+/* Scalar run state (checkpointing). */
+typedef struct {
+    uint32_t abi_version, struct_size;
+    int64_t step;              /* steps taken                                                  */
+    double time;               /* calculation-frame time (um / c)                              */
+    int64_t shift;             /* whole cells the window has moved                             */
+    int64_t next_row;          /* next plasma lattice row to create                            */
+    int32_t zoff;              /* ring offset of the z rows                                    */
+    int32_t e_cur, b_cur, p_cur; /* which half of each ping-pong pair is current              */
+    int32_t nseg_e, nseg_i;    /* particle segments in use                                     */
+    int32_t since_sort;
+    int32_t have_plasma, have_laser, nstations;
+} bf_state;
+
+/* ---- set-up ---------------------------------------------------------------------------- */
+
+/* Pure: validates cfg (BF_EINVAL, BF_ECFL) and lists the device buffers it needs.  On entry
+   *n_inout is the capacity of out (may be 0 with out == NULL); on return the number of
+   buffers.  Names are static strings. */
+bf_status bf_query_buffers(const bf_config* cfg, bf_buffer_desc* out, int* n_inout);
+
+/* Creates a handle over caller-owned buffers (every name from bf_query_buffers must be
+   bound with at least the listed size and alignment).  hip_stream: hipStream_t or NULL for
+   the default stream.  Buffers are cleared on the stream. */
+bf_status bf_create(const bf_config* cfg, const bf_buffer_binding* bindings, int n,
+                    void* hip_stream, bf_sim** out);
+
+/* Loads the plasma lattice rows lying inside the window at t = 0 (Sec. 3.1.1: background
+   plasma fixed in the lab, created continuously at the front plane afterwards). */
+bf_status bf_init_plasma(bf_sim* sim, const bf_plasma* plasma);
+
+/* Installs the laser antenna: one positive and one negative macro-particle per transverse
+   cell on the lab-fixed plane (Sec. 3.1.2). */
+bf_status bf_init_laser(bf_sim* sim, const bf_laser* laser);
+
+/* Adds a lab-frame station; *station_id receives its index. */
+bf_status bf_add_station(bf_sim* sim, const bf_station* station, int* station_id);
+
+/* Replaces the electron set by n explicit particles (host arrays, positions in um relative
+   to the interior origin, momenta u = gamma v / c, weights in the library's normalised
+   units).  id may be NULL.  Ions and antenna are unchanged. */
+bf_status bf_load_electrons(bf_sim* sim, int64_t n, const uint32_t* id, const double* x,
+                            const double* z, const double* ux, const double* uy,
+                            const double* uz, const double* w);
+
+/* ---- stepping -------------------------------------------------------------------------- */
+
+/* Advances nsteps PIC steps (Faraday+Friedman+PML, stations, gather/push/deposit, antenna,
+   filter, Ampere+PML, window and injection, periodic tile sort).  Asynchronous. */
+bf_status bf_step(bf_sim* sim, int nsteps);
+
+/* ---- diagnostics and state ------------------------------------------------------------- */
+
+enum {
+    BF_DIAG_FIELD = 0,     /* arg = field id (BF_F_*): stored_z x stored_x doubles          */
+    BF_DIAG_PARTICLES = 1, /* arg = species (0 e-, 1 ions): 7 arrays of n doubles (id, x, z,
+                              ux, uy, uz, w), n = BF_DIAG_COUNTS value                        */
+    BF_DIAG_COUNTS = 2,    /* 4 int64: live electrons, live ions, slots e-, slots ions     */
+    BF_DIAG_STATION = 3,   /* arg = station: int64 count then count x 7 doubles (t_lab, Ex,
+                              Ey, Ez, Bx, By, Bz in the lab frame)                           */
+    BF_DIAG_ENERGY = 4,    /* 3 doubles: field energy E, field energy B, kinetic energy     */
+    BF_DIAG_GAUSS = 5,     /* stored_z x stored_x doubles: div E - F[rho] on the nodes      */
+    BF_DIAG_INFO = 6,      /* bf_info                                                       */
+    BF_DIAG_ANTENNA = 7,   /* nx doubles: transverse positions of the moving antenna sheet  */
+    BF_DIAG_TIMERS = 8     /* BF_PHASE_COUNT x 2 doubles: accumulated ms and launches per
+                              phase since the last call (phase_timers = 1); arg != 0 resets */
+};
+
+/* phases of one bf_step (BF_DIAG_TIMERS rows) */
+enum {
+    BF_PHASE_FARADAY = 0,  /* Faraday + Friedman + PML, stations                            */
+    BF_PHASE_PUSH,         /* electrons: gather, push, deposit                              */
+    BF_PHASE_IONS,         /* rigid-ion current                                             */
+    BF_PHASE_ANTENNA,      /* laser antenna current                                         */
+    BF_PHASE_FILTER,       /* current filter                                                */
+    BF_PHASE_AMPERE,       /* Ampere + PML                                                  */
+    BF_PHASE_WINDOW,       /* window shift and plasma injection                             */
+    BF_PHASE_SORT,         /* tile sort                                                     */
+    BF_PHASE_COUNT
+};
+
+/* field ids (logical layout [stored_z][stored_x], x fastest) */
+enum {
+    BF_F_EX = 0, BF_F_EY, BF_F_EZ, BF_F_BX, BF_F_BY, BF_F_BZ, BF_F_JX, BF_F_JY, BF_F_JZ,
+    BF_F_EXO, BF_F_EYO, BF_F_EZO, BF_F_EXB, BF_F_EYB, BF_F_EZB, BF_F_BYX, BF_F_EYX,
+    BF_F_BXO, BF_F_BYO, BF_F_BZO, BF_F_COUNT
+};
+
+typedef struct {
+    double dt, dt_crit, beta, gamma, v_window, n0_norm, e0_norm, omega, alpha2, beta2;
+    double antenna_weight;
+    int32_t stored_x, stored_z, pml_x, pml_z;
+    int64_t step;
+    double time;
+    int64_t shift, next_row;
+    int32_t tile_x, tile_z, ntiles, sort_every;
+} bf_info;
+
+/* Synchronises; copies the requested diagnostic (FP64, host order described above) into
+   host_out of `bytes` bytes (BF_EINVAL if too small).  Allowed after a sticky error. */
+bf_status bf_diagnose(bf_sim* sim, int kind, int arg, void* host_out, size_t bytes);
+
+/* Overwrites one field array (logical layout, doubles) on the device.  Synchronous. */
+bf_status bf_set_field(bf_sim* sim, int field, const double* host_in, size_t bytes);
+
+/* Synchronises and returns the sticky device status (BF_OK, BF_ECAPACITY, BF_ENONFINITE). */
+bf_status bf_sync_status(bf_sim* sim);
+
+/* Scalar state for checkpointing (device buffers are the caller's to copy). */
+bf_status bf_get_state(const bf_sim* sim, bf_state* out);
+bf_status bf_set_state(bf_sim* sim, const bf_state* in);
+
+const char* bf_status_string(bf_status s);
+const char* bf_last_error(const bf_sim* sim);
+
+/* Frees host metadata only; the caller frees its buffers afterwards. */
+void bf_destroy(bf_sim* sim);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1178 @@
+// bf_host.hip -- host runtime of the C ABI declared in include/bfpic.h.
+//
+// Owns only host metadata: device memory comes from the caller's bindings.  One bf_step()
+// enqueues, per PIC step, on the bound stream:
+//   Faraday + Friedman + PML -> stations -> gather/push/deposit (electrons) -> rigid-ion
+//   deposit -> antenna -> filter -> Ampere + PML -> window shift -> injection -> tile sort
+// The order follows the time levels of the paper: B^{n+1/2} from E^n (Sec. 4.3, indices
+// shifted by one), the push at E^n and B^n = (B^{n-1/2}+B^{n+1/2})/2, J^{n+1/2} from the
+// x^n -> x^{n+1} move, E^{n+1} from B^{n+1/2} and the filtered J^{n+1/2} (Sec. 4.2).
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bfpic.h"
+#include "bf_kernels.h"
+
+using namespace bf;
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+// CODATA 2018
+constexpr double C_LIGHT = 299792458.0;
+constexpr double EPS0 = 8.8541878128e-12;
+constexpr double ME_KG = 9.1093837015e-31;
+constexpr double Q_E = 1.602176634e-19;
+
+// field arrays inside the "fields" buffer
+enum {
+    A_E0 = 0,   // E set 0: 3 arrays
+    A_E1 = 3,   // E set 1
+    A_EB0 = 6,  // Ebar set 0
+    A_EB1 = 9,  // Ebar set 1
+    A_B0 = 12,  // B set 0
+    A_B1 = 15,  // B set 1
+    A_J = 18,   // raw J
+    A_JF = 21,  // filtered J
+    A_BYX = 24,
+    A_EYX = 25,
+    A_COUNT = 26
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// keeps the first HIP error of a sequence of calls
+struct Chk {
+    hipError_t e = hipSuccess;
+    void operator()(hipError_t r)
+    {
+        if (e == hipSuccess) e = r;
+    }
+};
+
+struct Layout {
+    int real;            // bytes
+    int Sx, Sz, pitch, Px, Pz;
+    size_t field_array;  // bytes per field array
+    size_t fields_bytes;
+    int64_t cap;
+    size_t e_off[7], e_bytes;   // x z ux uy uz w id
+    size_t i_off[4], i_bytes;   // x z0 w id
+    int tile_x, tile_z, ntx, ntz, ntiles, nchunks, seg_cap;
+    // work buffer
+    size_t w_seg[2], w_bbe[2], w_segi[2], w_bbi[2], w_counts, w_cursor, w_nused, w_status,
+        w_pml_r, w_pml_on, w_st_z, w_st_rec, w_st_cnt, w_ant, w_rho, w_bytes;
+    int nst, stcap;
+};
+
+bool layout_of(const bf_config* c, Layout* L)
+{
+    const int real = c->real_bytes;
+    L->real = real;
+    const int perx = c->periodic_mask & 1, perz = (c->periodic_mask >> 2) & 1;
+    L->Px = perx ? 0 : c->pml_cells;
+    L->Pz = perz ? 0 : c->pml_cells;
+    L->Sx = perx ? c->nx : c->nx + 2 * L->Px + 1;
+    L->Sz = perz ? c->nz : c->nz + 2 * L->Pz + 1;
+    const int pe = 256 / real;                 // 256-byte row alignment
+    L->pitch = (int)align_up((size_t)L->Sx, (size_t)pe);
+    L->field_array = (size_t)L->pitch * L->Sz * real;
+    L->fields_bytes = L->field_array * A_COUNT;
+    L->cap = c->particle_capacity;
+    size_t o = 0;
+    const size_t esz[7] = {8, 8, (size_t)real, (size_t)real, (size_t)real, (size_t)real, 4};
+    for (int k = 0; k < 7; k++) { L->e_off[k] = o; o = align_up(o + esz[k] * L->cap, 256); }
+    L->e_bytes = std::max<size_t>(o, 256);
+    o = 0;
+    const size_t isz[4] = {8, 8, (size_t)real, 4};
+    for (int k = 0; k < 4; k++) { L->i_off[k] = o; o = align_up(o + isz[k] * L->cap, 256); }
+    L->i_bytes = std::max<size_t>(o, 256);
+    L->tile_x = c->tile_x > 0 ? c->tile_x : 16;
+    L->tile_z = c->tile_z > 0 ? c->tile_z : 16;
+    L->ntx = (c->nx + L->tile_x - 1) / L->tile_x;
+    L->ntz = (c->nz + L->tile_z - 1) / L->tile_z;
+    L->ntiles = L->ntx * L->ntz;
+    L->nchunks = L->ntx;
+    L->seg_cap = L->ntiles + (c->nz + 64) * L->nchunks;
+    L->nst = std::max(c->max_stations, 0);
+    L->stcap = std::max(c->station_capacity, 1);
+    o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
+    for (int k = 0; k < 2; k++) {
+        L->w_seg[k] = take(sizeof(Segment) * L->seg_cap);
+        L->w_bbe[k] = take(sizeof(int4) * L->seg_cap);
+        L->w_segi[k] = take(sizeof(Segment) * L->seg_cap);
+        L->w_bbi[k] = take(sizeof(int4) * L->seg_cap);
+    }
+    L->w_counts = take(sizeof(int) * (L->ntiles + 1));
+    L->w_cursor = take(sizeof(int) * (L->ntiles + 1));
+    L->w_nused = take(sizeof(int) * 4);
+    L->w_status = take(sizeof(int) * 4);
+    L->w_pml_r = take((size_t)real * 2 * 2 * (L->Sx + L->Sz) * 2);
+    L->w_pml_on = take(2 * 2 * (size_t)(L->Sx + L->Sz));
+    L->w_st_z = take(sizeof(double) * std::max(L->nst, 1));
+    L->w_st_rec = take(sizeof(double) * 7 * (size_t)std::max(L->nst, 1) * L->stcap);
+    L->w_st_cnt = take(sizeof(int) * std::max(L->nst, 1));
+    L->w_ant = take(sizeof(double) * (size_t)c->nx);
+    L->w_rho = take(2 * sizeof(double) * (size_t)L->Sx * L->Sz);
+    L->w_bytes = o;
+    return true;
+}
+
+// CFL (Sec. 4.2.1 Eq. cfl): the dispersion right-hand side is multilinear in the s_d^2, so
+// its maximum over the zone is on a vertex; 2D takes k_y = 0 (c_y = 1).  Friedman (Sec.
+// 4.3) scales it by sqrt((2+theta)/(2+3theta)).
+double cfl2d(double a, double b, double g, double dx, double dz, double theta)
+{
+    double best = 0.0;
+    const double kx = 1.0 / (dx * dx), kz = 1.0 / (dz * dz);
+    for (int v = 1; v < 4; v++) {
+        const double sx = (v & 1) ? 1.0 : 0.0, sz = (v & 2) ? 1.0 : 0.0;
+        const double cx = 1.0 - 2.0 * sx, cz = 1.0 - 2.0 * sz;
+        const double Cx = a + 2.0 * b * (1.0 + cz) + 4.0 * g * cz;
+        const double Cz = a + 2.0 * b * (cx + 1.0) + 4.0 * g * cx;
+        best = std::max(best, Cx * sx * kx + Cz * sz * kz);
+    }
+    return std::sqrt((2.0 + theta) / (2.0 + 3.0 * theta)) / std::sqrt(best);
+}
+
+bf_status validate(const bf_config* c)
+{
+    if (!c) return BF_EINVAL;
+    if (c->abi_version != BF_ABI_VERSION || c->struct_size != sizeof(bf_config)) return BF_EINVAL;
+    if (c->dim != 2) return BF_EUNSUPPORTED;
+    if (c->nx <= 0 || c->nz <= 0 || c->dx_um <= 0 || c->dz_um <= 0) return BF_EINVAL;
+    if (c->real_bytes != 4 && c->real_bytes != 8) return BF_EINVAL;
+    if (c->shape_order != 3) return BF_EUNSUPPORTED;
+    if (c->friedman_theta < 0 || c->friedman_theta > 1) return BF_EINVAL;
+    if (c->filter_npass < 0 || c->filter_npass > 10) return BF_EINVAL;
+    if (c->pml_cells < 0 || c->pml_cells > 64) return BF_EINVAL;
+    if ((c->periodic_mask & 1) == 0 && c->pml_cells < 4) return BF_EINVAL;
+    if (((c->periodic_mask >> 2) & 1) == 0 && c->pml_cells < 4) return BF_EINVAL;
+    if (((c->periodic_mask >> 2) & 1) && c->moving_window) return BF_EINVAL;
+    if (c->gamma_boost < 1.0) return BF_EINVAL;
+    if (c->particle_capacity < 0 || c->particle_capacity > (int64_t)INT32_MAX - 65536) return BF_EINVAL;
+    if (c->tile_x < 0 || c->tile_z < 0 || c->tile_x > 64 || c->tile_z > 64) return BF_EINVAL;
+    if (c->max_stations < 0 || c->max_stations > 64 || c->station_capacity < 0) return BF_EINVAL;
+    const double a2 = c->ck_alpha + 2 * c->ck_beta;
+    if (std::fabs(c->ck_alpha + 4 * c->ck_beta + 4 * c->ck_gamma - 1.0) > 1e-12) return BF_EINVAL;
+    (void)a2;
+    if (!(c->cfl_fraction > 0.0)) return BF_EINVAL;
+    if (c->cfl_fraction > 1.0) return BF_ECFL;
+    return BF_OK;
+}
+
+const char* kNames[] = {"fields", "electrons0", "electrons1", "ions0", "ions1", "work"};
+
+}  // namespace
+
+struct bf_sim {
+    bf_config cfg;
+    Layout L;
+    hipStream_t stream = nullptr;
+    void* buf[6] = {};
+    Geo g;
+    double dt = 0, dt_crit = 0, beta = 0, gamma = 1, a2 = 1, b2 = 0, theta = 0, vw = 0;
+    double n0 = 0, omega = 0, e0 = 0, w0 = 0, sig_t = 0, t0 = 0, za_lab = 0, aw = 0;
+    bf_plasma plasma{};
+    int have_plasma = 0, have_laser = 0;
+    int e_cur = 0, b_cur = 0, eb_cur = 0, p_cur = 0, bb_cur = 0, sg_cur = 0;
+    int nseg_e = 0, nseg_i = 0;
+    int64_t step = 0, shift = 0, next_row = 0;
+    double t = 0;
+    int since_sort = 0, sort_every = 20, lds_cells = 0;
+    int nst = 0;
+    std::vector<double> st_z;
+    int err = BF_OK;
+    std::string msg;
+    // phase timers: HIP events recorded on the stream around each phase of a step
+    struct Mark { hipEvent_t a, b; int phase; };
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<Mark> marks;
+    double tacc[BF_PHASE_COUNT] = {};
+    double tcnt[BF_PHASE_COUNT] = {};
+
+    ~bf_sim()
+    {
+        for (auto& m : marks) { ev_pool.push_back(m.a); ev_pool.push_back(m.b); }
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    }
+    hipEvent_t tick()
+    {
+        if (!cfg.phase_timers) return nullptr;
+        hipEvent_t e = nullptr;
+        if (!ev_pool.empty()) { e = ev_pool.back(); ev_pool.pop_back(); }
+        else if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        (void)hipEventRecord(e, stream);
+        return e;
+    }
+    void tock(hipEvent_t a, int phase)
+    {
+        if (!a) return;
+        hipEvent_t b = tick();
+        if (!b) { ev_pool.push_back(a); return; }
+        marks.push_back(Mark{a, b, phase});
+    }
+    // folds recorded marks into the accumulators (synchronises the stream)
+    hipError_t fold_marks()
+    {
+        hipError_t e = hipStreamSynchronize(stream);
+        for (auto& m : marks) {
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, m.a, m.b);
+            tacc[m.phase] += ms;
+            tcnt[m.phase] += 1.0;
+            ev_pool.push_back(m.a);
+            ev_pool.push_back(m.b);
+        }
+        marks.clear();
+        return e;
+    }
+
+    char* fields() const { return (char*)buf[0]; }
+    char* work() const { return (char*)buf[5]; }
+    template <typename T> T* w(size_t off) const { return reinterpret_cast<T*>(work() + off); }
+    template <typename R> R* arr(int a) const { return reinterpret_cast<R*>(fields() + L.field_array * a); }
+};
+
+namespace {
+
+bf_status fail(bf_sim* s, bf_status st, const char* m)
+{
+    if (s) s->msg = m;
+    return st;
+}
+
+bf_status hip_check(bf_sim* s, hipError_t e, const char* where)
+{
+    if (e == hipSuccess) return BF_OK;
+    char b[256];
+    snprintf(b, sizeof b, "%s: %s", where, hipGetErrorString(e));
+    if (s) { s->msg = b; s->err = BF_EDEVICE; }
+    return BF_EDEVICE;
+}
+
+template <typename R>
+FieldSet<R> field_set(const bf_sim* s)
+{
+    FieldSet<R> f;
+    const int e = s->e_cur, b = s->b_cur, eb = s->eb_cur;
+    for (int c = 0; c < 3; c++) {
+        f.E[c] = s->arr<R>((e ? A_E1 : A_E0) + c);
+        f.Eo[c] = s->arr<R>((e ? A_E0 : A_E1) + c);
+        f.Eb[c] = s->arr<R>((eb ? A_EB1 : A_EB0) + c);
+        f.Ebn[c] = s->arr<R>((eb ? A_EB0 : A_EB1) + c);
+        f.B[c] = s->arr<R>((b ? A_B1 : A_B0) + c);
+        f.Bn[c] = s->arr<R>((b ? A_B0 : A_B1) + c);
+        f.J[c] = s->arr<R>(A_J + c);
+        f.Jf[c] = s->cfg.filter_npass > 0 ? s->arr<R>(A_JF + c) : s->arr<R>(A_J + c);
+    }
+    f.Byx = s->arr<R>(A_BYX);
+    f.Eyx = s->arr<R>(A_EYX);
+    return f;
+}
+
+template <typename R>
+PmlTab<R> pml_tab(const bf_sim* s)
+{
+    PmlTab<R> p;
+    R* base = s->w<R>(s->L.w_pml_r);
+    uint8_t* on = s->w<uint8_t>(s->L.w_pml_on);
+    const int n[2] = {s->L.Sx, s->L.Sz};
+    size_t ro = 0, oo = 0;
+    for (int ax = 0; ax < 2; ax++)
+        for (int h = 0; h < 2; h++) {
+            p.xi[ax][h] = base + ro; ro += n[ax];
+            p.c[ax][h] = base + ro; ro += n[ax];
+            p.on[ax][h] = on + oo; oo += n[ax];
+        }
+    return p;
+}
+
+template <typename R>
+ElectronArrays<R> electrons(const bf_sim* s, int set)
+{
+    char* b = (char*)s->buf[1 + set];
+    ElectronArrays<R> e;
+    e.x = (double*)(b + s->L.e_off[0]);
+    e.z = (double*)(b + s->L.e_off[1]);
+    e.ux = (R*)(b + s->L.e_off[2]);
+    e.uy = (R*)(b + s->L.e_off[3]);
+    e.uz = (R*)(b + s->L.e_off[4]);
+    e.w = (R*)(b + s->L.e_off[5]);
+    e.id = (uint32_t*)(b + s->L.e_off[6]);
+    return e;
+}
+
+template <typename R>
+IonArrays<R> ions(const bf_sim* s, int set)
+{
+    char* b = (char*)s->buf[3 + set];
+    IonArrays<R> e;
+    e.x = (double*)(b + s->L.i_off[0]);
+    e.z0 = (double*)(b + s->L.i_off[1]);
+    e.w = (R*)(b + s->L.i_off[2]);
+    e.id = (uint32_t*)(b + s->L.i_off[3]);
+    return e;
+}
+
+// PML conductivity at interior-relative position p (cells) on an axis of N interior cells:
+// sigma_m (d/5)^2 with sigma_m = 4 c / delta (Appendix II test prescription), d the depth
+double sigma_at(double p, int N, int P, double d)
+{
+    if (P == 0) return 0.0;
+    double dep = 0.0;
+    if (p < 0.0) dep = -p; else if (p > (double)N) dep = p - (double)N;
+    if (dep <= 0.0) return 0.0;
+    return (4.0 / d) * (dep / 5.0) * (dep / 5.0);
+}
+
+template <typename R>
+hipError_t upload_pml(bf_sim* s)
+{
+    const int n[2] = {s->L.Sx, s->L.Sz};
+    const int P[2] = {s->L.Px, s->L.Pz};
+    const int N[2] = {s->cfg.nx, s->cfg.nz};
+    const double d[2] = {s->cfg.dx_um, s->cfg.dz_um};
+    std::vector<R> r;
+    std::vector<uint8_t> on;
+    for (int ax = 0; ax < 2; ax++)
+        for (int h = 0; h < 2; h++) {
+            std::vector<R> xi(n[ax]), c(n[ax]);
+            for (int i = 0; i < n[ax]; i++) {
+                const double p = (double)(i - P[ax]) + 0.5 * h;
+                const double sg = sigma_at(p, N[ax], P[ax], d[ax]);
+                double x = 1.0, cc = s->dt;
+                if (sg != 0.0) { x = std::exp(-sg * s->dt); cc = (1.0 - x) / sg; }
+                xi[i] = (R)x;
+                c[i] = (R)cc;
+                on.push_back(sg != 0.0 ? 1 : 0);
+            }
+            r.insert(r.end(), xi.begin(), xi.end());
+            r.insert(r.end(), c.begin(), c.end());
+        }
+    Chk ck;
+    ck(hipMemcpy(s->w<char>(s->L.w_pml_r), r.data(), r.size() * sizeof(R), hipMemcpyHostToDevice));
+    ck(hipMemcpy(s->w<char>(s->L.w_pml_on), on.data(), on.size(), hipMemcpyHostToDevice));
+    return ck.e;
+}
+
+void update_window_speed(bf_sim* s)
+{
+    // beta_w = (1 + omega_p^2/omega^2)^(-1/2) (Sec. 2 Eq. 1); beta_w* = (beta_w - beta)/(1 -
+    // beta_w beta) (Sec. 2); vacuum or no laser: the window moves at c
+    if (!s->cfg.moving_window) { s->vw = 0.0; return; }
+    double bw = 1.0;
+    if (s->have_laser) {
+        const double wp2 = s->have_plasma ? s->n0 : 0.0;
+        bw = 1.0 / std::sqrt(1.0 + wp2 / (s->omega * s->omega));
+    }
+    s->vw = (bw - s->beta) / (1.0 - bw * s->beta);
+}
+
+Geo geo_of(const bf_sim* s, int zoff)
+{
+    Geo g;
+    g.Nx = s->cfg.nx; g.Nz = s->cfg.nz;
+    g.Px = s->L.Px; g.Pz = s->L.Pz;
+    g.Sx = s->L.Sx; g.Sz = s->L.Sz;
+    g.pitch = s->L.pitch;
+    g.perx = s->cfg.periodic_mask & 1;
+    g.perz = (s->cfg.periodic_mask >> 2) & 1;
+    g.zoff = zoff;
+    return g;
+}
+
+int* nused_e(const bf_sim* s) { return s->w<int>(s->L.w_nused); }
+int* nused_i(const bf_sim* s) { return s->w<int>(s->L.w_nused) + 1; }
+int* status_word(const bf_sim* s) { return s->w<int>(s->L.w_status); }
+Segment* seg_e(const bf_sim* s, int k) { return s->w<Segment>(s->L.w_seg[k]); }
+Segment* seg_i(const bf_sim* s, int k) { return s->w<Segment>(s->L.w_segi[k]); }
+int4* bb_e(const bf_sim* s, int k) { return s->w<int4>(s->L.w_bbe[k]); }
+int4* bb_i(const bf_sim* s, int k) { return s->w<int4>(s->L.w_bbi[k]); }
+
+double ion_shift(const bf_sim* s, double t)
+{
+    return s->beta * t / s->cfg.dz_um + (double)s->shift;
+}
+
+template <typename R>
+void sort_now(bf_sim* s)
+{
+    const Geo g = geo_of(s, s->g.zoff);
+    const Layout& L = s->L;
+    const int k = s->sg_cur;
+    launch_sort_electrons<R>(g, L.tile_x, L.tile_z, L.ntx, L.ntiles, electrons<R>(s, s->p_cur),
+                             electrons<R>(s, 1 - s->p_cur), seg_e(s, k), s->nseg_e, seg_e(s, 1 - k),
+                             bb_e(s, s->bb_cur), s->w<int>(L.w_counts), s->w<int>(L.w_cursor),
+                             nused_e(s), s->stream);
+    if (s->plasma.ion_mode == 1 && s->have_plasma) {
+        launch_sort_ions<R>(g, L.tile_x, L.tile_z, L.ntx, L.ntiles, ions<R>(s, s->p_cur),
+                            ions<R>(s, 1 - s->p_cur), seg_i(s, k), s->nseg_i, seg_i(s, 1 - k),
+                            bb_i(s, s->bb_cur), ion_shift(s, s->t), s->w<int>(L.w_counts),
+                            s->w<int>(L.w_cursor), nused_i(s), s->stream);
+        s->nseg_i = L.ntiles;
+    }
+    s->p_cur ^= 1;
+    s->sg_cur ^= 1;
+    s->nseg_e = L.ntiles;
+    s->since_sort = 0;
+}
+
+// rows of the plasma lattice whose upper edge has entered the interior at the current time
+// (same rule as the reference: the whole row is created at the front plane)
+int64_t rows_entering(const bf_sim* s)
+{
+    int64_t r = s->next_row;
+    for (;;) {
+        const double upper = (double)(r + 1) - s->beta * s->t / s->cfg.dz_um - (double)s->shift;
+        if (upper > (double)s->cfg.nz) break;
+        r++;
+    }
+    return r - s->next_row;
+}
+
+template <typename R>
+void inject(bf_sim* s, int64_t nrows)
+{
+    if (nrows <= 0) return;
+    const Layout& L = s->L;
+    if (s->nseg_e + nrows * L.nchunks > L.seg_cap) sort_now<R>(s);
+    if (s->nseg_e + nrows * L.nchunks > L.seg_cap) {
+        // more rows than one table holds (initial load of a tall box): split
+        const int64_t per = std::max<int64_t>(1, (L.seg_cap - s->nseg_e) / L.nchunks);
+        while (nrows > 0) {
+            const int64_t n = std::min(nrows, per);
+            inject<R>(s, n);
+            nrows -= n;
+            if (nrows > 0) sort_now<R>(s);
+        }
+        return;
+    }
+    InjectParams ip;
+    ip.row0 = s->next_row;
+    ip.nrows = (int)nrows;
+    ip.nchunks = L.nchunks;
+    ip.tile_x = L.tile_x;
+    ip.ppc = s->plasma.ppc;
+    ip.ion_mode = s->plasma.ion_mode;
+    ip.beta = s->beta;
+    ip.gamma = s->gamma;
+    ip.t = s->t;
+    ip.dz_um = s->cfg.dz_um;
+    ip.dx_um = s->cfg.dx_um;
+    ip.shift = (double)s->shift;
+    ip.n0 = s->n0;
+    ip.ramp_start = s->plasma.start_um;
+    ip.ramp_len = s->plasma.ramp_um;
+    ip.wfac = s->gamma * s->cfg.dx_um * s->cfg.dz_um / (double)s->plasma.ppc;
+    ip.uz0 = -s->gamma * s->beta;
+    ip.seed = s->cfg.seed;
+    ip.seg_base = s->nseg_e;
+    ip.cap = L.cap;
+    const int k = s->sg_cur;
+    launch_inject<R>(s->g, electrons<R>(s, s->p_cur), ions<R>(s, s->p_cur), seg_e(s, k),
+                     bb_e(s, s->bb_cur), seg_i(s, k), bb_i(s, s->bb_cur), nused_e(s), nused_i(s), ip,
+                     status_word(s), s->stream);
+    s->nseg_e += (int)nrows * L.nchunks;
+    if (s->plasma.ion_mode == 1) s->nseg_i = s->nseg_e;
+    s->next_row += nrows;
+}
+
+template <typename R>
+PtrList<R> all_arrays(const bf_sim* s)
+{
+    PtrList<R> p;
+    p.n = A_COUNT;
+    for (int a = 0; a < A_COUNT; a++) p.p[a] = s->arr<R>(a);
+    return p;
+}
+
+template <typename R>
+bf_status step_impl(bf_sim* s, int nsteps)
+{
+    const bf_config& c = s->cfg;
+    const Layout& L = s->L;
+    SolverCoef sc{s->dt, s->a2, s->b2, s->theta, 1.0 / c.dx_um, 1.0 / c.dz_um};
+    const PmlTab<R> pm = pml_tab<R>(s);
+    for (int n = 0; n < nsteps; n++) {
+        const FieldSet<R> f = field_set<R>(s);
+        // Faraday + Friedman + PML
+        hipEvent_t t_ph = s->tick();
+        launch_faraday<R>(s->g, f, pm, sc, s->stream);
+        // stations (E^n, B^n)
+        if (s->nst > 0) {
+            StationParams sp;
+            sp.n = s->nst;
+            sp.zlab = s->w<double>(L.w_st_z);
+            sp.gamma = s->gamma; sp.beta = s->beta; sp.t = s->t; sp.dz_um = c.dz_um;
+            sp.shift = (double)s->shift; sp.xc = 0.5 * c.nx; sp.cap = L.stcap;
+            launch_stations<R>(s->g, f, sp, s->w<double>(L.w_st_rec), s->w<int>(L.w_st_cnt), s->stream);
+        }
+        s->tock(t_ph, BF_PHASE_FARADAY);
+        // window position after this step
+        const double t1 = (double)(s->step + 1) * s->dt;
+        int64_t s1 = s->shift;
+        if (c.moving_window) s1 = (int64_t)std::trunc(s->vw * t1 / c.dz_um);
+        const int d = (int)(s1 - s->shift);
+        // electrons
+        PushParams<R> pp;
+        pp.qdt2 = (R)(-0.5 * s->dt);
+        pp.dtdx = (R)(s->dt / c.dx_um);
+        pp.dtdz = (R)(s->dt / c.dz_um);
+        pp.fjx = (R)(1.0 / (c.dz_um * s->dt));    // -q/(dz dt) with q = -1 (times w)
+        pp.fjz = (R)(1.0 / (c.dx_um * s->dt));
+        pp.fjy = (R)(-1.0 / (c.dx_um * c.dz_um));
+        pp.shift = d;
+        pp.lds_cells = s->lds_cells;
+        t_ph = s->tick();
+        launch_gpd<R>(s->g, f, electrons<R>(s, s->p_cur), seg_e(s, s->sg_cur), bb_e(s, s->bb_cur),
+                      bb_e(s, 1 - s->bb_cur), s->nseg_e, pp, status_word(s), s->stream);
+        s->tock(t_ph, BF_PHASE_PUSH);
+        // rigid ions: deposit-only J_z
+        t_ph = s->tick();
+        if (s->have_plasma && s->plasma.ion_mode == 1)
+            launch_ions<R>(s->g, f, ions<R>(s, s->p_cur), seg_i(s, s->sg_cur), bb_i(s, s->bb_cur),
+                           bb_i(s, 1 - s->bb_cur), s->nseg_i, ion_shift(s, s->t), ion_shift(s, t1), d,
+                           (R)(-1.0 / (c.dx_um * s->dt)), s->lds_cells * 9, s->stream);
+        s->tock(t_ph, BF_PHASE_IONS);
+        // antenna
+        t_ph = s->tick();
+        if (s->have_laser) {
+            AntennaParams ap;
+            ap.n = c.nx;
+            ap.za = (s->za_lab / s->gamma - s->beta * s->t) / c.dz_um - (double)s->shift;
+            ap.zb = (s->za_lab / s->gamma - s->beta * t1) / c.dz_um - (double)s->shift;
+            ap.tmid = s->t + 0.5 * s->dt;
+            ap.gamma = s->gamma; ap.e0 = s->e0; ap.omega = s->omega; ap.w0 = s->w0;
+            ap.sig_t = s->sig_t; ap.t0 = s->t0; ap.dx_um = c.dx_um; ap.xc_um = 0.5 * c.nx * c.dx_um;
+            ap.weight = s->aw; ap.dt = s->dt; ap.dx = c.dx_um; ap.dz = c.dz_um;
+            ap.active = (ap.za >= 0.0 && ap.za < (double)c.nz) ? 1 : 0;
+            launch_antenna<R>(s->g, f, s->w<double>(L.w_ant), ap, s->stream);
+        }
+        s->tock(t_ph, BF_PHASE_ANTENNA);
+        // filter
+        t_ph = s->tick();
+        if (c.filter_npass > 0) {
+            R* in[3] = {f.J[0], f.J[1], f.J[2]};
+            R* out[3] = {f.Jf[0], f.Jf[1], f.Jf[2]};
+            const int hx[3] = {1, 0, 0}, hz[3] = {0, 0, 1};
+            launch_filter<R>(s->g, in, out, hx, hz, 3, c.filter_npass, c.filter_compensate, s->stream);
+        }
+        s->tock(t_ph, BF_PHASE_FILTER);
+        // Ampere + PML (E^{n+1} into the E^{n-1} set), clears raw J
+        t_ph = s->tick();
+        launch_ampere<R>(s->g, f, pm, sc, true, s->stream);
+        s->tock(t_ph, BF_PHASE_AMPERE);
+        s->e_cur ^= 1;
+        s->b_cur ^= 1;
+        if (s->theta > 0.0) s->eb_cur ^= 1;
+        s->bb_cur ^= 1;
+        s->step++;
+        s->t = (double)s->step * s->dt;
+        // moving window: advance the ring offset and clear the new rows
+        t_ph = s->tick();
+        if (d != 0) {
+            s->g.zoff = (int)(((int64_t)s->g.zoff + d) % L.Sz);
+            if (s->g.zoff < 0) s->g.zoff += L.Sz;
+            s->shift = s1;
+            EntryRows er{};
+            // rows that just left the z-PML for the interior drop their split x-part
+            for (int h = 0; h < 2; h++) {
+                for (int k = 0; k < L.Sz; k++) {
+                    const double pk = (double)(k - L.Pz) + 0.5 * h;
+                    if (sigma_at(pk, c.nz, L.Pz, c.dz_um) != 0.0) continue;
+                    if (sigma_at(pk + d, c.nz, L.Pz, c.dz_um) == 0.0) continue;
+                    if (h == 1 && er.nh < 4) er.h[er.nh++] = k;
+                    if (h == 0 && er.nn < 4) er.n[er.nn++] = k;
+                }
+            }
+            const FieldSet<R> f2 = field_set<R>(s);
+            launch_window_rows<R>(s->g, all_arrays<R>(s), d, er, f2, pm, s->stream);
+        }
+        // plasma injection at the front plane
+        if (s->have_plasma) inject<R>(s, rows_entering(s));
+        s->tock(t_ph, BF_PHASE_WINDOW);
+        t_ph = s->tick();
+        if (++s->since_sort >= s->sort_every && s->have_plasma) sort_now<R>(s);
+        s->tock(t_ph, BF_PHASE_SORT);
+        if (s->marks.size() > 40000) {
+            hipError_t e = s->fold_marks();
+            if (e != hipSuccess) return hip_check(s, e, "phase timers");
+        }
+    }
+    return BF_OK;
+}
+
+}  // namespace
+
+// ======================================================================================
+// C ABI
+// ======================================================================================
+
+extern "C" {
+
+const char* bf_status_string(bf_status s)
+{
+    switch (s) {
+    case BF_OK: return "ok";
+    case BF_EINVAL: return "invalid argument";
+    case BF_ECFL: return "time step above the CFL limit";
+    case BF_ECAPACITY: return "particle capacity exceeded";
+    case BF_ENONFINITE: return "non-finite particle momentum";
+    case BF_EDEVICE: return "HIP runtime error";
+    case BF_ESTATE: return "call not allowed in this state";
+    case BF_EUNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown status";
+}
+
+const char* bf_last_error(const bf_sim* s) { return s ? s->msg.c_str() : "null handle"; }
+
+bf_status bf_query_buffers(const bf_config* cfg, bf_buffer_desc* out, int* n_inout)
+{
+    if (!n_inout) return BF_EINVAL;
+    const bf_status v = validate(cfg);
+    if (v != BF_OK) return v;
+    Layout L;
+    layout_of(cfg, &L);
+    const size_t sizes[6] = {L.fields_bytes, L.e_bytes, L.e_bytes, L.i_bytes, L.i_bytes, L.w_bytes};
+    const int cap = *n_inout;
+    *n_inout = 6;
+    if (!out) return BF_OK;
+    if (cap < 6) return BF_EINVAL;
+    for (int k = 0; k < 6; k++) {
+        out[k].name = kNames[k];
+        out[k].bytes = sizes[k];
+        out[k].align = 256;
+        out[k].dtype = 0;
+    }
+    return BF_OK;
+}
+
+bf_status bf_create(const bf_config* cfg, const bf_buffer_binding* b, int n, void* stream, bf_sim** out)
+{
+    if (!out) return BF_EINVAL;
+    *out = nullptr;
+    const bf_status v = validate(cfg);
+    if (v != BF_OK) return v;
+    bf_sim* s = new bf_sim();
+    s->cfg = *cfg;
+    layout_of(cfg, &s->L);
+    const size_t sizes[6] = {s->L.fields_bytes, s->L.e_bytes, s->L.e_bytes, s->L.i_bytes, s->L.i_bytes,
+                             s->L.w_bytes};
+    for (int k = 0; k < 6; k++) {
+        for (int q = 0; q < n; q++)
+            if (b[q].name && std::strcmp(b[q].name, kNames[k]) == 0) {
+                if (b[q].bytes < sizes[k] || !b[q].ptr || ((uintptr_t)b[q].ptr & 255u)) {
+                    delete s;
+                    return BF_EINVAL;
+                }
+                s->buf[k] = b[q].ptr;
+            }
+        if (!s->buf[k]) { delete s; return BF_EINVAL; }
+    }
+    s->stream = (hipStream_t)stream;
+    s->gamma = cfg->gamma_boost;
+    s->beta = std::sqrt(1.0 - 1.0 / (s->gamma * s->gamma));
+    s->a2 = cfg->ck_alpha + 2.0 * cfg->ck_beta;   // 2D: k_y = 0 folds the y neighbours
+    s->b2 = cfg->ck_beta + 2.0 * cfg->ck_gamma;
+    s->theta = cfg->friedman_theta;
+    s->dt_crit = cfl2d(cfg->ck_alpha, cfg->ck_beta, cfg->ck_gamma, cfg->dx_um, cfg->dz_um, s->theta);
+    s->dt = cfg->cfl_fraction * s->dt_crit;
+    s->sort_every = cfg->sort_every > 0 ? cfg->sort_every : 20;
+    // LDS tile budget in cells: 9 components (6 field + 3 current) of one tile
+    s->lds_cells = cfg->real_bytes == 4 ? 1024 : 640;
+    s->g = geo_of(s, 0);
+    update_window_speed(s);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 6; k++) {
+        const size_t sz = k == 0 ? s->L.fields_bytes : (k == 5 ? s->L.w_bytes : (k < 3 ? s->L.e_bytes : s->L.i_bytes));
+        if (e == hipSuccess) e = hipMemsetAsync(s->buf[k], 0, sz, s->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) { delete s; return BF_EDEVICE; }
+    e = cfg->real_bytes == 4 ? upload_pml<float>(s) : upload_pml<double>(s);
+    if (e != hipSuccess) { delete s; return BF_EDEVICE; }
+    // empty segment tables: all tiles empty
+    *out = s;
+    return BF_OK;
+}
+
+void bf_destroy(bf_sim* s) { delete s; }
+
+static bf_status guard(bf_sim* s)
+{
+    if (!s) return BF_EINVAL;
+    if (s->err != BF_OK) return fail(s, BF_ESTATE, "handle is in an error state");
+    return BF_OK;
+}
+
+bf_status bf_init_plasma(bf_sim* s, const bf_plasma* p)
+{
+    bf_status st = guard(s);
+    if (st != BF_OK) return st;
+    if (!p || p->ppc <= 0 || p->ppc > 1024 || p->n0_cm3 < 0 || (p->ion_mode != 0 && p->ion_mode != 1))
+        return fail(s, BF_EINVAL, "bad plasma");
+    if (s->have_plasma) return fail(s, BF_ESTATE, "plasma already loaded");
+    s->plasma = *p;
+    const double nu = EPS0 * ME_KG * C_LIGHT * C_LIGHT / (Q_E * Q_E * 1e-12);   // m^-3
+    s->n0 = p->n0_cm3 * 1e6 / nu;
+    s->have_plasma = 1;
+    s->next_row = 0;
+    update_window_speed(s);
+    // initial rows: every lattice row inside the window at the current time
+    if (s->cfg.real_bytes == 4) {
+        inject<float>(s, rows_entering(s));
+        sort_now<float>(s);
+    } else {
+        inject<double>(s, rows_entering(s));
+        sort_now<double>(s);
+    }
+    return hip_check(s, hipStreamSynchronize(s->stream), "init_plasma");
+}
+
+bf_status bf_init_laser(bf_sim* s, const bf_laser* l)
+{
+    bf_status st = guard(s);
+    if (st != BF_OK) return st;
+    if (!l || l->lambda_um <= 0 || l->waist_um <= 0 || l->fwhm_fs <= 0) return fail(s, BF_EINVAL, "bad laser");
+    s->have_laser = 1;
+    s->omega = 2.0 * PI / l->lambda_um;
+    s->e0 = l->a0 * s->omega;                              // a0 = e E0 / (m c omega)
+    s->w0 = l->waist_um;
+    s->sig_t = l->fwhm_fs * 1e-15 * C_LIGHT * 1e6 / (2.0 * std::sqrt(std::log(2.0)));
+    s->t0 = 3.0 * s->sig_t;
+    s->za_lab = l->z_antenna_um;
+    s->aw = (2.0 * s->e0 / s->gamma) * s->cfg.dx_um / 0.01;  // |v| of the moving sheet <= 0.01 c
+    std::vector<double> xm(s->cfg.nx);
+    for (int i = 0; i < s->cfg.nx; i++) xm[i] = i + 0.5;
+    update_window_speed(s);
+    return hip_check(s, hipMemcpy(s->w<double>(s->L.w_ant), xm.data(), xm.size() * 8, hipMemcpyHostToDevice),
+                     "init_laser");
+}
+
+bf_status bf_add_station(bf_sim* s, const bf_station* st_, int* id)
+{
+    bf_status st = guard(s);
+    if (st != BF_OK) return st;
+    if (!st_ || s->nst >= s->L.nst) return fail(s, BF_EINVAL, "no station slot left");
+    s->st_z.push_back(st_->z_lab_um);
+    hipError_t e = hipMemcpy(s->w<double>(s->L.w_st_z), s->st_z.data(), s->st_z.size() * 8, hipMemcpyHostToDevice);
+    if (id) *id = s->nst;
+    s->nst++;
+    return hip_check(s, e, "add_station");
+}
+
+bf_status bf_load_electrons(bf_sim* s, int64_t n, const uint32_t* id, const double* x, const double* z,
+                            const double* ux, const double* uy, const double* uz, const double* w)
+{
+    bf_status st = guard(s);
+    if (st != BF_OK) return st;
+    if (n < 0 || n > s->L.cap || (n > 0 && (!x || !z || !ux || !uy || !uz || !w)))
+        return fail(s, BF_EINVAL, "bad particle arrays");
+    const bool f32 = s->cfg.real_bytes == 4;
+    std::vector<double> hx(n), hz(n);
+    std::vector<float> f[4];
+    std::vector<double> d[4];
+    std::vector<uint32_t> hid(n);
+    const double* src[4] = {ux, uy, uz, w};
+    for (int q = 0; q < 4; q++) { if (f32) f[q].resize(n); else d[q].resize(n); }
+    for (int64_t p = 0; p < n; p++) {
+        hx[p] = x[p] / s->cfg.dx_um;
+        hz[p] = z[p] / s->cfg.dz_um;
+        for (int q = 0; q < 4; q++) { if (f32) f[q][p] = (float)src[q][p]; else d[q][p] = src[q][p]; }
+        hid[p] = id ? id[p] : (uint32_t)p;
+    }
+    char* b = (char*)s->buf[1 + s->p_cur];
+    hipError_t e = hipSuccess;
+    const size_t rb = s->cfg.real_bytes;
+    if (n > 0) {
+        e = hipMemcpy(b + s->L.e_off[0], hx.data(), n * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(b + s->L.e_off[1], hz.data(), n * 8, hipMemcpyHostToDevice);
+        for (int q = 0; q < 4 && e == hipSuccess; q++)
+            e = hipMemcpy(b + s->L.e_off[2 + q], f32 ? (void*)f[q].data() : (void*)d[q].data(), n * rb,
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(b + s->L.e_off[6], hid.data(), n * 4, hipMemcpyHostToDevice);
+    }
+    // one segment per 1024 particles, then a sort into tiles
+    std::vector<Segment> sg;
+    for (int64_t p = 0; p < n; p += 1024) sg.push_back(Segment{(int)p, (int)std::min<int64_t>(1024, n - p)});
+    if (e == hipSuccess && !sg.empty())
+        e = hipMemcpy(seg_e(s, s->sg_cur), sg.data(), sg.size() * sizeof(Segment), hipMemcpyHostToDevice);
+    int nu = (int)n;
+    if (e == hipSuccess) e = hipMemcpy(nused_e(s), &nu, sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_check(s, e, "load_electrons");
+    if ((int)sg.size() > s->L.seg_cap) return fail(s, BF_EINVAL, "too many particles for the segment table");
+    s->nseg_e = (int)sg.size();
+    if (f32) sort_now<float>(s); else sort_now<double>(s);
+    return hip_check(s, hipStreamSynchronize(s->stream), "load_electrons");
+}
+
+bf_status bf_step(bf_sim* s, int nsteps)
+{
+    bf_status st = guard(s);
+    if (st != BF_OK) return st;
+    if (nsteps < 0) return fail(s, BF_EINVAL, "negative step count");
+    if (s->cfg.real_bytes == 4) st = step_impl<float>(s, nsteps);
+    else st = step_impl<double>(s, nsteps);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_check(s, e, "step launch");
+    return st;
+}
+
+bf_status bf_sync_status(bf_sim* s)
+{
+    if (!s) return BF_EINVAL;
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_check(s, e, "sync");
+    int word = 0;
+    e = hipMemcpy(&word, status_word(s), sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_check(s, e, "sync");
+    if (word & ST_CAPACITY) { s->err = BF_ECAPACITY; s->msg = "particle capacity exceeded"; return BF_ECAPACITY; }
+    if (word & ST_NONFINITE) { s->err = BF_ENONFINITE; s->msg = "non-finite particle momentum"; return BF_ENONFINITE; }
+    return s->err == BF_OK ? BF_OK : (bf_status)s->err;
+}
+
+}  // extern "C"
+
+// ---- diagnostics ----------------------------------------------------------------------------
+
+static void field_ptr_of(const bf_sim* s, int id, int* arr_index)
+{
+    const int e = s->e_cur, b = s->b_cur, eb = s->eb_cur;
+    int a = -1;
+    switch (id) {
+    case BF_F_EX: case BF_F_EY: case BF_F_EZ: a = (e ? A_E1 : A_E0) + (id - BF_F_EX); break;
+    case BF_F_EXO: case BF_F_EYO: case BF_F_EZO: a = (e ? A_E0 : A_E1) + (id - BF_F_EXO); break;
+    case BF_F_BX: case BF_F_BY: case BF_F_BZ: a = (b ? A_B1 : A_B0) + (id - BF_F_BX); break;
+    case BF_F_BXO: case BF_F_BYO: case BF_F_BZO: a = (b ? A_B0 : A_B1) + (id - BF_F_BXO); break;
+    case BF_F_EXB: case BF_F_EYB: case BF_F_EZB: a = (eb ? A_EB1 : A_EB0) + (id - BF_F_EXB); break;
+    case BF_F_JX: case BF_F_JY: case BF_F_JZ:
+        a = (s->cfg.filter_npass > 0 ? A_JF : A_J) + (id - BF_F_JX); break;
+    case BF_F_BYX: a = A_BYX; break;
+    case BF_F_EYX: a = A_EYX; break;
+    default: a = -1;
+    }
+    *arr_index = a;
+}
+
+static bf_status read_field(bf_sim* s, int a, double* out)
+{
+    const Layout& L = s->L;
+    std::vector<char> raw(L.field_array);
+    hipError_t e = hipMemcpy(raw.data(), s->fields() + L.field_array * a, L.field_array, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_check(s, e, "read field");
+    for (int k = 0; k < L.Sz; k++) {
+        const int pr = (k + s->g.zoff) % L.Sz;
+        for (int i = 0; i < L.Sx; i++) {
+            const size_t o = (size_t)pr * L.pitch + i;
+            out[(size_t)k * L.Sx + i] = L.real == 4 ? (double)((float*)raw.data())[o] : ((double*)raw.data())[o];
+        }
+    }
+    return BF_OK;
+}
+
+static bf_status read_particles(bf_sim* s, int species, std::vector<double>* cols, int64_t* nlive)
+{
+    const Layout& L = s->L;
+    int nu[2] = {0, 0};
+    hipError_t e = hipMemcpy(nu, nused_e(s), 2 * sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_check(s, e, "read counts");
+    const int n = std::min<int64_t>(species == 0 ? nu[0] : nu[1], L.cap);
+    const bool f32 = L.real == 4;
+    char* b = (char*)s->buf[(species == 0 ? 1 : 3) + s->p_cur];
+    std::vector<double> x(n), z(n);
+    std::vector<char> w(n * (size_t)L.real);
+    std::vector<uint32_t> id(n);
+    std::vector<char> u[3];
+    Chk ck;
+    if (n > 0) {
+        ck(hipMemcpy(x.data(), b + (species == 0 ? L.e_off[0] : L.i_off[0]), n * 8, hipMemcpyDeviceToHost));
+        ck(hipMemcpy(z.data(), b + (species == 0 ? L.e_off[1] : L.i_off[1]), n * 8, hipMemcpyDeviceToHost));
+        ck(hipMemcpy(w.data(), b + (species == 0 ? L.e_off[5] : L.i_off[2]), n * (size_t)L.real,
+                     hipMemcpyDeviceToHost));
+        ck(hipMemcpy(id.data(), b + (species == 0 ? L.e_off[6] : L.i_off[3]), n * 4, hipMemcpyDeviceToHost));
+        if (species == 0)
+            for (int q = 0; q < 3; q++) {
+                u[q].resize(n * (size_t)L.real);
+                ck(hipMemcpy(u[q].data(), b + L.e_off[2 + q], n * (size_t)L.real, hipMemcpyDeviceToHost));
+            }
+    }
+    e = ck.e;
+    if (e != hipSuccess) return hip_check(s, e, "read particles");
+    auto rd = [&](const std::vector<char>& v, int p) {
+        return f32 ? (double)((const float*)v.data())[p] : ((const double*)v.data())[p];
+    };
+    for (int q = 0; q < 7; q++) cols[q].clear();
+    const double zsh = ion_shift(s, s->t);
+    const int Nx = s->cfg.nx, Nz = s->cfg.nz;
+    const bool perx = s->cfg.periodic_mask & 1, perz = (s->cfg.periodic_mask >> 2) & 1;
+    for (int p = 0; p < n; p++) {
+        const double wv = rd(w, p);
+        if (wv == 0.0) continue;
+        double xc = x[p], zc = species == 0 ? z[p] : z[p] - zsh;
+        if (perx) { xc = std::fmod(xc, (double)Nx); if (xc < 0) xc += Nx; if (xc >= Nx) xc -= Nx; }
+        if (perz) { zc = std::fmod(zc, (double)Nz); if (zc < 0) zc += Nz; if (zc >= Nz) zc -= Nz; }
+        cols[0].push_back((double)id[p]);
+        cols[1].push_back(xc * s->cfg.dx_um);
+        cols[2].push_back(zc * s->cfg.dz_um);
+        if (species == 0) {
+            cols[3].push_back(rd(u[0], p));
+            cols[4].push_back(rd(u[1], p));
+            cols[5].push_back(rd(u[2], p));
+        } else {
+            cols[3].push_back(0.0);
+            cols[4].push_back(0.0);
+            cols[5].push_back(-s->gamma * s->beta);
+        }
+        cols[6].push_back(wv);
+    }
+    *nlive = (int64_t)cols[0].size();
+    return BF_OK;
+}
+
+template <typename R>
+static bf_status gauss_impl(bf_sim* s, double* out)
+{
+    const Layout& L = s->L;
+    const size_t grid = (size_t)L.Sx * L.Sz;
+    double* rho = s->w<double>(L.w_rho);
+    double* rhof = rho + grid;
+    Chk ck;
+    ck(hipMemsetAsync(rho, 0, sizeof(double) * grid, s->stream));
+    int nu[2] = {0, 0};
+    ck(hipMemcpy(nu, nused_e(s), 2 * sizeof(int), hipMemcpyDeviceToHost));
+    if (ck.e != hipSuccess) return hip_check(s, ck.e, "gauss");
+    Geo g0 = s->g;
+    g0.zoff = 0;
+    g0.pitch = L.Sx;
+    const double inv_cell = 1.0 / (s->cfg.dx_um * s->cfg.dz_um);
+    const int ni = (s->have_plasma && s->plasma.ion_mode == 1) ? nu[1] : 0;
+    double za = 0.0;
+    int na = 0;
+    if (s->have_laser) {
+        za = (s->za_lab / s->gamma - s->beta * s->t) / s->cfg.dz_um - (double)s->shift;
+        if (za >= 0.0 && za < s->cfg.nz) na = s->cfg.nx;
+    }
+    launch_rho<R>(g0, electrons<R>(s, s->p_cur), nu[0], ions<R>(s, s->p_cur), ni, ion_shift(s, s->t),
+                  s->w<double>(L.w_ant), na, 0.5, za, s->aw, inv_cell, rho, s->stream);
+    double* res = rho;
+    if (s->cfg.filter_npass > 0) {
+        double* in[3] = {rho, rho, rho};
+        double* o3[3] = {rhof, rhof, rhof};
+        const int hx[3] = {0, 0, 0}, hz[3] = {0, 0, 0};
+        launch_filter<double>(g0, in, o3, hx, hz, 1, s->cfg.filter_npass, s->cfg.filter_compensate,
+                              s->stream);
+        res = rhof;
+    }
+    ck(hipStreamSynchronize(s->stream));
+    std::vector<double> r(grid), ex(grid), ez(grid);
+    ck(hipMemcpy(r.data(), res, grid * 8, hipMemcpyDeviceToHost));
+    if (ck.e != hipSuccess) return hip_check(s, ck.e, "gauss");
+    int a;
+    field_ptr_of(s, BF_F_EX, &a);
+    bf_status st = read_field(s, a, ex.data());
+    if (st != BF_OK) return st;
+    field_ptr_of(s, BF_F_EZ, &a);
+    st = read_field(s, a, ez.data());
+    if (st != BF_OK) return st;
+    const bool perx = s->cfg.periodic_mask & 1, perz = (s->cfg.periodic_mask >> 2) & 1;
+    for (int k = 0; k < L.Sz; k++)
+        for (int i = 0; i < L.Sx; i++) {
+            int il = i - 1, kl = k - 1;
+            if (perx) il = (il + L.Sx) % L.Sx;
+            if (perz) kl = (kl + L.Sz) % L.Sz;
+            const double exl = il >= 0 ? ex[(size_t)k * L.Sx + il] : 0.0;
+            const double ezl = kl >= 0 ? ez[(size_t)kl * L.Sx + i] : 0.0;
+            const double div = (ex[(size_t)k * L.Sx + i] - exl) / s->cfg.dx_um +
+                               (ez[(size_t)k * L.Sx + i] - ezl) / s->cfg.dz_um;
+            out[(size_t)k * L.Sx + i] = div - r[(size_t)k * L.Sx + i];
+        }
+    return hip_check(s, hipGetLastError(), "gauss");
+}
+
+extern "C" {
+
+bf_status bf_diagnose(bf_sim* s, int kind, int arg, void* host_out, size_t bytes)
+{
+    if (!s || !host_out) return BF_EINVAL;
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_check(s, e, "diagnose");
+    const Layout& L = s->L;
+    const size_t grid = (size_t)L.Sx * L.Sz;
+    switch (kind) {
+    case BF_DIAG_FIELD: {
+        int a;
+        field_ptr_of(s, arg, &a);
+        if (a < 0) return fail(s, BF_EINVAL, "bad field id");
+        if (bytes < grid * 8) return fail(s, BF_EINVAL, "buffer too small");
+        return read_field(s, a, (double*)host_out);
+    }
+    case BF_DIAG_COUNTS: {
+        if (bytes < 4 * sizeof(int64_t)) return fail(s, BF_EINVAL, "buffer too small");
+        std::vector<double> cols[7];
+        int64_t ne = 0, ni = 0;
+        bf_status st = read_particles(s, 0, cols, &ne);
+        if (st != BF_OK) return st;
+        if (s->have_plasma && s->plasma.ion_mode == 1) {
+            st = read_particles(s, 1, cols, &ni);
+            if (st != BF_OK) return st;
+        }
+        int nu[2] = {0, 0};
+        e = hipMemcpy(nu, nused_e(s), 2 * sizeof(int), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_check(s, e, "counts");
+        int64_t* o = (int64_t*)host_out;
+        o[0] = ne; o[1] = ni; o[2] = nu[0]; o[3] = nu[1];
+        return BF_OK;
+    }
+    case BF_DIAG_PARTICLES: {
+        std::vector<double> cols[7];
+        int64_t n = 0;
+        bf_status st = read_particles(s, arg, cols, &n);
+        if (st != BF_OK) return st;
+        if (bytes < (size_t)n * 7 * 8) return fail(s, BF_EINVAL, "buffer too small");
+        double* o = (double*)host_out;
+        for (int q = 0; q < 7; q++) std::memcpy(o + (size_t)q * n, cols[q].data(), n * 8);
+        return BF_OK;
+    }
+    case BF_DIAG_STATION: {
+        if (arg < 0 || arg >= s->nst) return fail(s, BF_EINVAL, "bad station");
+        int cnt = 0;
+        e = hipMemcpy(&cnt, s->w<int>(L.w_st_cnt) + arg, sizeof(int), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_check(s, e, "station");
+        if (bytes < 8 + (size_t)cnt * 7 * 8) return fail(s, BF_EINVAL, "buffer too small");
+        *(int64_t*)host_out = cnt;
+        if (cnt > 0)
+            e = hipMemcpy((char*)host_out + 8, s->w<double>(L.w_st_rec) + (size_t)arg * L.stcap * 7,
+                          (size_t)cnt * 7 * 8, hipMemcpyDeviceToHost);
+        return hip_check(s, e, "station");
+    }
+    case BF_DIAG_ENERGY: {
+        if (bytes < 3 * 8) return fail(s, BF_EINVAL, "buffer too small");
+        std::vector<double> f(grid);
+        double ue = 0, ub = 0;
+        const int ids[6] = {BF_F_EX, BF_F_EY, BF_F_EZ, BF_F_BX, BF_F_BY, BF_F_BZ};
+        for (int q = 0; q < 6; q++) {
+            int a;
+            field_ptr_of(s, ids[q], &a);
+            bf_status st = read_field(s, a, f.data());
+            if (st != BF_OK) return st;
+            double acc = 0;
+            for (double v : f) acc += v * v;
+            (q < 3 ? ue : ub) += acc;
+        }
+        std::vector<double> cols[7];
+        int64_t n = 0;
+        bf_status st = read_particles(s, 0, cols, &n);
+        if (st != BF_OK) return st;
+        double k = 0;
+        for (int64_t p = 0; p < n; p++) {
+            const double ux = cols[3][p], uy = cols[4][p], uz = cols[5][p];
+            k += cols[6][p] * (std::sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
+        }
+        const double dv = s->cfg.dx_um * s->cfg.dz_um;
+        double* o = (double*)host_out;
+        o[0] = 0.5 * ue * dv; o[1] = 0.5 * ub * dv; o[2] = k;
+        return BF_OK;
+    }
+    case BF_DIAG_GAUSS: {
+        if (bytes < grid * 8) return fail(s, BF_EINVAL, "buffer too small");
+        return L.real == 4 ? gauss_impl<float>(s, (double*)host_out) : gauss_impl<double>(s, (double*)host_out);
+    }
+    case BF_DIAG_INFO: {
+        if (bytes < sizeof(bf_info)) return fail(s, BF_EINVAL, "buffer too small");
+        bf_info* o = (bf_info*)host_out;
+        std::memset(o, 0, sizeof *o);
+        o->dt = s->dt; o->dt_crit = s->dt_crit; o->beta = s->beta; o->gamma = s->gamma;
+        o->v_window = s->vw; o->n0_norm = s->n0; o->e0_norm = s->e0; o->omega = s->omega;
+        o->alpha2 = s->a2; o->beta2 = s->b2; o->antenna_weight = s->aw;
+        o->stored_x = L.Sx; o->stored_z = L.Sz; o->pml_x = L.Px; o->pml_z = L.Pz;
+        o->step = s->step; o->time = s->t; o->shift = s->shift; o->next_row = s->next_row;
+        o->tile_x = L.tile_x; o->tile_z = L.tile_z; o->ntiles = L.ntiles; o->sort_every = s->sort_every;
+        return BF_OK;
+    }
+    case BF_DIAG_ANTENNA: {
+        if (!s->have_laser) return fail(s, BF_EINVAL, "no laser");
+        if (bytes < (size_t)s->cfg.nx * 8) return fail(s, BF_EINVAL, "buffer too small");
+        std::vector<double> xm(s->cfg.nx);
+        e = hipMemcpy(xm.data(), s->w<double>(L.w_ant), xm.size() * 8, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_check(s, e, "antenna");
+        for (int i = 0; i < s->cfg.nx; i++) ((double*)host_out)[i] = xm[i] * s->cfg.dx_um;
+        return BF_OK;
+    }
+    case BF_DIAG_TIMERS: {
+        if (bytes < sizeof(double) * 2 * BF_PHASE_COUNT) return fail(s, BF_EINVAL, "buffer too small");
+        e = s->fold_marks();
+        if (e != hipSuccess) return hip_check(s, e, "timers");
+        double* o = (double*)host_out;
+        for (int q = 0; q < BF_PHASE_COUNT; q++) { o[2 * q] = s->tacc[q]; o[2 * q + 1] = s->tcnt[q]; }
+        if (arg) for (int q = 0; q < BF_PHASE_COUNT; q++) { s->tacc[q] = 0.0; s->tcnt[q] = 0.0; }
+        return BF_OK;
+    }
+    default:
+        return fail(s, BF_EINVAL, "unknown diagnostic");
+    }
+}
+
+bf_status bf_set_field(bf_sim* s, int field, const double* in, size_t bytes)
+{
+    bf_status st = guard(s);
+    if (st != BF_OK) return st;
+    const Layout& L = s->L;
+    if (!in || bytes < (size_t)L.Sx * L.Sz * 8) return fail(s, BF_EINVAL, "buffer too small");
+    int a;
+    field_ptr_of(s, field, &a);
+    if (a < 0) return fail(s, BF_EINVAL, "bad field id");
+    hipError_t e = hipStreamSynchronize(s->stream);
+    std::vector<char> raw(L.field_array, 0);
+    for (int k = 0; k < L.Sz; k++) {
+        const int pr = (k + s->g.zoff) % L.Sz;
+        for (int i = 0; i < L.Sx; i++) {
+            const size_t o = (size_t)pr * L.pitch + i;
+            const double v = in[(size_t)k * L.Sx + i];
+            if (L.real == 4) ((float*)raw.data())[o] = (float)v;
+            else ((double*)raw.data())[o] = v;
+        }
+    }
+    if (e == hipSuccess)
+        e = hipMemcpy(s->fields() + L.field_array * a, raw.data(), L.field_array, hipMemcpyHostToDevice);
+    return hip_check(s, e, "set_field");
+}
+
+bf_status bf_get_state(const bf_sim* s, bf_state* o)
+{
+    if (!s || !o) return BF_EINVAL;
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return BF_EDEVICE;
+    std::memset(o, 0, sizeof *o);
+    o->abi_version = BF_ABI_VERSION;
+    o->struct_size = sizeof(bf_state);
+    o->step = s->step; o->time = s->t; o->shift = s->shift; o->next_row = s->next_row;
+    o->zoff = s->g.zoff;
+    o->e_cur = s->e_cur | (s->eb_cur << 1) | (s->bb_cur << 2) | (s->sg_cur << 3);
+    o->b_cur = s->b_cur;
+    o->p_cur = s->p_cur;
+    o->nseg_e = s->nseg_e; o->nseg_i = s->nseg_i; o->since_sort = s->since_sort;
+    o->have_plasma = s->have_plasma; o->have_laser = s->have_laser; o->nstations = s->nst;
+    return BF_OK;
+}
+
+bf_status bf_set_state(bf_sim* s, const bf_state* in)
+{
+    if (!s || !in || in->abi_version != BF_ABI_VERSION || in->struct_size != sizeof(bf_state)) return BF_EINVAL;
+    if (in->zoff < 0 || in->zoff >= s->L.Sz || in->nseg_e < 0 || in->nseg_e > s->L.seg_cap) return BF_EINVAL;
+    s->step = in->step; s->t = in->time; s->shift = in->shift; s->next_row = in->next_row;
+    s->g.zoff = in->zoff;
+    s->e_cur = in->e_cur & 1; s->eb_cur = (in->e_cur >> 1) & 1; s->bb_cur = (in->e_cur >> 2) & 1;
+    s->sg_cur = (in->e_cur >> 3) & 1;
+    s->b_cur = in->b_cur & 1; s->p_cur = in->p_cur & 1;
+    s->nseg_e = in->nseg_e; s->nseg_i = in->nseg_i; s->since_sort = in->since_sort;
+    return BF_OK;
+}
+
+}  // extern "C"

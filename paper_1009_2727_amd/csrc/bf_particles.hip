@@ -1,0 +1,858 @@
+// bf_particles.hip -- particle kernels of the boosted-frame PIC step for gfx950.
+//
+//  * k_gpd: one workgroup per particle segment (a tile after the last sort, or a row chunk
+//    injected since).  The segment's bounding box plus a halo is staged in LDS: E^n and
+//    B^n = (B^{n-1/2} + B^{n+1/2})/2 (6 components) for the cubic "energy-conserving" gather
+//    straight from the staggered Yee locations (Sec. 5.1), and a zeroed J tile (3
+//    components).  Each thread then pushes particles (Boris), deposits the Esirkepov current
+//    (charge-conserving, Sec. 4.2.2) into the LDS tile with LDS atomics, writes the particle
+//    back (positions FP64, rebased by the window shift), and the tile is flushed to HBM with
+//    global atomics.  A segment whose box does not fit the LDS budget (or a particle outside
+//    its box) takes the same code with global memory accessors.
+//  * k_ions: rigid ions (at rest in the lab) deposit their J_z from z0 - beta c t.
+//  * k_antenna: the laser antenna's +/- sheet particles (Sec. 3.1.2), in FP64 per pair.
+//  * k_inject: creates plasma lattice rows at the front plane (Sec. 3.1.1).
+//  * k_sort_*: counting sort by tile (histogram, scan, scatter) that also drops absorbed
+//    particles and folds periodic coordinates back into the box.
+#include <climits>
+#include "bf_kernels.h"
+
+namespace bf {
+
+constexpr int NTHR = 256;
+
+// ---- accessors ---------------------------------------------------------------------------
+// field component ids inside the staged tile: 0..2 E, 3..5 B (time-centred)
+template <typename R>
+struct LdsAcc {
+    R* f;       // 6 x L
+    R* j;       // 3 x L
+    int xb, zb, lx, lz, L;
+    __device__ __forceinline__ bool inside(int jx0, int jx1, int jz0, int jz1) const
+    {
+        return jx0 >= xb && jx1 < xb + lx && jz0 >= zb && jz1 < zb + lz;
+    }
+    __device__ __forceinline__ R fld(int c, int jx, int jz) const
+    {
+        return f[c * L + (jz - zb) * lx + (jx - xb)];
+    }
+    __device__ __forceinline__ void dep(int c, int jx, int jz, R v) const
+    {
+        atomicAdd(&j[c * L + (jz - zb) * lx + (jx - xb)], v);
+    }
+};
+
+template <typename R>
+struct GlobAcc {
+    Geo g;
+    const R* E[3];
+    const R* B[3];
+    const R* Bn[3];
+    R* J[3];
+    __device__ __forceinline__ bool inside(int, int, int, int) const { return true; }
+    __device__ __forceinline__ R fld(int c, int jx, int jz) const
+    {
+        int i = swrap(jx + g.Px, g.Sx, g.perx), k = swrap(jz + g.Pz, g.Sz, g.perz);
+        if (i < 0 || k < 0) return R(0);
+        long o = gofs(g, i, k);
+        if (c < 3) return E[c][o];
+        return R(0.5) * (B[c - 3][o] + Bn[c - 3][o]);
+    }
+    __device__ __forceinline__ void dep(int c, int jx, int jz, R v) const
+    {
+        int i = swrap(jx + g.Px, g.Sx, g.perx), k = swrap(jz + g.Pz, g.Sz, g.perz);
+        if (i < 0 || k < 0) return;
+        atomicAdd(&J[c][gofs(g, i, k)], v);
+    }
+};
+
+template <typename R>
+__device__ __forceinline__ GlobAcc<R> make_glob(const Geo& g, const FieldSet<R>& f)
+{
+    GlobAcc<R> a;
+    a.g = g;
+    for (int c = 0; c < 3; c++) {
+        a.E[c] = f.E[c];
+        a.B[c] = f.B[c];
+        a.Bn[c] = f.Bn[c];
+        a.J[c] = f.J[c];
+    }
+    return a;
+}
+
+// shape factors of a particle on the 5-node window starting at node `base`:
+// nonzero at offsets o-1 .. o+2 where o = i - base (1 or 2)
+template <typename R>
+__device__ __forceinline__ void window5(R f, int o, R s[5])
+{
+    R w[4];
+    bspline3(f, w);
+    if (o == 1) { s[0] = w[0]; s[1] = w[1]; s[2] = w[2]; s[3] = w[3]; s[4] = R(0); }
+    else        { s[0] = R(0); s[1] = w[0]; s[2] = w[1]; s[3] = w[2]; s[4] = w[3]; }
+}
+
+// Esirkepov (2001) current of one particle moving (ix+fx, iz+fz) -> (ix1+fx1, iz1+fz1),
+// |displacement| < 1 cell per axis.  2-1/2D form:
+//   W_x = DS_x (S0_z + DS_z/2),  W_z = DS_z (S0_x + DS_x/2),
+//   W_y = S0_x S0_z + DS_x S0_z/2 + S0_x DS_z/2 + DS_x DS_z/3,
+//   J_x(i+1/2) - J_x(i-1/2) = cx W_x(i), J_z likewise, J_y = cy W_y.
+template <typename R, typename A>
+__device__ __forceinline__ void esirkepov(const A& acc, int ix, R fx, int iz, R fz, int ix1, R fx1,
+                                          int iz1, R fz1, R cx, R cz, R cy)
+{
+    const int bx = min(ix, ix1) - 1, bz = min(iz, iz1) - 1;
+    R S0x[5], S1x[5], S0z[5], S1z[5];
+    window5(fx, ix - bx, S0x);
+    window5(fx1, ix1 - bx, S1x);
+    window5(fz, iz - bz, S0z);
+    window5(fz1, iz1 - bz, S1z);
+    R DSx[5], DSz[5];
+#pragma unroll
+    for (int m = 0; m < 5; m++) { DSx[m] = S1x[m] - S0x[m]; DSz[m] = S1z[m] - S0z[m]; }
+    if (cx != R(0)) {
+#pragma unroll
+        for (int b = 0; b < 5; b++) {
+            R zf = S0z[b] + R(0.5) * DSz[b];
+            R acc_ = R(0);
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+                acc_ += DSx[m] * zf;
+                acc.dep(0, bx + m, bz + b, cx * acc_);
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 5; m++) {
+        R xf = S0x[m] + R(0.5) * DSx[m];
+        R acc_ = R(0);
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            acc_ += DSz[b] * xf;
+            acc.dep(2, bx + m, bz + b, cz * acc_);
+        }
+    }
+    if (cy != R(0)) {
+        const R third = R(1) / R(3);
+#pragma unroll
+        for (int m = 0; m < 5; m++)
+#pragma unroll
+            for (int b = 0; b < 5; b++) {
+                R W = S0x[m] * S0z[b] + R(0.5) * DSx[m] * S0z[b] + R(0.5) * S0x[m] * DSz[b]
+                    + third * DSx[m] * DSz[b];
+                acc.dep(1, bx + m, bz + b, cy * W);
+            }
+    }
+}
+
+// gather E^n, B^n at (x, z) (cells) with cubic weights at each component's stagger
+template <typename R, typename A>
+__device__ __forceinline__ void gather(const A& acc, double x, double z, R E[3], R B[3])
+{
+    const int ix = (int)floor(x), iz = (int)floor(z);
+    const double xh = x - 0.5, zh = z - 0.5;
+    const int ixh = (int)floor(xh), izh = (int)floor(zh);
+    R wxn[4], wxh[4], wzn[4], wzh[4];
+    bspline3((R)(x - ix), wxn);
+    bspline3((R)(xh - ixh), wxh);
+    bspline3((R)(z - iz), wzn);
+    bspline3((R)(zh - izh), wzh);
+    R e0 = 0, e1 = 0, e2 = 0, b0 = 0, b1 = 0, b2 = 0;
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+        R ex = 0, ey = 0, ez = 0, bx = 0, by = 0, bz = 0;
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+            ex += wxh[a] * acc.fld(0, ixh - 1 + a, iz - 1 + b);
+            ey += wxn[a] * acc.fld(1, ix - 1 + a, iz - 1 + b);
+            bz += wxh[a] * acc.fld(5, ixh - 1 + a, iz - 1 + b);
+            ez += wxn[a] * acc.fld(2, ix - 1 + a, izh - 1 + b);
+            bx += wxn[a] * acc.fld(3, ix - 1 + a, izh - 1 + b);
+            by += wxh[a] * acc.fld(4, ixh - 1 + a, izh - 1 + b);
+        }
+        e0 += wzn[b] * ex; e1 += wzn[b] * ey; b2 += wzn[b] * bz;
+        e2 += wzh[b] * ez; b0 += wzh[b] * bx; b1 += wzh[b] * by;
+    }
+    E[0] = e0; E[1] = e1; E[2] = e2;
+    B[0] = b0; B[1] = b1; B[2] = b2;
+}
+
+// Boris rotation (q/m folded into h = q dt / 2m)
+template <typename R>
+__device__ __forceinline__ void boris(R h, const R E[3], const R B[3], R& ux, R& uy, R& uz)
+{
+    R umx = ux + h * E[0], umy = uy + h * E[1], umz = uz + h * E[2];
+    R g = sqrt(R(1) + umx * umx + umy * umy + umz * umz);
+    R ig = R(1) / g;
+    R tx = h * B[0] * ig, ty = h * B[1] * ig, tz = h * B[2] * ig;
+    R t2 = tx * tx + ty * ty + tz * tz;
+    R sf = R(2) / (R(1) + t2);
+    R sx = sf * tx, sy = sf * ty, sz = sf * tz;
+    R upx = umx + (umy * tz - umz * ty);
+    R upy = umy + (umz * tx - umx * tz);
+    R upz = umz + (umx * ty - umy * tx);
+    R uqx = umx + (upy * sz - upz * sy);
+    R uqy = umy + (upz * sx - upx * sz);
+    R uqz = umz + (upx * sy - upy * sx);
+    ux = uqx + h * E[0];
+    uy = uqy + h * E[1];
+    uz = uqz + h * E[2];
+}
+
+// one electron: gather, push, deposit, absorb.  Returns false if absorbed.
+template <typename R, typename A, typename G>
+__device__ __forceinline__ bool advance_electron(const A& lds, const G& glb, const Geo& g,
+                                                 const PushParams<R>& pp, double& x, double& z,
+                                                 R& ux, R& uy, R& uz, R w, int* status)
+{
+    const int ix = (int)floor(x), iz = (int)floor(z);
+    R E[3], B[3];
+    if (lds.inside(ix - 2, ix + 2, iz - 2, iz + 2)) gather(lds, x, z, E, B);
+    else gather(glb, x, z, E, B);
+    boris(pp.qdt2, E, B, ux, uy, uz);
+    const R ig = R(1) / sqrt(R(1) + ux * ux + uy * uy + uz * uz);
+    const R vx = ux * ig, vy = uy * ig, vz = uz * ig;
+    if (!isfinite(ux + uy + uz)) atomicOr(status, ST_NONFINITE);
+    const double x1 = x + (double)(pp.dtdx * vx), z1 = z + (double)(pp.dtdz * vz);
+    const int ix1 = (int)floor(x1), iz1 = (int)floor(z1);
+    const R fx = (R)(x - ix), fz = (R)(z - iz), fx1 = (R)(x1 - ix1), fz1 = (R)(z1 - iz1);
+    const R cx = pp.fjx * w, cz = pp.fjz * w, cy = pp.fjy * w * vy;
+    const int bx = min(ix, ix1) - 1, bz = min(iz, iz1) - 1;
+    if (lds.inside(bx, bx + 4, bz, bz + 4) && abs(ix1 - ix) <= 1 && abs(iz1 - iz) <= 1)
+        esirkepov(lds, ix, fx, iz, fz, ix1, fx1, iz1, fz1, cx, cz, cy);
+    else
+        esirkepov(glb, ix, fx, iz, fz, ix1, fx1, iz1, fz1, cx, cz, cy);
+    x = x1;
+    z = z1;
+    bool alive = true;
+    if (!g.perx && (x1 < 0.0 || x1 >= (double)g.Nx)) alive = false;
+    if (!g.perz && (z1 < 0.0 || z1 >= (double)g.Nz)) alive = false;
+    return alive;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NTHR) k_gpd(Geo g, FieldSet<R> f, ElectronArrays<R> e,
+                                              const Segment* __restrict__ seg,
+                                              const int4* __restrict__ bbin, int4* __restrict__ bbout,
+                                              PushParams<R> pp, int* status)
+{
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ int4 red[NTHR / 64];
+    const int s = blockIdx.x;
+    const Segment sg = seg[s];
+    const int4 bb = bbin[s];
+    if (sg.count <= 0 || bb.x > bb.y || bb.z > bb.w) {
+        if (threadIdx.x == 0) bbout[s] = make_int4(INT_MAX, INT_MIN, INT_MAX, INT_MIN);
+        return;
+    }
+    const GlobAcc<R> glb = make_glob(g, f);
+    LdsAcc<R> lds;
+    lds.xb = bb.x - 2;
+    lds.zb = bb.z - 2;
+    lds.lx = bb.y - bb.x + 6;
+    lds.lz = bb.w - bb.z + 6;
+    lds.L = lds.lx * lds.lz;
+    const bool use_lds = lds.L <= pp.lds_cells;
+    lds.f = reinterpret_cast<R*>(smem_raw);
+    lds.j = lds.f + 6 * lds.L;
+    if (!use_lds) { lds.lx = 0; lds.lz = 0; }   // every inside() test fails: global path
+    if (use_lds) {
+        for (int q = threadIdx.x; q < lds.L; q += NTHR) {
+            const int a = q % lds.lx, b = q / lds.lx;
+            const int i = swrap(lds.xb + a + g.Px, g.Sx, g.perx);
+            const int k = swrap(lds.zb + b + g.Pz, g.Sz, g.perz);
+            R v[6] = {0, 0, 0, 0, 0, 0};
+            if (i >= 0 && k >= 0) {
+                const long o = gofs(g, i, k);
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    v[c] = f.E[c][o];
+                    v[3 + c] = R(0.5) * (f.B[c][o] + f.Bn[c][o]);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 6; c++) lds.f[c * lds.L + q] = v[c];
+#pragma unroll
+            for (int c = 0; c < 3; c++) lds.j[c * lds.L + q] = R(0);
+        }
+        __syncthreads();
+    }
+    int x0 = INT_MAX, x1 = INT_MIN, z0 = INT_MAX, z1 = INT_MIN;
+    const int end = sg.start + sg.count;
+    for (int p = sg.start + threadIdx.x; p < end; p += NTHR) {
+        const R w = e.w[p];
+        if (w == R(0)) continue;
+        double x = e.x[p], z = e.z[p];
+        R ux = e.ux[p], uy = e.uy[p], uz = e.uz[p];
+        const bool alive = advance_electron(lds, glb, g, pp, x, z, ux, uy, uz, w, status);
+        z -= (double)pp.shift;
+        e.x[p] = x;
+        e.z[p] = z;
+        e.ux[p] = ux;
+        e.uy[p] = uy;
+        e.uz[p] = uz;
+        if (!alive) {
+            e.w[p] = R(0);
+        } else {
+            const int cx = (int)floor(x), cz = (int)floor(z);
+            x0 = min(x0, cx); x1 = max(x1, cx);
+            z0 = min(z0, cz); z1 = max(z1, cz);
+        }
+    }
+    if (use_lds) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < lds.L; q += NTHR) {
+            const int a = q % lds.lx, b = q / lds.lx;
+            const int i = swrap(lds.xb + a + g.Px, g.Sx, g.perx);
+            const int k = swrap(lds.zb + b + g.Pz, g.Sz, g.perz);
+            if (i < 0 || k < 0) continue;
+            const long o = gofs(g, i, k);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const R v = lds.j[c * lds.L + q];
+                if (v != R(0)) atomicAdd(&f.J[c][o], v);
+            }
+        }
+    }
+    block_bbox(x0, x1, z0, z1, red);
+    if (threadIdx.x == 0) bbout[s] = make_int4(x0, x1, z0, z1);
+}
+
+// ---- rigid ions --------------------------------------------------------------------------
+template <typename R, typename A>
+__device__ __forceinline__ void ion_current(const A& acc, int ix, R fx, int iz, R fz, int iz1, R fz1,
+                                            R cz)
+{
+    const int bx = ix - 1, bz = min(iz, iz1) - 1;
+    R Sx[5], S0z[5], S1z[5];
+    window5(fx, 1, Sx);
+    window5(fz, iz - bz, S0z);
+    window5(fz1, iz1 - bz, S1z);
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+        R acc_ = R(0);
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            acc_ += (S1z[b] - S0z[b]) * Sx[m];
+            acc.dep(2, bx + m, bz + b, cz * acc_);
+        }
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NTHR) k_ions(Geo g, FieldSet<R> f, IonArrays<R> ion,
+                                               const Segment* __restrict__ seg,
+                                               const int4* __restrict__ bbin, int4* __restrict__ bbout,
+                                               double zsh_a, double zsh_b, int shift, R fjz,
+                                               int lds_cells)
+{
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ int4 red[NTHR / 64];
+    const int s = blockIdx.x;
+    const Segment sg = seg[s];
+    const int4 bb = bbin[s];
+    if (sg.count <= 0 || bb.x > bb.y || bb.z > bb.w) {
+        if (threadIdx.x == 0) bbout[s] = make_int4(INT_MAX, INT_MIN, INT_MAX, INT_MIN);
+        return;
+    }
+    GlobAcc<R> glb = make_glob(g, f);
+    LdsAcc<R> lds;
+    lds.xb = bb.x - 2;
+    lds.zb = bb.z - 2;
+    lds.lx = bb.y - bb.x + 6;
+    lds.lz = bb.w - bb.z + 6;
+    lds.L = lds.lx * lds.lz;
+    const bool use_lds = lds.L <= lds_cells;
+    // only J_z (component 2) is staged: point j so that component 2 starts at smem
+    lds.f = nullptr;
+    lds.j = reinterpret_cast<R*>(smem_raw) - 2 * lds.L;
+    if (!use_lds) { lds.lx = 0; lds.lz = 0; }
+    if (use_lds) {
+        R* jz = reinterpret_cast<R*>(smem_raw);
+        for (int q = threadIdx.x; q < lds.L; q += NTHR) jz[q] = R(0);
+        __syncthreads();
+    }
+    int x0 = INT_MAX, x1 = INT_MIN, z0 = INT_MAX, z1 = INT_MIN;
+    const int end = sg.start + sg.count;
+    for (int p = sg.start + threadIdx.x; p < end; p += NTHR) {
+        const R w = ion.w[p];
+        if (w == R(0)) continue;
+        const double x = ion.x[p], zc0 = ion.z0[p];
+        const double za = zc0 - zsh_a, zb = zc0 - zsh_b;
+        const int ix = (int)floor(x), iz = (int)floor(za), iz1 = (int)floor(zb);
+        const R fx = (R)(x - ix), fz = (R)(za - iz), fz1 = (R)(zb - iz1);
+        const int bz = min(iz, iz1) - 1;
+        if (lds.inside(ix - 1, ix + 2, bz, bz + 4) && abs(iz1 - iz) <= 1)
+            ion_current(lds, ix, fx, iz, fz, iz1, fz1, fjz * w);
+        else
+            ion_current(glb, ix, fx, iz, fz, iz1, fz1, fjz * w);
+        bool alive = !(!g.perz && (zb < 0.0 || zb >= (double)g.Nz));
+        if (!alive) {
+            ion.w[p] = R(0);
+        } else {
+            const int cz = (int)floor(zb - (double)shift);
+            x0 = min(x0, ix); x1 = max(x1, ix);
+            z0 = min(z0, cz); z1 = max(z1, cz);
+        }
+    }
+    if (use_lds) {
+        __syncthreads();
+        const R* jz = reinterpret_cast<const R*>(smem_raw);
+        for (int q = threadIdx.x; q < lds.L; q += NTHR) {
+            const R v = jz[q];
+            if (v == R(0)) continue;
+            const int a = q % lds.lx, b = q / lds.lx;
+            const int i = swrap(lds.xb + a + g.Px, g.Sx, g.perx);
+            const int k = swrap(lds.zb + b + g.Pz, g.Sz, g.perz);
+            if (i < 0 || k < 0) continue;
+            atomicAdd(&f.J[2][gofs(g, i, k)], v);
+        }
+    }
+    block_bbox(x0, x1, z0, z1, red);
+    if (threadIdx.x == 0) bbout[s] = make_int4(x0, x1, z0, z1);
+}
+
+// ---- antenna (FP64) ------------------------------------------------------------------------
+__device__ __forceinline__ void bspline3d(double f, double w[4])
+{
+    double g = 1.0 - f, f2 = f * f, f3 = f2 * f;
+    w[0] = g * g * g / 6.0;
+    w[1] = (3.0 * f3 - 6.0 * f2 + 4.0) / 6.0;
+    w[2] = (-3.0 * f3 + 3.0 * f2 + 3.0 * f + 1.0) / 6.0;
+    w[3] = f3 / 6.0;
+}
+
+// add the Esirkepov current of one particle (charge factor q w) into a 6x6 FP64 patch whose
+// lower corner is (px, pz)
+__device__ void esirkepov_patch(double x0, double z0, double x1, double z1, double qw, double vy,
+                                double dx, double dz, double dt, int px, int pz, double jx[6][6],
+                                double jy[6][6], double jz[6][6])
+{
+    const int ix = (int)floor(x0), iz = (int)floor(z0), ix1 = (int)floor(x1), iz1 = (int)floor(z1);
+    if (abs(ix1 - ix) > 1 || abs(iz1 - iz) > 1) return;   // one step moves less than a cell
+    const int bx = min(ix, ix1) - 1, bz = min(iz, iz1) - 1;
+    double S0x[5] = {0, 0, 0, 0, 0}, S1x[5] = {0, 0, 0, 0, 0}, S0z[5] = {0, 0, 0, 0, 0},
+           S1z[5] = {0, 0, 0, 0, 0}, w[4];
+    bspline3d(x0 - ix, w);
+    for (int m = 0; m < 4; m++) S0x[ix - bx - 1 + m] = w[m];
+    bspline3d(x1 - ix1, w);
+    for (int m = 0; m < 4; m++) S1x[ix1 - bx - 1 + m] = w[m];
+    bspline3d(z0 - iz, w);
+    for (int m = 0; m < 4; m++) S0z[iz - bz - 1 + m] = w[m];
+    bspline3d(z1 - iz1, w);
+    for (int m = 0; m < 4; m++) S1z[iz1 - bz - 1 + m] = w[m];
+    const int ox = bx - px, oz = bz - pz;
+    // the 5-node window must sit inside the 6-node patch (caller keeps |drift| < 1/2 cell)
+    if (ox < 0 || ox > 1 || oz < 0 || oz > 1) return;
+    for (int b = 0; b < 5; b++) {
+        double acc = 0.0;
+        for (int m = 0; m < 4; m++) {
+            acc += (S1x[m] - S0x[m]) * (S0z[b] + 0.5 * (S1z[b] - S0z[b]));
+            jx[oz + b][ox + m] -= qw * acc / (dz * dt);
+        }
+    }
+    for (int m = 0; m < 5; m++) {
+        double acc = 0.0;
+        for (int b = 0; b < 4; b++) {
+            acc += (S1z[b] - S0z[b]) * (S0x[m] + 0.5 * (S1x[m] - S0x[m]));
+            jz[oz + b][ox + m] -= qw * acc / (dx * dt);
+        }
+    }
+    if (vy != 0.0)
+        for (int m = 0; m < 5; m++)
+            for (int b = 0; b < 5; b++) {
+                double dsx = S1x[m] - S0x[m], dsz = S1z[b] - S0z[b];
+                jy[oz + b][ox + m] += qw * vy *
+                    (S0x[m] * S0z[b] + 0.5 * dsx * S0z[b] + 0.5 * S0x[m] * dsz + dsx * dsz / 3.0) /
+                    (dx * dz);
+            }
+}
+
+template <typename R>
+__global__ void k_antenna(Geo g, FieldSet<R> f, double* xm, AntennaParams ap)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ap.n) return;
+    const double xh = i + 0.5;                   // home position (cells)
+    const double xum = xh * ap.dx_um;
+    // field to emit: (E0/gamma) f sin(omega t'/gamma - phase) with the lab time elapsed at the
+    // lab-fixed plane t'/gamma; the sheet current is K = -2 E_perp (eps0 = c = 1)
+    const double tau = ap.tmid / ap.gamma - ap.t0;
+    const double env = exp(-(xum - ap.xc_um) * (xum - ap.xc_um) / (ap.w0 * ap.w0)) *
+                       exp(-tau * tau / (2.0 * ap.sig_t * ap.sig_t));
+    const double Ep = (ap.e0 / ap.gamma) * env * sin(ap.omega * tau);
+    const double K = -2.0 * Ep;
+    const double vx = K * ap.dx / (-ap.weight);   // moving sheet has charge -w
+    const double xa = xm[i], xb = xa + vx * ap.dt / ap.dx;
+    double jx[6][6], jy[6][6], jz[6][6];
+    for (int a = 0; a < 6; a++)
+        for (int b = 0; b < 6; b++) { jx[a][b] = 0.0; jy[a][b] = 0.0; jz[a][b] = 0.0; }
+    const int px = (int)floor(xh) - 2;
+    const int pz = (int)floor(fmin(ap.za, ap.zb)) - 1;
+    esirkepov_patch(xa, ap.za, xb, ap.zb, -ap.weight, 0.0, ap.dx, ap.dz, ap.dt, px, pz, jx, jy, jz);
+    esirkepov_patch(xh, ap.za, xh, ap.zb, ap.weight, 0.0, ap.dx, ap.dz, ap.dt, px, pz, jx, jy, jz);
+    xm[i] = xb;
+    for (int b = 0; b < 6; b++)
+        for (int a = 0; a < 6; a++) {
+            const int si = swrap(px + a + g.Px, g.Sx, g.perx), sk = swrap(pz + b + g.Pz, g.Sz, g.perz);
+            if (si < 0 || sk < 0) continue;
+            const long o = gofs(g, si, sk);
+            if (jx[b][a] != 0.0) atomicAdd(&f.J[0][o], (R)jx[b][a]);
+            if (jz[b][a] != 0.0) atomicAdd(&f.J[2][o], (R)jz[b][a]);
+        }
+}
+
+// ---- plasma injection --------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k)
+{
+    // SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output number k of the generator
+    // started at `seed` (state advances by the golden gamma, output = mix(state))
+    uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double u01(uint64_t seed, uint64_t k)
+{
+    return (double)(splitmix64(seed, k) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NTHR) k_inject(Geo g, ElectronArrays<R> e, IonArrays<R> ion,
+                                                 Segment* seg_e, int4* bbox_e, Segment* seg_i,
+                                                 int4* bbox_i, int* nused_e, int* nused_i,
+                                                 InjectParams ip, int* status)
+{
+    __shared__ int sh_start[2];
+    __shared__ int4 red[NTHR / 64];
+    const int chunk = blockIdx.x, r = blockIdx.y;
+    const int64_t row = ip.row0 + r;
+    const int cx0 = chunk * ip.tile_x;
+    const int ncell = min(ip.tile_x, g.Nx - cx0);
+    const int count = ncell * ip.ppc;
+    const int slot = ip.seg_base + r * ip.nchunks + chunk;
+    if (threadIdx.x == 0) {
+        int se = atomicAdd(nused_e, count);
+        int si = ip.ion_mode ? atomicAdd(nused_i, count) : 0;
+        if ((int64_t)se + count > ip.cap || (int64_t)si + count > ip.cap) {
+            atomicOr(status, ST_CAPACITY);
+            se = -1;
+        }
+        sh_start[0] = se;
+        sh_start[1] = si;
+    }
+    __syncthreads();
+    const int se = sh_start[0], si = sh_start[1];
+    if (se < 0) {
+        if (threadIdx.x == 0) {
+            seg_e[slot] = Segment{0, 0};
+            bbox_e[slot] = make_int4(INT_MAX, INT_MIN, INT_MAX, INT_MIN);
+            if (ip.ion_mode) {
+                seg_i[slot] = Segment{0, 0};
+                bbox_i[slot] = make_int4(INT_MAX, INT_MIN, INT_MAX, INT_MIN);
+            }
+        }
+        return;
+    }
+    int x0 = INT_MAX, x1 = INT_MIN, z0 = INT_MAX, z1 = INT_MIN;
+    for (int q = threadIdx.x; q < count; q += NTHR) {
+        const int cell = q / ip.ppc, k = q - cell * ip.ppc;
+        const int ix = cx0 + cell;
+        const uint64_t id = ((uint64_t)row * (uint64_t)g.Nx + (uint64_t)ix) * (uint64_t)ip.ppc + (uint64_t)k;
+        const double rx = u01(ip.seed, 2 * id + 1), rz = u01(ip.seed, 2 * id + 2);
+        const double zbc = (double)row + rz;                 // boosted position at t = 0, cells
+        const double zl = ip.gamma * (zbc * ip.dz_um);       // lab position of the element
+        double n = 0.0;
+        if (zl >= ip.ramp_start) {
+            n = ip.n0;
+            if (ip.ramp_len > 0.0 && zl < ip.ramp_start + ip.ramp_len)
+                n = ip.n0 * (zl - ip.ramp_start) / ip.ramp_len;
+        }
+        const double wgt = ip.wfac * n;
+        const double x = (double)ix + rx;
+        const double z = zbc - ip.beta * ip.t / ip.dz_um - ip.shift;
+        const int p = se + q;
+        e.x[p] = x;
+        e.z[p] = z;
+        e.ux[p] = R(0);
+        e.uy[p] = R(0);
+        e.uz[p] = (R)ip.uz0;
+        e.w[p] = (R)wgt;
+        e.id[p] = (uint32_t)id;
+        if (ip.ion_mode) {
+            const int pi = si + q;
+            ion.x[pi] = x;
+            ion.z0[pi] = zbc;
+            ion.w[pi] = (R)wgt;
+            ion.id[pi] = (uint32_t)id;
+        }
+        if (wgt != 0.0) {
+            const int ci = (int)floor(x), ck = (int)floor(z);
+            x0 = min(x0, ci); x1 = max(x1, ci);
+            z0 = min(z0, ck); z1 = max(z1, ck);
+        }
+    }
+    block_bbox(x0, x1, z0, z1, red);
+    if (threadIdx.x == 0) {
+        seg_e[slot] = Segment{se, count};
+        bbox_e[slot] = make_int4(x0, x1, z0, z1);
+        if (ip.ion_mode) {
+            seg_i[slot] = Segment{si, count};
+            bbox_i[slot] = make_int4(x0, x1, z0, z1);
+        }
+    }
+}
+
+// ---- counting sort by tile ----------------------------------------------------------------------
+__device__ __forceinline__ double fold(double v, int N, int per)
+{
+    if (!per) return v;
+    double r = v - floor(v / (double)N) * (double)N;
+    return r >= (double)N ? r - (double)N : r;
+}
+
+__device__ __forceinline__ int tile_key(double x, double z, const Geo& g, int tx, int tz, int ntx,
+                                        int ntz)
+{
+    int cx = min(max((int)floor(x), 0), g.Nx - 1) / tx;
+    int cz = min(max((int)floor(z), 0), g.Nz - 1) / tz;
+    (void)ntz;
+    return cz * ntx + cx;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NTHR) k_sort_count_e(Geo g, ElectronArrays<R> e,
+                                                       const Segment* seg, int tx, int tz, int ntx,
+                                                       int ntz, int* counts)
+{
+    const Segment sg = seg[blockIdx.x];
+    for (int base = 0; base < sg.count; base += NTHR) {
+        const int q = base + threadIdx.x;
+        bool act = false;
+        int key = 0;
+        if (q < sg.count) {
+            const int p = sg.start + q;
+            if (e.w[p] != R(0)) {
+                act = true;
+                key = tile_key(fold(e.x[p], g.Nx, g.perx), fold(e.z[p], g.Nz, g.perz), g, tx, tz, ntx, ntz);
+            }
+        }
+        wave_slot(counts, key, act);
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NTHR) k_sort_scatter_e(Geo g, ElectronArrays<R> src,
+                                                         ElectronArrays<R> dst, const Segment* seg,
+                                                         int tx, int tz, int ntx, int ntz, int* cursor)
+{
+    const Segment sg = seg[blockIdx.x];
+    for (int base = 0; base < sg.count; base += NTHR) {
+        const int q = base + threadIdx.x;
+        bool act = false;
+        int key = 0, p = 0;
+        double x = 0, z = 0;
+        if (q < sg.count) {
+            p = sg.start + q;
+            if (src.w[p] != R(0)) {
+                act = true;
+                x = fold(src.x[p], g.Nx, g.perx);
+                z = fold(src.z[p], g.Nz, g.perz);
+                key = tile_key(x, z, g, tx, tz, ntx, ntz);
+            }
+        }
+        const int d = wave_slot(cursor, key, act);
+        if (act) {
+            dst.x[d] = x;
+            dst.z[d] = z;
+            dst.ux[d] = src.ux[p];
+            dst.uy[d] = src.uy[p];
+            dst.uz[d] = src.uz[p];
+            dst.w[d] = src.w[p];
+            dst.id[d] = src.id[p];
+        }
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NTHR) k_sort_count_i(Geo g, IonArrays<R> ion, const Segment* seg,
+                                                       double zsh, int tx, int tz, int ntx, int ntz,
+                                                       int* counts)
+{
+    const Segment sg = seg[blockIdx.x];
+    for (int base = 0; base < sg.count; base += NTHR) {
+        const int q = base + threadIdx.x;
+        bool act = false;
+        int key = 0;
+        if (q < sg.count) {
+            const int p = sg.start + q;
+            if (ion.w[p] != R(0)) {
+                act = true;
+                key = tile_key(fold(ion.x[p], g.Nx, g.perx), ion.z0[p] - zsh, g, tx, tz, ntx, ntz);
+            }
+        }
+        wave_slot(counts, key, act);
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NTHR) k_sort_scatter_i(Geo g, IonArrays<R> src, IonArrays<R> dst,
+                                                         const Segment* seg, double zsh, int tx,
+                                                         int tz, int ntx, int ntz, int* cursor)
+{
+    const Segment sg = seg[blockIdx.x];
+    for (int base = 0; base < sg.count; base += NTHR) {
+        const int q = base + threadIdx.x;
+        bool act = false;
+        int key = 0, p = 0;
+        double x = 0;
+        if (q < sg.count) {
+            p = sg.start + q;
+            if (src.w[p] != R(0)) {
+                act = true;
+                x = fold(src.x[p], g.Nx, g.perx);
+                key = tile_key(x, src.z0[p] - zsh, g, tx, tz, ntx, ntz);
+            }
+        }
+        const int d = wave_slot(cursor, key, act);
+        if (act) {
+            dst.x[d] = x;
+            dst.z0[d] = src.z0[p];
+            dst.w[d] = src.w[p];
+            dst.id[d] = src.id[p];
+        }
+    }
+}
+
+// exclusive scan of the tile counts; writes the new segment table (one per tile), each
+// tile's box (the tile rectangle), the scatter cursors and the new slot count
+__global__ void __launch_bounds__(1024) k_sort_scan(const int* counts, int ntiles, int ntx, int tx,
+                                                    int tz, int Nx, int Nz, Segment* seg, int4* bbox,
+                                                    int* cursor, int* nused)
+{
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int per = (ntiles + 1023) / 1024;
+    const int lo = min(t * per, ntiles), hi = min(lo + per, ntiles);
+    int sum = 0;
+    for (int i = lo; i < hi; i++) sum += counts[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        int v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - sum;   // exclusive prefix of this thread's chunk
+    for (int i = lo; i < hi; i++) {
+        const int c = counts[i];
+        seg[i] = Segment{run, c};
+        cursor[i] = run;
+        const int cxi = i % ntx, czi = i / ntx;
+        const int xa = cxi * tx, za = czi * tz;
+        bbox[i] = c > 0 ? make_int4(xa, min(xa + tx, Nx) - 1, za, min(za + tz, Nz) - 1)
+                        : make_int4(INT_MAX, INT_MIN, INT_MAX, INT_MIN);
+        run += c;
+    }
+    if (t == 1023) *nused = part[1023];
+}
+
+// ---- launchers ---------------------------------------------------------------------------------
+template <typename R>
+void launch_gpd(const Geo& g, const FieldSet<R>& f, const ElectronArrays<R>& e, const Segment* seg,
+                const int4* bbox_in, int4* bbox_out, int nseg, const PushParams<R>& pp, int* status,
+                hipStream_t s)
+{
+    if (nseg <= 0) return;
+    const size_t lds = (size_t)pp.lds_cells * 9 * sizeof(R);
+    hipLaunchKernelGGL((k_gpd<R>), dim3(nseg), dim3(NTHR), lds, s, g, f, e, seg, bbox_in, bbox_out,
+                       pp, status);
+}
+
+template <typename R>
+void launch_ions(const Geo& g, const FieldSet<R>& f, const IonArrays<R>& ion, const Segment* seg,
+                 const int4* bbox_in, int4* bbox_out, int nseg, double zsh_a, double zsh_b, int shift,
+                 R fjz, int lds_cells, hipStream_t s)
+{
+    if (nseg <= 0) return;
+    const size_t lds = (size_t)lds_cells * sizeof(R);
+    hipLaunchKernelGGL((k_ions<R>), dim3(nseg), dim3(NTHR), lds, s, g, f, ion, seg, bbox_in, bbox_out,
+                       zsh_a, zsh_b, shift, fjz, lds_cells);
+}
+
+template <typename R>
+void launch_antenna(const Geo& g, const FieldSet<R>& f, double* xminus, const AntennaParams& ap,
+                    hipStream_t s)
+{
+    if (!ap.active || ap.n <= 0) return;
+    hipLaunchKernelGGL((k_antenna<R>), dim3((ap.n + 63) / 64), dim3(64), 0, s, g, f, xminus, ap);
+}
+
+template <typename R>
+void launch_inject(const Geo& g, const ElectronArrays<R>& e, const IonArrays<R>& ion, Segment* seg_e,
+                   int4* bbox_e, Segment* seg_i, int4* bbox_i, int* nused_e, int* nused_i,
+                   const InjectParams& ip, int* status, hipStream_t s)
+{
+    if (ip.nrows <= 0) return;
+    hipLaunchKernelGGL((k_inject<R>), dim3(ip.nchunks, ip.nrows), dim3(NTHR), 0, s, g, e, ion, seg_e,
+                       bbox_e, seg_i, bbox_i, nused_e, nused_i, ip, status);
+}
+
+template <typename R>
+void launch_sort_electrons(const Geo& g, int tile_x, int tile_z, int ntx, int ntiles,
+                           const ElectronArrays<R>& src, const ElectronArrays<R>& dst,
+                           const Segment* seg_old, int nseg_old, Segment* seg_new, int4* bbox_new,
+                           int* counts, int* cursor, int* nused, hipStream_t s)
+{
+    const int ntz = ntiles / ntx;
+    launch_fill_int(counts, ntiles, 0, s);
+    if (nseg_old > 0)
+        hipLaunchKernelGGL((k_sort_count_e<R>), dim3(nseg_old), dim3(NTHR), 0, s, g, src, seg_old,
+                           tile_x, tile_z, ntx, ntz, counts);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, (const int*)counts, ntiles, ntx, tile_x,
+                       tile_z, g.Nx, g.Nz, seg_new, bbox_new, cursor, nused);
+    if (nseg_old > 0)
+        hipLaunchKernelGGL((k_sort_scatter_e<R>), dim3(nseg_old), dim3(NTHR), 0, s, g, src, dst,
+                           seg_old, tile_x, tile_z, ntx, ntz, cursor);
+}
+
+template <typename R>
+void launch_sort_ions(const Geo& g, int tile_x, int tile_z, int ntx, int ntiles, const IonArrays<R>& src,
+                      const IonArrays<R>& dst, const Segment* seg_old, int nseg_old, Segment* seg_new,
+                      int4* bbox_new, double zsh, int* counts, int* cursor, int* nused, hipStream_t s)
+{
+    const int ntz = ntiles / ntx;
+    launch_fill_int(counts, ntiles, 0, s);
+    if (nseg_old > 0)
+        hipLaunchKernelGGL((k_sort_count_i<R>), dim3(nseg_old), dim3(NTHR), 0, s, g, src, seg_old, zsh,
+                           tile_x, tile_z, ntx, ntz, counts);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, (const int*)counts, ntiles, ntx, tile_x,
+                       tile_z, g.Nx, g.Nz, seg_new, bbox_new, cursor, nused);
+    if (nseg_old > 0)
+        hipLaunchKernelGGL((k_sort_scatter_i<R>), dim3(nseg_old), dim3(NTHR), 0, s, g, src, dst, seg_old,
+                           zsh, tile_x, tile_z, ntx, ntz, cursor);
+}
+
+#define BF_INST(R)                                                                                    \
+    template void launch_gpd<R>(const Geo&, const FieldSet<R>&, const ElectronArrays<R>&,             \
+                                const Segment*, const int4*, int4*, int, const PushParams<R>&, int*,  \
+                                hipStream_t);                                                         \
+    template void launch_ions<R>(const Geo&, const FieldSet<R>&, const IonArrays<R>&,                 \
+                                 const Segment*, const int4*, int4*, int, double, double, int, R,     \
+                                 int, hipStream_t);                                                   \
+    template void launch_antenna<R>(const Geo&, const FieldSet<R>&, double*, const AntennaParams&,    \
+                                    hipStream_t);                                                     \
+    template void launch_inject<R>(const Geo&, const ElectronArrays<R>&, const IonArrays<R>&,         \
+                                   Segment*, int4*, Segment*, int4*, int*, int*,                      \
+                                   const InjectParams&, int*, hipStream_t);                           \
+    template void launch_sort_electrons<R>(const Geo&, int, int, int, int, const ElectronArrays<R>&,  \
+                                           const ElectronArrays<R>&, const Segment*, int, Segment*,   \
+                                           int4*, int*, int*, int*, hipStream_t);                     \
+    template void launch_sort_ions<R>(const Geo&, int, int, int, int, const IonArrays<R>&,            \
+                                      const IonArrays<R>&, const Segment*, int, Segment*, int4*,      \
+                                      double, int*, int*, int*, hipStream_t);
+BF_INST(float)
+BF_INST(double)
+
+}  // namespace bf

@@ -1,0 +1,92 @@
+"""C-ABI conformance on the CPU: the library loads, exports every symbol the header declares,
+its structs have the C layout, and configuration validation returns the documented codes.
+No compute call is made (there is no GPU here)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1009_2727_amd as P
+import pic_inputs as pi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bfpic.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:bf_status|const char\*|void)\s+(bf_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("libbfpic.so not built")
+    L = P.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(P.EXPORTS)
+
+
+def test_struct_layouts_match_c(tmp_path):
+    prog = tmp_path / "sz.c"
+    prog.write_text('#include "bfpic.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                    'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(bf_config),'
+                    ' sizeof(bf_plasma), sizeof(bf_laser), sizeof(bf_station), sizeof(bf_state),'
+                    ' sizeof(bf_info), offsetof(bf_config, seed), offsetof(bf_config, particle_capacity),'
+                    ' offsetof(bf_state, nstations));}\n')
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [C.sizeof(P.bf_config), C.sizeof(P.bf_plasma), C.sizeof(P.bf_laser), C.sizeof(P.bf_station),
+            C.sizeof(P.bf_state), C.sizeof(P.bf_info), P.bf_config.seed.offset,
+            P.bf_config.particle_capacity.offset, P.bf_state.nstations.offset]
+    assert got == want
+
+
+def _cfg(**over):
+    w = pi.c1()
+    c = P.make_config(w["config"], 1000)
+    for k, v in over.items():
+        setattr(c, k, v)
+    return c
+
+
+def test_query_buffers_and_validation():
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("libbfpic.so not built")
+    descs = P.bf_query_buffers(_cfg())
+    assert [d[0] for d in descs] == ["fields", "electrons0", "electrons1", "ions0", "ions1", "work"]
+    assert all(d[1] > 0 and d[2] == 256 for d in descs)
+    with pytest.raises(P.BfError) as e:
+        P.bf_query_buffers(_cfg(cfl_fraction=1.2))
+    assert e.value.code == -2                                   # BF_ECFL
+    for bad in (dict(abi_version=7), dict(nx=0), dict(real_bytes=2), dict(friedman_theta=1.5),
+                dict(ck_alpha=0.5)):
+        with pytest.raises(P.BfError) as e:
+            P.bf_query_buffers(_cfg(**bad))
+        assert e.value.code == -1                               # BF_EINVAL
+    with pytest.raises(P.BfError) as e:
+        P.bf_query_buffers(_cfg(dim=3))
+    assert e.value.code == -7                                   # BF_EUNSUPPORTED
+    # window on a periodic z axis is meaningless
+    with pytest.raises(P.BfError):
+        P.bf_query_buffers(_cfg(periodic_mask=5, moving_window=1))
+
+
+def test_status_strings():
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("libbfpic.so not built")
+    for code in range(-7, 1):
+        assert P.lib().bf_status_string(code)
+
+
+def test_buffer_sizes_scale_with_capacity():
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("libbfpic.so not built")
+    a = dict((n, b) for n, b, _ in P.bf_query_buffers(_cfg(particle_capacity=1000)))
+    b = dict((n, b) for n, b, _ in P.bf_query_buffers(_cfg(particle_capacity=100000)))
+    assert b["electrons0"] > a["electrons0"] and b["fields"] == a["fields"]
