@@ -194,7 +194,7 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_filter(Geo g, const R* __restrict__ in, R* __restrict__ out,
                                                 int hx, int hz, int npass, int comp)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];   // 16-byte aligned: FP64 DS ops
     R* buf0 = reinterpret_cast<R*>(smem_raw);
     const int H = npass + (comp ? 1 : 0);
     const int LX = FTX + 2 * H, LZ = FTZ + 2 * H, L = LX * LZ;

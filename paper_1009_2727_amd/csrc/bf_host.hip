@@ -539,7 +539,7 @@ bf_status step_impl(bf_sim* s, int nsteps)
         if (s->have_plasma && s->plasma.ion_mode == 1)
             launch_ions<R>(s->g, f, ions<R>(s, s->p_cur), seg_i(s, s->sg_cur), bb_i(s, s->bb_cur),
                            bb_i(s, 1 - s->bb_cur), s->nseg_i, ion_shift(s, s->t), ion_shift(s, t1), d,
-                           (R)(-1.0 / (c.dx_um * s->dt)), s->lds_cells * 9, s->stream);
+                           (R)(-1.0 / (c.dx_um * s->dt)), 4096, s->stream);
         s->tock(t_ph, BF_PHASE_IONS);
         // antenna
         t_ph = s->tick();
@@ -686,8 +686,9 @@ bf_status bf_create(const bf_config* cfg, const bf_buffer_binding* b, int n, voi
     s->dt_crit = cfl2d(cfg->ck_alpha, cfg->ck_beta, cfg->ck_gamma, cfg->dx_um, cfg->dz_um, s->theta);
     s->dt = cfg->cfl_fraction * s->dt_crit;
     s->sort_every = cfg->sort_every > 0 ? cfg->sort_every : 20;
-    // LDS tile budget in cells: 9 components (6 field + 3 current) of one tile
-    s->lds_cells = cfg->real_bytes == 4 ? 1024 : 640;
+    // LDS tile budget in cells (6 field components in the run's precision + 3 FP64 current
+    // accumulators): 768 cells = 36 KB (FP32) keeps four 256-thread workgroups per CU
+    s->lds_cells = cfg->real_bytes == 4 ? 768 : 640;
     s->g = geo_of(s, 0);
     update_window_speed(s);
     hipError_t e = hipSuccess;

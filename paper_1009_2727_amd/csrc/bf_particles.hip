@@ -26,7 +26,7 @@ constexpr int NTHR = 256;
 template <typename R>
 struct LdsAcc {
     R* f;       // 6 x L
-    R* j;       // 3 x L
+    double* j;  // 3 x L, accumulated with FP64 LDS atomics (the FP32 ones are far slower)
     int xb, zb, lx, lz, L;
     __device__ __forceinline__ bool inside(int jx0, int jx1, int jz0, int jz1) const
     {
@@ -38,7 +38,7 @@ struct LdsAcc {
     }
     __device__ __forceinline__ void dep(int c, int jx, int jz, R v) const
     {
-        atomicAdd(&j[c * L + (jz - zb) * lx + (jx - xb)], v);
+        atomicAdd(&j[c * L + (jz - zb) * lx + (jx - xb)], (double)v);
     }
 };
 
@@ -198,45 +198,61 @@ __device__ __forceinline__ void boris(R h, const R E[3], const R B[3], R& ux, R&
     uz = uqz + h * E[2];
 }
 
-// one electron: gather, push, deposit, absorb.  Returns false if absorbed.
-template <typename R, typename A, typename G>
-__device__ __forceinline__ bool advance_electron(const A& lds, const G& glb, const Geo& g,
-                                                 const PushParams<R>& pp, double& x, double& z,
-                                                 R& ux, R& uy, R& uz, R w, int* status)
+// one electron with accessor A: gather, push, deposit, absorb, rebase; updates the box.
+// The caller guarantees the gather window [ix-2, ix+2] and the deposit window [ix-2, ix+3]
+// (one-cell move) are addressable through A.
+template <typename R, typename A>
+__device__ __forceinline__ void advance_electron(const A& acc, const Geo& g, const PushParams<R>& pp,
+                                                 const ElectronArrays<R>& e, int p, R w, int* status,
+                                                 int& x0, int& x1, int& z0, int& z1)
 {
+    double x = e.x[p], z = e.z[p];
+    R ux = e.ux[p], uy = e.uy[p], uz = e.uz[p];
     const int ix = (int)floor(x), iz = (int)floor(z);
     R E[3], B[3];
-    if (lds.inside(ix - 2, ix + 2, iz - 2, iz + 2)) gather(lds, x, z, E, B);
-    else gather(glb, x, z, E, B);
+    gather(acc, x, z, E, B);
     boris(pp.qdt2, E, B, ux, uy, uz);
     const R ig = R(1) / sqrt(R(1) + ux * ux + uy * uy + uz * uz);
     const R vx = ux * ig, vy = uy * ig, vz = uz * ig;
+    const double xn = x + (double)(pp.dtdx * vx), zn = z + (double)(pp.dtdz * vz);
+    const int ix1 = (int)floor(xn), iz1 = (int)floor(zn);
+    if (abs(ix1 - ix) <= 1 && abs(iz1 - iz) <= 1) {
+        const R fx = (R)(x - ix), fz = (R)(z - iz), fx1 = (R)(xn - ix1), fz1 = (R)(zn - iz1);
+        esirkepov(acc, ix, fx, iz, fz, ix1, fx1, iz1, fz1, pp.fjx * w, pp.fjz * w, pp.fjy * w * vy);
+    } else {
+        atomicOr(status, ST_NONFINITE);   // faster than light: only a non-finite state gets here
+    }
     if (!isfinite(ux + uy + uz)) atomicOr(status, ST_NONFINITE);
-    const double x1 = x + (double)(pp.dtdx * vx), z1 = z + (double)(pp.dtdz * vz);
-    const int ix1 = (int)floor(x1), iz1 = (int)floor(z1);
-    const R fx = (R)(x - ix), fz = (R)(z - iz), fx1 = (R)(x1 - ix1), fz1 = (R)(z1 - iz1);
-    const R cx = pp.fjx * w, cz = pp.fjz * w, cy = pp.fjy * w * vy;
-    const int bx = min(ix, ix1) - 1, bz = min(iz, iz1) - 1;
-    if (lds.inside(bx, bx + 4, bz, bz + 4) && abs(ix1 - ix) <= 1 && abs(iz1 - iz) <= 1)
-        esirkepov(lds, ix, fx, iz, fz, ix1, fx1, iz1, fz1, cx, cz, cy);
-    else
-        esirkepov(glb, ix, fx, iz, fz, ix1, fx1, iz1, fz1, cx, cz, cy);
-    x = x1;
-    z = z1;
     bool alive = true;
-    if (!g.perx && (x1 < 0.0 || x1 >= (double)g.Nx)) alive = false;
-    if (!g.perz && (z1 < 0.0 || z1 >= (double)g.Nz)) alive = false;
-    return alive;
+    if (!g.perx && (xn < 0.0 || xn >= (double)g.Nx)) alive = false;
+    if (!g.perz && (zn < 0.0 || zn >= (double)g.Nz)) alive = false;
+    const double zr = zn - (double)pp.shift;   // rebase into the next window frame
+    e.x[p] = xn;
+    e.z[p] = zr;
+    e.ux[p] = ux;
+    e.uy[p] = uy;
+    e.uz[p] = uz;
+    if (!alive) {
+        e.w[p] = R(0);
+    } else {
+        const int cx = (int)floor(xn), cz = (int)floor(zr);
+        x0 = min(x0, cx); x1 = max(x1, cx);
+        z0 = min(z0, cz); z1 = max(z1, cz);
+    }
 }
 
+constexpr int MISFIT_CAP = 256;
+
 template <typename R>
-__global__ void __launch_bounds__(NTHR) k_gpd(Geo g, FieldSet<R> f, ElectronArrays<R> e,
+__global__ void __launch_bounds__(NTHR, sizeof(R) == 4 ? 3 : 1) k_gpd(Geo g, FieldSet<R> f, ElectronArrays<R> e,
                                               const Segment* __restrict__ seg,
                                               const int4* __restrict__ bbin, int4* __restrict__ bbout,
                                               PushParams<R> pp, int* status)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];   // 16-byte aligned: FP64 DS ops
     __shared__ int4 red[NTHR / 64];
+    __shared__ int misfit[MISFIT_CAP];
+    __shared__ int nmisfit;
     const int s = blockIdx.x;
     const Segment sg = seg[s];
     const int4 bb = bbin[s];
@@ -244,18 +260,19 @@ __global__ void __launch_bounds__(NTHR) k_gpd(Geo g, FieldSet<R> f, ElectronArra
         if (threadIdx.x == 0) bbout[s] = make_int4(INT_MAX, INT_MIN, INT_MAX, INT_MIN);
         return;
     }
-    const GlobAcc<R> glb = make_glob(g, f);
     LdsAcc<R> lds;
     lds.xb = bb.x - 2;
     lds.zb = bb.z - 2;
     lds.lx = bb.y - bb.x + 6;
     lds.lz = bb.w - bb.z + 6;
     lds.L = lds.lx * lds.lz;
-    const bool use_lds = lds.L <= pp.lds_cells;
     lds.f = reinterpret_cast<R*>(smem_raw);
-    lds.j = lds.f + 6 * lds.L;
-    if (!use_lds) { lds.lx = 0; lds.lz = 0; }   // every inside() test fails: global path
+    lds.j = reinterpret_cast<double*>(lds.f + 6 * lds.L);   // 6L elements: 8-byte aligned
+    const bool use_lds = lds.L <= pp.lds_cells;
+    int x0 = INT_MAX, x1 = INT_MIN, z0 = INT_MAX, z1 = INT_MIN;
+    const int end = sg.start + sg.count;
     if (use_lds) {
+        if (threadIdx.x == 0) nmisfit = 0;
         for (int q = threadIdx.x; q < lds.L; q += NTHR) {
             const int a = q % lds.lx, b = q / lds.lx;
             const int i = swrap(lds.xb + a + g.Px, g.Sx, g.perx);
@@ -272,33 +289,21 @@ __global__ void __launch_bounds__(NTHR) k_gpd(Geo g, FieldSet<R> f, ElectronArra
 #pragma unroll
             for (int c = 0; c < 6; c++) lds.f[c * lds.L + q] = v[c];
 #pragma unroll
-            for (int c = 0; c < 3; c++) lds.j[c * lds.L + q] = R(0);
+            for (int c = 0; c < 3; c++) lds.j[c * lds.L + q] = 0.0;
         }
         __syncthreads();
-    }
-    int x0 = INT_MAX, x1 = INT_MIN, z0 = INT_MAX, z1 = INT_MIN;
-    const int end = sg.start + sg.count;
-    for (int p = sg.start + threadIdx.x; p < end; p += NTHR) {
-        const R w = e.w[p];
-        if (w == R(0)) continue;
-        double x = e.x[p], z = e.z[p];
-        R ux = e.ux[p], uy = e.uy[p], uz = e.uz[p];
-        const bool alive = advance_electron(lds, glb, g, pp, x, z, ux, uy, uz, w, status);
-        z -= (double)pp.shift;
-        e.x[p] = x;
-        e.z[p] = z;
-        e.ux[p] = ux;
-        e.uy[p] = uy;
-        e.uz[p] = uz;
-        if (!alive) {
-            e.w[p] = R(0);
-        } else {
-            const int cx = (int)floor(x), cz = (int)floor(z);
-            x0 = min(x0, cx); x1 = max(x1, cx);
-            z0 = min(z0, cz); z1 = max(z1, cz);
+        for (int p = sg.start + threadIdx.x; p < end; p += NTHR) {
+            const R w = e.w[p];
+            if (w == R(0)) continue;
+            const int ix = (int)floor(e.x[p]), iz = (int)floor(e.z[p]);
+            if (!lds.inside(ix - 2, ix + 3, iz - 2, iz + 3)) {
+                const int slot = atomicAdd(&nmisfit, 1);
+                if (slot < MISFIT_CAP) misfit[slot] = p;
+                else atomicOr(status, ST_SEGMENTS);
+                continue;
+            }
+            advance_electron(lds, g, pp, e, p, w, status, x0, x1, z0, z1);
         }
-    }
-    if (use_lds) {
         __syncthreads();
         for (int q = threadIdx.x; q < lds.L; q += NTHR) {
             const int a = q % lds.lx, b = q / lds.lx;
@@ -308,9 +313,25 @@ __global__ void __launch_bounds__(NTHR) k_gpd(Geo g, FieldSet<R> f, ElectronArra
             const long o = gofs(g, i, k);
 #pragma unroll
             for (int c = 0; c < 3; c++) {
-                const R v = lds.j[c * lds.L + q];
+                const R v = (R)lds.j[c * lds.L + q];
                 if (v != R(0)) atomicAdd(&f.J[c][o], v);
             }
+        }
+        // particles outside the staged box (none for a consistent box): global accessors
+        const int nm = min(nmisfit, MISFIT_CAP);
+        if (nm > 0) {
+            const GlobAcc<R> glb = make_glob(g, f);
+            for (int q = threadIdx.x; q < nm; q += NTHR) {
+                const int p = misfit[q];
+                advance_electron(glb, g, pp, e, p, e.w[p], status, x0, x1, z0, z1);
+            }
+        }
+    } else {
+        const GlobAcc<R> glb = make_glob(g, f);
+        for (int p = sg.start + threadIdx.x; p < end; p += NTHR) {
+            const R w = e.w[p];
+            if (w == R(0)) continue;
+            advance_electron(glb, g, pp, e, p, w, status, x0, x1, z0, z1);
         }
     }
     block_bbox(x0, x1, z0, z1, red);
@@ -345,7 +366,7 @@ __global__ void __launch_bounds__(NTHR) k_ions(Geo g, FieldSet<R> f, IonArrays<R
                                                double zsh_a, double zsh_b, int shift, R fjz,
                                                int lds_cells)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];   // 16-byte aligned: FP64 DS ops
     __shared__ int4 red[NTHR / 64];
     const int s = blockIdx.x;
     const Segment sg = seg[s];
@@ -364,11 +385,11 @@ __global__ void __launch_bounds__(NTHR) k_ions(Geo g, FieldSet<R> f, IonArrays<R
     const bool use_lds = lds.L <= lds_cells;
     // only J_z (component 2) is staged: point j so that component 2 starts at smem
     lds.f = nullptr;
-    lds.j = reinterpret_cast<R*>(smem_raw) - 2 * lds.L;
+    lds.j = reinterpret_cast<double*>(smem_raw) - 2 * lds.L;
     if (!use_lds) { lds.lx = 0; lds.lz = 0; }
     if (use_lds) {
-        R* jz = reinterpret_cast<R*>(smem_raw);
-        for (int q = threadIdx.x; q < lds.L; q += NTHR) jz[q] = R(0);
+        double* jz = reinterpret_cast<double*>(smem_raw);
+        for (int q = threadIdx.x; q < lds.L; q += NTHR) jz[q] = 0.0;
         __syncthreads();
     }
     int x0 = INT_MAX, x1 = INT_MIN, z0 = INT_MAX, z1 = INT_MIN;
@@ -396,9 +417,9 @@ __global__ void __launch_bounds__(NTHR) k_ions(Geo g, FieldSet<R> f, IonArrays<R
     }
     if (use_lds) {
         __syncthreads();
-        const R* jz = reinterpret_cast<const R*>(smem_raw);
+        const double* jz = reinterpret_cast<const double*>(smem_raw);
         for (int q = threadIdx.x; q < lds.L; q += NTHR) {
-            const R v = jz[q];
+            const R v = (R)jz[q];
             if (v == R(0)) continue;
             const int a = q % lds.lx, b = q / lds.lx;
             const int i = swrap(lds.xb + a + g.Px, g.Sx, g.perx);
@@ -603,6 +624,74 @@ __global__ void __launch_bounds__(NTHR) k_inject(Geo g, ElectronArrays<R> e, Ion
     }
 }
 
+// modular inverse of a mod n (gcd(a, n) == 1), extended Euclid
+__device__ __forceinline__ int64_t inv_mod(int64_t a, int64_t n)
+{
+    int64_t t = 0, nt = 1, r = n, nr = a % n;
+    while (nr != 0) {
+        const int64_t q = r / nr, tt = t - q * nt, rr = r - q * nr;
+        t = nt; nt = tt; r = nr; nr = rr;
+    }
+    return t < 0 ? t + n : t;
+}
+
+__device__ __forceinline__ int64_t gcd64(int64_t a, int64_t b)
+{
+    while (b) { const int64_t t = a % b; a = b; b = t; }
+    return a;
+}
+
+// Exclusive scan of the tile counts; writes the new segment table (one per tile), each
+// tile's box (the tile rectangle), the scatter rank counters (zero) and the new slot count.
+// counts[] is overwritten with each tile's slot multiplier m: the particle arriving r-th in
+// a tile goes to slot (r m) mod count, so that consecutive slots hold arrivals d = 1/m apart
+// with d just above the mean count per cell -- the particles of one cell, which arrive
+// together, land in different waves and the LDS current atomics of a wave rarely collide.
+__global__ void __launch_bounds__(1024) k_sort_scan(int* counts, int ntiles, int ntx, int tx,
+                                                    int tz, int Nx, int Nz, Segment* seg, int4* bbox,
+                                                    int* cursor, int* nused)
+{
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int per = (ntiles + 1023) / 1024;
+    const int lo = min(t * per, ntiles), hi = min(lo + per, ntiles);
+    int sum = 0;
+    for (int i = lo; i < hi; i++) sum += counts[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        int v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - sum;   // exclusive prefix of this thread's chunk
+    for (int i = lo; i < hi; i++) {
+        const int c = counts[i];
+        seg[i] = Segment{run, c};
+        cursor[i] = 0;
+        int64_t m = 1;
+        if (c > 2) {
+            int64_t d = c / (tx * tz) + 1;
+            while (d < c && gcd64(d, c) != 1) d++;
+            m = d < c ? inv_mod(d, c) : 1;
+        }
+        counts[i] = (int)m;
+        const int cxi = i % ntx, czi = i / ntx;
+        const int xa = cxi * tx, za = czi * tz;
+        bbox[i] = c > 0 ? make_int4(xa, min(xa + tx, Nx) - 1, za, min(za + tz, Nz) - 1)
+                        : make_int4(INT_MAX, INT_MIN, INT_MAX, INT_MIN);
+        run += c;
+    }
+    if (t == 1023) *nused = part[1023];
+}
+
+__device__ __forceinline__ int tile_slot(const Segment* seg, const int* mult, int key, int rank)
+{
+    const Segment sg = seg[key];
+    return sg.start + (int)(((int64_t)rank * (int64_t)mult[key]) % (int64_t)sg.count);
+}
+
 // ---- counting sort by tile ----------------------------------------------------------------------
 __device__ __forceinline__ double fold(double v, int N, int per)
 {
@@ -644,7 +733,8 @@ __global__ void __launch_bounds__(NTHR) k_sort_count_e(Geo g, ElectronArrays<R> 
 template <typename R>
 __global__ void __launch_bounds__(NTHR) k_sort_scatter_e(Geo g, ElectronArrays<R> src,
                                                          ElectronArrays<R> dst, const Segment* seg,
-                                                         int tx, int tz, int ntx, int ntz, int* cursor)
+                                                         int tx, int tz, int ntx, int ntz, int* cursor,
+                                                         const Segment* seg_new, const int* mult)
 {
     const Segment sg = seg[blockIdx.x];
     for (int base = 0; base < sg.count; base += NTHR) {
@@ -661,7 +751,8 @@ __global__ void __launch_bounds__(NTHR) k_sort_scatter_e(Geo g, ElectronArrays<R
                 key = tile_key(x, z, g, tx, tz, ntx, ntz);
             }
         }
-        const int d = wave_slot(cursor, key, act);
+        const int r = wave_slot(cursor, key, act);
+        const int d = act ? tile_slot(seg_new, mult, key, r) : 0;
         if (act) {
             dst.x[d] = x;
             dst.z[d] = z;
@@ -698,7 +789,8 @@ __global__ void __launch_bounds__(NTHR) k_sort_count_i(Geo g, IonArrays<R> ion, 
 template <typename R>
 __global__ void __launch_bounds__(NTHR) k_sort_scatter_i(Geo g, IonArrays<R> src, IonArrays<R> dst,
                                                          const Segment* seg, double zsh, int tx,
-                                                         int tz, int ntx, int ntz, int* cursor)
+                                                         int tz, int ntx, int ntz, int* cursor,
+                                                         const Segment* seg_new, const int* mult)
 {
     const Segment sg = seg[blockIdx.x];
     for (int base = 0; base < sg.count; base += NTHR) {
@@ -714,7 +806,8 @@ __global__ void __launch_bounds__(NTHR) k_sort_scatter_i(Geo g, IonArrays<R> src
                 key = tile_key(x, src.z0[p] - zsh, g, tx, tz, ntx, ntz);
             }
         }
-        const int d = wave_slot(cursor, key, act);
+        const int r = wave_slot(cursor, key, act);
+        const int d = act ? tile_slot(seg_new, mult, key, r) : 0;
         if (act) {
             dst.x[d] = x;
             dst.z0[d] = src.z0[p];
@@ -724,40 +817,6 @@ __global__ void __launch_bounds__(NTHR) k_sort_scatter_i(Geo g, IonArrays<R> src
     }
 }
 
-// exclusive scan of the tile counts; writes the new segment table (one per tile), each
-// tile's box (the tile rectangle), the scatter cursors and the new slot count
-__global__ void __launch_bounds__(1024) k_sort_scan(const int* counts, int ntiles, int ntx, int tx,
-                                                    int tz, int Nx, int Nz, Segment* seg, int4* bbox,
-                                                    int* cursor, int* nused)
-{
-    __shared__ int part[1024];
-    const int t = threadIdx.x;
-    const int per = (ntiles + 1023) / 1024;
-    const int lo = min(t * per, ntiles), hi = min(lo + per, ntiles);
-    int sum = 0;
-    for (int i = lo; i < hi; i++) sum += counts[i];
-    part[t] = sum;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        int v = t >= o ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int run = part[t] - sum;   // exclusive prefix of this thread's chunk
-    for (int i = lo; i < hi; i++) {
-        const int c = counts[i];
-        seg[i] = Segment{run, c};
-        cursor[i] = run;
-        const int cxi = i % ntx, czi = i / ntx;
-        const int xa = cxi * tx, za = czi * tz;
-        bbox[i] = c > 0 ? make_int4(xa, min(xa + tx, Nx) - 1, za, min(za + tz, Nz) - 1)
-                        : make_int4(INT_MAX, INT_MIN, INT_MAX, INT_MIN);
-        run += c;
-    }
-    if (t == 1023) *nused = part[1023];
-}
-
 // ---- launchers ---------------------------------------------------------------------------------
 template <typename R>
 void launch_gpd(const Geo& g, const FieldSet<R>& f, const ElectronArrays<R>& e, const Segment* seg,
@@ -765,7 +824,7 @@ void launch_gpd(const Geo& g, const FieldSet<R>& f, const ElectronArrays<R>& e, 
                 hipStream_t s)
 {
     if (nseg <= 0) return;
-    const size_t lds = (size_t)pp.lds_cells * 9 * sizeof(R);
+    const size_t lds = (size_t)pp.lds_cells * (6 * sizeof(R) + 3 * sizeof(double));
     hipLaunchKernelGGL((k_gpd<R>), dim3(nseg), dim3(NTHR), lds, s, g, f, e, seg, bbox_in, bbox_out,
                        pp, status);
 }
@@ -776,7 +835,7 @@ void launch_ions(const Geo& g, const FieldSet<R>& f, const IonArrays<R>& ion, co
                  R fjz, int lds_cells, hipStream_t s)
 {
     if (nseg <= 0) return;
-    const size_t lds = (size_t)lds_cells * sizeof(R);
+    const size_t lds = (size_t)lds_cells * sizeof(double);
     hipLaunchKernelGGL((k_ions<R>), dim3(nseg), dim3(NTHR), lds, s, g, f, ion, seg, bbox_in, bbox_out,
                        zsh_a, zsh_b, shift, fjz, lds_cells);
 }
@@ -810,11 +869,12 @@ void launch_sort_electrons(const Geo& g, int tile_x, int tile_z, int ntx, int nt
     if (nseg_old > 0)
         hipLaunchKernelGGL((k_sort_count_e<R>), dim3(nseg_old), dim3(NTHR), 0, s, g, src, seg_old,
                            tile_x, tile_z, ntx, ntz, counts);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, (const int*)counts, ntiles, ntx, tile_x,
-                       tile_z, g.Nx, g.Nz, seg_new, bbox_new, cursor, nused);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, counts, ntiles, ntx, tile_x, tile_z, g.Nx,
+                       g.Nz, seg_new, bbox_new, cursor, nused);
     if (nseg_old > 0)
         hipLaunchKernelGGL((k_sort_scatter_e<R>), dim3(nseg_old), dim3(NTHR), 0, s, g, src, dst,
-                           seg_old, tile_x, tile_z, ntx, ntz, cursor);
+                           seg_old, tile_x, tile_z, ntx, ntz, cursor, (const Segment*)seg_new,
+                           (const int*)counts);
 }
 
 template <typename R>
@@ -827,11 +887,12 @@ void launch_sort_ions(const Geo& g, int tile_x, int tile_z, int ntx, int ntiles,
     if (nseg_old > 0)
         hipLaunchKernelGGL((k_sort_count_i<R>), dim3(nseg_old), dim3(NTHR), 0, s, g, src, seg_old, zsh,
                            tile_x, tile_z, ntx, ntz, counts);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, (const int*)counts, ntiles, ntx, tile_x,
-                       tile_z, g.Nx, g.Nz, seg_new, bbox_new, cursor, nused);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, counts, ntiles, ntx, tile_x, tile_z, g.Nx,
+                       g.Nz, seg_new, bbox_new, cursor, nused);
     if (nseg_old > 0)
         hipLaunchKernelGGL((k_sort_scatter_i<R>), dim3(nseg_old), dim3(NTHR), 0, s, g, src, dst, seg_old,
-                           zsh, tile_x, tile_z, ntx, ntz, cursor);
+                           zsh, tile_x, tile_z, ntx, ntz, cursor, (const Segment*)seg_new,
+                           (const int*)counts);
 }
 
 #define BF_INST(R)                                                                                    \
