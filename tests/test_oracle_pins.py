@@ -6,6 +6,7 @@ relation, CFL column, Friedman factor, Lorentz transformation), brute force over
 inputs, conservation identities, and special cases.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -93,20 +94,35 @@ def test_filter_printed_properties():
 # T2: CFL (Sec. 4.2.1 Eq. cfl, Table CKcoefs) and Friedman factor (Sec. 4.3)
 # ---------------------------------------------------------------------------------------
 
-TABLE_CFL = {"yee": 1 / math.sqrt(3), "ck": 1.0, "ck2": 1 / math.sqrt(2), "ck3": 1 / math.sqrt(2),
-             "ck4": math.sqrt(2) / math.sqrt(3), "ck5": math.sqrt(5) / math.sqrt(6)}
-TABLE_PRIME = {"yee": (0, 0), "ck": (-1, 1), "ck2": (-0.5, 0.5), "ck3": (0, -1),
-               "ck4": (-0.5, 0), "ck5": (-0.9, 0.9)}
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-@pytest.mark.parametrize("name", list(TABLE_CFL))
+def _printed_value(tok):
+    # the table's entries: integers, fractions p/q and quotients of square roots
+    v = 1.0
+    for k, part in enumerate(tok.split("/")):
+        x = math.sqrt(float(part[5:-1])) if part.startswith("sqrt(") else float(part)
+        v = x if k == 0 else v / x
+    return v
+
+
+def _golden_rows(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [l.split() for l in f if l.strip() and not l.startswith("#")]
+
+
+CK_TABLE = {r[0]: [_printed_value(t) for t in r[1:]] for r in _golden_rows("ck_coefficient_table.txt")}
+
+
+@pytest.mark.parametrize("name", list(CK_TABLE))
 def test_coefficient_table_and_3d_cfl(name):
+    bp, gp, ta, tb, tg, tcfl = CK_TABLE[name]
     a, b, g = pi.CK_SETS[name]
+    assert (a, b, g) == pytest.approx((ta, tb, tg), abs=1e-15)
     assert a + 4 * b + 4 * g == pytest.approx(1.0, abs=1e-15)
-    bp, gp = TABLE_PRIME[name]
     assert -8 * b - 16 * g == pytest.approx(bp, abs=1e-15)
     assert 48 * g == pytest.approx(gp, abs=1e-15)
-    assert cfl_3d(a, b, g, 1.0, 1.0, 1.0) == pytest.approx(TABLE_CFL[name], rel=1e-14)
+    assert cfl_3d(a, b, g, 1.0, 1.0, 1.0) == pytest.approx(tcfl, rel=1e-14)
 
 
 def _brute_cfl_2d(a, b, g, dx, dz, n=401):
@@ -120,7 +136,7 @@ def _brute_cfl_2d(a, b, g, dx, dz, n=401):
     return 1.0 / math.sqrt(rhs.max())
 
 
-@pytest.mark.parametrize("name", list(TABLE_CFL))
+@pytest.mark.parametrize("name", list(CK_TABLE))
 @pytest.mark.parametrize("dx,dz", [(1.0, 1.0), (0.65, 0.05), (0.3, 0.7)])
 def test_2d_cfl_is_dispersion_maximum(name, dx, dz):
     a, b, g = pi.CK_SETS[name]
@@ -459,8 +475,8 @@ def test_antenna_emission_amplitude_and_frequency(gamma):
 # T11: printed plasma numbers (Sec. 2.1, Sec. 5.1): lambda_p and gamma_w
 # ---------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,lp,gw", [(1e19, 10.6, 13.2), (1e18, 33.4, 41.7), (1e17, 106.0, 132.0),
-                                     (1e16, 334.0, 417.0)])
+@pytest.mark.parametrize("n,lp,gw", [tuple(float(t) for t in r)
+                                     for r in _golden_rows("stage_plasma_numbers.txt")])
 def test_printed_plasma_numbers(n, lp, gw):
     cfg = pi.make_config(8, 8, 0.1, 0.1, periodic_x=1, moving_window=1)
     o = Oracle(cfg)
