@@ -68,6 +68,38 @@ def cpu_baseline(args):
                       f"{args.cpu_steps} steps after one untimed step, FP64, single thread"}
 
 
+def learned_filter_leg(args, w, plain_filter_ms):
+    """The same workload and steps with the learned current filter (BF16 MFMA convolutions)
+    in place of the bilinear one.  Its weights are the exact factorisation of the 4-pass +
+    compensation filter, so the physics is the plain filter's and only the cost differs."""
+    import torch
+    import copy
+    from paper_1009_2727_amd import Sim, bilinear_factor_params
+    w2 = copy.deepcopy(w)
+    w2["config"]["filter_kind"] = 1
+    cfg = w2["config"]
+    sim = Sim.from_workload(w2, sort_every=args.sort_every, timers=True)
+    sim.set_learned_filter(bilinear_factor_params(cfg["filter_npass"], bool(cfg["filter_compensate"])))
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    c0 = sim.counts()
+    sim.timers(reset=True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(sim.stream)
+    sim.step(args.steps)
+    t1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    c1 = sim.counts()
+    tm = sim.timers(reset=True)
+    ne = 0.5 * (c0[0] + c1[0])
+    return {"value": ne * args.steps / (ms / 1e3), "unit": "electron pushes/s",
+            "ms_per_step": ms / args.steps, "filter_ms_per_step": tm["filter"][0] / args.steps,
+            "plain_filter_ms_per_step": plain_filter_ms, "status": sim.sync_status(),
+            "weights": "exact factorisation of the 4-pass + compensation filter"}
+
+
 def read_pmc():
     if not os.path.exists(PMC_FILE):
         return None
@@ -120,6 +152,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--sort-every", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned-filter", action="store_true",
+                    help="skip the second run with the learned (MFMA) current filter")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
@@ -204,6 +238,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": gpd_bytes, "avg_launch_ms": gpd_ms},
     }
+    if not args.no_learned_filter:
+        del sim
+        torch.cuda.empty_cache()
+        out["learned_filter"] = learned_filter_leg(args, w, timers["filter"][0] / max(args.steps, 1))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)

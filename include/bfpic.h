@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define BF_ABI_VERSION 1u
+#define BF_ABI_VERSION 2u
 
 typedef enum {
     BF_OK = 0,
@@ -67,6 +67,8 @@ typedef struct {
     double cfl_fraction;       /* dt = cfl_fraction * dt*_c (Eq. cfl x sqrt((2+t)/(2+3t)))      */
     int filter_npass;          /* bilinear passes per axis (Sec. 4.1)                          */
     int filter_compensate;     /* 1: one extra pass with alpha_c = n/2 + 1                     */
+    int filter_kind;           /* BF_FILTER_BILINEAR, or BF_FILTER_LEARNED (FP32 runs only;
+                                  weights from bf_set_learned_filter)                         */
     int pml_cells;             /* PML depth on non-periodic faces (Appendix II)                */
     int periodic_mask;         /* bit 0: x periodic, bit 2: z periodic (no moving window)      */
     double gamma_boost;        /* Lorentz factor of the calculation frame (>= 1)              */
@@ -189,11 +191,13 @@ enum {
     BF_PHASE_COUNT
 };
 
-/* field ids (logical layout [stored_z][stored_x], x fastest) */
+/* field ids (logical layout [stored_z][stored_x], x fastest).  J_x, J_y, J_z are the current
+   Ampere used (filtered when a filter is on); J_xr, J_yr, J_zr the raw deposited current of
+   the last step, before the filter. */
 enum {
     BF_F_EX = 0, BF_F_EY, BF_F_EZ, BF_F_BX, BF_F_BY, BF_F_BZ, BF_F_JX, BF_F_JY, BF_F_JZ,
     BF_F_EXO, BF_F_EYO, BF_F_EZO, BF_F_EXB, BF_F_EYB, BF_F_EZB, BF_F_BYX, BF_F_EYX,
-    BF_F_BXO, BF_F_BYO, BF_F_BZO, BF_F_COUNT
+    BF_F_BXO, BF_F_BYO, BF_F_BZO, BF_F_JXR, BF_F_JYR, BF_F_JZR, BF_F_COUNT
 };
 
 typedef struct {
@@ -225,6 +229,53 @@ const char* bf_last_error(const bf_sim* sim);
 
 /* Frees host metadata only; the caller frees its buffers afterwards. */
 void bf_destroy(bf_sim* sim);
+
+/* ---- learned current filter ---------------------------------------------------------------
+   An addition that replaces the n-pass bilinear + compensation filter of Sec. 4.1 (Eq.
+   3ptfilter) when filter_kind is BF_FILTER_LEARNED; the bilinear filter stays the default and
+   the reference it is judged against.  Three 5x5 convolutions, channels 1 -> 16 -> 16 -> 1,
+   identity activations, no bias, one network shared by J_x, J_y, J_z, each on its own
+   staggered domain with the bilinear filter's boundary rule per layer (wrap on periodic
+   axes, zero outside otherwise).  It is linear and shift-invariant, so it keeps Gauss's law
+   (Sec. 4.2.2) as the bilinear filter does.  Arithmetic: BF16 weights, every layer input split
+   into BF16 hi + lo parts, FP32 accumulation on the matrix cores.
+   Parameters (FP32, BF_LF_PARAMS values): W1[t][co] (25 x 16), then W2[t][ci][co]
+   (25 x 16 x 16), then W3[t][ci] (25 x 16); tap t = 5 (dy + 2) + (dx + 2) with dy along the
+   rows (z) and dx along x, and layer output(p) = sum_t W[t] . input(p + (dx, dy)). */
+#define BF_FILTER_BILINEAR 0
+#define BF_FILTER_LEARNED 1
+#define BF_LF_PARAMS 7200
+
+/* Loads the learned filter's parameters (host array of n = BF_LF_PARAMS floats) into the
+   handle; required before bf_step when filter_kind is BF_FILTER_LEARNED.  Synchronous.
+   BF_EINVAL: wrong n or null; BF_ESTATE: the handle was created with the bilinear filter. */
+bf_status bf_set_learned_filter(bf_sim* sim, const float* host_params, int64_t n);
+
+/* Standalone use on batches of device images (row-major [img][y][x], FP32, one channel):
+   bytes of the device work buffer that bf_lf_apply / bf_lf_train_step need for nimg images of
+   ny x nx, or -1 for invalid sizes (nimg < 1 or > 65535, ny or nx < 1, too many pixels). */
+int64_t bf_lf_work_bytes(int nimg, int ny, int nx);
+
+/* out = filter(in) per image; params, in, out and work are device pointers; periodic_x/y
+   select wrap instead of zero padding.  Asynchronous on hip_stream (NULL: default stream).
+   BF_EINVAL: null pointer, bad sizes or work_bytes below bf_lf_work_bytes. */
+bf_status bf_lf_apply(void* work, int64_t work_bytes, const float* params, const float* in,
+                      float* out, int nimg, int ny, int nx, int periodic_x, int periodic_y,
+                      void* hip_stream);
+
+/* One training step on device images: loss = mean over the pixels at least `margin` from the
+   image edges of (filter(in) - target)^2; gradient by backpropagation through the three
+   convolutions (the BF16 weights as used in the forward pass); then, if lr != 0, one Adam
+   step (Kingma & Ba 2015, bias-corrected with step number `step` >= 1) on params using the
+   device moment arrays adam_m and adam_v (BF_LF_PARAMS floats each, start at zero).
+   grad_out (BF_LF_PARAMS floats) and loss_out (one double) are optional device outputs that
+   receive the gradient and the loss before the update.  Asynchronous on hip_stream.
+   BF_EINVAL: null pointer, bad sizes, 2 margin >= ny or nx, missing moments with lr != 0. */
+bf_status bf_lf_train_step(void* work, int64_t work_bytes, float* params, float* adam_m,
+                           float* adam_v, const float* in, const float* target, int nimg, int ny,
+                           int nx, int margin, int periodic_x, int periodic_y, float lr,
+                           float beta1, float beta2, float eps, int64_t step, float* grad_out,
+                           double* loss_out, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -16,9 +16,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbfpic.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 FIELDS = ["Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "Exo", "Eyo", "Ezo",
-          "Exb", "Eyb", "Ezb", "Byx", "Eyx", "Bxo", "Byo", "Bzo"]
+          "Exb", "Eyb", "Ezb", "Byx", "Eyx", "Bxo", "Byo", "Bzo", "Jxr", "Jyr", "Jzr"]
 FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 DIAG_FIELD, DIAG_PARTICLES, DIAG_COUNTS, DIAG_STATION, DIAG_ENERGY, DIAG_GAUSS, DIAG_INFO, \
     DIAG_ANTENNA, DIAG_TIMERS = range(9)
@@ -40,7 +40,7 @@ class bf_config(C.Structure):
                 ("shape_order", C.c_int), ("ck_alpha", C.c_double), ("ck_beta", C.c_double),
                 ("ck_gamma", C.c_double), ("friedman_theta", C.c_double),
                 ("cfl_fraction", C.c_double), ("filter_npass", C.c_int),
-                ("filter_compensate", C.c_int), ("pml_cells", C.c_int),
+                ("filter_compensate", C.c_int), ("filter_kind", C.c_int), ("pml_cells", C.c_int),
                 ("periodic_mask", C.c_int), ("gamma_boost", C.c_double),
                 ("moving_window", C.c_int), ("particle_capacity", C.c_int64),
                 ("sort_every", C.c_int), ("tile_x", C.c_int), ("tile_z", C.c_int),
@@ -93,7 +93,10 @@ class bf_info(C.Structure):
 
 EXPORTS = ["bf_query_buffers", "bf_create", "bf_init_plasma", "bf_init_laser", "bf_add_station",
            "bf_load_electrons", "bf_step", "bf_diagnose", "bf_set_field", "bf_sync_status",
-           "bf_get_state", "bf_set_state", "bf_status_string", "bf_last_error", "bf_destroy"]
+           "bf_get_state", "bf_set_state", "bf_status_string", "bf_last_error", "bf_destroy",
+           "bf_set_learned_filter", "bf_lf_work_bytes", "bf_lf_apply", "bf_lf_train_step"]
+FILTER_BILINEAR, FILTER_LEARNED = 0, 1
+LF_PARAMS = 7200
 
 _lib = None
 
@@ -128,8 +131,16 @@ def lib(path: str = LIB_PATH):
     L.bf_last_error.restype = C.c_char_p
     L.bf_destroy.argtypes = [P]
     L.bf_destroy.restype = None
+    F = C.POINTER(C.c_float)
+    L.bf_set_learned_filter.argtypes = [P, F, C.c_int64]
+    L.bf_lf_work_bytes.argtypes = [C.c_int, C.c_int, C.c_int]
+    L.bf_lf_work_bytes.restype = C.c_int64
+    L.bf_lf_apply.argtypes = [P, C.c_int64, P, P, P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P]
+    L.bf_lf_train_step.argtypes = [P, C.c_int64, P, P, P, P, P, C.c_int, C.c_int, C.c_int, C.c_int,
+                                   C.c_int, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float,
+                                   C.c_int64, P, P, P]
     for n in EXPORTS:
-        if n not in ("bf_status_string", "bf_last_error", "bf_destroy"):
+        if n not in ("bf_status_string", "bf_last_error", "bf_destroy", "bf_lf_work_bytes"):
             getattr(L, n).restype = C.c_int
     _lib = L
     return L
@@ -181,6 +192,7 @@ def make_config(cfg: dict, capacity: int, stations: int = 0, station_capacity: i
     c.cfl_fraction = cfg["cfl_fraction"]
     c.filter_npass = cfg["filter_npass"]
     c.filter_compensate = cfg["filter_compensate"]
+    c.filter_kind = cfg.get("filter_kind", FILTER_BILINEAR)
     c.pml_cells = cfg["pml_cells"]
     c.periodic_mask = (1 if cfg.get("periodic_x") else 0) | (4 if cfg.get("periodic_z") else 0)
     c.gamma_boost = cfg["gamma_boost"]
@@ -338,3 +350,112 @@ class Sim:
 
     def set_state(self, st: bf_state):
         self._ck(lib().bf_set_state(self.handle, C.byref(st)))
+
+    def set_learned_filter(self, params):
+        """Loads the learned filter's BF_LF_PARAMS FP32 parameters (host array)."""
+        a = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+        self._ck(lib().bf_set_learned_filter(self.handle, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+
+
+def bilinear_factor_params(npass: int = 4, compensate: bool = True) -> np.ndarray:
+    """Learned-filter parameters that reproduce the n-pass bilinear filter (+ compensation
+    with alpha_c = n/2 + 1) of Sec. 4.1 exactly: per axis the 1D stencil
+    ((1 + z)/2)^(2n) (compensation) is cut into three factors of at most 5 taps, and each
+    layer carries the outer product of its factor with itself in channel 0."""
+    room = [4, 4, 2 if compensate else 4]
+    left = 2 * npass
+    stencils = []
+    for r in room:
+        k = min(r, left)
+        left -= k
+        s = np.array([1.0])
+        for _ in range(k):
+            s = np.convolve(s, [0.5, 0.5])
+        stencils.append(s)
+    if left:
+        raise ValueError("at most 5 bilinear passes (4 with compensation) fit three 5-tap layers")
+    if compensate:
+        a = 0.5 * npass + 1.0
+        stencils[2] = np.convolve(stencils[2], [0.5 * (1.0 - a), a, 0.5 * (1.0 - a)])
+    out = np.zeros(LF_PARAMS, np.float32)
+    sizes = [(0, 1, 16), (400, 16, 16), (6800, 16, 1)]     # (offset, c_in, c_out) per layer
+    for (off, cin, cout), s in zip(sizes, stencils):
+        s5 = np.zeros(5)
+        s5[(5 - s.size) // 2:(5 - s.size) // 2 + s.size] = s
+        taps = np.outer(s5, s5).ravel()                      # t = 5 (dy + 2) + (dx + 2)
+        out[off + np.arange(25) * cin * cout] = taps         # (t, ci = 0, co = 0)
+    return out
+
+
+def _ck(code):
+    if code != 0:
+        raise BfError(code, lib().bf_status_string(code).decode())
+
+
+class LearnedFilter:
+    """The learned current filter on batches of device images (torch float32 tensors of shape
+    (nimg, ny, nx)): inference and training through the library's MFMA kernels.  Holds the
+    FP32 parameters and the Adam moments on the device."""
+
+    def __init__(self, params=None, device=None, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        p = np.zeros(LF_PARAMS, np.float32) if params is None else np.asarray(params, np.float32).ravel()
+        if p.size != LF_PARAMS:
+            raise ValueError(f"expected {LF_PARAMS} parameters")
+        self.params = torch.tensor(p, dtype=torch.float32, device=self.device)
+        self.m = torch.zeros(LF_PARAMS, dtype=torch.float32, device=self.device)
+        self.v = torch.zeros(LF_PARAMS, dtype=torch.float32, device=self.device)
+        self.t = 0
+        self.stream = stream
+        self._work = None
+
+    def _stream_ptr(self):
+        s = self.stream if self.stream is not None else self.torch.cuda.current_stream(self.device)
+        return C.c_void_p(s.cuda_stream)
+
+    def _work_for(self, nimg, ny, nx):
+        n = lib().bf_lf_work_bytes(nimg, ny, nx)
+        if n < 0:
+            raise BfError(-1, "bad image sizes")
+        if self._work is None or self._work.numel() < n:
+            self._work = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+        return self._work
+
+    @staticmethod
+    def _check(x):
+        if x.dtype != np.float32 and str(x.dtype) != "torch.float32":
+            raise TypeError("images must be float32")
+        if x.dim() != 3 or not x.is_contiguous():
+            raise ValueError("images must be a contiguous (nimg, ny, nx) tensor")
+
+    def apply(self, images, periodic=(False, False)):
+        self._check(images)
+        nimg, ny, nx = images.shape
+        out = self.torch.empty_like(images)
+        w = self._work_for(nimg, ny, nx)
+        _ck(lib().bf_lf_apply(C.c_void_p(w.data_ptr()), w.numel(), C.c_void_p(self.params.data_ptr()),
+                              C.c_void_p(images.data_ptr()), C.c_void_p(out.data_ptr()), nimg, ny, nx,
+                              int(periodic[0]), int(periodic[1]), self._stream_ptr()))
+        return out
+
+    def train_step(self, images, targets, margin, lr, beta1=0.9, beta2=0.999, eps=1e-8,
+                   periodic=(False, False), want_grad=False):
+        """One step; returns (loss, grad) as device tensors (grad None unless asked)."""
+        self._check(images)
+        self._check(targets)
+        nimg, ny, nx = images.shape
+        w = self._work_for(nimg, ny, nx)
+        loss = self.torch.zeros(1, dtype=self.torch.float64, device=self.device)
+        grad = self.torch.empty(LF_PARAMS, dtype=self.torch.float32, device=self.device) if want_grad else None
+        if lr != 0:
+            self.t += 1
+        _ck(lib().bf_lf_train_step(C.c_void_p(w.data_ptr()), w.numel(), C.c_void_p(self.params.data_ptr()),
+                                   C.c_void_p(self.m.data_ptr()), C.c_void_p(self.v.data_ptr()),
+                                   C.c_void_p(images.data_ptr()), C.c_void_p(targets.data_ptr()),
+                                   nimg, ny, nx, margin, int(periodic[0]), int(periodic[1]), lr, beta1,
+                                   beta2, eps, max(self.t, 1),
+                                   C.c_void_p(grad.data_ptr()) if grad is not None else None,
+                                   C.c_void_p(loss.data_ptr()), self._stream_ptr()))
+        return loss, grad

@@ -6,6 +6,7 @@
 //    Etilde = (1+theta/4) E^n - 1/2 E^{n-1} + (1/2-theta/4) Ebar (Sec. 4.3, Eq.
 //    Faraday_Friedman, indices shifted by one), split-field PML (Appendix II) on the borders.
 //  * k_ampere: Yee Ampere E^{n+1} = E^n + dt (curl B^{n+1/2} - J) with the PML split.
+//    k_faraday, first in the step, clears the raw current the deposit accumulates into.
 //  * k_filter: n bilinear passes plus compensation per axis (Sec. 4.1), all passes of one
 //    axis run in LDS on a tile with an (n + 1)-cell halo.
 //  * k_window_rows: moving-window advance = ring offset change + clearing the new rows.
@@ -126,11 +127,14 @@ __global__ void __launch_bounds__(256) k_faraday(Geo g, FieldSet<R> f, PmlTab<R>
         for (int c = 0; c < 3; c++)
             f.Ebn[c][o] = (R(1) - R(0.5) * th) * f.Eo[c][o] + R(0.5) * th * f.Eb[c][o];
     }
+    // the raw current of the previous step is cleared here, at the start of the step, so that
+    // it stays readable between steps
+    for (int c = 0; c < 3; c++) f.J[c][o] = R(0);
 }
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_ampere(Geo g, FieldSet<R> f, PmlTab<R> pm, R dt, R idx,
-                                                R idz, int zero_raw)
+                                                R idz)
 {
     const int i = blockIdx.x * 64 + (threadIdx.x & 63);
     const int k = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -176,11 +180,6 @@ __global__ void __launch_bounds__(256) k_ampere(Geo g, FieldSet<R> f, PmlTab<R> 
             }
         }
         f.Eo[1][o] = e;
-    }
-    if (zero_raw) {
-        f.J[0][o] = R(0);
-        f.J[1][o] = R(0);
-        f.J[2][o] = R(0);
     }
 }
 
@@ -389,11 +388,10 @@ void launch_faraday(const Geo& g, const FieldSet<R>& f, const PmlTab<R>& pm, con
 
 template <typename R>
 void launch_ampere(const Geo& g, const FieldSet<R>& f, const PmlTab<R>& pm, const SolverCoef& c,
-                   bool zero_raw, hipStream_t s)
+                   hipStream_t s)
 {
     dim3 grid((g.Sx + 63) / 64, (g.Sz + 3) / 4);
-    hipLaunchKernelGGL((k_ampere<R>), grid, dim3(256), 0, s, g, f, pm, (R)c.dt, (R)c.idx, (R)c.idz,
-                       zero_raw ? 1 : 0);
+    hipLaunchKernelGGL((k_ampere<R>), grid, dim3(256), 0, s, g, f, pm, (R)c.dt, (R)c.idx, (R)c.idz);
 }
 
 template <typename R>
@@ -445,7 +443,7 @@ void launch_fill_int(int* p, int n, int v, hipStream_t s)
     template void launch_faraday<R>(const Geo&, const FieldSet<R>&, const PmlTab<R>&,              \
                                     const SolverCoef&, hipStream_t);                               \
     template void launch_ampere<R>(const Geo&, const FieldSet<R>&, const PmlTab<R>&,               \
-                                   const SolverCoef&, bool, hipStream_t);                          \
+                                   const SolverCoef&, hipStream_t);                                \
     template void launch_filter<R>(const Geo&, R* const[3], R* const[3], const int[3],             \
                                    const int[3], int, int, int, hipStream_t);                      \
     template void launch_window_rows<R>(const Geo&, const PtrList<R>&, int, const EntryRows&,      \

@@ -17,6 +17,7 @@
 
 #include "../../include/bfpic.h"
 #include "bf_kernels.h"
+#include "bf_lfilter.h"
 
 using namespace bf;
 
@@ -66,7 +67,8 @@ struct Layout {
     int tile_x, tile_z, ntx, ntz, ntiles, nchunks, seg_cap;
     // work buffer
     size_t w_seg[2], w_bbe[2], w_segi[2], w_bbi[2], w_counts, w_cursor, w_nused, w_status,
-        w_pml_r, w_pml_on, w_st_z, w_st_rec, w_st_cnt, w_ant, w_rho, w_bytes;
+        w_pml_r, w_pml_on, w_st_z, w_st_rec, w_st_cnt, w_ant, w_rho, w_lf_par, w_lf_pk[3], w_lf_h1,
+        w_lf_h2, w_bytes;
     int nst, stcap;
 };
 
@@ -120,6 +122,15 @@ bool layout_of(const bf_config* c, Layout* L)
     L->w_st_cnt = take(sizeof(int) * std::max(L->nst, 1));
     L->w_ant = take(sizeof(double) * (size_t)c->nx);
     L->w_rho = take(2 * sizeof(double) * (size_t)L->Sx * L->Sz);
+    // learned filter: FP32 parameters, packed BF16 fragments of the three layers, two
+    // 16-channel intermediate images of the stored grid
+    const bool lfk = c->filter_kind == BF_FILTER_LEARNED;
+    const int nq[3] = {lf::chunks(1), lf::chunks(lf::C), lf::chunks(lf::C)};
+    L->w_lf_par = take(lfk ? sizeof(float) * lf::NPARAM : 0);
+    for (int k = 0; k < 3; k++) L->w_lf_pk[k] = take(lfk ? (size_t)nq[k] * lf::CHUNK_BYTES : 0);
+    const size_t hbytes = lfk ? sizeof(float) * lf::C * (size_t)L->Sx * L->Sz : 0;
+    L->w_lf_h1 = take(hbytes);
+    L->w_lf_h2 = take(hbytes);
     L->w_bytes = o;
     return true;
 }
@@ -151,6 +162,8 @@ bf_status validate(const bf_config* c)
     if (c->shape_order != 3) return BF_EUNSUPPORTED;
     if (c->friedman_theta < 0 || c->friedman_theta > 1) return BF_EINVAL;
     if (c->filter_npass < 0 || c->filter_npass > 10) return BF_EINVAL;
+    if (c->filter_kind != BF_FILTER_BILINEAR && c->filter_kind != BF_FILTER_LEARNED) return BF_EINVAL;
+    if (c->filter_kind == BF_FILTER_LEARNED && c->real_bytes != 4) return BF_EUNSUPPORTED;
     if (c->pml_cells < 0 || c->pml_cells > 64) return BF_EINVAL;
     if ((c->periodic_mask & 1) == 0 && c->pml_cells < 4) return BF_EINVAL;
     if (((c->periodic_mask >> 2) & 1) == 0 && c->pml_cells < 4) return BF_EINVAL;
@@ -180,12 +193,12 @@ struct bf_sim {
     double dt = 0, dt_crit = 0, beta = 0, gamma = 1, a2 = 1, b2 = 0, theta = 0, vw = 0;
     double n0 = 0, omega = 0, e0 = 0, w0 = 0, sig_t = 0, t0 = 0, za_lab = 0, aw = 0;
     bf_plasma plasma{};
-    int have_plasma = 0, have_laser = 0;
+    int have_plasma = 0, have_laser = 0, have_lf = 0;
     int e_cur = 0, b_cur = 0, eb_cur = 0, p_cur = 0, bb_cur = 0, sg_cur = 0;
     int nseg_e = 0, nseg_i = 0;
     int64_t step = 0, shift = 0, next_row = 0;
     double t = 0;
-    int since_sort = 0, sort_every = 20, lds_cells = 0;
+    int since_sort = 0, sort_every = 20;
     int nst = 0;
     std::vector<double> st_z;
     int err = BF_OK;
@@ -270,7 +283,8 @@ FieldSet<R> field_set(const bf_sim* s)
         f.B[c] = s->arr<R>((b ? A_B1 : A_B0) + c);
         f.Bn[c] = s->arr<R>((b ? A_B0 : A_B1) + c);
         f.J[c] = s->arr<R>(A_J + c);
-        f.Jf[c] = s->cfg.filter_npass > 0 ? s->arr<R>(A_JF + c) : s->arr<R>(A_J + c);
+        f.Jf[c] = (s->cfg.filter_npass > 0 || s->cfg.filter_kind == BF_FILTER_LEARNED)
+                      ? s->arr<R>(A_JF + c) : s->arr<R>(A_J + c);
     }
     f.Byx = s->arr<R>(A_BYX);
     f.Eyx = s->arr<R>(A_EYX);
@@ -493,6 +507,35 @@ PtrList<R> all_arrays(const bf_sim* s)
     return p;
 }
 
+lf::Packed lf_packed(bf_sim* s)
+{
+    lf::Packed p{};
+    for (int k = 0; k < 3; k++) p.fwd[k] = s->w<unsigned char>(s->L.w_lf_pk[k]);
+    return p;
+}
+
+// the learned filter on J_x, J_y, J_z, each on its own staggered domain (as the bilinear
+// filter), reading and writing the ring-buffered rows in place
+void learned_filter(bf_sim* s, const FieldSet<float>& f)
+{
+    const Geo& g = s->g;
+    const int hx[3] = {1, 0, 0}, hz[3] = {0, 0, 1};
+    const lf::Packed pk = lf_packed(s);
+    for (int c = 0; c < 3; c++) {
+        lf::Domain d;
+        d.nimg = 1;
+        d.nx = g.perx ? g.Sx : g.Sx - hx[c];
+        d.ny = g.perz ? g.Sz : g.Sz - hz[c];
+        d.perx = g.perx;
+        d.pery = g.perz;
+        lf::View jin{f.J[c], 0, g.pitch, 1, g.zoff, g.Sz};
+        lf::View jout{f.Jf[c], 0, g.pitch, 1, g.zoff, g.Sz};
+        lf::View h1{s->w<float>(s->L.w_lf_h1), 0, (long)d.nx * lf::C, lf::C, 0, d.ny};
+        lf::View h2{s->w<float>(s->L.w_lf_h2), 0, (long)d.nx * lf::C, lf::C, 0, d.ny};
+        lf::forward(jin, h1, h2, jout, d, pk, s->stream);
+    }
+}
+
 template <typename R>
 bf_status step_impl(bf_sim* s, int nsteps)
 {
@@ -529,7 +572,6 @@ bf_status step_impl(bf_sim* s, int nsteps)
         pp.fjz = (R)(1.0 / (c.dx_um * s->dt));
         pp.fjy = (R)(-1.0 / (c.dx_um * c.dz_um));
         pp.shift = d;
-        pp.lds_cells = s->lds_cells;
         t_ph = s->tick();
         launch_gpd<R>(s->g, f, electrons<R>(s, s->p_cur), seg_e(s, s->sg_cur), bb_e(s, s->bb_cur),
                       bb_e(s, 1 - s->bb_cur), s->nseg_e, pp, status_word(s), s->stream);
@@ -539,7 +581,7 @@ bf_status step_impl(bf_sim* s, int nsteps)
         if (s->have_plasma && s->plasma.ion_mode == 1)
             launch_ions<R>(s->g, f, ions<R>(s, s->p_cur), seg_i(s, s->sg_cur), bb_i(s, s->bb_cur),
                            bb_i(s, 1 - s->bb_cur), s->nseg_i, ion_shift(s, s->t), ion_shift(s, t1), d,
-                           (R)(-1.0 / (c.dx_um * s->dt)), 4096, s->stream);
+                           (R)(-1.0 / (c.dx_um * s->dt)), s->stream);
         s->tock(t_ph, BF_PHASE_IONS);
         // antenna
         t_ph = s->tick();
@@ -558,16 +600,18 @@ bf_status step_impl(bf_sim* s, int nsteps)
         s->tock(t_ph, BF_PHASE_ANTENNA);
         // filter
         t_ph = s->tick();
-        if (c.filter_npass > 0) {
+        if (c.filter_kind == BF_FILTER_LEARNED) {
+            if constexpr (sizeof(R) == 4) learned_filter(s, f);
+        } else if (c.filter_npass > 0) {
             R* in[3] = {f.J[0], f.J[1], f.J[2]};
             R* out[3] = {f.Jf[0], f.Jf[1], f.Jf[2]};
             const int hx[3] = {1, 0, 0}, hz[3] = {0, 0, 1};
             launch_filter<R>(s->g, in, out, hx, hz, 3, c.filter_npass, c.filter_compensate, s->stream);
         }
         s->tock(t_ph, BF_PHASE_FILTER);
-        // Ampere + PML (E^{n+1} into the E^{n-1} set), clears raw J
+        // Ampere + PML (E^{n+1} into the E^{n-1} set)
         t_ph = s->tick();
-        launch_ampere<R>(s->g, f, pm, sc, true, s->stream);
+        launch_ampere<R>(s->g, f, pm, sc, s->stream);
         s->tock(t_ph, BF_PHASE_AMPERE);
         s->e_cur ^= 1;
         s->b_cur ^= 1;
@@ -686,9 +730,6 @@ bf_status bf_create(const bf_config* cfg, const bf_buffer_binding* b, int n, voi
     s->dt_crit = cfl2d(cfg->ck_alpha, cfg->ck_beta, cfg->ck_gamma, cfg->dx_um, cfg->dz_um, s->theta);
     s->dt = cfg->cfl_fraction * s->dt_crit;
     s->sort_every = cfg->sort_every > 0 ? cfg->sort_every : 20;
-    // LDS tile budget in cells (6 field components in the run's precision + 3 FP64 current
-    // accumulators): 768 cells = 36 KB (FP32) keeps four 256-thread workgroups per CU
-    s->lds_cells = cfg->real_bytes == 4 ? 768 : 640;
     s->g = geo_of(s, 0);
     update_window_speed(s);
     hipError_t e = hipSuccess;
@@ -820,11 +861,28 @@ bf_status bf_step(bf_sim* s, int nsteps)
     bf_status st = guard(s);
     if (st != BF_OK) return st;
     if (nsteps < 0) return fail(s, BF_EINVAL, "negative step count");
+    if (s->cfg.filter_kind == BF_FILTER_LEARNED && !s->have_lf)
+        return fail(s, BF_ESTATE, "learned filter selected but its parameters are not loaded");
     if (s->cfg.real_bytes == 4) st = step_impl<float>(s, nsteps);
     else st = step_impl<double>(s, nsteps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_check(s, e, "step launch");
     return st;
+}
+
+bf_status bf_set_learned_filter(bf_sim* s, const float* host_params, int64_t n)
+{
+    if (!s || !host_params || n != lf::NPARAM) return BF_EINVAL;
+    if (s->cfg.filter_kind != BF_FILTER_LEARNED) return fail(s, BF_ESTATE, "handle uses the bilinear filter");
+    float* dev = s->w<float>(s->L.w_lf_par);
+    hipError_t e = hipMemcpyAsync(dev, host_params, sizeof(float) * lf::NPARAM, hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) return hip_check(s, e, "learned filter parameters");
+    lf::pack_forward(dev, lf_packed(s), s->stream);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_check(s, e, "learned filter packing");
+    s->have_lf = 1;
+    return BF_OK;
 }
 
 bf_status bf_sync_status(bf_sim* s)
@@ -855,7 +913,10 @@ static void field_ptr_of(const bf_sim* s, int id, int* arr_index)
     case BF_F_BXO: case BF_F_BYO: case BF_F_BZO: a = (b ? A_B0 : A_B1) + (id - BF_F_BXO); break;
     case BF_F_EXB: case BF_F_EYB: case BF_F_EZB: a = (eb ? A_EB1 : A_EB0) + (id - BF_F_EXB); break;
     case BF_F_JX: case BF_F_JY: case BF_F_JZ:
-        a = (s->cfg.filter_npass > 0 ? A_JF : A_J) + (id - BF_F_JX); break;
+        a = (s->cfg.filter_npass > 0 || s->cfg.filter_kind == BF_FILTER_LEARNED ? A_JF : A_J) + (id - BF_F_JX);
+        break;
+    case BF_F_JXR: case BF_F_JYR: case BF_F_JZR:
+        a = A_J + (id - BF_F_JXR); break;
     case BF_F_BYX: a = A_BYX; break;
     case BF_F_EYX: a = A_EYX; break;
     default: a = -1;

@@ -72,7 +72,6 @@ struct PushParams {
     R dtdx, dtdz;      // dt / dx, dt / dz  (cell units per unit velocity)
     R fjx, fjz, fjy;   // -q/(dz dt), -q/(dx dt), q/(dx dz)   (times w, v_y)
     int shift;         // window shift (cells) applied after this step
-    int lds_cells;     // capacity of the LDS tile in cells (per field component)
 };
 
 struct InjectParams {
@@ -111,7 +110,7 @@ void launch_faraday(const Geo& g, const FieldSet<R>& f, const PmlTab<R>& pm, con
                     hipStream_t s);
 template <typename R>
 void launch_ampere(const Geo& g, const FieldSet<R>& f, const PmlTab<R>& pm, const SolverCoef& c,
-                   bool zero_raw, hipStream_t s);
+                   hipStream_t s);
 template <typename R>
 void launch_filter(const Geo& g, R* const in[3], R* const out[3], const int hx[3],
                    const int hz[3], int ncomp, int npass, int compensate, hipStream_t s);
@@ -137,7 +136,7 @@ void launch_gpd(const Geo& g, const FieldSet<R>& f, const ElectronArrays<R>& e,
 template <typename R>
 void launch_ions(const Geo& g, const FieldSet<R>& f, const IonArrays<R>& ion, const Segment* seg,
                  const int4* bbox_in, int4* bbox_out, int nseg, double zsh_a, double zsh_b,
-                 int shift, R fjz, int lds_cells, hipStream_t s);
+                 int shift, R fjz, hipStream_t s);
 template <typename R>
 void launch_antenna(const Geo& g, const FieldSet<R>& f, double* xminus, const AntennaParams& ap,
                     hipStream_t s);

@@ -21,24 +21,82 @@ namespace bf {
 
 constexpr int NTHR = 256;
 
+// sum of v over the workgroup, returned to every thread (red: NTHR/64 doubles of LDS)
+__device__ __forceinline__ double block_sum(double v, double* red)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NTHR / 64; w++) t += red[w];
+    return t;
+}
+
 // ---- accessors ---------------------------------------------------------------------------
-// field component ids inside the staged tile: 0..2 E, 3..5 B (time-centred)
+// The staged tile has a fixed odd row pitch, so every stencil offset is a compile-time
+// immediate of the LDS instruction and rows of one column fall in different banks.
+constexpr int TPX = 33;                 // row pitch of the staged tile (cells)
+// rows of the staged tile: 6 field planes + 3 FP64 current planes stay under 64 KB
+template <typename R> constexpr int trows() { return sizeof(R) == 4 ? 31 : 21; }
+template <typename R> constexpr int tcells() { return TPX * trows<R>(); }
+
+// Current accumulator of the staged tile.  FP32 runs accumulate in 64-bit integer fixed
+// point: the integer LDS add is faster than the FP64 one on gfx950 (the FP32 LDS add is far
+// slower than either), and integer sums do not depend on the order of the adds.  The quantum q
+// of a segment is max|fj| * sum|w| / 2^46, so no cell's sum reaches 2^46 quanta.  A
+// contribution v is rounded by one FMA, t = v/q + 1.5 * 2^52, whose bit pattern is the
+// constant 0x4338000000000000 plus round(v/q) as a 64-bit two's-complement integer.  The raw
+// bit patterns are summed: the constant only touches bits 48..63, so the low 48 bits of the
+// sum, sign-extended, are the exact sum of the rounded contributions.  FP64 runs accumulate
+// in FP64.
+template <typename R> struct JAcc { using T = double; static constexpr bool fixed = false; };
+template <> struct JAcc<float> { using T = unsigned long long; static constexpr bool fixed = true; };
+constexpr double FIX_MAGIC = 6755399441055744.0;   // 1.5 * 2^52
+constexpr double FIX_RANGE = 70368744177664.0;     // 2^46
+
+// value of a fixed-point tile sum: sign-extended low 48 bits
+__device__ __forceinline__ double fix_value(unsigned long long t)
+{
+    return (double)((long long)(t << 16) >> 16);
+}
+
+// field component ids inside the staged tile: 0..2 E, 3..5 B (time-centred).
+// A handle is the offset of a stencil's lower corner; stencil nodes are (handle, a, b).
 template <typename R>
 struct LdsAcc {
-    R* f;       // 6 x L
-    double* j;  // 3 x L, accumulated with FP64 LDS atomics (the FP32 ones are far slower)
-    int xb, zb, lx, lz, L;
+    static constexpr int TCELLS = tcells<R>();
+    static constexpr bool FIX = JAcc<R>::fixed;
+    using JT = typename JAcc<R>::T;
+    R* f;       // 6 planes of TCELLS
+    JT* j;      // 3 planes of TCELLS
+    int xb, zb, lx, lz;
     __device__ __forceinline__ bool inside(int jx0, int jx1, int jz0, int jz1) const
     {
         return jx0 >= xb && jx1 < xb + lx && jz0 >= zb && jz1 < zb + lz;
     }
-    __device__ __forceinline__ R fld(int c, int jx, int jz) const
+    __device__ __forceinline__ int handle(int jx, int jz) const { return (jz - zb) * TPX + (jx - xb); }
+    __device__ __forceinline__ R fld(int h, int c, int a, int b) const
     {
-        return f[c * L + (jz - zb) * lx + (jx - xb)];
+        return f[c * TCELLS + h + b * TPX + a];
     }
-    __device__ __forceinline__ void dep(int c, int jx, int jz, R v) const
+    // contributions a*b and a*b + c*d, already in quanta for the fixed-point tile
+    __device__ __forceinline__ double prod(double a, double b) const
     {
-        atomicAdd(&j[c * L + (jz - zb) * lx + (jx - xb)], (double)v);
+        if constexpr (FIX) return fma(a, b, FIX_MAGIC);
+        else return a * b;
+    }
+    __device__ __forceinline__ double prod2(double a, double b, double c, double d) const
+    {
+        if constexpr (FIX) return fma(a, b, fma(c, d, FIX_MAGIC));
+        else return a * b + c * d;
+    }
+    __device__ __forceinline__ void dep(int h, int c, int a, int b, double v) const
+    {
+        if constexpr (FIX)
+            atomicAdd(&j[c * TCELLS + h + b * TPX + a], (unsigned long long)__double_as_longlong(v));
+        else
+            atomicAdd(&j[c * TCELLS + h + b * TPX + a], v);
     }
 };
 
@@ -50,19 +108,25 @@ struct GlobAcc {
     const R* Bn[3];
     R* J[3];
     __device__ __forceinline__ bool inside(int, int, int, int) const { return true; }
-    __device__ __forceinline__ R fld(int c, int jx, int jz) const
+    __device__ __forceinline__ int2 handle(int jx, int jz) const { return make_int2(jx, jz); }
+    __device__ __forceinline__ R fld(int2 h, int c, int a, int b) const
     {
-        int i = swrap(jx + g.Px, g.Sx, g.perx), k = swrap(jz + g.Pz, g.Sz, g.perz);
+        int i = swrap(h.x + a + g.Px, g.Sx, g.perx), k = swrap(h.y + b + g.Pz, g.Sz, g.perz);
         if (i < 0 || k < 0) return R(0);
         long o = gofs(g, i, k);
         if (c < 3) return E[c][o];
         return R(0.5) * (B[c - 3][o] + Bn[c - 3][o]);
     }
-    __device__ __forceinline__ void dep(int c, int jx, int jz, R v) const
+    __device__ __forceinline__ double prod(double a, double b) const { return a * b; }
+    __device__ __forceinline__ double prod2(double a, double b, double c, double d) const
     {
-        int i = swrap(jx + g.Px, g.Sx, g.perx), k = swrap(jz + g.Pz, g.Sz, g.perz);
+        return a * b + c * d;
+    }
+    __device__ __forceinline__ void dep(int2 h, int c, int a, int b, double v) const
+    {
+        int i = swrap(h.x + a + g.Px, g.Sx, g.perx), k = swrap(h.y + b + g.Pz, g.Sz, g.perz);
         if (i < 0 || k < 0) return;
-        atomicAdd(&J[c][gofs(g, i, k)], v);
+        atomicAdd(&J[c][gofs(g, i, k)], (R)v);
     }
 };
 
@@ -80,67 +144,86 @@ __device__ __forceinline__ GlobAcc<R> make_glob(const Geo& g, const FieldSet<R>&
     return a;
 }
 
-// shape factors of a particle on the 5-node window starting at node `base`:
-// nonzero at offsets o-1 .. o+2 where o = i - base (1 or 2)
-template <typename R>
-__device__ __forceinline__ void window5(R f, int o, R s[5])
+// reciprocal and reciprocal square root: the hardware instructions (1 ulp) in FP32, exact
+// division in FP64
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
+
+// cubic B-spline weights (FP64) of a particle at fraction f of its cell, on the 5-node window
+// starting one node below the particle's (hi = false) or two below (hi = true)
+__device__ __forceinline__ void window5(double f, bool hi, double s[5])
 {
-    R w[4];
-    bspline3(f, w);
-    if (o == 1) { s[0] = w[0]; s[1] = w[1]; s[2] = w[2]; s[3] = w[3]; s[4] = R(0); }
-    else        { s[0] = R(0); s[1] = w[0]; s[2] = w[1]; s[3] = w[2]; s[4] = w[3]; }
+    const double g = 1.0 - f, f2 = f * f, f3 = f2 * f, sixth = 1.0 / 6.0;
+    const double w0 = g * g * g * sixth;
+    const double w1 = (3.0 * f3 - 6.0 * f2 + 4.0) * sixth;
+    const double w2 = (-3.0 * f3 + 3.0 * f2 + 3.0 * f + 1.0) * sixth;
+    const double w3 = f3 * sixth;
+    s[0] = hi ? 0.0 : w0;
+    s[1] = hi ? w0 : w1;
+    s[2] = hi ? w1 : w2;
+    s[3] = hi ? w2 : w3;
+    s[4] = hi ? w3 : 0.0;
 }
 
 // Esirkepov (2001) current of one particle moving (ix+fx, iz+fz) -> (ix1+fx1, iz1+fz1),
-// |displacement| < 1 cell per axis.  2-1/2D form:
+// |displacement| < 1 cell per axis, on the 5x5 window whose lower corner is
+// (min(ix,ix1)-1, min(iz,iz1)-1).  With S0, S1 the old and new shape factors and
+// DS = S1 - S0, the 2-1/2D weights are
 //   W_x = DS_x (S0_z + DS_z/2),  W_z = DS_z (S0_x + DS_x/2),
 //   W_y = S0_x S0_z + DS_x S0_z/2 + S0_x DS_z/2 + DS_x DS_z/3,
-//   J_x(i+1/2) - J_x(i-1/2) = cx W_x(i), J_z likewise, J_y = cy W_y.
-template <typename R, typename A>
-__device__ __forceinline__ void esirkepov(const A& acc, int ix, R fx, int iz, R fz, int ix1, R fx1,
-                                          int iz1, R fz1, R cx, R cz, R cy)
+// J_x(i+1/2) - J_x(i-1/2) = cx W_x(i) (likewise z), J_y = cy W_y.  Evaluated in factored
+// form: J_x(m,b) = cx (S0_z+S1_z)(b)/2 * sum_{k<=m} DS_x(k),  J_z likewise, and
+// W_y = S0_x (S0_z/3 + S1_z/6) + S1_x (S0_z/6 + S1_z/3).
+template <typename A>
+__device__ __forceinline__ void esirkepov(const A& acc, int ix, double fx, int iz, double fz, int ix1,
+                                          double fx1, int iz1, double fz1, double cx, double cz,
+                                          double cy)
 {
     const int bx = min(ix, ix1) - 1, bz = min(iz, iz1) - 1;
-    R S0x[5], S1x[5], S0z[5], S1z[5];
-    window5(fx, ix - bx, S0x);
-    window5(fx1, ix1 - bx, S1x);
-    window5(fz, iz - bz, S0z);
-    window5(fz1, iz1 - bz, S1z);
-    R DSx[5], DSz[5];
+    double S0x[5], S1x[5], S0z[5], S1z[5];
+    window5(fx, ix > bx + 1, S0x);
+    window5(fx1, ix1 > bx + 1, S1x);
+    window5(fz, iz > bz + 1, S0z);
+    window5(fz1, iz1 > bz + 1, S1z);
+    const auto h = acc.handle(bx, bz);
+    if (cx != 0.0) {
+        double czf[5];
 #pragma unroll
-    for (int m = 0; m < 5; m++) { DSx[m] = S1x[m] - S0x[m]; DSz[m] = S1z[m] - S0z[m]; }
-    if (cx != R(0)) {
+        for (int b = 0; b < 5; b++) czf[b] = 0.5 * cx * (S0z[b] + S1z[b]);
+        double pd = 0.0;
 #pragma unroll
-        for (int b = 0; b < 5; b++) {
-            R zf = S0z[b] + R(0.5) * DSz[b];
-            R acc_ = R(0);
+        for (int m = 0; m < 4; m++) {
+            pd += S1x[m] - S0x[m];
 #pragma unroll
-            for (int m = 0; m < 4; m++) {
-                acc_ += DSx[m] * zf;
-                acc.dep(0, bx + m, bz + b, cx * acc_);
-            }
+            for (int b = 0; b < 5; b++) acc.dep(h, 0, m, b, acc.prod(pd, czf[b]));
         }
     }
+    {
+        double cxf[5];
 #pragma unroll
-    for (int m = 0; m < 5; m++) {
-        R xf = S0x[m] + R(0.5) * DSx[m];
-        R acc_ = R(0);
+        for (int m = 0; m < 5; m++) cxf[m] = 0.5 * cz * (S0x[m] + S1x[m]);
+        double pd = 0.0;
 #pragma unroll
         for (int b = 0; b < 4; b++) {
-            acc_ += DSz[b] * xf;
-            acc.dep(2, bx + m, bz + b, cz * acc_);
+            pd += S1z[b] - S0z[b];
+#pragma unroll
+            for (int m = 0; m < 5; m++) acc.dep(h, 2, m, b, acc.prod(pd, cxf[m]));
         }
     }
-    if (cy != R(0)) {
-        const R third = R(1) / R(3);
+    if (cy != 0.0) {
+        const double c3 = cy * (1.0 / 3.0), c6 = cy * (1.0 / 6.0);
+        double P[5], Q[5];
 #pragma unroll
-        for (int m = 0; m < 5; m++)
+        for (int b = 0; b < 5; b++) {
+            P[b] = c3 * S0z[b] + c6 * S1z[b];
+            Q[b] = c6 * S0z[b] + c3 * S1z[b];
+        }
 #pragma unroll
-            for (int b = 0; b < 5; b++) {
-                R W = S0x[m] * S0z[b] + R(0.5) * DSx[m] * S0z[b] + R(0.5) * S0x[m] * DSz[b]
-                    + third * DSx[m] * DSz[b];
-                acc.dep(1, bx + m, bz + b, cy * W);
-            }
+        for (int b = 0; b < 5; b++)
+#pragma unroll
+            for (int m = 0; m < 5; m++) acc.dep(h, 1, m, b, acc.prod2(S0x[m], P[b], S1x[m], Q[b]));
     }
 }
 
@@ -156,18 +239,20 @@ __device__ __forceinline__ void gather(const A& acc, double x, double z, R E[3],
     bspline3((R)(xh - ixh), wxh);
     bspline3((R)(z - iz), wzn);
     bspline3((R)(zh - izh), wzh);
+    const auto hnn = acc.handle(ix - 1, iz - 1), hhn = acc.handle(ixh - 1, iz - 1);
+    const auto hnh = acc.handle(ix - 1, izh - 1), hhh = acc.handle(ixh - 1, izh - 1);
     R e0 = 0, e1 = 0, e2 = 0, b0 = 0, b1 = 0, b2 = 0;
 #pragma unroll
     for (int b = 0; b < 4; b++) {
         R ex = 0, ey = 0, ez = 0, bx = 0, by = 0, bz = 0;
 #pragma unroll
         for (int a = 0; a < 4; a++) {
-            ex += wxh[a] * acc.fld(0, ixh - 1 + a, iz - 1 + b);
-            ey += wxn[a] * acc.fld(1, ix - 1 + a, iz - 1 + b);
-            bz += wxh[a] * acc.fld(5, ixh - 1 + a, iz - 1 + b);
-            ez += wxn[a] * acc.fld(2, ix - 1 + a, izh - 1 + b);
-            bx += wxn[a] * acc.fld(3, ix - 1 + a, izh - 1 + b);
-            by += wxh[a] * acc.fld(4, ixh - 1 + a, izh - 1 + b);
+            ex += wxh[a] * acc.fld(hhn, 0, a, b);
+            ey += wxn[a] * acc.fld(hnn, 1, a, b);
+            bz += wxh[a] * acc.fld(hhn, 5, a, b);
+            ez += wxn[a] * acc.fld(hnh, 2, a, b);
+            bx += wxn[a] * acc.fld(hnh, 3, a, b);
+            by += wxh[a] * acc.fld(hhh, 4, a, b);
         }
         e0 += wzn[b] * ex; e1 += wzn[b] * ey; b2 += wzn[b] * bz;
         e2 += wzh[b] * ez; b0 += wzh[b] * bx; b1 += wzh[b] * by;
@@ -181,11 +266,10 @@ template <typename R>
 __device__ __forceinline__ void boris(R h, const R E[3], const R B[3], R& ux, R& uy, R& uz)
 {
     R umx = ux + h * E[0], umy = uy + h * E[1], umz = uz + h * E[2];
-    R g = sqrt(R(1) + umx * umx + umy * umy + umz * umz);
-    R ig = R(1) / g;
+    R ig = rsqrt_(R(1) + umx * umx + umy * umy + umz * umz);
     R tx = h * B[0] * ig, ty = h * B[1] * ig, tz = h * B[2] * ig;
     R t2 = tx * tx + ty * ty + tz * tz;
-    R sf = R(2) / (R(1) + t2);
+    R sf = R(2) * rcp_(R(1) + t2);
     R sx = sf * tx, sy = sf * ty, sz = sf * tz;
     R upx = umx + (umy * tz - umz * ty);
     R upy = umy + (umz * tx - umx * tz);
@@ -198,27 +282,55 @@ __device__ __forceinline__ void boris(R h, const R E[3], const R B[3], R& ux, R&
     uz = uqz + h * E[2];
 }
 
-// one electron with accessor A: gather, push, deposit, absorb, rebase; updates the box.
-// The caller guarantees the gather window [ix-2, ix+2] and the deposit window [ix-2, ix+3]
-// (one-cell move) are addressable through A.
+// the state of one electron as read from HBM
+template <typename R>
+struct EState {
+    double x, z;
+    R ux, uy, uz, w;
+};
+
+template <typename R>
+__device__ __forceinline__ EState<R> load_electron(const ElectronArrays<R>& e, int p)
+{
+    return EState<R>{e.x[p], e.z[p], e.ux[p], e.uy[p], e.uz[p], e.w[p]};
+}
+
+// writes back an advanced state (the weight only when the particle was absorbed)
+template <typename R>
+__device__ __forceinline__ void store_electron(const ElectronArrays<R>& e, int p, const EState<R>& st)
+{
+    e.x[p] = st.x;
+    e.z[p] = st.z;
+    e.ux[p] = st.ux;
+    e.uy[p] = st.uy;
+    e.uz[p] = st.uz;
+    if (st.w == R(0)) e.w[p] = R(0);
+}
+
+// one electron with accessor A: gather, push, deposit, absorb (w = 0), rebase; st is advanced
+// in place (the caller writes it back) and the box is updated.  The caller guarantees the
+// gather window [ix-2, ix+2] and the deposit window [ix-2, ix+3] (one-cell move) are
+// addressable through A.  js scales the current into A's units.
 template <typename R, typename A>
 __device__ __forceinline__ void advance_electron(const A& acc, const Geo& g, const PushParams<R>& pp,
-                                                 const ElectronArrays<R>& e, int p, R w, int* status,
-                                                 int& x0, int& x1, int& z0, int& z1)
+                                                 EState<R>& st, double js, int* status, int& x0,
+                                                 int& x1, int& z0, int& z1)
 {
-    double x = e.x[p], z = e.z[p];
-    R ux = e.ux[p], uy = e.uy[p], uz = e.uz[p];
+    const double x = st.x, z = st.z;
+    const R w = st.w;
+    R ux = st.ux, uy = st.uy, uz = st.uz;
     const int ix = (int)floor(x), iz = (int)floor(z);
     R E[3], B[3];
     gather(acc, x, z, E, B);
     boris(pp.qdt2, E, B, ux, uy, uz);
-    const R ig = R(1) / sqrt(R(1) + ux * ux + uy * uy + uz * uz);
+    const R ig = rsqrt_(R(1) + ux * ux + uy * uy + uz * uz);
     const R vx = ux * ig, vy = uy * ig, vz = uz * ig;
     const double xn = x + (double)(pp.dtdx * vx), zn = z + (double)(pp.dtdz * vz);
     const int ix1 = (int)floor(xn), iz1 = (int)floor(zn);
     if (abs(ix1 - ix) <= 1 && abs(iz1 - iz) <= 1) {
-        const R fx = (R)(x - ix), fz = (R)(z - iz), fx1 = (R)(xn - ix1), fz1 = (R)(zn - iz1);
-        esirkepov(acc, ix, fx, iz, fz, ix1, fx1, iz1, fz1, pp.fjx * w, pp.fjz * w, pp.fjy * w * vy);
+        const double jw = js * (double)w;
+        esirkepov(acc, ix, x - ix, iz, z - iz, ix1, xn - ix1, iz1, zn - iz1, jw * (double)pp.fjx,
+                  jw * (double)pp.fjz, jw * (double)(pp.fjy * vy));
     } else {
         atomicOr(status, ST_NONFINITE);   // faster than light: only a non-finite state gets here
     }
@@ -227,13 +339,13 @@ __device__ __forceinline__ void advance_electron(const A& acc, const Geo& g, con
     if (!g.perx && (xn < 0.0 || xn >= (double)g.Nx)) alive = false;
     if (!g.perz && (zn < 0.0 || zn >= (double)g.Nz)) alive = false;
     const double zr = zn - (double)pp.shift;   // rebase into the next window frame
-    e.x[p] = xn;
-    e.z[p] = zr;
-    e.ux[p] = ux;
-    e.uy[p] = uy;
-    e.uz[p] = uz;
+    st.x = xn;
+    st.z = zr;
+    st.ux = ux;
+    st.uy = uy;
+    st.uz = uz;
     if (!alive) {
-        e.w[p] = R(0);
+        st.w = R(0);
     } else {
         const int cx = (int)floor(xn), cz = (int)floor(zr);
         x0 = min(x0, cx); x1 = max(x1, cx);
@@ -251,6 +363,7 @@ __global__ void __launch_bounds__(NTHR, sizeof(R) == 4 ? 3 : 1) k_gpd(Geo g, Fie
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];   // 16-byte aligned: FP64 DS ops
     __shared__ int4 red[NTHR / 64];
+    __shared__ double redd[NTHR / 64];
     __shared__ int misfit[MISFIT_CAP];
     __shared__ int nmisfit;
     const int s = blockIdx.x;
@@ -265,15 +378,26 @@ __global__ void __launch_bounds__(NTHR, sizeof(R) == 4 ? 3 : 1) k_gpd(Geo g, Fie
     lds.zb = bb.z - 2;
     lds.lx = bb.y - bb.x + 6;
     lds.lz = bb.w - bb.z + 6;
-    lds.L = lds.lx * lds.lz;
     lds.f = reinterpret_cast<R*>(smem_raw);
-    lds.j = reinterpret_cast<double*>(lds.f + 6 * lds.L);   // 6L elements: 8-byte aligned
-    const bool use_lds = lds.L <= pp.lds_cells;
+    constexpr int TCELLS = tcells<R>();
+    using JT = typename LdsAcc<R>::JT;
+    lds.j = reinterpret_cast<JT*>(lds.f + 6 * TCELLS);   // 6 TCELLS elements: 8-byte aligned
+    const bool use_lds = lds.lx <= TPX && lds.lz <= trows<R>();
     int x0 = INT_MAX, x1 = INT_MIN, z0 = INT_MAX, z1 = INT_MIN;
     const int end = sg.start + sg.count;
+    const int L = lds.lx * lds.lz;
     if (use_lds) {
+        double js = 1.0, jq = 1.0;   // current into tile units and back
+        if constexpr (LdsAcc<R>::FIX) {
+            double sw = 0.0;
+            for (int p = sg.start + threadIdx.x; p < end; p += NTHR) sw += fabs((double)e.w[p]);
+            sw = block_sum(sw, redd);
+            const double fj = fmax(fabs((double)pp.fjx), fmax(fabs((double)pp.fjz), fabs((double)pp.fjy)));
+            const double bound = fj * sw;   // |v_y| < 1 and every weight factor is <= 1
+            if (bound > 0.0) { js = FIX_RANGE / bound; jq = bound / FIX_RANGE; }
+        }
         if (threadIdx.x == 0) nmisfit = 0;
-        for (int q = threadIdx.x; q < lds.L; q += NTHR) {
+        for (int q = threadIdx.x; q < L; q += NTHR) {
             const int a = q % lds.lx, b = q / lds.lx;
             const int i = swrap(lds.xb + a + g.Px, g.Sx, g.perx);
             const int k = swrap(lds.zb + b + g.Pz, g.Sz, g.perz);
@@ -286,34 +410,57 @@ __global__ void __launch_bounds__(NTHR, sizeof(R) == 4 ? 3 : 1) k_gpd(Geo g, Fie
                     v[3 + c] = R(0.5) * (f.B[c][o] + f.Bn[c][o]);
                 }
             }
+            const int t = b * TPX + a;
 #pragma unroll
-            for (int c = 0; c < 6; c++) lds.f[c * lds.L + q] = v[c];
+            for (int c = 0; c < 6; c++) lds.f[c * TCELLS + t] = v[c];
 #pragma unroll
-            for (int c = 0; c < 3; c++) lds.j[c * lds.L + q] = 0.0;
+            for (int c = 0; c < 3; c++) lds.j[c * TCELLS + t] = JT(0);
         }
         __syncthreads();
-        for (int p = sg.start + threadIdx.x; p < end; p += NTHR) {
-            const R w = e.w[p];
-            if (w == R(0)) continue;
-            const int ix = (int)floor(e.x[p]), iz = (int)floor(e.z[p]);
+        // the next particle's state is read while the current one is pushed (the loop is
+        // otherwise bound by the HBM latency of its loads); its result is written back at the
+        // top of the next iteration, ahead of the following prefetch, so that waiting for the
+        // prefetch never waits for fresh stores
+        int p = sg.start + threadIdx.x;
+        EState<R> nxt{}, done{};
+        int pdone = -1;
+        if (p < end) nxt = load_electron(e, p);
+        for (; p < end; p += NTHR) {
+            EState<R> cur = nxt;
+            // the prefetched registers are taken here, before this iteration's stores and
+            // loads are issued, so the wait for them covers only memory operations issued one
+            // iteration ago (an empty asm that reads them; it emits no instruction)
+            asm volatile("" ::"v"(cur.x), "v"(cur.z), "v"(cur.ux), "v"(cur.uy), "v"(cur.uz), "v"(cur.w)
+                         : "memory");
+            if (pdone >= 0) store_electron(e, pdone, done);
+            pdone = -1;
+            if (p + NTHR < end) nxt = load_electron(e, p + NTHR);
+            if (cur.w == R(0)) continue;
+            const int ix = (int)floor(cur.x), iz = (int)floor(cur.z);
             if (!lds.inside(ix - 2, ix + 3, iz - 2, iz + 3)) {
                 const int slot = atomicAdd(&nmisfit, 1);
                 if (slot < MISFIT_CAP) misfit[slot] = p;
                 else atomicOr(status, ST_SEGMENTS);
                 continue;
             }
-            advance_electron(lds, g, pp, e, p, w, status, x0, x1, z0, z1);
+            advance_electron(lds, g, pp, cur, js, status, x0, x1, z0, z1);
+            done = cur;
+            pdone = p;
         }
+        if (pdone >= 0) store_electron(e, pdone, done);
         __syncthreads();
-        for (int q = threadIdx.x; q < lds.L; q += NTHR) {
+        for (int q = threadIdx.x; q < L; q += NTHR) {
             const int a = q % lds.lx, b = q / lds.lx;
             const int i = swrap(lds.xb + a + g.Px, g.Sx, g.perx);
             const int k = swrap(lds.zb + b + g.Pz, g.Sz, g.perz);
             if (i < 0 || k < 0) continue;
             const long o = gofs(g, i, k);
+            const int t = b * TPX + a;
 #pragma unroll
             for (int c = 0; c < 3; c++) {
-                const R v = (R)lds.j[c * lds.L + q];
+                R v;
+                if constexpr (LdsAcc<R>::FIX) v = (R)(fix_value(lds.j[c * TCELLS + t]) * jq);
+                else v = (R)lds.j[c * TCELLS + t];
                 if (v != R(0)) atomicAdd(&f.J[c][o], v);
             }
         }
@@ -323,15 +470,18 @@ __global__ void __launch_bounds__(NTHR, sizeof(R) == 4 ? 3 : 1) k_gpd(Geo g, Fie
             const GlobAcc<R> glb = make_glob(g, f);
             for (int q = threadIdx.x; q < nm; q += NTHR) {
                 const int p = misfit[q];
-                advance_electron(glb, g, pp, e, p, e.w[p], status, x0, x1, z0, z1);
+                EState<R> st = load_electron(e, p);
+                advance_electron(glb, g, pp, st, 1.0, status, x0, x1, z0, z1);
+                store_electron(e, p, st);
             }
         }
     } else {
         const GlobAcc<R> glb = make_glob(g, f);
         for (int p = sg.start + threadIdx.x; p < end; p += NTHR) {
-            const R w = e.w[p];
-            if (w == R(0)) continue;
-            advance_electron(glb, g, pp, e, p, w, status, x0, x1, z0, z1);
+            EState<R> st = load_electron(e, p);
+            if (st.w == R(0)) continue;
+            advance_electron(glb, g, pp, st, 1.0, status, x0, x1, z0, z1);
+            store_electron(e, p, st);
         }
     }
     block_bbox(x0, x1, z0, z1, red);
@@ -339,23 +489,28 @@ __global__ void __launch_bounds__(NTHR, sizeof(R) == 4 ? 3 : 1) k_gpd(Geo g, Fie
 }
 
 // ---- rigid ions --------------------------------------------------------------------------
-template <typename R, typename A>
-__device__ __forceinline__ void ion_current(const A& acc, int ix, R fx, int iz, R fz, int iz1, R fz1,
-                                            R cz)
+// J_z of a particle at fixed x moving (iz+fz) -> (iz1+fz1): the Esirkepov form with DS_x = 0,
+// J_z(m,b) = cz S_x(m) sum_{k<=b} DS_z(k) on the 4 x 5 window with lower corner
+// (ix-1, min(iz,iz1)-1).
+template <typename A>
+__device__ __forceinline__ void ion_current(const A& acc, int ix, double fx, int iz, double fz, int iz1,
+                                            double fz1, double cz)
 {
-    const int bx = ix - 1, bz = min(iz, iz1) - 1;
-    R Sx[5], S0z[5], S1z[5];
-    window5(fx, 1, Sx);
-    window5(fz, iz - bz, S0z);
-    window5(fz1, iz1 - bz, S1z);
+    const int bz = min(iz, iz1) - 1;
+    double Sx[5], S0z[5], S1z[5];
+    window5(fx, false, Sx);
+    window5(fz, iz > bz + 1, S0z);
+    window5(fz1, iz1 > bz + 1, S1z);
+    double cxs[4];
 #pragma unroll
-    for (int m = 0; m < 4; m++) {
-        R acc_ = R(0);
+    for (int m = 0; m < 4; m++) cxs[m] = cz * Sx[m];
+    const auto h = acc.handle(ix - 1, bz);
+    double pd = 0.0;
 #pragma unroll
-        for (int b = 0; b < 4; b++) {
-            acc_ += (S1z[b] - S0z[b]) * Sx[m];
-            acc.dep(2, bx + m, bz + b, cz * acc_);
-        }
+    for (int b = 0; b < 4; b++) {
+        pd += S1z[b] - S0z[b];
+#pragma unroll
+        for (int m = 0; m < 4; m++) acc.dep(h, 2, m, b, acc.prod(pd, cxs[m]));
     }
 }
 
@@ -363,11 +518,11 @@ template <typename R>
 __global__ void __launch_bounds__(NTHR) k_ions(Geo g, FieldSet<R> f, IonArrays<R> ion,
                                                const Segment* __restrict__ seg,
                                                const int4* __restrict__ bbin, int4* __restrict__ bbout,
-                                               double zsh_a, double zsh_b, int shift, R fjz,
-                                               int lds_cells)
+                                               double zsh_a, double zsh_b, int shift, R fjz)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];   // 16-byte aligned: FP64 DS ops
     __shared__ int4 red[NTHR / 64];
+    __shared__ double redd[NTHR / 64];
     const int s = blockIdx.x;
     const Segment sg = seg[s];
     const int4 bb = bbin[s];
@@ -375,37 +530,53 @@ __global__ void __launch_bounds__(NTHR) k_ions(Geo g, FieldSet<R> f, IonArrays<R
         if (threadIdx.x == 0) bbout[s] = make_int4(INT_MAX, INT_MIN, INT_MAX, INT_MIN);
         return;
     }
+    using JT = typename LdsAcc<R>::JT;
     GlobAcc<R> glb = make_glob(g, f);
     LdsAcc<R> lds;
     lds.xb = bb.x - 2;
     lds.zb = bb.z - 2;
     lds.lx = bb.y - bb.x + 6;
     lds.lz = bb.w - bb.z + 6;
-    lds.L = lds.lx * lds.lz;
-    const bool use_lds = lds.L <= lds_cells;
+    constexpr int TCELLS = tcells<R>();
+    const bool use_lds = lds.lx <= TPX && lds.lz <= trows<R>();
     // only J_z (component 2) is staged: point j so that component 2 starts at smem
     lds.f = nullptr;
-    lds.j = reinterpret_cast<double*>(smem_raw) - 2 * lds.L;
+    lds.j = reinterpret_cast<JT*>(smem_raw) - 2 * TCELLS;
     if (!use_lds) { lds.lx = 0; lds.lz = 0; }
+    const int L = lds.lx * lds.lz;
+    JT* jz = reinterpret_cast<JT*>(smem_raw);
+    const int end = sg.start + sg.count;
+    double js = 1.0, jq = 1.0;   // current into tile units and back (fixed-point tile)
     if (use_lds) {
-        double* jz = reinterpret_cast<double*>(smem_raw);
-        for (int q = threadIdx.x; q < lds.L; q += NTHR) jz[q] = 0.0;
+        if constexpr (LdsAcc<R>::FIX) {
+            double sw = 0.0;
+            for (int p = sg.start + threadIdx.x; p < end; p += NTHR) sw += fabs((double)ion.w[p]);
+            sw = block_sum(sw, redd);
+            const double bound = fabs((double)fjz) * sw;
+            if (bound > 0.0) { js = FIX_RANGE / bound; jq = bound / FIX_RANGE; }
+        }
+        for (int q = threadIdx.x; q < L; q += NTHR) jz[(q / lds.lx) * TPX + q % lds.lx] = JT(0);
         __syncthreads();
     }
     int x0 = INT_MAX, x1 = INT_MIN, z0 = INT_MAX, z1 = INT_MIN;
-    const int end = sg.start + sg.count;
-    for (int p = sg.start + threadIdx.x; p < end; p += NTHR) {
-        const R w = ion.w[p];
+    // the next ion is read while the current one deposits
+    int p = sg.start + threadIdx.x;
+    double nx_ = 0.0, nz_ = 0.0;
+    R nw = R(0);
+    if (p < end) { nx_ = ion.x[p]; nz_ = ion.z0[p]; nw = ion.w[p]; }
+    for (; p < end; p += NTHR) {
+        const R w = nw;
+        const double x = nx_, zc0 = nz_;
+        if (p + NTHR < end) { nx_ = ion.x[p + NTHR]; nz_ = ion.z0[p + NTHR]; nw = ion.w[p + NTHR]; }
         if (w == R(0)) continue;
-        const double x = ion.x[p], zc0 = ion.z0[p];
         const double za = zc0 - zsh_a, zb = zc0 - zsh_b;
         const int ix = (int)floor(x), iz = (int)floor(za), iz1 = (int)floor(zb);
-        const R fx = (R)(x - ix), fz = (R)(za - iz), fz1 = (R)(zb - iz1);
+        const double fx = x - ix, fz = za - iz, fz1 = zb - iz1;
         const int bz = min(iz, iz1) - 1;
         if (lds.inside(ix - 1, ix + 2, bz, bz + 4) && abs(iz1 - iz) <= 1)
-            ion_current(lds, ix, fx, iz, fz, iz1, fz1, fjz * w);
+            ion_current(lds, ix, fx, iz, fz, iz1, fz1, js * (double)(fjz * w));
         else
-            ion_current(glb, ix, fx, iz, fz, iz1, fz1, fjz * w);
+            ion_current(glb, ix, fx, iz, fz, iz1, fz1, (double)(fjz * w));
         bool alive = !(!g.perz && (zb < 0.0 || zb >= (double)g.Nz));
         if (!alive) {
             ion.w[p] = R(0);
@@ -417,11 +588,12 @@ __global__ void __launch_bounds__(NTHR) k_ions(Geo g, FieldSet<R> f, IonArrays<R
     }
     if (use_lds) {
         __syncthreads();
-        const double* jz = reinterpret_cast<const double*>(smem_raw);
-        for (int q = threadIdx.x; q < lds.L; q += NTHR) {
-            const R v = (R)jz[q];
-            if (v == R(0)) continue;
+        for (int q = threadIdx.x; q < L; q += NTHR) {
             const int a = q % lds.lx, b = q / lds.lx;
+            R v;
+            if constexpr (LdsAcc<R>::FIX) v = (R)(fix_value(jz[b * TPX + a]) * jq);
+            else v = (R)jz[b * TPX + a];
+            if (v == R(0)) continue;
             const int i = swrap(lds.xb + a + g.Px, g.Sx, g.perx);
             const int k = swrap(lds.zb + b + g.Pz, g.Sz, g.perz);
             if (i < 0 || k < 0) continue;
@@ -824,7 +996,7 @@ void launch_gpd(const Geo& g, const FieldSet<R>& f, const ElectronArrays<R>& e, 
                 hipStream_t s)
 {
     if (nseg <= 0) return;
-    const size_t lds = (size_t)pp.lds_cells * (6 * sizeof(R) + 3 * sizeof(double));
+    const size_t lds = (size_t)tcells<R>() * (6 * sizeof(R) + 3 * sizeof(typename LdsAcc<R>::JT));
     hipLaunchKernelGGL((k_gpd<R>), dim3(nseg), dim3(NTHR), lds, s, g, f, e, seg, bbox_in, bbox_out,
                        pp, status);
 }
@@ -832,12 +1004,12 @@ void launch_gpd(const Geo& g, const FieldSet<R>& f, const ElectronArrays<R>& e, 
 template <typename R>
 void launch_ions(const Geo& g, const FieldSet<R>& f, const IonArrays<R>& ion, const Segment* seg,
                  const int4* bbox_in, int4* bbox_out, int nseg, double zsh_a, double zsh_b, int shift,
-                 R fjz, int lds_cells, hipStream_t s)
+                 R fjz, hipStream_t s)
 {
     if (nseg <= 0) return;
-    const size_t lds = (size_t)lds_cells * sizeof(double);
+    const size_t lds = (size_t)tcells<R>() * sizeof(typename LdsAcc<R>::JT);
     hipLaunchKernelGGL((k_ions<R>), dim3(nseg), dim3(NTHR), lds, s, g, f, ion, seg, bbox_in, bbox_out,
-                       zsh_a, zsh_b, shift, fjz, lds_cells);
+                       zsh_a, zsh_b, shift, fjz);
 }
 
 template <typename R>
@@ -901,7 +1073,7 @@ void launch_sort_ions(const Geo& g, int tile_x, int tile_z, int ntx, int ntiles,
                                 hipStream_t);                                                         \
     template void launch_ions<R>(const Geo&, const FieldSet<R>&, const IonArrays<R>&,                 \
                                  const Segment*, const int4*, int4*, int, double, double, int, R,     \
-                                 int, hipStream_t);                                                   \
+                                 hipStream_t);                                                        \
     template void launch_antenna<R>(const Geo&, const FieldSet<R>&, double*, const AntennaParams&,    \
                                     hipStream_t);                                                     \
     template void launch_inject<R>(const Geo&, const ElectronArrays<R>&, const IonArrays<R>&,         \

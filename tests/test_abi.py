@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "bfpic.h")
 
 def _declared():
     src = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:bf_status|const char\*|void)\s+(bf_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:bf_status|const char\*|void|int64_t)\s+(bf_\w+)\s*\(", src, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
