@@ -100,6 +100,59 @@ def learned_filter_leg(args, w, plain_filter_ms):
             "weights": "exact factorisation of the 4-pass + compensation filter"}
 
 
+def bench_scan(args):
+    """The batched scan: independent boosted runs of uneven grid, boost, density, time step
+    and ppc.  Tiles and sort cadence per run class come from the autotuner.  The same runs are
+    timed stepped one after another (one launch per phase and run) and as one batch (one
+    persistent launch per heavy phase for all runs)."""
+    import torch
+    import pic_inputs as pi
+    from paper_1009_2727_amd import Batch, Sim
+    from paper_1009_2727_amd.autotune import Autotuner
+    runs = pi.c4(nruns=args.c4_runs, scale=args.c4_scale)
+    t0 = time.perf_counter()
+    tuner = None if args.no_autotune else Autotuner()
+    picks = tuner.tune_all(runs) if tuner else [{"tile": (16, 16), "sort_every": 20}] * len(runs)
+    tune_s = time.perf_counter() - t0
+    sims = [Sim.from_workload(w, tile=tuple(c["tile"]), sort_every=c["sort_every"]) for w, c in zip(runs, picks)]
+    stream = torch.cuda.current_stream()
+    for s in sims:
+        s.step(args.warmup)
+    torch.cuda.synchronize()
+    ne = sum(s.counts()[0] for s in sims)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for s in sims:
+        s.step(args.steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    single_ms = a.elapsed_time(b)
+    batch = Batch(sims, stream=stream)
+    batch.step(args.warmup)
+    torch.cuda.synchronize()
+    a.record(stream)
+    batch.step(args.steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    batch_ms = a.elapsed_time(b)
+    status = [s.sync_status() for s in sims]
+    ne2 = sum(s.counts()[0] for s in sims)
+    ne_avg = 0.5 * (ne + ne2)
+    value = ne_avg * args.steps / (batch_ms / 1e3)
+    return {
+        "metric": "particle pushes/s", "value": value, "unit": "electron pushes/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": batch_ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched scan of {len(runs)} independent 2D boosted runs (grid scale "
+                               f"{args.c4_scale:g}), pre-loaded, CK2 + Friedman 0.1, 4+comp filter",
+                   "electrons": int(ne_avg), "runs": len(runs), "status_ok": all(x == 0 for x in status)},
+        "one_at_a_time": {"value": ne_avg * args.steps / (single_ms / 1e3), "ms_per_step": single_ms / args.steps},
+        "batched_over_one_at_a_time": single_ms / batch_ms,
+        "autotune": {"seconds": tune_s, "classes": {str(k): v for k, v in (tuner.cache.items() if tuner else [])}},
+    }
+
+
 def read_pmc():
     if not os.path.exists(PMC_FILE):
         return None
@@ -158,6 +211,12 @@ def main():
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_GIB"))
+    ap.add_argument("--workload", choices=["c2", "c4"], default="c2",
+                    help="c2: the 256x4096 boosted run (default); c4: the batched scan of "
+                         "independent boosted runs (persistent batched launch vs one run at a time)")
+    ap.add_argument("--c4-runs", type=int, default=64)
+    ap.add_argument("--c4-scale", type=float, default=1.0, help="grid scale of the scan's runs")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
 
     if args.summarize_pmc:
@@ -175,6 +234,10 @@ def main():
     import torch
     import pic_inputs as pi
     from paper_1009_2727_amd import Sim
+
+    if args.workload == "c4":
+        print(json.dumps(bench_scan(args)), flush=True)
+        return
 
     if args.calib_copy_gib > 0:
         n = int(args.calib_copy_gib * 2 ** 30)

@@ -230,6 +230,35 @@ const char* bf_last_error(const bf_sim* sim);
 /* Frees host metadata only; the caller frees its buffers afterwards. */
 void bf_destroy(bf_sim* sim);
 
+/* ---- batched independent runs -----------------------------------------------------------
+   Several handles stepped together, e.g. a scan over boost factor, density, grid and time step
+   (each run follows Sec. 2-4 on its own).  Each heavy phase of a step -- Faraday, particle
+   push, rigid ions, bilinear filter, Ampere -- is one persistent launch over a device queue of
+   (run, work item) pairs; the light phases (stations, antenna, learned filter, window shift,
+   injection, sort) are each run's own launches, in phase order.  Results equal each run's
+   bf_step up to the order of floating-point atomic additions.  Runs must be FP32 handles on
+   the current device without a sticky error; phase timers are not recorded in batched steps. */
+typedef struct bf_batch bf_batch;
+
+/* Bytes of the device work buffer (descriptor tables) for n runs; -1 for n < 1 or > 4096. */
+int64_t bf_batch_work_bytes(int nsims);
+
+/* Creates a batch over n distinct handles (not owned).  work: device buffer of at least
+   bf_batch_work_bytes(n) bytes, 256-byte aligned, owned by the caller.  hip_stream: the stream
+   of the batched launches (NULL: default).  BF_EINVAL: bad arguments or a repeated handle;
+   BF_EUNSUPPORTED: an FP64 handle; BF_ESTATE: a handle with a sticky error;
+   BF_EDEVICE: pinned staging memory could not be allocated. */
+bf_status bf_batch_create(bf_sim* const* sims, int n, void* work, int64_t work_bytes,
+                          void* hip_stream, bf_batch** out);
+
+/* nsteps steps of every run, asynchronous on the batch stream, ordered after the work queued
+   on each run's own stream and before later work there.  BF_ESTATE: a run has a sticky error
+   or lacks its learned-filter parameters. */
+bf_status bf_batch_step(bf_batch* batch, int nsteps);
+
+/* Frees the batch's host resources (not the runs, not the work buffer). */
+void bf_batch_destroy(bf_batch* batch);
+
 /* ---- learned current filter ---------------------------------------------------------------
    An addition that replaces the n-pass bilinear + compensation filter of Sec. 4.1 (Eq.
    3ptfilter) when filter_kind is BF_FILTER_LEARNED; the bilinear filter stays the default and

@@ -94,7 +94,8 @@ class bf_info(C.Structure):
 EXPORTS = ["bf_query_buffers", "bf_create", "bf_init_plasma", "bf_init_laser", "bf_add_station",
            "bf_load_electrons", "bf_step", "bf_diagnose", "bf_set_field", "bf_sync_status",
            "bf_get_state", "bf_set_state", "bf_status_string", "bf_last_error", "bf_destroy",
-           "bf_set_learned_filter", "bf_lf_work_bytes", "bf_lf_apply", "bf_lf_train_step"]
+           "bf_set_learned_filter", "bf_lf_work_bytes", "bf_lf_apply", "bf_lf_train_step",
+           "bf_batch_work_bytes", "bf_batch_create", "bf_batch_step", "bf_batch_destroy"]
 FILTER_BILINEAR, FILTER_LEARNED = 0, 1
 LF_PARAMS = 7200
 
@@ -139,8 +140,15 @@ def lib(path: str = LIB_PATH):
     L.bf_lf_train_step.argtypes = [P, C.c_int64, P, P, P, P, P, C.c_int, C.c_int, C.c_int, C.c_int,
                                    C.c_int, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float,
                                    C.c_int64, P, P, P]
+    L.bf_batch_work_bytes.argtypes = [C.c_int]
+    L.bf_batch_work_bytes.restype = C.c_int64
+    L.bf_batch_create.argtypes = [C.POINTER(P), C.c_int, P, C.c_int64, P, C.POINTER(P)]
+    L.bf_batch_step.argtypes = [P, C.c_int]
+    L.bf_batch_destroy.argtypes = [P]
+    L.bf_batch_destroy.restype = None
     for n in EXPORTS:
-        if n not in ("bf_status_string", "bf_last_error", "bf_destroy", "bf_lf_work_bytes"):
+        if n not in ("bf_status_string", "bf_last_error", "bf_destroy", "bf_lf_work_bytes",
+                     "bf_batch_work_bytes", "bf_batch_destroy"):
             getattr(L, n).restype = C.c_int
     _lib = L
     return L
@@ -390,6 +398,36 @@ def bilinear_factor_params(npass: int = 4, compensate: bool = True) -> np.ndarra
 def _ck(code):
     if code != 0:
         raise BfError(code, lib().bf_status_string(code).decode())
+
+
+class Batch:
+    """Several Sim handles (FP32, same device) stepped together: each heavy phase of a step is
+    one persistent launch over all runs.  The Sims stay usable for diagnostics."""
+
+    def __init__(self, sims, stream=None):
+        import torch
+        self.torch = torch
+        self.sims = list(sims)
+        dev = self.sims[0].device
+        n = lib().bf_batch_work_bytes(len(self.sims))
+        if n < 0:
+            raise BfError(-1, "bad batch size")
+        self.work = torch.empty(n, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        arr = (C.c_void_p * len(self.sims))(*[s.handle for s in self.sims])
+        h = C.c_void_p()
+        _ck(lib().bf_batch_create(arr, len(self.sims), C.c_void_p(self.work.data_ptr()), n,
+                                  C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.handle = h
+
+    def step(self, n: int = 1):
+        _ck(lib().bf_batch_step(self.handle, n))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib().bf_batch_destroy(h)
+            self.handle = None
 
 
 class LearnedFilter:

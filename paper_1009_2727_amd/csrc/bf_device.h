@@ -112,4 +112,29 @@ __device__ __forceinline__ void block_bbox(int& x0, int& x1, int& z0, int& z1, i
     x0 = r.x; x1 = r.y; z0 = r.z; z1 = r.w;
 }
 
+// A device work queue over the items of several runs: run r owns items [off[r], off[r+1]);
+// workgroups take items in increasing order from an atomic counter (zero before the launch).
+struct QueueRef {
+    const int* off;
+    int nrun, total;
+    int* counter;
+};
+
+// the workgroup's next item, or -1 once the queue is drained (every thread gets the same value)
+__device__ __forceinline__ int next_item(const QueueRef& q, int* slot)
+{
+    __syncthreads();   // the previous item is done with the LDS and with *slot
+    if (threadIdx.x == 0) *slot = atomicAdd(q.counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(*slot);
+    return it < q.total ? it : -1;
+}
+
+// run owning item `it`; items arrive in increasing order, so the search resumes from `r`
+__device__ __forceinline__ int run_of(const QueueRef& q, int it, int r)
+{
+    while (r + 1 < q.nrun && q.off[r + 1] <= it) r++;
+    return __builtin_amdgcn_readfirstlane(r);
+}
+
 }  // namespace bf

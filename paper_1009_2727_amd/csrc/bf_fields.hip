@@ -45,12 +45,13 @@ __device__ __forceinline__ R etilde(const Grid2<R>& G, const FieldSet<R>& f, int
     return (R(1) + R(0.25) * th) * e - R(0.5) * eo + (R(0.5) - R(0.25) * th) * ebn;
 }
 
+// one 64 x 4 block of stored cells (bx, by), one thread per cell
 template <typename R, bool FRIED>
-__global__ void __launch_bounds__(256) k_faraday(Geo g, FieldSet<R> f, PmlTab<R> pm, R dt, R a2,
-                                                 R b2, R th, R idx, R idz)
+__device__ __forceinline__ void faraday_block(const Geo& g, const FieldSet<R>& f, const PmlTab<R>& pm,
+                                              R dt, R a2, R b2, R th, R idx, R idz, int bx, int by)
 {
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int k = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int i = bx * 64 + (threadIdx.x & 63);
+    const int k = by * 4 + (threadIdx.x >> 6);
     if (i >= g.Sx || k >= g.Sz) return;
     Grid2<R> G{g};
     const long o = gofs(g, i, k);
@@ -132,12 +133,19 @@ __global__ void __launch_bounds__(256) k_faraday(Geo g, FieldSet<R> f, PmlTab<R>
     for (int c = 0; c < 3; c++) f.J[c][o] = R(0);
 }
 
-template <typename R>
-__global__ void __launch_bounds__(256) k_ampere(Geo g, FieldSet<R> f, PmlTab<R> pm, R dt, R idx,
-                                                R idz)
+template <typename R, bool FRIED>
+__global__ void __launch_bounds__(256) k_faraday(Geo g, FieldSet<R> f, PmlTab<R> pm, R dt, R a2,
+                                                 R b2, R th, R idx, R idz)
 {
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int k = blockIdx.y * 4 + (threadIdx.x >> 6);
+    faraday_block<R, FRIED>(g, f, pm, dt, a2, b2, th, idx, idz, blockIdx.x, blockIdx.y);
+}
+
+template <typename R>
+__device__ __forceinline__ void ampere_block(const Geo& g, const FieldSet<R>& f, const PmlTab<R>& pm,
+                                             R dt, R idx, R idz, int bx, int by)
+{
+    const int i = bx * 64 + (threadIdx.x & 63);
+    const int k = by * 4 + (threadIdx.x >> 6);
     if (i >= g.Sx || k >= g.Sz) return;
     Grid2<R> G{g};
     const long o = gofs(g, i, k);
@@ -183,6 +191,13 @@ __global__ void __launch_bounds__(256) k_ampere(Geo g, FieldSet<R> f, PmlTab<R> 
     }
 }
 
+template <typename R>
+__global__ void __launch_bounds__(256) k_ampere(Geo g, FieldSet<R> f, PmlTab<R> pm, R dt, R idx,
+                                                R idz)
+{
+    ampere_block<R>(g, f, pm, dt, idx, idz, blockIdx.x, blockIdx.y);
+}
+
 // ---- filter ------------------------------------------------------------------------------
 // Tile of FTX x FTZ output cells, halo H = number of passes per axis.  All x passes run over
 // the whole LDS tile (rows of the z halo included), then all z passes; a cell outside the
@@ -190,15 +205,15 @@ __global__ void __launch_bounds__(256) k_ampere(Geo g, FieldSet<R> f, PmlTab<R> 
 constexpr int FTX = 64, FTZ = 16, FMAXH = 12;
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_filter(Geo g, const R* __restrict__ in, R* __restrict__ out,
-                                                int hx, int hz, int npass, int comp)
+__device__ __forceinline__ void filter_tile(const Geo& g, const R* __restrict__ in, R* __restrict__ out,
+                                            int hx, int hz, int npass, int comp, int bx, int by)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];   // 16-byte aligned: FP64 DS ops
     R* buf0 = reinterpret_cast<R*>(smem_raw);
     const int H = npass + (comp ? 1 : 0);
     const int LX = FTX + 2 * H, LZ = FTZ + 2 * H, L = LX * LZ;
     R* buf1 = buf0 + L;
-    const int x0 = blockIdx.x * FTX - H, z0 = blockIdx.y * FTZ - H;
+    const int x0 = bx * FTX - H, z0 = by * FTZ - H;
     const int xmax = smax(g.Sx, g.perx, hx), zmax = smax(g.Sz, g.perz, hz);
     auto inx = [&](int gi) { return g.perx || (gi >= 0 && gi <= xmax); };
     auto inz = [&](int gk) { return g.perz || (gk >= 0 && gk <= zmax); };
@@ -247,6 +262,64 @@ __global__ void __launch_bounds__(256) k_filter(Geo g, const R* __restrict__ in,
         int gi = x0 + H + a, gk = z0 + H + b;
         if (gi >= g.Sx || gk >= g.Sz) continue;
         out[gofs(g, gi, gk)] = src[(b + H) * LX + a + H];
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_filter(Geo g, const R* __restrict__ in, R* __restrict__ out,
+                                                int hx, int hz, int npass, int comp)
+{
+    filter_tile<R>(g, in, out, hx, hz, npass, comp, blockIdx.x, blockIdx.y);
+}
+
+// ---- batched runs: one persistent launch per phase over a device work queue ----------------
+template <typename R>
+__global__ void __launch_bounds__(256) k_faraday_batch(const FaradayDesc<R>* __restrict__ d, QueueRef q)
+{
+    __shared__ int slot;
+    int r = 0;
+    for (;;) {
+        const int it = next_item(q, &slot);
+        if (it < 0) return;
+        r = run_of(q, it, r);
+        const FaradayDesc<R>& D = d[r];
+        const int local = it - q.off[r];
+        if (D.fried)
+            faraday_block<R, true>(D.g, D.f, D.pm, D.dt, D.a2, D.b2, D.th, D.idx, D.idz, local % D.gx,
+                                   local / D.gx);
+        else
+            faraday_block<R, false>(D.g, D.f, D.pm, D.dt, D.a2, D.b2, D.th, D.idx, D.idz, local % D.gx,
+                                    local / D.gx);
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_ampere_batch(const AmpereDesc<R>* __restrict__ d, QueueRef q)
+{
+    __shared__ int slot;
+    int r = 0;
+    for (;;) {
+        const int it = next_item(q, &slot);
+        if (it < 0) return;
+        r = run_of(q, it, r);
+        const AmpereDesc<R>& D = d[r];
+        const int local = it - q.off[r];
+        ampere_block<R>(D.g, D.f, D.pm, D.dt, D.idx, D.idz, local % D.gx, local / D.gx);
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_filter_batch(const FilterDesc<R>* __restrict__ d, QueueRef q)
+{
+    __shared__ int slot;
+    int r = 0;
+    for (;;) {
+        const int it = next_item(q, &slot);
+        if (it < 0) return;
+        r = run_of(q, it, r);
+        const FilterDesc<R>& D = d[r];
+        const int local = it - q.off[r];
+        filter_tile<R>(D.g, D.in, D.out, D.hx, D.hz, D.npass, D.comp, local % D.gx, local / D.gx);
     }
 }
 
@@ -374,6 +447,32 @@ __global__ void k_fill_int(int* p, int n, int v)
 
 // ---- launchers ------------------------------------------------------------------------------
 template <typename R>
+void launch_faraday_batch(const FaradayDesc<R>* d, const QueueRef& q, int nblocks, hipStream_t s)
+{
+    if (q.total > 0)
+        hipLaunchKernelGGL((k_faraday_batch<R>), dim3(nblocks), dim3(256), 0, s, d, q);
+}
+
+template <typename R>
+void launch_ampere_batch(const AmpereDesc<R>* d, const QueueRef& q, int nblocks, hipStream_t s)
+{
+    if (q.total > 0)
+        hipLaunchKernelGGL((k_ampere_batch<R>), dim3(nblocks), dim3(256), 0, s, d, q);
+}
+
+template <typename R>
+void launch_filter_batch(const FilterDesc<R>* d, const QueueRef& q, int max_halo, int nblocks,
+                         hipStream_t s)
+{
+    const size_t lds = 2 * (size_t)(FTX + 2 * max_halo) * (FTZ + 2 * max_halo) * sizeof(R);
+    if (q.total > 0)
+        hipLaunchKernelGGL((k_filter_batch<R>), dim3(nblocks), dim3(256), lds, s, d, q);
+}
+
+int filter_tiles(const Geo& g) { return ((g.Sx + FTX - 1) / FTX) * ((g.Sz + FTZ - 1) / FTZ); }
+int filter_tiles_x(const Geo& g) { return (g.Sx + FTX - 1) / FTX; }
+
+template <typename R>
 void launch_faraday(const Geo& g, const FieldSet<R>& f, const PmlTab<R>& pm, const SolverCoef& c,
                     hipStream_t s)
 {
@@ -444,6 +543,9 @@ void launch_fill_int(int* p, int n, int v, hipStream_t s)
                                     const SolverCoef&, hipStream_t);                               \
     template void launch_ampere<R>(const Geo&, const FieldSet<R>&, const PmlTab<R>&,               \
                                    const SolverCoef&, hipStream_t);                                \
+    template void launch_faraday_batch<R>(const FaradayDesc<R>*, const QueueRef&, int, hipStream_t); \
+    template void launch_ampere_batch<R>(const AmpereDesc<R>*, const QueueRef&, int, hipStream_t);   \
+    template void launch_filter_batch<R>(const FilterDesc<R>*, const QueueRef&, int, int, hipStream_t); \
     template void launch_filter<R>(const Geo&, R* const[3], R* const[3], const int[3],             \
                                    const int[3], int, int, int, hipStream_t);                      \
     template void launch_window_rows<R>(const Geo&, const PtrList<R>&, int, const EntryRows&,      \

@@ -18,6 +18,7 @@
 #include "../../include/bfpic.h"
 #include "bf_kernels.h"
 #include "bf_lfilter.h"
+#include "bf_batch.h"
 
 using namespace bf;
 
@@ -215,9 +216,19 @@ struct bf_sim {
         for (auto& m : marks) { ev_pool.push_back(m.a); ev_pool.push_back(m.b); }
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     }
+    // batched execution: while rec is set, launches are gathered into rec's phase slots
+    BatchRec* rec = nullptr;
+    int slot = 0;
+    template <class F>
+    void run(F&& f)
+    {
+        if (rec) rec->slots[slot].emplace_back(std::forward<F>(f));
+        else f(stream);
+    }
+
     hipEvent_t tick()
     {
-        if (!cfg.phase_timers) return nullptr;
+        if (!cfg.phase_timers || rec) return nullptr;
         hipEvent_t e = nullptr;
         if (!ev_pool.empty()) { e = ev_pool.back(); ev_pool.pop_back(); }
         else if (hipEventCreate(&e) != hipSuccess) return nullptr;
@@ -421,15 +432,26 @@ void sort_now(bf_sim* s)
     const Geo g = geo_of(s, s->g.zoff);
     const Layout& L = s->L;
     const int k = s->sg_cur;
-    launch_sort_electrons<R>(g, L.tile_x, L.tile_z, L.ntx, L.ntiles, electrons<R>(s, s->p_cur),
-                             electrons<R>(s, 1 - s->p_cur), seg_e(s, k), s->nseg_e, seg_e(s, 1 - k),
-                             bb_e(s, s->bb_cur), s->w<int>(L.w_counts), s->w<int>(L.w_cursor),
-                             nused_e(s), s->stream);
+    {
+        const ElectronArrays<R> src = electrons<R>(s, s->p_cur), dst = electrons<R>(s, 1 - s->p_cur);
+        Segment *so = seg_e(s, k), *sn = seg_e(s, 1 - k);
+        int4* bb = bb_e(s, s->bb_cur);
+        int *cnt = s->w<int>(L.w_counts), *cur = s->w<int>(L.w_cursor), *nu = nused_e(s);
+        const int tx = L.tile_x, tz = L.tile_z, ntx = L.ntx, nt = L.ntiles, ns = s->nseg_e;
+        s->run([=](hipStream_t st) {
+            launch_sort_electrons<R>(g, tx, tz, ntx, nt, src, dst, so, ns, sn, bb, cnt, cur, nu, st);
+        });
+    }
     if (s->plasma.ion_mode == 1 && s->have_plasma) {
-        launch_sort_ions<R>(g, L.tile_x, L.tile_z, L.ntx, L.ntiles, ions<R>(s, s->p_cur),
-                            ions<R>(s, 1 - s->p_cur), seg_i(s, k), s->nseg_i, seg_i(s, 1 - k),
-                            bb_i(s, s->bb_cur), ion_shift(s, s->t), s->w<int>(L.w_counts),
-                            s->w<int>(L.w_cursor), nused_i(s), s->stream);
+        const IonArrays<R> src = ions<R>(s, s->p_cur), dst = ions<R>(s, 1 - s->p_cur);
+        Segment *so = seg_i(s, k), *sn = seg_i(s, 1 - k);
+        int4* bb = bb_i(s, s->bb_cur);
+        int *cnt = s->w<int>(L.w_counts), *cur = s->w<int>(L.w_cursor), *nu = nused_i(s);
+        const int tx = L.tile_x, tz = L.tile_z, ntx = L.ntx, nt = L.ntiles, ns = s->nseg_i;
+        const double zsh = ion_shift(s, s->t);
+        s->run([=](hipStream_t st) {
+            launch_sort_ions<R>(g, tx, tz, ntx, nt, src, dst, so, ns, sn, bb, zsh, cnt, cur, nu, st);
+        });
         s->nseg_i = L.ntiles;
     }
     s->p_cur ^= 1;
@@ -490,9 +512,15 @@ void inject(bf_sim* s, int64_t nrows)
     ip.seg_base = s->nseg_e;
     ip.cap = L.cap;
     const int k = s->sg_cur;
-    launch_inject<R>(s->g, electrons<R>(s, s->p_cur), ions<R>(s, s->p_cur), seg_e(s, k),
-                     bb_e(s, s->bb_cur), seg_i(s, k), bb_i(s, s->bb_cur), nused_e(s), nused_i(s), ip,
-                     status_word(s), s->stream);
+    {
+        const Geo g = s->g;
+        const ElectronArrays<R> e = electrons<R>(s, s->p_cur);
+        const IonArrays<R> ion = ions<R>(s, s->p_cur);
+        Segment *se = seg_e(s, k), *si = seg_i(s, k);
+        int4 *be = bb_e(s, s->bb_cur), *bi = bb_i(s, s->bb_cur);
+        int *ne = nused_e(s), *ni = nused_i(s), *stw = status_word(s);
+        s->run([=](hipStream_t st) { launch_inject<R>(g, e, ion, se, be, si, bi, ne, ni, ip, stw, st); });
+    }
     s->nseg_e += (int)nrows * L.nchunks;
     if (s->plasma.ion_mode == 1) s->nseg_i = s->nseg_e;
     s->next_row += nrows;
@@ -518,7 +546,7 @@ lf::Packed lf_packed(bf_sim* s)
 // filter), reading and writing the ring-buffered rows in place
 void learned_filter(bf_sim* s, const FieldSet<float>& f)
 {
-    const Geo& g = s->g;
+    const Geo g = s->g;
     const int hx[3] = {1, 0, 0}, hz[3] = {0, 0, 1};
     const lf::Packed pk = lf_packed(s);
     for (int c = 0; c < 3; c++) {
@@ -532,8 +560,16 @@ void learned_filter(bf_sim* s, const FieldSet<float>& f)
         lf::View jout{f.Jf[c], 0, g.pitch, 1, g.zoff, g.Sz};
         lf::View h1{s->w<float>(s->L.w_lf_h1), 0, (long)d.nx * lf::C, lf::C, 0, d.ny};
         lf::View h2{s->w<float>(s->L.w_lf_h2), 0, (long)d.nx * lf::C, lf::C, 0, d.ny};
-        lf::forward(jin, h1, h2, jout, d, pk, s->stream);
+        s->run([=](hipStream_t st) { lf::forward(jin, h1, h2, jout, d, pk, st); });
     }
+}
+
+// batched recording is FP32 only (a batch is created from FP32 runs)
+template <typename R>
+BatchRec* batch_rec(bf_sim* s)
+{
+    if constexpr (sizeof(R) == 4) return s->rec;
+    else return nullptr;
 }
 
 template <typename R>
@@ -545,9 +581,21 @@ bf_status step_impl(bf_sim* s, int nsteps)
     const PmlTab<R> pm = pml_tab<R>(s);
     for (int n = 0; n < nsteps; n++) {
         const FieldSet<R> f = field_set<R>(s);
+        const Geo g = s->g;
+        BatchRec* rb = batch_rec<R>(s);
         // Faraday + Friedman + PML
+        s->slot = SLOT_FARADAY;
         hipEvent_t t_ph = s->tick();
-        launch_faraday<R>(s->g, f, pm, sc, s->stream);
+        if constexpr (sizeof(R) == 4) {
+            if (rb) {
+                const int gx = (g.Sx + 63) / 64, gz = (g.Sz + 3) / 4;
+                rb->faraday.push_back(FaradayDesc<float>{g, f, pm, (float)sc.dt, (float)sc.a2, (float)sc.b2,
+                                                         (float)sc.theta, (float)sc.idx, (float)sc.idz,
+                                                         sc.theta > 0.0 ? 1 : 0, gx});
+                rb->n_faraday.push_back(gx * gz);
+            }
+        }
+        if (!rb) launch_faraday<R>(g, f, pm, sc, s->stream);
         // stations (E^n, B^n)
         if (s->nst > 0) {
             StationParams sp;
@@ -555,7 +603,10 @@ bf_status step_impl(bf_sim* s, int nsteps)
             sp.zlab = s->w<double>(L.w_st_z);
             sp.gamma = s->gamma; sp.beta = s->beta; sp.t = s->t; sp.dz_um = c.dz_um;
             sp.shift = (double)s->shift; sp.xc = 0.5 * c.nx; sp.cap = L.stcap;
-            launch_stations<R>(s->g, f, sp, s->w<double>(L.w_st_rec), s->w<int>(L.w_st_cnt), s->stream);
+            double* rec = s->w<double>(L.w_st_rec);
+            int* cnt = s->w<int>(L.w_st_cnt);
+            s->slot = SLOT_STATIONS;
+            s->run([=](hipStream_t st) { launch_stations<R>(g, f, sp, rec, cnt, st); });
         }
         s->tock(t_ph, BF_PHASE_FARADAY);
         // window position after this step
@@ -572,18 +623,43 @@ bf_status step_impl(bf_sim* s, int nsteps)
         pp.fjz = (R)(1.0 / (c.dx_um * s->dt));
         pp.fjy = (R)(-1.0 / (c.dx_um * c.dz_um));
         pp.shift = d;
+        s->slot = SLOT_PUSH;
         t_ph = s->tick();
-        launch_gpd<R>(s->g, f, electrons<R>(s, s->p_cur), seg_e(s, s->sg_cur), bb_e(s, s->bb_cur),
-                      bb_e(s, 1 - s->bb_cur), s->nseg_e, pp, status_word(s), s->stream);
+        {
+            const ElectronArrays<R> e = electrons<R>(s, s->p_cur);
+            const Segment* sg = seg_e(s, s->sg_cur);
+            const int4* bi = bb_e(s, s->bb_cur);
+            int4* bo = bb_e(s, 1 - s->bb_cur);
+            if constexpr (sizeof(R) == 4) {
+                if (rb && s->nseg_e > 0) {
+                    rb->gpd.push_back(GpdDesc<float>{g, f, e, sg, bi, bo, pp, status_word(s)});
+                    rb->n_gpd.push_back(s->nseg_e);
+                }
+            }
+            if (!rb) launch_gpd<R>(g, f, e, sg, bi, bo, s->nseg_e, pp, status_word(s), s->stream);
+        }
         s->tock(t_ph, BF_PHASE_PUSH);
         // rigid ions: deposit-only J_z
+        s->slot = SLOT_IONS;
         t_ph = s->tick();
-        if (s->have_plasma && s->plasma.ion_mode == 1)
-            launch_ions<R>(s->g, f, ions<R>(s, s->p_cur), seg_i(s, s->sg_cur), bb_i(s, s->bb_cur),
-                           bb_i(s, 1 - s->bb_cur), s->nseg_i, ion_shift(s, s->t), ion_shift(s, t1), d,
-                           (R)(-1.0 / (c.dx_um * s->dt)), s->stream);
+        if (s->have_plasma && s->plasma.ion_mode == 1) {
+            const IonArrays<R> ion = ions<R>(s, s->p_cur);
+            const Segment* sg = seg_i(s, s->sg_cur);
+            const int4* bi = bb_i(s, s->bb_cur);
+            int4* bo = bb_i(s, 1 - s->bb_cur);
+            const double za = ion_shift(s, s->t), zb = ion_shift(s, t1);
+            const R fjz = (R)(-1.0 / (c.dx_um * s->dt));
+            if constexpr (sizeof(R) == 4) {
+                if (rb && s->nseg_i > 0) {
+                    rb->ion.push_back(IonDesc<float>{g, f, ion, sg, bi, bo, za, zb, d, fjz});
+                    rb->n_ion.push_back(s->nseg_i);
+                }
+            }
+            if (!rb) launch_ions<R>(g, f, ion, sg, bi, bo, s->nseg_i, za, zb, d, fjz, s->stream);
+        }
         s->tock(t_ph, BF_PHASE_IONS);
         // antenna
+        s->slot = SLOT_ANTENNA;
         t_ph = s->tick();
         if (s->have_laser) {
             AntennaParams ap;
@@ -595,10 +671,12 @@ bf_status step_impl(bf_sim* s, int nsteps)
             ap.sig_t = s->sig_t; ap.t0 = s->t0; ap.dx_um = c.dx_um; ap.xc_um = 0.5 * c.nx * c.dx_um;
             ap.weight = s->aw; ap.dt = s->dt; ap.dx = c.dx_um; ap.dz = c.dz_um;
             ap.active = (ap.za >= 0.0 && ap.za < (double)c.nz) ? 1 : 0;
-            launch_antenna<R>(s->g, f, s->w<double>(L.w_ant), ap, s->stream);
+            double* xm = s->w<double>(L.w_ant);
+            s->run([=](hipStream_t st) { launch_antenna<R>(g, f, xm, ap, st); });
         }
         s->tock(t_ph, BF_PHASE_ANTENNA);
         // filter
+        s->slot = SLOT_FILTER;
         t_ph = s->tick();
         if (c.filter_kind == BF_FILTER_LEARNED) {
             if constexpr (sizeof(R) == 4) learned_filter(s, f);
@@ -606,12 +684,30 @@ bf_status step_impl(bf_sim* s, int nsteps)
             R* in[3] = {f.J[0], f.J[1], f.J[2]};
             R* out[3] = {f.Jf[0], f.Jf[1], f.Jf[2]};
             const int hx[3] = {1, 0, 0}, hz[3] = {0, 0, 1};
-            launch_filter<R>(s->g, in, out, hx, hz, 3, c.filter_npass, c.filter_compensate, s->stream);
+            if constexpr (sizeof(R) == 4) {
+                if (rb) {
+                    for (int q = 0; q < 3; q++) {
+                        rb->filter.push_back(FilterDesc<float>{g, in[q], out[q], hx[q], hz[q], c.filter_npass,
+                                                               c.filter_compensate, filter_tiles_x(g)});
+                        rb->n_filter.push_back(filter_tiles(g));
+                    }
+                    rb->max_halo = std::max(rb->max_halo, c.filter_npass + (c.filter_compensate ? 1 : 0));
+                }
+            }
+            if (!rb) launch_filter<R>(g, in, out, hx, hz, 3, c.filter_npass, c.filter_compensate, s->stream);
         }
         s->tock(t_ph, BF_PHASE_FILTER);
         // Ampere + PML (E^{n+1} into the E^{n-1} set)
+        s->slot = SLOT_AMPERE;
         t_ph = s->tick();
-        launch_ampere<R>(s->g, f, pm, sc, s->stream);
+        if constexpr (sizeof(R) == 4) {
+            if (rb) {
+                const int gx = (g.Sx + 63) / 64, gz = (g.Sz + 3) / 4;
+                rb->ampere.push_back(AmpereDesc<float>{g, f, pm, (float)sc.dt, (float)sc.idx, (float)sc.idz, gx});
+                rb->n_ampere.push_back(gx * gz);
+            }
+        }
+        if (!rb) launch_ampere<R>(g, f, pm, sc, s->stream);
         s->tock(t_ph, BF_PHASE_AMPERE);
         s->e_cur ^= 1;
         s->b_cur ^= 1;
@@ -620,6 +716,7 @@ bf_status step_impl(bf_sim* s, int nsteps)
         s->step++;
         s->t = (double)s->step * s->dt;
         // moving window: advance the ring offset and clear the new rows
+        s->slot = SLOT_WINDOW;
         t_ph = s->tick();
         if (d != 0) {
             s->g.zoff = (int)(((int64_t)s->g.zoff + d) % L.Sz);
@@ -637,11 +734,14 @@ bf_status step_impl(bf_sim* s, int nsteps)
                 }
             }
             const FieldSet<R> f2 = field_set<R>(s);
-            launch_window_rows<R>(s->g, all_arrays<R>(s), d, er, f2, pm, s->stream);
+            const Geo g2 = s->g;
+            const PtrList<R> arrs = all_arrays<R>(s);
+            s->run([=](hipStream_t st) { launch_window_rows<R>(g2, arrs, d, er, f2, pm, st); });
         }
         // plasma injection at the front plane
         if (s->have_plasma) inject<R>(s, rows_entering(s));
         s->tock(t_ph, BF_PHASE_WINDOW);
+        s->slot = SLOT_SORT;
         t_ph = s->tick();
         if (++s->since_sort >= s->sort_every && s->have_plasma) sort_now<R>(s);
         s->tock(t_ph, BF_PHASE_SORT);
@@ -869,6 +969,186 @@ bf_status bf_step(bf_sim* s, int nsteps)
     if (e != hipSuccess) return hip_check(s, e, "step launch");
     return st;
 }
+
+// ---- batched runs ----------------------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+constexpr int BATCH_RING = 4;   // descriptor tables in flight
+
+size_t al256(size_t v) { return (v + 255) / 256 * 256; }
+
+// bytes of one descriptor table for n runs: counters, then per batched phase its
+// descriptors and its item offsets
+size_t batch_table_bytes(int n)
+{
+    const size_t m = (size_t)n;
+    return 256 + al256(m * sizeof(FaradayDesc<float>)) + al256((m + 1) * 4) +
+           al256(m * sizeof(AmpereDesc<float>)) + al256((m + 1) * 4) +
+           al256(3 * m * sizeof(FilterDesc<float>)) + al256((3 * m + 1) * 4) +
+           al256(m * sizeof(GpdDesc<float>)) + al256((m + 1) * 4) +
+           al256(m * sizeof(IonDesc<float>)) + al256((m + 1) * 4);
+}
+
+}  // namespace
+
+struct bf_batch {
+    std::vector<bf_sim*> sims;
+    hipStream_t stream = nullptr;
+    unsigned char* dev = nullptr;
+    size_t table = 0;
+    unsigned char* host[BATCH_RING] = {};
+    hipEvent_t ev[BATCH_RING] = {};
+    bool used[BATCH_RING] = {};
+    hipEvent_t join = nullptr;
+    int ring = 0, cus = 256;
+    BatchRec rec;
+    ~bf_batch()
+    {
+        for (int r = 0; r < BATCH_RING; r++) {
+            if (host[r]) (void)hipHostFree(host[r]);
+            if (ev[r]) (void)hipEventDestroy(ev[r]);
+        }
+        if (join) (void)hipEventDestroy(join);
+    }
+};
+
+namespace {
+
+// copies one phase's descriptors and item offsets into the staging table; returns the queue
+// as seen from the device
+template <typename D>
+QueueRef stage_phase(unsigned char* H, unsigned char* Dv, size_t& o, const std::vector<D>& descs,
+                     const std::vector<int>& items, int* counter_dev, const D** dev_descs)
+{
+    const size_t n = descs.size();
+    std::memcpy(H + o, descs.data(), n * sizeof(D));
+    *dev_descs = reinterpret_cast<const D*>(Dv + o);
+    o = al256(o + n * sizeof(D));
+    int* off = reinterpret_cast<int*>(H + o);
+    int total = 0;
+    for (size_t r = 0; r < n; r++) { off[r] = total; total += items[r]; }
+    off[n] = total;
+    QueueRef q{reinterpret_cast<const int*>(Dv + o), (int)n, total, counter_dev};
+    o = al256(o + (n + 1) * 4);
+    return q;
+}
+
+bf_status batch_one_step(bf_batch* b)
+{
+    BatchRec& rec = b->rec;
+    rec.clear();
+    for (bf_sim* s : b->sims) {
+        s->rec = &rec;
+        const bf_status st = step_impl<float>(s, 1);
+        s->rec = nullptr;
+        if (st != BF_OK) return st;
+    }
+    const int r = b->ring;
+    b->ring = (b->ring + 1) % BATCH_RING;
+    if (b->used[r] && hipEventSynchronize(b->ev[r]) != hipSuccess) return BF_EDEVICE;
+    unsigned char* H = b->host[r];
+    unsigned char* Dv = b->dev + (size_t)r * b->table;
+    std::memset(H, 0, 256);
+    int* cnt = reinterpret_cast<int*>(Dv);
+    size_t o = 256;
+    const FaradayDesc<float>* dfar;
+    const AmpereDesc<float>* damp;
+    const FilterDesc<float>* dfil;
+    const GpdDesc<float>* dgpd;
+    const IonDesc<float>* dion;
+    const QueueRef qf = stage_phase(H, Dv, o, rec.faraday, rec.n_faraday, cnt + 0, &dfar);
+    const QueueRef qa = stage_phase(H, Dv, o, rec.ampere, rec.n_ampere, cnt + 1, &damp);
+    const QueueRef ql = stage_phase(H, Dv, o, rec.filter, rec.n_filter, cnt + 2, &dfil);
+    const QueueRef qg = stage_phase(H, Dv, o, rec.gpd, rec.n_gpd, cnt + 3, &dgpd);
+    const QueueRef qi = stage_phase(H, Dv, o, rec.ion, rec.n_ion, cnt + 4, &dion);
+    hipStream_t st = b->stream;
+    if (hipMemcpyAsync(Dv, H, o, hipMemcpyHostToDevice, st) != hipSuccess) return BF_EDEVICE;
+    auto grid = [&](const QueueRef& q, int per_cu) { return std::max(1, std::min(q.total, per_cu * b->cus)); };
+    auto closures = [&](int slot) { for (auto& fn : rec.slots[slot]) fn(st); };
+    launch_faraday_batch<float>(dfar, qf, grid(qf, 8), st);
+    closures(SLOT_FARADAY);
+    closures(SLOT_STATIONS);
+    launch_gpd_batch<float>(dgpd, qg, grid(qg, 3), st);
+    closures(SLOT_PUSH);
+    launch_ions_batch<float>(dion, qi, grid(qi, 4), st);
+    closures(SLOT_IONS);
+    closures(SLOT_ANTENNA);
+    launch_filter_batch<float>(dfil, ql, rec.max_halo, grid(ql, 4), st);
+    closures(SLOT_FILTER);
+    launch_ampere_batch<float>(damp, qa, grid(qa, 8), st);
+    closures(SLOT_AMPERE);
+    closures(SLOT_WINDOW);
+    closures(SLOT_SORT);
+    if (hipEventRecord(b->ev[r], st) != hipSuccess) return BF_EDEVICE;
+    b->used[r] = true;
+    return hipGetLastError() == hipSuccess ? BF_OK : BF_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t bf_batch_work_bytes(int nsims)
+{
+    if (nsims < 1 || nsims > 4096) return -1;
+    return (int64_t)(BATCH_RING * batch_table_bytes(nsims));
+}
+
+bf_status bf_batch_create(bf_sim* const* sims, int n, void* work, int64_t work_bytes, void* hip_stream,
+                          bf_batch** out)
+{
+    if (!sims || !out || !work || n < 1 || n > 4096) return BF_EINVAL;
+    if (work_bytes < bf_batch_work_bytes(n)) return BF_EINVAL;
+    for (int q = 0; q < n; q++) {
+        if (!sims[q] || sims[q]->cfg.real_bytes != 4) return BF_EUNSUPPORTED;
+        if (sims[q]->err != BF_OK) return BF_ESTATE;
+        for (int p = 0; p < q; p++)
+            if (sims[p] == sims[q]) return BF_EINVAL;
+    }
+    bf_batch* b = new bf_batch();
+    b->sims.assign(sims, sims + n);
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    b->dev = static_cast<unsigned char*>(work);
+    b->table = batch_table_bytes(n);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        b->cus = cus;
+    bool ok = hipEventCreateWithFlags(&b->join, hipEventDisableTiming) == hipSuccess;
+    for (int r = 0; ok && r < BATCH_RING; r++) {
+        ok = hipHostMalloc(reinterpret_cast<void**>(&b->host[r]), b->table, hipHostMallocDefault) == hipSuccess &&
+             hipEventCreateWithFlags(&b->ev[r], hipEventDisableTiming) == hipSuccess;
+    }
+    if (!ok) { delete b; return BF_EDEVICE; }
+    *out = b;
+    return BF_OK;
+}
+
+bf_status bf_batch_step(bf_batch* b, int nsteps)
+{
+    if (!b || nsteps < 0) return BF_EINVAL;
+    for (bf_sim* s : b->sims) {
+        if (s->err != BF_OK) return BF_ESTATE;
+        if (s->cfg.filter_kind == BF_FILTER_LEARNED && !s->have_lf) return BF_ESTATE;
+        // work already queued on a run's own stream comes first
+        if (hipEventRecord(b->join, s->stream) != hipSuccess || hipStreamWaitEvent(b->stream, b->join, 0) != hipSuccess)
+            return BF_EDEVICE;
+    }
+    for (int q = 0; q < nsteps; q++) {
+        const bf_status st = batch_one_step(b);
+        if (st != BF_OK) return st;
+    }
+    // later calls on a run's own stream follow the batch
+    if (hipEventRecord(b->join, b->stream) != hipSuccess) return BF_EDEVICE;
+    for (bf_sim* s : b->sims)
+        if (hipStreamWaitEvent(s->stream, b->join, 0) != hipSuccess) return BF_EDEVICE;
+    return BF_OK;
+}
+
+void bf_batch_destroy(bf_batch* b) { delete b; }
 
 bf_status bf_set_learned_filter(bf_sim* s, const float* host_params, int64_t n)
 {

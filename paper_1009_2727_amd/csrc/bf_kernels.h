@@ -104,6 +104,68 @@ struct StationParams {
     int cap;
 };
 
+// ---- batched runs: per-run arguments of the persistent launch of each phase ------------
+template <typename R>
+struct FaradayDesc {
+    Geo g;
+    FieldSet<R> f;
+    PmlTab<R> pm;
+    R dt, a2, b2, th, idx, idz;
+    int fried, gx;     // Friedman on; blocks per row of the 64 x 4 block grid
+};
+template <typename R>
+struct AmpereDesc {
+    Geo g;
+    FieldSet<R> f;
+    PmlTab<R> pm;
+    R dt, idx, idz;
+    int gx;
+};
+template <typename R>
+struct FilterDesc {    // one per run and current component
+    Geo g;
+    const R* in;
+    R* out;
+    int hx, hz, npass, comp, gx;
+};
+template <typename R>
+struct GpdDesc {
+    Geo g;
+    FieldSet<R> f;
+    ElectronArrays<R> e;
+    const Segment* seg;
+    const int4* bbin;
+    int4* bbout;
+    PushParams<R> pp;
+    int* status;
+};
+template <typename R>
+struct IonDesc {
+    Geo g;
+    FieldSet<R> f;
+    IonArrays<R> ion;
+    const Segment* seg;
+    const int4* bbin;
+    int4* bbout;
+    double zsh_a, zsh_b;
+    int shift;
+    R fjz;
+};
+
+template <typename R>
+void launch_faraday_batch(const FaradayDesc<R>* d, const QueueRef& q, int nblocks, hipStream_t s);
+template <typename R>
+void launch_ampere_batch(const AmpereDesc<R>* d, const QueueRef& q, int nblocks, hipStream_t s);
+template <typename R>
+void launch_filter_batch(const FilterDesc<R>* d, const QueueRef& q, int max_halo, int nblocks,
+                         hipStream_t s);
+template <typename R>
+void launch_gpd_batch(const GpdDesc<R>* d, const QueueRef& q, int nblocks, hipStream_t s);
+template <typename R>
+void launch_ions_batch(const IonDesc<R>* d, const QueueRef& q, int nblocks, hipStream_t s);
+int filter_tiles(const Geo& g);
+int filter_tiles_x(const Geo& g);
+
 // ---- launchers (stream-ordered) -------------------------------------------------------
 template <typename R>
 void launch_faraday(const Geo& g, const FieldSet<R>& f, const PmlTab<R>& pm, const SolverCoef& c,

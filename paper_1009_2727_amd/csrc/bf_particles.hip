@@ -355,18 +355,18 @@ __device__ __forceinline__ void advance_electron(const A& acc, const Geo& g, con
 
 constexpr int MISFIT_CAP = 256;
 
+// gather, push and deposit of particle segment s by one workgroup
 template <typename R>
-__global__ void __launch_bounds__(NTHR, sizeof(R) == 4 ? 3 : 1) k_gpd(Geo g, FieldSet<R> f, ElectronArrays<R> e,
-                                              const Segment* __restrict__ seg,
-                                              const int4* __restrict__ bbin, int4* __restrict__ bbout,
-                                              PushParams<R> pp, int* status)
+__device__ __forceinline__ void gpd_segment(const Geo& g, const FieldSet<R>& f, const ElectronArrays<R>& e,
+                                            const Segment* __restrict__ seg, const int4* __restrict__ bbin,
+                                            int4* __restrict__ bbout, const PushParams<R>& pp, int* status,
+                                            int s)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];   // 16-byte aligned: FP64 DS ops
     __shared__ int4 red[NTHR / 64];
     __shared__ double redd[NTHR / 64];
     __shared__ int misfit[MISFIT_CAP];
     __shared__ int nmisfit;
-    const int s = blockIdx.x;
     const Segment sg = seg[s];
     const int4 bb = bbin[s];
     if (sg.count <= 0 || bb.x > bb.y || bb.z > bb.w) {
@@ -488,6 +488,30 @@ __global__ void __launch_bounds__(NTHR, sizeof(R) == 4 ? 3 : 1) k_gpd(Geo g, Fie
     if (threadIdx.x == 0) bbout[s] = make_int4(x0, x1, z0, z1);
 }
 
+template <typename R>
+__global__ void __launch_bounds__(NTHR, sizeof(R) == 4 ? 3 : 1) k_gpd(Geo g, FieldSet<R> f, ElectronArrays<R> e,
+                                              const Segment* __restrict__ seg,
+                                              const int4* __restrict__ bbin, int4* __restrict__ bbout,
+                                              PushParams<R> pp, int* status)
+{
+    gpd_segment<R>(g, f, e, seg, bbin, bbout, pp, status, blockIdx.x);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NTHR, sizeof(R) == 4 ? 3 : 1) k_gpd_batch(const GpdDesc<R>* __restrict__ d,
+                                                                            QueueRef q)
+{
+    __shared__ int slot;
+    int r = 0;
+    for (;;) {
+        const int it = next_item(q, &slot);
+        if (it < 0) return;
+        r = run_of(q, it, r);
+        const GpdDesc<R>& D = d[r];
+        gpd_segment<R>(D.g, D.f, D.e, D.seg, D.bbin, D.bbout, D.pp, D.status, it - q.off[r]);
+    }
+}
+
 // ---- rigid ions --------------------------------------------------------------------------
 // J_z of a particle at fixed x moving (iz+fz) -> (iz1+fz1): the Esirkepov form with DS_x = 0,
 // J_z(m,b) = cz S_x(m) sum_{k<=b} DS_z(k) on the 4 x 5 window with lower corner
@@ -515,15 +539,14 @@ __device__ __forceinline__ void ion_current(const A& acc, int ix, double fx, int
 }
 
 template <typename R>
-__global__ void __launch_bounds__(NTHR) k_ions(Geo g, FieldSet<R> f, IonArrays<R> ion,
-                                               const Segment* __restrict__ seg,
-                                               const int4* __restrict__ bbin, int4* __restrict__ bbout,
-                                               double zsh_a, double zsh_b, int shift, R fjz)
+__device__ __forceinline__ void ion_segment(const Geo& g, const FieldSet<R>& f, const IonArrays<R>& ion,
+                                            const Segment* __restrict__ seg, const int4* __restrict__ bbin,
+                                            int4* __restrict__ bbout, double zsh_a, double zsh_b, int shift,
+                                            R fjz, int s)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];   // 16-byte aligned: FP64 DS ops
     __shared__ int4 red[NTHR / 64];
     __shared__ double redd[NTHR / 64];
-    const int s = blockIdx.x;
     const Segment sg = seg[s];
     const int4 bb = bbin[s];
     if (sg.count <= 0 || bb.x > bb.y || bb.z > bb.w) {
@@ -602,6 +625,30 @@ __global__ void __launch_bounds__(NTHR) k_ions(Geo g, FieldSet<R> f, IonArrays<R
     }
     block_bbox(x0, x1, z0, z1, red);
     if (threadIdx.x == 0) bbout[s] = make_int4(x0, x1, z0, z1);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NTHR) k_ions(Geo g, FieldSet<R> f, IonArrays<R> ion,
+                                               const Segment* __restrict__ seg,
+                                               const int4* __restrict__ bbin, int4* __restrict__ bbout,
+                                               double zsh_a, double zsh_b, int shift, R fjz)
+{
+    ion_segment<R>(g, f, ion, seg, bbin, bbout, zsh_a, zsh_b, shift, fjz, blockIdx.x);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NTHR) k_ions_batch(const IonDesc<R>* __restrict__ d, QueueRef q)
+{
+    __shared__ int slot;
+    int r = 0;
+    for (;;) {
+        const int it = next_item(q, &slot);
+        if (it < 0) return;
+        r = run_of(q, it, r);
+        const IonDesc<R>& D = d[r];
+        ion_segment<R>(D.g, D.f, D.ion, D.seg, D.bbin, D.bbout, D.zsh_a, D.zsh_b, D.shift, D.fjz,
+                       it - q.off[r]);
+    }
 }
 
 // ---- antenna (FP64) ------------------------------------------------------------------------
@@ -1013,6 +1060,22 @@ void launch_ions(const Geo& g, const FieldSet<R>& f, const IonArrays<R>& ion, co
 }
 
 template <typename R>
+void launch_gpd_batch(const GpdDesc<R>* d, const QueueRef& q, int nblocks, hipStream_t s)
+{
+    const size_t lds = (size_t)tcells<R>() * (6 * sizeof(R) + 3 * sizeof(typename LdsAcc<R>::JT));
+    if (q.total > 0)
+        hipLaunchKernelGGL((k_gpd_batch<R>), dim3(nblocks), dim3(NTHR), lds, s, d, q);
+}
+
+template <typename R>
+void launch_ions_batch(const IonDesc<R>* d, const QueueRef& q, int nblocks, hipStream_t s)
+{
+    const size_t lds = (size_t)tcells<R>() * sizeof(typename LdsAcc<R>::JT);
+    if (q.total > 0)
+        hipLaunchKernelGGL((k_ions_batch<R>), dim3(nblocks), dim3(NTHR), lds, s, d, q);
+}
+
+template <typename R>
 void launch_antenna(const Geo& g, const FieldSet<R>& f, double* xminus, const AntennaParams& ap,
                     hipStream_t s)
 {
@@ -1074,6 +1137,8 @@ void launch_sort_ions(const Geo& g, int tile_x, int tile_z, int ntx, int ntiles,
     template void launch_ions<R>(const Geo&, const FieldSet<R>&, const IonArrays<R>&,                 \
                                  const Segment*, const int4*, int4*, int, double, double, int, R,     \
                                  hipStream_t);                                                        \
+    template void launch_gpd_batch<R>(const GpdDesc<R>*, const QueueRef&, int, hipStream_t);          \
+    template void launch_ions_batch<R>(const IonDesc<R>*, const QueueRef&, int, hipStream_t);         \
     template void launch_antenna<R>(const Geo&, const FieldSet<R>&, double*, const AntennaParams&,    \
                                     hipStream_t);                                                     \
     template void launch_inject<R>(const Geo&, const ElectronArrays<R>&, const IonArrays<R>&,         \

@@ -104,6 +104,38 @@ def c2(real="f32", nx=256, nz=4096, ppc=16, preload=False, gamma=13.0):
     )
 
 
+def c4(nruns=64, seed=10094, scale=1.0, real="f32"):
+    """The batched scan: independent 2D boosted runs with parameters drawn per run --
+    N_x ~ U{128..256}, N_z ~ U{1024..4096}, gamma = exp(U[ln 5, ln 100]),
+    n0 = exp(U[ln 1e17, ln 1e19]) cm^-3, ppc ~ U{4..16}, time step 0.95 (1 + u) of the
+    Friedman-corrected CFL limit with u ~ U[-0.1, 0.1] clamped at 0.999 -- and fixed square cells
+    of 1/32 of the boosted wavelength, CK2, theta = 0.1, 4 passes + compensation, 10-cell PML,
+    window at the wake velocity (backward when gamma exceeds gamma_w), laser a0 = 2, waist
+    20 um sqrt(1e18 / n0), 30 fs, pre-loaded plasma, 2000 steps each.  scale < 1 shrinks the
+    grids (parity-size batches)."""
+    rng = np.random.default_rng(seed)
+    runs = []
+    for q in range(nruns):
+        nx = int(rng.integers(128, 257) * scale)
+        nz = int(rng.integers(1024, 4097) * scale)
+        gamma = float(np.exp(rng.uniform(np.log(5.0), np.log(100.0))))
+        n0 = float(np.exp(rng.uniform(np.log(1e17), np.log(1e19))))
+        ppc = int(rng.integers(4, 17))
+        cfl = min(0.95 * (1.0 + rng.uniform(-0.1, 0.1)), 0.999)
+        d = boosted_cell(gamma)
+        z_ant = gamma * 0.6 * nz * d
+        runs.append(dict(
+            name=f"scan run {q}: gamma={gamma:.3g} n0={n0:.3g} {nx}x{nz} ppc={ppc} cfl={cfl:.3f}",
+            config=make_config(nx, nz, d, d, pml_cells=10, ck="ck2", theta=0.1, cfl_fraction=cfl,
+                               filter_npass=4, filter_compensate=1, gamma_boost=gamma,
+                               moving_window=1, seed=seed + q, real=real),
+            plasma=plasma(n0, ppc, start_um=-1e30, ion_mode=1),
+            laser=laser(2.0, 20.0 * np.sqrt(1e18 / n0), 30.0, z_ant),
+            steps=2000,
+        ))
+    return runs
+
+
 def small_lab(real="f64", nx=24, nz=96, ppc=4, seed=77, npass=1, comp=0, ck="yee", theta=0.0):
     """A C1-shaped lab-frame case the oracle finishes in seconds (several tiles + ragged tail)."""
     w = c1(real, nx=nx, nz=nz, ppc=ppc)

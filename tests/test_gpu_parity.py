@@ -157,6 +157,26 @@ def test_boosted_fp64_matches_oracle():
 
 
 @gpu
+def test_backward_window_matches_oracle():
+    # gamma above the wake's gamma_w (41.7 at 1e18 cm^-3): the window moves towards -z
+    # (Sec. 2), the ring offset steps backwards and new rows appear at the low-z end.
+    # Tolerance: the round-off of the cancelling electron and ion currents (order n0 gamma)
+    # is measured against the field scale E0/((1+beta) gamma), so its relative size grows as
+    # gamma^2: (60/13)^2 ~ 21 times the 1e-11 of the gamma = 13 runs.
+    w = pi.small_boosted(real="f64", nx=32, nz=120, ppc=2, gamma=60.0, preload=True)
+    sim, ref = _sim(w), Oracle.from_workload(w)
+    assert ref.info()["v_window"] < 0
+    tol = 1e-11 * (60.0 / 13.0) ** 2
+    for n in (7, 30):
+        sim.step(n)
+        ref.step(n)
+        compare_fields(sim, ref, tol, names=FIELDS + ["Exb", "Byx", "Eyx"], tag="backward64")
+        assert sim.info()["shift"] == ref.info()["shift"]
+    assert ref.info()["shift"] < -3
+    compare_particles(sim, ref, 1e-9, 1e-9)
+
+
+@gpu
 def test_boosted_fp32_matches_oracle():
     w = pi.small_boosted(real="f32", nx=40, nz=120, ppc=2)
     sim, ref = _sim(w), Oracle.from_workload(w)
