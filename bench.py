@@ -114,8 +114,10 @@ def bench_scan(args):
     tuner = None if args.no_autotune else Autotuner()
     picks = tuner.tune_all(runs) if tuner else [{"tile": (16, 16), "sort_every": 20}] * len(runs)
     tune_s = time.perf_counter() - t0
+    print(f"[scan] autotuned {len(runs)} runs in {tune_s:.1f} s", file=sys.stderr, flush=True)
     sims = [Sim.from_workload(w, tile=tuple(c["tile"]), sort_every=c["sort_every"]) for w, c in zip(runs, picks)]
     stream = torch.cuda.current_stream()
+    print(f"[scan] created {len(sims)} runs", file=sys.stderr, flush=True)
     for s in sims:
         s.step(args.warmup)
     torch.cuda.synchronize()
@@ -130,6 +132,7 @@ def bench_scan(args):
     batch = Batch(sims, stream=stream)
     batch.step(args.warmup)
     torch.cuda.synchronize()
+    print("[scan] one-at-a-time and batched warm-up done", file=sys.stderr, flush=True)
     a.record(stream)
     batch.step(args.steps)
     b.record(stream)
