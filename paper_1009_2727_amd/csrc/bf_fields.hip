@@ -199,9 +199,11 @@ __global__ void __launch_bounds__(256) k_ampere(Geo g, FieldSet<R> f, PmlTab<R> 
 }
 
 // ---- filter ------------------------------------------------------------------------------
-// Tile of FTX x FTZ output cells, halo H = number of passes per axis.  All x passes run over
-// the whole LDS tile (rows of the z halo included), then all z passes; a cell outside the
-// component's domain on a non-periodic axis is held at zero (zero padding).
+// Tile of FTX x FTZ output cells, halo H = number of passes per axis.  The n passes +
+// compensation along one axis are one (2H+1)-tap stencil (the passes' kernels convolved), so a
+// tile whose stencil support lies inside the component's domain is filtered with one x and one
+// z convolution.  A tile that reaches a non-periodic edge runs the passes one by one with the
+// cells outside the domain held at zero after every pass (zero padding per pass).
 constexpr int FTX = 64, FTZ = 16, FMAXH = 12;
 
 template <typename R>
@@ -217,6 +219,25 @@ __device__ __forceinline__ void filter_tile(const Geo& g, const R* __restrict__ 
     const int xmax = smax(g.Sx, g.perx, hx), zmax = smax(g.Sz, g.perz, hz);
     auto inx = [&](int gi) { return g.perx || (gi >= 0 && gi <= xmax); };
     auto inz = [&](int gk) { return g.perz || (gk >= 0 && gk <= zmax); };
+    __shared__ R taps[2 * FMAXH + 1];
+    const R ac = R(0.5) * R(npass) + R(1);
+    if (threadIdx.x == 0) {
+        // the passes' 3-point kernels convolved: binomial / 4^n times the compensation stencil
+        R t[2 * FMAXH + 3];
+        for (int k = 0; k < 2 * H + 3; k++) t[k] = R(0);
+        t[H + 1] = R(1);
+        for (int p = 0; p < H; p++) {
+            const R al = (p < npass) ? R(0.5) : ac;
+            const R be = (R(1) - al) * R(0.5);
+            R prev = R(0);
+            for (int k = 1; k <= 2 * H + 1; k++) {
+                const R cur = t[k];
+                t[k] = al * cur + be * (prev + t[k + 1]);
+                prev = cur;
+            }
+        }
+        for (int k = 0; k <= 2 * H; k++) taps[k] = t[k + 1];
+    }
     for (int q = threadIdx.x; q < L; q += blockDim.x) {
         int a = q % LX, b = q / LX;
         int gi = x0 + a, gk = z0 + b;
@@ -228,7 +249,26 @@ __device__ __forceinline__ void filter_tile(const Geo& g, const R* __restrict__ 
         buf0[q] = v;
     }
     __syncthreads();
-    const R ac = R(0.5) * R(npass) + R(1);
+    const bool inner = (g.perx || (x0 >= 0 && x0 + LX - 1 <= xmax)) && (g.perz || (z0 >= 0 && z0 + LZ - 1 <= zmax));
+    if (inner) {
+        for (int q = threadIdx.x; q < LZ * FTX; q += blockDim.x) {
+            const int a = q % FTX, b = q / FTX;
+            const R* row = buf0 + b * LX + a;
+            R s = R(0);
+            for (int k = 0; k <= 2 * H; k++) s += taps[k] * row[k];
+            buf1[b * FTX + a] = s;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < FTX * FTZ; q += blockDim.x) {
+            const int a = q % FTX, b = q / FTX;
+            const int gi = x0 + H + a, gk = z0 + H + b;
+            const R* col = buf1 + b * FTX + a;
+            R s = R(0);
+            for (int k = 0; k <= 2 * H; k++) s += taps[k] * col[k * FTX];
+            if (gi < g.Sx && gk < g.Sz) out[gofs(g, gi, gk)] = s;
+        }
+        return;
+    }
     R* src = buf0;
     R* dst = buf1;
     for (int p = 0; p < H; p++) {
@@ -265,11 +305,19 @@ __device__ __forceinline__ void filter_tile(const Geo& g, const R* __restrict__ 
     }
 }
 
+// the current components of one filter launch (blockIdx.z picks the component)
 template <typename R>
-__global__ void __launch_bounds__(256) k_filter(Geo g, const R* __restrict__ in, R* __restrict__ out,
-                                                int hx, int hz, int npass, int comp)
+struct FilterSet {
+    const R* in[3];
+    R* out[3];
+    int hx[3], hz[3];
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_filter(Geo g, FilterSet<R> fs, int npass, int comp)
 {
-    filter_tile<R>(g, in, out, hx, hz, npass, comp, blockIdx.x, blockIdx.y);
+    const int c = blockIdx.z;
+    filter_tile<R>(g, fs.in[c], fs.out[c], fs.hx[c], fs.hz[c], npass, comp, blockIdx.x, blockIdx.y);
 }
 
 // ---- batched runs: one persistent launch per phase over a device work queue ----------------
@@ -499,10 +547,16 @@ void launch_filter(const Geo& g, R* const in[3], R* const out[3], const int hx[3
 {
     const int H = npass + (compensate ? 1 : 0);
     const size_t lds = 2 * (size_t)(FTX + 2 * H) * (FTZ + 2 * H) * sizeof(R);
-    dim3 grid((g.Sx + FTX - 1) / FTX, (g.Sz + FTZ - 1) / FTZ);
-    for (int c = 0; c < ncomp; c++)
-        hipLaunchKernelGGL((k_filter<R>), grid, dim3(256), lds, s, g, (const R*)in[c], out[c], hx[c],
-                           hz[c], npass, compensate);
+    if (ncomp <= 0 || ncomp > 3) return;
+    FilterSet<R> fs{};
+    for (int c = 0; c < ncomp; c++) {
+        fs.in[c] = in[c];
+        fs.out[c] = out[c];
+        fs.hx[c] = hx[c];
+        fs.hz[c] = hz[c];
+    }
+    dim3 grid((g.Sx + FTX - 1) / FTX, (g.Sz + FTZ - 1) / FTZ, ncomp);
+    hipLaunchKernelGGL((k_filter<R>), grid, dim3(256), lds, s, g, fs, npass, compensate);
 }
 
 template <typename R>

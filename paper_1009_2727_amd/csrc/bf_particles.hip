@@ -652,65 +652,44 @@ __global__ void __launch_bounds__(NTHR) k_ions_batch(const IonDesc<R>* __restric
 }
 
 // ---- antenna (FP64) ------------------------------------------------------------------------
-__device__ __forceinline__ void bspline3d(double f, double w[4])
-{
-    double g = 1.0 - f, f2 = f * f, f3 = f2 * f;
-    w[0] = g * g * g / 6.0;
-    w[1] = (3.0 * f3 - 6.0 * f2 + 4.0) / 6.0;
-    w[2] = (-3.0 * f3 + 3.0 * f2 + 3.0 * f + 1.0) / 6.0;
-    w[3] = f3 / 6.0;
-}
 
-// add the Esirkepov current of one particle (charge factor q w) into a 6x6 FP64 patch whose
-// lower corner is (px, pz)
-__device__ void esirkepov_patch(double x0, double z0, double x1, double z1, double qw, double vy,
-                                double dx, double dz, double dt, int px, int pz, double jx[6][6],
-                                double jy[6][6], double jz[6][6])
+// Esirkepov current of one particle moving (x0, z0) -> (x1, z1) (cells, |move| < 1 cell),
+// charge factor qw, at cell (cx, cz) of the grid: J_x on (cx + 1/2, cz), J_z on (cx, cz + 1/2)
+// (2-1/2D weights as in esirkepov(); v_y = 0).  FP64 throughout.
+__device__ __forceinline__ void esirkepov_cell(double x0, double z0, double x1, double z1, double qw,
+                                               double dx, double dz, double dt, int cx, int cz,
+                                               double& jx, double& jz)
 {
     const int ix = (int)floor(x0), iz = (int)floor(z0), ix1 = (int)floor(x1), iz1 = (int)floor(z1);
     if (abs(ix1 - ix) > 1 || abs(iz1 - iz) > 1) return;   // one step moves less than a cell
     const int bx = min(ix, ix1) - 1, bz = min(iz, iz1) - 1;
-    double S0x[5] = {0, 0, 0, 0, 0}, S1x[5] = {0, 0, 0, 0, 0}, S0z[5] = {0, 0, 0, 0, 0},
-           S1z[5] = {0, 0, 0, 0, 0}, w[4];
-    bspline3d(x0 - ix, w);
-    for (int m = 0; m < 4; m++) S0x[ix - bx - 1 + m] = w[m];
-    bspline3d(x1 - ix1, w);
-    for (int m = 0; m < 4; m++) S1x[ix1 - bx - 1 + m] = w[m];
-    bspline3d(z0 - iz, w);
-    for (int m = 0; m < 4; m++) S0z[iz - bz - 1 + m] = w[m];
-    bspline3d(z1 - iz1, w);
-    for (int m = 0; m < 4; m++) S1z[iz1 - bz - 1 + m] = w[m];
-    const int ox = bx - px, oz = bz - pz;
-    // the 5-node window must sit inside the 6-node patch (caller keeps |drift| < 1/2 cell)
-    if (ox < 0 || ox > 1 || oz < 0 || oz > 1) return;
-    for (int b = 0; b < 5; b++) {
-        double acc = 0.0;
-        for (int m = 0; m < 4; m++) {
-            acc += (S1x[m] - S0x[m]) * (S0z[b] + 0.5 * (S1z[b] - S0z[b]));
-            jx[oz + b][ox + m] -= qw * acc / (dz * dt);
-        }
+    const int m = cx - bx, b = cz - bz;                    // node of the 5 x 5 window
+    if (m < 0 || m > 4 || b < 0 || b > 4) return;
+    double S0x[5], S1x[5], S0z[5], S1z[5];
+    window5(x0 - ix, ix > bx + 1, S0x);
+    window5(x1 - ix1, ix1 > bx + 1, S1x);
+    window5(z0 - iz, iz > bz + 1, S0z);
+    window5(z1 - iz1, iz1 > bz + 1, S1z);
+    if (m < 4) {
+        double pd = 0.0;
+        for (int k = 0; k <= m; k++) pd += S1x[k] - S0x[k];
+        jx += -qw / (dz * dt) * pd * 0.5 * (S0z[b] + S1z[b]);
     }
-    for (int m = 0; m < 5; m++) {
-        double acc = 0.0;
-        for (int b = 0; b < 4; b++) {
-            acc += (S1z[b] - S0z[b]) * (S0x[m] + 0.5 * (S1x[m] - S0x[m]));
-            jz[oz + b][ox + m] -= qw * acc / (dx * dt);
-        }
+    if (b < 4) {
+        double pd = 0.0;
+        for (int k = 0; k <= b; k++) pd += S1z[k] - S0z[k];
+        jz += -qw / (dx * dt) * pd * 0.5 * (S0x[m] + S1x[m]);
     }
-    if (vy != 0.0)
-        for (int m = 0; m < 5; m++)
-            for (int b = 0; b < 5; b++) {
-                double dsx = S1x[m] - S0x[m], dsz = S1z[b] - S0z[b];
-                jy[oz + b][ox + m] += qw * vy *
-                    (S0x[m] * S0z[b] + 0.5 * dsx * S0z[b] + 0.5 * S0x[m] * dsz + dsx * dsz / 3.0) /
-                    (dx * dz);
-            }
 }
 
+// One wave per sheet pair, one lane per cell of the pair's 6 x 6 patch: the + particle stays at
+// its home x and moves with the plane, the - particle also moves transversely so that the pair
+// carries the sheet current K = -2 E_perp (Sec. 3.1.2); both deposit by Esirkepov in FP64.
 template <typename R>
-__global__ void k_antenna(Geo g, FieldSet<R> f, double* xm, AntennaParams ap)
+__global__ void __launch_bounds__(64) k_antenna(Geo g, FieldSet<R> f, double* xm, AntennaParams ap)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x;
+    const int lane = threadIdx.x;
     if (i >= ap.n) return;
     const double xh = i + 0.5;                   // home position (cells)
     const double xum = xh * ap.dx_um;
@@ -723,22 +702,21 @@ __global__ void k_antenna(Geo g, FieldSet<R> f, double* xm, AntennaParams ap)
     const double K = -2.0 * Ep;
     const double vx = K * ap.dx / (-ap.weight);   // moving sheet has charge -w
     const double xa = xm[i], xb = xa + vx * ap.dt / ap.dx;
-    double jx[6][6], jy[6][6], jz[6][6];
-    for (int a = 0; a < 6; a++)
-        for (int b = 0; b < 6; b++) { jx[a][b] = 0.0; jy[a][b] = 0.0; jz[a][b] = 0.0; }
     const int px = (int)floor(xh) - 2;
     const int pz = (int)floor(fmin(ap.za, ap.zb)) - 1;
-    esirkepov_patch(xa, ap.za, xb, ap.zb, -ap.weight, 0.0, ap.dx, ap.dz, ap.dt, px, pz, jx, jy, jz);
-    esirkepov_patch(xh, ap.za, xh, ap.zb, ap.weight, 0.0, ap.dx, ap.dz, ap.dt, px, pz, jx, jy, jz);
-    xm[i] = xb;
-    for (int b = 0; b < 6; b++)
-        for (int a = 0; a < 6; a++) {
-            const int si = swrap(px + a + g.Px, g.Sx, g.perx), sk = swrap(pz + b + g.Pz, g.Sz, g.perz);
-            if (si < 0 || sk < 0) continue;
+    if (lane < 36) {
+        const int cx = px + lane % 6, cz = pz + lane / 6;
+        double jx = 0.0, jz = 0.0;
+        esirkepov_cell(xa, ap.za, xb, ap.zb, -ap.weight, ap.dx, ap.dz, ap.dt, cx, cz, jx, jz);
+        esirkepov_cell(xh, ap.za, xh, ap.zb, ap.weight, ap.dx, ap.dz, ap.dt, cx, cz, jx, jz);
+        const int si = swrap(cx + g.Px, g.Sx, g.perx), sk = swrap(cz + g.Pz, g.Sz, g.perz);
+        if (si >= 0 && sk >= 0) {
             const long o = gofs(g, si, sk);
-            if (jx[b][a] != 0.0) atomicAdd(&f.J[0][o], (R)jx[b][a]);
-            if (jz[b][a] != 0.0) atomicAdd(&f.J[2][o], (R)jz[b][a]);
+            if (jx != 0.0) atomicAdd(&f.J[0][o], (R)jx);
+            if (jz != 0.0) atomicAdd(&f.J[2][o], (R)jz);
         }
+    }
+    if (lane == 0) xm[i] = xb;
 }
 
 // ---- plasma injection --------------------------------------------------------------------------
@@ -1080,7 +1058,7 @@ void launch_antenna(const Geo& g, const FieldSet<R>& f, double* xminus, const An
                     hipStream_t s)
 {
     if (!ap.active || ap.n <= 0) return;
-    hipLaunchKernelGGL((k_antenna<R>), dim3((ap.n + 63) / 64), dim3(64), 0, s, g, f, xminus, ap);
+    hipLaunchKernelGGL((k_antenna<R>), dim3(ap.n), dim3(64), 0, s, g, f, xminus, ap);
 }
 
 template <typename R>
