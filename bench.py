@@ -15,12 +15,15 @@ the FP64 CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import math
 import glob
 import hashlib
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -156,6 +159,88 @@ def bench_scan(args):
     }
 
 
+def _axis_ez(sim, nx):
+    return sim.field("Ez")[:, nx // 2 + sim.info()["pml_x"]]
+
+
+def bench_learned_filter_study(args):
+    """The learned filter against the plain 4-pass + compensation filter.
+    - Training: Adam from a random start on (raw J, filtered J) patch pairs cut from three seeded
+      runs of the wake family, plus band-limited probes at |k| > pi/2 whose targets are the plain
+      filter's output (the spectral term).
+    - Gain: max |G_learned - G_plain| for |k| < 4 k_p and over the whole band.
+    - Growth: slope per step of ln(high-k E_z energy) in the boosted instability family with no
+      filter, the plain filter and the learned one.
+    - Wake error: on-axis E_z after 700 steps of the wake family (plain / learned) against an
+      unfiltered FP64 run at twice the resolution, max |dE_z| / max |E_z,ref|."""
+    import torch
+    import pic_inputs as pi
+    from paper_1009_2727_amd import Sim, bilinear_factor_params, filter_training as ft
+
+    t0 = time.perf_counter()
+    X, Y = [], []
+    for s in (1, 2, 3):
+        x, y = ft.current_pairs(pi.c5_wake(seed=1015 + s), steps=420, every=30, per_component=32, seed=s)
+        X.append(x)
+        Y.append(y)
+    X, Y = np.concatenate(X), np.concatenate(Y)
+    print(f"[c5] {len(X)} training pairs", file=sys.stderr, flush=True)
+    probes = ft.band_probes(1024)
+    lf, hist = ft.train(X, Y, probes, probe_weight=1.0, steps=args.c5_train_steps, lr=2e-3, batch=64,
+                        log_every=max(args.c5_train_steps // 10, 1))
+    params = lf.params.cpu().numpy()
+    print(f"[c5] trained, loss {hist[-1][1]:.3g}", file=sys.stderr, flush=True)
+    plain = bilinear_factor_params(4, True)
+
+    w = pi.c5_wake()
+    info = Sim.from_workload(w, laser=False).info()
+    kp = math.sqrt(info["n0_norm"]) * w["config"]["dz_um"]    # plasma wavenumber in grid units
+    gain = {"k_below_4kp": ft.gain_error(params, 4 * kp), "whole_band": ft.gain_error(params, math.pi),
+            "plain_vs_exact_factorisation": ft.gain_error(plain, math.pi)}
+
+    growth = {}
+    for name, npass, p in (("none", 0, None), ("plain", 4, None), ("learned", 4, params)):
+        g = pi.c5_growth(npass=npass, comp=1 if npass else 0)
+        growth[name] = ft.growth_rate(g, p, steps=g["steps"], every=20)[0]
+    print(f"[c5] growth {growth}", file=sys.stderr, flush=True)
+
+    def wake(params_or_none):
+        w2 = pi.c5_wake()
+        if params_or_none is not None:
+            w2["config"]["filter_kind"] = 1
+        sim = Sim.from_workload(w2)
+        if params_or_none is not None:
+            sim.set_learned_filter(params_or_none)
+        sim.step(w2["steps"])
+        return _axis_ez(sim, w2["config"]["nx"])
+
+    ez_plain, ez_learned = wake(None), wake(params)
+    ref = pi.c5_wake(real="f64", refine=2)
+    rsim = Sim.from_workload(ref)
+    rsim.step(ref["steps"])
+    ez_ref_f = _axis_ez(rsim, ref["config"]["nx"])
+    # E_z sits at half rows: coarse (k + 1/2) d = mean of fine rows 2k + 1/2 and 2k + 3/2
+    pz_c, pz_f = info["pml_z"], rsim.info()["pml_z"]
+    nz = w["config"]["nz"]
+    fine = ez_ref_f[pz_f:pz_f + 2 * nz]
+    ez_ref = 0.5 * (fine[0::2] + fine[1::2])
+    sl = slice(pz_c, pz_c + nz)
+    scale = np.abs(ez_ref).max()
+    err = {"plain": float(np.abs(ez_plain[sl] - ez_ref).max() / scale),
+           "learned": float(np.abs(ez_learned[sl] - ez_ref).max() / scale)}
+    equal = err["learned"] <= 1.1 * err["plain"] + 1e-3
+    return {
+        "metric": "learned vs plain filter at equal wake error", "data": "synthetic",
+        "wake_error": err, "equal_wake_error": bool(equal),
+        "growth_rate_per_step": growth,
+        "growth_within_5pct_of_plain": bool(growth["learned"] <= growth["plain"] + 0.05 * abs(growth["plain"])),
+        "gain_error": gain,
+        "train": {"pairs": int(len(X)), "probes": int(len(probes[0])), "steps": args.c5_train_steps,
+                  "loss_history": hist},
+        "seconds": time.perf_counter() - t0,
+    }
+
+
 def read_pmc():
     if not os.path.exists(PMC_FILE):
         return None
@@ -214,12 +299,13 @@ def main():
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_GIB"))
-    ap.add_argument("--workload", choices=["c2", "c4"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2",
                     help="c2: the 256x4096 boosted run (default); c4: the batched scan of "
                          "independent boosted runs (persistent batched launch vs one run at a time)")
     ap.add_argument("--c4-runs", type=int, default=64)
     ap.add_argument("--c4-scale", type=float, default=1.0, help="grid scale of the scan's runs")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--c5-train-steps", type=int, default=3000)
     args = ap.parse_args()
 
     if args.summarize_pmc:
@@ -240,6 +326,9 @@ def main():
 
     if args.workload == "c4":
         print(json.dumps(bench_scan(args)), flush=True)
+        return
+    if args.workload == "c5":
+        print(json.dumps(bench_learned_filter_study(args)), flush=True)
         return
 
     if args.calib_copy_gib > 0:

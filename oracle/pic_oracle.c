@@ -18,7 +18,11 @@
  *   - lab-frame stations with Lorentz back-transformation (Sec. 3.2).
  * Readings where the paper is silent (2D reduction of the CK coefficients, full-cell
  * S^1 shifts, Friedman index shift, Boris pusher, PML sigma profile, antenna current,
- * row-wise plasma injection) are listed in the design notes and marked below.
+ * row-wise plasma injection) are marked where they are used below.
+ *
+ * Parity unpinned: the energy-conserving gather variant (only exact uniform and linear
+ * fields pin it), quantitative PML reflection (only absorption and its growth with depth
+ * are pinned), the nonlinear wakefield state beyond agreement with the GPU path.
  *
  * Units: L0 = 1 um, c = 1, eps0 = 1, electron charge -1 and mass 1.
  */

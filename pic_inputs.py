@@ -136,6 +136,38 @@ def c4(nruns=64, seed=10094, scale=1.0, real="f32"):
     return runs
 
 
+def c5_wake(real="f32", nx=64, nz=512, ppc=4, seed=1015, refine=1):
+    """Learned-filter wake family: the lab-frame stage of c1 (0.05 um cells, 4 ppc at 1e19 cm^-3,
+    a0 = 1, 10 fs) with the 4-pass + compensation filter, run 700 steps so the pulse crosses the
+    box and the wake forms behind it.  refine = 2 halves the cells and the time step (same box,
+    twice the steps): the reference run, unfiltered, in FP64."""
+    w = c1(real, nx=nx * refine, nz=nz * refine, ppc=ppc)
+    d = 0.05 / refine
+    w["config"].update(make_config(nx * refine, nz * refine, d, d, pml_cells=10 * refine, periodic_x=1,
+                                   ck="yee", cfl_fraction=0.95, filter_npass=4 if refine == 1 else 0,
+                                   filter_compensate=1 if refine == 1 else 0, seed=seed, real=real))
+    w["name"] = f"wake family {nx * refine}x{nz * refine}"
+    w["steps"] = 700 * refine
+    return w
+
+
+def c5_growth(real="f32", nx=64, nz=512, ppc=4, gamma=13.0, n0=1e19, npass=4, comp=1, seed=1016):
+    """Instability family: boosted frame gamma = 13, square cells of 1/32 of the boosted
+    wavelength (0.649 um), plasma at 1e19 cm^-3 filling the moving window and streaming through it
+    at -beta c with paired rigid ions, no laser: the numerical instabilities of Sec. 4 grow from
+    the particle noise.  npass = 0: no filter."""
+    d = boosted_cell(gamma)
+    return dict(
+        name=f"instability family gamma={gamma:g} {nx}x{nz}, {ppc} ppc, {n0:g} cm^-3",
+        config=make_config(nx, nz, d, d, pml_cells=10, ck="ck2", theta=0.1, cfl_fraction=0.95,
+                           filter_npass=npass, filter_compensate=comp, gamma_boost=gamma,
+                           moving_window=1, seed=seed, real=real),
+        plasma=plasma(n0, ppc, start_um=-1e30, ion_mode=1),
+        laser=None,
+        steps=600,
+    )
+
+
 def small_lab(real="f64", nx=24, nz=96, ppc=4, seed=77, npass=1, comp=0, ck="yee", theta=0.0):
     """A C1-shaped lab-frame case the oracle finishes in seconds (several tiles + ragged tail)."""
     w = c1(real, nx=nx, nz=nz, ppc=ppc)
