@@ -68,8 +68,7 @@ struct Layout {
     int tile_x, tile_z, ntx, ntz, ntiles, nchunks, seg_cap;
     // work buffer
     size_t w_seg[2], w_bbe[2], w_segi[2], w_bbi[2], w_counts, w_cursor, w_nused, w_status,
-        w_pml_r, w_pml_on, w_st_z, w_st_rec, w_st_cnt, w_ant, w_rho, w_lf_par, w_lf_pk[3], w_lf_h1,
-        w_lf_h2, w_bytes;
+        w_pml_r, w_pml_on, w_st_z, w_st_rec, w_st_cnt, w_ant, w_rho, w_lf_par, w_lf_pk[3], w_bytes;
     int nst, stcap;
 };
 
@@ -129,9 +128,6 @@ bool layout_of(const bf_config* c, Layout* L)
     const int nq[3] = {lf::chunks(1), lf::chunks(lf::C), lf::chunks(lf::C)};
     L->w_lf_par = take(lfk ? sizeof(float) * lf::NPARAM : 0);
     for (int k = 0; k < 3; k++) L->w_lf_pk[k] = take(lfk ? (size_t)nq[k] * lf::CHUNK_BYTES : 0);
-    const size_t hbytes = lfk ? sizeof(float) * lf::C * (size_t)L->Sx * L->Sz : 0;
-    L->w_lf_h1 = take(hbytes);
-    L->w_lf_h2 = take(hbytes);
     L->w_bytes = o;
     return true;
 }
@@ -549,19 +545,17 @@ void learned_filter(bf_sim* s, const FieldSet<float>& f)
     const Geo g = s->g;
     const int hx[3] = {1, 0, 0}, hz[3] = {0, 0, 1};
     const lf::Packed pk = lf_packed(s);
+    struct { lf::View in[3], out[3]; lf::Domain d[3]; } a;
     for (int c = 0; c < 3; c++) {
-        lf::Domain d;
-        d.nimg = 1;
-        d.nx = g.perx ? g.Sx : g.Sx - hx[c];
-        d.ny = g.perz ? g.Sz : g.Sz - hz[c];
-        d.perx = g.perx;
-        d.pery = g.perz;
-        lf::View jin{f.J[c], 0, g.pitch, 1, g.zoff, g.Sz};
-        lf::View jout{f.Jf[c], 0, g.pitch, 1, g.zoff, g.Sz};
-        lf::View h1{s->w<float>(s->L.w_lf_h1), 0, (long)d.nx * lf::C, lf::C, 0, d.ny};
-        lf::View h2{s->w<float>(s->L.w_lf_h2), 0, (long)d.nx * lf::C, lf::C, 0, d.ny};
-        s->run([=](hipStream_t st) { lf::forward(jin, h1, h2, jout, d, pk, st); });
+        a.d[c].nimg = 1;
+        a.d[c].nx = g.perx ? g.Sx : g.Sx - hx[c];
+        a.d[c].ny = g.perz ? g.Sz : g.Sz - hz[c];
+        a.d[c].perx = g.perx;
+        a.d[c].pery = g.perz;
+        a.in[c] = lf::View{f.J[c], 0, g.pitch, 1, g.zoff, g.Sz};
+        a.out[c] = lf::View{f.Jf[c], 0, g.pitch, 1, g.zoff, g.Sz};
     }
+    s->run([=](hipStream_t st) { lf::forward_fused(a.in, a.out, a.d, 3, pk, st); });
 }
 
 // batched recording is FP32 only (a batch is created from FP32 runs)

@@ -47,6 +47,7 @@ void pack_forward(const float* params, const Packed& pk, hipStream_t s);
 void pack_adjoint(const float* params, const Packed& pk, hipStream_t s);
 void forward(const View& in, const View& h1, const View& h2, const View& out, const Domain& d,
              const Packed& pk, hipStream_t s);
+void forward_fused(const View* in, const View* out, const Domain* d, int nplanes, const Packed& pk, hipStream_t s);
 void backward(const View& in, const View& h1, const View& h2, const View& out, const View& gout,
               const View& gh1, const View& gh2, const Domain& d, const Packed& pk, float* dw,
               hipStream_t s);

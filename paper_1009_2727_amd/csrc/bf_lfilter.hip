@@ -21,6 +21,7 @@
 // g(p, co) is an MFMA GEMM over pixels (hi/lo products hi*hi + hi*lo + lo*hi); Adam (Kingma &
 // Ba 2015) updates the FP32 master weights.
 #include "bf_lfilter.h"
+#include <algorithm>
 
 namespace bf {
 namespace lf {
@@ -239,6 +240,176 @@ __global__ void k_lf_zero(float* p, int n)
     if (q < n) p[q] = 0.f;
 }
 
+// ---- streamed forward pass (inference) ---------------------------------------------------
+// A workgroup walks down a strip of SOW output columns, one row per step, with all three
+// layers in flight: at step s layer 1 produces h1 row s+1, layer 2 consumes h1 row s and
+// completes h2 row s-2, layer 3 consumes h2 row s-3 and completes output row s-5.  Each layer
+// reads its source one row at a time from small LDS rings (the input 8 rows, h1 and h2 two):
+//  * layer 2 (16 -> 16) keeps five accumulator tiles for the h2 rows s-2 .. s+2, so one A
+//    fragment of h1 row s (16 pixels x 16 channels, tap dx) feeds five MFMAs (taps dy = 0..4);
+//    its 25 B fragments stay in registers;
+//  * layer 3 (16 -> 1) puts the tap row dy in the MFMA's N dimension: column dy of the
+//    accumulator holds the partial sum of output row r + 2 - dy after h2 row r; shifting the
+//    columns by one lane (DPP row_shr) before each row moves every partial to its next dy, and
+//    column 4 leaves complete;
+//  * layer 1 (1 -> 16) gathers its 25 taps x {hi, lo} from the input ring (two MFMAs).
+// Out-of-domain h1 and h2 pixels on non-periodic axes are written as zeros, as the separate
+// layers read them.  Four waves: wave w computes h1 strip w (wave 0 also strip 4), h2 strip w
+// and output strip w, strips of 16 columns.
+constexpr int SOW = 60;              // output columns per workgroup: [x0, x0 + 60)
+constexpr int SNS = 5;               // h1 strips: [x0 - 4, x0 + 76)
+constexpr int SH1W = 16 * SNS;       // 80 h1 columns
+constexpr int SH2W = 68;             // h2 columns read by layer 3: [x0 - 2, x0 + 66); 64 computed
+constexpr int SIW = SH1W + 4;        // input columns: [x0 - 6, x0 + 78)
+constexpr int SIR = 8;               // input ring rows
+
+// one image plane per blockIdx.z % n (up to 3: the current components), images blockIdx.z / n
+struct Planes {
+    View in[3], out[3];
+    Domain d[3];
+    int n, oh;                      // planes, output rows per workgroup
+};
+
+__device__ __forceinline__ void split_store(unsigned short* dst, int drow, int px, int py, int ch, float v)
+{
+    const unsigned short hi = bf16_rne(v);
+    dst[py * drow + px * 32 + ch] = hi;
+    dst[py * drow + px * 32 + 16 + ch] = bf16_rne(v - bf16_val(hi));
+}
+
+__device__ __forceinline__ f32x4 shift_columns(f32x4 t)
+{
+    // lane i of each 16-lane row takes lane i - 1; lane 0 takes 0 (row_shr:1, bound_ctrl)
+    f32x4 r;
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+        r[k] = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t[k]), 0x111, 0xf, 0xf, true));
+    return r;
+}
+
+__global__ void __launch_bounds__(256) k_lf_stream(Planes P, const us8* __restrict__ w1, const us8* __restrict__ w2,
+                                                   const us8* __restrict__ w3)
+{
+    __shared__ unsigned sin[SIR * SIW];                                   // hi | lo << 16
+    __shared__ __attribute__((aligned(16))) unsigned short sh1[2 * SH1W * 32];   // [row][col][hi 16 | lo 16]
+    __shared__ __attribute__((aligned(16))) unsigned short sh2[2 * SH2W * 32];
+    const int pl = blockIdx.z % P.n, img = blockIdx.z / P.n;
+    const View in = P.in[pl], out = P.out[pl];
+    const Domain d = P.d[pl];
+    const int x0 = blockIdx.x * SOW, y0 = blockIdx.y * P.oh;
+    if (x0 >= d.nx || y0 >= d.ny || img >= d.nimg) return;
+    const int yend = min(y0 + P.oh, d.ny);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
+
+    for (int q = threadIdx.x; q < SH1W * 32; q += 256) reinterpret_cast<unsigned*>(sh1)[q] = 0u;
+    for (int q = threadIdx.x; q < SH2W * 32; q += 256) reinterpret_cast<unsigned*>(sh2)[q] = 0u;
+    us8 b1[2], b2[TAPS], b3[5];
+#pragma unroll
+    for (int q = 0; q < 2; q++) b1[q] = w1[q * 64 + lane];
+#pragma unroll
+    for (int t = 0; t < TAPS; t++) b2[t] = w2[t * 64 + lane];
+#pragma unroll
+    for (int dx = 0; dx < 5; dx++) b3[dx] = i < 5 ? w3[(5 * i + dx) * 64 + 16 * g] : us8{0, 0, 0, 0, 0, 0, 0, 0};
+
+    // this thread's column of input row r (wrapped or zero outside the domain)
+    const int xin = threadIdx.x < SIW ? dwrap(x0 - 6 + (int)threadIdx.x, d.nx, d.perx) : -1;
+    auto load_in = [&](int r) -> float {
+        const int y = dwrap(r, d.ny, d.pery);
+        return (xin >= 0 && y >= 0) ? in.p[vaddr(in, img, y, xin)] : 0.f;
+    };
+    auto put_in = [&](int r, float v) {
+        if (threadIdx.x < SIW) {
+            const unsigned short hi = bf16_rne(v);
+            sin[(r & (SIR - 1)) * SIW + threadIdx.x] = (unsigned)hi | ((unsigned)bf16_rne(v - bf16_val(hi)) << 16);
+        }
+    };
+    const int s0 = y0 - 5;
+    for (int r = s0 - 1; r <= s0 + 3; r++) put_in(r, load_in(r));
+    float next = load_in(s0 + 4);
+    __syncthreads();
+
+    f32x4 acc[5], T = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 5; k++) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nsteps = (yend - y0 + 10 + 4) / 5 * 5;
+    for (int s5 = s0; s5 < s0 + nsteps; s5 += 5) {
+#pragma unroll
+        for (int u = 0; u < 5; u++) {
+            const int s = s5 + u;
+            // layer 1: h1 row s + 1 from input rows s - 1 .. s + 3
+            {
+                unsigned short* h1 = sh1 + ((s + 1) & 1) * SH1W * 32;
+                const int yr = s + 1;
+                const bool rowok = d.pery || (yr >= 0 && yr < d.ny);
+                for (int st = wave; st < SNS; st += 4) {
+                    f32x4 a = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int q = 0; q < 2; q++) {
+                        us8 A;
+#pragma unroll
+                        for (int jj = 0; jj < 4; jj++) {
+                            const int t = 16 * q + 4 * g + jj;
+                            unsigned v = 0u;
+                            if (t < TAPS) v = sin[((yr + t / 5 - 2) & (SIR - 1)) * SIW + 16 * st + i + t % 5];
+                            A[2 * jj] = (unsigned short)(v & 0xffffu);
+                            A[2 * jj + 1] = (unsigned short)(v >> 16);
+                        }
+                        a = mfma(A, b1[q], a);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int c = 16 * st + 4 * g + r, x = x0 - 4 + c;
+                        const bool ok = rowok && (d.perx || (x >= 0 && x < d.nx));
+                        split_store(h1, 0, c, 0, i, ok ? a[r] : 0.f);
+                    }
+                }
+            }
+            // layer 2: h1 row s into the h2 rows s - 2 .. s + 2; row s - 2 completes
+            {
+                const unsigned short* src = sh1 + (s & 1) * SH1W * 32 + (16 * wave + i) * 32 + 8 * g;
+#pragma unroll
+                for (int dx = 0; dx < 5; dx++) {
+                    const us8 A = *reinterpret_cast<const us8*>(src + dx * 32);
+#pragma unroll
+                    for (int dy = 0; dy < 5; dy++) {
+                        const int k = (u + 7 - dy) % 5;
+                        acc[k] = mfma(A, b2[5 * dy + dx], acc[k]);
+                    }
+                }
+                f32x4& c2 = acc[(u + 3) % 5];
+                unsigned short* h2 = sh2 + ((s - 2) & 1) * SH2W * 32;
+                const int yr = s - 2;
+                const bool rowok = d.pery || (yr >= 0 && yr < d.ny);
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int c = 16 * wave + 4 * g + r, x = x0 - 2 + c;
+                    const bool ok = rowok && (d.perx || (x >= 0 && x < d.nx));
+                    split_store(h2, 0, c, 0, i, ok ? c2[r] : 0.f);
+                }
+                c2 = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+            // layer 3: h2 row s - 3; output row s - 5 completes in column 4
+            {
+                T = shift_columns(T);
+                const unsigned short* src = sh2 + ((s - 3) & 1) * SH2W * 32 + (16 * wave + i) * 32 + 8 * g;
+#pragma unroll
+                for (int dx = 0; dx < 5; dx++) T = mfma(*reinterpret_cast<const us8*>(src + dx * 32), b3[dx], T);
+                const int y = s - 5;
+                if (i == 4 && y >= y0 && y < yend) {
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int c = 16 * wave + 4 * g + r, x = x0 + c;
+                        if (c < SOW && x < d.nx) out.p[vaddr(out, img, y, x)] = T[r];
+                    }
+                }
+            }
+            put_in(s + 4, next);
+            next = load_in(s + 5);
+            __syncthreads();
+        }
+    }
+}
+
 // ---- host launchers ---------------------------------------------------------------------
 
 int chunks(int cin) { return (TAPS * cin * 2 + 31) / 32; }
@@ -287,13 +458,40 @@ void launch_zero(float* p, int n, hipStream_t s)
     hipLaunchKernelGGL(k_lf_zero, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
 }
 
-// the three-layer forward pass: in (1 channel) -> h1 (16) -> h2 (16) -> out (1 channel)
+// the three-layer forward pass: in (1 channel) -> h1 (16) -> h2 (16) -> out (1 channel), kept
+// in separate layers when the intermediates are needed (training)
 void forward(const View& in, const View& h1, const View& h2, const View& out, const Domain& d,
              const Packed& pk, hipStream_t s)
 {
     launch_conv<1, 16>(in, h1, d, pk.fwd[0], s);
     launch_conv<16, 16>(h1, h2, d, pk.fwd[1], s);
     launch_conv<16, 1>(h2, out, d, pk.fwd[2], s);
+}
+
+// the forward pass streamed in one kernel (inference), on up to three image planes at once
+void forward_fused(const View* in, const View* out, const Domain* d, int nplanes, const Packed& pk, hipStream_t s)
+{
+    Planes P{};
+    P.n = nplanes;
+    int nx = 0, ny = 0, nimg = 0;
+    for (int k = 0; k < nplanes; k++) {
+        P.in[k] = in[k];
+        P.out[k] = out[k];
+        P.d[k] = d[k];
+        nx = std::max(nx, d[k].nx);
+        ny = std::max(ny, d[k].ny);
+        nimg = std::max(nimg, d[k].nimg);
+    }
+    // rows per workgroup: the tallest strip that still gives about four workgroups per CU
+    const long cols = (long)((nx + SOW - 1) / SOW) * nimg * nplanes;
+    int oh = 16;
+    for (int c : {128, 96, 64, 48, 32, 24}) {
+        if (cols * ((ny + c - 1) / c) >= 1024) { oh = c; break; }
+    }
+    P.oh = oh;
+    const dim3 grid((nx + SOW - 1) / SOW, (ny + oh - 1) / oh, nimg * nplanes);
+    hipLaunchKernelGGL(k_lf_stream, grid, dim3(256), 0, s, P, reinterpret_cast<const us8*>(pk.fwd[0]),
+                       reinterpret_cast<const us8*>(pk.fwd[1]), reinterpret_cast<const us8*>(pk.fwd[2]));
 }
 
 void pack_forward(const float* params, const Packed& pk, hipStream_t s)
@@ -413,8 +611,8 @@ bf_status bf_lf_apply(void* work, int64_t work_bytes, const float* params, const
     const Domain d{nimg, ny, nx, periodic_x ? 1 : 0, periodic_y ? 1 : 0};
     (void)hipGetLastError();
     pack_forward(params, pk, s);
-    forward(image_view(in, ny, nx, 1), image_view(reinterpret_cast<float*>(b + w.h1), ny, nx, C),
-            image_view(reinterpret_cast<float*>(b + w.h2), ny, nx, C), image_view(out, ny, nx, 1), d, pk, s);
+    const View vin = image_view(in, ny, nx, 1), vout = image_view(out, ny, nx, 1);
+    forward_fused(&vin, &vout, &d, 1, pk, s);
     return hipGetLastError() == hipSuccess ? BF_OK : BF_EDEVICE;
 }
 
