@@ -33,10 +33,15 @@ PMC_FILE = os.path.join(ROOT, "profiles", "gpd_c2_pmc.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1009_2727_amd", "csrc", "bf_particles.hip")
 
 
+GPD_SOURCES = ("bf_particles.hip", "bf_device.h", "bf_kernels.h")
+
+
 def src_hash() -> str:
+    """Hash of the sources the gather/push/deposit kernel is compiled from: stored counter
+    totals are used only while it matches."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1009_2727_amd", "csrc", "*"))):
-        h.update(open(f, "rb").read())
+    for f in GPD_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1009_2727_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 

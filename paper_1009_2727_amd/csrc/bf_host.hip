@@ -450,7 +450,7 @@ void sort_now(bf_sim* s)
         });
         s->nseg_i = L.ntiles;
     }
-    s->p_cur ^= 1;
+    // both species end in their current buffers (the other one is the sort's scratch)
     s->sg_cur ^= 1;
     s->nseg_e = L.ntiles;
     s->since_sort = 0;

@@ -774,7 +774,7 @@ __global__ void __launch_bounds__(NTHR) k_inject(Geo g, ElectronArrays<R> e, Ion
     }
     int x0 = INT_MAX, x1 = INT_MIN, z0 = INT_MAX, z1 = INT_MIN;
     for (int q = threadIdx.x; q < count; q += NTHR) {
-        const int cell = q / ip.ppc, k = q - cell * ip.ppc;
+        const int cell = q % ncell, k = q / ncell;   // consecutive lanes in consecutive cells
         const int ix = cx0 + cell;
         const uint64_t id = ((uint64_t)row * (uint64_t)g.Nx + (uint64_t)ix) * (uint64_t)ip.ppc + (uint64_t)k;
         const double rx = u01(ip.seed, 2 * id + 1), rz = u01(ip.seed, 2 * id + 2);
@@ -840,13 +840,13 @@ __device__ __forceinline__ int64_t gcd64(int64_t a, int64_t b)
 
 // Exclusive scan of the tile counts; writes the new segment table (one per tile), each
 // tile's box (the tile rectangle), the scatter rank counters (zero) and the new slot count.
-// counts[] is overwritten with each tile's slot multiplier m: the particle arriving r-th in
-// a tile goes to slot (r m) mod count, so that consecutive slots hold arrivals d = 1/m apart
-// with d just above the mean count per cell -- the particles of one cell, which arrive
-// together, land in different waves and the LDS current atomics of a wave rarely collide.
-__global__ void __launch_bounds__(1024) k_sort_scan(int* counts, int ntiles, int ntx, int tx,
-                                                    int tz, int Nx, int Nz, Segment* seg, int4* bbox,
-                                                    int* cursor, int* nused)
+// counts[] is overwritten with each tile's slot multiplier, 1: the first pass of the sort
+// writes each tile's particles to consecutive slots in arrival order (a source wave's
+// particles mostly share a destination tile, so its writes stay coalesced); the second pass
+// (k_sort_disperse_*) orders them within the tile.
+__global__ void __launch_bounds__(1024) k_sort_scan(int* counts, int ntiles, int ntx, int tx, int tz,
+                                                    int Nx, int Nz, Segment* seg, int4* bbox, int* cursor,
+                                                    int* nused)
 {
     __shared__ int part[1024];
     const int t = threadIdx.x;
@@ -867,13 +867,7 @@ __global__ void __launch_bounds__(1024) k_sort_scan(int* counts, int ntiles, int
         const int c = counts[i];
         seg[i] = Segment{run, c};
         cursor[i] = 0;
-        int64_t m = 1;
-        if (c > 2) {
-            int64_t d = c / (tx * tz) + 1;
-            while (d < c && gcd64(d, c) != 1) d++;
-            m = d < c ? inv_mod(d, c) : 1;
-        }
-        counts[i] = (int)m;
+        counts[i] = 1;
         const int cxi = i % ntx, czi = i / ntx;
         const int xa = cxi * tx, za = czi * tz;
         bbox[i] = c > 0 ? make_int4(xa, min(xa + tx, Nx) - 1, za, min(za + tz, Nz) - 1)
@@ -1014,6 +1008,162 @@ __global__ void __launch_bounds__(NTHR) k_sort_scatter_i(Geo g, IonArrays<R> src
     }
 }
 
+// ---- second pass of the sort: order within each tile --------------------------------------------
+// One block per tile reads the tile's particles (consecutive after the first pass) and ranks
+// them by cell in row-major order (LDS histogram, scan, per-cell counters).  The particle of
+// rank r goes to slot (r m) mod N of the tile, m the inverse of a spacing d coprime to N that
+// is at least the largest cell count of the tile: consecutive slots hold ranks d apart, so a
+// run of slots holds at most one particle per cell (while 64 d fits in N) and the 64 lanes of
+// a wave of the particle kernel deposit into 64 distinct cells of a compact block -- its LDS
+// current atomics neither collide nor pile up in a bank.  The copy runs in slot order (slot s
+// takes rank s d mod N through an LDS rank -> particle table), so the writes are coalesced and
+// the scattered reads stay within the tile's particles.  A tile with more particles than the
+// table holds writes each particle to its slot directly.  Particle order changes no result
+// (the FP32 tile sums are exact integer sums).
+constexpr int SORT_MAX_CELLS = 64 * 64;   // the largest tile the configuration accepts
+constexpr int SORT_TABLE = 8192;          // particles per tile ordered through the LDS table
+constexpr int SORT_THREADS = 512;
+
+struct TileCells {
+    int xa, za, w, h;
+    __device__ __forceinline__ int of(double x, double z, const Geo& g) const
+    {
+        const int cx = min(max((int)floor(x), 0), g.Nx - 1) - xa;
+        const int cz = min(max((int)floor(z), 0), g.Nz - 1) - za;
+        return min(max(cz, 0), h - 1) * w + min(max(cx, 0), w - 1);
+    }
+};
+
+__device__ __forceinline__ TileCells tile_cells(const Geo& g, int tx, int tz, int ntx)
+{
+    TileCells t;
+    t.xa = (blockIdx.x % ntx) * tx;
+    t.za = (blockIdx.x / ntx) * tz;
+    t.w = min(tx, g.Nx - t.xa);
+    t.h = min(tz, g.Nz - t.za);
+    return t;
+}
+
+// LDS state of the tile ordering
+struct TileSort {
+    int cnt[SORT_MAX_CELLS], base[SORT_MAX_CELLS], idx[SORT_TABLE];
+    int part[SORT_THREADS], pmax[SORT_THREADS];
+    int mult, spacing;
+};
+
+// cnt[] holds the tile's cell counts: replaces them by zeros, fills base[] with the exclusive
+// scan and sets the slot multiplier m and the spacing d
+__device__ void tile_ranks(TileSort& ts, int C, int N)
+{
+    const int t = threadIdx.x;
+    const int per = (C + SORT_THREADS - 1) / SORT_THREADS, lo = min(t * per, C), hi = min(lo + per, C);
+    int sum = 0, mx = 0;
+    for (int i = lo; i < hi; i++) {
+        sum += ts.cnt[i];
+        mx = max(mx, ts.cnt[i]);
+    }
+    ts.part[t] = sum;
+    ts.pmax[t] = mx;
+    __syncthreads();
+    for (int o = 1; o < SORT_THREADS; o <<= 1) {
+        const int v = t >= o ? ts.part[t - o] : 0, m = t >= o ? ts.pmax[t - o] : 0;
+        __syncthreads();
+        ts.part[t] += v;
+        ts.pmax[t] = max(ts.pmax[t], m);
+        __syncthreads();
+    }
+    int run = ts.part[t] - sum;
+    for (int i = lo; i < hi; i++) {
+        ts.base[i] = run;
+        run += ts.cnt[i];
+        ts.cnt[i] = 0;
+    }
+    if (t == 0) {
+        int64_t d = 1, m = 1;
+        if (N > 2) {
+            d = max(ts.pmax[SORT_THREADS - 1], 1);
+            while (d < N && gcd64(d, N) != 1) d++;
+            if (d < N) m = inv_mod(d, N);
+            else d = m = 1;
+        }
+        ts.mult = (int)m;
+        ts.spacing = (int)d;
+    }
+    __syncthreads();
+}
+
+// pos(q) -> (x, z) of the tile's q-th particle; copy(q, slot) moves it
+template <typename Pos, typename Copy>
+__device__ void order_tile(TileSort& ts, const Segment& sg, const TileCells& tc, const Geo& g, Pos pos, Copy copy)
+{
+    const int C = tc.w * tc.h, N = sg.count;
+    for (int i = threadIdx.x; i < C; i += SORT_THREADS) ts.cnt[i] = 0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < N; q += SORT_THREADS) {
+        const double2 xz = pos(q);
+        atomicAdd(&ts.cnt[tc.of(xz.x, xz.y, g)], 1);
+    }
+    __syncthreads();
+    tile_ranks(ts, C, N);
+    const int m = ts.mult, d = ts.spacing;
+    const bool table = N <= SORT_TABLE;
+    for (int q = threadIdx.x; q < N; q += SORT_THREADS) {
+        const double2 xz = pos(q);
+        const int c = tc.of(xz.x, xz.y, g);
+        const int r = ts.base[c] + atomicAdd(&ts.cnt[c], 1);
+        if (table) ts.idx[r] = q;
+        else copy(q, (int)(((int64_t)r * m) % N));
+    }
+    if (!table) return;
+    __syncthreads();
+    for (int sl = threadIdx.x; sl < N; sl += SORT_THREADS) copy(ts.idx[(int)(((int64_t)sl * d) % N)], sl);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(SORT_THREADS) k_sort_disperse_e(Geo g, ElectronArrays<R> src,
+                                                                  ElectronArrays<R> dst, const Segment* seg,
+                                                                  int tx, int tz, int ntx)
+{
+    __shared__ TileSort ts;
+    const Segment sg = seg[blockIdx.x];
+    if (sg.count == 0) return;
+    const TileCells tc = tile_cells(g, tx, tz, ntx);
+    const int o = sg.start;
+    order_tile(
+        ts, sg, tc, g, [&](int q) { return make_double2(src.x[o + q], src.z[o + q]); },
+        [&](int q, int sl) {
+            const int p = o + q, d = o + sl;
+            dst.x[d] = src.x[p];
+            dst.z[d] = src.z[p];
+            dst.ux[d] = src.ux[p];
+            dst.uy[d] = src.uy[p];
+            dst.uz[d] = src.uz[p];
+            dst.w[d] = src.w[p];
+            dst.id[d] = src.id[p];
+        });
+}
+
+template <typename R>
+__global__ void __launch_bounds__(SORT_THREADS) k_sort_disperse_i(Geo g, IonArrays<R> src, IonArrays<R> dst,
+                                                                  const Segment* seg, double zsh, int tx, int tz,
+                                                                  int ntx)
+{
+    __shared__ TileSort ts;
+    const Segment sg = seg[blockIdx.x];
+    if (sg.count == 0) return;
+    const TileCells tc = tile_cells(g, tx, tz, ntx);
+    const int o = sg.start;
+    order_tile(
+        ts, sg, tc, g, [&](int q) { return make_double2(src.x[o + q], src.z0[o + q] - zsh); },
+        [&](int q, int sl) {
+            const int p = o + q, d = o + sl;
+            dst.x[d] = src.x[p];
+            dst.z0[d] = src.z0[p];
+            dst.w[d] = src.w[p];
+            dst.id[d] = src.id[p];
+        });
+}
+
 // ---- launchers ---------------------------------------------------------------------------------
 template <typename R>
 void launch_gpd(const Geo& g, const FieldSet<R>& f, const ElectronArrays<R>& e, const Segment* seg,
@@ -1071,41 +1221,47 @@ void launch_inject(const Geo& g, const ElectronArrays<R>& e, const IonArrays<R>&
                        bbox_e, seg_i, bbox_i, nused_e, nused_i, ip, status);
 }
 
+// two-pass sort: a -> b by tile (consecutive slots per tile), then b -> a ordered within each
+// tile; the particles end in a under the new segment table
 template <typename R>
 void launch_sort_electrons(const Geo& g, int tile_x, int tile_z, int ntx, int ntiles,
-                           const ElectronArrays<R>& src, const ElectronArrays<R>& dst,
+                           const ElectronArrays<R>& a, const ElectronArrays<R>& b,
                            const Segment* seg_old, int nseg_old, Segment* seg_new, int4* bbox_new,
                            int* counts, int* cursor, int* nused, hipStream_t s)
 {
     const int ntz = ntiles / ntx;
     launch_fill_int(counts, ntiles, 0, s);
     if (nseg_old > 0)
-        hipLaunchKernelGGL((k_sort_count_e<R>), dim3(nseg_old), dim3(NTHR), 0, s, g, src, seg_old,
+        hipLaunchKernelGGL((k_sort_count_e<R>), dim3(nseg_old), dim3(NTHR), 0, s, g, a, seg_old,
                            tile_x, tile_z, ntx, ntz, counts);
     hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, counts, ntiles, ntx, tile_x, tile_z, g.Nx,
                        g.Nz, seg_new, bbox_new, cursor, nused);
     if (nseg_old > 0)
-        hipLaunchKernelGGL((k_sort_scatter_e<R>), dim3(nseg_old), dim3(NTHR), 0, s, g, src, dst,
+        hipLaunchKernelGGL((k_sort_scatter_e<R>), dim3(nseg_old), dim3(NTHR), 0, s, g, a, b,
                            seg_old, tile_x, tile_z, ntx, ntz, cursor, (const Segment*)seg_new,
                            (const int*)counts);
+    hipLaunchKernelGGL((k_sort_disperse_e<R>), dim3(ntiles), dim3(SORT_THREADS), 0, s, g, b, a, (const Segment*)seg_new,
+                       tile_x, tile_z, ntx);
 }
 
 template <typename R>
-void launch_sort_ions(const Geo& g, int tile_x, int tile_z, int ntx, int ntiles, const IonArrays<R>& src,
-                      const IonArrays<R>& dst, const Segment* seg_old, int nseg_old, Segment* seg_new,
+void launch_sort_ions(const Geo& g, int tile_x, int tile_z, int ntx, int ntiles, const IonArrays<R>& a,
+                      const IonArrays<R>& b, const Segment* seg_old, int nseg_old, Segment* seg_new,
                       int4* bbox_new, double zsh, int* counts, int* cursor, int* nused, hipStream_t s)
 {
     const int ntz = ntiles / ntx;
     launch_fill_int(counts, ntiles, 0, s);
     if (nseg_old > 0)
-        hipLaunchKernelGGL((k_sort_count_i<R>), dim3(nseg_old), dim3(NTHR), 0, s, g, src, seg_old, zsh,
+        hipLaunchKernelGGL((k_sort_count_i<R>), dim3(nseg_old), dim3(NTHR), 0, s, g, a, seg_old, zsh,
                            tile_x, tile_z, ntx, ntz, counts);
     hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, counts, ntiles, ntx, tile_x, tile_z, g.Nx,
                        g.Nz, seg_new, bbox_new, cursor, nused);
     if (nseg_old > 0)
-        hipLaunchKernelGGL((k_sort_scatter_i<R>), dim3(nseg_old), dim3(NTHR), 0, s, g, src, dst, seg_old,
+        hipLaunchKernelGGL((k_sort_scatter_i<R>), dim3(nseg_old), dim3(NTHR), 0, s, g, a, b, seg_old,
                            zsh, tile_x, tile_z, ntx, ntz, cursor, (const Segment*)seg_new,
                            (const int*)counts);
+    hipLaunchKernelGGL((k_sort_disperse_i<R>), dim3(ntiles), dim3(SORT_THREADS), 0, s, g, b, a, (const Segment*)seg_new,
+                       zsh, tile_x, tile_z, ntx);
 }
 
 #define BF_INST(R)                                                                                    \
