@@ -74,8 +74,8 @@ typedef struct {
     double gamma_boost;        /* Lorentz factor of the calculation frame (>= 1)              */
     int moving_window;         /* 1: window follows the wake at beta_w* c (Sec. 2)             */
     int64_t particle_capacity; /* slots per species (electrons; rigid ions alike)              */
-    int sort_every;            /* steps between tile sorts (0: library default)                */
-    int tile_x, tile_z;        /* particle tile in cells (0: library default)                  */
+    int sort_every;            /* steps between tile sorts (0: library default, 20)            */
+    int tile_x, tile_z;        /* particle tile in cells (0: library default, 26 x 8)          */
     int max_stations;          /* lab-frame stations that may be added                         */
     int station_capacity;      /* samples kept per station                                     */
     int phase_timers;          /* 1: record HIP events around every phase of bf_step          */

@@ -13,8 +13,8 @@ from __future__ import annotations
 import copy
 import math
 
-TILES = ((8, 8), (16, 8), (8, 16), (16, 16), (24, 16), (16, 24))
-SORT_EVERY = (5, 10, 20, 40)
+TILES = ((16, 8), (16, 16), (24, 8), (26, 8), (26, 12), (24, 16))
+SORT_EVERY = (10, 20, 40, 80)
 
 
 def run_class(workload) -> tuple:

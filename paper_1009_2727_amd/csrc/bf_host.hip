@@ -94,8 +94,13 @@ bool layout_of(const bf_config* c, Layout* L)
     const size_t isz[4] = {8, 8, (size_t)real, 4};
     for (int k = 0; k < 4; k++) { L->i_off[k] = o; o = align_up(o + isz[k] * L->cap, 256); }
     L->i_bytes = std::max<size_t>(o, 256);
-    L->tile_x = c->tile_x > 0 ? c->tile_x : 16;
-    L->tile_z = c->tile_z > 0 ? c->tile_z : 16;
+    // default tile 26 x 8: with the LDS tile pitch of 33 cells, the cells of a tile whose
+    // row-major ranks are less than 25 apart fall in distinct 8-byte bank pairs (33 = 1 mod
+    // 32), so the 16 lanes an LDS atomic serves at once, spread over the tile's cells by the
+    // sort, rarely conflict; 26 + the 5-cell deposit halo leaves 2 columns of slack in the
+    // 33-column LDS tile for particles drifting out between sorts
+    L->tile_x = c->tile_x > 0 ? c->tile_x : 26;
+    L->tile_z = c->tile_z > 0 ? c->tile_z : 8;
     L->ntx = (c->nx + L->tile_x - 1) / L->tile_x;
     L->ntz = (c->nz + L->tile_z - 1) / L->tile_z;
     L->ntiles = L->ntx * L->ntz;
