@@ -239,6 +239,29 @@ def test_sort_cadence_does_not_change_results():
 
 
 # ---------------------------------------------------------------------------------------
+# the benchmarked workload at its full size and launch configuration
+# ---------------------------------------------------------------------------------------
+
+@gpu
+def test_full_size_boosted_fp32_matches_oracle():
+    # 256 x 4096 cells, 16 ppc pre-loaded (16.8M electrons + 16.8M rigid ions), FP32 with FP64
+    # positions, the library's default tile and the benchmark's sort cadence; two steps on both
+    # sides from the same counter-based loading, then every field cell and every electron
+    import sys
+    w = pi.c2(real="f32", preload=True)
+    print("full-size c2: GPU", flush=True)
+    sim = _sim(w, sort_every=80)
+    sim.step(2)
+    assert sim.sync_status() == 0
+    print("full-size c2: oracle (about a minute)", flush=True)
+    ref = Oracle.from_workload(w)
+    ref.step(2)
+    sys.stdout.flush()
+    compare_fields(sim, ref, 1e-5, tag="full c2 f32")
+    compare_particles(sim, ref, 1e-5, 1e-5)
+
+
+# ---------------------------------------------------------------------------------------
 # invariants and edge cases
 # ---------------------------------------------------------------------------------------
 
