@@ -1,4 +1,4 @@
-"""ctypes wrapper of the FP64 CPU oracle (oracle/pic_oracle.c).
+"""ctypes wrapper of the FP64 CPU oracle (oracle/pic_oracle.c; the 3D one is in oracle/pic3.py).
 
 TEST INFRASTRUCTURE ONLY: imported by tests/, by __graft_entry__.smoke() and by the
 CPU-baseline leg of bench.py.  The product package never imports it.
@@ -24,11 +24,17 @@ FIELDS = ["Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "Exo", "Eyo", "E
 FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 
 
+_SOURCES = ("pic_oracle.c", "pic_oracle3.c", "pic_oracle.h", "pic_oracle3.h")
+
+
 def build(force: bool = False) -> str:
-    src = os.path.join(_HERE, "pic_oracle.c")
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(src):
+    """Compiles the 2-1/2D and the 3D references into one shared library."""
+    srcs = [os.path.join(_HERE, f) for f in _SOURCES]
+    newest = max(os.path.getmtime(f) for f in srcs)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp,
+                               *[f for f in srcs if f.endswith(".c")], "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

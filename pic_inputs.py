@@ -187,6 +187,68 @@ def small_boosted(real="f64", nx=40, nz=150, ppc=4, seed=78, gamma=13.0, preload
     return w
 
 
+# ---------------------------------------------------------------------------------------
+# Three dimensions
+# ---------------------------------------------------------------------------------------
+
+def make_config3(nx, ny, nz, dx_um, dy_um, dz_um, *, pml_cells=10, periodic_x=0, periodic_y=0,
+                 periodic_z=0, ck="yee", theta=0.0, cfl_fraction=0.95, filter_npass=0,
+                 filter_compensate=0, gamma_boost=1.0, moving_window=0, seed=1009, real="f64"):
+    a, b, g = CK_SETS[ck] if isinstance(ck, str) else ck
+    return dict(dim=3, nx=int(nx), ny=int(ny), nz=int(nz), dx_um=float(dx_um), dy_um=float(dy_um),
+                dz_um=float(dz_um), pml_cells=int(pml_cells), periodic_x=int(periodic_x),
+                periodic_y=int(periodic_y), periodic_z=int(periodic_z), ck_alpha=a, ck_beta=b,
+                ck_gamma=g, theta=float(theta), cfl_fraction=float(cfl_fraction),
+                filter_npass=int(filter_npass), filter_compensate=int(filter_compensate),
+                gamma_boost=float(gamma_boost), moving_window=int(moving_window), seed=int(seed),
+                real=real)
+
+
+def c3(real="f32", nx=128, ny=128, nz=1024, ppc=8, preload=False, gamma=30.0):
+    """3D boosted frame gamma=30: 128x128x1024, 8 ppc (134M electrons when filled), lab
+    density 1e17 cm^-3 with a 20 um linear up-ramp starting 2 um ahead of the antenna, laser
+    a0=2 waist 50 um, CK2 solver, Friedman theta=0.1, 4 bilinear passes + compensation,
+    10-cell PML on every face, moving window, rigid ions, 5000 steps."""
+    d = boosted_cell(gamma)
+    z_ant = gamma * 0.6 * nz * d
+    start = -1e30 if preload else z_ant + 2.0
+    ramp = 0.0 if preload else 20.0
+    # laser FWHM = half a plasma wavelength at 1e17 cm^-3 (lambda_p = 105.59 um)
+    fwhm = 0.5 * 105.59 / 0.299792458
+    return dict(
+        name=(f"3D boosted gamma={gamma:g} {nx}x{ny}x{nz}, {ppc} ppc, 1e17 cm^-3"
+              f"{' (pre-loaded window)' if preload else ''}, a0=2, CK2 + Friedman 0.1,"
+              " 4-pass bilinear + compensation, 10-cell PML, moving window"),
+        config=make_config3(nx, ny, nz, d, d, d, pml_cells=10, ck="ck2", theta=0.1,
+                            cfl_fraction=0.95, filter_npass=4, filter_compensate=1,
+                            gamma_boost=gamma, moving_window=1, seed=1012, real=real),
+        plasma=plasma(1e17, ppc, ramp_um=ramp, start_um=start, ion_mode=1),
+        laser=laser(2.0, 50.0, fwhm, z_ant),
+        steps=5000,
+    )
+
+
+def small_boosted3(real="f64", nx=12, ny=10, nz=48, ppc=2, seed=79, gamma=30.0, preload=False):
+    """A C3-shaped case (window, PML on all faces, CK2 + Friedman, 4+comp filter, rigid ions,
+    antenna) small enough for the 3D oracle; the laser waist is scaled to the box."""
+    w = c3(real, nx=nx, ny=ny, nz=nz, ppc=ppc, preload=preload, gamma=gamma)
+    w["config"]["seed"] = seed
+    w["laser"]["waist_um"] = 0.3 * nx * w["config"]["dx_um"]
+    w["name"] = f"small boosted 3D {nx}x{ny}x{nz}"
+    return w
+
+
+def random_electrons3(n, nx, ny, nz, d, seed, umax=1.0, margin=3.0):
+    r = np.random.default_rng(seed)
+    x = (margin + r.random(n) * (nx - 2 * margin)) * d[0]
+    y = (margin + r.random(n) * (ny - 2 * margin)) * d[1]
+    z = (margin + r.random(n) * (nz - 2 * margin)) * d[2]
+    u = (2.0 * r.random((3, n)) - 1.0) * umax
+    w = 0.5 + r.random(n)
+    ids = np.arange(n, dtype=np.uint32)
+    return dict(id=ids, x=x, y=y, z=z, ux=u[0], uy=u[1], uz=u[2], w=w)
+
+
 def copy_workload(w):
     return copy.deepcopy(w)
 
