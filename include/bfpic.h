@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define BF_ABI_VERSION 2u
+#define BF_ABI_VERSION 3u
 
 typedef enum {
     BF_OK = 0,
@@ -56,7 +56,7 @@ typedef struct bf_sim bf_sim;
    sizeof(bf_config). */
 typedef struct {
     uint32_t abi_version, struct_size;
-    int dim;                   /* 2 (x, z plane)                                               */
+    int dim;                   /* 2 (x, z plane) or 3 (x, y transverse, z the boost axis)      */
     int nx, ny, nz;            /* interior cells (ny unused in 2D)                             */
     double dx_um, dy_um, dz_um;/* cell sizes in the calculation frame                          */
     int real_bytes;            /* 4: FP32 fields/momenta, 8: FP64 throughout                   */
@@ -70,7 +70,7 @@ typedef struct {
     int filter_kind;           /* BF_FILTER_BILINEAR, or BF_FILTER_LEARNED (FP32 runs only;
                                   weights from bf_set_learned_filter)                         */
     int pml_cells;             /* PML depth on non-periodic faces (Appendix II)                */
-    int periodic_mask;         /* bit 0: x periodic, bit 2: z periodic (no moving window)      */
+    int periodic_mask;         /* bit 0: x, bit 1: y (3D), bit 2: z periodic (no moving window) */
     double gamma_boost;        /* Lorentz factor of the calculation frame (>= 1)              */
     int moving_window;         /* 1: window follows the wake at beta_w* c (Sec. 2)             */
     int64_t particle_capacity; /* slots per species (electrons; rigid ions alike)              */
@@ -150,10 +150,15 @@ bf_status bf_add_station(bf_sim* sim, const bf_station* station, int* station_id
 
 /* Replaces the electron set by n explicit particles (host arrays, positions in um relative
    to the interior origin, momenta u = gamma v / c, weights in the library's normalised
-   units).  id may be NULL.  Ions and antenna are unchanged. */
+   units).  id may be NULL.  Ions and antenna are unchanged.  2D runs only. */
 bf_status bf_load_electrons(bf_sim* sim, int64_t n, const uint32_t* id, const double* x,
                             const double* z, const double* ux, const double* uy,
                             const double* uz, const double* w);
+
+/* The same for a 3D run (dim == 3), with the y positions. */
+bf_status bf_load_electrons3(bf_sim* sim, int64_t n, const uint32_t* id, const double* x,
+                             const double* y, const double* z, const double* ux, const double* uy,
+                             const double* uz, const double* w);
 
 /* ---- stepping -------------------------------------------------------------------------- */
 
@@ -164,16 +169,18 @@ bf_status bf_step(bf_sim* sim, int nsteps);
 /* ---- diagnostics and state ------------------------------------------------------------- */
 
 enum {
-    BF_DIAG_FIELD = 0,     /* arg = field id (BF_F_*): stored_z x stored_x doubles          */
+    BF_DIAG_FIELD = 0,     /* arg = field id (BF_F_*): stored_z x stored_x doubles (3D:
+                              stored_z x stored_y x stored_x)                               */
     BF_DIAG_PARTICLES = 1, /* arg = species (0 e-, 1 ions): 7 arrays of n doubles (id, x, z,
-                              ux, uy, uz, w), n = BF_DIAG_COUNTS value                        */
+                              ux, uy, uz, w), n = BF_DIAG_COUNTS value; 3D: 8 arrays (id, x,
+                              y, z, ux, uy, uz, w)                                           */
     BF_DIAG_COUNTS = 2,    /* 4 int64: live electrons, live ions, slots e-, slots ions     */
     BF_DIAG_STATION = 3,   /* arg = station: int64 count then count x 7 doubles (t_lab, Ex,
                               Ey, Ez, Bx, By, Bz in the lab frame)                           */
     BF_DIAG_ENERGY = 4,    /* 3 doubles: field energy E, field energy B, kinetic energy     */
-    BF_DIAG_GAUSS = 5,     /* stored_z x stored_x doubles: div E - F[rho] on the nodes      */
+    BF_DIAG_GAUSS = 5,     /* stored_z x stored_x doubles: div E - F[rho] on the nodes (2D) */
     BF_DIAG_INFO = 6,      /* bf_info                                                       */
-    BF_DIAG_ANTENNA = 7,   /* nx doubles: transverse positions of the moving antenna sheet  */
+    BF_DIAG_ANTENNA = 7,   /* nx doubles (3D: nx x ny): x of the moving antenna particles   */
     BF_DIAG_TIMERS = 8     /* BF_PHASE_COUNT x 2 doubles: accumulated ms and launches per
                               phase since the last call (phase_timers = 1); arg != 0 resets */
 };
@@ -193,11 +200,14 @@ enum {
 
 /* field ids (logical layout [stored_z][stored_x], x fastest).  J_x, J_y, J_z are the current
    Ampere used (filtered when a filter is on); J_xr, J_yr, J_zr the raw deposited current of
-   the last step, before the filter. */
+   the last step, before the filter.  B_yx, E_yx are the 2D PML split parts; in 3D every
+   component has one, E_xs .. B_zs (the part along the axis cyclically next to the
+   component). */
 enum {
     BF_F_EX = 0, BF_F_EY, BF_F_EZ, BF_F_BX, BF_F_BY, BF_F_BZ, BF_F_JX, BF_F_JY, BF_F_JZ,
     BF_F_EXO, BF_F_EYO, BF_F_EZO, BF_F_EXB, BF_F_EYB, BF_F_EZB, BF_F_BYX, BF_F_EYX,
-    BF_F_BXO, BF_F_BYO, BF_F_BZO, BF_F_JXR, BF_F_JYR, BF_F_JZR, BF_F_COUNT
+    BF_F_BXO, BF_F_BYO, BF_F_BZO, BF_F_JXR, BF_F_JYR, BF_F_JZR,
+    BF_F_EXS, BF_F_EYS, BF_F_EZS, BF_F_BXS, BF_F_BYS, BF_F_BZS, BF_F_COUNT
 };
 
 typedef struct {
@@ -208,6 +218,7 @@ typedef struct {
     double time;
     int64_t shift, next_row;
     int32_t tile_x, tile_z, ntiles, sort_every;
+    int32_t dim, stored_y, pml_y, reserved;   /* 3D: stored y extent and its PML depth      */
 } bf_info;
 
 /* Synchronises; copies the requested diagnostic (FP64, host order described above) into

@@ -16,9 +16,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbfpic.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 FIELDS = ["Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "Exo", "Eyo", "Ezo",
-          "Exb", "Eyb", "Ezb", "Byx", "Eyx", "Bxo", "Byo", "Bzo", "Jxr", "Jyr", "Jzr"]
+          "Exb", "Eyb", "Ezb", "Byx", "Eyx", "Bxo", "Byo", "Bzo", "Jxr", "Jyr", "Jzr",
+          "Exs", "Eys", "Ezs", "Bxs", "Bys", "Bzs"]
 FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 DIAG_FIELD, DIAG_PARTICLES, DIAG_COUNTS, DIAG_STATION, DIAG_ENERGY, DIAG_GAUSS, DIAG_INFO, \
     DIAG_ANTENNA, DIAG_TIMERS = range(9)
@@ -88,11 +89,12 @@ class bf_info(C.Structure):
                 ("stored_z", C.c_int32), ("pml_x", C.c_int32), ("pml_z", C.c_int32),
                 ("step", C.c_int64), ("time", C.c_double), ("shift", C.c_int64),
                 ("next_row", C.c_int64), ("tile_x", C.c_int32), ("tile_z", C.c_int32),
-                ("ntiles", C.c_int32), ("sort_every", C.c_int32)]
+                ("ntiles", C.c_int32), ("sort_every", C.c_int32), ("dim", C.c_int32),
+                ("stored_y", C.c_int32), ("pml_y", C.c_int32), ("reserved", C.c_int32)]
 
 
 EXPORTS = ["bf_query_buffers", "bf_create", "bf_init_plasma", "bf_init_laser", "bf_add_station",
-           "bf_load_electrons", "bf_step", "bf_diagnose", "bf_set_field", "bf_sync_status",
+           "bf_load_electrons", "bf_load_electrons3", "bf_step", "bf_diagnose", "bf_set_field", "bf_sync_status",
            "bf_get_state", "bf_set_state", "bf_status_string", "bf_last_error", "bf_destroy",
            "bf_set_learned_filter", "bf_lf_work_bytes", "bf_lf_apply", "bf_lf_train_step",
            "bf_batch_work_bytes", "bf_batch_create", "bf_batch_step", "bf_batch_destroy"]
@@ -120,6 +122,7 @@ def lib(path: str = LIB_PATH):
     L.bf_init_laser.argtypes = [P, C.POINTER(bf_laser)]
     L.bf_add_station.argtypes = [P, C.POINTER(bf_station), C.POINTER(C.c_int)]
     L.bf_load_electrons.argtypes = [P, C.c_int64, C.POINTER(C.c_uint32), D, D, D, D, D, D]
+    L.bf_load_electrons3.argtypes = [P, C.c_int64, C.POINTER(C.c_uint32), D, D, D, D, D, D, D]
     L.bf_step.argtypes = [P, C.c_int]
     L.bf_diagnose.argtypes = [P, C.c_int, C.c_int, P, C.c_size_t]
     L.bf_set_field.argtypes = [P, C.c_int, D, C.c_size_t]
@@ -190,9 +193,13 @@ def make_config(cfg: dict, capacity: int, stations: int = 0, station_capacity: i
     c = bf_config()
     c.abi_version = ABI_VERSION
     c.struct_size = C.sizeof(bf_config)
-    c.dim = 2
-    c.nx, c.ny, c.nz = cfg["nx"], 1, cfg["nz"]
-    c.dx_um, c.dy_um, c.dz_um = cfg["dx_um"], cfg["dx_um"], cfg["dz_um"]
+    c.dim = int(cfg.get("dim", 2))
+    if c.dim == 3:
+        c.nx, c.ny, c.nz = cfg["nx"], cfg["ny"], cfg["nz"]
+        c.dx_um, c.dy_um, c.dz_um = cfg["dx_um"], cfg["dy_um"], cfg["dz_um"]
+    else:
+        c.nx, c.ny, c.nz = cfg["nx"], 1, cfg["nz"]
+        c.dx_um, c.dy_um, c.dz_um = cfg["dx_um"], cfg["dx_um"], cfg["dz_um"]
     c.real_bytes = 4 if cfg.get("real", "f32") == "f32" else 8
     c.shape_order = 3
     c.ck_alpha, c.ck_beta, c.ck_gamma = cfg["ck_alpha"], cfg["ck_beta"], cfg["ck_gamma"]
@@ -202,7 +209,8 @@ def make_config(cfg: dict, capacity: int, stations: int = 0, station_capacity: i
     c.filter_compensate = cfg["filter_compensate"]
     c.filter_kind = cfg.get("filter_kind", FILTER_BILINEAR)
     c.pml_cells = cfg["pml_cells"]
-    c.periodic_mask = (1 if cfg.get("periodic_x") else 0) | (4 if cfg.get("periodic_z") else 0)
+    c.periodic_mask = ((1 if cfg.get("periodic_x") else 0) | (2 if cfg.get("periodic_y") else 0)
+                       | (4 if cfg.get("periodic_z") else 0))
     c.gamma_boost = cfg["gamma_boost"]
     c.moving_window = cfg["moving_window"]
     c.particle_capacity = int(capacity)
@@ -216,7 +224,8 @@ def make_config(cfg: dict, capacity: int, stations: int = 0, station_capacity: i
 
 
 def default_capacity(cfg: dict, ppc: int) -> int:
-    return int(cfg["nx"] * (cfg["nz"] + 8) * max(ppc, 1) * 1.15) + 4096
+    ny = cfg["ny"] if cfg.get("dim", 2) == 3 else 1
+    return int(cfg["nx"] * ny * (cfg["nz"] + 8) * max(ppc, 1) * 1.15) + 4096
 
 
 class Sim:
@@ -245,7 +254,9 @@ class Sim:
             bindings.append((name, t.data_ptr(), t.numel()))
         self.handle = bf_create(self.cfg, bindings, self.stream.cuda_stream)
         info = self.info()
-        self.shape = (info["stored_z"], info["stored_x"])
+        self.dim = int(config.get("dim", 2))
+        self.shape = ((info["stored_z"], info["stored_y"], info["stored_x"]) if self.dim == 3
+                      else (info["stored_z"], info["stored_x"]))
 
     # ---- lifecycle --------------------------------------------------------------------
     def close(self):
@@ -288,9 +299,14 @@ class Sim:
 
     def load_electrons(self, p: dict):
         n = len(p["x"])
-        arr = {k: np.ascontiguousarray(p[k], dtype=np.float64) for k in ("x", "z", "ux", "uy", "uz", "w")}
-        ids = np.ascontiguousarray(p.get("id", np.arange(n)), dtype=np.uint32)
         dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+        ids = np.ascontiguousarray(p.get("id", np.arange(n)), dtype=np.uint32)
+        if self.dim == 3:
+            a3 = {k: np.ascontiguousarray(p[k], dtype=np.float64) for k in ("x", "y", "z", "ux", "uy", "uz", "w")}
+            self._ck(lib().bf_load_electrons3(self.handle, n, ids.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                              *[dp(a3[k]) for k in ("x", "y", "z", "ux", "uy", "uz", "w")]))
+            return
+        arr = {k: np.ascontiguousarray(p[k], dtype=np.float64) for k in ("x", "z", "ux", "uy", "uz", "w")}
         self._ck(lib().bf_load_electrons(self.handle, n, ids.ctypes.data_as(C.POINTER(C.c_uint32)),
                                          dp(arr["x"]), dp(arr["z"]), dp(arr["ux"]), dp(arr["uy"]),
                                          dp(arr["uz"]), dp(arr["w"])))
@@ -325,9 +341,12 @@ class Sim:
 
     def particles(self, species: int = 0) -> dict:
         n = int(self.counts()[species])
-        out = self._diag(DIAG_PARTICLES, species, np.zeros((7, max(n, 1))))
-        out = out.reshape(7, -1)[:, :n] if n > 0 else np.zeros((7, 0))
-        d = {k: out[q].copy() for q, k in enumerate(["id", "x", "z", "ux", "uy", "uz", "w"])}
+        keys = (["id", "x", "y", "z", "ux", "uy", "uz", "w"] if self.dim == 3
+                else ["id", "x", "z", "ux", "uy", "uz", "w"])
+        m = len(keys)
+        out = self._diag(DIAG_PARTICLES, species, np.zeros((m, max(n, 1))))
+        out = out.reshape(m, -1)[:, :n] if n > 0 else np.zeros((m, 0))
+        d = {k: out[q].copy() for q, k in enumerate(keys)}
         d["id"] = d["id"].astype(np.uint32)
         return d
 
@@ -349,7 +368,8 @@ class Sim:
         return {p: (out[2 * q], out[2 * q + 1]) for q, p in enumerate(PHASES)}
 
     def antenna(self) -> np.ndarray:
-        return self._diag(DIAG_ANTENNA, 0, np.zeros(self.config["nx"]))
+        n = self.config["nx"] * (self.config["ny"] if self.dim == 3 else 1)
+        return self._diag(DIAG_ANTENNA, 0, np.zeros(n))
 
     def get_state(self) -> bf_state:
         st = bf_state()

@@ -19,6 +19,7 @@
 #include "bf_kernels.h"
 #include "bf_lfilter.h"
 #include "bf_batch.h"
+#include "bf_kernels3.h"
 
 using namespace bf;
 
@@ -158,8 +159,14 @@ bf_status validate(const bf_config* c)
 {
     if (!c) return BF_EINVAL;
     if (c->abi_version != BF_ABI_VERSION || c->struct_size != sizeof(bf_config)) return BF_EINVAL;
-    if (c->dim != 2) return BF_EUNSUPPORTED;
+    if (c->dim != 2 && c->dim != 3) return BF_EUNSUPPORTED;
     if (c->nx <= 0 || c->nz <= 0 || c->dx_um <= 0 || c->dz_um <= 0) return BF_EINVAL;
+    if (c->dim == 3) {
+        if (c->ny <= 0 || c->dy_um <= 0) return BF_EINVAL;
+        if (c->filter_kind != BF_FILTER_BILINEAR) return BF_EUNSUPPORTED;
+        if (((c->periodic_mask >> 1) & 1) == 0 && c->pml_cells < 4) return BF_EINVAL;
+        if ((int64_t)c->nx * c->ny > (1 << 24)) return BF_EINVAL;
+    }
     if (c->real_bytes != 4 && c->real_bytes != 8) return BF_EINVAL;
     if (c->shape_order != 3) return BF_EUNSUPPORTED;
     if (c->friedman_theta < 0 || c->friedman_theta > 1) return BF_EINVAL;
@@ -186,9 +193,13 @@ const char* kNames[] = {"fields", "electrons0", "electrons1", "ions0", "ions1", 
 
 }  // namespace
 
+struct Sim3;
+void sim3_free(Sim3* d);
+
 struct bf_sim {
     bf_config cfg;
     Layout L;
+    Sim3* d3 = nullptr;   // the 3D run state (dim == 3)
     hipStream_t stream = nullptr;
     void* buf[6] = {};
     Geo g;
@@ -214,6 +225,7 @@ struct bf_sim {
 
     ~bf_sim()
     {
+        sim3_free(d3);
         for (auto& m : marks) { ev_pool.push_back(m.a); ev_pool.push_back(m.b); }
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     }
@@ -758,6 +770,587 @@ bf_status step_impl(bf_sim* s, int nsteps)
 // C ABI
 // ======================================================================================
 
+// ---- 3D runs -----------------------------------------------------------------------------------
+// The same C ABI drives the 3D step (bf_config.dim == 3): fields [z][y][x] with a ring of z
+// planes, SoA particles with x, y, z, and the 3D kernels of bf_sim3.hip.  Particles live in one
+// of two copies; every sort_every steps the live ones are compacted into the other copy.
+
+struct Sim3 {
+    bf3::G3 g{};
+    size_t fa = 0, fa8 = 0, fields_bytes = 0;   // bytes per array (run's type, FP64)
+    size_t e_off[8] = {}, e_bytes = 0, i_off[5] = {}, i_bytes = 0;
+    size_t w_status = 0, w_nused = 0, w_cnt = 0, w_pml = 0, w_ant = 0, w_st_z = 0, w_st_rec = 0, w_st_cnt = 0,
+           w_bytes = 0;
+    int64_t cap = 0;
+    int nst_max = 0, stcap = 1, p_cur = 0, since_compact = 0;
+    int64_t ne = 0, ni = 0;   // slots in use (host mirror of the device counters)
+    int na = 0;
+};
+
+void sim3_free(Sim3* d) { delete d; }
+
+namespace {
+
+// arrays in the run's type, then the three FP64 current accumulators (ids A3_J + c)
+enum { A3_E = 0, A3_EO = 3, A3_EB = 6, A3_B = 9, A3_BO = 12, A3_JG = 15, A3_JF = 18, A3_SE = 21, A3_SB = 24,
+       A3_T = 27, A3_COUNT = 30, A3_J = 100 };
+
+double cfl3d(double a, double b, double g, const double d[3], double theta)
+{
+    double best = 0.0;
+    for (int v = 1; v < 8; v++) {
+        double s[3], c[3];
+        for (int k = 0; k < 3; k++) { s[k] = (v >> k) & 1 ? 1.0 : 0.0; c[k] = 1.0 - 2.0 * s[k]; }
+        double rhs = 0.0;
+        for (int k = 0; k < 3; k++) {
+            const double ck = c[(k + 1) % 3], cl = c[(k + 2) % 3];
+            rhs += (a + 2.0 * b * (ck + cl) + 4.0 * g * ck * cl) * s[k] / (d[k] * d[k]);
+        }
+        best = std::max(best, rhs);
+    }
+    return std::sqrt((2.0 + theta) / (2.0 + 3.0 * theta)) / std::sqrt(best);
+}
+
+void layout3(const bf_config* c, Sim3* L)
+{
+    const int N[3] = {c->nx, c->ny, c->nz};
+    const double d[3] = {c->dx_um, c->dy_um, c->dz_um};
+    const size_t real = c->real_bytes;
+    for (int a = 0; a < 3; a++) {
+        L->g.N[a] = N[a];
+        L->g.per[a] = (c->periodic_mask >> a) & 1;
+        L->g.P[a] = L->g.per[a] ? 0 : c->pml_cells;
+        L->g.S[a] = L->g.per[a] ? N[a] : N[a] + 2 * L->g.P[a] + 1;
+        L->g.d[a] = d[a];
+    }
+    L->g.pitch = (long)align_up((size_t)L->g.S[0], 256 / real);
+    L->g.plane = L->g.pitch * L->g.S[1];
+    L->g.zoff = 0;
+    L->fa = align_up((size_t)L->g.plane * L->g.S[2] * real, 256);
+    L->fa8 = align_up((size_t)L->g.plane * L->g.S[2] * 8, 256);
+    L->fields_bytes = L->fa * A3_COUNT + 3 * L->fa8;
+    L->cap = std::max<int64_t>(c->particle_capacity, 1);
+    size_t o = 0;
+    const size_t esz[8] = {8, 8, 8, real, real, real, real, 4};
+    for (int k = 0; k < 8; k++) { L->e_off[k] = o; o = align_up(o + esz[k] * L->cap, 256); }
+    L->e_bytes = std::max<size_t>(o, 256);
+    o = 0;
+    const size_t isz[5] = {8, 8, 8, real, 4};
+    for (int k = 0; k < 5; k++) { L->i_off[k] = o; o = align_up(o + isz[k] * L->cap, 256); }
+    L->i_bytes = std::max<size_t>(o, 256);
+    L->nst_max = std::max(c->max_stations, 0);
+    L->stcap = std::max(c->station_capacity, 1);
+    o = 0;
+    auto take = [&](size_t b) { size_t r = o; o = align_up(o + b, 256); return r; };
+    L->w_status = take(16);
+    L->w_nused = take(16);
+    L->w_cnt = take(16);
+    L->w_pml = take(sizeof(double) * 3 * 2 * 3 * (size_t)(L->g.S[0] + L->g.S[1] + L->g.S[2]));
+    L->w_ant = take(sizeof(double) * 3 * (size_t)N[0] * N[1]);
+    L->w_st_z = take(sizeof(double) * std::max(L->nst_max, 1));
+    L->w_st_rec = take(sizeof(double) * 7 * (size_t)std::max(L->nst_max, 1) * L->stcap);
+    L->w_st_cnt = take(sizeof(int) * std::max(L->nst_max, 1));
+    L->w_bytes = o;
+}
+
+void sizes3(const Sim3& L, size_t out[6])
+{
+    out[0] = L.fields_bytes;
+    out[1] = out[2] = L.e_bytes;
+    out[3] = out[4] = L.i_bytes;
+    out[5] = L.w_bytes;
+}
+
+template <typename T> T* w3(const bf_sim* s, size_t off) { return reinterpret_cast<T*>((char*)s->buf[5] + off); }
+
+template <typename R>
+R* arr3(const bf_sim* s, int a) { return reinterpret_cast<R*>((char*)s->buf[0] + s->d3->fa * a); }
+
+double* jacc3(const bf_sim* s, int c)
+{
+    return reinterpret_cast<double*>((char*)s->buf[0] + s->d3->fa * A3_COUNT + s->d3->fa8 * c);
+}
+
+template <typename R>
+bf3::F3<R> fields3(const bf_sim* s)
+{
+    bf3::F3<R> f;
+    for (int c = 0; c < 3; c++) {
+        f.E[c] = arr3<R>(s, A3_E + c); f.Eo[c] = arr3<R>(s, A3_EO + c); f.Eb[c] = arr3<R>(s, A3_EB + c);
+        f.B[c] = arr3<R>(s, A3_B + c); f.Bo[c] = arr3<R>(s, A3_BO + c); f.J[c] = jacc3(s, c);
+        f.Jf[c] = arr3<R>(s, A3_JF + c); f.Jg[c] = arr3<R>(s, A3_JG + c);
+        f.SE[c] = arr3<R>(s, A3_SE + c); f.SB[c] = arr3<R>(s, A3_SB + c);
+        f.T[c] = arr3<R>(s, A3_T + c);
+    }
+    return f;
+}
+
+template <typename R>
+bf3::E3<R> electrons3(const bf_sim* s, int copy)
+{
+    char* b = (char*)s->buf[1 + copy];
+    const Sim3& L = *s->d3;
+    bf3::E3<R> e;
+    e.x = (double*)(b + L.e_off[0]); e.y = (double*)(b + L.e_off[1]); e.z = (double*)(b + L.e_off[2]);
+    e.ux = (R*)(b + L.e_off[3]); e.uy = (R*)(b + L.e_off[4]); e.uz = (R*)(b + L.e_off[5]);
+    e.w = (R*)(b + L.e_off[6]); e.id = (uint32_t*)(b + L.e_off[7]);
+    return e;
+}
+
+template <typename R>
+bf3::I3<R> ions3(const bf_sim* s, int copy)
+{
+    char* b = (char*)s->buf[3 + copy];
+    const Sim3& L = *s->d3;
+    bf3::I3<R> ion;
+    ion.x = (double*)(b + L.i_off[0]); ion.y = (double*)(b + L.i_off[1]); ion.z0 = (double*)(b + L.i_off[2]);
+    ion.w = (R*)(b + L.i_off[3]); ion.id = (uint32_t*)(b + L.i_off[4]);
+    return ion;
+}
+
+bf3::Pml3 pml3(const bf_sim* s)
+{
+    const Sim3& L = *s->d3;
+    bf3::Pml3 p;
+    double* base = w3<double>(s, L.w_pml);
+    size_t o = 0;
+    for (int a = 0; a < 3; a++)
+        for (int h = 0; h < 2; h++) {
+            p.sig[a][h] = base + o; o += L.g.S[a];
+            p.xi[a][h] = base + o; o += L.g.S[a];
+            p.c[a][h] = base + o; o += L.g.S[a];
+        }
+    return p;
+}
+
+hipError_t upload_pml3(bf_sim* s)
+{
+    const Sim3& L = *s->d3;
+    std::vector<double> t;
+    for (int a = 0; a < 3; a++)
+        for (int h = 0; h < 2; h++) {
+            std::vector<double> sg(L.g.S[a]), xi(L.g.S[a]), c(L.g.S[a]);
+            for (int i = 0; i < L.g.S[a]; i++) {
+                const double p = (double)(i - L.g.P[a]) + 0.5 * h;
+                sg[i] = L.g.per[a] ? 0.0 : sigma_at(p, L.g.N[a], L.g.P[a], L.g.d[a]);
+                xi[i] = 1.0;
+                c[i] = s->dt;
+                if (sg[i] != 0.0) { xi[i] = std::exp(-sg[i] * s->dt); c[i] = (1.0 - xi[i]) / sg[i]; }
+            }
+            t.insert(t.end(), sg.begin(), sg.end());
+            t.insert(t.end(), xi.begin(), xi.end());
+            t.insert(t.end(), c.begin(), c.end());
+        }
+    return hipMemcpy(w3<char>(s, L.w_pml), t.data(), t.size() * 8, hipMemcpyHostToDevice);
+}
+
+bf_status create3(const bf_config* cfg, const bf_buffer_binding* b, int n, void* stream, bf_sim** out)
+{
+    bf_sim* s = new bf_sim();
+    s->cfg = *cfg;
+    s->d3 = new Sim3();
+    layout3(cfg, s->d3);
+    size_t sizes[6];
+    sizes3(*s->d3, sizes);
+    for (int k = 0; k < 6; k++) {
+        for (int q = 0; q < n; q++)
+            if (b[q].name && std::strcmp(b[q].name, kNames[k]) == 0) {
+                if (b[q].bytes < sizes[k] || !b[q].ptr || ((uintptr_t)b[q].ptr & 255u)) { delete s; return BF_EINVAL; }
+                s->buf[k] = b[q].ptr;
+            }
+        if (!s->buf[k]) { delete s; return BF_EINVAL; }
+    }
+    s->stream = (hipStream_t)stream;
+    s->gamma = cfg->gamma_boost;
+    s->beta = std::sqrt(1.0 - 1.0 / (s->gamma * s->gamma));
+    s->theta = cfg->friedman_theta;
+    const double d[3] = {cfg->dx_um, cfg->dy_um, cfg->dz_um};
+    s->dt_crit = cfl3d(cfg->ck_alpha, cfg->ck_beta, cfg->ck_gamma, d, s->theta);
+    s->dt = cfg->cfl_fraction * s->dt_crit;
+    s->sort_every = cfg->sort_every > 0 ? cfg->sort_every : 20;
+    update_window_speed(s);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 6 && e == hipSuccess; k++) e = hipMemsetAsync(s->buf[k], 0, sizes[k], s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = upload_pml3(s);
+    if (e != hipSuccess) { delete s; return BF_EDEVICE; }
+    *out = s;
+    return BF_OK;
+}
+
+template <typename R>
+hipError_t inject3(bf_sim* s, int64_t nrows)
+{
+    Sim3& L = *s->d3;
+    if (nrows <= 0) return hipSuccess;
+    bf3::Inject3 ip;
+    ip.row0 = s->next_row;
+    ip.nrows = (int)nrows;
+    ip.ppc = s->plasma.ppc;
+    ip.ion_mode = s->plasma.ion_mode;
+    ip.cap = L.cap;
+    ip.seed = s->cfg.seed;
+    ip.gamma = s->gamma;
+    ip.beta = s->beta;
+    ip.t = s->t;
+    ip.dx = s->cfg.dx_um;
+    ip.dy = s->cfg.dy_um;
+    ip.dz = s->cfg.dz_um;
+    ip.n0 = s->n0;
+    ip.ramp_start = s->plasma.start_um;
+    ip.ramp_len = s->plasma.ramp_um;
+    ip.uz0 = -s->gamma * s->beta;
+    ip.shift = (double)s->shift;
+    int* nu = w3<int>(s, L.w_nused);
+    bf3::launch3_inject<R>(L.g, electrons3<R>(s, L.p_cur), ions3<R>(s, L.p_cur), nu, nu + 1, ip,
+                           w3<int>(s, L.w_status), s->stream);
+    const int64_t add = (int64_t)L.g.N[0] * L.g.N[1] * s->plasma.ppc * nrows;
+    L.ne = std::min(L.ne + add, L.cap);
+    if (s->plasma.ion_mode) L.ni = std::min(L.ni + add, L.cap);
+    s->next_row += nrows;
+    return hipGetLastError();
+}
+
+// live particles into the other copy; the device counts become the new slot counts
+template <typename R>
+hipError_t compact3(bf_sim* s)
+{
+    Sim3& L = *s->d3;
+    const int a = L.p_cur, b = 1 - a;
+    int* cnt = w3<int>(s, L.w_cnt);
+    bf3::launch3_compact_e<R>(electrons3<R>(s, a), electrons3<R>(s, b), (int)L.ne, cnt, s->stream);
+    bf3::launch3_compact_i<R>(ions3<R>(s, a), ions3<R>(s, b), (int)L.ni, cnt + 1, s->stream);
+    int h[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(h, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return e;
+    L.ne = h[0];
+    L.ni = s->plasma.ion_mode ? h[1] : 0;
+    L.p_cur = b;
+    L.since_compact = 0;
+    int nu[2] = {h[0], h[1]};
+    return hipMemcpy(w3<int>(s, L.w_nused), nu, sizeof nu, hipMemcpyHostToDevice);
+}
+
+template <typename R>
+bf_status step3(bf_sim* s, int nsteps)
+{
+    Sim3& L = *s->d3;
+    const double d[3] = {s->cfg.dx_um, s->cfg.dy_um, s->cfg.dz_um};
+    const double ck[3] = {s->cfg.ck_alpha, s->cfg.ck_beta, s->cfg.ck_gamma};
+    const bf3::Pml3 pml = pml3(s);
+    for (int it = 0; it < nsteps; it++) {
+        const bf3::F3<R> f = fields3<R>(s);
+        const bf3::G3 g = L.g;
+        hipEvent_t ev = s->tick();
+        if (s->theta > 0.0) bf3::launch3_friedman<R>(g, f, s->theta, s->stream);
+        bf3::launch3_faraday<R>(g, f, pml, ck, s->theta, s->dt, s->stream);
+        bf3::launch3_stations<R>(g, f, w3<double>(s, L.w_st_z), s->nst, s->gamma, s->beta, s->t, (double)s->shift,
+                                 w3<double>(s, L.w_st_rec), w3<int>(s, L.w_st_cnt), L.stcap, s->stream);
+        s->tock(ev, BF_PHASE_FARADAY);
+        // the window shift at the end of this step (particles are rebased in the push)
+        const double t1 = (double)(s->step + 1) * s->dt;
+        int64_t sn = s->shift;
+        if (s->cfg.moving_window && !L.g.per[2]) sn = (int64_t)std::trunc(s->vw * t1 / d[2]);
+        const int dsh = (int)(sn - s->shift);
+        bf3::Push3 pp;
+        pp.dt = s->dt;
+        for (int a = 0; a < 3; a++) {
+            pp.dtd[a] = s->dt / d[a];
+            pp.jk[a] = 1.0 / (d[(a + 1) % 3] * d[(a + 2) % 3] * s->dt);
+        }
+        pp.shift = (double)dsh;
+        ev = s->tick();
+        bf3::launch3_zero_j<R>(g, f, s->stream);
+        bf3::launch3_push<R>(g, f, electrons3<R>(s, L.p_cur), (int)L.ne, pp, w3<int>(s, L.w_status), s->stream);
+        s->tock(ev, BF_PHASE_PUSH);
+        ev = s->tick();
+        if (s->have_plasma && s->plasma.ion_mode == 1)
+            bf3::launch3_ions<R>(g, f, ions3<R>(s, L.p_cur), (int)L.ni, s->beta * s->t / d[2] + (double)s->shift,
+                                 s->beta * t1 / d[2] + (double)s->shift, pp, s->stream);
+        s->tock(ev, BF_PHASE_IONS);
+        ev = s->tick();
+        if (s->have_laser) {
+            const double za = s->za_lab / s->gamma - s->beta * s->t - (double)s->shift * d[2];
+            const double zb = s->za_lab / s->gamma - s->beta * t1 - (double)s->shift * d[2];
+            if (za >= 0.0 && za < L.g.N[2] * d[2]) {
+                bf3::Antenna3 a;
+                a.n = L.na;
+                a.za = za / d[2];
+                a.zb = zb / d[2];
+                a.tm = s->t + 0.5 * s->dt;
+                a.e0g = s->e0 / s->gamma;
+                a.w0 = s->w0;
+                a.xc = 0.5 * L.g.N[0] * d[0];
+                a.yc = 0.5 * L.g.N[1] * d[1];
+                a.gamma = s->gamma;
+                a.t0 = s->t0;
+                a.sig_t = s->sig_t;
+                a.omega = s->omega;
+                a.aw = s->aw;
+                double* ant = w3<double>(s, L.w_ant);
+                const size_t na = (size_t)L.na;
+                bf3::launch3_antenna<R>(g, f, ant, ant + na, ant + 2 * na, a, pp, s->stream);
+            }
+        }
+        s->tock(ev, BF_PHASE_ANTENNA);
+        ev = s->tick();
+        const R* jout[3];
+        bf3::launch3_filter<R>(g, f, s->cfg.filter_npass, s->cfg.filter_compensate, jout, s->stream);
+        s->tock(ev, BF_PHASE_FILTER);
+        ev = s->tick();
+        bf3::launch3_ampere<R>(g, f, jout, pml, s->dt, s->stream);
+        s->tock(ev, BF_PHASE_AMPERE);
+        ev = s->tick();
+        s->step++;
+        s->t = (double)s->step * s->dt;
+        if (dsh != 0) {
+            int z = (L.g.zoff + dsh) % L.g.S[2];
+            if (z < 0) z += L.g.S[2];
+            L.g.zoff = z;
+            s->shift = sn;
+            bf3::launch3_window<R>(L.g, f, pml, dsh, s->stream);
+        }
+        hipError_t e = inject3<R>(s, rows_entering(s));
+        s->tock(ev, BF_PHASE_WINDOW);
+        if (e != hipSuccess) return hip_check(s, e, "3D injection");
+        if (++L.since_compact >= s->sort_every && s->have_plasma) {
+            ev = s->tick();
+            e = compact3<R>(s);
+            s->tock(ev, BF_PHASE_SORT);
+            if (e != hipSuccess) return hip_check(s, e, "3D compaction");
+        }
+    }
+    return hip_check(s, hipGetLastError(), "3D step launch");
+}
+
+bf_status init_plasma3(bf_sim* s)
+{
+    hipError_t e = s->cfg.real_bytes == 4 ? inject3<float>(s, rows_entering(s)) : inject3<double>(s, rows_entering(s));
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    return hip_check(s, e, "3D init_plasma");
+}
+
+bf_status init_laser3(bf_sim* s)
+{
+    Sim3& L = *s->d3;
+    L.na = L.g.N[0] * L.g.N[1];
+    s->aw = (2.0 * s->e0 / s->gamma) * s->cfg.dx_um * s->cfg.dy_um / 0.01;
+    std::vector<double> a(3 * (size_t)L.na);
+    for (int q = 0; q < L.na; q++) {
+        a[q] = a[L.na + q] = (q % L.g.N[0]) + 0.5;
+        a[2 * (size_t)L.na + q] = (q / L.g.N[0]) + 0.5;
+    }
+    return hip_check(s, hipMemcpy(w3<double>(s, L.w_ant), a.data(), a.size() * 8, hipMemcpyHostToDevice),
+                     "3D init_laser");
+}
+
+// field id -> array (-1: none)
+int array3_of(int id)
+{
+    switch (id) {
+    case BF_F_EX: case BF_F_EY: case BF_F_EZ: return A3_E + (id - BF_F_EX);
+    case BF_F_EXO: case BF_F_EYO: case BF_F_EZO: return A3_EO + (id - BF_F_EXO);
+    case BF_F_EXB: case BF_F_EYB: case BF_F_EZB: return A3_EB + (id - BF_F_EXB);
+    case BF_F_BX: case BF_F_BY: case BF_F_BZ: return A3_B + (id - BF_F_BX);
+    case BF_F_BXO: case BF_F_BYO: case BF_F_BZO: return A3_BO + (id - BF_F_BXO);
+    case BF_F_JXR: case BF_F_JYR: case BF_F_JZR: return A3_J + (id - BF_F_JXR);
+    case BF_F_EXS: case BF_F_EYS: case BF_F_EZS: return A3_SE + (id - BF_F_EXS);
+    case BF_F_BXS: case BF_F_BYS: case BF_F_BZS: return A3_SB + (id - BF_F_BXS);
+    default: return -1;
+    }
+}
+
+// the filtered current: the filter's first operation writes Jf, the next ones alternate
+int filtered3(const bf_config& c, int comp)
+{
+    const int np = c.filter_npass + (c.filter_compensate ? 1 : 0);
+    const int ops = np > 0 ? 3 * np : 1;
+    return ((ops & 1) ? A3_JF : A3_JG) + comp;
+}
+
+bf_status read_field3(bf_sim* s, int a, double* out)
+{
+    const Sim3& L = *s->d3;
+    const bool acc = a >= A3_J;
+    const size_t bytes = acc ? L.fa8 : L.fa;
+    std::vector<char> raw(bytes);
+    const char* src = acc ? (const char*)jacc3(s, a - A3_J) : (const char*)s->buf[0] + L.fa * a;
+    hipError_t e = hipMemcpy(raw.data(), src, bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_check(s, e, "3D read field");
+    const bool f32 = s->cfg.real_bytes == 4 && !acc;
+    for (int k = 0; k < L.g.S[2]; k++) {
+        const int pk = (k + L.g.zoff) % L.g.S[2];
+        for (int j = 0; j < L.g.S[1]; j++)
+            for (int i = 0; i < L.g.S[0]; i++) {
+                const size_t o = (size_t)pk * L.g.plane + (size_t)j * L.g.pitch + i;
+                out[((size_t)k * L.g.S[1] + j) * L.g.S[0] + i] =
+                    f32 ? (double)((float*)raw.data())[o] : ((double*)raw.data())[o];
+            }
+    }
+    return BF_OK;
+}
+
+bf_status write_field3(bf_sim* s, int a, const double* in)
+{
+    const Sim3& L = *s->d3;
+    const bool acc = a >= A3_J;
+    const size_t bytes = acc ? L.fa8 : L.fa;
+    std::vector<char> raw(bytes, 0);
+    const bool f32 = s->cfg.real_bytes == 4 && !acc;
+    for (int k = 0; k < L.g.S[2]; k++) {
+        const int pk = (k + L.g.zoff) % L.g.S[2];
+        for (int j = 0; j < L.g.S[1]; j++)
+            for (int i = 0; i < L.g.S[0]; i++) {
+                const size_t o = (size_t)pk * L.g.plane + (size_t)j * L.g.pitch + i;
+                const double v = in[((size_t)k * L.g.S[1] + j) * L.g.S[0] + i];
+                if (f32) ((float*)raw.data())[o] = (float)v;
+                else ((double*)raw.data())[o] = v;
+            }
+    }
+    char* dst = acc ? (char*)jacc3(s, a - A3_J) : (char*)s->buf[0] + L.fa * a;
+    return hip_check(s, hipMemcpy(dst, raw.data(), bytes, hipMemcpyHostToDevice), "3D write field");
+}
+
+// live particles: 8 columns (id, x, y, z in um, ux, uy, uz, w)
+bf_status read_particles3(bf_sim* s, int species, std::vector<double>* cols, int64_t* nlive)
+{
+    const Sim3& L = *s->d3;
+    const int64_t n = species == 0 ? L.ne : L.ni;
+    const bool f32 = s->cfg.real_bytes == 4;
+    const size_t rb = s->cfg.real_bytes;
+    const char* b = (const char*)s->buf[(species == 0 ? 1 : 3) + L.p_cur];
+    const int ncol = species == 0 ? 8 : 5;
+    std::vector<std::vector<char>> raw(ncol);
+    for (int q = 0; q < ncol; q++) {
+        const size_t off = species == 0 ? L.e_off[q] : L.i_off[q];
+        const size_t sz = q < 3 ? 8 : (q == ncol - 1 ? 4 : rb);
+        raw[q].resize(std::max<int64_t>(n, 1) * sz);
+        if (n > 0) {
+            hipError_t e = hipMemcpy(raw[q].data(), b + off, n * sz, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_check(s, e, "3D read particles");
+        }
+    }
+    auto rv = [&](int q, int64_t p) { return f32 ? (double)((float*)raw[q].data())[p] : ((double*)raw[q].data())[p]; };
+    for (int q = 0; q < 8; q++) cols[q].clear();
+    const double d[3] = {s->cfg.dx_um, s->cfg.dy_um, s->cfg.dz_um};
+    for (int64_t p = 0; p < n; p++) {
+        const double w = species == 0 ? rv(6, p) : rv(3, p);
+        if (w == 0.0) continue;
+        const double* xyz = (const double*)raw[0].data();
+        const double x = xyz[p] * d[0], y = ((const double*)raw[1].data())[p] * d[1];
+        double z = ((const double*)raw[2].data())[p];
+        if (species == 1) z = z - (s->beta * s->t / d[2] + (double)s->shift);
+        cols[0].push_back((double)((const uint32_t*)raw[ncol - 1].data())[p]);
+        cols[1].push_back(x);
+        cols[2].push_back(y);
+        cols[3].push_back(z * d[2]);
+        cols[4].push_back(species == 0 ? rv(3, p) : 0.0);
+        cols[5].push_back(species == 0 ? rv(4, p) : 0.0);
+        cols[6].push_back(species == 0 ? rv(5, p) : -s->gamma * s->beta);
+        cols[7].push_back(w);
+    }
+    *nlive = (int64_t)cols[0].size();
+    return BF_OK;
+}
+
+bf_status diagnose3(bf_sim* s, int kind, int arg, void* host_out, size_t bytes)
+{
+    const Sim3& L = *s->d3;
+    const size_t grid = (size_t)L.g.S[0] * L.g.S[1] * L.g.S[2];
+    switch (kind) {
+    case BF_DIAG_FIELD: {
+        int a = (arg == BF_F_JX || arg == BF_F_JY || arg == BF_F_JZ) ? filtered3(s->cfg, arg - BF_F_JX) : array3_of(arg);
+        if (a < 0) return fail(s, BF_EINVAL, "bad field id");
+        if (bytes < grid * 8) return fail(s, BF_EINVAL, "buffer too small");
+        return read_field3(s, a, (double*)host_out);
+    }
+    case BF_DIAG_COUNTS: {
+        if (bytes < 4 * sizeof(int64_t)) return fail(s, BF_EINVAL, "buffer too small");
+        std::vector<double> cols[8];
+        int64_t ne = 0, ni = 0;
+        bf_status st = read_particles3(s, 0, cols, &ne);
+        if (st == BF_OK && s->have_plasma && s->plasma.ion_mode == 1) st = read_particles3(s, 1, cols, &ni);
+        if (st != BF_OK) return st;
+        int64_t* o = (int64_t*)host_out;
+        o[0] = ne; o[1] = ni; o[2] = L.ne; o[3] = L.ni;
+        return BF_OK;
+    }
+    case BF_DIAG_PARTICLES: {
+        std::vector<double> cols[8];
+        int64_t n = 0;
+        bf_status st = read_particles3(s, arg, cols, &n);
+        if (st != BF_OK) return st;
+        if (bytes < (size_t)n * 8 * 8) return fail(s, BF_EINVAL, "buffer too small");
+        for (int q = 0; q < 8; q++) std::memcpy((double*)host_out + (size_t)q * n, cols[q].data(), n * 8);
+        return BF_OK;
+    }
+    case BF_DIAG_STATION: {
+        if (arg < 0 || arg >= s->nst) return fail(s, BF_EINVAL, "bad station");
+        int cnt = 0;
+        hipError_t e = hipMemcpy(&cnt, w3<int>(s, L.w_st_cnt) + arg, sizeof(int), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_check(s, e, "station");
+        if (bytes < 8 + (size_t)cnt * 7 * 8) return fail(s, BF_EINVAL, "buffer too small");
+        *(int64_t*)host_out = cnt;
+        if (cnt > 0)
+            e = hipMemcpy((char*)host_out + 8, w3<double>(s, L.w_st_rec) + (size_t)arg * L.stcap * 7,
+                          (size_t)cnt * 7 * 8, hipMemcpyDeviceToHost);
+        return hip_check(s, e, "station");
+    }
+    case BF_DIAG_ENERGY: {
+        if (bytes < 3 * 8) return fail(s, BF_EINVAL, "buffer too small");
+        std::vector<double> f(grid);
+        double ue = 0, ub = 0;
+        for (int q = 0; q < 6; q++) {
+            bf_status st = read_field3(s, q < 3 ? A3_E + q : A3_B + q - 3, f.data());
+            if (st != BF_OK) return st;
+            double acc = 0;
+            for (double v : f) acc += v * v;
+            (q < 3 ? ue : ub) += acc;
+        }
+        std::vector<double> cols[8];
+        int64_t n = 0;
+        bf_status st = read_particles3(s, 0, cols, &n);
+        if (st != BF_OK) return st;
+        double k = 0;
+        for (int64_t p = 0; p < n; p++) {
+            const double ux = cols[4][p], uy = cols[5][p], uz = cols[6][p];
+            k += cols[7][p] * (std::sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
+        }
+        const double dv = s->cfg.dx_um * s->cfg.dy_um * s->cfg.dz_um;
+        double* o = (double*)host_out;
+        o[0] = 0.5 * ue * dv; o[1] = 0.5 * ub * dv; o[2] = k;
+        return BF_OK;
+    }
+    case BF_DIAG_INFO: {
+        if (bytes < sizeof(bf_info)) return fail(s, BF_EINVAL, "buffer too small");
+        bf_info* o = (bf_info*)host_out;
+        std::memset(o, 0, sizeof *o);
+        o->dt = s->dt; o->dt_crit = s->dt_crit; o->beta = s->beta; o->gamma = s->gamma;
+        o->v_window = s->vw; o->n0_norm = s->n0; o->e0_norm = s->e0; o->omega = s->omega;
+        o->alpha2 = s->cfg.ck_alpha; o->beta2 = s->cfg.ck_beta; o->antenna_weight = s->aw;
+        o->stored_x = L.g.S[0]; o->stored_z = L.g.S[2]; o->pml_x = L.g.P[0]; o->pml_z = L.g.P[2];
+        o->step = s->step; o->time = s->t; o->shift = s->shift; o->next_row = s->next_row;
+        o->sort_every = s->sort_every;
+        o->dim = 3; o->stored_y = L.g.S[1]; o->pml_y = L.g.P[1];
+        return BF_OK;
+    }
+    case BF_DIAG_ANTENNA: {
+        if (!s->have_laser) return fail(s, BF_EINVAL, "no laser");
+        if (bytes < (size_t)L.na * 8) return fail(s, BF_EINVAL, "buffer too small");
+        std::vector<double> xm(L.na);
+        hipError_t e = hipMemcpy(xm.data(), w3<double>(s, L.w_ant), xm.size() * 8, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_check(s, e, "antenna");
+        for (int q = 0; q < L.na; q++) ((double*)host_out)[q] = xm[q] * s->cfg.dx_um;
+        return BF_OK;
+    }
+    default:
+        return fail(s, BF_EUNSUPPORTED, "diagnostic not available in 3D");
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* bf_status_string(bf_status s)
@@ -782,9 +1375,17 @@ bf_status bf_query_buffers(const bf_config* cfg, bf_buffer_desc* out, int* n_ino
     if (!n_inout) return BF_EINVAL;
     const bf_status v = validate(cfg);
     if (v != BF_OK) return v;
-    Layout L;
-    layout_of(cfg, &L);
-    const size_t sizes[6] = {L.fields_bytes, L.e_bytes, L.e_bytes, L.i_bytes, L.i_bytes, L.w_bytes};
+    size_t sizes[6];
+    if (cfg->dim == 3) {
+        Sim3 L3;
+        layout3(cfg, &L3);
+        sizes3(L3, sizes);
+    } else {
+        Layout L;
+        layout_of(cfg, &L);
+        const size_t s2[6] = {L.fields_bytes, L.e_bytes, L.e_bytes, L.i_bytes, L.i_bytes, L.w_bytes};
+        for (int k = 0; k < 6; k++) sizes[k] = s2[k];
+    }
     const int cap = *n_inout;
     *n_inout = 6;
     if (!out) return BF_OK;
@@ -804,6 +1405,7 @@ bf_status bf_create(const bf_config* cfg, const bf_buffer_binding* b, int n, voi
     *out = nullptr;
     const bf_status v = validate(cfg);
     if (v != BF_OK) return v;
+    if (cfg->dim == 3) return create3(cfg, b, n, stream, out);
     bf_sim* s = new bf_sim();
     s->cfg = *cfg;
     layout_of(cfg, &s->L);
@@ -867,6 +1469,7 @@ bf_status bf_init_plasma(bf_sim* s, const bf_plasma* p)
     s->have_plasma = 1;
     s->next_row = 0;
     update_window_speed(s);
+    if (s->d3) return init_plasma3(s);
     // initial rows: every lattice row inside the window at the current time
     if (s->cfg.real_bytes == 4) {
         inject<float>(s, rows_entering(s));
@@ -890,6 +1493,10 @@ bf_status bf_init_laser(bf_sim* s, const bf_laser* l)
     s->sig_t = l->fwhm_fs * 1e-15 * C_LIGHT * 1e6 / (2.0 * std::sqrt(std::log(2.0)));
     s->t0 = 3.0 * s->sig_t;
     s->za_lab = l->z_antenna_um;
+    if (s->d3) {
+        update_window_speed(s);
+        return init_laser3(s);
+    }
     s->aw = (2.0 * s->e0 / s->gamma) * s->cfg.dx_um / 0.01;  // |v| of the moving sheet <= 0.01 c
     std::vector<double> xm(s->cfg.nx);
     for (int i = 0; i < s->cfg.nx; i++) xm[i] = i + 0.5;
@@ -902,9 +1509,11 @@ bf_status bf_add_station(bf_sim* s, const bf_station* st_, int* id)
 {
     bf_status st = guard(s);
     if (st != BF_OK) return st;
-    if (!st_ || s->nst >= s->L.nst) return fail(s, BF_EINVAL, "no station slot left");
+    const int nmax = s->d3 ? s->d3->nst_max : s->L.nst;
+    if (!st_ || s->nst >= nmax) return fail(s, BF_EINVAL, "no station slot left");
     s->st_z.push_back(st_->z_lab_um);
-    hipError_t e = hipMemcpy(s->w<double>(s->L.w_st_z), s->st_z.data(), s->st_z.size() * 8, hipMemcpyHostToDevice);
+    double* dz = s->d3 ? w3<double>(s, s->d3->w_st_z) : s->w<double>(s->L.w_st_z);
+    hipError_t e = hipMemcpy(dz, s->st_z.data(), s->st_z.size() * 8, hipMemcpyHostToDevice);
     if (id) *id = s->nst;
     s->nst++;
     return hip_check(s, e, "add_station");
@@ -915,6 +1524,7 @@ bf_status bf_load_electrons(bf_sim* s, int64_t n, const uint32_t* id, const doub
 {
     bf_status st = guard(s);
     if (st != BF_OK) return st;
+    if (s->d3) return fail(s, BF_EINVAL, "3D runs load electrons with bf_load_electrons3");
     if (n < 0 || n > s->L.cap || (n > 0 && (!x || !z || !ux || !uy || !uz || !w)))
         return fail(s, BF_EINVAL, "bad particle arrays");
     const bool f32 = s->cfg.real_bytes == 4;
@@ -955,6 +1565,46 @@ bf_status bf_load_electrons(bf_sim* s, int64_t n, const uint32_t* id, const doub
     return hip_check(s, hipStreamSynchronize(s->stream), "load_electrons");
 }
 
+bf_status bf_load_electrons3(bf_sim* s, int64_t n, const uint32_t* id, const double* x, const double* y,
+                             const double* z, const double* ux, const double* uy, const double* uz, const double* w)
+{
+    bf_status st = guard(s);
+    if (st != BF_OK) return st;
+    if (!s->d3) return fail(s, BF_EINVAL, "2D runs load electrons with bf_load_electrons");
+    Sim3& L = *s->d3;
+    if (n < 0 || n > L.cap || (n > 0 && (!x || !y || !z || !ux || !uy || !uz || !w)))
+        return fail(s, BF_EINVAL, "bad particle arrays");
+    const bool f32 = s->cfg.real_bytes == 4;
+    const size_t rb = s->cfg.real_bytes;
+    const double d[3] = {s->cfg.dx_um, s->cfg.dy_um, s->cfg.dz_um};
+    const double* pos[3] = {x, y, z};
+    const double* mom[4] = {ux, uy, uz, w};
+    char* b = (char*)s->buf[1 + L.p_cur];
+    hipError_t e = hipSuccess;
+    std::vector<double> h(n);
+    for (int a = 0; a < 3 && e == hipSuccess; a++) {
+        for (int64_t p = 0; p < n; p++) h[p] = pos[a][p] / d[a];
+        if (n > 0) e = hipMemcpy(b + L.e_off[a], h.data(), n * 8, hipMemcpyHostToDevice);
+    }
+    std::vector<float> hf(n);
+    for (int q = 0; q < 4 && e == hipSuccess; q++) {
+        if (n == 0) break;
+        if (f32) {
+            for (int64_t p = 0; p < n; p++) hf[p] = (float)mom[q][p];
+            e = hipMemcpy(b + L.e_off[3 + q], hf.data(), n * rb, hipMemcpyHostToDevice);
+        } else {
+            e = hipMemcpy(b + L.e_off[3 + q], mom[q], n * rb, hipMemcpyHostToDevice);
+        }
+    }
+    std::vector<uint32_t> hid(n);
+    for (int64_t p = 0; p < n; p++) hid[p] = id ? id[p] : (uint32_t)p;
+    if (e == hipSuccess && n > 0) e = hipMemcpy(b + L.e_off[7], hid.data(), n * 4, hipMemcpyHostToDevice);
+    L.ne = n;
+    int nu[2] = {(int)n, (int)L.ni};
+    if (e == hipSuccess) e = hipMemcpy(w3<int>(s, L.w_nused), nu, sizeof nu, hipMemcpyHostToDevice);
+    return hip_check(s, e, "load_electrons3");
+}
+
 bf_status bf_step(bf_sim* s, int nsteps)
 {
     bf_status st = guard(s);
@@ -962,6 +1612,7 @@ bf_status bf_step(bf_sim* s, int nsteps)
     if (nsteps < 0) return fail(s, BF_EINVAL, "negative step count");
     if (s->cfg.filter_kind == BF_FILTER_LEARNED && !s->have_lf)
         return fail(s, BF_ESTATE, "learned filter selected but its parameters are not loaded");
+    if (s->d3) return s->cfg.real_bytes == 4 ? step3<float>(s, nsteps) : step3<double>(s, nsteps);
     if (s->cfg.real_bytes == 4) st = step_impl<float>(s, nsteps);
     else st = step_impl<double>(s, nsteps);
     hipError_t e = hipGetLastError();
@@ -1102,7 +1753,7 @@ bf_status bf_batch_create(bf_sim* const* sims, int n, void* work, int64_t work_b
     if (!sims || !out || !work || n < 1 || n > 4096) return BF_EINVAL;
     if (work_bytes < bf_batch_work_bytes(n)) return BF_EINVAL;
     for (int q = 0; q < n; q++) {
-        if (!sims[q] || sims[q]->cfg.real_bytes != 4) return BF_EUNSUPPORTED;
+        if (!sims[q] || sims[q]->cfg.real_bytes != 4 || sims[q]->d3) return BF_EUNSUPPORTED;
         if (sims[q]->err != BF_OK) return BF_ESTATE;
         for (int p = 0; p < q; p++)
             if (sims[p] == sims[q]) return BF_EINVAL;
@@ -1170,7 +1821,7 @@ bf_status bf_sync_status(bf_sim* s)
     hipError_t e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return hip_check(s, e, "sync");
     int word = 0;
-    e = hipMemcpy(&word, status_word(s), sizeof(int), hipMemcpyDeviceToHost);
+    e = hipMemcpy(&word, s->d3 ? w3<int>(s, s->d3->w_status) : status_word(s), sizeof(int), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_check(s, e, "sync");
     if (word & ST_CAPACITY) { s->err = BF_ECAPACITY; s->msg = "particle capacity exceeded"; return BF_ECAPACITY; }
     if (word & ST_NONFINITE) { s->err = BF_ENONFINITE; s->msg = "non-finite particle momentum"; return BF_ENONFINITE; }
@@ -1345,6 +1996,7 @@ bf_status bf_diagnose(bf_sim* s, int kind, int arg, void* host_out, size_t bytes
     if (!s || !host_out) return BF_EINVAL;
     hipError_t e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return hip_check(s, e, "diagnose");
+    if (s->d3 && kind != BF_DIAG_TIMERS) return diagnose3(s, kind, arg, host_out, bytes);
     const Layout& L = s->L;
     const size_t grid = (size_t)L.Sx * L.Sz;
     switch (kind) {
@@ -1465,6 +2117,16 @@ bf_status bf_set_field(bf_sim* s, int field, const double* in, size_t bytes)
 {
     bf_status st = guard(s);
     if (st != BF_OK) return st;
+    if (s->d3) {
+        const Sim3& L3 = *s->d3;
+        const int a = (field == BF_F_JX || field == BF_F_JY || field == BF_F_JZ) ? filtered3(s->cfg, field - BF_F_JX)
+                                                                                : array3_of(field);
+        if (a < 0) return fail(s, BF_EINVAL, "bad field id");
+        if (!in || bytes < (size_t)L3.g.S[0] * L3.g.S[1] * L3.g.S[2] * 8) return fail(s, BF_EINVAL, "buffer too small");
+        hipError_t e3 = hipStreamSynchronize(s->stream);
+        if (e3 != hipSuccess) return hip_check(s, e3, "set_field");
+        return write_field3(s, a, in);
+    }
     const Layout& L = s->L;
     if (!in || bytes < (size_t)L.Sx * L.Sz * 8) return fail(s, BF_EINVAL, "buffer too small");
     int a;
@@ -1500,12 +2162,26 @@ bf_status bf_get_state(const bf_sim* s, bf_state* o)
     o->p_cur = s->p_cur;
     o->nseg_e = s->nseg_e; o->nseg_i = s->nseg_i; o->since_sort = s->since_sort;
     o->have_plasma = s->have_plasma; o->have_laser = s->have_laser; o->nstations = s->nst;
+    if (s->d3) {   // 3D: particle slots in use in place of the segment counts
+        o->zoff = s->d3->g.zoff; o->p_cur = s->d3->p_cur; o->since_sort = s->d3->since_compact;
+        o->nseg_e = (int32_t)s->d3->ne; o->nseg_i = (int32_t)s->d3->ni;
+    }
     return BF_OK;
 }
 
 bf_status bf_set_state(bf_sim* s, const bf_state* in)
 {
     if (!s || !in || in->abi_version != BF_ABI_VERSION || in->struct_size != sizeof(bf_state)) return BF_EINVAL;
+    if (s->d3) {
+        Sim3& L3 = *s->d3;
+        if (in->zoff < 0 || in->zoff >= L3.g.S[2] || in->nseg_e < 0 || in->nseg_e > L3.cap || in->nseg_i < 0 ||
+            in->nseg_i > L3.cap)
+            return BF_EINVAL;
+        s->step = in->step; s->t = in->time; s->shift = in->shift; s->next_row = in->next_row;
+        L3.g.zoff = in->zoff; L3.p_cur = in->p_cur & 1; L3.since_compact = in->since_sort;
+        L3.ne = in->nseg_e; L3.ni = in->nseg_i;
+        return BF_OK;
+    }
     if (in->zoff < 0 || in->zoff >= s->L.Sz || in->nseg_e < 0 || in->nseg_e > s->L.seg_cap) return BF_EINVAL;
     s->step = in->step; s->t = in->time; s->shift = in->shift; s->next_row = in->next_row;
     s->g.zoff = in->zoff;

@@ -1,0 +1,120 @@
+// bf_kernels3.h -- device-side types and launchers of the 3D step (x, y transverse, z the boost
+// axis).  Fields are [z plane][y row][x] with a padded x pitch; the z planes form a ring buffer
+// (stored plane = (plane + zoff) mod Sz) so that the moving window only moves zoff and clears
+// the planes that wrap round.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace bf3 {
+
+struct G3 {
+    int N[3];          // interior cells
+    int S[3];          // stored cells (N + 2 P + 1 on a non-periodic axis, N on a periodic one)
+    int P[3];          // PML depth (0 on a periodic axis)
+    int per[3];        // periodic flags
+    long pitch, plane; // x pitch and plane stride (elements)
+    int zoff;          // ring offset of the z planes
+    double d[3];       // cell sizes
+};
+
+// per-axis PML coefficients at nodes (h = 0) and half nodes (h = 1): sigma, xi = exp(-sigma dt)
+// and c = (1 - xi) / sigma (dt where sigma = 0); entry [axis][h] points at S[axis] values
+struct Pml3 {
+    const double* sig[3][2];
+    const double* xi[3][2];
+    const double* c[3][2];
+};
+
+template <typename R>
+struct F3 {
+    R* E[3];
+    R* Eo[3];   // E^{n-1}
+    R* Eb[3];   // Friedman average
+    R* B[3];
+    R* Bo[3];   // B^{n-1/2} (kept for the gather average)
+    double* J[3];   // deposited current, accumulated in FP64 (the electron and ion currents
+                    // nearly cancel in a plasma drifting at -beta c)
+    R* Jf[3];       // filter passes ping-pong between Jf and Jg
+    R* Jg[3];
+    R* SE[3];   // PML split parts of E (part along the cyclic-next axis)
+    R* SB[3];   // PML split parts of B
+    R* T[3];    // E-tilde of the Friedman step
+};
+
+template <typename R>
+struct E3 {     // electrons: positions in cells of the current window (FP64)
+    double *x, *y, *z;
+    R *ux, *uy, *uz, *w;
+    uint32_t* id;
+};
+
+template <typename R>
+struct I3 {     // rigid ions: x, y fixed, z0 the boosted position at t = 0 (cells)
+    double *x, *y, *z0;
+    R* w;
+    uint32_t* id;
+};
+
+struct Push3 {
+    double dt;          // time step
+    double dtd[3];      // dt / d (cells per unit velocity)
+    double jk[3];       // -q w factor of J_c: 1 / (d_a1 d_a2 dt) (times q w per particle)
+    double shift;       // whole cells the window moves at the end of this step
+};
+
+struct Inject3 {
+    int64_t row0;
+    int nrows, ppc, ion_mode;
+    int64_t cap;
+    uint64_t seed;
+    double gamma, beta, t, dx, dy, dz, n0, ramp_start, ramp_len, uz0, shift;
+};
+
+struct Antenna3 {
+    int n;              // transverse cells
+    double za, zb;      // plane position at t_n and t_{n+1} (cells)
+    double tm;          // time of the emitted field
+    double e0g, w0, xc, yc, gamma, t0, sig_t, omega;
+    double aw;          // macro-weight of each sheet particle
+};
+
+// status bits (same meaning as the 2D path)
+constexpr int ST3_CAPACITY = 1, ST3_NONFINITE = 2;
+
+template <typename R> void launch3_friedman(const G3& g, const F3<R>& f, double theta, hipStream_t s);
+template <typename R>
+void launch3_faraday(const G3& g, const F3<R>& f, const Pml3& pml, const double ck[3], double theta, double dt,
+                     hipStream_t s);
+template <typename R>
+void launch3_ampere(const G3& g, const F3<R>& f, const R* const J[3], const Pml3& pml, double dt, hipStream_t s);
+// n bilinear passes (+ compensation) per axis on J (the first pass reads the FP64 deposit,
+// the others ping-pong between Jf and Jg); returns in out[] where each component's result lies
+template <typename R>
+void launch3_filter(const G3& g, const F3<R>& f, int npass, int comp, const R* out[3], hipStream_t s);
+template <typename R> void launch3_zero_j(const G3& g, const F3<R>& f, hipStream_t s);
+template <typename R>
+void launch3_push(const G3& g, const F3<R>& f, const E3<R>& e, int n, const Push3& pp, int* status, hipStream_t s);
+template <typename R>
+void launch3_ions(const G3& g, const F3<R>& f, const I3<R>& ion, int n, double za_shift, double zb_shift,
+                  const Push3& pp, hipStream_t s);
+template <typename R>
+void launch3_antenna(const G3& g, const F3<R>& f, double* xm, const double* xh, const double* yh,
+                     const Antenna3& a, const Push3& pp, hipStream_t s);
+template <typename R>
+void launch3_inject(const G3& g, const E3<R>& e, const I3<R>& ion, int* nused_e, int* nused_i,
+                    const Inject3& ip, int* status, hipStream_t s);
+// window moved by d planes (zoff already advanced): clear the planes that wrapped round, drop
+// split parts in planes that just left the z PML, keep tangential E zero on the end walls
+template <typename R>
+void launch3_window(const G3& g, const F3<R>& f, const Pml3& pml, int d, hipStream_t s);
+// compaction of live particles (w != 0) from a into b; counters in cnt (zeroed here)
+template <typename R>
+void launch3_compact_e(const E3<R>& a, const E3<R>& b, int n, int* cnt, hipStream_t s);
+template <typename R>
+void launch3_compact_i(const I3<R>& a, const I3<R>& b, int n, int* cnt, hipStream_t s);
+template <typename R>
+void launch3_stations(const G3& g, const F3<R>& f, const double* zlab, int nst, double gamma, double beta,
+                      double t, double shift_cells, double* rec, int* cnt, int cap, hipStream_t s);
+
+}  // namespace bf3

@@ -1,0 +1,821 @@
+// bf_sim3.hip -- kernels of the 3D boosted-frame step (x, y transverse, z the boost axis).
+//
+// The method is the 2-1/2D one in three dimensions:
+//   * Faraday with the tunable (Cole-Karkkainen) operator Delta* = (alpha + beta S^1 + gamma
+//     S^2) Delta, S^1 the four one-cell shifts along the two transverse axes and S^2 the four
+//     diagonal shifts, and Friedman damping (Sec. 4.2, Sec. 4.3); Ampere with Yee differences;
+//   * split-field PML on every component (Appendix II): each component's two curl terms are
+//     damped by the conductivity of their derivative's axis; the stored split part is the one
+//     along the axis cyclically next to the component, and it carries the current source;
+//   * cubic B-spline gather from the staggered locations (Sec. 5.1), Boris push, Esirkepov's
+//     charge-conserving deposit in 3D (Sec. 4.2.2) on 5-node windows;
+//   * n-pass bilinear filter plus compensation along x, y and z (Sec. 4.1);
+//   * laser sheets on a lab-fixed plane with one +/- pair per transverse cell (Sec. 3.1.2);
+//   * moving window as a ring offset of the z planes, plane-wise plasma injection.
+// This first 3D path is written for correctness: one thread per cell for the field stages and
+// one per particle for the particle stages, fields read from HBM and the current deposited
+// with global atomics.
+#include "bf_kernels3.h"
+#include <cmath>
+
+namespace bf3 {
+
+constexpr int NT = 256;
+
+__device__ __forceinline__ int nb(int i, int o, int S, int per)
+{
+    int j = i + o;
+    if (per) {
+        j %= S;
+        return j < 0 ? j + S : j;
+    }
+    return (j < 0 || j >= S) ? -1 : j;
+}
+
+__device__ __forceinline__ long o3(const G3& g, int i, int j, int k)
+{
+    int kk = k + g.zoff;
+    if (kk >= g.S[2]) kk -= g.S[2];
+    return (long)kk * g.plane + (long)j * g.pitch + i;
+}
+
+// stored index of interior-relative node (or half node) j along axis a; -1 outside
+__device__ __forceinline__ int sidx(const G3& g, int a, int j)
+{
+    if (g.per[a]) {
+        j %= g.N[a];
+        return j < 0 ? j + g.N[a] : j;
+    }
+    j += g.P[a];
+    return (j < 0 || j >= g.S[a]) ? -1 : j;
+}
+
+__device__ __forceinline__ bool cell_of(const G3& g, long idx, int q[3])
+{
+    const long n = (long)g.S[0] * g.S[1] * g.S[2];
+    if (idx >= n) return false;
+    q[0] = (int)(idx % g.S[0]);
+    q[1] = (int)((idx / g.S[0]) % g.S[1]);
+    q[2] = (int)(idx / ((long)g.S[0] * g.S[1]));
+    return true;
+}
+
+inline dim3 cells_grid(const G3& g)
+{
+    const long n = (long)g.S[0] * g.S[1] * g.S[2];
+    return dim3((unsigned)((n + NT - 1) / NT));
+}
+
+// ---- field solver ---------------------------------------------------------------------------
+
+// difference of G along AX towards a target with stagger ht there: right neighbour q + ht, left
+// q + ht - 1 (a neighbour beyond a non-periodic edge reads 0)
+template <int AX, typename R>
+__device__ __forceinline__ R dG(const R* __restrict__ G, const G3& g, const int q[3], int ht)
+{
+    int p[3] = {q[0], q[1], q[2]};
+    const int r = nb(q[AX], ht, g.S[AX], g.per[AX]), l = nb(q[AX], ht - 1, g.S[AX], g.per[AX]);
+    R gr = R(0), gl = R(0);
+    if (r >= 0) { p[AX] = r; gr = G[o3(g, p[0], p[1], p[2])]; }
+    if (l >= 0) { p[AX] = l; gl = G[o3(g, p[0], p[1], p[2])]; }
+    return (gr - gl) / (R)g.d[AX];
+}
+
+template <int AX, typename R>
+__device__ __forceinline__ R dstar(const R* __restrict__ G, const G3& g, const int q[3], int ht, R a, R b, R c)
+{
+    R v = a * dG<AX>(G, g, q, ht);
+    if (b == R(0) && c == R(0)) return v;
+    constexpr int T1 = (AX + 1) % 3, T2 = (AX + 2) % 3;
+#pragma unroll
+    for (int s = -1; s <= 1; s += 2) {
+        int p[3] = {q[0], q[1], q[2]};
+        p[T1] = nb(q[T1], s, g.S[T1], g.per[T1]);
+        if (p[T1] >= 0) v += b * dG<AX>(G, g, p, ht);
+        int r[3] = {q[0], q[1], q[2]};
+        r[T2] = nb(q[T2], s, g.S[T2], g.per[T2]);
+        if (r[T2] >= 0) v += b * dG<AX>(G, g, r, ht);
+    }
+    if (c != R(0)) {
+#pragma unroll
+        for (int s1 = -1; s1 <= 1; s1 += 2)
+#pragma unroll
+            for (int s2 = -1; s2 <= 1; s2 += 2) {
+                int p[3] = {q[0], q[1], q[2]};
+                p[T1] = nb(q[T1], s1, g.S[T1], g.per[T1]);
+                p[T2] = nb(q[T2], s2, g.S[T2], g.per[T2]);
+                if (p[T1] >= 0 && p[T2] >= 0) v += c * dG<AX>(G, g, p, ht);
+            }
+    }
+    return v;
+}
+
+// split update of one component from its curl terms t1 (axis A1, the stored part) and t2
+template <int A1, int A2, typename R>
+__device__ __forceinline__ R split_update(R old, R* sp, long o, R t1, R t2, const Pml3& pml, const int q[3],
+                                          const int h[3], R dt)
+{
+    const double s1 = pml.sig[A1][h[A1]][q[A1]], s2 = pml.sig[A2][h[A2]][q[A2]];
+    if (s1 == 0.0 && s2 == 0.0) return old + dt * (t1 + t2);
+    const R x1 = (R)pml.xi[A1][h[A1]][q[A1]], c1 = (R)pml.c[A1][h[A1]][q[A1]];
+    const R x2 = (R)pml.xi[A2][h[A2]][q[A2]], c2 = (R)pml.c[A2][h[A2]][q[A2]];
+    R p1 = sp[o];
+    R p2 = old - p1;
+    p1 = x1 * p1 + c1 * t1;
+    p2 = x2 * p2 + c2 * t2;
+    sp[o] = p1;
+    return p1 + p2;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NT) k3_friedman(G3 g, F3<R> f, R th)
+{
+    int q[3];
+    if (!cell_of(g, (long)blockIdx.x * NT + threadIdx.x, q)) return;
+    const long o = o3(g, q[0], q[1], q[2]);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const R eo = f.Eo[c][o];
+        const R eb = (R(1) - R(0.5) * th) * eo + R(0.5) * th * f.Eb[c][o];
+        f.Eb[c][o] = eb;
+        f.T[c][o] = (R(1) + R(0.25) * th) * f.E[c][o] - R(0.5) * eo + (R(0.5) - R(0.25) * th) * eb;
+    }
+}
+
+// dB_C/dt = -(Delta*_A1 E_A2 - Delta*_A2 E_A1), (C, A1, A2) cyclic; B_C sits on a node along C
+// and on half nodes along A1, A2
+template <int C, typename R>
+__device__ __forceinline__ void faraday_comp(const G3& g, const F3<R>& f, const R* const* Et, const Pml3& pml,
+                                             const int q[3], R a, R b, R cg, R dt)
+{
+    constexpr int A1 = (C + 1) % 3, A2 = (C + 2) % 3;
+    const int h[3] = {C == 0 ? 0 : 1, C == 1 ? 0 : 1, C == 2 ? 0 : 1};
+    const long o = o3(g, q[0], q[1], q[2]);
+    const R old = f.B[C][o];
+    f.Bo[C][o] = old;
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+        if (!g.per[d] && q[d] > g.S[d] - 1 - h[d]) return;
+    const R t1 = -dstar<A1>(Et[A2], g, q, h[A1], a, b, cg);
+    const R t2 = dstar<A2>(Et[A1], g, q, h[A2], a, b, cg);
+    f.B[C][o] = split_update<A1, A2>(old, f.SB[C], o, t1, t2, pml, q, h, dt);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NT) k3_faraday(G3 g, F3<R> f, Pml3 pml, R a, R b, R cg, R dt, int use_t)
+{
+    int q[3];
+    if (!cell_of(g, (long)blockIdx.x * NT + threadIdx.x, q)) return;
+    const R* Et[3] = {use_t ? f.T[0] : f.E[0], use_t ? f.T[1] : f.E[1], use_t ? f.T[2] : f.E[2]};
+    faraday_comp<0>(g, f, Et, pml, q, a, b, cg, dt);
+    faraday_comp<1>(g, f, Et, pml, q, a, b, cg, dt);
+    faraday_comp<2>(g, f, Et, pml, q, a, b, cg, dt);
+}
+
+// dE_C/dt = Delta_A1 B_A2 - Delta_A2 B_A1 - J_C; E_C sits on a half node along C, nodes along
+// A1, A2; conducting walls keep the tangential components at 0 (nodes 0 and S-1 of a
+// non-periodic axis stay untouched)
+template <int C, typename R>
+__device__ __forceinline__ void ampere_comp(const G3& g, const F3<R>& f, const R* const* J, const Pml3& pml,
+                                            const int q[3], R dt)
+{
+    constexpr int A1 = (C + 1) % 3, A2 = (C + 2) % 3;
+    const int h[3] = {C == 0 ? 1 : 0, C == 1 ? 1 : 0, C == 2 ? 1 : 0};
+    const long o = o3(g, q[0], q[1], q[2]);
+    const R old = f.E[C][o];
+    f.Eo[C][o] = old;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        if (g.per[d]) continue;
+        if (q[d] < (h[d] ? 0 : 1) || q[d] > g.S[d] - 2) return;
+    }
+    const R t1 = dG<A1>(f.B[A2], g, q, h[A1]) - J[C][o];
+    const R t2 = -dG<A2>(f.B[A1], g, q, h[A2]);
+    f.E[C][o] = split_update<A1, A2>(old, f.SE[C], o, t1, t2, pml, q, h, dt);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NT) k3_ampere(G3 g, F3<R> f, const R* J0, const R* J1, const R* J2, Pml3 pml, R dt)
+{
+    int q[3];
+    if (!cell_of(g, (long)blockIdx.x * NT + threadIdx.x, q)) return;
+    const R* J[3] = {J0, J1, J2};
+    ampere_comp<0>(g, f, J, pml, q, dt);
+    ampere_comp<1>(g, f, J, pml, q, dt);
+    ampere_comp<2>(g, f, J, pml, q, dt);
+}
+
+// one 3-point pass along AX over the stored range of a component with stagger h there;
+// neighbours beyond the range read 0, cells beyond it are copied
+template <int AX, typename TI, typename R>
+__global__ void __launch_bounds__(NT) k3_fpass(G3 g, const TI* __restrict__ in, R* __restrict__ out, int h, R alpha)
+{
+    int q[3];
+    if (!cell_of(g, (long)blockIdx.x * NT + threadIdx.x, q)) return;
+    const long o = o3(g, q[0], q[1], q[2]);
+    const int hi = g.per[AX] ? g.S[AX] - 1 : g.S[AX] - 1 - h;
+    if (q[AX] > hi) { out[o] = (R)in[o]; return; }
+    int p[3] = {q[0], q[1], q[2]};
+    const int l = nb(q[AX], -1, g.S[AX], g.per[AX]), r = nb(q[AX], 1, g.S[AX], g.per[AX]);
+    TI vl = TI(0), vr = TI(0);
+    if (l >= 0 && l <= hi) { p[AX] = l; vl = in[o3(g, p[0], p[1], p[2])]; }
+    if (r >= 0 && r <= hi) { p[AX] = r; vr = in[o3(g, p[0], p[1], p[2])]; }
+    out[o] = (R)((TI)alpha * in[o] + (TI(1) - (TI)alpha) * TI(0.5) * (vl + vr));
+}
+
+__global__ void __launch_bounds__(NT) k3_zero3(G3 g, double* a, double* b, double* c)
+{
+    int q[3];
+    if (!cell_of(g, (long)blockIdx.x * NT + threadIdx.x, q)) return;
+    const long o = o3(g, q[0], q[1], q[2]);
+    a[o] = 0.0;
+    b[o] = 0.0;
+    c[o] = 0.0;
+}
+
+// ---- particles --------------------------------------------------------------------------------
+
+// cubic B-spline weights of nodes j0-1 .. j0+2 for a particle at fraction f of cell j0
+template <typename R>
+__device__ __forceinline__ void bspline4(R f, R w[4])
+{
+    const R g = R(1) - f, f2 = f * f, f3 = f2 * f, sixth = R(1) / R(6);
+    w[0] = g * g * g * sixth;
+    w[1] = (R(3) * f3 - R(6) * f2 + R(4)) * sixth;
+    w[2] = (-R(3) * f3 + R(3) * f2 + R(3) * f + R(1)) * sixth;
+    w[3] = f3 * sixth;
+}
+
+// the same weights on the 5-node window starting one node below the particle's (hi = false)
+// or two below (hi = true), FP64 (Esirkepov)
+__device__ __forceinline__ void window5(double f, bool hi, double s[5])
+{
+    const double g = 1.0 - f, f2 = f * f, f3 = f2 * f, sixth = 1.0 / 6.0;
+    const double w0 = g * g * g * sixth, w1 = (3.0 * f3 - 6.0 * f2 + 4.0) * sixth;
+    const double w2 = (-3.0 * f3 + 3.0 * f2 + 3.0 * f + 1.0) * sixth, w3 = f3 * sixth;
+    s[0] = hi ? 0.0 : w0;
+    s[1] = hi ? w0 : w1;
+    s[2] = hi ? w1 : w2;
+    s[3] = hi ? w2 : w3;
+    s[4] = hi ? w3 : 0.0;
+}
+
+// gather of E^n and B^n = (B^{n-1/2} + B^{n+1/2}) / 2 at r (cells), cubic weights at each
+// component's stagger
+template <typename R>
+__device__ void gather3(const G3& g, const F3<R>& f, const double r[3], R E[3], R B[3])
+{
+    R w[3][2][4];
+    int id[3][2][4];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const double xs = r[a] - 0.5 * h;
+            const int j0 = (int)floor(xs);
+            bspline4((R)(xs - j0), w[a][h]);
+#pragma unroll
+            for (int m = 0; m < 4; m++) id[a][h][m] = sidx(g, a, j0 - 1 + m);
+        }
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+        const int hx = c < 3 ? (c == 0) : (c != 3), hy = c < 3 ? (c == 1) : (c != 4), hz = c < 3 ? (c == 2) : (c != 5);
+        R acc = R(0), acc2 = R(0);
+        const R* F = c < 3 ? f.E[c] : f.B[c - 3];
+        const R* Fo = c < 3 ? f.E[c] : f.Bo[c - 3];
+        for (int k = 0; k < 4; k++) {
+            const int sk = id[2][hz][k];
+            if (sk < 0) continue;
+            for (int j = 0; j < 4; j++) {
+                const int sj = id[1][hy][j];
+                if (sj < 0) continue;
+                const R wjk = w[1][hy][j] * w[2][hz][k];
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const int si = id[0][hx][i];
+                    if (si < 0) continue;
+                    const long o = o3(g, si, sj, sk);
+                    acc += w[0][hx][i] * wjk * F[o];
+                    if (c >= 3) acc2 += w[0][hx][i] * wjk * Fo[o];
+                }
+            }
+        }
+        if (c < 3) E[c] = acc;
+        else B[c - 3] = R(0.5) * (acc + acc2);
+    }
+}
+
+// Esirkepov's 3D deposit of one particle moving r0 -> r1 (cells, |move| < 1 cell per axis):
+//   W_C = DS_C (S0_A1 S0_A2 + DS_A1 S0_A2 / 2 + S0_A1 DS_A2 / 2 + DS_A1 DS_A2 / 3),
+//   J_C(node + 1/2) - J_C(node - 1/2) = k_C W_C   (k_C = -q w / (d_A1 d_A2 dt))
+__device__ void esirkepov3(const G3& g, double* const* J, const double r0[3], const double r1[3], const double k[3])
+{
+    double S0[3][5], DS[3][5];
+    int base[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int i0 = (int)floor(r0[a]), i1 = (int)floor(r1[a]);
+        const int b = min(i0, i1) - 1;
+        base[a] = b;
+        double s1[5];
+        window5(r0[a] - i0, i0 > b + 1, S0[a]);
+        window5(r1[a] - i1, i1 > b + 1, s1);
+#pragma unroll
+        for (int m = 0; m < 5; m++) DS[a][m] = s1[m] - S0[a][m];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if (k[c] == 0.0) continue;
+        const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+        int sc[4];
+#pragma unroll
+        for (int m = 0; m < 4; m++) sc[m] = sidx(g, c, base[c] + m);
+        for (int m1 = 0; m1 < 5; m1++) {
+            const int s1 = sidx(g, a1, base[a1] + m1);
+            if (s1 < 0) continue;
+            for (int m2 = 0; m2 < 5; m2++) {
+                const int s2 = sidx(g, a2, base[a2] + m2);
+                if (s2 < 0) continue;
+                const double T = S0[a1][m1] * S0[a2][m2] + 0.5 * DS[a1][m1] * S0[a2][m2] +
+                                 0.5 * S0[a1][m1] * DS[a2][m2] + DS[a1][m1] * DS[a2][m2] * (1.0 / 3.0);
+                if (T == 0.0) continue;
+                double acc = 0.0;
+#pragma unroll
+                for (int mc = 0; mc < 4; mc++) {
+                    acc += k[c] * DS[c][mc] * T;
+                    if (acc == 0.0 || sc[mc] < 0) continue;
+                    int q[3];
+                    q[c] = sc[mc];
+                    q[a1] = s1;
+                    q[a2] = s2;
+                    atomicAdd(&J[c][o3(g, q[0], q[1], q[2])], acc);
+                }
+            }
+        }
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ R rsq(R x)
+{
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_rsqf(x);
+    else return 1.0 / sqrt(x);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NT) k3_push(G3 g, F3<R> f, E3<R> e, int n, Push3 pp, int* status)
+{
+    const int p = blockIdx.x * NT + threadIdx.x;
+    if (p >= n) return;
+    const R w = e.w[p];
+    if (w == R(0)) return;
+    const double r0[3] = {e.x[p], e.y[p], e.z[p]};
+    R E[3], B[3];
+    gather3(g, f, r0, E, B);
+    // Boris (q/m = -1), h = q dt / 2m
+    const R h = (R)(-0.5 * pp.dt);
+    R ux = e.ux[p], uy = e.uy[p], uz = e.uz[p];
+    const R umx = ux + h * E[0], umy = uy + h * E[1], umz = uz + h * E[2];
+    const R ig = rsq(R(1) + umx * umx + umy * umy + umz * umz);
+    const R tx = h * B[0] * ig, ty = h * B[1] * ig, tz = h * B[2] * ig;
+    const R sf = R(2) / (R(1) + tx * tx + ty * ty + tz * tz);
+    const R sx = sf * tx, sy = sf * ty, sz = sf * tz;
+    const R upx = umx + (umy * tz - umz * ty), upy = umy + (umz * tx - umx * tz), upz = umz + (umx * ty - umy * tx);
+    ux = umx + (upy * sz - upz * sy) + h * E[0];
+    uy = umy + (upz * sx - upx * sz) + h * E[1];
+    uz = umz + (upx * sy - upy * sx) + h * E[2];
+    const R gi = rsq(R(1) + ux * ux + uy * uy + uz * uz);
+    double r1[3] = {r0[0] + pp.dtd[0] * (double)(ux * gi), r0[1] + pp.dtd[1] * (double)(uy * gi),
+                    r0[2] + pp.dtd[2] * (double)(uz * gi)};
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) ok = ok && fabs(r1[a] - r0[a]) < 1.0;
+    if (ok) {
+        const double k[3] = {pp.jk[0] * (double)w, pp.jk[1] * (double)w, pp.jk[2] * (double)w};   // q = -1
+        esirkepov3(g, f.J, r0, r1, k);
+    } else {
+        atomicOr(status, ST3_NONFINITE);
+    }
+    if (!isfinite((double)(ux + uy + uz))) atomicOr(status, ST3_NONFINITE);
+    bool alive = true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double L = (double)g.N[a];
+        if (g.per[a]) {
+            if (r1[a] < 0.0) r1[a] += L;
+            else if (r1[a] >= L) r1[a] -= L;
+        } else if (r1[a] < 0.0 || r1[a] >= L) {
+            alive = false;
+        }
+    }
+    if (!alive) {
+        e.w[p] = R(0);
+        return;
+    }
+    e.x[p] = r1[0];
+    e.y[p] = r1[1];
+    e.z[p] = r1[2] - pp.shift;
+    e.ux[p] = ux;
+    e.uy[p] = uy;
+    e.uz[p] = uz;
+}
+
+// rigid ions: z(t) = z0 - (beta t / dz + shift), deposit only (q = +1)
+template <typename R>
+__global__ void __launch_bounds__(NT) k3_ions(G3 g, F3<R> f, I3<R> ion, int n, double zsa, double zsb, Push3 pp)
+{
+    const int p = blockIdx.x * NT + threadIdx.x;
+    if (p >= n) return;
+    const R w = ion.w[p];
+    if (w == R(0)) return;
+    const double x = ion.x[p], y = ion.y[p], z0 = ion.z0[p];
+    const double r0[3] = {x, y, z0 - zsa}, r1[3] = {x, y, z0 - zsb};
+    const double k[3] = {0.0, 0.0, -pp.jk[2] * (double)w};
+    esirkepov3(g, f.J, r0, r1, k);
+    if (!g.per[2] && (r1[2] < 0.0 || r1[2] >= (double)g.N[2])) ion.w[p] = R(0);
+}
+
+// laser antenna: per transverse cell a + particle fixed at the cell centre and a - particle
+// moving along x with the sheet current K = -2 E_perp (FP64 throughout)
+template <typename R>
+__global__ void __launch_bounds__(64) k3_antenna(G3 g, F3<R> f, double* xm, const double* xh, const double* yh,
+                                                 Antenna3 a, Push3 pp)
+{
+    const int q = blockIdx.x * 64 + threadIdx.x;
+    if (q >= a.n) return;
+    const double xu = xh[q] * g.d[0], yu = yh[q] * g.d[1];
+    const double tau = a.tm / a.gamma - a.t0;
+    const double r2 = (xu - a.xc) * (xu - a.xc) + (yu - a.yc) * (yu - a.yc);
+    const double E = a.e0g * exp(-r2 / (a.w0 * a.w0)) * exp(-tau * tau / (2.0 * a.sig_t * a.sig_t)) * sin(a.omega * tau);
+    const double K = -2.0 * E;
+    const double vx = K * g.d[0] * g.d[1] / (-1.0 * a.aw);   // um per unit time
+    const double x0 = xm[q], x1 = x0 + vx * pp.dt / g.d[0];
+    const double m0[3] = {x0, yh[q], a.za}, m1[3] = {x1, yh[q], a.zb};
+    const double km[3] = {pp.jk[0] * a.aw, pp.jk[1] * a.aw, pp.jk[2] * a.aw};   // q = -1
+    esirkepov3(g, f.J, m0, m1, km);
+    const double h0[3] = {xh[q], yh[q], a.za}, h1[3] = {xh[q], yh[q], a.zb};
+    const double kp[3] = {-km[0], -km[1], -km[2]};                           // q = +1
+    esirkepov3(g, f.J, h0, h1, kp);
+    xm[q] = x1;
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): output number k of the generator started at seed
+__device__ __forceinline__ double u01(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + k * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// lattice planes row0 .. row0+nrows-1 of the lab-fixed plasma; consecutive particles of a
+// block sit in consecutive cells of a plane
+template <typename R>
+__global__ void __launch_bounds__(NT) k3_inject(G3 g, E3<R> e, I3<R> ion, int* nused_e, int* nused_i, Inject3 ip,
+                                                int* status)
+{
+    __shared__ int base[2];
+    const int64_t per_plane = (int64_t)g.N[0] * g.N[1] * ip.ppc;
+    const int64_t total = per_plane * ip.nrows;
+    const int64_t b0 = (int64_t)blockIdx.x * NT;
+    const int cnt = (int)min<int64_t>(NT, total - b0);
+    if (cnt <= 0) return;
+    if (threadIdx.x == 0) {
+        int se = atomicAdd(nused_e, cnt);
+        int si = ip.ion_mode ? atomicAdd(nused_i, cnt) : 0;
+        if ((int64_t)se + cnt > ip.cap || (int64_t)si + cnt > ip.cap) {
+            atomicOr(status, ST3_CAPACITY);
+            se = -1;
+        }
+        base[0] = se;
+        base[1] = si;
+    }
+    __syncthreads();
+    if (base[0] < 0 || (int)threadIdx.x >= cnt) return;
+    const int64_t gq = b0 + threadIdx.x;
+    const int64_t r = gq / per_plane, rem = gq - r * per_plane;
+    const int64_t ncell = (int64_t)g.N[0] * g.N[1];
+    const int64_t cell = rem % ncell, k = rem / ncell;
+    const int i = (int)(cell % g.N[0]), j = (int)(cell / g.N[0]);
+    const int64_t l = ip.row0 + r;
+    const uint64_t id = (((uint64_t)l * (uint64_t)g.N[1] + (uint64_t)j) * (uint64_t)g.N[0] + (uint64_t)i) *
+                            (uint64_t)ip.ppc + (uint64_t)k;
+    const double rx = u01(ip.seed, 3 * id + 1), ry = u01(ip.seed, 3 * id + 2), rz = u01(ip.seed, 3 * id + 3);
+    const double zbc = (double)l + rz;
+    const double zl = ip.gamma * (zbc * ip.dz);
+    double n = 0.0;
+    if (zl >= ip.ramp_start) {
+        n = ip.n0;
+        if (ip.ramp_len > 0.0 && zl < ip.ramp_start + ip.ramp_len) n = ip.n0 * (zl - ip.ramp_start) / ip.ramp_len;
+    }
+    const double wgt = ip.gamma * n * ip.dx * ip.dy * ip.dz / (double)ip.ppc;
+    const int p = base[0] + threadIdx.x;
+    e.x[p] = (double)i + rx;
+    e.y[p] = (double)j + ry;
+    e.z[p] = zbc - ip.beta * ip.t / ip.dz - ip.shift;
+    e.ux[p] = R(0);
+    e.uy[p] = R(0);
+    e.uz[p] = (R)ip.uz0;
+    e.w[p] = (R)wgt;
+    e.id[p] = (uint32_t)id;
+    if (ip.ion_mode) {
+        const int pi = base[1] + threadIdx.x;
+        ion.x[pi] = (double)i + rx;
+        ion.y[pi] = (double)j + ry;
+        ion.z0[pi] = zbc;
+        ion.w[pi] = (R)wgt;
+        ion.id[pi] = (uint32_t)id;
+    }
+}
+
+// window moved by d planes (zoff already advanced)
+template <typename R>
+__global__ void __launch_bounds__(NT) k3_window(G3 g, F3<R> f, int d)
+{
+    int q[3];
+    if (!cell_of(g, (long)blockIdx.x * NT + threadIdx.x, q)) return;
+    const int Sz = g.S[2], k = q[2];
+    const long o = o3(g, q[0], q[1], k);
+    if ((d > 0 && k >= Sz - d) || (d < 0 && k < -d)) {
+        R* all[30] = {f.E[0], f.E[1], f.E[2], f.Eo[0], f.Eo[1], f.Eo[2], f.Eb[0], f.Eb[1], f.Eb[2],
+                      f.B[0], f.B[1], f.B[2], f.Bo[0], f.Bo[1], f.Bo[2], f.Jg[0], f.Jg[1], f.Jg[2],
+                      f.Jf[0], f.Jf[1], f.Jf[2], f.SE[0], f.SE[1], f.SE[2], f.SB[0], f.SB[1], f.SB[2],
+                      f.T[0], f.T[1], f.T[2]};
+#pragma unroll
+        for (int m = 0; m < 30; m++) all[m][o] = R(0);
+#pragma unroll
+        for (int c = 0; c < 3; c++) f.J[c][o] = 0.0;
+    } else {
+        // a split part is meaningful only where one of its two axes has a conductivity: drop
+        // it in planes whose content just came out of the z PML
+        auto inside = [&](int a, int idx, int h) {
+            if (g.per[a]) return true;
+            const double pos = (double)(idx - g.P[a]) + 0.5 * h;
+            return pos >= 0.0 && pos <= (double)g.N[a];
+        };
+#pragma unroll
+        for (int c = 0; c < 2; c++) {   // x and y components: the only ones with a z derivative
+            const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+            // E_c: half along c, nodes elsewhere; B_c: node along c, half elsewhere
+            const int hE[3] = {c == 0 ? 1 : 0, c == 1 ? 1 : 0, 0};
+            const int hB[3] = {c == 0 ? 0 : 1, c == 1 ? 0 : 1, 1};
+            if (inside(2, k, hE[2]) && !inside(2, k + d, hE[2]) && inside(a1, q[a1], hE[a1]) &&
+                inside(a2, q[a2], hE[a2]))
+                f.SE[c][o] = R(0);
+            if (inside(2, k, hB[2]) && !inside(2, k + d, hB[2]) && inside(a1, q[a1], hB[a1]) &&
+                inside(a2, q[a2], hB[a2]))
+                f.SB[c][o] = R(0);
+        }
+    }
+    // tangential E stays zero on the conducting end walls
+    if (!g.per[2] && (k == 0 || k == Sz - 1)) {
+        f.E[0][o] = R(0); f.E[1][o] = R(0);
+        f.Eo[0][o] = R(0); f.Eo[1][o] = R(0);
+        f.Eb[0][o] = R(0); f.Eb[1][o] = R(0);
+    }
+}
+
+// live particles (w != 0) of a into b, wave-aggregated slots
+template <typename R>
+__global__ void __launch_bounds__(NT) k3_compact_e(E3<R> a, E3<R> b, int n, int* cnt)
+{
+    const int p = blockIdx.x * NT + threadIdx.x;
+    const bool live = p < n && a.w[p] != R(0);
+    const unsigned long long m = __ballot(live);
+    const int lane = __lane_id();
+    const int leader = m ? __ffsll((long long)m) - 1 : 0;
+    int base = 0;
+    if (m && lane == leader) base = atomicAdd(cnt, __popcll(m));
+    base = __shfl(base, leader);
+    if (!live) return;
+    const int d = base + __popcll(m & ((1ull << lane) - 1ull));
+    b.x[d] = a.x[p]; b.y[d] = a.y[p]; b.z[d] = a.z[p];
+    b.ux[d] = a.ux[p]; b.uy[d] = a.uy[p]; b.uz[d] = a.uz[p];
+    b.w[d] = a.w[p]; b.id[d] = a.id[p];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NT) k3_compact_i(I3<R> a, I3<R> b, int n, int* cnt)
+{
+    const int p = blockIdx.x * NT + threadIdx.x;
+    const bool live = p < n && a.w[p] != R(0);
+    const unsigned long long m = __ballot(live);
+    const int lane = __lane_id();
+    const int leader = m ? __ffsll((long long)m) - 1 : 0;
+    int base = 0;
+    if (m && lane == leader) base = atomicAdd(cnt, __popcll(m));
+    base = __shfl(base, leader);
+    if (!live) return;
+    const int d = base + __popcll(m & ((1ull << lane) - 1ull));
+    b.x[d] = a.x[p]; b.y[d] = a.y[p]; b.z0[d] = a.z0[p]; b.w[d] = a.w[p]; b.id[d] = a.id[p];
+}
+
+// trilinear sample of a component with staggers h at r (cells)
+template <typename R>
+__device__ double trilin(const G3& g, const R* F, const int h[3], const double r[3])
+{
+    int j[3];
+    double fr[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double xs = r[a] - 0.5 * h[a];
+        j[a] = (int)floor(xs);
+        fr[a] = xs - j[a];
+    }
+    double v = 0.0;
+    for (int c = 0; c < 2; c++)
+        for (int b = 0; b < 2; b++)
+            for (int a = 0; a < 2; a++) {
+                const int i0 = sidx(g, 0, j[0] + a), i1 = sidx(g, 1, j[1] + b), i2 = sidx(g, 2, j[2] + c);
+                if (i0 < 0 || i1 < 0 || i2 < 0) continue;
+                v += (a ? fr[0] : 1.0 - fr[0]) * (b ? fr[1] : 1.0 - fr[1]) * (c ? fr[2] : 1.0 - fr[2]) *
+                     (double)F[o3(g, i0, i1, i2)];
+            }
+    return v;
+}
+
+template <typename R>
+__global__ void k3_stations(G3 g, F3<R> f, const double* zlab, int nst, double gamma, double beta, double t,
+                            double shift_cells, double* rec, int* cnt, int cap)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nst) return;
+    const double zb = zlab[q] / gamma - beta * t;
+    const double zc = zb / g.d[2] - shift_cells;
+    if (zc < 0.0 || zc >= (double)g.N[2] || cnt[q] >= cap) return;
+    const double r[3] = {0.5 * g.N[0], 0.5 * g.N[1], zc};
+    double E[3], B[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const int hE[3] = {c == 0, c == 1, c == 2}, hB[3] = {c != 0, c != 1, c != 2};
+        E[c] = trilin(g, f.E[c], hE, r);
+        B[c] = 0.5 * (trilin(g, f.Bo[c], hB, r) + trilin(g, f.B[c], hB, r));
+    }
+    double* o = rec + ((size_t)q * cap + cnt[q]) * 7;
+    o[0] = gamma * (t + beta * zb);
+    o[1] = gamma * (E[0] + beta * B[1]);
+    o[2] = gamma * (E[1] - beta * B[0]);
+    o[3] = E[2];
+    o[4] = gamma * (B[0] - beta * E[1]);
+    o[5] = gamma * (B[1] + beta * E[0]);
+    o[6] = B[2];
+    cnt[q] += 1;
+}
+
+// ---- launchers ----------------------------------------------------------------------------------
+
+template <typename R>
+void launch3_friedman(const G3& g, const F3<R>& f, double theta, hipStream_t s)
+{
+    hipLaunchKernelGGL((k3_friedman<R>), cells_grid(g), dim3(NT), 0, s, g, f, (R)theta);
+}
+
+template <typename R>
+void launch3_faraday(const G3& g, const F3<R>& f, const Pml3& pml, const double ck[3], double theta, double dt,
+                     hipStream_t s)
+{
+    hipLaunchKernelGGL((k3_faraday<R>), cells_grid(g), dim3(NT), 0, s, g, f, pml, (R)ck[0], (R)ck[1], (R)ck[2],
+                       (R)dt, theta > 0.0 ? 1 : 0);
+}
+
+template <typename R>
+void launch3_ampere(const G3& g, const F3<R>& f, const R* const J[3], const Pml3& pml, double dt, hipStream_t s)
+{
+    hipLaunchKernelGGL((k3_ampere<R>), cells_grid(g), dim3(NT), 0, s, g, f, J[0], J[1], J[2], pml, (R)dt);
+}
+
+template <int AX, typename TI, typename R>
+void fpass(const G3& g, const TI* in, R* out, int h, R alpha, hipStream_t s)
+{
+    hipLaunchKernelGGL((k3_fpass<AX, TI, R>), cells_grid(g), dim3(NT), 0, s, g, in, out, h, alpha);
+}
+
+template <typename R>
+void launch3_filter(const G3& g, const F3<R>& f, int npass, int comp, const R* out[3], hipStream_t s)
+{
+    for (int c = 0; c < 3; c++) {
+        const int h[3] = {c == 0, c == 1, c == 2};
+        const int np = npass + (comp ? 1 : 0);
+        R* cur = f.Jf[c];
+        R* oth = f.Jg[c];
+        bool first = true;
+        for (int ax = 0; ax < 3 && np > 0; ax++) {
+            for (int p = 0; p < np; p++) {
+                const R alpha = p < npass ? R(0.5) : (R)(0.5 * npass + 1.0);
+                if (first) {
+                    // the first pass reads the FP64 deposit
+                    if (ax == 0) fpass<0>(g, (const double*)f.J[c], cur, h[0], alpha, s);
+                    else if (ax == 1) fpass<1>(g, (const double*)f.J[c], cur, h[1], alpha, s);
+                    else fpass<2>(g, (const double*)f.J[c], cur, h[2], alpha, s);
+                    first = false;
+                    continue;
+                }
+                if (ax == 0) fpass<0>(g, (const R*)cur, oth, h[0], alpha, s);
+                else if (ax == 1) fpass<1>(g, (const R*)cur, oth, h[1], alpha, s);
+                else fpass<2>(g, (const R*)cur, oth, h[2], alpha, s);
+                R* t = cur;
+                cur = oth;
+                oth = t;
+            }
+        }
+        if (first) fpass<0>(g, (const double*)f.J[c], cur, 0, R(1), s);   // no filter: a copy in the run's type
+        out[c] = cur;
+    }
+}
+
+template <typename R>
+void launch3_zero_j(const G3& g, const F3<R>& f, hipStream_t s)
+{
+    hipLaunchKernelGGL(k3_zero3, cells_grid(g), dim3(NT), 0, s, g, f.J[0], f.J[1], f.J[2]);
+}
+
+template <typename R>
+void launch3_push(const G3& g, const F3<R>& f, const E3<R>& e, int n, const Push3& pp, int* status, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k3_push<R>), dim3((n + NT - 1) / NT), dim3(NT), 0, s, g, f, e, n, pp, status);
+}
+
+template <typename R>
+void launch3_ions(const G3& g, const F3<R>& f, const I3<R>& ion, int n, double za_shift, double zb_shift,
+                  const Push3& pp, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k3_ions<R>), dim3((n + NT - 1) / NT), dim3(NT), 0, s, g, f, ion, n, za_shift, zb_shift, pp);
+}
+
+template <typename R>
+void launch3_antenna(const G3& g, const F3<R>& f, double* xm, const double* xh, const double* yh,
+                     const Antenna3& a, const Push3& pp, hipStream_t s)
+{
+    if (a.n <= 0) return;
+    hipLaunchKernelGGL((k3_antenna<R>), dim3((a.n + 63) / 64), dim3(64), 0, s, g, f, xm, xh, yh, a, pp);
+}
+
+template <typename R>
+void launch3_inject(const G3& g, const E3<R>& e, const I3<R>& ion, int* nused_e, int* nused_i,
+                    const Inject3& ip, int* status, hipStream_t s)
+{
+    const int64_t total = (int64_t)g.N[0] * g.N[1] * ip.ppc * ip.nrows;
+    if (total <= 0) return;
+    hipLaunchKernelGGL((k3_inject<R>), dim3((unsigned)((total + NT - 1) / NT)), dim3(NT), 0, s, g, e, ion, nused_e,
+                       nused_i, ip, status);
+}
+
+template <typename R>
+void launch3_window(const G3& g, const F3<R>& f, const Pml3& pml, int d, hipStream_t s)
+{
+    (void)pml;
+    if (d == 0) return;
+    hipLaunchKernelGGL((k3_window<R>), cells_grid(g), dim3(NT), 0, s, g, f, d);
+}
+
+template <typename R>
+void launch3_compact_e(const E3<R>& a, const E3<R>& b, int n, int* cnt, hipStream_t s)
+{
+    (void)hipMemsetAsync(cnt, 0, sizeof(int), s);
+    if (n > 0) hipLaunchKernelGGL((k3_compact_e<R>), dim3((n + NT - 1) / NT), dim3(NT), 0, s, a, b, n, cnt);
+}
+
+template <typename R>
+void launch3_compact_i(const I3<R>& a, const I3<R>& b, int n, int* cnt, hipStream_t s)
+{
+    (void)hipMemsetAsync(cnt, 0, sizeof(int), s);
+    if (n > 0) hipLaunchKernelGGL((k3_compact_i<R>), dim3((n + NT - 1) / NT), dim3(NT), 0, s, a, b, n, cnt);
+}
+
+template <typename R>
+void launch3_stations(const G3& g, const F3<R>& f, const double* zlab, int nst, double gamma, double beta,
+                      double t, double shift_cells, double* rec, int* cnt, int cap, hipStream_t s)
+{
+    if (nst <= 0) return;
+    hipLaunchKernelGGL((k3_stations<R>), dim3(1), dim3(64), 0, s, g, f, zlab, nst, gamma, beta, t, shift_cells,
+                       rec, cnt, cap);
+}
+
+#define BF3_INST(R)                                                                                           \
+    template void launch3_friedman<R>(const G3&, const F3<R>&, double, hipStream_t);                        \
+    template void launch3_faraday<R>(const G3&, const F3<R>&, const Pml3&, const double*, double, double,   \
+                                     hipStream_t);                                                          \
+    template void launch3_ampere<R>(const G3&, const F3<R>&, const R* const*, const Pml3&, double,          \
+                                    hipStream_t);                                                           \
+    template void launch3_filter<R>(const G3&, const F3<R>&, int, int, const R**, hipStream_t);             \
+    template void launch3_zero_j<R>(const G3&, const F3<R>&, hipStream_t);                                  \
+    template void launch3_push<R>(const G3&, const F3<R>&, const E3<R>&, int, const Push3&, int*,           \
+                                  hipStream_t);                                                             \
+    template void launch3_ions<R>(const G3&, const F3<R>&, const I3<R>&, int, double, double, const Push3&, \
+                                  hipStream_t);                                                             \
+    template void launch3_antenna<R>(const G3&, const F3<R>&, double*, const double*, const double*,        \
+                                     const Antenna3&, const Push3&, hipStream_t);                           \
+    template void launch3_inject<R>(const G3&, const E3<R>&, const I3<R>&, int*, int*, const Inject3&, int*, \
+                                    hipStream_t);                                                           \
+    template void launch3_window<R>(const G3&, const F3<R>&, const Pml3&, int, hipStream_t);                \
+    template void launch3_compact_e<R>(const E3<R>&, const E3<R>&, int, int*, hipStream_t);                 \
+    template void launch3_compact_i<R>(const I3<R>&, const I3<R>&, int, int*, hipStream_t);                 \
+    template void launch3_stations<R>(const G3&, const F3<R>&, const double*, int, double, double, double,  \
+                                      double, double*, int*, int, hipStream_t);
+BF3_INST(float)
+BF3_INST(double)
+
+}  // namespace bf3

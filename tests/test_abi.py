@@ -70,8 +70,18 @@ def test_query_buffers_and_validation():
             P.bf_query_buffers(_cfg(**bad))
         assert e.value.code == -1                               # BF_EINVAL
     with pytest.raises(P.BfError) as e:
-        P.bf_query_buffers(_cfg(dim=3))
+        P.bf_query_buffers(_cfg(dim=4))
     assert e.value.code == -7                                   # BF_EUNSUPPORTED
+    # 3D: needs ny and dy, keeps the bilinear filter
+    d3 = dict((n, b) for n, b, _ in P.bf_query_buffers(_cfg(dim=3, ny=16, dy_um=0.05)))
+    d2 = dict((n, b) for n, b, _ in P.bf_query_buffers(_cfg()))
+    assert d3["fields"] > d2["fields"]
+    with pytest.raises(P.BfError) as e:
+        P.bf_query_buffers(_cfg(dim=3, ny=0, dy_um=0.05))
+    assert e.value.code == -1
+    with pytest.raises(P.BfError) as e:
+        P.bf_query_buffers(_cfg(dim=3, ny=16, dy_um=0.05, filter_kind=1))
+    assert e.value.code == -7
     # window on a periodic z axis is meaningless
     with pytest.raises(P.BfError):
         P.bf_query_buffers(_cfg(periodic_mask=5, moving_window=1))

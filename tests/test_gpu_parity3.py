@@ -1,0 +1,124 @@
+"""GPU (HIP, gfx950) 3D path against the 3D FP64 oracle, element by element, through the C ABI.
+
+Errors are measured as in the 2D parity tests: max |GPU - oracle| over the grid divided by
+the physical scale of the field group (the emitted laser amplitude for E and B, the larger
+of the plasma and antenna-sheet current densities for J), never below the field's own
+maximum.  Tolerances: FP64 1e-10 (summation order of the atomics only), FP32 1e-5.
+"""
+import numpy as np
+import pytest
+
+import pic_inputs as pi
+from oracle.pic3 import Oracle3
+
+gpu = pytest.mark.gpu
+FIELDS = ["Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz"]
+
+
+def _sim(w, **kw):
+    from paper_1009_2727_amd import Sim
+    return Sim.from_workload(w, **kw)
+
+
+def field_scales(ref):
+    i = ref.info()
+    cfg = ref.config
+    g, b = i["gamma"], i["beta"]
+    e_emit = i["e0_norm"] / ((1 + b) * g) if i["e0_norm"] else 0.0
+    j_plasma = i["n0_norm"] * g
+    j_ant = 2 * i["e0_norm"] / g / cfg["dz_um"] if i["e0_norm"] else 0.0
+    return {"E": e_emit, "B": e_emit, "J": max(j_plasma, j_ant)}
+
+
+def compare_fields3(sim, ref, tol, names=FIELDS):
+    floor = field_scales(ref)
+    a = {n: sim.field(n) for n in names}
+    b = {n: ref.field(n) for n in names}
+    scale = {}
+    for n in names:
+        scale[n[0]] = max(scale.get(n[0], 0.0), np.abs(b[n]).max(), floor[n[0]])
+    errs = {n: float(np.abs(a[n] - b[n]).max() / scale[n[0]]) if scale[n[0]] > 0 else float(np.abs(a[n]).max())
+            for n in names}
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, f"field mismatch above {tol:g}: {bad} (all: {errs})"
+    return errs
+
+
+def compare_particles3(sim, ref, xtol, utol):
+    a, b = sim.particles(0), ref.particles(0)
+    assert len(a["id"]) == len(b["id"]), (len(a["id"]), len(b["id"]))
+    ia, ib = np.argsort(a["id"], kind="stable"), np.argsort(b["id"], kind="stable")
+    np.testing.assert_array_equal(a["id"][ia], b["id"][ib])
+    for k, tol in (("x", xtol), ("y", xtol), ("z", xtol), ("ux", utol), ("uy", utol), ("uz", utol)):
+        d = np.abs(a[k][ia] - b[k][ib])
+        scale = 1.0 if k in ("x", "y", "z") else max(np.abs(b[k]).max(), 1.0)
+        assert d.max() <= tol * scale, (k, d.max())
+
+
+@gpu
+def test_3d_initial_plasma_bitwise():
+    w = pi.small_boosted3(real="f64", nx=10, ny=8, nz=40, ppc=2, preload=True)
+    sim, ref = _sim(w), Oracle3.from_workload(w)
+    a, b = sim.particles(0), ref.particles(0)
+    ia, ib = np.argsort(a["id"]), np.argsort(b["id"])
+    np.testing.assert_array_equal(a["id"][ia], b["id"][ib])
+    for k in ("x", "y", "w"):
+        np.testing.assert_array_equal(a[k][ia], b[k][ib])
+    np.testing.assert_allclose(a["z"][ia], b["z"][ib], rtol=0, atol=1e-12)
+
+
+@gpu
+@pytest.mark.parametrize("real,tol,xtol", [("f64", 1e-10, 1e-9), ("f32", 1e-5, 1e-5)])
+def test_3d_boosted_matches_oracle(real, tol, xtol):
+    # C3-shaped: boosted gamma = 30, window, PML on every face, CK2 + Friedman, 4 + comp filter,
+    # rigid ions, antenna; ragged against nothing (one thread per cell / particle)
+    w = pi.small_boosted3(real=real, nx=10, ny=8, nz=40, ppc=2)
+    sim, ref = _sim(w, sort_every=7), Oracle3.from_workload(w)
+    sim.step(24)
+    ref.step(24)
+    assert sim.sync_status() == 0
+    assert sim.info()["shift"] == ref.info()["shift"] > 0
+    compare_fields3(sim, ref, tol)
+    compare_particles3(sim, ref, xtol, xtol)
+
+
+@gpu
+@pytest.mark.parametrize("real,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_3d_random_state_single_step(real, tol):
+    nx, ny, nz = 11, 9, 13   # ragged
+    d = (0.1, 0.12, 0.09)
+    cfg = pi.make_config3(nx, ny, nz, *d, periodic_x=1, periodic_y=1, periodic_z=1, pml_cells=0,
+                          ck="ck2", theta=0.3, filter_npass=2, filter_compensate=1, real=real, seed=5)
+    from paper_1009_2727_amd import Sim
+    sim = Sim(cfg, capacity=4000)
+    ref = Oracle3(cfg)
+    for k, name in enumerate(["Ex", "Ey", "Ez", "Bx", "By", "Bz", "Exo", "Eyo", "Ezo", "Exb", "Eyb", "Ezb"]):
+        f = pi.random_field(ref.shape, seed=100 + k, amp=0.5)
+        ref.set_field(name, f)
+        sim.set_field(name, f)
+    p = pi.random_electrons3(3000, nx, ny, nz, d, seed=11, umax=3.0, margin=0.0)
+    ref.set_electrons(p)
+    sim.load_electrons(p)
+    ref.step(1)
+    sim.step(1)
+    for n in FIELDS:
+        a, b = sim.field(n), ref.field(n)
+        assert np.abs(a - b).max() <= tol * max(np.abs(b).max(), 1.0), n
+    compare_particles3(sim, ref, 1e-9 if real == "f64" else 1e-5, 1e-10 if real == "f64" else 1e-5)
+
+
+@gpu
+def test_3d_vacuum_pml_matches_oracle():
+    # fields only: a solenoidal pulse through the split PML on all faces
+    w = pi.small_boosted3(real="f64", nx=10, ny=8, nz=30)
+    sim, ref = _sim(w, plasma=False, laser=False), Oracle3.from_workload(w, plasma=False, laser=False)
+    Sz, Sy, Sx = ref.shape
+    Z, Y, X = np.meshgrid(np.arange(Sz), np.arange(Sy), np.arange(Sx), indexing="ij")
+    f = np.exp(-((X - Sx / 2) ** 2 + (Z - Sz / 2) ** 2) / 8.0)
+    for o in (sim, ref):
+        o.set_field("By", f)
+    sim.step(40)
+    ref.step(40)
+    for n in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+        a, b = sim.field(n), ref.field(n)
+        assert np.abs(a - b).max() <= 1e-11 * np.abs(f).max(), n
