@@ -60,6 +60,89 @@ def bytes_model(ne: int, ni: int, nx: int, nz: int, real: int = 4):
     return gpd, step
 
 
+def bytes_model3(ne: int, ni: int, nx: int, ny: int, nz: int, real: int = 4):
+    """Algorithmic HBM bytes of the 3D step.  Per electron (FP32 momenta, FP64 positions):
+    read x,y,z (24) + u (12) + w (4), write x,y,z,u (36) = 76 B.  Per rigid ion: read x, y, z0
+    (24) + w (4) = 28 B.  Per interior cell: Friedman 9 read / 6 write words, Faraday 6 / 6,
+    gather 9 read, Ampere 9 / 6, filtered current 3 written, plus the FP64 current: cleared,
+    deposited and read by the filter (3 x 8 B each).  The gather/push/deposit kernel alone moves
+    its electrons, the 9 gathered field words and the 3 deposited FP64 words per cell."""
+    cells = nx * ny * nz
+    gpd = ne * 76 + cells * (9 * real + 24)
+    step = ne * 76 + ni * 28 + cells * ((15 + 12 + 9 + 15 + 3) * real + 72)
+    return gpd, step
+
+
+def cpu_baseline3(args):
+    """FP64 3D oracle on a bounded sample: a 32 x 32 x 64 slab of the same physics (8 ppc,
+    pre-loaded, gamma = 30), a few steps, single thread."""
+    import pic_inputs as pi
+    from oracle.pic3 import Oracle3
+    w = pi.c3(real="f64", nx=32, ny=32, nz=64, ppc=8, preload=True)
+    o = Oracle3.from_workload(w)
+    ne = len(o.particles(0)["id"])
+    o.step(1)
+    t0 = time.perf_counter()
+    o.step(args.cpu_steps3)
+    dt = time.perf_counter() - t0
+    return {"value": ne * args.cpu_steps3 / dt, "unit": "electron pushes/s", "cores": 1, "kind": "oracle",
+            "sample": f"32x32x64 slab of the same 3D workload, 8 ppc pre-loaded ({ne} electrons), "
+                      f"{args.cpu_steps3} steps after one untimed step, FP64, single thread"}
+
+
+def bench_3d(args):
+    """The 3D boosted run (gamma = 30, 128 x 128 x 1024, 8 ppc, window pre-loaded) timed over
+    the whole step; the roofline is that of the 3D gather/push/deposit kernel."""
+    import torch
+    import pic_inputs as pi
+    from paper_1009_2727_amd import Sim
+    w = pi.c3(real="f32", preload=True)
+    cfg = w["config"]
+    sim = Sim.from_workload(w, sort_every=args.sort_every, timers=True)
+    stream = sim.stream
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    c0 = sim.counts()
+    sim.timers(reset=True)
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    sim.step(args.steps)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms = t_start.elapsed_time(t_end)
+    status = sim.sync_status()
+    c1 = sim.counts()
+    timers = sim.timers(reset=True)
+    ne = 0.5 * (c0[0] + c1[0])
+    ni = 0.5 * (c0[1] + c1[1])
+    ms_step = ms / args.steps
+    gpd_bytes, step_bytes = bytes_model3(int(ne), int(ni), cfg["nx"], cfg["ny"], cfg["nz"])
+    push_ms, push_n = timers["push"]
+    gpd_ms = push_ms / max(push_n, 1)
+    achieved = gpd_bytes / (gpd_ms / 1e3) / 1e9
+    out = {
+        "metric": "particle pushes/s",
+        "value": ne * args.steps / (ms / 1e3),
+        "unit": "electron pushes/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w["name"], "grid": f"{cfg['nx']}x{cfg['ny']}x{cfg['nz']}", "ppc": 8,
+                   "gamma_boost": cfg["gamma_boost"], "electrons": int(ne), "rigid_ions": int(ni),
+                   "positions": "f64", "current_accumulation": "f64", "compact_every": sim.info()["sort_every"],
+                   "status": status},
+        "hbm_gbps_per_step": step_bytes / (ms_step / 1e3) / 1e9,
+        "phases_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in timers.items()},
+        "roofline": {"bound": "hbm", "kernel": "k3_push (gather + push + deposit)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": gpd_bytes, "avg_launch_ms": gpd_ms},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline3(args)
+    return out
+
+
 def cpu_baseline(args):
     """FP64 oracle on a bounded sample of the workload: a 256 x 256 slab of the same
     physics (16 ppc, pre-loaded), a few steps, single thread."""
@@ -307,9 +390,11 @@ def main():
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_GIB"))
-    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2",
-                    help="c2: the 256x4096 boosted run (default); c4: the batched scan of "
-                         "independent boosted runs (persistent batched launch vs one run at a time)")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
+                    help="c2: the 256x4096 boosted run (default); c3: the 3D 128x128x1024 boosted run; "
+                         "c4: the batched scan of independent boosted runs (persistent batched launch "
+                         "vs one run at a time); c5: learned vs plain current filter")
+    ap.add_argument("--cpu-steps3", type=int, default=8)
     ap.add_argument("--c4-runs", type=int, default=64)
     ap.add_argument("--c4-scale", type=float, default=1.0, help="grid scale of the scan's runs")
     ap.add_argument("--no-autotune", action="store_true")
@@ -334,6 +419,9 @@ def main():
 
     if args.workload == "c4":
         print(json.dumps(bench_scan(args)), flush=True)
+        return
+    if args.workload == "c3":
+        print(json.dumps(bench_3d(args)), flush=True)
         return
     if args.workload == "c5":
         print(json.dumps(bench_learned_filter_study(args)), flush=True)

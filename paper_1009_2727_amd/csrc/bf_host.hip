@@ -1267,11 +1267,20 @@ bf_status diagnose3(bf_sim* s, int kind, int arg, void* host_out, size_t bytes)
     }
     case BF_DIAG_COUNTS: {
         if (bytes < 4 * sizeof(int64_t)) return fail(s, BF_EINVAL, "buffer too small");
-        std::vector<double> cols[8];
-        int64_t ne = 0, ni = 0;
-        bf_status st = read_particles3(s, 0, cols, &ne);
-        if (st == BF_OK && s->have_plasma && s->plasma.ion_mode == 1) st = read_particles3(s, 1, cols, &ni);
-        if (st != BF_OK) return st;
+        // live particles counted on the device (slots of removed particles hold w = 0)
+        int* cnt = w3<int>(s, L.w_cnt);
+        int h[2] = {0, 0};
+        const bool f32 = s->cfg.real_bytes == 4;
+        for (int sp = 0; sp < 2; sp++) {
+            const int n = (int)(sp == 0 ? L.ne : L.ni);
+            const char* base = (const char*)s->buf[(sp == 0 ? 1 : 3) + L.p_cur] + (sp == 0 ? L.e_off[6] : L.i_off[3]);
+            if (f32) bf3::launch3_count_live<float>((const float*)base, n, cnt + sp, s->stream);
+            else bf3::launch3_count_live<double>((const double*)base, n, cnt + sp, s->stream);
+        }
+        hipError_t e = hipMemcpyAsync(h, cnt, sizeof h, hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return hip_check(s, e, "3D counts");
+        const int64_t ne = h[0], ni = (s->have_plasma && s->plasma.ion_mode == 1) ? h[1] : 0;
         int64_t* o = (int64_t*)host_out;
         o[0] = ne; o[1] = ni; o[2] = L.ne; o[3] = L.ni;
         return BF_OK;

@@ -113,6 +113,8 @@ template <typename R>
 void launch3_compact_e(const E3<R>& a, const E3<R>& b, int n, int* cnt, hipStream_t s);
 template <typename R>
 void launch3_compact_i(const I3<R>& a, const I3<R>& b, int n, int* cnt, hipStream_t s);
+// live particles (w != 0) among n slots into *cnt (zeroed here)
+template <typename R> void launch3_count_live(const R* w, int n, int* cnt, hipStream_t s);
 template <typename R>
 void launch3_stations(const G3& g, const F3<R>& f, const double* zlab, int nst, double gamma, double beta,
                       double t, double shift_cells, double* rec, int* cnt, int cap, hipStream_t s);

@@ -611,6 +611,15 @@ __global__ void __launch_bounds__(NT) k3_compact_i(I3<R> a, I3<R> b, int n, int*
     b.x[d] = a.x[p]; b.y[d] = a.y[p]; b.z0[d] = a.z0[p]; b.w[d] = a.w[p]; b.id[d] = a.id[p];
 }
 
+// number of live particles (w != 0) among n slots, one atomic per wave
+template <typename R>
+__global__ void __launch_bounds__(NT) k3_count_live(const R* w, int n, int* cnt)
+{
+    const int p = blockIdx.x * NT + threadIdx.x;
+    const unsigned long long m = __ballot(p < n && w[p] != R(0));
+    if (__lane_id() == 0 && m) atomicAdd(cnt, __popcll(m));
+}
+
 // trilinear sample of a component with staggers h at r (cells)
 template <typename R>
 __device__ double trilin(const G3& g, const R* F, const int h[3], const double r[3])
@@ -786,6 +795,13 @@ void launch3_compact_i(const I3<R>& a, const I3<R>& b, int n, int* cnt, hipStrea
 }
 
 template <typename R>
+void launch3_count_live(const R* w, int n, int* cnt, hipStream_t s)
+{
+    (void)hipMemsetAsync(cnt, 0, sizeof(int), s);
+    if (n > 0) hipLaunchKernelGGL((k3_count_live<R>), dim3((n + NT - 1) / NT), dim3(NT), 0, s, w, n, cnt);
+}
+
+template <typename R>
 void launch3_stations(const G3& g, const F3<R>& f, const double* zlab, int nst, double gamma, double beta,
                       double t, double shift_cells, double* rec, int* cnt, int cap, hipStream_t s)
 {
@@ -802,6 +818,7 @@ void launch3_stations(const G3& g, const F3<R>& f, const double* zlab, int nst, 
                                     hipStream_t);                                                           \
     template void launch3_filter<R>(const G3&, const F3<R>&, int, int, const R**, hipStream_t);             \
     template void launch3_zero_j<R>(const G3&, const F3<R>&, hipStream_t);                                  \
+    template void launch3_count_live<R>(const R*, int, int*, hipStream_t);                                  \
     template void launch3_push<R>(const G3&, const F3<R>&, const E3<R>&, int, const Push3&, int*,           \
                                   hipStream_t);                                                             \
     template void launch3_ions<R>(const G3&, const F3<R>&, const I3<R>&, int, double, double, const Push3&, \
