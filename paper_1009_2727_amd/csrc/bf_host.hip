@@ -773,17 +773,21 @@ bf_status step_impl(bf_sim* s, int nsteps)
 // ---- 3D runs -----------------------------------------------------------------------------------
 // The same C ABI drives the 3D step (bf_config.dim == 3): fields [z][y][x] with a ring of z
 // planes, SoA particles with x, y, z, and the 3D kernels of bf_sim3.hip.  Particles live in one
-// of two copies; every sort_every steps the live ones are compacted into the other copy.
+// of two copies; every sort_every steps the live ones are sorted by tile into the other copy.
 
 struct Sim3 {
     bf3::G3 g{};
     size_t fa = 0, fa8 = 0, fields_bytes = 0;   // bytes per array (run's type, FP64)
     size_t e_off[8] = {}, e_bytes = 0, i_off[5] = {}, i_bytes = 0;
     size_t w_status = 0, w_nused = 0, w_cnt = 0, w_pml = 0, w_ant = 0, w_st_z = 0, w_st_rec = 0, w_st_cnt = 0,
+           w_seg_e = 0, w_seg_i = 0, w_box_e[2] = {}, w_box_i[2] = {}, w_counts = 0, w_cursor = 0, w_tot = 0,
+           w_lists = 0, w_mis = 0,
            w_bytes = 0;
     int64_t cap = 0;
-    int nst_max = 0, stcap = 1, p_cur = 0, since_compact = 0;
-    int64_t ne = 0, ni = 0;   // slots in use (host mirror of the device counters)
+    int nst_max = 0, stcap = 1, p_cur = 0, since_sort = 0;
+    bf3::Tiles3 tl{};
+    int seg_cap = 0, nseg = 0, bb_cur = 0;   // segments (tiles of the last sort, then injected chunks)
+    int pz = 0;                              // z planes of the LDS box
     int na = 0;
 };
 
@@ -840,11 +844,35 @@ void layout3(const bf_config* c, Sim3* L)
     L->i_bytes = std::max<size_t>(o, 256);
     L->nst_max = std::max(c->max_stations, 0);
     L->stcap = std::max(c->station_capacity, 1);
+    // particle tiles: t x t transverse (the LDS box pitch leaves room for the stencil reach and
+    // one cell of spread) by tz cells along z
+    const int tt = std::min(std::max(c->tile_x > 0 ? c->tile_x : 8, 1), bf3::BOX_PX - 6);
+    const int tz = std::max(c->tile_z > 0 ? c->tile_z : (real == 4 ? 10 : 4), 1);
+    const int tv[3] = {tt, tt, tz};
+    L->tl.ntiles = 1;
+    for (int a = 0; a < 3; a++) {
+        L->tl.t[a] = tv[a];
+        L->tl.nt[a] = (N[a] + tv[a] - 1) / tv[a];
+        L->tl.ntiles *= L->tl.nt[a];
+    }
+    const int sort_every = c->sort_every > 0 ? c->sort_every : 20;
+    L->seg_cap = L->tl.ntiles + L->tl.nt[0] * L->tl.nt[1] * (3 * sort_every + 16);
     o = 0;
     auto take = [&](size_t b) { size_t r = o; o = align_up(o + b, 256); return r; };
     L->w_status = take(16);
     L->w_nused = take(16);
     L->w_cnt = take(16);
+    L->w_tot = take(16);
+    L->w_seg_e = take(sizeof(bf3::Seg3) * L->seg_cap);
+    L->w_seg_i = take(sizeof(bf3::Seg3) * L->seg_cap);
+    for (int k = 0; k < 2; k++) {
+        L->w_box_e[k] = take(sizeof(bf3::Box3) * L->seg_cap);
+        L->w_box_i[k] = take(sizeof(bf3::Box3) * L->seg_cap);
+    }
+    L->w_counts = take(sizeof(int) * L->tl.ntiles);
+    L->w_lists = take(sizeof(int) * (2 + (size_t)L->seg_cap));
+    L->w_mis = take(sizeof(int) * 2 * (size_t)L->cap);
+    L->w_cursor = take(sizeof(int) * L->tl.ntiles);
     L->w_pml = take(sizeof(double) * 3 * 2 * 3 * (size_t)(L->g.S[0] + L->g.S[1] + L->g.S[2]));
     L->w_ant = take(sizeof(double) * 3 * (size_t)N[0] * N[1]);
     L->w_st_z = take(sizeof(double) * std::max(L->nst_max, 1));
@@ -969,6 +997,16 @@ bf_status create3(const bf_config* cfg, const bf_buffer_binding* b, int n, void*
     s->dt = cfg->cfl_fraction * s->dt_crit;
     s->sort_every = cfg->sort_every > 0 ? cfg->sort_every : 20;
     update_window_speed(s);
+    {
+        // z planes of the LDS box: the tile, one cell of drift and the stencil reach, as far as
+        // the workgroup's LDS allows
+        int dev = 0, lds_max = 65536;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        const int cell = cfg->real_bytes == 4 ? bf3::box_cell_bytes<float>() : bf3::box_cell_bytes<double>();
+        const int fit = lds_max / (bf3::BOX_PX * bf3::BOX_PY * cell);
+        s->d3->pz = std::min(s->d3->tl.t[2] + 7, fit);
+    }
     hipError_t e = hipSuccess;
     for (int k = 0; k < 6 && e == hipSuccess; k++) e = hipMemsetAsync(s->buf[k], 0, sizes[k], s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -979,10 +1017,59 @@ bf_status create3(const bf_config* cfg, const bf_buffer_binding* b, int n, void*
 }
 
 template <typename R>
+bf3::Seg3* seg3(const bf_sim* s, int species)
+{
+    return w3<bf3::Seg3>(s, species == 0 ? s->d3->w_seg_e : s->d3->w_seg_i);
+}
+
+bf3::Box3* box3(const bf_sim* s, int species, int k)
+{
+    return w3<bf3::Box3>(s, species == 0 ? s->d3->w_box_e[k] : s->d3->w_box_i[k]);
+}
+
+// ions' boosted position in the current window frame: z = z0 - zshift3
+double zshift3(const bf_sim* s, double t)
+{
+    return s->beta * t / s->cfg.dz_um + (double)s->shift;
+}
+
+// counting sort of both species by tile (drops removed particles); segments = tiles
+template <typename R>
+void sort3(bf_sim* s)
+{
+    Sim3& L = *s->d3;
+    const int a = L.p_cur, b = 1 - a;
+    int* nu = w3<int>(s, L.w_nused);
+    int *cnt = w3<int>(s, L.w_counts), *cur = w3<int>(s, L.w_cursor), *tot = w3<int>(s, L.w_tot);
+    bf3::launch3_sort_e<R>(L.g, L.tl, electrons3<R>(s, a), electrons3<R>(s, b), nu, cnt, cur, tot, seg3<R>(s, 0),
+                           box3(s, 0, L.bb_cur), L.cap, s->stream);
+    if (s->have_plasma && s->plasma.ion_mode == 1)
+        bf3::launch3_sort_i<R>(L.g, L.tl, ions3<R>(s, a), ions3<R>(s, b), zshift3(s, s->t), nu + 1, cnt, cur,
+                               tot + 1, seg3<R>(s, 1), box3(s, 1, L.bb_cur), L.cap, s->stream);
+    L.p_cur = b;
+    L.nseg = L.tl.ntiles;
+    L.since_sort = 0;
+}
+
+template <typename R>
 hipError_t inject3(bf_sim* s, int64_t nrows)
 {
     Sim3& L = *s->d3;
     if (nrows <= 0) return hipSuccess;
+    const int chunks = L.tl.nt[0] * L.tl.nt[1];
+    if (L.nseg + nrows * chunks > L.seg_cap) sort3<R>(s);
+    if (L.nseg + nrows * chunks > L.seg_cap) {
+        // more planes than one table holds (the initial load of a long box): in parts
+        const int64_t per = std::max<int64_t>(1, (L.seg_cap - L.nseg) / chunks);
+        while (nrows > 0) {
+            const int64_t n = std::min(nrows, per);
+            hipError_t e = inject3<R>(s, n);
+            if (e != hipSuccess) return e;
+            nrows -= n;
+            if (nrows > 0) sort3<R>(s);
+        }
+        return hipSuccess;
+    }
     bf3::Inject3 ip;
     ip.row0 = s->next_row;
     ip.nrows = (int)nrows;
@@ -1002,34 +1089,23 @@ hipError_t inject3(bf_sim* s, int64_t nrows)
     ip.uz0 = -s->gamma * s->beta;
     ip.shift = (double)s->shift;
     int* nu = w3<int>(s, L.w_nused);
-    bf3::launch3_inject<R>(L.g, electrons3<R>(s, L.p_cur), ions3<R>(s, L.p_cur), nu, nu + 1, ip,
+    bf3::launch3_inject<R>(L.g, L.tl, electrons3<R>(s, L.p_cur), ions3<R>(s, L.p_cur), nu, nu + 1, seg3<R>(s, 0),
+                           box3(s, 0, L.bb_cur), seg3<R>(s, 1), box3(s, 1, L.bb_cur), L.nseg, ip,
                            w3<int>(s, L.w_status), s->stream);
-    const int64_t add = (int64_t)L.g.N[0] * L.g.N[1] * s->plasma.ppc * nrows;
-    L.ne = std::min(L.ne + add, L.cap);
-    if (s->plasma.ion_mode) L.ni = std::min(L.ni + add, L.cap);
+    L.nseg += (int)nrows * chunks;
     s->next_row += nrows;
     return hipGetLastError();
 }
 
-// live particles into the other copy; the device counts become the new slot counts
-template <typename R>
-hipError_t compact3(bf_sim* s)
+// particle slots in use of a species (synchronous read of the device counter)
+hipError_t slots3(bf_sim* s, int species, int64_t* n)
 {
-    Sim3& L = *s->d3;
-    const int a = L.p_cur, b = 1 - a;
-    int* cnt = w3<int>(s, L.w_cnt);
-    bf3::launch3_compact_e<R>(electrons3<R>(s, a), electrons3<R>(s, b), (int)L.ne, cnt, s->stream);
-    bf3::launch3_compact_i<R>(ions3<R>(s, a), ions3<R>(s, b), (int)L.ni, cnt + 1, s->stream);
-    int h[2] = {0, 0};
-    hipError_t e = hipMemcpyAsync(h, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s->stream);
+    int v = 0;
+    hipError_t e = hipMemcpyAsync(&v, w3<int>(s, s->d3->w_nused) + species, sizeof(int), hipMemcpyDeviceToHost,
+                                  s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (e != hipSuccess) return e;
-    L.ne = h[0];
-    L.ni = s->plasma.ion_mode ? h[1] : 0;
-    L.p_cur = b;
-    L.since_compact = 0;
-    int nu[2] = {h[0], h[1]};
-    return hipMemcpy(w3<int>(s, L.w_nused), nu, sizeof nu, hipMemcpyHostToDevice);
+    *n = v;
+    return e;
 }
 
 template <typename R>
@@ -1062,12 +1138,17 @@ bf_status step3(bf_sim* s, int nsteps)
         pp.shift = (double)dsh;
         ev = s->tick();
         bf3::launch3_zero_j<R>(g, f, s->stream);
-        bf3::launch3_push<R>(g, f, electrons3<R>(s, L.p_cur), (int)L.ne, pp, w3<int>(s, L.w_status), s->stream);
+        bf3::launch3_gpd<R>(g, f, electrons3<R>(s, L.p_cur), seg3<R>(s, 0), box3(s, 0, L.bb_cur),
+                            box3(s, 0, 1 - L.bb_cur), L.nseg, pp, L.pz, w3<int>(s, L.w_status), w3<int>(s, L.w_lists),
+                            w3<int2>(s, L.w_mis), s->stream);
         s->tock(ev, BF_PHASE_PUSH);
         ev = s->tick();
         if (s->have_plasma && s->plasma.ion_mode == 1)
-            bf3::launch3_ions<R>(g, f, ions3<R>(s, L.p_cur), (int)L.ni, s->beta * s->t / d[2] + (double)s->shift,
-                                 s->beta * t1 / d[2] + (double)s->shift, pp, s->stream);
+            bf3::launch3_gpi<R>(g, f, ions3<R>(s, L.p_cur), seg3<R>(s, 1), box3(s, 1, L.bb_cur),
+                                box3(s, 1, 1 - L.bb_cur), L.nseg, s->beta * s->t / d[2] + (double)s->shift,
+                                s->beta * t1 / d[2] + (double)s->shift, s->beta * t1 / d[2] + (double)sn, pp, L.pz,
+                                s->stream);
+        L.bb_cur ^= 1;
         s->tock(ev, BF_PHASE_IONS);
         ev = s->tick();
         if (s->have_laser) {
@@ -1114,11 +1195,10 @@ bf_status step3(bf_sim* s, int nsteps)
         hipError_t e = inject3<R>(s, rows_entering(s));
         s->tock(ev, BF_PHASE_WINDOW);
         if (e != hipSuccess) return hip_check(s, e, "3D injection");
-        if (++L.since_compact >= s->sort_every && s->have_plasma) {
+        if (++L.since_sort >= s->sort_every) {
             ev = s->tick();
-            e = compact3<R>(s);
+            sort3<R>(s);
             s->tock(ev, BF_PHASE_SORT);
-            if (e != hipSuccess) return hip_check(s, e, "3D compaction");
         }
     }
     return hip_check(s, hipGetLastError(), "3D step launch");
@@ -1216,7 +1296,9 @@ bf_status write_field3(bf_sim* s, int a, const double* in)
 bf_status read_particles3(bf_sim* s, int species, std::vector<double>* cols, int64_t* nlive)
 {
     const Sim3& L = *s->d3;
-    const int64_t n = species == 0 ? L.ne : L.ni;
+    int64_t n = 0;
+    hipError_t e0 = slots3(s, species, &n);
+    if (e0 != hipSuccess) return hip_check(s, e0, "3D read particles");
     const bool f32 = s->cfg.real_bytes == 4;
     const size_t rb = s->cfg.real_bytes;
     const char* b = (const char*)s->buf[(species == 0 ? 1 : 3) + L.p_cur];
@@ -1272,17 +1354,23 @@ bf_status diagnose3(bf_sim* s, int kind, int arg, void* host_out, size_t bytes)
         int h[2] = {0, 0};
         const bool f32 = s->cfg.real_bytes == 4;
         for (int sp = 0; sp < 2; sp++) {
-            const int n = (int)(sp == 0 ? L.ne : L.ni);
+            int64_t n = 0;
+            hipError_t es = slots3(s, sp, &n);
+            if (es != hipSuccess) return hip_check(s, es, "3D counts");
             const char* base = (const char*)s->buf[(sp == 0 ? 1 : 3) + L.p_cur] + (sp == 0 ? L.e_off[6] : L.i_off[3]);
-            if (f32) bf3::launch3_count_live<float>((const float*)base, n, cnt + sp, s->stream);
-            else bf3::launch3_count_live<double>((const double*)base, n, cnt + sp, s->stream);
+            if (f32) bf3::launch3_count_live<float>((const float*)base, (int)n, cnt + sp, s->stream);
+            else bf3::launch3_count_live<double>((const double*)base, (int)n, cnt + sp, s->stream);
         }
         hipError_t e = hipMemcpyAsync(h, cnt, sizeof h, hipMemcpyDeviceToHost, s->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
         if (e != hipSuccess) return hip_check(s, e, "3D counts");
         const int64_t ne = h[0], ni = (s->have_plasma && s->plasma.ion_mode == 1) ? h[1] : 0;
         int64_t* o = (int64_t*)host_out;
-        o[0] = ne; o[1] = ni; o[2] = L.ne; o[3] = L.ni;
+        int64_t se = 0, si = 0;
+        e = slots3(s, 0, &se);
+        if (e == hipSuccess) e = slots3(s, 1, &si);
+        if (e != hipSuccess) return hip_check(s, e, "3D counts");
+        o[0] = ne; o[1] = ni; o[2] = se; o[3] = si;
         return BF_OK;
     }
     case BF_DIAG_PARTICLES: {
@@ -1608,9 +1696,13 @@ bf_status bf_load_electrons3(bf_sim* s, int64_t n, const uint32_t* id, const dou
     std::vector<uint32_t> hid(n);
     for (int64_t p = 0; p < n; p++) hid[p] = id ? id[p] : (uint32_t)p;
     if (e == hipSuccess && n > 0) e = hipMemcpy(b + L.e_off[7], hid.data(), n * 4, hipMemcpyHostToDevice);
-    L.ne = n;
-    int nu[2] = {(int)n, (int)L.ni};
-    if (e == hipSuccess) e = hipMemcpy(w3<int>(s, L.w_nused), nu, sizeof nu, hipMemcpyHostToDevice);
+    const int nu = (int)n;
+    if (e == hipSuccess) e = hipMemcpy(w3<int>(s, L.w_nused), &nu, sizeof nu, hipMemcpyHostToDevice);
+    // bin the loaded particles (and any plasma) by tile
+    if (e == hipSuccess) {
+        if (f32) sort3<float>(s); else sort3<double>(s);
+        e = hipStreamSynchronize(s->stream);
+    }
     return hip_check(s, e, "load_electrons3");
 }
 
@@ -2171,9 +2263,10 @@ bf_status bf_get_state(const bf_sim* s, bf_state* o)
     o->p_cur = s->p_cur;
     o->nseg_e = s->nseg_e; o->nseg_i = s->nseg_i; o->since_sort = s->since_sort;
     o->have_plasma = s->have_plasma; o->have_laser = s->have_laser; o->nstations = s->nst;
-    if (s->d3) {   // 3D: particle slots in use in place of the segment counts
-        o->zoff = s->d3->g.zoff; o->p_cur = s->d3->p_cur; o->since_sort = s->d3->since_compact;
-        o->nseg_e = (int32_t)s->d3->ne; o->nseg_i = (int32_t)s->d3->ni;
+    if (s->d3) {   // 3D: one segment table per species, both of nseg segments
+        o->zoff = s->d3->g.zoff; o->p_cur = s->d3->p_cur; o->since_sort = s->d3->since_sort;
+        o->nseg_e = o->nseg_i = s->d3->nseg;
+        o->e_cur = s->d3->bb_cur << 2;
     }
     return BF_OK;
 }
@@ -2183,12 +2276,12 @@ bf_status bf_set_state(bf_sim* s, const bf_state* in)
     if (!s || !in || in->abi_version != BF_ABI_VERSION || in->struct_size != sizeof(bf_state)) return BF_EINVAL;
     if (s->d3) {
         Sim3& L3 = *s->d3;
-        if (in->zoff < 0 || in->zoff >= L3.g.S[2] || in->nseg_e < 0 || in->nseg_e > L3.cap || in->nseg_i < 0 ||
-            in->nseg_i > L3.cap)
+        if (in->zoff < 0 || in->zoff >= L3.g.S[2] || in->nseg_e < 0 || in->nseg_e > L3.seg_cap ||
+            in->nseg_i != in->nseg_e)
             return BF_EINVAL;
         s->step = in->step; s->t = in->time; s->shift = in->shift; s->next_row = in->next_row;
-        L3.g.zoff = in->zoff; L3.p_cur = in->p_cur & 1; L3.since_compact = in->since_sort;
-        L3.ne = in->nseg_e; L3.ni = in->nseg_i;
+        L3.g.zoff = in->zoff; L3.p_cur = in->p_cur & 1; L3.since_sort = in->since_sort;
+        L3.nseg = in->nseg_e; L3.bb_cur = (in->e_cur >> 2) & 1;
         return BF_OK;
     }
     if (in->zoff < 0 || in->zoff >= s->L.Sz || in->nseg_e < 0 || in->nseg_e > s->L.seg_cap) return BF_EINVAL;

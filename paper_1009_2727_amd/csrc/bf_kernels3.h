@@ -63,6 +63,20 @@ struct Push3 {
     double shift;       // whole cells the window moves at the end of this step
 };
 
+// particle segment: a contiguous index range whose particles share a cell box
+struct Seg3 { int start, count; };
+// cell bounding box (interior cells, inclusive); empty when lo > hi
+struct Box3 { int lo[3], hi[3]; };
+// tiles of the particle sort: t cells per tile along each axis, nt tiles per axis
+struct Tiles3 { int t[3]; int nt[3]; int ntiles; };
+
+// LDS box of the particle kernels: a segment's cell box widened by the stencil reach (2 cells
+// below, 3 above) must fit BOX_PX x BOX_PY cells transversely and the run's plane count in z
+constexpr int BOX_PX = 14, BOX_PY = 14;
+// LDS bytes per box cell of the electron kernel: 6 field components in the run's type and 3
+// current accumulators of 8 bytes
+template <typename R> constexpr int box_cell_bytes() { return 6 * (int)sizeof(R) + 24; }
+
 struct Inject3 {
     int64_t row0;
     int nrows, ppc, ion_mode;
@@ -93,26 +107,41 @@ void launch3_ampere(const G3& g, const F3<R>& f, const R* const J[3], const Pml3
 template <typename R>
 void launch3_filter(const G3& g, const F3<R>& f, int npass, int comp, const R* out[3], hipStream_t s);
 template <typename R> void launch3_zero_j(const G3& g, const F3<R>& f, hipStream_t s);
+// gather, push and deposit of the electrons of nseg segments (one workgroup each); bin holds
+// each segment's cell box at the start of the step, bout receives the box after the push (in
+// the next window frame); pz = z planes of the LDS box
+// lists: 2 + nseg ints of scratch, mis: one int2 per particle slot (particles outside their
+// segment's box and segments too large for LDS are pushed in a second pass, on HBM)
 template <typename R>
-void launch3_push(const G3& g, const F3<R>& f, const E3<R>& e, int n, const Push3& pp, int* status, hipStream_t s);
+void launch3_gpd(const G3& g, const F3<R>& f, const E3<R>& e, const Seg3* seg, const Box3* bin, Box3* bout,
+                 int nseg, const Push3& pp, int pz, int* status, int* lists, int2* mis, hipStream_t s);
+// rigid-ion J_z of nseg segments: z = z0 - zsa at t_n, z0 - zsb at t_{n+1}, z0 - zsn in the
+// next window frame (for the boxes)
 template <typename R>
-void launch3_ions(const G3& g, const F3<R>& f, const I3<R>& ion, int n, double za_shift, double zb_shift,
-                  const Push3& pp, hipStream_t s);
+void launch3_gpi(const G3& g, const F3<R>& f, const I3<R>& ion, const Seg3* seg, const Box3* bin, Box3* bout,
+                 int nseg, double zsa, double zsb, double zsn, const Push3& pp, int pz, hipStream_t s);
 template <typename R>
 void launch3_antenna(const G3& g, const F3<R>& f, double* xm, const double* xh, const double* yh,
                      const Antenna3& a, const Push3& pp, hipStream_t s);
+// lattice planes into slots nused.. of both species, laid out in transverse tile chunks; chunk
+// c of plane r becomes segment seg_base + r * chunks + c (table and box of each species)
 template <typename R>
-void launch3_inject(const G3& g, const E3<R>& e, const I3<R>& ion, int* nused_e, int* nused_i,
-                    const Inject3& ip, int* status, hipStream_t s);
+void launch3_inject(const G3& g, const Tiles3& tl, const E3<R>& e, const I3<R>& ion, int* nused_e, int* nused_i,
+                    Seg3* seg_e, Box3* box_e, Seg3* seg_i, Box3* box_i, int seg_base, const Inject3& ip,
+                    int* status, hipStream_t s);
 // window moved by d planes (zoff already advanced): clear the planes that wrapped round, drop
 // split parts in planes that just left the z PML, keep tangential E zero on the end walls
 template <typename R>
 void launch3_window(const G3& g, const F3<R>& f, const Pml3& pml, int d, hipStream_t s);
-// compaction of live particles (w != 0) from a into b; counters in cnt (zeroed here)
+// counting sort of the live particles (w != 0) of slots [0, *nused) of src by tile into dst:
+// segment t = tile t with its cell box, *nused = live count; counts/cursor hold ntiles ints,
+// tot one int of scratch.  Ions are binned at z0 - zsh.
 template <typename R>
-void launch3_compact_e(const E3<R>& a, const E3<R>& b, int n, int* cnt, hipStream_t s);
+void launch3_sort_e(const G3& g, const Tiles3& tl, const E3<R>& src, const E3<R>& dst, int* nused, int* counts,
+                    int* cursor, int* tot, Seg3* seg, Box3* box, int64_t cap, hipStream_t s);
 template <typename R>
-void launch3_compact_i(const I3<R>& a, const I3<R>& b, int n, int* cnt, hipStream_t s);
+void launch3_sort_i(const G3& g, const Tiles3& tl, const I3<R>& src, const I3<R>& dst, double zsh, int* nused,
+                    int* counts, int* cursor, int* tot, Seg3* seg, Box3* box, int64_t cap, hipStream_t s);
 // live particles (w != 0) among n slots into *cnt (zeroed here)
 template <typename R> void launch3_count_live(const R* w, int n, int* cnt, hipStream_t s);
 template <typename R>

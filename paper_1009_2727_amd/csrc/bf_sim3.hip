@@ -12,10 +12,13 @@
 //   * n-pass bilinear filter plus compensation along x, y and z (Sec. 4.1);
 //   * laser sheets on a lab-fixed plane with one +/- pair per transverse cell (Sec. 3.1.2);
 //   * moving window as a ring offset of the z planes, plane-wise plasma injection.
-// This first 3D path is written for correctness: one thread per cell for the field stages and
-// one per particle for the particle stages, fields read from HBM and the current deposited
-// with global atomics.
+// Field stages run one thread per cell on the arrays in HBM.  Particles are binned by tile
+// (periodic counting sort) and pushed one segment per workgroup on an LDS-staged box; the
+// deposited current is summed in FP64 in HBM (fixed point or FP64 in LDS).
 #include "bf_kernels3.h"
+#include "bf_device.h"
+#include <algorithm>
+#include <climits>
 #include <cmath>
 
 namespace bf3 {
@@ -362,17 +365,290 @@ __device__ __forceinline__ R rsq(R x)
     else return 1.0 / sqrt(x);
 }
 
-template <typename R>
-__global__ void __launch_bounds__(NT) k3_push(G3 g, F3<R> f, E3<R> e, int n, Push3 pp, int* status)
+// ---- particles: segments staged in LDS --------------------------------------------------------
+//
+// One workgroup per particle segment: a tile of the last sort, or a transverse chunk of a
+// plane injected since.  The segment's cell box, widened by the stencil reach (2 cells below,
+// 3 above), is staged in LDS: E^n and B^n = (B^{n-1/2} + B^{n+1/2}) / 2 in the run's type and a
+// zeroed current accumulator.  Each thread gathers, pushes and deposits its particles into
+// the accumulator, then the box is added to the FP64 current in HBM with one atomic per cell
+// and component.  FP32 runs accumulate in 64-bit integer fixed point, exact and independent
+// of the order of the adds: a contribution v becomes round(v / q), q = max|k| sum|w| / 2^46
+// over the segment, through one FMA with 1.5 * 2^52 whose bit pattern is 0x4338000000000000 +
+// round(v / q); the low 48 bits of the raw sum, sign-extended, are the exact sum.  FP64 runs
+// add in FP64.  A particle whose cell lies outside its segment's box, and every particle of a
+// segment whose box exceeds the LDS pitches, takes the same steps on the fields and current
+// in HBM.
+
+constexpr int GT = 512;        // threads of a segment workgroup
+constexpr int HBM_GRID = 1024; // workgroups of the pass over the particles left to HBM
+constexpr int BPX = BOX_PX, BPY = BOX_PY, BPL = BOX_PX * BOX_PY;
+
+template <typename R> struct Acc3 { using T = double; static constexpr bool fixed = false; };
+template <> struct Acc3<float> { using T = unsigned long long; static constexpr bool fixed = true; };
+constexpr double FX_MAGIC = 6755399441055744.0;   // 1.5 * 2^52
+constexpr double FX_RANGE = 70368744177664.0;     // 2^46
+
+__device__ __forceinline__ double fx_value(unsigned long long t)
 {
-    const int p = blockIdx.x * NT + threadIdx.x;
-    if (p >= n) return;
+    return (double)((long long)(t << 16) >> 16);
+}
+
+// stride of axis a in the LDS box (cells)
+__host__ __device__ constexpr int bstride(int a) { return a == 0 ? 1 : (a == 1 ? BPX : BPL); }
+
+template <typename R>
+struct BoxL {
+    using JT = typename Acc3<R>::T;
+    JT* j;         // current planes of n cells (3 for electrons, J_z only for ions)
+    R* f;          // 6 field planes of n cells: E x, y, z and B x, y, z (time-centred)
+    int n;         // cells per plane: BPL * planes
+    int lo[3];     // interior cell index of box cell (0, 0, 0)
+    int ext[3];    // box extent (cells)
+};
+
+template <typename R>
+__device__ __forceinline__ void jadd(typename Acc3<R>::T* p, double a, double b)
+{
+    if constexpr (Acc3<R>::fixed) atomicAdd(p, (unsigned long long)__double_as_longlong(fma(a, b, FX_MAGIC)));
+    else atomicAdd(p, a * b);
+}
+
+template <typename R>
+__device__ __forceinline__ double jvalue(typename Acc3<R>::T t, double jq)
+{
+    if constexpr (Acc3<R>::fixed) return fx_value(t) * jq;
+    else return t;
+}
+
+// the cell of r and its stencils lie inside the box
+template <typename R>
+__device__ __forceinline__ bool in_box(const BoxL<R>& bx, const double r[3])
+{
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int c = (int)floor(r[a]);
+        in = in && c - 2 >= bx.lo[a] && c + 3 < bx.lo[a] + bx.ext[a];
+    }
+    return in;
+}
+
+// gather of E^n, B^n at r from the staged box, cubic weights at each component's stagger
+template <typename R>
+__device__ __forceinline__ void gather_box(const BoxL<R>& bx, const double r[3], R E[3], R B[3])
+{
+    R w[3][2][4];
+    int ob[3][2];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const double xs = r[a] - 0.5 * h;
+            const int j0 = (int)floor(xs);
+            bspline4((R)(xs - j0), w[a][h]);
+            ob[a][h] = (j0 - 1 - bx.lo[a]) * bstride(a);
+        }
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+        const int hx = c < 3 ? (c == 0) : (c != 3), hy = c < 3 ? (c == 1) : (c != 4), hz = c < 3 ? (c == 2) : (c != 5);
+        const R* F = bx.f + c * bx.n + ob[0][hx] + ob[1][hy] + ob[2][hz];
+        R acc = R(0);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            R tk = R(0);
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const R* row = F + j * BPX + k * BPL;
+                const R rr = w[0][hx][0] * row[0] + w[0][hx][1] * row[1] + w[0][hx][2] * row[2] + w[0][hx][3] * row[3];
+                tk += w[1][hy][j] * rr;
+            }
+            acc += w[2][hz][k] * tk;
+        }
+        if (c < 3) E[c] = acc;
+        else B[c - 3] = acc;
+    }
+}
+
+// Esirkepov's 3D deposit into the box: with (C, A1, A2) cyclic and T = S0_A1 (S0_A2 + DS_A2 / 2)
+// + DS_A1 (S0_A2 / 2 + DS_A2 / 3) (the four-term weight regrouped), J_C at node base + m along
+// C gains k_C (DS_C[0] + ... + DS_C[m]) T(m1, m2)
+template <typename R>
+__device__ __forceinline__ void deposit_box(const BoxL<R>& bx, const double r0[3], const double r1[3],
+                                            const double k[3])
+{
+    double S0[3][5], DS[3][5];
+    int base = 0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int i0 = (int)floor(r0[a]), i1 = (int)floor(r1[a]);
+        const int b = min(i0, i1) - 1;
+        double s1[5];
+        window5(r0[a] - i0, i0 > b + 1, S0[a]);
+        window5(r1[a] - i1, i1 > b + 1, s1);
+#pragma unroll
+        for (int m = 0; m < 5; m++) DS[a][m] = s1[m] - S0[a][m];
+        base += (b - bx.lo[a]) * bstride(a);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+        double P[5], Q[5], kp[4];
+#pragma unroll
+        for (int m = 0; m < 5; m++) {
+            P[m] = S0[a2][m] + 0.5 * DS[a2][m];
+            Q[m] = 0.5 * S0[a2][m] + (1.0 / 3.0) * DS[a2][m];
+        }
+        double pd = 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            pd += DS[c][m];
+            kp[m] = k[c] * pd;
+        }
+        typename Acc3<R>::T* J = bx.j + c * bx.n + base;
+#pragma unroll
+        for (int m1 = 0; m1 < 5; m1++)
+#pragma unroll
+            for (int m2 = 0; m2 < 5; m2++) {
+                const double T = S0[a1][m1] * P[m2] + DS[a1][m1] * Q[m2];
+#pragma unroll
+                for (int mc = 0; mc < 4; mc++)
+                    jadd<R>(J + mc * bstride(c) + m1 * bstride(a1) + m2 * bstride(a2), kp[mc], T);
+            }
+    }
+}
+
+// the same for a rigid ion moving along z only (x, y fixed): T = Sx Sy on 4 x 4 nodes
+template <typename R>
+__device__ __forceinline__ void deposit_box_z(const BoxL<R>& bx, double x, double y, double z0, double z1, double kz)
+{
+    const int ix = (int)floor(x), iy = (int)floor(y), i0 = (int)floor(z0), i1 = (int)floor(z1);
+    const int b = min(i0, i1) - 1;
+    double Sx[5], Sy[5], S0[5], S1[5], kp[4];
+    window5(x - ix, false, Sx);
+    window5(y - iy, false, Sy);
+    window5(z0 - i0, i0 > b + 1, S0);
+    window5(z1 - i1, i1 > b + 1, S1);
+    double pd = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+        pd += S1[m] - S0[m];
+        kp[m] = kz * pd;
+    }
+    typename Acc3<R>::T* J = bx.j + (ix - 1 - bx.lo[0]) + (iy - 1 - bx.lo[1]) * BPX + (b - bx.lo[2]) * BPL;
+#pragma unroll
+    for (int m1 = 0; m1 < 4; m1++)
+#pragma unroll
+        for (int m2 = 0; m2 < 4; m2++) {
+            const double T = Sx[m1] * Sy[m2];
+#pragma unroll
+            for (int mc = 0; mc < 4; mc++) jadd<R>(J + mc * BPL + m2 * BPX + m1, kp[mc], T);
+        }
+}
+
+// stage the box: fields (electrons) and zeroed accumulators (nj planes)
+template <typename R, bool FIELDS>
+__device__ void stage_box(const G3& g, const F3<R>& f, const BoxL<R>& bx, int nj)
+{
+    const int L = bx.ext[0] * bx.ext[1] * bx.ext[2];
+    for (int q = threadIdx.x; q < L; q += GT) {
+        const int a = q % bx.ext[0], b = (q / bx.ext[0]) % bx.ext[1], c = q / (bx.ext[0] * bx.ext[1]);
+        const int t = a + BPX * b + BPL * c;
+        if constexpr (FIELDS) {
+            const int si = sidx(g, 0, bx.lo[0] + a), sj = sidx(g, 1, bx.lo[1] + b), sk = sidx(g, 2, bx.lo[2] + c);
+            R v[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+            if (si >= 0 && sj >= 0 && sk >= 0) {
+                const long o = o3(g, si, sj, sk);
+#pragma unroll
+                for (int cc = 0; cc < 3; cc++) {
+                    v[cc] = f.E[cc][o];
+                    v[3 + cc] = R(0.5) * (f.B[cc][o] + f.Bo[cc][o]);
+                }
+            }
+#pragma unroll
+            for (int cc = 0; cc < 6; cc++) bx.f[cc * bx.n + t] = v[cc];
+        }
+        for (int cc = 0; cc < nj; cc++) bx.j[cc * bx.n + t] = typename Acc3<R>::T(0);
+    }
+}
+
+// add the box's accumulators to the FP64 current (planes c0 .. c0 + nj - 1 of J)
+template <typename R>
+__device__ void flush_box(const G3& g, const F3<R>& f, const BoxL<R>& bx, int c0, int nj, double jq)
+{
+    const int L = bx.ext[0] * bx.ext[1] * bx.ext[2];
+    for (int q = threadIdx.x; q < L; q += GT) {
+        const int a = q % bx.ext[0], b = (q / bx.ext[0]) % bx.ext[1], c = q / (bx.ext[0] * bx.ext[1]);
+        const int si = sidx(g, 0, bx.lo[0] + a), sj = sidx(g, 1, bx.lo[1] + b), sk = sidx(g, 2, bx.lo[2] + c);
+        if (si < 0 || sj < 0 || sk < 0) continue;
+        const long o = o3(g, si, sj, sk);
+        const int t = a + BPX * b + BPL * c;
+        for (int cc = 0; cc < nj; cc++) {
+            const double v = jvalue<R>(bx.j[cc * bx.n + t], jq);
+            if (v != 0.0) atomicAdd(&f.J[c0 + cc][o], v);
+        }
+    }
+}
+
+__device__ __forceinline__ double block_sum3(double v, double* red)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < GT / 64; w++) t += red[w];
+    return t;
+}
+
+// min/max of the 6 box bounds over the workgroup, written by thread 0
+__device__ __forceinline__ void block_box(int nb[6], int (*red)[GT / 64], Box3* out)
+{
+#pragma unroll
+    for (int q = 0; q < 6; q++)
+        for (int o = 32; o > 0; o >>= 1) {
+            const int v = __shfl_xor(nb[q], o);
+            nb[q] = (q & 1) ? max(nb[q], v) : min(nb[q], v);
+        }
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int q = 0; q < 6; q++) red[q][threadIdx.x >> 6] = nb[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Box3 b;
+        for (int a = 0; a < 3; a++) {
+            int lo = INT_MAX, hi = INT_MIN;
+            for (int w = 0; w < GT / 64; w++) {
+                lo = min(lo, red[2 * a][w]);
+                hi = max(hi, red[2 * a + 1][w]);
+            }
+            b.lo[a] = lo;
+            b.hi[a] = hi;
+        }
+        *out = b;
+    }
+}
+
+__device__ __forceinline__ void grow(int nb[6], int a, int c)
+{
+    nb[2 * a] = min(nb[2 * a], c);
+    nb[2 * a + 1] = max(nb[2 * a + 1], c);
+}
+
+// one electron: gather, Boris push (q/m = -1), deposit, absorption, window rebase; on the
+// staged box (LDS) or on the fields and current in HBM.  The staged form returns false,
+// leaving the particle untouched, when its cell lies outside the box.
+template <bool LDS, typename R>
+__device__ __forceinline__ bool electron3(const G3& g, const F3<R>& f, const BoxL<R>& bx, const E3<R>& e, int p,
+                                          const Push3& pp, double js, int* status, int nb[6])
+{
     const R w = e.w[p];
-    if (w == R(0)) return;
+    if (w == R(0)) return true;
     const double r0[3] = {e.x[p], e.y[p], e.z[p]};
+    if (LDS && !in_box(bx, r0)) return false;
     R E[3], B[3];
-    gather3(g, f, r0, E, B);
-    // Boris (q/m = -1), h = q dt / 2m
+    if constexpr (LDS) gather_box(bx, r0, E, B);
+    else gather3(g, f, r0, E, B);
     const R h = (R)(-0.5 * pp.dt);
     R ux = e.ux[p], uy = e.uy[p], uz = e.uz[p];
     const R umx = ux + h * E[0], umy = uy + h * E[1], umz = uz + h * E[2];
@@ -392,7 +668,12 @@ __global__ void __launch_bounds__(NT) k3_push(G3 g, F3<R> f, E3<R> e, int n, Pus
     for (int a = 0; a < 3; a++) ok = ok && fabs(r1[a] - r0[a]) < 1.0;
     if (ok) {
         const double k[3] = {pp.jk[0] * (double)w, pp.jk[1] * (double)w, pp.jk[2] * (double)w};   // q = -1
-        esirkepov3(g, f.J, r0, r1, k);
+        if constexpr (LDS) {
+            const double ks[3] = {k[0] * js, k[1] * js, k[2] * js};
+            deposit_box(bx, r0, r1, ks);
+        } else {
+            esirkepov3(g, f.J, r0, r1, k);
+        }
     } else {
         atomicOr(status, ST3_NONFINITE);
     }
@@ -410,29 +691,191 @@ __global__ void __launch_bounds__(NT) k3_push(G3 g, F3<R> f, E3<R> e, int n, Pus
     }
     if (!alive) {
         e.w[p] = R(0);
-        return;
+        return true;
     }
+    const double zr = r1[2] - pp.shift;
     e.x[p] = r1[0];
     e.y[p] = r1[1];
-    e.z[p] = r1[2] - pp.shift;
+    e.z[p] = zr;
     e.ux[p] = ux;
     e.uy[p] = uy;
     e.uz[p] = uz;
+    grow(nb, 0, (int)floor(r1[0]));
+    grow(nb, 1, (int)floor(r1[1]));
+    grow(nb, 2, (int)floor(zr));
+    return true;
 }
 
-// rigid ions: z(t) = z0 - (beta t / dz + shift), deposit only (q = +1)
 template <typename R>
-__global__ void __launch_bounds__(NT) k3_ions(G3 g, F3<R> f, I3<R> ion, int n, double zsa, double zsb, Push3 pp)
+__device__ __forceinline__ void box_of(const Box3& bb, int pz, BoxL<R>& bx, bool& lds)
 {
-    const int p = blockIdx.x * NT + threadIdx.x;
-    if (p >= n) return;
-    const R w = ion.w[p];
-    if (w == R(0)) return;
-    const double x = ion.x[p], y = ion.y[p], z0 = ion.z0[p];
-    const double r0[3] = {x, y, z0 - zsa}, r1[3] = {x, y, z0 - zsb};
-    const double k[3] = {0.0, 0.0, -pp.jk[2] * (double)w};
-    esirkepov3(g, f.J, r0, r1, k);
-    if (!g.per[2] && (r1[2] < 0.0 || r1[2] >= (double)g.N[2])) ion.w[p] = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        bx.lo[a] = bb.lo[a] - 2;
+        bx.ext[a] = bb.hi[a] - bb.lo[a] + 6;
+    }
+    bx.n = BPL * pz;
+    lds = bx.ext[0] <= BPX && bx.ext[1] <= BPY && bx.ext[2] <= pz;
+}
+
+// Staged segments.  A segment whose box exceeds the LDS pitches goes to the list big, a particle
+// outside its segment's box to the list mis (segment, particle); k3_gpd_hbm pushes both.
+template <typename R>
+__global__ void __launch_bounds__(GT) k3_gpd(G3 g, F3<R> f, E3<R> e, const Seg3* __restrict__ seg,
+                                             const Box3* __restrict__ bin, Box3* __restrict__ bout, Push3 pp, int pz,
+                                             int* status, int* big, int* nbig, int2* mis, int* nmis)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem3[];
+    __shared__ int red[6][GT / 64];
+    __shared__ double redd[GT / 64];
+    const Seg3 sg = seg[blockIdx.x];
+    const Box3 bb = bin[blockIdx.x];
+    int nb[6] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN};
+    if (sg.count > 0 && bb.lo[0] <= bb.hi[0] && bb.lo[1] <= bb.hi[1] && bb.lo[2] <= bb.hi[2]) {
+        BoxL<R> bx;
+        bool lds;
+        box_of(bb, pz, bx, lds);
+        bx.j = reinterpret_cast<typename Acc3<R>::T*>(smem3);
+        bx.f = reinterpret_cast<R*>(bx.j + 3 * bx.n);
+        const int end = sg.start + sg.count;
+        double js = 1.0, jq = 1.0;
+        if (lds) {
+            if constexpr (Acc3<R>::fixed) {
+                double sw = 0.0;
+                for (int p = sg.start + threadIdx.x; p < end; p += GT) sw += fabs((double)e.w[p]);
+                sw = block_sum3(sw, redd);
+                const double bound = fmax(fabs(pp.jk[0]), fmax(fabs(pp.jk[1]), fabs(pp.jk[2]))) * sw;
+                if (bound > 0.0) { js = FX_RANGE / bound; jq = bound / FX_RANGE; }
+            }
+            stage_box<R, true>(g, f, bx, 3);
+            __syncthreads();
+            for (int p = sg.start + threadIdx.x; p < end; p += GT)
+                if (!electron3<true>(g, f, bx, e, p, pp, js, status, nb)) mis[atomicAdd(nmis, 1)] = make_int2(blockIdx.x, p);
+            __syncthreads();
+            flush_box(g, f, bx, 0, 3, jq);
+        } else if (threadIdx.x == 0) {
+            big[atomicAdd(nbig, 1)] = blockIdx.x;
+        }
+    }
+    block_box(nb, red, &bout[blockIdx.x]);
+}
+
+// box bounds of a wave's particles into a segment's box (one lane per wave)
+__device__ __forceinline__ void wave_grow(int nb[6], Box3* out)
+{
+#pragma unroll
+    for (int q = 0; q < 6; q++)
+        for (int o = 32; o > 0; o >>= 1) {
+            const int v = __shfl_xor(nb[q], o);
+            nb[q] = (q & 1) ? max(nb[q], v) : min(nb[q], v);
+        }
+    if (__lane_id() == 0 && nb[0] <= nb[1]) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            atomicMin(&out->lo[a], nb[2 * a]);
+            atomicMax(&out->hi[a], nb[2 * a + 1]);
+        }
+    }
+}
+
+// the particles k3_gpd left: whole segments of list big (one workgroup each, in turn) and
+// single particles of list mis, on the fields and current in HBM; their cells widen the
+// segments' next boxes
+template <typename R>
+__global__ void __launch_bounds__(NT) k3_gpd_hbm(G3 g, F3<R> f, E3<R> e, const Seg3* __restrict__ seg,
+                                                 Box3* __restrict__ bout, Push3 pp, int* status, const int* big,
+                                                 const int* nbig, const int2* mis, const int* nmis)
+{
+    const BoxL<R> none{};
+    const int nb_ = *nbig;
+    for (int b = blockIdx.x; b < nb_; b += gridDim.x) {
+        const int q = big[b];
+        const Seg3 sg = seg[q];
+        const int end = sg.start + sg.count;
+        for (int base = sg.start; base < end; base += NT) {
+            int nb[6] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN};
+            const int p = base + threadIdx.x;
+            if (p < end) electron3<false>(g, f, none, e, p, pp, 1.0, status, nb);
+            wave_grow(nb, &bout[q]);
+        }
+    }
+    const int nm = *nmis;
+    for (int base = blockIdx.x * NT; base < nm; base += gridDim.x * NT) {
+        int nb[6] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN};
+        const int i = base + threadIdx.x;
+        int q = 0;
+        if (i < nm) {
+            const int2 m = mis[i];
+            q = m.x;
+            electron3<false>(g, f, none, e, m.y, pp, 1.0, status, nb);
+        }
+        // lanes may belong to different segments: one atomic set per lane
+        if (i < nm && nb[0] <= nb[1]) {
+            for (int a = 0; a < 3; a++) {
+                atomicMin(&bout[q].lo[a], nb[2 * a]);
+                atomicMax(&bout[q].hi[a], nb[2 * a + 1]);
+            }
+        }
+    }
+}
+
+// rigid ions (q = +1): z(t) = z0 - (beta t / dz + shift), J_z only
+template <typename R>
+__global__ void __launch_bounds__(GT) k3_gpi(G3 g, F3<R> f, I3<R> ion, const Seg3* __restrict__ seg,
+                                             const Box3* __restrict__ bin, Box3* __restrict__ bout, double zsa,
+                                             double zsb, double zsn, Push3 pp, int pz)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem3[];
+    __shared__ int red[6][GT / 64];
+    __shared__ double redd[GT / 64];
+    const Seg3 sg = seg[blockIdx.x];
+    const Box3 bb = bin[blockIdx.x];
+    int nb[6] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN};
+    if (sg.count > 0 && bb.lo[0] <= bb.hi[0] && bb.lo[1] <= bb.hi[1] && bb.lo[2] <= bb.hi[2]) {
+        BoxL<R> bx;
+        bool lds;
+        box_of(bb, pz, bx, lds);
+        bx.j = reinterpret_cast<typename Acc3<R>::T*>(smem3);
+        bx.f = nullptr;
+        const int end = sg.start + sg.count;
+        double js = 1.0, jq = 1.0;
+        if (lds) {
+            if constexpr (Acc3<R>::fixed) {
+                double sw = 0.0;
+                for (int p = sg.start + threadIdx.x; p < end; p += GT) sw += fabs((double)ion.w[p]);
+                sw = block_sum3(sw, redd);
+                const double bound = fabs(pp.jk[2]) * sw;
+                if (bound > 0.0) { js = FX_RANGE / bound; jq = bound / FX_RANGE; }
+            }
+            stage_box<R, false>(g, f, bx, 1);
+            __syncthreads();
+        }
+        for (int p = sg.start + threadIdx.x; p < end; p += GT) {
+            const R w = ion.w[p];
+            if (w == R(0)) continue;
+            const double x = ion.x[p], y = ion.y[p], z0 = ion.z0[p];
+            const double r0[3] = {x, y, z0 - zsa}, r1[3] = {x, y, z0 - zsb};
+            const double kz = -pp.jk[2] * (double)w;
+            if (lds && in_box(bx, r0)) {
+                deposit_box_z(bx, x, y, r0[2], r1[2], kz * js);
+            } else {
+                const double k[3] = {0.0, 0.0, kz};
+                esirkepov3(g, f.J, r0, r1, k);
+            }
+            if (!g.per[2] && (r1[2] < 0.0 || r1[2] >= (double)g.N[2])) {
+                ion.w[p] = R(0);
+                continue;
+            }
+            grow(nb, 0, (int)floor(x));
+            grow(nb, 1, (int)floor(y));
+            grow(nb, 2, (int)floor(z0 - zsn));
+        }
+        if (lds) {
+            __syncthreads();
+            flush_box(g, f, bx, 2, 1, jq);
+        }
+    }
+    block_box(nb, red, &bout[blockIdx.x]);
 }
 
 // laser antenna: per transverse cell a + particle fixed at the cell centre and a - particle
@@ -469,37 +912,59 @@ __device__ __forceinline__ double u01(uint64_t seed, uint64_t k)
     return (double)(z >> 11) * (1.0 / 9007199254740992.0);
 }
 
-// lattice planes row0 .. row0+nrows-1 of the lab-fixed plasma; consecutive particles of a
-// block sit in consecutive cells of a plane
+// lattice planes row0 .. row0+nrows-1 of the lab-fixed plasma into slots base.. (base = the
+// particles in use), one thread per particle.  A plane is laid out in transverse tile chunks
+// (rows of chunks along y, chunks along x, then ppc, then the chunk's cells x-fastest); each
+// chunk becomes a segment whose box spans its cells and the plane's z cells.  The particle id
+// (and so its random offsets) depends only on the plane, the cell and k.
 template <typename R>
-__global__ void __launch_bounds__(NT) k3_inject(G3 g, E3<R> e, I3<R> ion, int* nused_e, int* nused_i, Inject3 ip,
-                                                int* status)
+__global__ void __launch_bounds__(NT) k3_inject(G3 g, Tiles3 tl, E3<R> e, I3<R> ion, const int* nused_e,
+                                                const int* nused_i, Seg3* seg_e, Box3* box_e, Seg3* seg_i,
+                                                Box3* box_i, int seg_base, Inject3 ip, int* status)
 {
-    __shared__ int base[2];
-    const int64_t per_plane = (int64_t)g.N[0] * g.N[1] * ip.ppc;
+    const int N0 = g.N[0], N1 = g.N[1], tx = tl.t[0], ty = tl.t[1];
+    const int64_t per_plane = (int64_t)N0 * N1 * ip.ppc;
     const int64_t total = per_plane * ip.nrows;
-    const int64_t b0 = (int64_t)blockIdx.x * NT;
-    const int cnt = (int)min<int64_t>(NT, total - b0);
-    if (cnt <= 0) return;
-    if (threadIdx.x == 0) {
-        int se = atomicAdd(nused_e, cnt);
-        int si = ip.ion_mode ? atomicAdd(nused_i, cnt) : 0;
-        if ((int64_t)se + cnt > ip.cap || (int64_t)si + cnt > ip.cap) {
-            atomicOr(status, ST3_CAPACITY);
-            se = -1;
-        }
-        base[0] = se;
-        base[1] = si;
+    const int64_t gq = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (gq >= total) return;
+    const int be = *nused_e, bi = ip.ion_mode ? *nused_i : 0;
+    const bool room = (int64_t)be + total <= ip.cap && (int64_t)bi + total <= ip.cap;
+    if (!room) {
+        if (gq == 0) atomicOr(status, ST3_CAPACITY);
     }
-    __syncthreads();
-    if (base[0] < 0 || (int)threadIdx.x >= cnt) return;
-    const int64_t gq = b0 + threadIdx.x;
     const int64_t r = gq / per_plane, rem = gq - r * per_plane;
-    const int64_t ncell = (int64_t)g.N[0] * g.N[1];
-    const int64_t cell = rem % ncell, k = rem / ncell;
-    const int i = (int)(cell % g.N[0]), j = (int)(cell / g.N[0]);
+    const int64_t rowp = (int64_t)ty * N0 * ip.ppc;           // particles of a full row of chunks
+    const int cyi = (int)(rem / rowp);
+    const int64_t rem1 = rem - (int64_t)cyi * rowp;
+    const int hy = min(ty, N1 - cyi * ty);
+    const int64_t chp = (int64_t)tx * hy * ip.ppc;            // particles of a full chunk of this row
+    const int cxi = (int)(rem1 / chp);
+    const int64_t rem2 = rem1 - (int64_t)cxi * chp;
+    const int hx = min(tx, N0 - cxi * tx);
+    const int ncc = hx * hy;
+    const int k = (int)(rem2 / ncc), lc = (int)(rem2 - (int64_t)k * ncc);
+    const int i = cxi * tx + lc % hx, j = cyi * ty + lc / hx;
     const int64_t l = ip.row0 + r;
-    const uint64_t id = (((uint64_t)l * (uint64_t)g.N[1] + (uint64_t)j) * (uint64_t)g.N[0] + (uint64_t)i) *
+    const double c = ip.beta * ip.t / ip.dz + ip.shift;
+    if (rem2 == 0) {
+        // this chunk's segment (count 0 when the particle arrays are full)
+        const int q = seg_base + (int)r * tl.nt[0] * tl.nt[1] + cyi * tl.nt[0] + cxi;
+        const int64_t off = r * per_plane + (int64_t)cyi * rowp + (int64_t)cxi * chp;
+        Box3 b;
+        b.lo[0] = cxi * tx; b.hi[0] = cxi * tx + hx - 1;
+        b.lo[1] = cyi * ty; b.hi[1] = cyi * ty + hy - 1;
+        b.lo[2] = (int)floor((double)l - c) - 1;
+        b.hi[2] = (int)floor((double)l + 1.0 - c) + 1;
+        const int cnt = room ? (int)(hx * hy * ip.ppc) : 0;
+        seg_e[q] = Seg3{be + (int)off, cnt};
+        box_e[q] = b;
+        if (ip.ion_mode) {
+            seg_i[q] = Seg3{bi + (int)off, cnt};
+            box_i[q] = b;
+        }
+    }
+    if (!room) return;
+    const uint64_t id = (((uint64_t)l * (uint64_t)N1 + (uint64_t)j) * (uint64_t)N0 + (uint64_t)i) *
                             (uint64_t)ip.ppc + (uint64_t)k;
     const double rx = u01(ip.seed, 3 * id + 1), ry = u01(ip.seed, 3 * id + 2), rz = u01(ip.seed, 3 * id + 3);
     const double zbc = (double)l + rz;
@@ -510,7 +975,7 @@ __global__ void __launch_bounds__(NT) k3_inject(G3 g, E3<R> e, I3<R> ion, int* n
         if (ip.ramp_len > 0.0 && zl < ip.ramp_start + ip.ramp_len) n = ip.n0 * (zl - ip.ramp_start) / ip.ramp_len;
     }
     const double wgt = ip.gamma * n * ip.dx * ip.dy * ip.dz / (double)ip.ppc;
-    const int p = base[0] + threadIdx.x;
+    const int p = be + (int)gq;
     e.x[p] = (double)i + rx;
     e.y[p] = (double)j + ry;
     e.z[p] = zbc - ip.beta * ip.t / ip.dz - ip.shift;
@@ -520,7 +985,7 @@ __global__ void __launch_bounds__(NT) k3_inject(G3 g, E3<R> e, I3<R> ion, int* n
     e.w[p] = (R)wgt;
     e.id[p] = (uint32_t)id;
     if (ip.ion_mode) {
-        const int pi = base[1] + threadIdx.x;
+        const int pi = bi + (int)gq;
         ion.x[pi] = (double)i + rx;
         ion.y[pi] = (double)j + ry;
         ion.z0[pi] = zbc;
@@ -528,6 +993,16 @@ __global__ void __launch_bounds__(NT) k3_inject(G3 g, E3<R> e, I3<R> ion, int* n
         ion.id[pi] = (uint32_t)id;
     }
 }
+
+// the injected particles enter the counters once the injection kernel has read them
+__global__ void k3_bump(int* nused_e, int* nused_i, int64_t total, int64_t cap, int ion_mode)
+{
+    const int be = *nused_e, bi = ion_mode ? *nused_i : 0;
+    if ((int64_t)be + total > cap || (int64_t)bi + total > cap) return;
+    *nused_e = be + (int)total;
+    if (ion_mode) *nused_i = bi + (int)total;
+}
+
 
 // window moved by d planes (zoff already advanced)
 template <typename R>
@@ -576,40 +1051,129 @@ __global__ void __launch_bounds__(NT) k3_window(G3 g, F3<R> f, int d)
     }
 }
 
-// live particles (w != 0) of a into b, wave-aggregated slots
-template <typename R>
-__global__ void __launch_bounds__(NT) k3_compact_e(E3<R> a, E3<R> b, int n, int* cnt)
+// ---- tile sort ----------------------------------------------------------------------------------
+
+// tile of a position (cells, clamped into the interior)
+__device__ __forceinline__ int tile_key3(const G3& g, const Tiles3& tl, double x, double y, double z)
 {
-    const int p = blockIdx.x * NT + threadIdx.x;
-    const bool live = p < n && a.w[p] != R(0);
-    const unsigned long long m = __ballot(live);
-    const int lane = __lane_id();
-    const int leader = m ? __ffsll((long long)m) - 1 : 0;
-    int base = 0;
-    if (m && lane == leader) base = atomicAdd(cnt, __popcll(m));
-    base = __shfl(base, leader);
-    if (!live) return;
-    const int d = base + __popcll(m & ((1ull << lane) - 1ull));
-    b.x[d] = a.x[p]; b.y[d] = a.y[p]; b.z[d] = a.z[p];
-    b.ux[d] = a.ux[p]; b.uy[d] = a.uy[p]; b.uz[d] = a.uz[p];
-    b.w[d] = a.w[p]; b.id[d] = a.id[p];
+    const double r[3] = {x, y, z};
+    int key = 0;
+#pragma unroll
+    for (int a = 2; a >= 0; a--) {
+        const int c = min(max((int)floor(r[a]), 0), g.N[a] - 1);
+        key = key * tl.nt[a] + c / tl.t[a];
+    }
+    return key;
+}
+
+constexpr int SORT_GRID = 4096;   // workgroups of the grid-stride sort passes
+
+template <typename R>
+__global__ void __launch_bounds__(NT) k3_sort_count_e(G3 g, Tiles3 tl, E3<R> e, const int* nused, int* counts)
+{
+    const int n = *nused;
+    for (int base = blockIdx.x * NT; base < n; base += gridDim.x * NT) {
+        const int p = base + threadIdx.x;
+        const bool act = p < n && e.w[p] != R(0);
+        const int key = act ? tile_key3(g, tl, e.x[p], e.y[p], e.z[p]) : 0;
+        bf::wave_slot(counts, key, act);
+    }
 }
 
 template <typename R>
-__global__ void __launch_bounds__(NT) k3_compact_i(I3<R> a, I3<R> b, int n, int* cnt)
+__global__ void __launch_bounds__(NT) k3_sort_count_i(G3 g, Tiles3 tl, I3<R> ion, double zsh, const int* nused,
+                                                      int* counts)
 {
-    const int p = blockIdx.x * NT + threadIdx.x;
-    const bool live = p < n && a.w[p] != R(0);
-    const unsigned long long m = __ballot(live);
-    const int lane = __lane_id();
-    const int leader = m ? __ffsll((long long)m) - 1 : 0;
-    int base = 0;
-    if (m && lane == leader) base = atomicAdd(cnt, __popcll(m));
-    base = __shfl(base, leader);
-    if (!live) return;
-    const int d = base + __popcll(m & ((1ull << lane) - 1ull));
-    b.x[d] = a.x[p]; b.y[d] = a.y[p]; b.z0[d] = a.z0[p]; b.w[d] = a.w[p]; b.id[d] = a.id[p];
+    const int n = *nused;
+    for (int base = blockIdx.x * NT; base < n; base += gridDim.x * NT) {
+        const int p = base + threadIdx.x;
+        const bool act = p < n && ion.w[p] != R(0);
+        const int key = act ? tile_key3(g, tl, ion.x[p], ion.y[p], ion.z0[p] - zsh) : 0;
+        bf::wave_slot(counts, key, act);
+    }
 }
+
+// exclusive scan of the tile counts (one workgroup): segment t = tile t with the tile's cells
+// as its box, cursor t = its first slot, *tot = the live count
+__global__ void __launch_bounds__(1024) k3_sort_scan(G3 g, Tiles3 tl, const int* counts, int* cursor, Seg3* seg,
+                                                     Box3* box, int* tot)
+{
+    __shared__ int part[1024];
+    const int per = (tl.ntiles + 1023) / 1024;
+    const int b0 = min(tl.ntiles, (int)threadIdx.x * per), b1 = min(tl.ntiles, b0 + per);
+    int s = 0;
+    for (int i = b0; i < b1; i++) s += counts[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int v = (int)threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int off = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    for (int i = b0; i < b1; i++) {
+        const int c = counts[i];
+        seg[i] = Seg3{off, c};
+        cursor[i] = off;
+        const int ti[3] = {i % tl.nt[0], (i / tl.nt[0]) % tl.nt[1], i / (tl.nt[0] * tl.nt[1])};
+        Box3 b;
+        for (int a = 0; a < 3; a++) {
+            b.lo[a] = ti[a] * tl.t[a];
+            b.hi[a] = min(g.N[a], (ti[a] + 1) * tl.t[a]) - 1;
+        }
+        box[i] = b;
+        off += c;
+    }
+    if (threadIdx.x == 1023) *tot = part[1023];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NT) k3_sort_scatter_e(G3 g, Tiles3 tl, E3<R> src, E3<R> dst, const int* nused,
+                                                        int* cursor)
+{
+    const int n = *nused;
+    for (int base = blockIdx.x * NT; base < n; base += gridDim.x * NT) {
+        const int p = base + threadIdx.x;
+        const bool act = p < n && src.w[p] != R(0);
+        double x = 0, y = 0, z = 0;
+        int key = 0;
+        if (act) {
+            x = src.x[p]; y = src.y[p]; z = src.z[p];
+            key = tile_key3(g, tl, x, y, z);
+        }
+        const int d = bf::wave_slot(cursor, key, act);
+        if (act) {
+            dst.x[d] = x; dst.y[d] = y; dst.z[d] = z;
+            dst.ux[d] = src.ux[p]; dst.uy[d] = src.uy[p]; dst.uz[d] = src.uz[p];
+            dst.w[d] = src.w[p]; dst.id[d] = src.id[p];
+        }
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NT) k3_sort_scatter_i(G3 g, Tiles3 tl, I3<R> src, I3<R> dst, double zsh,
+                                                        const int* nused, int* cursor)
+{
+    const int n = *nused;
+    for (int base = blockIdx.x * NT; base < n; base += gridDim.x * NT) {
+        const int p = base + threadIdx.x;
+        const bool act = p < n && src.w[p] != R(0);
+        double x = 0, y = 0, z0 = 0;
+        int key = 0;
+        if (act) {
+            x = src.x[p]; y = src.y[p]; z0 = src.z0[p];
+            key = tile_key3(g, tl, x, y, z0 - zsh);
+        }
+        const int d = bf::wave_slot(cursor, key, act);
+        if (act) {
+            dst.x[d] = x; dst.y[d] = y; dst.z0[d] = z0; dst.w[d] = src.w[p]; dst.id[d] = src.id[p];
+        }
+    }
+}
+
+__global__ void k3_set_count(int* nused, const int* tot) { *nused = *tot; }
+
 
 // number of live particles (w != 0) among n slots, one atomic per wave
 template <typename R>
@@ -740,18 +1304,28 @@ void launch3_zero_j(const G3& g, const F3<R>& f, hipStream_t s)
 }
 
 template <typename R>
-void launch3_push(const G3& g, const F3<R>& f, const E3<R>& e, int n, const Push3& pp, int* status, hipStream_t s)
+void launch3_gpd(const G3& g, const F3<R>& f, const E3<R>& e, const Seg3* seg, const Box3* bin, Box3* bout,
+                 int nseg, const Push3& pp, int pz, int* status, int* lists, int2* mis, hipStream_t s)
 {
-    if (n <= 0) return;
-    hipLaunchKernelGGL((k3_push<R>), dim3((n + NT - 1) / NT), dim3(NT), 0, s, g, f, e, n, pp, status);
+    if (nseg <= 0) return;
+    const size_t lds = (size_t)BPL * pz * box_cell_bytes<R>();
+    int *nbig = lists, *nmis = lists + 1, *big = lists + 2;
+    (void)hipMemsetAsync(lists, 0, 2 * sizeof(int), s);
+    (void)hipFuncSetAttribute((const void*)k3_gpd<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k3_gpd<R>), dim3(nseg), dim3(GT), lds, s, g, f, e, seg, bin, bout, pp, pz, status, big,
+                       nbig, mis, nmis);
+    hipLaunchKernelGGL((k3_gpd_hbm<R>), dim3(std::min(HBM_GRID, nseg)), dim3(NT), 0, s, g, f, e, seg, bout, pp,
+                       status, big, nbig, mis, nmis);
 }
 
 template <typename R>
-void launch3_ions(const G3& g, const F3<R>& f, const I3<R>& ion, int n, double za_shift, double zb_shift,
-                  const Push3& pp, hipStream_t s)
+void launch3_gpi(const G3& g, const F3<R>& f, const I3<R>& ion, const Seg3* seg, const Box3* bin, Box3* bout,
+                 int nseg, double zsa, double zsb, double zsn, const Push3& pp, int pz, hipStream_t s)
 {
-    if (n <= 0) return;
-    hipLaunchKernelGGL((k3_ions<R>), dim3((n + NT - 1) / NT), dim3(NT), 0, s, g, f, ion, n, za_shift, zb_shift, pp);
+    if (nseg <= 0) return;
+    const size_t lds = (size_t)BPL * pz * 8;
+    (void)hipFuncSetAttribute((const void*)k3_gpi<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k3_gpi<R>), dim3(nseg), dim3(GT), lds, s, g, f, ion, seg, bin, bout, zsa, zsb, zsn, pp, pz);
 }
 
 template <typename R>
@@ -763,13 +1337,15 @@ void launch3_antenna(const G3& g, const F3<R>& f, double* xm, const double* xh, 
 }
 
 template <typename R>
-void launch3_inject(const G3& g, const E3<R>& e, const I3<R>& ion, int* nused_e, int* nused_i,
-                    const Inject3& ip, int* status, hipStream_t s)
+void launch3_inject(const G3& g, const Tiles3& tl, const E3<R>& e, const I3<R>& ion, int* nused_e, int* nused_i,
+                    Seg3* seg_e, Box3* box_e, Seg3* seg_i, Box3* box_i, int seg_base, const Inject3& ip,
+                    int* status, hipStream_t s)
 {
     const int64_t total = (int64_t)g.N[0] * g.N[1] * ip.ppc * ip.nrows;
     if (total <= 0) return;
-    hipLaunchKernelGGL((k3_inject<R>), dim3((unsigned)((total + NT - 1) / NT)), dim3(NT), 0, s, g, e, ion, nused_e,
-                       nused_i, ip, status);
+    hipLaunchKernelGGL((k3_inject<R>), dim3((unsigned)((total + NT - 1) / NT)), dim3(NT), 0, s, g, tl, e, ion,
+                       nused_e, nused_i, seg_e, box_e, seg_i, box_i, seg_base, ip, status);
+    hipLaunchKernelGGL(k3_bump, dim3(1), dim3(1), 0, s, nused_e, nused_i, total, ip.cap, ip.ion_mode);
 }
 
 template <typename R>
@@ -781,17 +1357,27 @@ void launch3_window(const G3& g, const F3<R>& f, const Pml3& pml, int d, hipStre
 }
 
 template <typename R>
-void launch3_compact_e(const E3<R>& a, const E3<R>& b, int n, int* cnt, hipStream_t s)
+void launch3_sort_e(const G3& g, const Tiles3& tl, const E3<R>& src, const E3<R>& dst, int* nused, int* counts,
+                    int* cursor, int* tot, Seg3* seg, Box3* box, int64_t cap, hipStream_t s)
 {
-    (void)hipMemsetAsync(cnt, 0, sizeof(int), s);
-    if (n > 0) hipLaunchKernelGGL((k3_compact_e<R>), dim3((n + NT - 1) / NT), dim3(NT), 0, s, a, b, n, cnt);
+    const dim3 grid((unsigned)std::min<int64_t>(SORT_GRID, (cap + NT - 1) / NT));
+    (void)hipMemsetAsync(counts, 0, sizeof(int) * tl.ntiles, s);
+    hipLaunchKernelGGL((k3_sort_count_e<R>), grid, dim3(NT), 0, s, g, tl, src, nused, counts);
+    hipLaunchKernelGGL(k3_sort_scan, dim3(1), dim3(1024), 0, s, g, tl, counts, cursor, seg, box, tot);
+    hipLaunchKernelGGL((k3_sort_scatter_e<R>), grid, dim3(NT), 0, s, g, tl, src, dst, nused, cursor);
+    hipLaunchKernelGGL(k3_set_count, dim3(1), dim3(1), 0, s, nused, tot);
 }
 
 template <typename R>
-void launch3_compact_i(const I3<R>& a, const I3<R>& b, int n, int* cnt, hipStream_t s)
+void launch3_sort_i(const G3& g, const Tiles3& tl, const I3<R>& src, const I3<R>& dst, double zsh, int* nused,
+                    int* counts, int* cursor, int* tot, Seg3* seg, Box3* box, int64_t cap, hipStream_t s)
 {
-    (void)hipMemsetAsync(cnt, 0, sizeof(int), s);
-    if (n > 0) hipLaunchKernelGGL((k3_compact_i<R>), dim3((n + NT - 1) / NT), dim3(NT), 0, s, a, b, n, cnt);
+    const dim3 grid((unsigned)std::min<int64_t>(SORT_GRID, (cap + NT - 1) / NT));
+    (void)hipMemsetAsync(counts, 0, sizeof(int) * tl.ntiles, s);
+    hipLaunchKernelGGL((k3_sort_count_i<R>), grid, dim3(NT), 0, s, g, tl, src, zsh, nused, counts);
+    hipLaunchKernelGGL(k3_sort_scan, dim3(1), dim3(1024), 0, s, g, tl, counts, cursor, seg, box, tot);
+    hipLaunchKernelGGL((k3_sort_scatter_i<R>), grid, dim3(NT), 0, s, g, tl, src, dst, zsh, nused, cursor);
+    hipLaunchKernelGGL(k3_set_count, dim3(1), dim3(1), 0, s, nused, tot);
 }
 
 template <typename R>
@@ -819,17 +1405,19 @@ void launch3_stations(const G3& g, const F3<R>& f, const double* zlab, int nst, 
     template void launch3_filter<R>(const G3&, const F3<R>&, int, int, const R**, hipStream_t);             \
     template void launch3_zero_j<R>(const G3&, const F3<R>&, hipStream_t);                                  \
     template void launch3_count_live<R>(const R*, int, int*, hipStream_t);                                  \
-    template void launch3_push<R>(const G3&, const F3<R>&, const E3<R>&, int, const Push3&, int*,           \
-                                  hipStream_t);                                                             \
-    template void launch3_ions<R>(const G3&, const F3<R>&, const I3<R>&, int, double, double, const Push3&, \
-                                  hipStream_t);                                                             \
+    template void launch3_gpd<R>(const G3&, const F3<R>&, const E3<R>&, const Seg3*, const Box3*, Box3*, int,  \
+                                 const Push3&, int, int*, int*, int2*, hipStream_t);                        \
+    template void launch3_gpi<R>(const G3&, const F3<R>&, const I3<R>&, const Seg3*, const Box3*, Box3*, int,  \
+                                 double, double, double, const Push3&, int, hipStream_t);                   \
     template void launch3_antenna<R>(const G3&, const F3<R>&, double*, const double*, const double*,        \
                                      const Antenna3&, const Push3&, hipStream_t);                           \
-    template void launch3_inject<R>(const G3&, const E3<R>&, const I3<R>&, int*, int*, const Inject3&, int*, \
-                                    hipStream_t);                                                           \
+    template void launch3_inject<R>(const G3&, const Tiles3&, const E3<R>&, const I3<R>&, int*, int*, Seg3*,   \
+                                    Box3*, Seg3*, Box3*, int, const Inject3&, int*, hipStream_t);          \
     template void launch3_window<R>(const G3&, const F3<R>&, const Pml3&, int, hipStream_t);                \
-    template void launch3_compact_e<R>(const E3<R>&, const E3<R>&, int, int*, hipStream_t);                 \
-    template void launch3_compact_i<R>(const I3<R>&, const I3<R>&, int, int*, hipStream_t);                 \
+    template void launch3_sort_e<R>(const G3&, const Tiles3&, const E3<R>&, const E3<R>&, int*, int*, int*,   \
+                                    int*, Seg3*, Box3*, int64_t, hipStream_t);                              \
+    template void launch3_sort_i<R>(const G3&, const Tiles3&, const I3<R>&, const I3<R>&, double, int*, int*,  \
+                                    int*, int*, Seg3*, Box3*, int64_t, hipStream_t);                        \
     template void launch3_stations<R>(const G3&, const F3<R>&, const double*, int, double, double, double,  \
                                       double, double*, int*, int, hipStream_t);
 BF3_INST(float)

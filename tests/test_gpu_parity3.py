@@ -122,3 +122,32 @@ def test_3d_vacuum_pml_matches_oracle():
     for n in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
         a, b = sim.field(n), ref.field(n)
         assert np.abs(a - b).max() <= 1e-11 * np.abs(f).max(), n
+
+
+@gpu
+@pytest.mark.parametrize("real,tol", [("f64", 1e-11), ("f32", 1e-5)])
+def test_3d_spreading_segments_match_oracle(real, tol):
+    # fast random electrons on a periodic box with no re-sort: the segments' boxes grow each
+    # step until they exceed the LDS box, and particles wrapping round a periodic face widen
+    # theirs at once, so both the staged and the HBM forms of the push run
+    nx, ny, nz = 12, 10, 22
+    d = (0.1, 0.11, 0.09)
+    cfg = pi.make_config3(nx, ny, nz, *d, periodic_x=1, periodic_y=1, periodic_z=1, pml_cells=0,
+                          ck="ck2", theta=0.2, filter_npass=1, filter_compensate=1, real=real, seed=6)
+    from paper_1009_2727_amd import Sim
+    sim = Sim(cfg, capacity=6000, sort_every=1000)
+    ref = Oracle3(cfg)
+    for k, name in enumerate(["Ex", "Ey", "Ez", "Bx", "By", "Bz"]):
+        f = pi.random_field(ref.shape, seed=300 + k, amp=0.2)
+        ref.set_field(name, f)
+        sim.set_field(name, f)
+    p = pi.random_electrons3(5000, nx, ny, nz, d, seed=12, umax=4.0, margin=0.0)
+    ref.set_electrons(p)
+    sim.load_electrons(p)
+    ref.step(8)
+    sim.step(8)
+    assert sim.sync_status() == 0
+    for n in FIELDS:
+        a, b = sim.field(n), ref.field(n)
+        assert np.abs(a - b).max() <= tol * max(np.abs(b).max(), 1.0), n
+    compare_particles3(sim, ref, 1e-9 if real == "f64" else 2e-5, 1e-9 if real == "f64" else 2e-5)
