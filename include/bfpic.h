@@ -181,9 +181,13 @@ enum {
     BF_DIAG_GAUSS = 5,     /* stored_z x stored_x doubles: div E - F[rho] on the nodes (2D) */
     BF_DIAG_INFO = 6,      /* bf_info                                                       */
     BF_DIAG_ANTENNA = 7,   /* nx doubles (3D: nx x ny): x of the moving antenna particles   */
-    BF_DIAG_TIMERS = 8     /* BF_PHASE_COUNT x 2 doubles: accumulated ms and launches per
+    BF_DIAG_TIMERS = 8,    /* BF_PHASE_COUNT x 2 doubles: accumulated ms and launches per
                               phase since the last call (phase_timers = 1); arg != 0 resets */
+    BF_DIAG_PARTICLE_BLOCK = 9 /* 3D only; arg = species + 2 b: the live particles of slots
+                              [b, b + 1) x BF_PARTICLE_BLOCK, as int64 n then 8 arrays of n
+                              doubles (id, x, y, z, ux, uy, uz, w); a sample of a large run  */
 };
+#define BF_PARTICLE_BLOCK 65536
 
 /* phases of one bf_step (BF_DIAG_TIMERS rows) */
 enum {

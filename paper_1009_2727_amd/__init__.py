@@ -22,7 +22,8 @@ FIELDS = ["Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "Exo", "Eyo", "E
           "Exs", "Eys", "Ezs", "Bxs", "Bys", "Bzs"]
 FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 DIAG_FIELD, DIAG_PARTICLES, DIAG_COUNTS, DIAG_STATION, DIAG_ENERGY, DIAG_GAUSS, DIAG_INFO, \
-    DIAG_ANTENNA, DIAG_TIMERS = range(9)
+    DIAG_ANTENNA, DIAG_TIMERS, DIAG_PARTICLE_BLOCK = range(10)
+PARTICLE_BLOCK = 65536
 PHASES = ["faraday", "push", "ions", "antenna", "filter", "ampere", "window", "sort"]
 STATUS = {0: "BF_OK", -1: "BF_EINVAL", -2: "BF_ECFL", -3: "BF_ECAPACITY", -4: "BF_ENONFINITE",
           -5: "BF_EDEVICE", -6: "BF_ESTATE", -7: "BF_EUNSUPPORTED"}
@@ -361,6 +362,15 @@ class Sim:
         raw = self._diag(DIAG_STATION, q, np.zeros(1 + 7 * cap))
         n = int(raw[:1].view(np.int64)[0])
         return raw[1:1 + 7 * n].reshape(n, 7)
+
+    def particle_block(self, species: int, block: int) -> dict:
+        """3D: the live particles of slots [block, block + 1) * PARTICLE_BLOCK (a sample)."""
+        out = self._diag(DIAG_PARTICLE_BLOCK, species + 2 * block, np.zeros(1 + 8 * PARTICLE_BLOCK))
+        n = int(out[:1].view(np.int64)[0])
+        cols = out[1:1 + 8 * n].reshape(8, n)
+        d = {k: cols[q].copy() for q, k in enumerate(["id", "x", "y", "z", "ux", "uy", "uz", "w"])}
+        d["id"] = d["id"].astype(np.uint32)
+        return d
 
     def timers(self, reset: bool = True) -> dict:
         """Accumulated device time (ms) and launch count of each step phase."""

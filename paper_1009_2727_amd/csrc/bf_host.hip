@@ -1033,7 +1033,8 @@ double zshift3(const bf_sim* s, double t)
     return s->beta * t / s->cfg.dz_um + (double)s->shift;
 }
 
-// counting sort of both species by tile (drops removed particles); segments = tiles
+// counting sort of both species by tile (drops removed particles); segments = tiles.  The
+// particles end in their current copy (the other one is the sort's scratch).
 template <typename R>
 void sort3(bf_sim* s)
 {
@@ -1046,7 +1047,6 @@ void sort3(bf_sim* s)
     if (s->have_plasma && s->plasma.ion_mode == 1)
         bf3::launch3_sort_i<R>(L.g, L.tl, ions3<R>(s, a), ions3<R>(s, b), zshift3(s, s->t), nu + 1, cnt, cur,
                                tot + 1, seg3<R>(s, 1), box3(s, 1, L.bb_cur), L.cap, s->stream);
-    L.p_cur = b;
     L.nseg = L.tl.ntiles;
     L.since_sort = 0;
 }
@@ -1293,12 +1293,16 @@ bf_status write_field3(bf_sim* s, int a, const double* in)
 }
 
 // live particles: 8 columns (id, x, y, z in um, ux, uy, uz, w)
-bf_status read_particles3(bf_sim* s, int species, std::vector<double>* cols, int64_t* nlive)
+// live particles of slots [first, first + count) of a species (count < 0: up to the slots in use)
+bf_status read_particles3(bf_sim* s, int species, std::vector<double>* cols, int64_t* nlive, int64_t first = 0,
+                          int64_t count = -1)
 {
     const Sim3& L = *s->d3;
-    int64_t n = 0;
-    hipError_t e0 = slots3(s, species, &n);
+    int64_t used = 0;
+    hipError_t e0 = slots3(s, species, &used);
     if (e0 != hipSuccess) return hip_check(s, e0, "3D read particles");
+    first = std::min(std::max<int64_t>(first, 0), used);
+    const int64_t n = count < 0 ? used - first : std::min(count, used - first);
     const bool f32 = s->cfg.real_bytes == 4;
     const size_t rb = s->cfg.real_bytes;
     const char* b = (const char*)s->buf[(species == 0 ? 1 : 3) + L.p_cur];
@@ -1309,7 +1313,7 @@ bf_status read_particles3(bf_sim* s, int species, std::vector<double>* cols, int
         const size_t sz = q < 3 ? 8 : (q == ncol - 1 ? 4 : rb);
         raw[q].resize(std::max<int64_t>(n, 1) * sz);
         if (n > 0) {
-            hipError_t e = hipMemcpy(raw[q].data(), b + off, n * sz, hipMemcpyDeviceToHost);
+            hipError_t e = hipMemcpy(raw[q].data(), b + off + first * sz, n * sz, hipMemcpyDeviceToHost);
             if (e != hipSuccess) return hip_check(s, e, "3D read particles");
         }
     }
@@ -1380,6 +1384,18 @@ bf_status diagnose3(bf_sim* s, int kind, int arg, void* host_out, size_t bytes)
         if (st != BF_OK) return st;
         if (bytes < (size_t)n * 8 * 8) return fail(s, BF_EINVAL, "buffer too small");
         for (int q = 0; q < 8; q++) std::memcpy((double*)host_out + (size_t)q * n, cols[q].data(), n * 8);
+        return BF_OK;
+    }
+    case BF_DIAG_PARTICLE_BLOCK: {
+        if (arg < 0) return fail(s, BF_EINVAL, "bad particle block");
+        std::vector<double> cols[8];
+        int64_t n = 0;
+        bf_status st = read_particles3(s, arg & 1, cols, &n, (int64_t)(arg >> 1) * BF_PARTICLE_BLOCK,
+                                       BF_PARTICLE_BLOCK);
+        if (st != BF_OK) return st;
+        if (bytes < 8 + (size_t)n * 8 * 8) return fail(s, BF_EINVAL, "buffer too small");
+        *(int64_t*)host_out = n;
+        for (int q = 0; q < 8; q++) std::memcpy((double*)host_out + 1 + (size_t)q * n, cols[q].data(), n * 8);
         return BF_OK;
     }
     case BF_DIAG_STATION: {

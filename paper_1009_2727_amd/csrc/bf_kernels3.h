@@ -133,7 +133,8 @@ void launch3_inject(const G3& g, const Tiles3& tl, const E3<R>& e, const I3<R>& 
 // split parts in planes that just left the z PML, keep tangential E zero on the end walls
 template <typename R>
 void launch3_window(const G3& g, const F3<R>& f, const Pml3& pml, int d, hipStream_t s);
-// counting sort of the live particles (w != 0) of slots [0, *nused) of src by tile into dst:
+// counting sort of the live particles (w != 0) of slots [0, *nused) of src by tile, through dst
+// (scatter by tile into dst, then each tile back into src level by level in cell order):
 // segment t = tile t with its cell box, *nused = live count; counts/cursor hold ntiles ints,
 // tot one int of scratch.  Ions are binned at z0 - zsh.
 template <typename R>

@@ -472,12 +472,15 @@ __device__ __forceinline__ void gather_box(const BoxL<R>& bx, const double r[3],
 
 // Esirkepov's 3D deposit into the box: with (C, A1, A2) cyclic and T = S0_A1 (S0_A2 + DS_A2 / 2)
 // + DS_A1 (S0_A2 / 2 + DS_A2 / 3) (the four-term weight regrouped), J_C at node base + m along
-// C gains k_C (DS_C[0] + ... + DS_C[m]) T(m1, m2)
+// C gains k_C (DS_C[0] + ... + DS_C[m]) T(m1, m2).  Along an axis that no particle of the wave
+// crosses a cell face on, the fifth window node has zero weight and the prefix sum is complete
+// at the fourth node: those adds are skipped for the whole wave.
 template <typename R>
 __device__ __forceinline__ void deposit_box(const BoxL<R>& bx, const double r0[3], const double r1[3],
                                             const double k[3])
 {
     double S0[3][5], DS[3][5];
+    bool any[3];
     int base = 0;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
@@ -489,6 +492,7 @@ __device__ __forceinline__ void deposit_box(const BoxL<R>& bx, const double r0[3
 #pragma unroll
         for (int m = 0; m < 5; m++) DS[a][m] = s1[m] - S0[a][m];
         base += (b - bx.lo[a]) * bstride(a);
+        any[a] = __ballot(i1 != i0) != 0ull;
     }
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -507,14 +511,19 @@ __device__ __forceinline__ void deposit_box(const BoxL<R>& bx, const double r0[3
         }
         typename Acc3<R>::T* J = bx.j + c * bx.n + base;
 #pragma unroll
-        for (int m1 = 0; m1 < 5; m1++)
+        for (int m1 = 0; m1 < 5; m1++) {
+            if (m1 == 4 && !any[a1]) continue;
 #pragma unroll
             for (int m2 = 0; m2 < 5; m2++) {
+                if (m2 == 4 && !any[a2]) continue;
                 const double T = S0[a1][m1] * P[m2] + DS[a1][m1] * Q[m2];
 #pragma unroll
-                for (int mc = 0; mc < 4; mc++)
+                for (int mc = 0; mc < 4; mc++) {
+                    if (mc == 3 && !any[c]) continue;
                     jadd<R>(J + mc * bstride(c) + m1 * bstride(a1) + m2 * bstride(a2), kp[mc], T);
+                }
             }
+        }
     }
 }
 
@@ -1174,14 +1183,164 @@ __global__ void __launch_bounds__(NT) k3_sort_scatter_i(G3 g, Tiles3 tl, I3<R> s
 
 __global__ void k3_set_count(int* nused, const int* tot) { *nused = *tot; }
 
+// Order within each tile after the scatter: the particles of level k are the k-th particles
+// of their cells, and the tile is laid out level by level, each level in cell order (x
+// fastest).  Consecutive lanes of a wave then sit in consecutive cells of a few x rows, whose
+// LDS accumulators fall in distinct bank pairs for the 8-byte adds of the deposit.
+constexpr int ORD_THREADS = 512;
+constexpr int ORD_MAX_CELLS = 1024;   // cells of a tile ordered in LDS (larger tiles keep the scatter order)
+constexpr int ORD_TABLE = 8192;       // particles of a tile ordered in LDS
 
-// number of live particles (w != 0) among n slots, one atomic per wave
+struct TileOrder {
+    int cnt[ORD_MAX_CELLS], pos[ORD_MAX_CELLS];
+    int tab[ORD_TABLE];               // per particle: tile cell | level << 16
+    int part[ORD_THREADS];
+    int kmax;
+};
+
+// cell of a tile (clamped as the tile key clamps)
+struct TileBox3 {
+    int o[3], w[3];
+    __device__ __forceinline__ int of(const G3& g, double x, double y, double z) const
+    {
+        const double r[3] = {x, y, z};
+        int c = 0;
+#pragma unroll
+        for (int a = 2; a >= 0; a--) {
+            const int v = min(max((int)floor(r[a]), 0), g.N[a] - 1) - o[a];
+            c = c * w[a] + min(max(v, 0), w[a] - 1);
+        }
+        return c;
+    }
+};
+
+__device__ __forceinline__ TileBox3 tile_box3(const G3& g, const Tiles3& tl, int t)
+{
+    const int ti[3] = {t % tl.nt[0], (t / tl.nt[0]) % tl.nt[1], t / (tl.nt[0] * tl.nt[1])};
+    TileBox3 b;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        b.o[a] = ti[a] * tl.t[a];
+        b.w[a] = min(tl.t[a], g.N[a] - b.o[a]);
+    }
+    return b;
+}
+
+// exclusive scan of flag over the tile's C cells into pos; returns the total
+__device__ int scan_cells(TileOrder& ts, int C, int k)
+{
+    const int t = threadIdx.x;
+    const int per = (C + ORD_THREADS - 1) / ORD_THREADS, lo = min(t * per, C), hi = min(lo + per, C);
+    int s = 0;
+    for (int i = lo; i < hi; i++) s += ts.cnt[i] > k;
+    ts.part[t] = s;
+    __syncthreads();
+    for (int o = 1; o < ORD_THREADS; o <<= 1) {
+        const int v = t >= o ? ts.part[t - o] : 0;
+        __syncthreads();
+        ts.part[t] += v;
+        __syncthreads();
+    }
+    int run = ts.part[t] - s;
+    for (int i = lo; i < hi; i++) {
+        ts.pos[i] = run;
+        run += ts.cnt[i] > k;
+    }
+    const int total = ts.part[ORD_THREADS - 1];
+    __syncthreads();
+    return total;
+}
+
+// pos3(q) -> cell of the tile's q-th particle, copy(q, slot) moves it
+template <typename Cell, typename Copy>
+__device__ void order_tile3(TileOrder& ts, int C, int N, Cell cell_of_q, Copy copy)
+{
+    if (C > ORD_MAX_CELLS || N > ORD_TABLE) {
+        for (int q = threadIdx.x; q < N; q += ORD_THREADS) copy(q, q);
+        return;
+    }
+    for (int i = threadIdx.x; i < C; i += ORD_THREADS) ts.cnt[i] = 0;
+    if (threadIdx.x == 0) ts.kmax = 0;
+    __syncthreads();
+    int km = 0;
+    for (int q = threadIdx.x; q < N; q += ORD_THREADS) {
+        const int c = cell_of_q(q);
+        const int k = atomicAdd(&ts.cnt[c], 1);
+        ts.tab[q] = c | (k << 16);
+        km = max(km, k + 1);
+    }
+    for (int o = 32; o > 0; o >>= 1) km = max(km, __shfl_xor(km, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(&ts.kmax, km);
+    __syncthreads();
+    const int K = ts.kmax;
+    int base = 0;
+    for (int k = 0; k < K; k++) {
+        const int L = scan_cells(ts, C, k);
+        for (int q = threadIdx.x; q < N; q += ORD_THREADS) {
+            const int v = ts.tab[q];
+            if ((v >> 16) == k) copy(q, base + ts.pos[v & 0xffff]);
+        }
+        base += L;
+        __syncthreads();
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(ORD_THREADS) k3_sort_order_e(G3 g, Tiles3 tl, E3<R> src, E3<R> dst,
+                                                               const Seg3* seg)
+{
+    __shared__ TileOrder ts;
+    const Seg3 sg = seg[blockIdx.x];
+    if (sg.count <= 0) return;
+    const TileBox3 tb = tile_box3(g, tl, blockIdx.x);
+    const int o = sg.start;
+    order_tile3(
+        ts, tb.w[0] * tb.w[1] * tb.w[2], sg.count,
+        [&](int q) { return tb.of(g, src.x[o + q], src.y[o + q], src.z[o + q]); },
+        [&](int q, int sl) {
+            const int p = o + q, d = o + sl;
+            dst.x[d] = src.x[p]; dst.y[d] = src.y[p]; dst.z[d] = src.z[p];
+            dst.ux[d] = src.ux[p]; dst.uy[d] = src.uy[p]; dst.uz[d] = src.uz[p];
+            dst.w[d] = src.w[p]; dst.id[d] = src.id[p];
+        });
+}
+
+template <typename R>
+__global__ void __launch_bounds__(ORD_THREADS) k3_sort_order_i(G3 g, Tiles3 tl, I3<R> src, I3<R> dst, double zsh,
+                                                               const Seg3* seg)
+{
+    __shared__ TileOrder ts;
+    const Seg3 sg = seg[blockIdx.x];
+    if (sg.count <= 0) return;
+    const TileBox3 tb = tile_box3(g, tl, blockIdx.x);
+    const int o = sg.start;
+    order_tile3(
+        ts, tb.w[0] * tb.w[1] * tb.w[2], sg.count,
+        [&](int q) { return tb.of(g, src.x[o + q], src.y[o + q], src.z0[o + q] - zsh); },
+        [&](int q, int sl) {
+            const int p = o + q, d = o + sl;
+            dst.x[d] = src.x[p]; dst.y[d] = src.y[p]; dst.z0[d] = src.z0[p];
+            dst.w[d] = src.w[p]; dst.id[d] = src.id[p];
+        });
+}
+
+
+
+// number of live particles (w != 0) among n slots, one atomic per workgroup
 template <typename R>
 __global__ void __launch_bounds__(NT) k3_count_live(const R* w, int n, int* cnt)
 {
-    const int p = blockIdx.x * NT + threadIdx.x;
-    const unsigned long long m = __ballot(p < n && w[p] != R(0));
-    if (__lane_id() == 0 && m) atomicAdd(cnt, __popcll(m));
+    __shared__ int part[NT / 64];
+    int c = 0;
+    for (int p = blockIdx.x * NT + threadIdx.x; p - (int)threadIdx.x < n; p += gridDim.x * NT)
+        c += __popcll(__ballot(p < n && w[p] != R(0)));
+    if (__lane_id() == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int q = 0; q < NT / 64; q++) t += part[q];
+        if (t) atomicAdd(cnt, t);
+    }
 }
 
 // trilinear sample of a component with staggers h at r (cells)
@@ -1365,6 +1524,7 @@ void launch3_sort_e(const G3& g, const Tiles3& tl, const E3<R>& src, const E3<R>
     hipLaunchKernelGGL((k3_sort_count_e<R>), grid, dim3(NT), 0, s, g, tl, src, nused, counts);
     hipLaunchKernelGGL(k3_sort_scan, dim3(1), dim3(1024), 0, s, g, tl, counts, cursor, seg, box, tot);
     hipLaunchKernelGGL((k3_sort_scatter_e<R>), grid, dim3(NT), 0, s, g, tl, src, dst, nused, cursor);
+    hipLaunchKernelGGL((k3_sort_order_e<R>), dim3(tl.ntiles), dim3(ORD_THREADS), 0, s, g, tl, dst, src, seg);
     hipLaunchKernelGGL(k3_set_count, dim3(1), dim3(1), 0, s, nused, tot);
 }
 
@@ -1377,6 +1537,7 @@ void launch3_sort_i(const G3& g, const Tiles3& tl, const I3<R>& src, const I3<R>
     hipLaunchKernelGGL((k3_sort_count_i<R>), grid, dim3(NT), 0, s, g, tl, src, zsh, nused, counts);
     hipLaunchKernelGGL(k3_sort_scan, dim3(1), dim3(1024), 0, s, g, tl, counts, cursor, seg, box, tot);
     hipLaunchKernelGGL((k3_sort_scatter_i<R>), grid, dim3(NT), 0, s, g, tl, src, dst, zsh, nused, cursor);
+    hipLaunchKernelGGL((k3_sort_order_i<R>), dim3(tl.ntiles), dim3(ORD_THREADS), 0, s, g, tl, dst, src, zsh, seg);
     hipLaunchKernelGGL(k3_set_count, dim3(1), dim3(1), 0, s, nused, tot);
 }
 
@@ -1384,7 +1545,8 @@ template <typename R>
 void launch3_count_live(const R* w, int n, int* cnt, hipStream_t s)
 {
     (void)hipMemsetAsync(cnt, 0, sizeof(int), s);
-    if (n > 0) hipLaunchKernelGGL((k3_count_live<R>), dim3((n + NT - 1) / NT), dim3(NT), 0, s, w, n, cnt);
+    if (n > 0)
+        hipLaunchKernelGGL((k3_count_live<R>), dim3(std::min((n + NT - 1) / NT, SORT_GRID)), dim3(NT), 0, s, w, n, cnt);
 }
 
 template <typename R>

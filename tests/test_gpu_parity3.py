@@ -151,3 +151,52 @@ def test_3d_spreading_segments_match_oracle(real, tol):
         a, b = sim.field(n), ref.field(n)
         assert np.abs(a - b).max() <= tol * max(np.abs(b).max(), 1.0), n
     compare_particles3(sim, ref, 1e-9 if real == "f64" else 2e-5, 1e-9 if real == "f64" else 2e-5)
+
+
+@gpu
+def test_3d_full_size_faraday_and_sampled_electrons_match_oracle():
+    # The 3D workload at its full size (128x128x1024, 8 ppc, 134 M electrons) in the benchmark's
+    # launch configuration (default tiles, sort every 80 steps).  After three steps the fields
+    # are replaced by random ones (both sides), one more step is taken, and the oracle repeats
+    # it from the same state: every cell of B^{n+1/2} (Faraday with Friedman and the split PML)
+    # and a block of 65536 electron slots from the middle of the window (gather and push) are
+    # compared.  The current, which sums all 134 M electrons, is covered by the smaller cases.
+    from paper_1009_2727_amd import Sim, PARTICLE_BLOCK
+    w = pi.c3(real="f32", preload=True)
+    sim = Sim.from_workload(w, sort_every=80)
+    sim.step(3)
+    i0 = sim.info()
+    ref = Oracle3(w["config"])
+    ref.set_clock(i0["step"], i0["time"], i0["shift"], i0["next_row"])
+    for k, name in enumerate(["Ex", "Ey", "Ez", "Bx", "By", "Bz", "Exo", "Eyo", "Ezo", "Exb", "Eyb", "Ezb"]):
+        f = pi.random_field(ref.shape, seed=500 + k, amp=1.0)
+        sim.set_field(name, f)
+        ref.set_field(name, f)
+        del f
+    for name in ["Exs", "Eys", "Ezs", "Bxs", "Bys", "Bzs"]:
+        ref.set_field(name, sim.field(name))
+    blk = int(sim.counts()[2]) // PARTICLE_BLOCK // 2
+    before = sim.particle_block(0, blk)
+    assert len(before["id"]) > PARTICLE_BLOCK // 2
+    ref.set_electrons(before)
+    sim.step(1)
+    assert sim.sync_status() == 0
+    d = int(sim.info()["shift"] - i0["shift"])
+    after = sim.particle_block(0, blk)
+    ref.stage("faraday")
+    ref.stage("particles")
+    for name in ("Bx", "By", "Bz"):
+        a, b = sim.field(name), ref.field(name)
+        assert np.abs(a - b).max() <= 1e-5 * np.abs(b).max(), name
+        del a, b
+    got = ref.particles(0)
+    ia, ib = np.argsort(after["id"], kind="stable"), np.argsort(got["id"], kind="stable")
+    np.testing.assert_array_equal(after["id"][ia], got["id"][ib])
+    dz = w["config"]["dz_um"]
+    after["z"] = after["z"] + d * dz           # the GPU's positions are rebased into the next window
+    for k in ("x", "y", "z"):
+        cell = w["config"]["d" + k + "_um"]
+        assert np.abs(after[k][ia] - got[k][ib]).max() <= 1e-5 * cell, k
+    for k in ("ux", "uy", "uz"):
+        scale = max(np.abs(got[k]).max(), 1.0)
+        assert np.abs(after[k][ia] - got[k][ib]).max() <= 1e-5 * scale, k
