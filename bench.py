@@ -13,6 +13,10 @@ particle tile and a sort every 80 steps (the sort's amortised cost is inside the
 Prints ONE JSON line with the metric, the roofline of
 the dominant kernel (gather/push/deposit, timed with HIP events on the library's stream) and
 the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+Other workloads: --workload c3 (3D boosted frame gamma = 30, 128 x 128 x 1024, 8 ppc, 134 M
+electrons + 134 M rigid ions, window pre-loaded, 8 x 8 x 10 tiles), c4 (the batched scan),
+c5 (learned vs plain current filter).
 """
 from __future__ import annotations
 
@@ -134,7 +138,7 @@ def bench_3d(args):
                    "status": status},
         "hbm_gbps_per_step": step_bytes / (ms_step / 1e3) / 1e9,
         "phases_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in timers.items()},
-        "roofline": {"bound": "hbm", "kernel": "k3_push (gather + push + deposit)", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "k3_gpd (gather + push + deposit)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": gpd_bytes, "avg_launch_ms": gpd_ms},
     }

@@ -846,8 +846,8 @@ void layout3(const bf_config* c, Sim3* L)
     L->stcap = std::max(c->station_capacity, 1);
     // particle tiles: t x t transverse (the LDS box pitch leaves room for the stencil reach and
     // one cell of spread) by tz cells along z
-    const int tt = std::min(std::max(c->tile_x > 0 ? c->tile_x : 8, 1), bf3::BOX_PX - 6);
-    const int tz = std::max(c->tile_z > 0 ? c->tile_z : (real == 4 ? 10 : 4), 1);
+    const int tt = std::min(std::max(c->tile_x > 0 ? c->tile_x : 8, 1), std::min(bf3::BOX_PX, bf3::BOX_PY) - 6);
+    const int tz = std::max(c->tile_z > 0 ? c->tile_z : (real == 4 ? 7 : 2), 1);
     const int tv[3] = {tt, tt, tz};
     L->tl.ntiles = 1;
     for (int a = 0; a < 3; a++) {
@@ -1004,7 +1004,7 @@ bf_status create3(const bf_config* cfg, const bf_buffer_binding* b, int n, void*
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         const int cell = cfg->real_bytes == 4 ? bf3::box_cell_bytes<float>() : bf3::box_cell_bytes<double>();
-        const int fit = lds_max / (bf3::BOX_PX * bf3::BOX_PY * cell);
+        const int fit = lds_max / (bf3::BOX_PL * cell);
         s->d3->pz = std::min(s->d3->tl.t[2] + 7, fit);
     }
     hipError_t e = hipSuccess;

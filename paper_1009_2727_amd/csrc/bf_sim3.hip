@@ -382,7 +382,7 @@ __device__ __forceinline__ R rsq(R x)
 
 constexpr int GT = 512;        // threads of a segment workgroup
 constexpr int HBM_GRID = 1024; // workgroups of the pass over the particles left to HBM
-constexpr int BPX = BOX_PX, BPY = BOX_PY, BPL = BOX_PX * BOX_PY;
+constexpr int BPX = BOX_PX, BPY = BOX_PY, BPL = BOX_PL;
 
 template <typename R> struct Acc3 { using T = double; static constexpr bool fixed = false; };
 template <> struct Acc3<float> { using T = unsigned long long; static constexpr bool fixed = true; };
