@@ -1241,11 +1241,12 @@ int array3_of(int id)
     }
 }
 
-// the filtered current: the filter's first operation writes Jf, the next ones alternate
+// the filtered current: the filter's first launch writes Jf, the next ones alternate (one
+// launch per axis up to the fused limit, one per pass beyond it)
 int filtered3(const bf_config& c, int comp)
 {
     const int np = c.filter_npass + (c.filter_compensate ? 1 : 0);
-    const int ops = np > 0 ? 3 * np : 1;
+    const int ops = np <= 0 ? 1 : (np <= bf3::FILTER_FUSED ? 3 : 3 * np);
     return ((ops & 1) ? A3_JF : A3_JG) + comp;
 }
 

@@ -106,8 +106,10 @@ void launch3_faraday(const G3& g, const F3<R>& f, const Pml3& pml, const double 
                      hipStream_t s);
 template <typename R>
 void launch3_ampere(const G3& g, const F3<R>& f, const R* const J[3], const Pml3& pml, double dt, hipStream_t s);
-// n bilinear passes (+ compensation) per axis on J (the first pass reads the FP64 deposit,
-// the others ping-pong between Jf and Jg); returns in out[] where each component's result lies
+// n bilinear passes (+ compensation) per axis on J; returns in out[] where each component's
+// result lies.  Up to FILTER_FUSED passes per axis run as one launch per axis (Jf <- J, Jg <- Jf,
+// Jf <- Jg); more run pass by pass, ping-ponging between Jf and Jg after the first.
+constexpr int FILTER_FUSED = 8;
 template <typename R>
 void launch3_filter(const G3& g, const F3<R>& f, int npass, int comp, const R* out[3], hipStream_t s);
 template <typename R> void launch3_zero_j(const G3& g, const F3<R>& f, hipStream_t s);

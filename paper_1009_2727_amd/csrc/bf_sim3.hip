@@ -210,6 +210,52 @@ __global__ void __launch_bounds__(NT) k3_ampere(G3 g, F3<R> f, const R* J0, cons
 
 // one 3-point pass along AX over the stored range of a component with stagger h there;
 // neighbours beyond the range read 0, cells beyond it are copied
+// all np passes along AX at once (np <= FH): the result at a cell depends only on the 2 np + 1
+// values around it along AX, so the passes run on that window in registers, neighbours beyond
+// the component's range reading 0 after every pass (cells beyond it are copied)
+constexpr int FH = FILTER_FUSED;
+
+template <int AX, typename TI, typename R>
+__global__ void __launch_bounds__(NT) k3_ffused(G3 g, const TI* __restrict__ in, R* __restrict__ out, int h, int np,
+                                                int npass, double ac)
+{
+    int q[3];
+    if (!cell_of(g, (long)blockIdx.x * NT + threadIdx.x, q)) return;
+    const long o = o3(g, q[0], q[1], q[2]);
+    const int S = g.S[AX], per = g.per[AX];
+    const int hi = per ? S - 1 : S - 1 - h;
+    if (q[AX] > hi) { out[o] = (R)in[o]; return; }
+    double w[2 * FH + 1];
+    bool m[2 * FH + 1];
+    int p[3] = {q[0], q[1], q[2]};
+#pragma unroll
+    for (int d = -FH; d <= FH; d++) {
+        w[d + FH] = 0.0;
+        m[d + FH] = false;
+        if (d < -np || d > np) continue;
+        int j = q[AX] + d;
+        if (per) {
+            j %= S;
+            if (j < 0) j += S;
+        }
+        if (j < 0 || j > hi) continue;
+        p[AX] = j;
+        w[d + FH] = (double)in[o3(g, p[0], p[1], p[2])];
+        m[d + FH] = true;
+    }
+#pragma unroll
+    for (int s = 0; s < FH; s++) {
+        if (s >= np) break;
+        const double a = s < npass ? 0.5 : ac, b = 0.5 * (1.0 - a);
+        double t[2 * FH + 1];
+#pragma unroll
+        for (int d = 1; d < 2 * FH; d++) t[d] = m[d] ? a * w[d] + b * (w[d - 1] + w[d + 1]) : 0.0;
+#pragma unroll
+        for (int d = 1; d < 2 * FH; d++) w[d] = t[d];
+    }
+    out[o] = (R)w[FH];
+}
+
 template <int AX, typename TI, typename R>
 __global__ void __launch_bounds__(NT) k3_fpass(G3 g, const TI* __restrict__ in, R* __restrict__ out, int h, R alpha)
 {
@@ -1423,9 +1469,28 @@ void fpass(const G3& g, const TI* in, R* out, int h, R alpha, hipStream_t s)
     hipLaunchKernelGGL((k3_fpass<AX, TI, R>), cells_grid(g), dim3(NT), 0, s, g, in, out, h, alpha);
 }
 
+template <int AX, typename TI, typename R>
+void ffused(const G3& g, const TI* in, R* out, int h, int np, int npass, hipStream_t s)
+{
+    hipLaunchKernelGGL((k3_ffused<AX, TI, R>), cells_grid(g), dim3(NT), 0, s, g, in, out, h, np, npass,
+                       0.5 * npass + 1.0);
+}
+
 template <typename R>
 void launch3_filter(const G3& g, const F3<R>& f, int npass, int comp, const R* out[3], hipStream_t s)
 {
+    const int np = npass + (comp ? 1 : 0);
+    if (np > 0 && np <= FH) {
+        // one launch per axis: Jf <- J (FP64), Jg <- Jf, Jf <- Jg
+        for (int c = 0; c < 3; c++) {
+            const int h[3] = {c == 0, c == 1, c == 2};
+            ffused<0>(g, (const double*)f.J[c], f.Jf[c], h[0], np, npass, s);
+            ffused<1>(g, (const R*)f.Jf[c], f.Jg[c], h[1], np, npass, s);
+            ffused<2>(g, (const R*)f.Jg[c], f.Jf[c], h[2], np, npass, s);
+            out[c] = f.Jf[c];
+        }
+        return;
+    }
     for (int c = 0; c < 3; c++) {
         const int h[3] = {c == 0, c == 1, c == 2};
         const int np = npass + (comp ? 1 : 0);
