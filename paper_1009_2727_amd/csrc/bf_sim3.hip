@@ -53,21 +53,25 @@ __device__ __forceinline__ int sidx(const G3& g, int a, int j)
     return (j < 0 || j >= g.S[a]) ? -1 : j;
 }
 
-__device__ __forceinline__ bool cell_of(const G3& g, long idx, int q[3])
+// cell of a thread in the per-cell launches: 32 x 8 threads per workgroup over (x, y), one
+// workgroup row per z plane
+constexpr int CBX = 32, CBY = 8;
+
+__device__ __forceinline__ bool cell_of(const G3& g, int q[3])
 {
-    const long n = (long)g.S[0] * g.S[1] * g.S[2];
-    if (idx >= n) return false;
-    q[0] = (int)(idx % g.S[0]);
-    q[1] = (int)((idx / g.S[0]) % g.S[1]);
-    q[2] = (int)(idx / ((long)g.S[0] * g.S[1]));
-    return true;
+    q[0] = (int)(blockIdx.x * CBX + threadIdx.x);
+    q[1] = (int)(blockIdx.y * CBY + threadIdx.y);
+    q[2] = (int)blockIdx.z;
+    return q[0] < g.S[0] && q[1] < g.S[1];
 }
 
 inline dim3 cells_grid(const G3& g)
 {
-    const long n = (long)g.S[0] * g.S[1] * g.S[2];
-    return dim3((unsigned)((n + NT - 1) / NT));
+    return dim3((unsigned)((g.S[0] + CBX - 1) / CBX), (unsigned)((g.S[1] + CBY - 1) / CBY), (unsigned)g.S[2]);
 }
+
+inline dim3 cells_block() { return dim3(CBX, CBY); }
+static_assert(CBX * CBY == NT, "per-cell launches use NT threads");
 
 // ---- field solver ---------------------------------------------------------------------------
 
@@ -113,6 +117,31 @@ __device__ __forceinline__ R dstar(const R* __restrict__ G, const G3& g, const i
     return v;
 }
 
+// Delta*_AX G of a cell at least one cell from every non-periodic edge: off[a][s + 1] is the
+// offset of shift s in {-1, 0, 1} along axis a (the z entries carry the ring), so every
+// neighbour is one sum of three offsets
+template <int AX, typename R>
+__device__ __forceinline__ R dstar_in(const R* __restrict__ G, const long off[3][3], int ht, R a, R b, R c, R id)
+{
+    constexpr int T1 = (AX + 1) % 3, T2 = (AX + 2) % 3;
+    auto D = [&](int t1, int t2) {
+        int s[3];
+        s[T1] = t1;
+        s[T2] = t2;
+        s[AX] = ht;
+        const long hi = off[0][s[0] + 1] + off[1][s[1] + 1] + off[2][s[2] + 1];
+        s[AX] = ht - 1;
+        const long lo = off[0][s[0] + 1] + off[1][s[1] + 1] + off[2][s[2] + 1];
+        return G[hi] - G[lo];
+    };
+    R v = a * D(0, 0);
+    if (b != R(0) || c != R(0)) {
+        v += b * (D(1, 0) + D(-1, 0) + D(0, 1) + D(0, -1));
+        if (c != R(0)) v += c * (D(1, 1) + D(1, -1) + D(-1, 1) + D(-1, -1));
+    }
+    return v * id;
+}
+
 // split update of one component from its curl terms t1 (axis A1, the stored part) and t2
 template <int A1, int A2, typename R>
 __device__ __forceinline__ R split_update(R old, R* sp, long o, R t1, R t2, const Pml3& pml, const int q[3],
@@ -134,7 +163,7 @@ template <typename R>
 __global__ void __launch_bounds__(NT) k3_friedman(G3 g, F3<R> f, R th)
 {
     int q[3];
-    if (!cell_of(g, (long)blockIdx.x * NT + threadIdx.x, q)) return;
+    if (!cell_of(g, q)) return;
     const long o = o3(g, q[0], q[1], q[2]);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -149,7 +178,7 @@ __global__ void __launch_bounds__(NT) k3_friedman(G3 g, F3<R> f, R th)
 // and on half nodes along A1, A2
 template <int C, typename R>
 __device__ __forceinline__ void faraday_comp(const G3& g, const F3<R>& f, const R* const* Et, const Pml3& pml,
-                                             const int q[3], R a, R b, R cg, R dt)
+                                             const int q[3], R a, R b, R cg, R dt, bool in, const long (&off)[3][3])
 {
     constexpr int A1 = (C + 1) % 3, A2 = (C + 2) % 3;
     const int h[3] = {C == 0 ? 0 : 1, C == 1 ? 0 : 1, C == 2 ? 0 : 1};
@@ -159,8 +188,14 @@ __device__ __forceinline__ void faraday_comp(const G3& g, const F3<R>& f, const 
 #pragma unroll
     for (int d = 0; d < 3; d++)
         if (!g.per[d] && q[d] > g.S[d] - 1 - h[d]) return;
-    const R t1 = -dstar<A1>(Et[A2], g, q, h[A1], a, b, cg);
-    const R t2 = dstar<A2>(Et[A1], g, q, h[A2], a, b, cg);
+    R t1, t2;
+    if (in) {
+        t1 = -dstar_in<A1>(Et[A2], off, h[A1], a, b, cg, (R)(1.0 / g.d[A1]));
+        t2 = dstar_in<A2>(Et[A1], off, h[A2], a, b, cg, (R)(1.0 / g.d[A2]));
+    } else {
+        t1 = -dstar<A1>(Et[A2], g, q, h[A1], a, b, cg);
+        t2 = dstar<A2>(Et[A1], g, q, h[A2], a, b, cg);
+    }
     f.B[C][o] = split_update<A1, A2>(old, f.SB[C], o, t1, t2, pml, q, h, dt);
 }
 
@@ -168,11 +203,23 @@ template <typename R>
 __global__ void __launch_bounds__(NT) k3_faraday(G3 g, F3<R> f, Pml3 pml, R a, R b, R cg, R dt, int use_t)
 {
     int q[3];
-    if (!cell_of(g, (long)blockIdx.x * NT + threadIdx.x, q)) return;
+    if (!cell_of(g, q)) return;
     const R* Et[3] = {use_t ? f.T[0] : f.E[0], use_t ? f.T[1] : f.E[1], use_t ? f.T[2] : f.E[2]};
-    faraday_comp<0>(g, f, Et, pml, q, a, b, cg, dt);
-    faraday_comp<1>(g, f, Et, pml, q, a, b, cg, dt);
-    faraday_comp<2>(g, f, Et, pml, q, a, b, cg, dt);
+    bool in = true;
+#pragma unroll
+    for (int d = 0; d < 3; d++) in = in && (g.per[d] || (q[d] >= 1 && q[d] <= g.S[d] - 2));
+    long off[3][3];
+#pragma unroll
+    for (int s = -1; s <= 1; s++) {
+        off[0][s + 1] = nb(q[0], s, g.S[0], g.per[0]);
+        off[1][s + 1] = (long)nb(q[1], s, g.S[1], g.per[1]) * g.pitch;
+        int kk = nb(q[2], s, g.S[2], g.per[2]) + g.zoff;
+        if (kk >= g.S[2]) kk -= g.S[2];
+        off[2][s + 1] = (long)kk * g.plane;
+    }
+    faraday_comp<0>(g, f, Et, pml, q, a, b, cg, dt, in, off);
+    faraday_comp<1>(g, f, Et, pml, q, a, b, cg, dt, in, off);
+    faraday_comp<2>(g, f, Et, pml, q, a, b, cg, dt, in, off);
 }
 
 // dE_C/dt = Delta_A1 B_A2 - Delta_A2 B_A1 - J_C; E_C sits on a half node along C, nodes along
@@ -201,7 +248,7 @@ template <typename R>
 __global__ void __launch_bounds__(NT) k3_ampere(G3 g, F3<R> f, const R* J0, const R* J1, const R* J2, Pml3 pml, R dt)
 {
     int q[3];
-    if (!cell_of(g, (long)blockIdx.x * NT + threadIdx.x, q)) return;
+    if (!cell_of(g, q)) return;
     const R* J[3] = {J0, J1, J2};
     ampere_comp<0>(g, f, J, pml, q, dt);
     ampere_comp<1>(g, f, J, pml, q, dt);
@@ -220,7 +267,7 @@ __global__ void __launch_bounds__(NT) k3_ffused(G3 g, const TI* __restrict__ in,
                                                 int npass, double ac)
 {
     int q[3];
-    if (!cell_of(g, (long)blockIdx.x * NT + threadIdx.x, q)) return;
+    if (!cell_of(g, q)) return;
     const long o = o3(g, q[0], q[1], q[2]);
     const int S = g.S[AX], per = g.per[AX];
     const int hi = per ? S - 1 : S - 1 - h;
@@ -260,7 +307,7 @@ template <int AX, typename TI, typename R>
 __global__ void __launch_bounds__(NT) k3_fpass(G3 g, const TI* __restrict__ in, R* __restrict__ out, int h, R alpha)
 {
     int q[3];
-    if (!cell_of(g, (long)blockIdx.x * NT + threadIdx.x, q)) return;
+    if (!cell_of(g, q)) return;
     const long o = o3(g, q[0], q[1], q[2]);
     const int hi = g.per[AX] ? g.S[AX] - 1 : g.S[AX] - 1 - h;
     if (q[AX] > hi) { out[o] = (R)in[o]; return; }
@@ -275,7 +322,7 @@ __global__ void __launch_bounds__(NT) k3_fpass(G3 g, const TI* __restrict__ in, 
 __global__ void __launch_bounds__(NT) k3_zero3(G3 g, double* a, double* b, double* c)
 {
     int q[3];
-    if (!cell_of(g, (long)blockIdx.x * NT + threadIdx.x, q)) return;
+    if (!cell_of(g, q)) return;
     const long o = o3(g, q[0], q[1], q[2]);
     a[o] = 0.0;
     b[o] = 0.0;
@@ -1064,7 +1111,7 @@ template <typename R>
 __global__ void __launch_bounds__(NT) k3_window(G3 g, F3<R> f, int d)
 {
     int q[3];
-    if (!cell_of(g, (long)blockIdx.x * NT + threadIdx.x, q)) return;
+    if (!cell_of(g, q)) return;
     const int Sz = g.S[2], k = q[2];
     const long o = o3(g, q[0], q[1], k);
     if ((d > 0 && k >= Sz - d) || (d < 0 && k < -d)) {
@@ -1446,33 +1493,33 @@ __global__ void k3_stations(G3 g, F3<R> f, const double* zlab, int nst, double g
 template <typename R>
 void launch3_friedman(const G3& g, const F3<R>& f, double theta, hipStream_t s)
 {
-    hipLaunchKernelGGL((k3_friedman<R>), cells_grid(g), dim3(NT), 0, s, g, f, (R)theta);
+    hipLaunchKernelGGL((k3_friedman<R>), cells_grid(g), cells_block(), 0, s, g, f, (R)theta);
 }
 
 template <typename R>
 void launch3_faraday(const G3& g, const F3<R>& f, const Pml3& pml, const double ck[3], double theta, double dt,
                      hipStream_t s)
 {
-    hipLaunchKernelGGL((k3_faraday<R>), cells_grid(g), dim3(NT), 0, s, g, f, pml, (R)ck[0], (R)ck[1], (R)ck[2],
+    hipLaunchKernelGGL((k3_faraday<R>), cells_grid(g), cells_block(), 0, s, g, f, pml, (R)ck[0], (R)ck[1], (R)ck[2],
                        (R)dt, theta > 0.0 ? 1 : 0);
 }
 
 template <typename R>
 void launch3_ampere(const G3& g, const F3<R>& f, const R* const J[3], const Pml3& pml, double dt, hipStream_t s)
 {
-    hipLaunchKernelGGL((k3_ampere<R>), cells_grid(g), dim3(NT), 0, s, g, f, J[0], J[1], J[2], pml, (R)dt);
+    hipLaunchKernelGGL((k3_ampere<R>), cells_grid(g), cells_block(), 0, s, g, f, J[0], J[1], J[2], pml, (R)dt);
 }
 
 template <int AX, typename TI, typename R>
 void fpass(const G3& g, const TI* in, R* out, int h, R alpha, hipStream_t s)
 {
-    hipLaunchKernelGGL((k3_fpass<AX, TI, R>), cells_grid(g), dim3(NT), 0, s, g, in, out, h, alpha);
+    hipLaunchKernelGGL((k3_fpass<AX, TI, R>), cells_grid(g), cells_block(), 0, s, g, in, out, h, alpha);
 }
 
 template <int AX, typename TI, typename R>
 void ffused(const G3& g, const TI* in, R* out, int h, int np, int npass, hipStream_t s)
 {
-    hipLaunchKernelGGL((k3_ffused<AX, TI, R>), cells_grid(g), dim3(NT), 0, s, g, in, out, h, np, npass,
+    hipLaunchKernelGGL((k3_ffused<AX, TI, R>), cells_grid(g), cells_block(), 0, s, g, in, out, h, np, npass,
                        0.5 * npass + 1.0);
 }
 
@@ -1524,7 +1571,7 @@ void launch3_filter(const G3& g, const F3<R>& f, int npass, int comp, const R* o
 template <typename R>
 void launch3_zero_j(const G3& g, const F3<R>& f, hipStream_t s)
 {
-    hipLaunchKernelGGL(k3_zero3, cells_grid(g), dim3(NT), 0, s, g, f.J[0], f.J[1], f.J[2]);
+    hipLaunchKernelGGL(k3_zero3, cells_grid(g), cells_block(), 0, s, g, f.J[0], f.J[1], f.J[2]);
 }
 
 template <typename R>
@@ -1577,7 +1624,7 @@ void launch3_window(const G3& g, const F3<R>& f, const Pml3& pml, int d, hipStre
 {
     (void)pml;
     if (d == 0) return;
-    hipLaunchKernelGGL((k3_window<R>), cells_grid(g), dim3(NT), 0, s, g, f, d);
+    hipLaunchKernelGGL((k3_window<R>), cells_grid(g), cells_block(), 0, s, g, f, d);
 }
 
 template <typename R>
