@@ -140,7 +140,9 @@ def bench_3d(args):
         "phases_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in timers.items()},
         "roofline": {"bound": "hbm", "kernel": "k3_gpd (gather + push + deposit)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": gpd_bytes, "avg_launch_ms": gpd_ms},
+                     "algorithmic_bytes_per_launch": gpd_bytes, "avg_launch_ms": gpd_ms,
+                     "limiter": "LDS: 8-byte current adds and gather reads, with bank conflicts "
+                                "(rocprofv3 counters in profiles/)"},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline3(args)
