@@ -1043,10 +1043,10 @@ void sort3(bf_sim* s)
     int* nu = w3<int>(s, L.w_nused);
     int *cnt = w3<int>(s, L.w_counts), *cur = w3<int>(s, L.w_cursor), *tot = w3<int>(s, L.w_tot);
     bf3::launch3_sort_e<R>(L.g, L.tl, electrons3<R>(s, a), electrons3<R>(s, b), nu, cnt, cur, tot, seg3<R>(s, 0),
-                           box3(s, 0, L.bb_cur), L.cap, s->stream);
+                           box3(s, 0, L.bb_cur), L.cap, s->have_plasma ? s->plasma.ppc : 1, s->stream);
     if (s->have_plasma && s->plasma.ion_mode == 1)
         bf3::launch3_sort_i<R>(L.g, L.tl, ions3<R>(s, a), ions3<R>(s, b), zshift3(s, s->t), nu + 1, cnt, cur,
-                               tot + 1, seg3<R>(s, 1), box3(s, 1, L.bb_cur), L.cap, s->stream);
+                               tot + 1, seg3<R>(s, 1), box3(s, 1, L.bb_cur), L.cap, s->plasma.ppc, s->stream);
     L.nseg = L.tl.ntiles;
     L.since_sort = 0;
 }

@@ -140,15 +140,16 @@ void launch3_inject(const G3& g, const Tiles3& tl, const E3<R>& e, const I3<R>& 
 template <typename R>
 void launch3_window(const G3& g, const F3<R>& f, const Pml3& pml, int d, hipStream_t s);
 // counting sort of the live particles (w != 0) of slots [0, *nused) of src by tile, through dst
-// (scatter by tile into dst, then each tile back into src level by level in cell order):
+// (scatter by tile into dst, then each tile back into src in plasma-lattice order, ppc
+// particles per lattice cell):
 // segment t = tile t with its cell box, *nused = live count; counts/cursor hold ntiles ints,
 // tot one int of scratch.  Ions are binned at z0 - zsh.
 template <typename R>
 void launch3_sort_e(const G3& g, const Tiles3& tl, const E3<R>& src, const E3<R>& dst, int* nused, int* counts,
-                    int* cursor, int* tot, Seg3* seg, Box3* box, int64_t cap, hipStream_t s);
+                    int* cursor, int* tot, Seg3* seg, Box3* box, int64_t cap, int ppc, hipStream_t s);
 template <typename R>
 void launch3_sort_i(const G3& g, const Tiles3& tl, const I3<R>& src, const I3<R>& dst, double zsh, int* nused,
-                    int* counts, int* cursor, int* tot, Seg3* seg, Box3* box, int64_t cap, hipStream_t s);
+                    int* counts, int* cursor, int* tot, Seg3* seg, Box3* box, int64_t cap, int ppc, hipStream_t s);
 // live particles (w != 0) among n slots into *cnt (zeroed here)
 template <typename R> void launch3_count_live(const R* w, int n, int* cnt, hipStream_t s);
 template <typename R>

@@ -1276,20 +1276,65 @@ __global__ void __launch_bounds__(NT) k3_sort_scatter_i(G3 g, Tiles3 tl, I3<R> s
 
 __global__ void k3_set_count(int* nused, const int* tot) { *nused = *tot; }
 
-// Order within each tile after the scatter: the particles of level k are the k-th particles
-// of their cells, and the tile is laid out level by level, each level in cell order (x
-// fastest).  Consecutive lanes of a wave then sit in consecutive cells of a few x rows, whose
-// LDS accumulators fall in distinct bank pairs for the 8-byte adds of the deposit.
+// Order within each tile after the scatter, by the particle's place in the plasma lattice: its
+// id encodes the lattice plane l, the cell (i, j) and the index k < ppc within the cell, and
+// the tile is laid out by (l, k, j, i), i fastest, over the tile's i, j range.  A wave of 64
+// lanes then holds the k-th particles of one lattice plane over an 8 x 8 block of cells: the
+// lanes sit in distinct (x, y) cells and differ in z by at most one plane (the plasma drifts
+// rigidly), which the LDS box layout keeps in distinct bank pairs.  Ids outside the pattern
+// (particles loaded from outside) only fall in clamped places: any order is valid.  Equal
+// keys are spread level by level (the k-th particle with a key in level k).
 constexpr int ORD_THREADS = 512;
-constexpr int ORD_MAX_CELLS = 1024;   // cells of a tile ordered in LDS (larger tiles keep the scatter order)
-constexpr int ORD_TABLE = 8192;       // particles of a tile ordered in LDS
+constexpr int ORD_MAX_CELLS = 8192;   // keys of a tile ordered in LDS
+constexpr int ORD_TABLE = 8192;       // particles of a tile ordered in LDS (more keep the scatter order)
 
 struct TileOrder {
     int cnt[ORD_MAX_CELLS], pos[ORD_MAX_CELLS];
-    int tab[ORD_TABLE];               // per particle: tile cell | level << 16
+    int tab[ORD_TABLE];               // per particle: key | level << 16
     int part[ORD_THREADS];
-    int kmax;
+    int kmax, lmin;
 };
+
+// lattice key of a particle id within a tile (origin o, width w), planes from lmin, lr planes
+struct LatticeKey {
+    int n0, n1, ppc, o0, o1, w0, w1, lmin, lr;
+    __device__ __forceinline__ int row(uint32_t id) const { return (int)(id / (uint32_t)ppc / (uint32_t)(n0 * n1)); }
+    __device__ __forceinline__ int of(uint32_t id) const
+    {
+        const int k = (int)(id % (uint32_t)ppc);
+        const uint32_t rest = id / (uint32_t)ppc;
+        const int i = (int)(rest % (uint32_t)n0), j = (int)((rest / (uint32_t)n0) % (uint32_t)n1);
+        const int l = (int)(rest / (uint32_t)(n0 * n1));
+        const int li = min(max(i - o0, 0), w0 - 1), lj = min(max(j - o1, 0), w1 - 1);
+        const int ll = min(max(l - lmin, 0), lr - 1);
+        return ((ll * ppc + k) * w1 + lj) * w0 + li;
+    }
+};
+
+// the lattice key of the tile's particles (ids ids[0..N)) for block t
+__device__ LatticeKey lattice_key(TileOrder& ts, const G3& g, const Tiles3& tl, int t, int ppc, const uint32_t* ids,
+                                  int N)
+{
+    LatticeKey lk;
+    const int ti[2] = {t % tl.nt[0], (t / tl.nt[0]) % tl.nt[1]};
+    lk.n0 = g.N[0];
+    lk.n1 = g.N[1];
+    lk.ppc = max(ppc, 1);
+    lk.o0 = ti[0] * tl.t[0];
+    lk.o1 = ti[1] * tl.t[1];
+    lk.w0 = min(tl.t[0], g.N[0] - lk.o0);
+    lk.w1 = min(tl.t[1], g.N[1] - lk.o1);
+    lk.lr = max(1, ORD_MAX_CELLS / (lk.ppc * lk.w0 * lk.w1));
+    if (threadIdx.x == 0) ts.lmin = INT_MAX;
+    __syncthreads();
+    int lm = INT_MAX;
+    for (int q = threadIdx.x; q < N; q += ORD_THREADS) lm = min(lm, lk.row(ids[q]));
+    for (int o = 32; o > 0; o >>= 1) lm = min(lm, __shfl_xor(lm, o));
+    if ((threadIdx.x & 63) == 0) atomicMin(&ts.lmin, lm);
+    __syncthreads();
+    lk.lmin = ts.lmin;
+    return lk;
+}
 
 // cell of a tile (clamped as the tile key clamps)
 struct TileBox3 {
@@ -1380,16 +1425,15 @@ __device__ void order_tile3(TileOrder& ts, int C, int N, Cell cell_of_q, Copy co
 
 template <typename R>
 __global__ void __launch_bounds__(ORD_THREADS) k3_sort_order_e(G3 g, Tiles3 tl, E3<R> src, E3<R> dst,
-                                                               const Seg3* seg)
+                                                               const Seg3* seg, int ppc)
 {
     __shared__ TileOrder ts;
     const Seg3 sg = seg[blockIdx.x];
     if (sg.count <= 0) return;
-    const TileBox3 tb = tile_box3(g, tl, blockIdx.x);
     const int o = sg.start;
+    const LatticeKey lk = lattice_key(ts, g, tl, blockIdx.x, ppc, src.id + o, min(sg.count, ORD_TABLE));
     order_tile3(
-        ts, tb.w[0] * tb.w[1] * tb.w[2], sg.count,
-        [&](int q) { return tb.of(g, src.x[o + q], src.y[o + q], src.z[o + q]); },
+        ts, lk.lr * lk.ppc * lk.w0 * lk.w1, sg.count, [&](int q) { return lk.of(src.id[o + q]); },
         [&](int q, int sl) {
             const int p = o + q, d = o + sl;
             dst.x[d] = src.x[p]; dst.y[d] = src.y[p]; dst.z[d] = src.z[p];
@@ -1399,17 +1443,16 @@ __global__ void __launch_bounds__(ORD_THREADS) k3_sort_order_e(G3 g, Tiles3 tl, 
 }
 
 template <typename R>
-__global__ void __launch_bounds__(ORD_THREADS) k3_sort_order_i(G3 g, Tiles3 tl, I3<R> src, I3<R> dst, double zsh,
-                                                               const Seg3* seg)
+__global__ void __launch_bounds__(ORD_THREADS) k3_sort_order_i(G3 g, Tiles3 tl, I3<R> src, I3<R> dst,
+                                                               const Seg3* seg, int ppc)
 {
     __shared__ TileOrder ts;
     const Seg3 sg = seg[blockIdx.x];
     if (sg.count <= 0) return;
-    const TileBox3 tb = tile_box3(g, tl, blockIdx.x);
     const int o = sg.start;
+    const LatticeKey lk = lattice_key(ts, g, tl, blockIdx.x, ppc, src.id + o, min(sg.count, ORD_TABLE));
     order_tile3(
-        ts, tb.w[0] * tb.w[1] * tb.w[2], sg.count,
-        [&](int q) { return tb.of(g, src.x[o + q], src.y[o + q], src.z0[o + q] - zsh); },
+        ts, lk.lr * lk.ppc * lk.w0 * lk.w1, sg.count, [&](int q) { return lk.of(src.id[o + q]); },
         [&](int q, int sl) {
             const int p = o + q, d = o + sl;
             dst.x[d] = src.x[p]; dst.y[d] = src.y[p]; dst.z0[d] = src.z0[p];
@@ -1629,27 +1672,27 @@ void launch3_window(const G3& g, const F3<R>& f, const Pml3& pml, int d, hipStre
 
 template <typename R>
 void launch3_sort_e(const G3& g, const Tiles3& tl, const E3<R>& src, const E3<R>& dst, int* nused, int* counts,
-                    int* cursor, int* tot, Seg3* seg, Box3* box, int64_t cap, hipStream_t s)
+                    int* cursor, int* tot, Seg3* seg, Box3* box, int64_t cap, int ppc, hipStream_t s)
 {
     const dim3 grid((unsigned)std::min<int64_t>(SORT_GRID, (cap + NT - 1) / NT));
     (void)hipMemsetAsync(counts, 0, sizeof(int) * tl.ntiles, s);
     hipLaunchKernelGGL((k3_sort_count_e<R>), grid, dim3(NT), 0, s, g, tl, src, nused, counts);
     hipLaunchKernelGGL(k3_sort_scan, dim3(1), dim3(1024), 0, s, g, tl, counts, cursor, seg, box, tot);
     hipLaunchKernelGGL((k3_sort_scatter_e<R>), grid, dim3(NT), 0, s, g, tl, src, dst, nused, cursor);
-    hipLaunchKernelGGL((k3_sort_order_e<R>), dim3(tl.ntiles), dim3(ORD_THREADS), 0, s, g, tl, dst, src, seg);
+    hipLaunchKernelGGL((k3_sort_order_e<R>), dim3(tl.ntiles), dim3(ORD_THREADS), 0, s, g, tl, dst, src, seg, ppc);
     hipLaunchKernelGGL(k3_set_count, dim3(1), dim3(1), 0, s, nused, tot);
 }
 
 template <typename R>
 void launch3_sort_i(const G3& g, const Tiles3& tl, const I3<R>& src, const I3<R>& dst, double zsh, int* nused,
-                    int* counts, int* cursor, int* tot, Seg3* seg, Box3* box, int64_t cap, hipStream_t s)
+                    int* counts, int* cursor, int* tot, Seg3* seg, Box3* box, int64_t cap, int ppc, hipStream_t s)
 {
     const dim3 grid((unsigned)std::min<int64_t>(SORT_GRID, (cap + NT - 1) / NT));
     (void)hipMemsetAsync(counts, 0, sizeof(int) * tl.ntiles, s);
     hipLaunchKernelGGL((k3_sort_count_i<R>), grid, dim3(NT), 0, s, g, tl, src, zsh, nused, counts);
     hipLaunchKernelGGL(k3_sort_scan, dim3(1), dim3(1024), 0, s, g, tl, counts, cursor, seg, box, tot);
     hipLaunchKernelGGL((k3_sort_scatter_i<R>), grid, dim3(NT), 0, s, g, tl, src, dst, zsh, nused, cursor);
-    hipLaunchKernelGGL((k3_sort_order_i<R>), dim3(tl.ntiles), dim3(ORD_THREADS), 0, s, g, tl, dst, src, zsh, seg);
+    hipLaunchKernelGGL((k3_sort_order_i<R>), dim3(tl.ntiles), dim3(ORD_THREADS), 0, s, g, tl, dst, src, seg, ppc);
     hipLaunchKernelGGL(k3_set_count, dim3(1), dim3(1), 0, s, nused, tot);
 }
 
@@ -1689,9 +1732,9 @@ void launch3_stations(const G3& g, const F3<R>& f, const double* zlab, int nst, 
                                     Box3*, Seg3*, Box3*, int, const Inject3&, int*, hipStream_t);          \
     template void launch3_window<R>(const G3&, const F3<R>&, const Pml3&, int, hipStream_t);                \
     template void launch3_sort_e<R>(const G3&, const Tiles3&, const E3<R>&, const E3<R>&, int*, int*, int*,   \
-                                    int*, Seg3*, Box3*, int64_t, hipStream_t);                              \
+                                    int*, Seg3*, Box3*, int64_t, int, hipStream_t);                         \
     template void launch3_sort_i<R>(const G3&, const Tiles3&, const I3<R>&, const I3<R>&, double, int*, int*,  \
-                                    int*, int*, Seg3*, Box3*, int64_t, hipStream_t);                        \
+                                    int*, int*, Seg3*, Box3*, int64_t, int, hipStream_t);                   \
     template void launch3_stations<R>(const G3&, const F3<R>&, const double*, int, double, double, double,  \
                                       double, double*, int*, int, hipStream_t);
 BF3_INST(float)
