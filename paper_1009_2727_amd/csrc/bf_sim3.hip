@@ -473,7 +473,8 @@ __device__ __forceinline__ R rsq(R x)
 // segment whose box exceeds the LDS pitches, takes the same steps on the fields and current
 // in HBM.
 
-constexpr int GT = 512;        // threads of a segment workgroup
+constexpr int GT = 768;        // threads of an electron segment workgroup
+constexpr int GTI = 512;       // threads of an ion segment workgroup
 constexpr int HBM_GRID = 1024; // workgroups of the pass over the particles left to HBM
 constexpr int BPX = BOX_PX, BPY = BOX_PY, BPL = BOX_PL;
 
@@ -649,11 +650,11 @@ __device__ __forceinline__ void deposit_box_z(const BoxL<R>& bx, double x, doubl
 }
 
 // stage the box: fields (electrons) and zeroed accumulators (nj planes)
-template <typename R, bool FIELDS>
+template <int NTH, typename R, bool FIELDS>
 __device__ void stage_box(const G3& g, const F3<R>& f, const BoxL<R>& bx, int nj)
 {
     const int L = bx.ext[0] * bx.ext[1] * bx.ext[2];
-    for (int q = threadIdx.x; q < L; q += GT) {
+    for (int q = threadIdx.x; q < L; q += NTH) {
         const int a = q % bx.ext[0], b = (q / bx.ext[0]) % bx.ext[1], c = q / (bx.ext[0] * bx.ext[1]);
         const int t = a + BPX * b + BPL * c;
         if constexpr (FIELDS) {
@@ -675,11 +676,11 @@ __device__ void stage_box(const G3& g, const F3<R>& f, const BoxL<R>& bx, int nj
 }
 
 // add the box's accumulators to the FP64 current (planes c0 .. c0 + nj - 1 of J)
-template <typename R>
+template <int NTH, typename R>
 __device__ void flush_box(const G3& g, const F3<R>& f, const BoxL<R>& bx, int c0, int nj, double jq)
 {
     const int L = bx.ext[0] * bx.ext[1] * bx.ext[2];
-    for (int q = threadIdx.x; q < L; q += GT) {
+    for (int q = threadIdx.x; q < L; q += NTH) {
         const int a = q % bx.ext[0], b = (q / bx.ext[0]) % bx.ext[1], c = q / (bx.ext[0] * bx.ext[1]);
         const int si = sidx(g, 0, bx.lo[0] + a), sj = sidx(g, 1, bx.lo[1] + b), sk = sidx(g, 2, bx.lo[2] + c);
         if (si < 0 || sj < 0 || sk < 0) continue;
@@ -692,6 +693,7 @@ __device__ void flush_box(const G3& g, const F3<R>& f, const BoxL<R>& bx, int c0
     }
 }
 
+template <int NTH>
 __device__ __forceinline__ double block_sum3(double v, double* red)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -699,12 +701,13 @@ __device__ __forceinline__ double block_sum3(double v, double* red)
     __syncthreads();
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < GT / 64; w++) t += red[w];
+    for (int w = 0; w < NTH / 64; w++) t += red[w];
     return t;
 }
 
 // min/max of the 6 box bounds over the workgroup, written by thread 0
-__device__ __forceinline__ void block_box(int nb[6], int (*red)[GT / 64], Box3* out)
+template <int NTH>
+__device__ __forceinline__ void block_box(int nb[6], int (*red)[NTH / 64], Box3* out)
 {
 #pragma unroll
     for (int q = 0; q < 6; q++)
@@ -720,7 +723,7 @@ __device__ __forceinline__ void block_box(int nb[6], int (*red)[GT / 64], Box3* 
         Box3 b;
         for (int a = 0; a < 3; a++) {
             int lo = INT_MAX, hi = INT_MIN;
-            for (int w = 0; w < GT / 64; w++) {
+            for (int w = 0; w < NTH / 64; w++) {
                 lo = min(lo, red[2 * a][w]);
                 hi = max(hi, red[2 * a + 1][w]);
             }
@@ -845,21 +848,21 @@ __global__ void __launch_bounds__(GT) k3_gpd(G3 g, F3<R> f, E3<R> e, const Seg3*
             if constexpr (Acc3<R>::fixed) {
                 double sw = 0.0;
                 for (int p = sg.start + threadIdx.x; p < end; p += GT) sw += fabs((double)e.w[p]);
-                sw = block_sum3(sw, redd);
+                sw = block_sum3<GT>(sw, redd);
                 const double bound = fmax(fabs(pp.jk[0]), fmax(fabs(pp.jk[1]), fabs(pp.jk[2]))) * sw;
                 if (bound > 0.0) { js = FX_RANGE / bound; jq = bound / FX_RANGE; }
             }
-            stage_box<R, true>(g, f, bx, 3);
+            stage_box<GT, R, true>(g, f, bx, 3);
             __syncthreads();
             for (int p = sg.start + threadIdx.x; p < end; p += GT)
                 if (!electron3<true>(g, f, bx, e, p, pp, js, status, nb)) mis[atomicAdd(nmis, 1)] = make_int2(blockIdx.x, p);
             __syncthreads();
-            flush_box(g, f, bx, 0, 3, jq);
+            flush_box<GT>(g, f, bx, 0, 3, jq);
         } else if (threadIdx.x == 0) {
             big[atomicAdd(nbig, 1)] = blockIdx.x;
         }
     }
-    block_box(nb, red, &bout[blockIdx.x]);
+    block_box<GT>(nb, red, &bout[blockIdx.x]);
 }
 
 // box bounds of a wave's particles into a segment's box (one lane per wave)
@@ -923,13 +926,13 @@ __global__ void __launch_bounds__(NT) k3_gpd_hbm(G3 g, F3<R> f, E3<R> e, const S
 
 // rigid ions (q = +1): z(t) = z0 - (beta t / dz + shift), J_z only
 template <typename R>
-__global__ void __launch_bounds__(GT) k3_gpi(G3 g, F3<R> f, I3<R> ion, const Seg3* __restrict__ seg,
+__global__ void __launch_bounds__(GTI) k3_gpi(G3 g, F3<R> f, I3<R> ion, const Seg3* __restrict__ seg,
                                              const Box3* __restrict__ bin, Box3* __restrict__ bout, double zsa,
                                              double zsb, double zsn, Push3 pp, int pz)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem3[];
-    __shared__ int red[6][GT / 64];
-    __shared__ double redd[GT / 64];
+    __shared__ int red[6][GTI / 64];
+    __shared__ double redd[GTI / 64];
     const Seg3 sg = seg[blockIdx.x];
     const Box3 bb = bin[blockIdx.x];
     int nb[6] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN};
@@ -944,15 +947,15 @@ __global__ void __launch_bounds__(GT) k3_gpi(G3 g, F3<R> f, I3<R> ion, const Seg
         if (lds) {
             if constexpr (Acc3<R>::fixed) {
                 double sw = 0.0;
-                for (int p = sg.start + threadIdx.x; p < end; p += GT) sw += fabs((double)ion.w[p]);
-                sw = block_sum3(sw, redd);
+                for (int p = sg.start + threadIdx.x; p < end; p += GTI) sw += fabs((double)ion.w[p]);
+                sw = block_sum3<GTI>(sw, redd);
                 const double bound = fabs(pp.jk[2]) * sw;
                 if (bound > 0.0) { js = FX_RANGE / bound; jq = bound / FX_RANGE; }
             }
-            stage_box<R, false>(g, f, bx, 1);
+            stage_box<GTI, R, false>(g, f, bx, 1);
             __syncthreads();
         }
-        for (int p = sg.start + threadIdx.x; p < end; p += GT) {
+        for (int p = sg.start + threadIdx.x; p < end; p += GTI) {
             const R w = ion.w[p];
             if (w == R(0)) continue;
             const double x = ion.x[p], y = ion.y[p], z0 = ion.z0[p];
@@ -974,10 +977,10 @@ __global__ void __launch_bounds__(GT) k3_gpi(G3 g, F3<R> f, I3<R> ion, const Seg
         }
         if (lds) {
             __syncthreads();
-            flush_box(g, f, bx, 2, 1, jq);
+            flush_box<GTI>(g, f, bx, 2, 1, jq);
         }
     }
-    block_box(nb, red, &bout[blockIdx.x]);
+    block_box<GTI>(nb, red, &bout[blockIdx.x]);
 }
 
 // laser antenna: per transverse cell a + particle fixed at the cell centre and a - particle
@@ -1639,7 +1642,7 @@ void launch3_gpi(const G3& g, const F3<R>& f, const I3<R>& ion, const Seg3* seg,
     if (nseg <= 0) return;
     const size_t lds = (size_t)BPL * pz * 8;
     (void)hipFuncSetAttribute((const void*)k3_gpi<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k3_gpi<R>), dim3(nseg), dim3(GT), lds, s, g, f, ion, seg, bin, bout, zsa, zsb, zsn, pp, pz);
+    hipLaunchKernelGGL((k3_gpi<R>), dim3(nseg), dim3(GTI), lds, s, g, f, ion, seg, bin, bout, zsa, zsb, zsn, pp, pz);
 }
 
 template <typename R>
