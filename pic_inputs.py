@@ -205,16 +205,16 @@ def make_config3(nx, ny, nz, dx_um, dy_um, dz_um, *, pml_cells=10, periodic_x=0,
 
 
 def c3(real="f32", nx=128, ny=128, nz=1024, ppc=8, preload=False, gamma=30.0):
-    """3D boosted frame gamma=30: 128x128x1024, 8 ppc (134M electrons when filled), lab
-    density 1e17 cm^-3 with a 20 um linear up-ramp starting 2 um ahead of the antenna, laser
-    a0=2 waist 50 um, CK2 solver, Friedman theta=0.1, 4 bilinear passes + compensation,
-    10-cell PML on every face, moving window, rigid ions, 5000 steps."""
-    d = boosted_cell(gamma)
+    """3D boosted frame gamma=30: 128x128x1024 cubic cells of (1+beta) gamma lambda / 16 (so
+    that the stretched pulse and the antenna's path fit the box), 8 ppc (134M electrons when
+    filled), lab density 1e17 cm^-3 with a 20 um linear up-ramp starting 2 um ahead of the
+    antenna, laser a0=2 waist 50 um 30 fs, CK2 solver, Friedman theta=0.1, 4 bilinear passes
+    + compensation, 10-cell PML on every face, moving window, rigid ions, 5000 steps."""
+    d = boosted_cell(gamma, frac=1.0 / 16.0)
     z_ant = gamma * 0.6 * nz * d
     start = -1e30 if preload else z_ant + 2.0
     ramp = 0.0 if preload else 20.0
-    # laser FWHM = half a plasma wavelength at 1e17 cm^-3 (lambda_p = 105.59 um)
-    fwhm = 0.5 * 105.59 / 0.299792458
+    fwhm = 30.0
     return dict(
         name=(f"3D boosted gamma={gamma:g} {nx}x{ny}x{nz}, {ppc} ppc, 1e17 cm^-3"
               f"{' (pre-loaded window)' if preload else ''}, a0=2, CK2 + Friedman 0.1,"
