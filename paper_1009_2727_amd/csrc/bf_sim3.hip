@@ -1291,11 +1291,14 @@ constexpr int ORD_THREADS = 512;
 constexpr int ORD_MAX_CELLS = 8192;   // keys of a tile ordered in LDS
 constexpr int ORD_TABLE = 8192;       // particles of a tile ordered in LDS (more keep the scatter order)
 
+constexpr int ORD_GROUPS = 1024;     // (plane, k) groups of a tile regrouped complete-first
+
 struct TileOrder {
     int cnt[ORD_MAX_CELLS], pos[ORD_MAX_CELLS];
     int tab[ORD_TABLE];               // per particle: key | level << 16
     int part[ORD_THREADS];
-    int kmax, lmin;
+    int gcnt[ORD_GROUPS], grank[ORD_GROUPS];
+    int kmax, lmin, grouped;
 };
 
 // lattice key of a particle id within a tile (origin o, width w), planes from lmin, lr planes
@@ -1313,6 +1316,38 @@ struct LatticeKey {
         return ((ll * ppc + k) * w1 + lj) * w0 + li;
     }
 };
+
+// A tile's z faces cut the first and last lattice planes at random in-cell offsets, so some
+// (plane, k) groups are incomplete; the complete groups go first (each then fills whole waves
+// from a wave boundary) and the incomplete ones last.  Returns the regrouped key of a particle.
+__device__ void regroup(TileOrder& ts, const LatticeKey& lk, const uint32_t* ids, int N)
+{
+    const int W = lk.w0 * lk.w1, G = lk.lr * lk.ppc;
+    if (G > ORD_GROUPS) {   // too many groups for the table: plain lattice order
+        if (threadIdx.x == 0) ts.grouped = 0;
+        __syncthreads();
+        return;
+    }
+    for (int q = threadIdx.x; q < G; q += ORD_THREADS) ts.gcnt[q] = 0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < N; q += ORD_THREADS) atomicAdd(&ts.gcnt[lk.of(ids[q]) / W], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int r = 0;
+        for (int q = 0; q < G; q++)
+            if (ts.gcnt[q] == W) ts.grank[q] = r++;
+        for (int q = 0; q < G; q++)
+            if (ts.gcnt[q] != W) ts.grank[q] = r++;
+        ts.grouped = 1;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int regrouped(const TileOrder& ts, const LatticeKey& lk, uint32_t id)
+{
+    const int W = lk.w0 * lk.w1, key = lk.of(id);
+    return ts.grouped ? ts.grank[key / W] * W + key % W : key;
+}
 
 // the lattice key of the tile's particles (ids ids[0..N)) for block t
 __device__ LatticeKey lattice_key(TileOrder& ts, const G3& g, const Tiles3& tl, int t, int ppc, const uint32_t* ids,
@@ -1435,8 +1470,9 @@ __global__ void __launch_bounds__(ORD_THREADS) k3_sort_order_e(G3 g, Tiles3 tl, 
     if (sg.count <= 0) return;
     const int o = sg.start;
     const LatticeKey lk = lattice_key(ts, g, tl, blockIdx.x, ppc, src.id + o, min(sg.count, ORD_TABLE));
+    regroup(ts, lk, src.id + o, min(sg.count, ORD_TABLE));
     order_tile3(
-        ts, lk.lr * lk.ppc * lk.w0 * lk.w1, sg.count, [&](int q) { return lk.of(src.id[o + q]); },
+        ts, lk.lr * lk.ppc * lk.w0 * lk.w1, sg.count, [&](int q) { return regrouped(ts, lk, src.id[o + q]); },
         [&](int q, int sl) {
             const int p = o + q, d = o + sl;
             dst.x[d] = src.x[p]; dst.y[d] = src.y[p]; dst.z[d] = src.z[p];
@@ -1454,8 +1490,9 @@ __global__ void __launch_bounds__(ORD_THREADS) k3_sort_order_i(G3 g, Tiles3 tl, 
     if (sg.count <= 0) return;
     const int o = sg.start;
     const LatticeKey lk = lattice_key(ts, g, tl, blockIdx.x, ppc, src.id + o, min(sg.count, ORD_TABLE));
+    regroup(ts, lk, src.id + o, min(sg.count, ORD_TABLE));
     order_tile3(
-        ts, lk.lr * lk.ppc * lk.w0 * lk.w1, sg.count, [&](int q) { return lk.of(src.id[o + q]); },
+        ts, lk.lr * lk.ppc * lk.w0 * lk.w1, sg.count, [&](int q) { return regrouped(ts, lk, src.id[o + q]); },
         [&](int q, int sl) {
             const int p = o + q, d = o + sl;
             dst.x[d] = src.x[p]; dst.y[d] = src.y[p]; dst.z0[d] = src.z0[p];
