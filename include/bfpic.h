@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define BF_ABI_VERSION 3u
+#define BF_ABI_VERSION 4u
 
 typedef enum {
     BF_OK = 0,
@@ -94,10 +94,14 @@ typedef struct {
 } bf_plasma;
 
 /* Laser given in the lab frame (Sec. 3.1.2): wavelength, normalised amplitude a0, 1/e
-   field waist, intensity FWHM duration, lab position of the emitting plane.  Linear
-   polarisation along x; the pulse peak crosses the plane 3 sigma_t after t = 0. */
+   field waist, intensity FWHM duration, lab position of the emitting plane, lab time at
+   which the pulse peak crosses the plane (0 selects 3 sigma_t, so nothing is emitted before
+   t = 0; negative is BF_EINVAL), and the linear polarisation: 0 along x, 1 along y (in 2D
+   the out-of-plane component, E_y, B_x, B_z and J_y).  Any other pol is BF_EINVAL. */
 typedef struct {
     double lambda_um, a0, waist_um, fwhm_fs, z_antenna_um;
+    double t_peak_fs;
+    int pol;
 } bf_laser;
 
 /* Lab-frame station: fields sampled on axis at the lab position z_lab_um, back-transformed
@@ -180,7 +184,9 @@ enum {
     BF_DIAG_ENERGY = 4,    /* 3 doubles: field energy E, field energy B, kinetic energy     */
     BF_DIAG_GAUSS = 5,     /* stored_z x stored_x doubles: div E - F[rho] on the nodes (2D) */
     BF_DIAG_INFO = 6,      /* bf_info                                                       */
-    BF_DIAG_ANTENNA = 7,   /* nx doubles (3D: nx x ny): x of the moving antenna particles   */
+    BF_DIAG_ANTENNA = 7,   /* nx doubles (3D: nx x ny): coordinate of each moving antenna
+                              particle along the polarisation, in cells (x; 3D y polarisation:
+                              y; 2D y polarisation: x, which then stays at the home position) */
     BF_DIAG_TIMERS = 8,    /* BF_PHASE_COUNT x 2 doubles: accumulated ms and launches per
                               phase since the last call (phase_timers = 1); arg != 0 resets */
     BF_DIAG_PARTICLE_BLOCK = 9 /* 3D only; arg = species + 2 b: the live particles of slots

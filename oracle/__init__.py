@@ -55,7 +55,8 @@ class _Plasma(C.Structure):
 
 class _Laser(C.Structure):
     _fields_ = [("lambda_um", C.c_double), ("a0", C.c_double), ("waist_um", C.c_double),
-                ("fwhm_fs", C.c_double), ("z_antenna_um", C.c_double)]
+                ("fwhm_fs", C.c_double), ("z_antenna_um", C.c_double), ("t_peak_fs", C.c_double),
+                ("pol", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -110,6 +111,7 @@ def lib():
         _lib.orc_shape3.restype = C.c_double
         _lib.orc_shape3.argtypes = [C.c_double]
         _lib.orc_boris.argtypes = [C.c_double, C.c_double, D, D, D]
+        _lib.orc_gather_at.argtypes = [P, C.c_double, C.c_double, D]
         _lib.orc_deposit_one.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_double,
                                          C.c_double, C.c_double, C.c_double]
         _lib.orc_splitmix64.restype = C.c_uint64
@@ -252,6 +254,12 @@ class Oracle:
         out = np.zeros((max(n, 0), 7))
         if n > 0:
             lib().orc_station_samples(self._h, q, _dp(out), n)
+        return out
+
+    def gather_at(self, x: float, z: float) -> np.ndarray:
+        """E^n and B^n at (x, z) (um) as the particle stage gathers them: Ex, Ey, Ez, Bx, By, Bz."""
+        out = np.zeros(6)
+        lib().orc_gather_at(self._h, x, z, _dp(out))
         return out
 
     def deposit_one(self, q, w, x0, z0, x1, z1, vy):

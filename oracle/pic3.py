@@ -75,6 +75,7 @@ def lib3():
         L.orc3_station_samples.restype = C.c_long
         L.orc3_station_samples.argtypes = [P, C.c_int, D, C.c_long]
         L.orc3_deposit_one.argtypes = [P, C.c_double, C.c_double, D, D]
+        L.orc3_gather_at.argtypes = [P, D, D]
         _ready = True
     return L
 
@@ -205,3 +206,10 @@ class Oracle3:
         a = np.ascontiguousarray(r0, dtype=np.float64)
         b = np.ascontiguousarray(r1, dtype=np.float64)
         lib3().orc3_deposit_one(self._h, q, w, _dp(a), _dp(b))
+
+    def gather_at(self, r) -> np.ndarray:
+        """E^n and B^n at r = (x, y, z) (um) as the particle stage gathers them."""
+        a = np.ascontiguousarray(r, dtype=np.float64)
+        out = np.zeros(6)
+        lib3().orc3_gather_at(self._h, _dp(a), _dp(out))
+        return out

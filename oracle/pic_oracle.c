@@ -69,7 +69,7 @@ struct orc_sim {
     long ni, capi;
     uint32_t* iid; double *ix, *iz0, *iw;
     /* antenna */
-    int na; double *ax_home, *ax_minus; double aw, az_lab, sig_t, t0, w0;
+    int na, pol; double *ax_home, *ax_minus; double aw, az_lab, sig_t, t0, w0;
     /* stations */
     int nst; station_t st[16];
 };
@@ -333,7 +333,7 @@ int orc_init_plasma(orc_sim* s, const orc_plasma* p)
 
 int orc_init_laser(orc_sim* s, const orc_laser* l)
 {
-    if (!s || !l || l->lambda_um <= 0) return -1;
+    if (!s || !l || l->lambda_um <= 0 || l->pol < 0 || l->pol > 1 || l->t_peak_fs < 0) return -1;
     s->laser = *l;
     s->have_laser = 1;
     s->lambda = l->lambda_um;
@@ -342,7 +342,8 @@ int orc_init_laser(orc_sim* s, const orc_laser* l)
     s->w0 = l->waist_um;
     /* intensity FWHM tau -> field envelope exp(-t^2/(2 sigma_t^2)), sigma_t = tau/(2 sqrt(ln 2)) */
     s->sig_t = l->fwhm_fs * 1e-15 * C_LIGHT * 1e6 / (2.0 * sqrt(log(2.0)));
-    s->t0 = 3.0 * s->sig_t;
+    s->t0 = l->t_peak_fs > 0.0 ? l->t_peak_fs * 1e-15 * C_LIGHT * 1e6 : 3.0 * s->sig_t;
+    s->pol = l->pol;
     s->az_lab = l->z_antenna_um;
     s->na = s->ax.N;
     free(s->ax_home); free(s->ax_minus);
@@ -558,6 +559,19 @@ static double gather(const orc_sim* s, const double* F, int hx, int hz, double x
     return sum;
 }
 
+void orc_gather_at(const orc_sim* s, double x, double z, double out[6])
+{
+    /* the gather of the particle stage at one position (um, interior-relative): E^n and
+       B^n = (B^{n-1/2} + B^{n+1/2}) / 2, each component from its own staggered location */
+    double xc = x / s->ax.d, zc = z / s->az.d;
+    out[0] = gather(s, s->f[ORC_EX], 1, 0, xc, zc);
+    out[1] = gather(s, s->f[ORC_EY], 0, 0, xc, zc);
+    out[2] = gather(s, s->f[ORC_EZ], 0, 1, xc, zc);
+    out[3] = 0.5 * (gather(s, s->f[ORC_BXO], 0, 1, xc, zc) + gather(s, s->f[ORC_BX], 0, 1, xc, zc));
+    out[4] = 0.5 * (gather(s, s->f[ORC_BYO], 1, 1, xc, zc) + gather(s, s->f[ORC_BY], 1, 1, xc, zc));
+    out[5] = 0.5 * (gather(s, s->f[ORC_BZO], 1, 0, xc, zc) + gather(s, s->f[ORC_BZ], 1, 0, xc, zc));
+}
+
 void orc_boris(double qm, double dt, const double E[3], const double B[3], double u[3])
 {
     double h = 0.5 * qm * dt;
@@ -700,7 +714,8 @@ void orc_stage_particles(orc_sim* s)
     }
 
     /* laser antenna: a + and a - sheet particle per transverse cell; the - particle moves
-       transversely with v_x = K dx / (q w), K = -2 E_perp the sheet current */
+       along the polarisation with v = K dx / (q w), K = -2 E_perp the sheet current.  Along
+       y (out of the plane) the motion only enters J_y, and x stays at the home position. */
     if (s->have_laser) {
         double t0 = s->t, t1 = (double)(s->step + 1) * dt;
         double za = antenna_z(s, t0), zb = antenna_z(s, t1);
@@ -708,11 +723,15 @@ void orc_stage_particles(orc_sim* s)
             double tm = t0 + 0.5 * dt;
             for (int i = 0; i < s->na; i++) {
                 double K = -2.0 * antenna_field(s, s->ax_home[i], tm);
-                double vx = K * dx / (-1.0 * s->aw);
-                double xa = s->ax_minus[i], xb = xa + vx * dt;
-                orc_deposit_one(s, -1.0, s->aw, xa, za, xb, zb, 0.0);
+                double v = K * dx / (-1.0 * s->aw);
+                if (s->pol == 0) {
+                    double xa = s->ax_minus[i], xb = xa + v * dt;
+                    orc_deposit_one(s, -1.0, s->aw, xa, za, xb, zb, 0.0);
+                    s->ax_minus[i] = xb;
+                } else {
+                    orc_deposit_one(s, -1.0, s->aw, s->ax_minus[i], za, s->ax_minus[i], zb, v);
+                }
                 orc_deposit_one(s, 1.0, s->aw, s->ax_home[i], za, s->ax_home[i], zb, 0.0);
-                s->ax_minus[i] = xb;
             }
         }
     }

@@ -48,6 +48,9 @@ typedef struct {
 typedef struct {
     double lambda_um, a0, waist_um, fwhm_fs;
     double z_antenna_um;      /* lab-frame position of the emitting plane                */
+    double t_peak_fs;         /* lab time at which the pulse peak crosses the plane;
+                                 0 selects 3 sigma_t (nothing emitted before t = 0)      */
+    int pol;                  /* linear polarisation: 0 along x, 1 along y               */
 } orc_laser;
 
 /* field component ids */
@@ -99,7 +102,8 @@ int  orc_set_electrons(orc_sim* s, long n, const uint32_t* id, const double* x, 
                        const double* ux, const double* uy, const double* uz, const double* w);
 int  orc_set_ions(orc_sim* s, long n, const uint32_t* id, const double* x, const double* z0,
                   const double* w);
-/* antenna state: transverse positions of the moving (negative) sheet particles */
+/* antenna state: x of the moving (negative) sheet particles (they stay at their home x
+   when the polarisation is along y) */
 int  orc_get_antenna(const orc_sim* s, double* xminus);
 int  orc_set_antenna(orc_sim* s, const double* xminus);
 /* scalar state: step, time, window shift count, next lattice row */
@@ -114,6 +118,9 @@ int  orc_charge_density(const orc_sim* s, double* out);
 long orc_station_samples(const orc_sim* s, int station, double* out /* 7 per sample */, long cap);
 
 /* one-particle helpers for pins */
+/* E^n and B^n gathered at (x, z) (um, interior-relative) exactly as the particle stage does:
+   out = Ex, Ey, Ez, Bx, By, Bz */
+void orc_gather_at(const orc_sim* s, double x, double z, double out[6]);
 double orc_shape3(double r);
 void orc_boris(double q_over_m, double dt, const double E[3], const double B[3], double u[3]);
 /* Esirkepov deposit of one particle into a zeroed J (logical layout), for pins */

@@ -80,8 +80,9 @@ struct orc3_sim {
     uint32_t* iid;
     double *ix, *iy, *iz0, *iw;
     long na;
-    double *ah_x, *ah_y, *am_x;
+    double *ah_x, *ah_y, *am;           /* home x, y; moving particle's coordinate along pol */
     double aw, az_lab, sig_t, t0, w0;
+    int pol;
     int nst;
     st3_t st[16];
 };
@@ -186,7 +187,7 @@ void orc3_destroy(orc3_sim* s)
     free(s->eid); free(s->ex); free(s->ey); free(s->ez); free(s->eux); free(s->euy); free(s->euz);
     free(s->ew);
     free(s->iid); free(s->ix); free(s->iy); free(s->iz0); free(s->iw);
-    free(s->ah_x); free(s->ah_y); free(s->am_x);
+    free(s->ah_x); free(s->ah_y); free(s->am);
     for (int i = 0; i < s->nst; i++) free(s->st[i].rec);
     free(s);
 }
@@ -277,7 +278,7 @@ int orc3_init_plasma(orc3_sim* s, const orc_plasma* p)
 
 int orc3_init_laser(orc3_sim* s, const orc_laser* l)
 {
-    if (!s || !l || l->lambda_um <= 0) return -1;
+    if (!s || !l || l->lambda_um <= 0 || l->pol < 0 || l->pol > 1 || l->t_peak_fs < 0) return -1;
     s->laser = *l;
     s->have_laser = 1;
     s->lambda = l->lambda_um;
@@ -285,17 +286,19 @@ int orc3_init_laser(orc3_sim* s, const orc_laser* l)
     s->e0 = l->a0 * s->omega;
     s->w0 = l->waist_um;
     s->sig_t = l->fwhm_fs * 1e-15 * C_LIGHT * 1e6 / (2.0 * sqrt(log(2.0)));
-    s->t0 = 3.0 * s->sig_t;
+    s->t0 = l->t_peak_fs > 0.0 ? l->t_peak_fs * 1e-15 * C_LIGHT * 1e6 : 3.0 * s->sig_t;
+    s->pol = l->pol;
     s->az_lab = l->z_antenna_um;
     s->na = (long)s->a[0].N * s->a[1].N;
-    free(s->ah_x); free(s->ah_y); free(s->am_x);
+    free(s->ah_x); free(s->ah_y); free(s->am);
     s->ah_x = (double*)malloc(s->na * sizeof(double));
     s->ah_y = (double*)malloc(s->na * sizeof(double));
-    s->am_x = (double*)malloc(s->na * sizeof(double));
+    s->am = (double*)malloc(s->na * sizeof(double));
     for (long q = 0; q < s->na; q++) {
         long i = q % s->a[0].N, j = q / s->a[0].N;
-        s->ah_x[q] = s->am_x[q] = ((double)i + 0.5) * s->a[0].d;
+        s->ah_x[q] = ((double)i + 0.5) * s->a[0].d;
         s->ah_y[q] = ((double)j + 0.5) * s->a[1].d;
+        s->am[q] = s->pol == 0 ? s->ah_x[q] : s->ah_y[q];
     }
     /* sheet current K = -2 E_perp per unit area; the moving sheet stays below 0.01 c */
     s->aw = (2.0 * s->e0 / s->gamma) * s->a[0].d * s->a[1].d / 0.01;
@@ -548,6 +551,16 @@ static double antenna_field(const orc3_sim* s, double x, double y, double t)
     return (s->e0 / s->gamma) * f * sin(s->omega * tau);
 }
 
+void orc3_gather_at(const orc3_sim* s, const double r[3], double out[6])
+{
+    /* the gather of the particle stage at one position (um, interior-relative) */
+    double rc[3] = {r[0] / s->a[0].d, r[1] / s->a[1].d, r[2] / s->a[2].d};
+    for (int c = 0; c < 3; c++) {
+        out[c] = gather3(s, s->f[O3_EX + c], STAG_E[c], rc);
+        out[3 + c] = 0.5 * (gather3(s, s->f[O3_BXO + c], STAG_B[c], rc) + gather3(s, s->f[O3_BX + c], STAG_B[c], rc));
+    }
+}
+
 void orc3_stage_particles(orc3_sim* s)
 {
     const double dt = s->dt;
@@ -605,13 +618,15 @@ void orc3_stage_particles(orc3_sim* s)
             double tm = t0 + 0.5 * dt;
             for (long q = 0; q < s->na; q++) {
                 double K = -2.0 * antenna_field(s, s->ah_x[q], s->ah_y[q], tm);
-                double vx = K * s->a[0].d * s->a[1].d / (-1.0 * s->aw);
-                double xa = s->am_x[q], xb = xa + vx * dt;
-                double m0[3] = {xa, s->ah_y[q], za}, m1[3] = {xb, s->ah_y[q], zb};
+                double v = K * s->a[0].d * s->a[1].d / (-1.0 * s->aw);   /* along pol */
+                double ma = s->am[q], mb = ma + v * dt;
+                double m0[3] = {s->ah_x[q], s->ah_y[q], za}, m1[3] = {s->ah_x[q], s->ah_y[q], zb};
+                m0[s->pol] = ma;
+                m1[s->pol] = mb;
                 double h0[3] = {s->ah_x[q], s->ah_y[q], za}, h1[3] = {s->ah_x[q], s->ah_y[q], zb};
                 orc3_deposit_one(s, -1.0, s->aw, m0, m1);
                 orc3_deposit_one(s, 1.0, s->aw, h0, h1);
-                s->am_x[q] = xb;
+                s->am[q] = mb;
             }
         }
     }
@@ -869,14 +884,14 @@ int orc3_set_ions(orc3_sim* s, long n, const uint32_t* id, const double* x, cons
 int orc3_get_antenna(const orc3_sim* s, double* xm)
 {
     if (!s->have_laser) return -1;
-    memcpy(xm, s->am_x, s->na * sizeof(double));
+    memcpy(xm, s->am, s->na * sizeof(double));
     return (int)s->na;
 }
 
 int orc3_set_antenna(orc3_sim* s, const double* xm)
 {
     if (!s->have_laser) return -1;
-    memcpy(s->am_x, xm, s->na * sizeof(double));
+    memcpy(s->am, xm, s->na * sizeof(double));
     return (int)s->na;
 }
 
@@ -939,7 +954,8 @@ int orc3_charge_density(const orc3_sim* s_, double* rho)
         double za = antenna_z(s, s->t);
         if (za >= 0.0 && za < s->a[2].N * s->a[2].d)
             for (long q = 0; q < s->na; q++) {
-                double m[3] = {s->am_x[q], s->ah_y[q], za}, h[3] = {s->ah_x[q], s->ah_y[q], za};
+                double m[3] = {s->ah_x[q], s->ah_y[q], za}, h[3] = {s->ah_x[q], s->ah_y[q], za};
+                m[s->pol] = s->am[q];
                 deposit_rho(s, rho, -1.0, s->aw, m);
                 deposit_rho(s, rho, 1.0, s->aw, h);
             }

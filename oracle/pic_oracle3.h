@@ -75,7 +75,9 @@ int  orc3_set_electrons(orc3_sim* s, long n, const uint32_t* id, const double* x
                         const double* w);
 int  orc3_set_ions(orc3_sim* s, long n, const uint32_t* id, const double* x, const double* y,
                    const double* z0, const double* w);
-int  orc3_get_antenna(const orc3_sim* s, double* xminus);   /* nx * ny values, x fastest */
+/* antenna state: coordinate of each moving (negative) sheet particle along the polarisation
+   (x, or y for y polarisation), nx * ny values, x fastest */
+int  orc3_get_antenna(const orc3_sim* s, double* xminus);
 int  orc3_set_antenna(orc3_sim* s, const double* xminus);
 int  orc3_set_clock(orc3_sim* s, long step, double time, long shift, long next_row);
 
@@ -83,6 +85,9 @@ void orc3_energy(const orc3_sim* s, double out[3]);
 int  orc3_charge_density(const orc3_sim* s, double* out);
 int  orc3_gauss_residual(const orc3_sim* s, double* out);
 long orc3_station_samples(const orc3_sim* s, int station, double* out, long cap);
+
+/* E^n and B^n gathered at r (um, interior-relative) as the particle stage does, for pins */
+void orc3_gather_at(const orc3_sim* s, const double r[3], double out[6]);
 
 /* Esirkepov deposit of one particle into J (um, interior-relative), for pins */
 void orc3_deposit_one(orc3_sim* s, double q, double w, const double r0[3], const double r1[3]);

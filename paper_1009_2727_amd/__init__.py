@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbfpic.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 FIELDS = ["Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "Exo", "Eyo", "Ezo",
           "Exb", "Eyb", "Ezb", "Byx", "Eyx", "Bxo", "Byo", "Bzo", "Jxr", "Jyr", "Jzr",
           "Exs", "Eys", "Ezs", "Bxs", "Bys", "Bzs"]
@@ -57,7 +57,8 @@ class bf_plasma(C.Structure):
 
 class bf_laser(C.Structure):
     _fields_ = [("lambda_um", C.c_double), ("a0", C.c_double), ("waist_um", C.c_double),
-                ("fwhm_fs", C.c_double), ("z_antenna_um", C.c_double)]
+                ("fwhm_fs", C.c_double), ("z_antenna_um", C.c_double), ("t_peak_fs", C.c_double),
+                ("pol", C.c_int)]
 
 
 class bf_station(C.Structure):

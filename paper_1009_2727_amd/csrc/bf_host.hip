@@ -205,6 +205,7 @@ struct bf_sim {
     Geo g;
     double dt = 0, dt_crit = 0, beta = 0, gamma = 1, a2 = 1, b2 = 0, theta = 0, vw = 0;
     double n0 = 0, omega = 0, e0 = 0, w0 = 0, sig_t = 0, t0 = 0, za_lab = 0, aw = 0;
+    int pol = 0;                  // laser polarisation: 0 x, 1 y
     bf_plasma plasma{};
     int have_plasma = 0, have_laser = 0, have_lf = 0;
     int e_cur = 0, b_cur = 0, eb_cur = 0, p_cur = 0, bb_cur = 0, sg_cur = 0;
@@ -682,6 +683,7 @@ bf_status step_impl(bf_sim* s, int nsteps)
             ap.sig_t = s->sig_t; ap.t0 = s->t0; ap.dx_um = c.dx_um; ap.xc_um = 0.5 * c.nx * c.dx_um;
             ap.weight = s->aw; ap.dt = s->dt; ap.dx = c.dx_um; ap.dz = c.dz_um;
             ap.active = (ap.za >= 0.0 && ap.za < (double)c.nz) ? 1 : 0;
+            ap.pol = s->pol;
             double* xm = s->w<double>(L.w_ant);
             s->run([=](hipStream_t st) { launch_antenna<R>(g, f, xm, ap, st); });
         }
@@ -1169,6 +1171,7 @@ bf_status step3(bf_sim* s, int nsteps)
                 a.sig_t = s->sig_t;
                 a.omega = s->omega;
                 a.aw = s->aw;
+                a.pol = s->pol;
                 double* ant = w3<double>(s, L.w_ant);
                 const size_t na = (size_t)L.na;
                 bf3::launch3_antenna<R>(g, f, ant, ant + na, ant + 2 * na, a, pp, s->stream);
@@ -1218,8 +1221,9 @@ bf_status init_laser3(bf_sim* s)
     s->aw = (2.0 * s->e0 / s->gamma) * s->cfg.dx_um * s->cfg.dy_um / 0.01;
     std::vector<double> a(3 * (size_t)L.na);
     for (int q = 0; q < L.na; q++) {
-        a[q] = a[L.na + q] = (q % L.g.N[0]) + 0.5;
-        a[2 * (size_t)L.na + q] = (q / L.g.N[0]) + 0.5;
+        a[L.na + q] = (q % L.g.N[0]) + 0.5;                 // home x
+        a[2 * (size_t)L.na + q] = (q / L.g.N[0]) + 0.5;     // home y
+        a[q] = a[(size_t)(1 + s->pol) * L.na + q];           // moving coordinate along pol
     }
     return hip_check(s, hipMemcpy(w3<double>(s, L.w_ant), a.data(), a.size() * 8, hipMemcpyHostToDevice),
                      "3D init_laser");
@@ -1600,12 +1604,15 @@ bf_status bf_init_laser(bf_sim* s, const bf_laser* l)
     bf_status st = guard(s);
     if (st != BF_OK) return st;
     if (!l || l->lambda_um <= 0 || l->waist_um <= 0 || l->fwhm_fs <= 0) return fail(s, BF_EINVAL, "bad laser");
+    if (l->pol < 0 || l->pol > 1) return fail(s, BF_EINVAL, "laser polarisation must be 0 (x) or 1 (y)");
+    if (!(l->t_peak_fs >= 0)) return fail(s, BF_EINVAL, "negative laser peak time");
     s->have_laser = 1;
     s->omega = 2.0 * PI / l->lambda_um;
     s->e0 = l->a0 * s->omega;                              // a0 = e E0 / (m c omega)
     s->w0 = l->waist_um;
     s->sig_t = l->fwhm_fs * 1e-15 * C_LIGHT * 1e6 / (2.0 * std::sqrt(std::log(2.0)));
-    s->t0 = 3.0 * s->sig_t;
+    s->t0 = l->t_peak_fs > 0 ? l->t_peak_fs * 1e-15 * C_LIGHT * 1e6 : 3.0 * s->sig_t;
+    s->pol = l->pol;
     s->za_lab = l->z_antenna_um;
     if (s->d3) {
         update_window_speed(s);

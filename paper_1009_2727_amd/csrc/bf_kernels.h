@@ -94,6 +94,7 @@ struct AntennaParams {
     double weight;     // |q| w of each sheet particle
     double dt, dx, dz; // um
     int active;
+    int pol;           // 0: the - sheet moves along x (J_x); 1: along y, out of the plane (J_y)
 };
 
 struct StationParams {

@@ -95,6 +95,7 @@ struct Antenna3 {
     double tm;          // time of the emitted field
     double e0g, w0, xc, yc, gamma, t0, sig_t, omega;
     double aw;          // macro-weight of each sheet particle
+    int pol;            // axis the - sheet particle moves along: 0 x, 1 y
 };
 
 // status bits (same meaning as the 2D path)

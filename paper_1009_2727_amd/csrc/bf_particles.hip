@@ -653,12 +653,13 @@ __global__ void __launch_bounds__(NTHR) k_ions_batch(const IonDesc<R>* __restric
 
 // ---- antenna (FP64) ------------------------------------------------------------------------
 
-// Esirkepov current of one particle moving (x0, z0) -> (x1, z1) (cells, |move| < 1 cell),
-// charge factor qw, at cell (cx, cz) of the grid: J_x on (cx + 1/2, cz), J_z on (cx, cz + 1/2)
-// (2-1/2D weights as in esirkepov(); v_y = 0).  FP64 throughout.
+// Esirkepov current of one particle moving (x0, z0) -> (x1, z1) (cells, |move| < 1 cell) with
+// out-of-plane velocity vy, charge factor qw, at cell (cx, cz) of the grid: J_x on (cx + 1/2, cz),
+// J_z on (cx, cz + 1/2), J_y on the node (cx, cz) (2-1/2D weights as in esirkepov()).  FP64
+// throughout.
 __device__ __forceinline__ void esirkepov_cell(double x0, double z0, double x1, double z1, double qw,
-                                               double dx, double dz, double dt, int cx, int cz,
-                                               double& jx, double& jz)
+                                               double vy, double dx, double dz, double dt, int cx, int cz,
+                                               double& jx, double& jy, double& jz)
 {
     const int ix = (int)floor(x0), iz = (int)floor(z0), ix1 = (int)floor(x1), iz1 = (int)floor(z1);
     if (abs(ix1 - ix) > 1 || abs(iz1 - iz) > 1) return;   // one step moves less than a cell
@@ -680,11 +681,19 @@ __device__ __forceinline__ void esirkepov_cell(double x0, double z0, double x1, 
         for (int k = 0; k <= b; k++) pd += S1z[k] - S0z[k];
         jz += -qw / (dx * dt) * pd * 0.5 * (S0x[m] + S1x[m]);
     }
+    if (vy != 0.0) {
+        // W_y: time average of S_x S_z along the straight move
+        const double dsx = S1x[m] - S0x[m], dsz = S1z[b] - S0z[b];
+        const double wy = S0x[m] * S0z[b] + 0.5 * dsx * S0z[b] + 0.5 * S0x[m] * dsz + dsx * dsz / 3.0;
+        jy += qw * vy * wy / (dx * dz);
+    }
 }
 
 // One wave per sheet pair, one lane per cell of the pair's 6 x 6 patch: the + particle stays at
-// its home x and moves with the plane, the - particle also moves transversely so that the pair
-// carries the sheet current K = -2 E_perp (Sec. 3.1.2); both deposit by Esirkepov in FP64.
+// its home x and moves with the plane, the - particle also moves along the polarisation so that
+// the pair carries the sheet current K = -2 E_perp (Sec. 3.1.2): along x it moves in the plane
+// (J_x), along y it keeps its home x and its velocity enters J_y.  Both deposit by Esirkepov in
+// FP64.
 template <typename R>
 __global__ void __launch_bounds__(64) k_antenna(Geo g, FieldSet<R> f, double* xm, AntennaParams ap)
 {
@@ -700,19 +709,22 @@ __global__ void __launch_bounds__(64) k_antenna(Geo g, FieldSet<R> f, double* xm
                        exp(-tau * tau / (2.0 * ap.sig_t * ap.sig_t));
     const double Ep = (ap.e0 / ap.gamma) * env * sin(ap.omega * tau);
     const double K = -2.0 * Ep;
-    const double vx = K * ap.dx / (-ap.weight);   // moving sheet has charge -w
-    const double xa = xm[i], xb = xa + vx * ap.dt / ap.dx;
+    const double v = K * ap.dx / (-ap.weight);    // moving sheet has charge -w
+    const double xa = xm[i];
+    const double xb = ap.pol == 0 ? xa + v * ap.dt / ap.dx : xa;
+    const double vy = ap.pol == 0 ? 0.0 : v;
     const int px = (int)floor(xh) - 2;
     const int pz = (int)floor(fmin(ap.za, ap.zb)) - 1;
     if (lane < 36) {
         const int cx = px + lane % 6, cz = pz + lane / 6;
-        double jx = 0.0, jz = 0.0;
-        esirkepov_cell(xa, ap.za, xb, ap.zb, -ap.weight, ap.dx, ap.dz, ap.dt, cx, cz, jx, jz);
-        esirkepov_cell(xh, ap.za, xh, ap.zb, ap.weight, ap.dx, ap.dz, ap.dt, cx, cz, jx, jz);
+        double jx = 0.0, jy = 0.0, jz = 0.0;
+        esirkepov_cell(xa, ap.za, xb, ap.zb, -ap.weight, vy, ap.dx, ap.dz, ap.dt, cx, cz, jx, jy, jz);
+        esirkepov_cell(xh, ap.za, xh, ap.zb, ap.weight, 0.0, ap.dx, ap.dz, ap.dt, cx, cz, jx, jy, jz);
         const int si = swrap(cx + g.Px, g.Sx, g.perx), sk = swrap(cz + g.Pz, g.Sz, g.perz);
         if (si >= 0 && sk >= 0) {
             const long o = gofs(g, si, sk);
             if (jx != 0.0) atomicAdd(&f.J[0][o], (R)jx);
+            if (jy != 0.0) atomicAdd(&f.J[1][o], (R)jy);
             if (jz != 0.0) atomicAdd(&f.J[2][o], (R)jz);
         }
     }

@@ -984,7 +984,8 @@ __global__ void __launch_bounds__(GTI) k3_gpi(G3 g, F3<R> f, I3<R> ion, const Se
 }
 
 // laser antenna: per transverse cell a + particle fixed at the cell centre and a - particle
-// moving along x with the sheet current K = -2 E_perp (FP64 throughout)
+// moving along the polarisation (x or y) with the sheet current K = -2 E_perp (FP64
+// throughout); xm holds the moving particle's coordinate along the polarisation
 template <typename R>
 __global__ void __launch_bounds__(64) k3_antenna(G3 g, F3<R> f, double* xm, const double* xh, const double* yh,
                                                  Antenna3 a, Push3 pp)
@@ -996,9 +997,11 @@ __global__ void __launch_bounds__(64) k3_antenna(G3 g, F3<R> f, double* xm, cons
     const double r2 = (xu - a.xc) * (xu - a.xc) + (yu - a.yc) * (yu - a.yc);
     const double E = a.e0g * exp(-r2 / (a.w0 * a.w0)) * exp(-tau * tau / (2.0 * a.sig_t * a.sig_t)) * sin(a.omega * tau);
     const double K = -2.0 * E;
-    const double vx = K * g.d[0] * g.d[1] / (-1.0 * a.aw);   // um per unit time
-    const double x0 = xm[q], x1 = x0 + vx * pp.dt / g.d[0];
-    const double m0[3] = {x0, yh[q], a.za}, m1[3] = {x1, yh[q], a.zb};
+    const double v = K * g.d[0] * g.d[1] / (-1.0 * a.aw);    // um per unit time, along pol
+    const double x0 = xm[q], x1 = x0 + v * pp.dt / g.d[a.pol];
+    double m0[3] = {xh[q], yh[q], a.za}, m1[3] = {xh[q], yh[q], a.zb};
+    m0[a.pol] = x0;
+    m1[a.pol] = x1;
     const double km[3] = {pp.jk[0] * a.aw, pp.jk[1] * a.aw, pp.jk[2] * a.aw};   // q = -1
     esirkepov3(g, f.J, m0, m1, km);
     const double h0[3] = {xh[q], yh[q], a.za}, h1[3] = {xh[q], yh[q], a.zb};

@@ -55,9 +55,11 @@ def plasma(n0_cm3, ppc, *, ramp_um=0.0, start_um=0.0, ion_mode=0):
                 ppc=int(ppc), ion_mode=int(ion_mode))
 
 
-def laser(a0, waist_um, fwhm_fs, z_antenna_um, lambda_um=LAMBDA_UM):
+def laser(a0, waist_um, fwhm_fs, z_antenna_um, lambda_um=LAMBDA_UM, t_peak_fs=0.0, pol=0):
+    """pol: 0 along x, 1 along y; t_peak_fs: lab time the peak crosses the plane (0: 3 sigma_t)."""
     return dict(lambda_um=float(lambda_um), a0=float(a0), waist_um=float(waist_um),
-                fwhm_fs=float(fwhm_fs), z_antenna_um=float(z_antenna_um))
+                fwhm_fs=float(fwhm_fs), z_antenna_um=float(z_antenna_um), t_peak_fs=float(t_peak_fs),
+                pol=int(pol))
 
 
 # ---------------------------------------------------------------------------------------

@@ -336,3 +336,32 @@ def test_antenna3_plane_wave_amplitude():
         o.step(1)
         samples.append(o.field("Ex")[P + 480, 0, 0])
     assert np.abs(samples).max() == pytest.approx(E0 / ((1 + beta) * gamma), rel=0.02)
+
+
+# ---------------------------------------------------------------------------------------
+# every component, E and B^n alike, at its own Yee stagger (Sec. 5.1): linear fields written
+# at each component's stored positions come back exactly (a half-cell stagger error shows as
+# half a gradient step)
+# ---------------------------------------------------------------------------------------
+
+def test_gather3_each_component_at_its_own_stagger():
+    n, P = (9, 8, 10), 3
+    o = Oracle3(pi.make_config3(*n, *D3, pml_cells=P))           # non-periodic: no wrap
+    nz, ny, nx = o.shape
+    r = np.random.default_rng(4)
+    coef = {name: r.standard_normal(4) for name in ("Ex", "Ey", "Ez", "Bx", "By", "Bz")}
+    for name, c in coef.items():
+        h = STAG[name]
+        Z, Y, X = np.meshgrid((np.arange(nz) - P + 0.5 * h[2]) * D3[2], (np.arange(ny) - P + 0.5 * h[1]) * D3[1],
+                              (np.arange(nx) - P + 0.5 * h[0]) * D3[0], indexing="ij")
+        f = c[0] + c[1] * X + c[2] * Y + c[3] * Z
+        o.set_field(name, f)
+        if name[0] == "B":
+            o.set_field(name + "o", f - 0.5)
+    for _ in range(100):
+        p = np.array([(2.0 + r.random() * (n[k] - 4.0)) * D3[k] for k in range(3)])
+        got = o.gather_at(p)
+        for q, name in enumerate(("Ex", "Ey", "Ez", "Bx", "By", "Bz")):
+            c = coef[name]
+            want = c[0] + c[1] * p[0] + c[2] * p[1] + c[3] * p[2] - (0.25 if name[0] == "B" else 0.0)
+            assert got[q] == pytest.approx(want, abs=1e-12), (name, p)

@@ -437,28 +437,35 @@ def test_station_back_transform_invariants():
     assert s[1, 0] == pytest.approx(gamma * (0 + beta * 10.0), rel=1e-14)  # t_lab = gamma (t' + beta z')
 
 
-@pytest.mark.parametrize("gamma", [1.0, 5.0])
-def test_antenna_emission_amplitude_and_frequency(gamma):
-    # emitted boosted-frame amplitude E0/((1+beta) gamma) and frequency omega/((1+beta) gamma)
-    # (Sec. 3.1.2).  The lab-fixed plane drifts backwards at beta c, so the antenna starts
-    # near the front and the (short) pulse is emitted before it leaves the box.
-    beta = math.sqrt(1 - 1 / gamma ** 2)
-    lam = 0.8
+def _antenna_probe(gamma, pol, t_peak_fs=0.0, steps=700):
     d = pi.boosted_cell(gamma, 1.0 / 32.0)
     nz, P = 700, 10
     cfg = pi.make_config(4, nz, d, d, periodic_x=1, pml_cells=P, gamma_boost=gamma,
                          ck="ck", cfl_fraction=0.98)
     o = Oracle(cfg)
     a_cell = 600 if gamma > 1 else 300
-    o.init_laser(pi.laser(0.05, 1e7, 10.0, gamma * a_cell * d))
-    E0 = 0.05 * 2 * np.pi / lam
+    o.init_laser(pi.laser(0.05, 1e7, 10.0, gamma * a_cell * d, t_peak_fs=t_peak_fs, pol=pol))
     probe = 680 if gamma > 1 else 400
-    samples, times = [], []
-    for n in range(700):
+    samples, other, times = [], [], []
+    for n in range(steps):
         o.step(1)
-        samples.append(o.field("Ex")[P + probe, 0])
+        samples.append(o.field("Ey" if pol else "Ex")[P + probe, 0])
+        other.append(o.field("Ex" if pol else "Ey")[P + probe, 0])
         times.append(o.info()["time"])
-    s = np.array(samples)
+    return np.array(samples), np.array(other), np.array(times)
+
+
+@pytest.mark.parametrize("gamma,pol", [(1.0, 0), (5.0, 0), (5.0, 1)])
+def test_antenna_emission_amplitude_and_frequency(gamma, pol):
+    # emitted boosted-frame amplitude E0/((1+beta) gamma) and frequency omega/((1+beta) gamma)
+    # (Sec. 3.1.2), for either linear polarisation (pol 1: the out-of-plane E_y).  The
+    # lab-fixed plane drifts backwards at beta c, so the antenna starts near the front and
+    # the (short) pulse is emitted before it leaves the box.
+    beta = math.sqrt(1 - 1 / gamma ** 2)
+    lam = 0.8
+    E0 = 0.05 * 2 * np.pi / lam
+    s, other, times = _antenna_probe(gamma, pol)
+    assert np.abs(other).max() == 0.0                  # nothing in the other polarisation
     amp = np.abs(s).max()
     assert amp == pytest.approx(E0 / ((1 + beta) * gamma), rel=0.02)
     ipk = np.argmax(np.abs(s))
@@ -469,6 +476,22 @@ def test_antenna_emission_amplitude_and_frequency(gamma):
     period = 2 * (t[zc[-1]] - t[zc[0]]) / (len(zc) - 1)
     omega = 2 * np.pi / lam
     assert 2 * np.pi / period == pytest.approx(omega / ((1 + beta) * gamma), rel=0.02)
+
+
+def test_antenna_peak_time_is_lab_time_at_the_plane():
+    # the peak crosses the lab-fixed plane at lab time t_peak; at the plane lab time is
+    # t'/gamma (Sec. 3.1.2 reading), so moving the peak by dT delays the boosted-frame signal
+    # at a fixed probe by gamma dT (the plane drifts at -beta c: the probe ahead of it sees
+    # the emission a further beta gamma dT later, gamma (1 + beta) dT in all)
+    gamma = 5.0
+    beta = math.sqrt(1 - 1 / gamma ** 2)
+    sig_t = 10.0 / (2 * math.sqrt(math.log(2)))          # fs
+    cent = []
+    for tp in (3 * sig_t, 4.5 * sig_t):
+        s, _, t = _antenna_probe(gamma, 1, t_peak_fs=tp, steps=760)
+        cent.append((t * s ** 2).sum() / (s ** 2).sum())
+    dT = 1.5 * sig_t * 0.299792458                       # um / c
+    assert cent[1] - cent[0] == pytest.approx(gamma * (1 + beta) * dT, rel=0.02)
 
 
 # ---------------------------------------------------------------------------------------
@@ -596,3 +619,207 @@ def test_linear_wake_amplitude_and_wavelength():
     wn = 2 / dt * math.asin(dt / dz * math.sin(k0 * dz / 2))
     vg = math.cos(k0 * dz / 2) / math.cos(wn * dt / 2) * math.sqrt(1 - kp ** 2 / k0 ** 2)
     assert best[1] == pytest.approx(kp / vg, rel=0.005)
+
+
+# ---------------------------------------------------------------------------------------
+# Gather at each component's own staggered location (Sec. 5.1: fields gathered directly
+# from the Yee mesh locations).  A field linear in x and z, written at each component's
+# stored positions, must come back exactly at any particle position: cubic B-splines
+# reproduce polynomials of degree one, so a half-cell error in any component's stagger
+# (which partition of unity alone cannot see) shows as 0.5 * gradient * cell.
+# ---------------------------------------------------------------------------------------
+
+STAG2 = {"Ex": (1, 0), "Ey": (0, 0), "Ez": (0, 1), "Bx": (0, 1), "By": (1, 1), "Bz": (1, 0)}
+
+
+def test_gather_each_component_at_its_own_stagger():
+    nx, nz, dx, dz, P = 14, 12, 0.1, 0.13, 4
+    o = Oracle(pi.make_config(nx, nz, dx, dz, pml_cells=P))     # non-periodic: no wrap
+    Sz, Sx = o.shape
+    coef = {"Ex": (0.3, 0.7, -1.1), "Ey": (-0.2, 1.3, 0.4), "Ez": (0.9, -0.6, 0.25),
+            "Bx": (0.15, 0.5, 0.8), "By": (-0.7, -0.35, 1.9), "Bz": (0.05, 2.1, -0.45)}
+    for name, (a, bx, bz) in coef.items():
+        hx, hz = STAG2[name]
+        X = (np.arange(Sx) - P + 0.5 * hx) * dx       # um, interior-relative
+        Z = (np.arange(Sz) - P + 0.5 * hz) * dz
+        f = a + bx * X[None, :] + bz * Z[:, None]
+        o.set_field(name, f)
+        if name[0] == "B":                            # B^n is the mean of B^{n-1/2} and B^{n+1/2}
+            o.set_field(name + "o", f + 0.25)
+    r = np.random.default_rng(21)
+    for _ in range(200):
+        x = (2.0 + r.random() * (nx - 4.0)) * dx      # stencils stay inside the stored arrays
+        z = (2.0 + r.random() * (nz - 4.0)) * dz
+        got = o.gather_at(x, z)
+        for c, name in enumerate(("Ex", "Ey", "Ez", "Bx", "By", "Bz")):
+            a, bx, bz = coef[name]
+            want = a + bx * x + bz * z + (0.125 if name[0] == "B" else 0.0)
+            assert got[c] == pytest.approx(want, abs=1e-13), (name, x, z)
+
+
+def test_gather_linear_electric_field_through_the_push():
+    # the same through the particle stage: with B = 0 one Boris step changes u by q E dt
+    # exactly (Sec. 4 Boris reading), so u^{n+1/2} = -dt E(x^n) for a particle at rest
+    nx, nz, dx, dz, P = 12, 16, 0.1, 0.1, 4
+    o = Oracle(pi.make_config(nx, nz, dx, dz, pml_cells=P))
+    Sz, Sx = o.shape
+    dt = o.info()["dt"]
+    grads = {"Ex": (0.4, -0.3), "Ey": (-0.8, 0.6), "Ez": (0.25, 0.9)}
+    for name, (gx, gz) in grads.items():
+        hx, hz = STAG2[name]
+        X = (np.arange(Sx) - P + 0.5 * hx) * dx
+        Z = (np.arange(Sz) - P + 0.5 * hz) * dz
+        o.set_field(name, 1.0 + gx * X[None, :] + gz * Z[:, None])
+    p = pi.random_electrons(60, nx, nz, dx, dz, seed=8, umax=0.0, margin=3.0)
+    o.set_electrons(p)
+    o.stage("particles")
+    q = o.particles()
+    order = np.argsort(q["id"])
+    for name, u in (("Ex", "ux"), ("Ey", "uy"), ("Ez", "uz")):
+        gx, gz = grads[name]
+        want = -dt * (1.0 + gx * p["x"] + gz * p["z"])
+        np.testing.assert_allclose(q[u][order], want, rtol=1e-12, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------------------
+# S7: continuous injection at the front plane (Sec. 2 window speed, Sec. 3.1.1 background
+# plasma created at the front).  The plasma is fixed in the lab and streams through the
+# window at -(beta + beta_w*) c, so a flat plasma brings in the charge n* (beta + beta_w*)
+# c dt A_perp per step with n* = gamma n_lab (length contraction).  Whole rows are created,
+# so over T steps the count is exact up to the two rounding steps (at most two rows).
+# ---------------------------------------------------------------------------------------
+
+def test_injected_charge_per_step():
+    w = pi.c2(real="f64", nx=4, nz=32, ppc=2, preload=True)
+    o = Oracle.from_workload(w)
+    i0 = o.info()
+    g = w["config"]["gamma_boost"]
+    beta = math.sqrt(1.0 - 1.0 / g ** 2)
+    d = w["config"]["dz_um"]
+    Lx = w["config"]["nx"] * w["config"]["dx_um"]
+    nstar = g * i0["n0_norm"]
+    q0 = o.particles()["w"].sum()
+    row0 = i0["next_row"]
+    T = 1500
+    for _ in range(T):
+        o.stage("advance")          # time, window and injection only: no particle moves
+    i1 = o.info()
+    rows = i1["next_row"] - row0
+    flow = (beta + i1["v_window"]) * T * i1["dt"] / d          # rows that streamed in
+    assert abs(rows - flow) < 2.0
+    # exact row count of the creation rule: row l exists once (l + 1) - beta t / dz - shift <= N_z
+    t = i1["time"]
+    assert i1["next_row"] == math.floor(w["config"]["nz"] + beta * t / d + i1["shift"])
+    q1 = o.particles()["w"].sum()
+    per_row = nstar * Lx * d                                     # charge of one flat row
+    assert (q1 - q0) == pytest.approx(rows * per_row, rel=1e-12)
+    assert (q1 - q0) / (T * i1["dt"]) == pytest.approx(nstar * (beta + i1["v_window"]) * Lx,
+                                                       rel=2.0 / flow)
+    # every injected electron has its paired ion: the flow is neutral
+    ions = o.particles(1)
+    assert len(ions["id"]) == o.num_particles(0)
+    assert ions["w"].sum() == pytest.approx(q1, rel=1e-13)
+
+
+def test_ramp_weights_follow_the_boosted_density():
+    # R21: lab profile zero up to start, linear over the ramp, then flat; in the boosted frame
+    # n*(z', t') = gamma n_lab(gamma (z' + beta c t')).  Each macro-electron carries that
+    # density at its own lab position (row by row through the ramp), and the number of
+    # electrons in a lab interval is frame-invariant: the ramp holds n0 * ramp / 2 * L_x.
+    # The ramp starts 4 cells beyond the front plane, so every ramp row is created by the
+    # injection at the front while the plasma streams in (no laser: the window moves at c).
+    g, nx, nz, ppc = 13.0, 16, 48, 16
+    w = pi.c2(real="f64", nx=nx, nz=nz, ppc=ppc, gamma=g)
+    cfg = w["config"]
+    ramp = 150.0
+    start = g * (nz + 4) * cfg["dz_um"]
+    w["plasma"]["ramp_um"] = ramp
+    w["plasma"]["start_um"] = start
+    o = Oracle.from_workload(w, laser=False)
+    assert o.num_particles() == 0
+    beta = math.sqrt(1.0 - 1.0 / g ** 2)
+    o.step(30)                     # neutral pairs drifting at -beta c: no field develops
+    info = o.info()
+    n0 = info["n0_norm"]
+    p = o.particles()
+    zb = p["z"] + beta * info["time"] + info["shift"] * cfg["dz_um"]   # boosted position at t' = 0
+    zlab = g * zb
+    dens = p["w"] * ppc / (cfg["dx_um"] * cfg["dz_um"]) / g           # lab density carried
+    prof = n0 * np.clip((zlab - start) / ramp, 0.0, 1.0)
+    np.testing.assert_allclose(dens, prof, rtol=1e-12, atol=1e-12 * n0)
+    inramp = (zlab > start) & (zlab < start + ramp)
+    rows = np.unique((p["id"] // (nx * ppc))[inramp])
+    assert len(rows) > 10                             # the ramp spans many lattice rows
+    # rows wholly inside the ramp: their charge is the lab line density integrated (invariance)
+    lab_row = g * cfg["dz_um"]                        # lab length of one lattice row
+    full = [r for r in rows if start < g * r * cfg["dz_um"] and g * (r + 1) * cfg["dz_um"] < start + ramp]
+    sel = np.isin(p["id"] // (nx * ppc), full)
+    zl0 = g * np.array(full, float) * cfg["dz_um"]
+    want = (n0 * ((zl0 + 0.5 * lab_row - start) / ramp) * lab_row).sum() * nx * cfg["dx_um"]
+    assert p["w"][sel].sum() == pytest.approx(want, rel=0.01)     # Monte Carlo positions in cells
+
+
+# ---------------------------------------------------------------------------------------
+# T9, Appendix I: the 1D system (Eqs. 1db-1de) at c dt = dx driven by a current switched on
+# at one node.  A 2D CK run with fields uniform across x is exactly that system (the CK
+# operator's transverse shifts sum to the plain difference, and CK's 2D limit is dt = dx on
+# square cells), so the oracle must reproduce the recurrence to round-off.  Unfiltered, the
+# step source leaves an odd-even (Nyquist) oscillation behind; with the Nyquist-modulated
+# source it grows linearly; one bilinear pass of the source (gain 0 at the Nyquist
+# wavenumber) removes both.
+# ---------------------------------------------------------------------------------------
+
+def _app1_run(npass, nyq, steps=10, nz=64, k0=32):
+    d = 0.1
+    o = Oracle(pi.make_config(4, nz, d, d, periodic_x=1, periodic_z=1, pml_cells=0, ck="ck",
+                              cfl_fraction=1.0, filter_npass=npass))
+    Sz, Sx = o.shape
+    dt = o.info()["dt"]
+    hist = []
+    for n in range(steps):
+        o.stage("faraday")
+        src = np.zeros((Sz, Sx))
+        src[k0, :] = 1.0 * ((-1.0) ** n if nyq else 1.0)    # J_x on the half-x, node-z row k0
+        o.set_field("Jx", src)
+        o.stage("filter")
+        o.stage("ampere")
+        o.stage("advance")
+        hist.append(o.field("Ex")[:, 0].copy())
+    return o, dt, d, np.array(hist)
+
+
+def _app1_recurrence(dt, d, steps, nz, k0, nyq, npass):
+    # Eqs. 1db-1de written for (E_x, B_y) along z: B at half nodes, E at nodes, periodic
+    src = np.zeros(nz)
+    src[k0] = 1.0
+    for _ in range(npass):                               # the 1-2-1 pass of Sec. 4.1
+        src = 0.5 * src + 0.25 * (np.roll(src, 1) + np.roll(src, -1))
+    E = np.zeros(nz)
+    B = np.zeros(nz)                                     # B[k] at k + 1/2
+    out = []
+    for n in range(steps):
+        B = B - dt / d * (np.roll(E, -1) - E)          # dB_y/dt = -dE_x/dz
+        s = src * ((-1.0) ** n if nyq else 1.0)
+        E = E - dt / d * (B - np.roll(B, 1)) - dt * s  # dE_x/dt = -dB_y/dz - J_x
+        out.append(E.copy())
+    return np.array(out)
+
+
+@pytest.mark.parametrize("nyq", [False, True])
+def test_app1_odd_even_response_and_bilinear_cure(nyq):
+    nz, k0, steps = 64, 32, 10
+    o, dt, d, hist = _app1_run(0, nyq, steps, nz, k0)
+    assert dt == pytest.approx(d, rel=1e-14)            # c dt = dz: the case of Appendix I
+    ref = _app1_recurrence(dt, d, steps, nz, k0, nyq, 0)
+    np.testing.assert_allclose(hist, ref, rtol=0, atol=1e-13)
+    # Nyquist content at the source, N(E) = sum (-1)^k E_k over the cells the fronts left behind
+    sgn = (-1.0) ** np.arange(nz)
+    near = slice(k0 - 3, k0 + 4)
+    nyq_amp = np.array([abs((h * sgn)[near].sum()) for h in hist])
+    assert nyq_amp[-1] > 0.4 * dt                      # the spurious odd-even mode is there
+    if nyq:
+        # driven at its own frequency it grows linearly with time
+        assert nyq_amp[-1] > 1.5 * nyq_amp[4]
+    _, _, _, filt = _app1_run(1, nyq, steps, nz, k0)
+    np.testing.assert_allclose(filt, _app1_recurrence(dt, d, steps, nz, k0, nyq, 1), rtol=0, atol=1e-13)
+    assert max(abs((h * sgn).sum()) for h in filt) < 1e-13   # one 1-2-1 pass: no Nyquist content
