@@ -327,6 +327,14 @@ bf_status bf_lf_train_step(void* work, int64_t work_bytes, float* params, float*
                            float beta1, float beta2, float eps, int64_t step, float* grad_out,
                            double* loss_out, void* hip_stream);
 
+/* Host-side: the learned-filter parameters (n = BF_LF_PARAMS floats into host_params) that
+   reproduce the n-pass bilinear filter with or without the compensation pass alpha_c = n/2 + 1
+   of Sec. 4.1 (Eq. 3ptfilter) exactly: along each axis the composed stencil is cut into three
+   factors of at most five taps, one per layer, each layer carrying the outer product of its
+   factor with itself in channel 0.  BF_EINVAL: null pointer, wrong n, npass < 0, or more passes
+   than three 5-tap layers hold (npass <= 6 without compensation, <= 5 with it). */
+bf_status bf_lf_bilinear_params(int npass, int compensate, float* host_params, int64_t n);
+
 #ifdef __cplusplus
 }
 #endif

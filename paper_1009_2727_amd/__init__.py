@@ -99,6 +99,7 @@ EXPORTS = ["bf_query_buffers", "bf_create", "bf_init_plasma", "bf_init_laser", "
            "bf_load_electrons", "bf_load_electrons3", "bf_step", "bf_diagnose", "bf_set_field", "bf_sync_status",
            "bf_get_state", "bf_set_state", "bf_status_string", "bf_last_error", "bf_destroy",
            "bf_set_learned_filter", "bf_lf_work_bytes", "bf_lf_apply", "bf_lf_train_step",
+           "bf_lf_bilinear_params",
            "bf_batch_work_bytes", "bf_batch_create", "bf_batch_step", "bf_batch_destroy"]
 FILTER_BILINEAR, FILTER_LEARNED = 0, 1
 LF_PARAMS = 7200
@@ -145,6 +146,7 @@ def lib(path: str = LIB_PATH):
     L.bf_lf_train_step.argtypes = [P, C.c_int64, P, P, P, P, P, C.c_int, C.c_int, C.c_int, C.c_int,
                                    C.c_int, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float,
                                    C.c_int64, P, P, P]
+    L.bf_lf_bilinear_params.argtypes = [C.c_int, C.c_int, F, C.c_int64]
     L.bf_batch_work_bytes.argtypes = [C.c_int]
     L.bf_batch_work_bytes.restype = C.c_int64
     L.bf_batch_create.argtypes = [C.POINTER(P), C.c_int, P, C.c_int64, P, C.POINTER(P)]
@@ -397,32 +399,11 @@ class Sim:
 
 
 def bilinear_factor_params(npass: int = 4, compensate: bool = True) -> np.ndarray:
-    """Learned-filter parameters that reproduce the n-pass bilinear filter (+ compensation
-    with alpha_c = n/2 + 1) of Sec. 4.1 exactly: per axis the 1D stencil
-    ((1 + z)/2)^(2n) (compensation) is cut into three factors of at most 5 taps, and each
-    layer carries the outer product of its factor with itself in channel 0."""
-    room = [4, 4, 2 if compensate else 4]
-    left = 2 * npass
-    stencils = []
-    for r in room:
-        k = min(r, left)
-        left -= k
-        s = np.array([1.0])
-        for _ in range(k):
-            s = np.convolve(s, [0.5, 0.5])
-        stencils.append(s)
-    if left:
-        raise ValueError("at most 5 bilinear passes (4 with compensation) fit three 5-tap layers")
-    if compensate:
-        a = 0.5 * npass + 1.0
-        stencils[2] = np.convolve(stencils[2], [0.5 * (1.0 - a), a, 0.5 * (1.0 - a)])
+    """Learned-filter parameters equal to the n-pass bilinear filter (+ compensation) of
+    Sec. 4.1, from the library (bf_lf_bilinear_params)."""
     out = np.zeros(LF_PARAMS, np.float32)
-    sizes = [(0, 1, 16), (400, 16, 16), (6800, 16, 1)]     # (offset, c_in, c_out) per layer
-    for (off, cin, cout), s in zip(sizes, stencils):
-        s5 = np.zeros(5)
-        s5[(5 - s.size) // 2:(5 - s.size) // 2 + s.size] = s
-        taps = np.outer(s5, s5).ravel()                      # t = 5 (dy + 2) + (dx + 2)
-        out[off + np.arange(25) * cin * cout] = taps         # (t, ci = 0, co = 0)
+    _ck(lib().bf_lf_bilinear_params(int(npass), 1 if compensate else 0,
+                                    out.ctypes.data_as(C.POINTER(C.c_float)), LF_PARAMS))
     return out
 
 

@@ -526,7 +526,9 @@ void backward(const View& in, const View& h1, const View& h2, const View& out, c
 // C ABI: standalone learned filter (batched inference and training on device images)
 // ======================================================================================
 
+#include <algorithm>
 #include <cmath>
+#include <vector>
 #include "../../include/bfpic.h"
 
 namespace {
@@ -589,9 +591,59 @@ bool dims_ok(int nimg, int ny, int nx)
     return nimg > 0 && ny > 0 && nx > 0 && nimg <= 65535 && (long)nimg * ny * nx <= (1L << 31) / C;
 }
 
+// exact learned-filter form of the n-pass bilinear filter + compensation (Sec. 4.1): per axis
+// the composed 1D stencil ((1 + z) / 2)^(2n) (times the compensation pass) is cut into three
+// factors of at most five taps; each layer carries the outer product of its factor with itself
+// in channel 0
+bool bilinear_params(int npass, int comp, float* out)
+{
+    const int room[3] = {4, 4, comp ? 2 : 4};
+    int left = 2 * npass;
+    std::vector<double> st[3];
+    for (int l = 0; l < 3; l++) {
+        const int k = std::min(room[l], left);
+        left -= k;
+        std::vector<double> f{1.0};
+        for (int r = 0; r < k; r++) {                   // convolve with (1/2, 1/2)
+            std::vector<double> g(f.size() + 1, 0.0);
+            for (size_t i = 0; i < f.size(); i++) {
+                g[i] += 0.5 * f[i];
+                g[i + 1] += 0.5 * f[i];
+            }
+            f.swap(g);
+        }
+        st[l] = f;
+    }
+    if (left > 0) return false;
+    if (comp) {                                         // (1 - a)/2, a, (1 - a)/2 with a = n/2 + 1
+        const double a = 0.5 * npass + 1.0;
+        const double c3[3] = {0.5 * (1.0 - a), a, 0.5 * (1.0 - a)};
+        std::vector<double> g(st[2].size() + 2, 0.0);
+        for (size_t i = 0; i < st[2].size(); i++)
+            for (int j = 0; j < 3; j++) g[i + j] += st[2][i] * c3[j];
+        st[2].swap(g);
+    }
+    for (int i = 0; i < NPARAM; i++) out[i] = 0.f;
+    const int off[3] = {OFF_W1, OFF_W2, OFF_W3}, cc[3] = {C, C * C, C};   // (t, ci, co) strides
+    for (int l = 0; l < 3; l++) {
+        double s5[5] = {0, 0, 0, 0, 0};
+        const int n = (int)st[l].size(), o = (5 - n) / 2;
+        for (int i = 0; i < n; i++) s5[o + i] = st[l][i];
+        for (int a = 0; a < 5; a++)
+            for (int b = 0; b < 5; b++) out[off[l] + (5 * a + b) * cc[l]] = (float)(s5[a] * s5[b]);
+    }
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
+
+bf_status bf_lf_bilinear_params(int npass, int compensate, float* host_params, int64_t n)
+{
+    if (!host_params || n != NPARAM || npass < 0) return BF_EINVAL;
+    return bilinear_params(npass, compensate ? 1 : 0, host_params) ? BF_OK : BF_EINVAL;
+}
 
 int64_t bf_lf_work_bytes(int nimg, int ny, int nx)
 {

@@ -71,7 +71,7 @@ def test_3d_initial_plasma_bitwise():
 @pytest.mark.parametrize("real,tol,xtol", [("f64", 1e-10, 1e-9), ("f32", 1e-5, 1e-5)])
 def test_3d_boosted_matches_oracle(real, tol, xtol):
     # C3-shaped: boosted gamma = 30, window, PML on every face, CK2 + Friedman, 4 + comp filter,
-    # rigid ions, antenna; ragged against nothing (one thread per cell / particle)
+    # rigid ions, antenna, on a grid smaller than one particle tile
     w = pi.small_boosted3(real=real, nx=10, ny=8, nz=40, ppc=2)
     sim, ref = _sim(w, sort_every=7), Oracle3.from_workload(w)
     sim.step(24)
