@@ -45,7 +45,7 @@ class _Cfg(C.Structure):
                 ("ck_alpha", C.c_double), ("ck_beta", C.c_double), ("ck_gamma", C.c_double),
                 ("theta", C.c_double), ("cfl_fraction", C.c_double), ("filter_npass", C.c_int),
                 ("filter_compensate", C.c_int), ("gamma_boost", C.c_double),
-                ("moving_window", C.c_int), ("seed", C.c_uint64)]
+                ("moving_window", C.c_int), ("seed", C.c_uint64), ("filter_strides", C.c_int)]
 
 
 class _Plasma(C.Structure):
@@ -132,7 +132,7 @@ class Oracle:
 
     def __init__(self, config: dict):
         L = lib()
-        c = _Cfg(**{k: config[k] for k, _ in _Cfg._fields_})
+        c = _Cfg(**{k: config.get(k, 1) if k == "filter_strides" else config[k] for k, _ in _Cfg._fields_})
         self._h = L.orc_create(C.byref(c))
         if not self._h:
             raise ValueError("oracle rejected the configuration")

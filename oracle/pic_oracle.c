@@ -741,36 +741,41 @@ void orc_stage_particles(orc_sim* s)
 /* filter (Sec. 4.1)                                                   */
 /* ------------------------------------------------------------------ */
 
-static void filter_pass_x(orc_sim* s, double* F, int hx, double alpha, double* tmp)
+/* one pass of Eq. 3ptfilter_stride along x: phi_i <- alpha phi_i + (1-alpha)(phi_{i-st} +
+   phi_{i+st})/2 over the component's stored range; neighbours beyond it read 0 */
+static void filter_pass_x(orc_sim* s, double* F, int hx, double alpha, int st, double* tmp)
 {
     const long n = (long)s->ax.S * s->az.S;
     memcpy(tmp, F, n * sizeof(double));
     long ihi = hi_b(&s->ax, hx);
     for (long k = 0; k < s->az.S; k++)
         for (long i = 0; i <= ihi; i++) {
-            long l = snb(&s->ax, i, -1), r = snb(&s->ax, i, 1);
+            long l = snb(&s->ax, i, -st), r = snb(&s->ax, i, st);
             double vl = (l < 0 || l > ihi) ? 0.0 : tmp[ID(s, l, k)];
             double vr = (r < 0 || r > ihi) ? 0.0 : tmp[ID(s, r, k)];
             F[ID(s, i, k)] = alpha * tmp[ID(s, i, k)] + (1.0 - alpha) * 0.5 * (vl + vr);
         }
 }
 
-static void filter_pass_z(orc_sim* s, double* F, int hz, double alpha, double* tmp)
+static void filter_pass_z(orc_sim* s, double* F, int hz, double alpha, int st, double* tmp)
 {
     const long n = (long)s->ax.S * s->az.S;
     memcpy(tmp, F, n * sizeof(double));
     long khi = hi_b(&s->az, hz);
     for (long k = 0; k <= khi; k++)
         for (long i = 0; i < s->ax.S; i++) {
-            long l = snb(&s->az, k, -1), r = snb(&s->az, k, 1);
+            long l = snb(&s->az, k, -st), r = snb(&s->az, k, st);
             double vl = (l < 0 || l > khi) ? 0.0 : tmp[ID(s, i, l)];
             double vr = (r < 0 || r > khi) ? 0.0 : tmp[ID(s, i, r)];
             F[ID(s, i, k)] = alpha * tmp[ID(s, i, k)] + (1.0 - alpha) * 0.5 * (vl + vr);
         }
 }
 
-/* n passes with alpha = 1/2 then, if asked, one compensation pass alpha_c = n/2 + 1, along x
-   then along z (the 1D filter applied per axis) */
+/* n passes with alpha = 1/2 then, if asked, one compensation pass alpha_c = n/2 + 1, for each
+   stride of the mask in ascending order (the wideband S(1:2), S(1:2:3), ... filters of Sec.
+   4.1), along x then along z (the 1D filter applied per axis) */
+static int stride_mask(const orc_sim* s) { return s->cfg.filter_strides ? s->cfg.filter_strides : 1; }
+
 static void filter_array(orc_sim* s, double* F, int hx, int hz)
 {
     int np = s->cfg.filter_npass;
@@ -778,10 +783,17 @@ static void filter_array(orc_sim* s, double* F, int hx, int hz)
     const long n = (long)s->ax.S * s->az.S;
     double* tmp = (double*)malloc(n * sizeof(double));
     double ac = 0.5 * np + 1.0;
-    for (int p = 0; p < np; p++) filter_pass_x(s, F, hx, 0.5, tmp);
-    if (s->cfg.filter_compensate) filter_pass_x(s, F, hx, ac, tmp);
-    for (int p = 0; p < np; p++) filter_pass_z(s, F, hz, 0.5, tmp);
-    if (s->cfg.filter_compensate) filter_pass_z(s, F, hz, ac, tmp);
+    const int mask = stride_mask(s);
+    for (int st = 1; st <= 16; st++) {
+        if (!(mask & (1 << (st - 1)))) continue;
+        for (int p = 0; p < np; p++) filter_pass_x(s, F, hx, 0.5, st, tmp);
+        if (s->cfg.filter_compensate) filter_pass_x(s, F, hx, ac, st, tmp);
+    }
+    for (int st = 1; st <= 16; st++) {
+        if (!(mask & (1 << (st - 1)))) continue;
+        for (int p = 0; p < np; p++) filter_pass_z(s, F, hz, 0.5, st, tmp);
+        if (s->cfg.filter_compensate) filter_pass_z(s, F, hz, ac, st, tmp);
+    }
     free(tmp);
 }
 

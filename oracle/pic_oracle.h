@@ -35,6 +35,9 @@ typedef struct {
     double gamma_boost;       /* Lorentz factor of the calculation frame                 */
     int moving_window;        /* 1: window follows the wake at beta_w* c                 */
     uint64_t seed;
+    int filter_strides;       /* bit s-1 set: the n passes (+ compensation) are applied
+                                 with stride s (Eq. 3ptfilter_stride), strides ascending;
+                                 0 is the same as 1 (stride 1 only)                        */
 } orc_config;
 
 typedef struct {

@@ -638,7 +638,7 @@ void orc3_stage_particles(orc3_sim* s)
 
 /* one 3-point pass along axis ax over the stored range of a component with stagger h there;
    values beyond the range read 0 */
-static void filter_pass(orc3_sim* s, double* F, int ax, int h, double alpha, double* tmp)
+static void filter_pass(orc3_sim* s, double* F, int ax, int h, double alpha, int st, double* tmp)
 {
     memcpy(tmp, F, s->ncell * sizeof(double));
     const long hi = b_hi(&s->a[ax], h);
@@ -648,7 +648,7 @@ static void filter_pass(orc3_sim* s, double* F, int ax, int h, double alpha, dou
             for (q[0] = 0; q[0] < s->a[0].S; q[0]++) {
                 if (q[ax] > hi) continue;
                 long p[3] = {q[0], q[1], q[2]};
-                long l = snb(&s->a[ax], q[ax], -1), r = snb(&s->a[ax], q[ax], 1);
+                long l = snb(&s->a[ax], q[ax], -st), r = snb(&s->a[ax], q[ax], st);
                 double vl = 0.0, vr = 0.0;
                 if (l >= 0 && l <= hi) { p[ax] = l; vl = tmp[IDq(s, p)]; }
                 if (r >= 0 && r <= hi) { p[ax] = r; vr = tmp[IDq(s, p)]; }
@@ -662,10 +662,15 @@ static void filter_array(orc3_sim* s, double* F, const int h[3])
     if (np <= 0) return;
     double* tmp = (double*)malloc(s->ncell * sizeof(double));
     double ac = 0.5 * np + 1.0;
-    for (int ax = 0; ax < 3; ax++) {
-        for (int p = 0; p < np; p++) filter_pass(s, F, ax, h[ax], 0.5, tmp);
-        if (s->cfg.filter_compensate) filter_pass(s, F, ax, h[ax], ac, tmp);
-    }
+    const int mask = s->cfg.filter_strides ? s->cfg.filter_strides : 1;
+    /* per axis, for each stride of the mask in ascending order: n passes + compensation of
+       Eq. 3ptfilter_stride */
+    for (int ax = 0; ax < 3; ax++)
+        for (int st = 1; st <= 16; st++) {
+            if (!(mask & (1 << (st - 1)))) continue;
+            for (int p = 0; p < np; p++) filter_pass(s, F, ax, h[ax], 0.5, st, tmp);
+            if (s->cfg.filter_compensate) filter_pass(s, F, ax, h[ax], ac, st, tmp);
+        }
     free(tmp);
 }
 

@@ -189,6 +189,32 @@ def test_filter3_gain(npass, comp):
                                        atol=1e-13)
 
 
+@pytest.mark.parametrize("mask,strides", [(0b11, (1, 2)), (0b1011, (1, 2, 4))])
+def test_filter3_stride_gain(mask, strides):
+    # the wideband S(1:2) and S(1:2:4) filters (Eq. 3ptfilter_stride): per axis the product of
+    # g(s, 1/2, k)^4 g(s, 3, k) over the strides
+    n = (16, 12, 24)
+
+    def gain(kd):
+        G = 1.0
+        for s in strides:
+            G = G * (0.5 + 0.5 * np.cos(s * kd)) ** 4 * (3.0 - 2.0 * np.cos(s * kd))
+        return G
+
+    for m in [(1, 0, 0), (2, 3, 5), (4, 6, 6), (8, 0, 12)]:
+        o = _box(*n, filter_npass=4, filter_compensate=1, filter_strides=mask)
+        k = [2 * math.pi * m[i] / n[i] for i in range(3)]
+        for name in ("Jx", "Jy", "Jz"):
+            X, Y, Z = _positions(o, STAG[name])
+            o.set_field(name, np.cos(k[0] * X + k[1] * Y + k[2] * Z))
+        o.stage("filter")
+        G = gain(k[0]) * gain(k[1]) * gain(k[2])
+        for name in ("Jx", "Jy", "Jz"):
+            X, Y, Z = _positions(o, STAG[name])
+            np.testing.assert_allclose(o.field(name), G * np.cos(k[0] * X + k[1] * Y + k[2] * Z),
+                                       atol=1e-13)
+
+
 # ---------------------------------------------------------------------------------------
 # Gauss's law held over the whole loop (charge-conserving deposit + linear filter that
 # commutes with the divergence), with laser antenna, moving window and injection

@@ -823,3 +823,101 @@ def test_app1_odd_even_response_and_bilinear_cure(nyq):
     _, _, _, filt = _app1_run(1, nyq, steps, nz, k0)
     np.testing.assert_allclose(filt, _app1_recurrence(dt, d, steps, nz, k0, nyq, 1), rtol=0, atol=1e-13)
     assert max(abs((h * sgn).sum()) for h in filt) < 1e-13   # one 1-2-1 pass: no Nyquist content
+
+
+# ---------------------------------------------------------------------------------------
+# Wideband filters with stride (Sec. 4.1, Eq. 3ptfilter_stride): the gain of one pass is
+# g(s, alpha, k) = alpha + (1 - alpha) cos(s k dx); the S(1:2), S(1:2:3), S(1:2:4) filters are
+# 4 passes + compensation at each stride, so their gain is the product over strides.  Poles of
+# the bilinear pass at stride s sit where s k dx = arccos(alpha/(alpha-1)) = pi (mod 2 pi).
+# Their fall-off matches the 20-, 50- and 80-pass bilinear filters (Sec. 4.1, last paragraph).
+# ---------------------------------------------------------------------------------------
+
+STRIDE_SETS = {"S(1:2)": (0b11, (1, 2)), "S(1:2:3)": (0b111, (1, 2, 3)), "S(1:2:4)": (0b1011, (1, 2, 4))}
+
+
+def _stride_gain(kd, strides, n=4, comp=1):
+    G = 1.0
+    for s in strides:
+        g = lambda a: a + (1 - a) * np.cos(s * kd)  # noqa: E731  Eq. 3ptfilter_stride gain
+        G = G * g(0.5) ** n * (g(n / 2.0 + 1.0) if comp else 1.0)
+    return G
+
+
+@pytest.mark.parametrize("name", list(STRIDE_SETS))
+@pytest.mark.parametrize("comp_name,hx,hz", [("Jx", 1, 0), ("Jz", 0, 1)])
+def test_stride_filter_gain(name, comp_name, hx, hz):
+    mask, strides = STRIDE_SETS[name]
+    nx, nz = 96, 48
+    o = _periodic_box(nx, nz, filter_npass=4, filter_compensate=1, filter_strides=mask)
+    for mx, mz in [(1, 0), (5, 3), (12, 6), (24, 0), (0, 12), (7, 11), (48, 24)]:
+        kx, kz = 2 * np.pi * mx / nx, 2 * np.pi * mz / nz
+        X = np.arange(nx)[None, :] + 0.5 * hx
+        Z = np.arange(nz)[:, None] + 0.5 * hz
+        f0 = np.cos(kx * X + kz * Z + 0.3)
+        o.set_field(comp_name, f0)
+        o.stage("filter")
+        G = _stride_gain(kx, strides) * _stride_gain(kz, strides)
+        np.testing.assert_allclose(o.field(comp_name), G * f0, atol=1e-13)
+
+
+@pytest.mark.parametrize("s", [2, 3, 4])
+def test_stride_filter_poles(s):
+    # one stride, bilinear passes only: zero gain at k dx = pi (2m + 1) / s
+    nx = 96
+    o = _periodic_box(nx, 4, filter_npass=1, filter_compensate=0, filter_strides=1 << (s - 1))
+    X = np.arange(nx)[None, :] + np.zeros((4, 1))
+    for m in range(s):
+        kd = np.pi * (2 * m + 1) / s
+        if (kd * nx / (2 * np.pi)) % 1:
+            continue
+        o.set_field("Jy", np.cos(kd * X + 0.2))
+        o.stage("filter")
+        assert np.abs(o.field("Jy")).max() < 1e-13, (s, m)
+    # and a mode between the poles passes with gain (1 + cos(s k dx))/2
+    kd = 2 * np.pi * 5 / nx
+    o.set_field("Jy", np.cos(kd * X))
+    o.stage("filter")
+    assert o.field("Jy")[0, 0] == pytest.approx(0.5 * (1 + np.cos(s * kd)), abs=1e-14)
+
+
+def _measured_half_gain(o, nx):
+    X = np.arange(nx)[None, :] + np.zeros((4, 1))
+    gains = []
+    for m in range(1, nx // 2 + 1):
+        o.set_field("Jy", np.cos(2 * np.pi * m / nx * X))
+        o.stage("filter")
+        gains.append(o.field("Jy")[0, 0])
+    m = int(np.argmax(np.array(gains) < 0.5)) + 1       # first mode below one half
+    g0, g1 = gains[m - 2], gains[m - 1]
+    return 2 * np.pi / nx * (m - 1 + (g0 - 0.5) / (g0 - g1))
+
+
+@pytest.mark.parametrize("npass,name", [(20, "S(1:2)"), (50, "S(1:2:3)"), (80, "S(1:2:4)")])
+def test_stride_filters_match_many_pass_bilinear_falloff(npass, name):
+    nx = 384
+    mask, strides = STRIDE_SETS[name]
+    wide = _periodic_box(nx, 4, filter_npass=4, filter_compensate=1, filter_strides=mask)
+    many = _periodic_box(nx, 4, filter_npass=npass, filter_compensate=1)
+    kw, km = _measured_half_gain(wide, nx), _measured_half_gain(many, nx)
+    assert kw == pytest.approx(km, rel=0.05)
+    # operation count: 5 three-point passes per stride against npass + 1 (Sec. 4.1: 10, 15, 15
+    # against 21, 51, 81)
+    assert 5 * len(strides) == {20: 10, 50: 15, 80: 15}[npass]
+
+
+def test_gauss_invariant_with_stride_filter():
+    # the strided filter is linear and shift-invariant, so filtering J and rho alike keeps the
+    # Gauss residual constant (Sec. 4.2.2) away from the non-periodic ends
+    w = pi.small_lab(nx=24, nz=96, ppc=2, npass=4, comp=1, ck="ck2", theta=0.1)
+    w["config"]["filter_strides"] = 0b1011                  # S(1:2:4)
+    o = Oracle.from_workload(w)
+    g0 = o.gauss_residual()
+    rho0 = np.abs(o.charge_density()).max()
+    o.step(40)
+    g1 = o.gauss_residual()
+    P, R = 10, 35 + 4
+    inner = slice(P + R, P + 96 - R)
+    aw = o.info()["antenna_weight"] / (0.05 * 0.05)
+    assert np.abs(g1 - g0)[inner].max() < 1e-13 * max(aw, rho0)
+    assert np.abs(o.field("Ez")).max() > 1e-6
