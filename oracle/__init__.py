@@ -33,7 +33,7 @@ def build(force: bool = False) -> str:
     newest = max(os.path.getmtime(f) for f in srcs)
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp,
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-o", tmp,
                                *[f for f in srcs if f.endswith(".c")], "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -114,6 +114,8 @@ def lib():
         _lib.orc_gather_at.argtypes = [P, C.c_double, C.c_double, D]
         _lib.orc_deposit_one.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_double,
                                          C.c_double, C.c_double, C.c_double]
+        _lib.orc_set_threads.argtypes = [C.c_int]
+        _lib.orc_threads.restype = C.c_int
         _lib.orc_splitmix64.restype = C.c_uint64
         _lib.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
     return _lib
@@ -288,3 +290,17 @@ def cfl_3d(a, b, g, dx, dy, dz, theta=0.0):
 
 def splitmix64(seed, k):
     return lib().orc_splitmix64(seed, k)
+
+
+def set_threads(n: int) -> None:
+    """Host threads of the oracle's particle stages (2D and 3D); 1 unless set."""
+    lib().orc_set_threads(int(n))
+
+
+def host_threads(cap: int = 16) -> int:
+    """The threads a large oracle run may use: the host's cores, at most cap."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, cap))

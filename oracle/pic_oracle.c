@@ -31,6 +31,9 @@
 #include <stdlib.h>
 #include <string.h>
 #include <stdio.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define PI 3.14159265358979323846
 
@@ -77,6 +80,20 @@ struct orc_sim {
 /* ------------------------------------------------------------------ */
 /* small helpers                                                       */
 /* ------------------------------------------------------------------ */
+
+/* threads of the particle stages (1 unless set) */
+static int g_threads = 1;
+
+void orc_set_threads(int n) { g_threads = n > 0 ? n : 1; }
+
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return g_threads;
+#else
+    return 1;
+#endif
+}
 
 uint64_t orc_splitmix64(uint64_t seed, uint64_t k)
 {
@@ -599,8 +616,19 @@ static void addf(orc_sim* s, double* F, long jx, long jz, double v)
 /* Esirkepov (2001) charge-conserving deposit of one particle moving from (x0,z0) to (x1,z1)
    (um, interior-relative) during one step, with out-of-plane velocity vy.  A fixed 7-node
    window per axis is used; shape factors vanish outside their support. */
+static void deposit_into(orc_sim* s, double* Jx, double* Jy, double* Jz, double q, double w, double x0,
+                         double z0, double x1, double z1, double vy);
+
 void orc_deposit_one(orc_sim* s, double q, double w, double x0, double z0, double x1, double z1,
                      double vy)
+{
+    deposit_into(s, FLD(s, ORC_JX), FLD(s, ORC_JY), FLD(s, ORC_JZ), q, w, x0, z0, x1, z1, vy);
+}
+
+/* the deposit of one particle into the given current arrays (the particle stage gives each
+   thread arrays of its own and sums them in thread order afterwards) */
+static void deposit_into(orc_sim* s, double* Jx, double* Jy, double* Jz, double q, double w, double x0,
+                         double z0, double x1, double z1, double vy)
 {
     const double dx = s->ax.d, dz = s->az.d, dt = s->dt;
     double a0 = x0 / dx, b0 = z0 / dz, a1 = x1 / dx, b1 = z1 / dz;
@@ -614,7 +642,6 @@ void orc_deposit_one(orc_sim* s, double q, double w, double x0, double z0, doubl
         S1z[m] = orc_shape3(b1 - (double)(kb + m));
         DSz[m] = S1z[m] - S0z[m];
     }
-    double *Jx = FLD(s, ORC_JX), *Jy = FLD(s, ORC_JY), *Jz = FLD(s, ORC_JZ);
     /* J_x(i+1/2) - J_x(i-1/2) = -q w W_x(i) / (dz dt), W_x = DS_x (S0_z + DS_z/2) */
     for (int b = 0; b < 7; b++) {
         double acc = 0.0;
@@ -672,9 +699,20 @@ void orc_stage_particles(orc_sim* s)
     memset(FLD(s, ORC_JY), 0, n * sizeof(double));
     memset(FLD(s, ORC_JZ), 0, n * sizeof(double));
 
-    /* electrons */
+    /* Electrons, then rigid ions, split over the threads: each thread deposits into current
+       arrays of its own, which are added to J in thread order afterwards (a fixed order for a
+       given thread count); the new states are stored first and compacted in particle order. */
+    const int nt = orc_threads();
+    double* priv = (double*)calloc((size_t)nt * 3 * n, sizeof(double));
+    double* nxz = (double*)malloc((size_t)(s->ne > 0 ? s->ne : 1) * 5 * sizeof(double));
     long keep = 0;
+#pragma omp parallel for schedule(static) num_threads(nt)
     for (long p = 0; p < s->ne; p++) {
+        int th = 0;
+#ifdef _OPENMP
+        th = omp_get_thread_num();
+#endif
+        double* Jt = priv + (size_t)th * 3 * n;
         double xc = s->ex[p] / dx, zc = s->ez[p] / dz;
         double E[3] = {gather(s, Ex, 1, 0, xc, zc), gather(s, Ey, 0, 0, xc, zc), gather(s, Ez, 0, 1, xc, zc)};
         /* B^n = (B^{n-1/2} + B^{n+1/2}) / 2 */
@@ -685,33 +723,56 @@ void orc_stage_particles(orc_sim* s)
         orc_boris(-1.0, dt, E, B, u);
         double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
         double x1 = s->ex[p] + dt * u[0] / g, z1 = s->ez[p] + dt * u[2] / g;
-        orc_deposit_one(s, -1.0, s->ew[p], s->ex[p], s->ez[p], x1, z1, u[1] / g);
+        deposit_into(s, Jt, Jt + n, Jt + 2 * n, -1.0, s->ew[p], s->ex[p], s->ez[p], x1, z1, u[1] / g);
+        double* r = nxz + 5 * p;
+        r[0] = x1; r[1] = z1; r[2] = u[0]; r[3] = u[1]; r[4] = u[2];
+    }
+    for (long p = 0; p < s->ne; p++) {
+        const double* r = nxz + 5 * p;
+        double x1 = r[0], z1 = r[1];
         if (s->cfg.periodic_x) { if (x1 < 0.0) x1 += Lx; else if (x1 >= Lx) x1 -= Lx; }
         if (s->cfg.periodic_z) { if (z1 < 0.0) z1 += Lz; else if (z1 >= Lz) z1 -= Lz; }
         int out = (!s->cfg.periodic_x && (x1 < 0.0 || x1 >= Lx)) ||
                   (!s->cfg.periodic_z && (z1 < 0.0 || z1 >= Lz));
         if (out) continue;   /* absorbed after its last deposit */
         s->eid[keep] = s->eid[p]; s->ex[keep] = x1; s->ez[keep] = z1;
-        s->eux[keep] = u[0]; s->euy[keep] = u[1]; s->euz[keep] = u[2]; s->ew[keep] = s->ew[p];
+        s->eux[keep] = r[2]; s->euy[keep] = r[3]; s->euz[keep] = r[4]; s->ew[keep] = s->ew[p];
         keep++;
     }
     s->ne = keep;
+    free(nxz);
 
     /* rigid ions: z(t) = z0 - beta c t in the boosted frame, deposit only */
     if (s->plasma.ion_mode == 1) {
-        double t0 = s->t, t1 = s->t + dt;   /* t_n = n dt; t_{n+1} = t_n + dt */
-        t1 = (double)(s->step + 1) * dt;
-        long kp = 0;
+        double t0 = s->t, t1 = (double)(s->step + 1) * dt;   /* t_n = n dt, t_{n+1} */
+#pragma omp parallel for schedule(static) num_threads(nt)
         for (long p = 0; p < s->ni; p++) {
+            int th = 0;
+#ifdef _OPENMP
+            th = omp_get_thread_num();
+#endif
+            double* Jt = priv + (size_t)th * 3 * n;
             double za = s->iz0[p] - s->beta * t0 - (double)s->shift * dz;
             double zb = s->iz0[p] - s->beta * t1 - (double)s->shift * dz;
-            orc_deposit_one(s, 1.0, s->iw[p], s->ix[p], za, s->ix[p], zb, 0.0);
+            deposit_into(s, Jt, Jt + n, Jt + 2 * n, 1.0, s->iw[p], s->ix[p], za, s->ix[p], zb, 0.0);
+        }
+        long kp = 0;
+        for (long p = 0; p < s->ni; p++) {
+            double zb = s->iz0[p] - s->beta * t1 - (double)s->shift * dz;
             if (!s->cfg.periodic_z && (zb < 0.0 || zb >= Lz)) continue;
             s->iid[kp] = s->iid[p]; s->ix[kp] = s->ix[p]; s->iz0[kp] = s->iz0[p]; s->iw[kp] = s->iw[p];
             kp++;
         }
         s->ni = kp;
     }
+    for (int th = 0; th < nt; th++) {
+        const double* Jt = priv + (size_t)th * 3 * n;
+        for (int c = 0; c < 3; c++) {
+            double* J = FLD(s, ORC_JX + c);
+            for (long q = 0; q < n; q++) J[q] += Jt[(size_t)c * n + q];
+        }
+    }
+    free(priv);
 
     /* laser antenna: a + and a - sheet particle per transverse cell; the - particle moves
        along the polarisation with v = K dx / (q w), K = -2 E_perp the sheet current.  Along

@@ -130,6 +130,11 @@ void orc_boris(double q_over_m, double dt, const double E[3], const double B[3],
 void orc_deposit_one(orc_sim* s, double q, double w, double x0, double z0, double x1, double z1,
                      double vy);
 
+/* host threads of the particle stages (default 1; the result then does not depend on it
+   beyond the order of the floating-point sums of the current) */
+void orc_set_threads(int n);
+int  orc_threads(void);
+
 /* SplitMix64 output number k (k >= 1) from state `seed` */
 uint64_t orc_splitmix64(uint64_t seed, uint64_t k);
 

@@ -42,6 +42,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define PI 3.14159265358979323846
 
@@ -501,7 +504,18 @@ static void add3(orc3_sim* s, double* F, const long j[3], double v)
    DS = S1 - S0 on a 7-node window per axis,
      W_c = DS_c (S0_a1 S0_a2 + DS_a1 S0_a2 / 2 + S0_a1 DS_a2 / 2 + DS_a1 DS_a2 / 3),
      J_c(node + 1/2) - J_c(node - 1/2) = -q w W_c / (d_a1 d_a2 dt)    ((c, a1, a2) cyclic) */
+static void deposit_into3(orc3_sim* s, double* const Jc[3], double q, double w, const double r0[3],
+                          const double r1[3]);
+
 void orc3_deposit_one(orc3_sim* s, double q, double w, const double r0[3], const double r1[3])
+{
+    double* const J[3] = {s->f[O3_JX], s->f[O3_JY], s->f[O3_JZ]};
+    deposit_into3(s, J, q, w, r0, r1);
+}
+
+/* the same into the given current arrays (each thread of the particle stage has its own) */
+static void deposit_into3(orc3_sim* s, double* const Jc[3], double q, double w, const double r0[3],
+                          const double r1[3])
 {
     double S0[3][7], DS[3][7];
     long base[3];
@@ -516,7 +530,7 @@ void orc3_deposit_one(orc3_sim* s, double q, double w, const double r0[3], const
     for (int c = 0; c < 3; c++) {
         const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
         const double k = -q * w / (s->a[a1].d * s->a[a2].d * s->dt);
-        double* J = s->f[O3_JX + c];
+        double* J = Jc[c];
         for (int m1 = 0; m1 < 7; m1++)
             for (int m2 = 0; m2 < 7; m2++) {
                 double T = S0[a1][m1] * S0[a2][m2] + 0.5 * DS[a1][m1] * S0[a2][m2] +
@@ -568,8 +582,21 @@ void orc3_stage_particles(orc3_sim* s)
     for (int d = 0; d < 3; d++) L[d] = s->a[d].N * s->a[d].d;
     for (int c = 0; c < 3; c++) memset(s->f[O3_JX + c], 0, s->ncell * sizeof(double));
 
-    long keep = 0;
+    /* electrons, then rigid ions, split over the threads: each thread deposits into current
+       arrays of its own, added to J in thread order afterwards; new states are stored first
+       and compacted in particle order */
+    const int nt = orc_threads();
+    const size_t nc = (size_t)s->ncell;
+    double* priv = (double*)calloc((size_t)nt * 3 * nc, sizeof(double));
+    double* nst = (double*)malloc((size_t)(s->ne > 0 ? s->ne : 1) * 6 * sizeof(double));
+#pragma omp parallel for schedule(static) num_threads(nt)
     for (long p = 0; p < s->ne; p++) {
+        int th = 0;
+#ifdef _OPENMP
+        th = omp_get_thread_num();
+#endif
+        double* const Jt[3] = {priv + (size_t)th * 3 * nc, priv + ((size_t)th * 3 + 1) * nc,
+                               priv + ((size_t)th * 3 + 2) * nc};
         double r0[3] = {s->ex[p], s->ey[p], s->ez[p]};
         double rc[3] = {r0[0] / s->a[0].d, r0[1] / s->a[1].d, r0[2] / s->a[2].d};
         double E[3], B[3];
@@ -582,7 +609,13 @@ void orc3_stage_particles(orc3_sim* s)
         double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
         double r1[3];
         for (int d = 0; d < 3; d++) r1[d] = r0[d] + dt * u[d] / g;
-        orc3_deposit_one(s, -1.0, s->ew[p], r0, r1);
+        deposit_into3(s, Jt, -1.0, s->ew[p], r0, r1);
+        double* o = nst + 6 * p;
+        for (int d = 0; d < 3; d++) { o[d] = r1[d]; o[3 + d] = u[d]; }
+    }
+    long keep = 0;
+    for (long p = 0; p < s->ne; p++) {
+        double r1[3] = {nst[6 * p], nst[6 * p + 1], nst[6 * p + 2]};
         int out = 0;
         for (int d = 0; d < 3; d++) {
             if (s->a[d].periodic) { if (r1[d] < 0.0) r1[d] += L[d]; else if (r1[d] >= L[d]) r1[d] -= L[d]; }
@@ -591,25 +624,44 @@ void orc3_stage_particles(orc3_sim* s)
         if (out) continue;
         s->eid[keep] = s->eid[p];
         s->ex[keep] = r1[0]; s->ey[keep] = r1[1]; s->ez[keep] = r1[2];
-        s->eux[keep] = u[0]; s->euy[keep] = u[1]; s->euz[keep] = u[2]; s->ew[keep] = s->ew[p];
+        s->eux[keep] = nst[6 * p + 3]; s->euy[keep] = nst[6 * p + 4]; s->euz[keep] = nst[6 * p + 5];
+        s->ew[keep] = s->ew[p];
         keep++;
     }
     s->ne = keep;
+    free(nst);
 
     if (s->plasma.ion_mode == 1) {
         double t0 = s->t, t1 = (double)(s->step + 1) * dt;
-        long kp = 0;
+#pragma omp parallel for schedule(static) num_threads(nt)
         for (long p = 0; p < s->ni; p++) {
+            int th = 0;
+#ifdef _OPENMP
+            th = omp_get_thread_num();
+#endif
+            double* const Jt[3] = {priv + (size_t)th * 3 * nc, priv + ((size_t)th * 3 + 1) * nc,
+                                   priv + ((size_t)th * 3 + 2) * nc};
             double ra[3] = {s->ix[p], s->iy[p], s->iz0[p] - s->beta * t0 - (double)s->shift * s->a[2].d};
             double rb[3] = {s->ix[p], s->iy[p], s->iz0[p] - s->beta * t1 - (double)s->shift * s->a[2].d};
-            orc3_deposit_one(s, 1.0, s->iw[p], ra, rb);
-            if (!s->a[2].periodic && (rb[2] < 0.0 || rb[2] >= L[2])) continue;
+            deposit_into3(s, Jt, 1.0, s->iw[p], ra, rb);
+        }
+        long kp = 0;
+        for (long p = 0; p < s->ni; p++) {
+            double zb = s->iz0[p] - s->beta * t1 - (double)s->shift * s->a[2].d;
+            if (!s->a[2].periodic && (zb < 0.0 || zb >= L[2])) continue;
             s->iid[kp] = s->iid[p]; s->ix[kp] = s->ix[p]; s->iy[kp] = s->iy[p];
             s->iz0[kp] = s->iz0[p]; s->iw[kp] = s->iw[p];
             kp++;
         }
         s->ni = kp;
     }
+    for (int th = 0; th < nt; th++)
+        for (int c = 0; c < 3; c++) {
+            const double* Jt = priv + ((size_t)th * 3 + c) * nc;
+            double* J = s->f[O3_JX + c];
+            for (size_t q = 0; q < nc; q++) J[q] += Jt[q];
+        }
+    free(priv);
 
     if (s->have_laser) {
         double t0 = s->t, t1 = (double)(s->step + 1) * dt;
