@@ -69,6 +69,11 @@ typedef struct {
     int filter_compensate;     /* 1: one extra pass with alpha_c = n/2 + 1                     */
     int filter_kind;           /* BF_FILTER_BILINEAR, or BF_FILTER_LEARNED (FP32 runs only;
                                   weights from bf_set_learned_filter)                         */
+    int filter_strides;        /* bilinear filter strides (Eq. 3ptfilter_stride): bit s-1 set
+                                  applies the npass passes (+ compensation) with stride s, in
+                                  ascending order of s, e.g. 0x3 = S(1:2), 0x7 = S(1:2:3),
+                                  0xB = S(1:2:4); 0 means stride 1 only.  BF_EINVAL beyond
+                                  stride 16, 48 passes or a reach of 128 cells per axis       */
     int pml_cells;             /* PML depth on non-periodic faces (Appendix II)                */
     int periodic_mask;         /* bit 0: x, bit 1: y (3D), bit 2: z periodic (no moving window) */
     double gamma_boost;        /* Lorentz factor of the calculation frame (>= 1)              */
@@ -182,7 +187,9 @@ enum {
     BF_DIAG_STATION = 3,   /* arg = station: int64 count then count x 7 doubles (t_lab, Ex,
                               Ey, Ez, Bx, By, Bz in the lab frame)                           */
     BF_DIAG_ENERGY = 4,    /* 3 doubles: field energy E, field energy B, kinetic energy     */
-    BF_DIAG_GAUSS = 5,     /* stored_z x stored_x doubles: div E - F[rho] on the nodes (2D) */
+    BF_DIAG_GAUSS = 5,     /* div E - F[rho] on the nodes, doubles in the field layout; 3D
+                              uses the FP64 current accumulators as scratch (J_xr .. J_zr of
+                              the last step are gone afterwards)                            */
     BF_DIAG_INFO = 6,      /* bf_info                                                       */
     BF_DIAG_ANTENNA = 7,   /* nx doubles (3D: nx x ny): coordinate of each moving antenna
                               particle along the polarisation, in cells (x; 3D y polarisation:
@@ -267,7 +274,8 @@ int64_t bf_batch_work_bytes(int nsims);
 /* Creates a batch over n distinct handles (not owned).  work: device buffer of at least
    bf_batch_work_bytes(n) bytes, 256-byte aligned, owned by the caller.  hip_stream: the stream
    of the batched launches (NULL: default).  BF_EINVAL: bad arguments or a repeated handle;
-   BF_EUNSUPPORTED: an FP64 handle; BF_ESTATE: a handle with a sticky error;
+   BF_EUNSUPPORTED: an FP64 or 3D handle, or one with filter strides other than 1; BF_ESTATE: a
+   handle with a sticky error;
    BF_EDEVICE: pinned staging memory could not be allocated. */
 bf_status bf_batch_create(bf_sim* const* sims, int n, void* work, int64_t work_bytes,
                           void* hip_stream, bf_batch** out);

@@ -7,8 +7,9 @@
 //    Faraday_Friedman, indices shifted by one), split-field PML (Appendix II) on the borders.
 //  * k_ampere: Yee Ampere E^{n+1} = E^n + dt (curl B^{n+1/2} - J) with the PML split.
 //    k_faraday, first in the step, clears the raw current the deposit accumulates into.
-//  * k_filter: n bilinear passes plus compensation per axis (Sec. 4.1), all passes of one
-//    axis run in LDS on a tile with an (n + 1)-cell halo.
+//  * k_filter_batch: n bilinear passes plus compensation per axis (Sec. 4.1) for the batched
+//    runs, all passes of both axes in LDS on a tile with an (n + 1)-cell halo.  Single runs
+//    use the line filter of bf_sim3.hip (any stride mask) on the grid seen with one y plane.
 //  * k_window_rows: moving-window advance = ring offset change + clearing the new rows.
 //  * k_stations: lab-frame stations (Sec. 3.2).
 //  * k_rho: charge density for the Gauss diagnostic.
@@ -305,21 +306,6 @@ __device__ __forceinline__ void filter_tile(const Geo& g, const R* __restrict__ 
     }
 }
 
-// the current components of one filter launch (blockIdx.z picks the component)
-template <typename R>
-struct FilterSet {
-    const R* in[3];
-    R* out[3];
-    int hx[3], hz[3];
-};
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_filter(Geo g, FilterSet<R> fs, int npass, int comp)
-{
-    const int c = blockIdx.z;
-    filter_tile<R>(g, fs.in[c], fs.out[c], fs.hx[c], fs.hz[c], npass, comp, blockIdx.x, blockIdx.y);
-}
-
 // ---- batched runs: one persistent launch per phase over a device work queue ----------------
 template <typename R>
 __global__ void __launch_bounds__(256) k_faraday_batch(const FaradayDesc<R>* __restrict__ d, QueueRef q)
@@ -542,24 +528,6 @@ void launch_ampere(const Geo& g, const FieldSet<R>& f, const PmlTab<R>& pm, cons
 }
 
 template <typename R>
-void launch_filter(const Geo& g, R* const in[3], R* const out[3], const int hx[3], const int hz[3],
-                   int ncomp, int npass, int compensate, hipStream_t s)
-{
-    const int H = npass + (compensate ? 1 : 0);
-    const size_t lds = 2 * (size_t)(FTX + 2 * H) * (FTZ + 2 * H) * sizeof(R);
-    if (ncomp <= 0 || ncomp > 3) return;
-    FilterSet<R> fs{};
-    for (int c = 0; c < ncomp; c++) {
-        fs.in[c] = in[c];
-        fs.out[c] = out[c];
-        fs.hx[c] = hx[c];
-        fs.hz[c] = hz[c];
-    }
-    dim3 grid((g.Sx + FTX - 1) / FTX, (g.Sz + FTZ - 1) / FTZ, ncomp);
-    hipLaunchKernelGGL((k_filter<R>), grid, dim3(256), lds, s, g, fs, npass, compensate);
-}
-
-template <typename R>
 void launch_window_rows(const Geo& g, const PtrList<R>& arrays, int d, const EntryRows& er,
                         const FieldSet<R>& f, const PmlTab<R>& pm, hipStream_t s)
 {
@@ -600,8 +568,6 @@ void launch_fill_int(int* p, int n, int v, hipStream_t s)
     template void launch_faraday_batch<R>(const FaradayDesc<R>*, const QueueRef&, int, hipStream_t); \
     template void launch_ampere_batch<R>(const AmpereDesc<R>*, const QueueRef&, int, hipStream_t);   \
     template void launch_filter_batch<R>(const FilterDesc<R>*, const QueueRef&, int, int, hipStream_t); \
-    template void launch_filter<R>(const Geo&, R* const[3], R* const[3], const int[3],             \
-                                   const int[3], int, int, int, hipStream_t);                      \
     template void launch_window_rows<R>(const Geo&, const PtrList<R>&, int, const EntryRows&,      \
                                         const FieldSet<R>&, const PmlTab<R>&, hipStream_t);        \
     template void launch_stations<R>(const Geo&, const FieldSet<R>&, const StationParams&,         \

@@ -44,7 +44,8 @@ enum {
     A_JF = 21,  // filtered J
     A_BYX = 24,
     A_EYX = 25,
-    A_COUNT = 26
+    A_JT = 26,  // the filter's intermediate (after the x passes)
+    A_COUNT = 29
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -171,6 +172,11 @@ bf_status validate(const bf_config* c)
     if (c->shape_order != 3) return BF_EUNSUPPORTED;
     if (c->friedman_theta < 0 || c->friedman_theta > 1) return BF_EINVAL;
     if (c->filter_npass < 0 || c->filter_npass > 10) return BF_EINVAL;
+    if (c->filter_strides < 0 || c->filter_strides > 0xFFFF) return BF_EINVAL;
+    {
+        bf3::FiltSeq fs;
+        if (!bf3::filter_seq(c->filter_npass, c->filter_compensate, c->filter_strides, &fs)) return BF_EINVAL;
+    }
     if (c->filter_kind != BF_FILTER_BILINEAR && c->filter_kind != BF_FILTER_LEARNED) return BF_EINVAL;
     if (c->filter_kind == BF_FILTER_LEARNED && c->real_bytes != 4) return BF_EUNSUPPORTED;
     if (c->pml_cells < 0 || c->pml_cells > 64) return BF_EINVAL;
@@ -293,6 +299,21 @@ bf_status hip_check(bf_sim* s, hipError_t e, const char* where)
     snprintf(b, sizeof b, "%s: %s", where, hipGetErrorString(e));
     if (s) { s->msg = b; s->err = BF_EDEVICE; }
     return BF_EDEVICE;
+}
+
+// the 2-1/2D grid seen as a 3D one with a single y plane (for the line filter)
+bf3::G3 g3_of(const Geo& g, const bf_config& c)
+{
+    bf3::G3 h{};
+    h.N[0] = g.Nx; h.N[1] = 1; h.N[2] = g.Nz;
+    h.S[0] = g.Sx; h.S[1] = 1; h.S[2] = g.Sz;
+    h.P[0] = g.Px; h.P[1] = 0; h.P[2] = g.Pz;
+    h.per[0] = g.perx; h.per[1] = 1; h.per[2] = g.perz;
+    h.pitch = g.pitch;
+    h.plane = g.pitch;
+    h.zoff = g.zoff;
+    h.d[0] = c.dx_um; h.d[1] = c.dx_um; h.d[2] = c.dz_um;
+    return h;
 }
 
 template <typename R>
@@ -707,7 +728,12 @@ bf_status step_impl(bf_sim* s, int nsteps)
                     rb->max_halo = std::max(rb->max_halo, c.filter_npass + (c.filter_compensate ? 1 : 0));
                 }
             }
-            if (!rb) launch_filter<R>(g, in, out, hx, hz, 3, c.filter_npass, c.filter_compensate, s->stream);
+            if (!rb) {
+                bf3::FiltSeq fs;
+                bf3::filter_seq(c.filter_npass, c.filter_compensate, c.filter_strides, &fs);
+                R* tmp[3] = {s->arr<R>(A_JT), s->arr<R>(A_JT + 1), s->arr<R>(A_JT + 2)};
+                bf3::launch_filter_xz<R>(g3_of(g, c), in, tmp, out, hx, hz, 3, fs, s->stream);
+            }
         }
         s->tock(t_ph, BF_PHASE_FILTER);
         // Ampere + PML (E^{n+1} into the E^{n-1} set)
@@ -1180,7 +1206,9 @@ bf_status step3(bf_sim* s, int nsteps)
         s->tock(ev, BF_PHASE_ANTENNA);
         ev = s->tick();
         const R* jout[3];
-        bf3::launch3_filter<R>(g, f, s->cfg.filter_npass, s->cfg.filter_compensate, jout, s->stream);
+        bf3::FiltSeq fs;
+        bf3::filter_seq(s->cfg.filter_npass, s->cfg.filter_compensate, s->cfg.filter_strides, &fs);
+        bf3::launch3_filter<R>(g, f, fs, jout, s->stream);
         s->tock(ev, BF_PHASE_FILTER);
         ev = s->tick();
         bf3::launch3_ampere<R>(g, f, jout, pml, s->dt, s->stream);
@@ -1245,14 +1273,9 @@ int array3_of(int id)
     }
 }
 
-// the filtered current: the filter's first launch writes Jf, the next ones alternate (one
-// launch per axis up to the fused limit, one per pass beyond it)
-int filtered3(const bf_config& c, int comp)
-{
-    const int np = c.filter_npass + (c.filter_compensate ? 1 : 0);
-    const int ops = np <= 0 ? 1 : (np <= bf3::FILTER_FUSED ? 3 : 3 * np);
-    return ((ops & 1) ? A3_JF : A3_JG) + comp;
-}
+// the filtered current ends in Jf (x pass into Jf, y into Jg, z back into Jf; a copy into Jf
+// without passes)
+int filtered3(const bf_config&, int comp) { return A3_JF + comp; }
 
 bf_status read_field3(bf_sim* s, int a, double* out)
 {
@@ -1342,6 +1365,62 @@ bf_status read_particles3(bf_sim* s, int species, std::vector<double>* cols, int
         cols[7].push_back(w);
     }
     *nlive = (int64_t)cols[0].size();
+    return BF_OK;
+}
+
+// div E - F[rho] on the nodes (Sec. 4.2.2: the charge-conserving deposit keeps it constant), rho
+// from the particles with the deposit's cubic shape, filtered like the current.  The FP64 current
+// accumulators serve as scratch: the raw current of the last step is gone afterwards.
+template <typename R>
+bf_status gauss3_impl(bf_sim* s, double* out)
+{
+    const Sim3& L = *s->d3;
+    const double d[3] = {s->cfg.dx_um, s->cfg.dy_um, s->cfg.dz_um};
+    int64_t ne = 0, ni = 0;
+    hipError_t e = slots3(s, 0, &ne);
+    if (e == hipSuccess) e = slots3(s, 1, &ni);
+    if (e != hipSuccess) return hip_check(s, e, "3D gauss");
+    if (!(s->have_plasma && s->plasma.ion_mode == 1)) ni = 0;
+    double za = 0.0;
+    int na = 0;
+    if (s->have_laser) {
+        za = (s->za_lab / s->gamma - s->beta * s->t) / d[2] - (double)s->shift;
+        if (za >= 0.0 && za < L.g.N[2]) na = L.na;
+    }
+    double* a = jacc3(s, 0);
+    bf3::launch3_rho<R>(L.g, electrons3<R>(s, L.p_cur), (int)ne, ions3<R>(s, L.p_cur), (int)ni, zshift3(s, s->t),
+                        w3<double>(s, L.w_ant), na, s->pol, za, s->aw, 1.0 / (d[0] * d[1] * d[2]), a, s->stream);
+    bf3::FiltSeq fs;
+    bf3::filter_seq(s->cfg.filter_npass, s->cfg.filter_compensate, s->cfg.filter_strides, &fs);
+    const double* res = bf3::launch3_filter_nodal(L.g, a, jacc3(s, 1), jacc3(s, 2), fs, s->stream);
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_check(s, e, "3D gauss");
+    const size_t grid = (size_t)L.g.S[0] * L.g.S[1] * L.g.S[2];
+    std::vector<double> rho(grid), E[3];
+    bf_status st = read_field3(s, A3_J + (res == a ? 0 : 1), rho.data());
+    for (int c = 0; c < 3 && st == BF_OK; c++) {
+        E[c].resize(grid);
+        st = read_field3(s, A3_E + c, E[c].data());
+    }
+    if (st != BF_OK) return st;
+    const int S0 = L.g.S[0], S1 = L.g.S[1], S2 = L.g.S[2];
+    const int Sa[3] = {S0, S1, S2};
+    const size_t step[3] = {1, (size_t)S0, (size_t)S0 * S1};
+    for (int k = 0; k < S2; k++)
+        for (int j = 0; j < S1; j++)
+            for (int i = 0; i < S0; i++) {
+                const int q[3] = {i, j, k};
+                const size_t o = ((size_t)k * S1 + j) * S0 + i;
+                double div = 0.0;
+                for (int ax = 0; ax < 3; ax++) {
+                    // E_ax sits on half nodes along ax: node q lies between stored q - 1 and q
+                    int ql = q[ax] - 1;
+                    if (L.g.per[ax]) ql = (ql + Sa[ax]) % Sa[ax];
+                    const double el = ql >= 0 ? E[ax][o - (size_t)q[ax] * step[ax] + (size_t)ql * step[ax]] : 0.0;
+                    div += (E[ax][o] - el) / d[ax];
+                }
+                out[o] = div - rho[o];
+            }
     return BF_OK;
 }
 
@@ -1459,8 +1538,14 @@ bf_status diagnose3(bf_sim* s, int kind, int arg, void* host_out, size_t bytes)
         std::vector<double> xm(L.na);
         hipError_t e = hipMemcpy(xm.data(), w3<double>(s, L.w_ant), xm.size() * 8, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_check(s, e, "antenna");
-        for (int q = 0; q < L.na; q++) ((double*)host_out)[q] = xm[q] * s->cfg.dx_um;
+        const double dm = s->pol == 0 ? s->cfg.dx_um : s->cfg.dy_um;
+        for (int q = 0; q < L.na; q++) ((double*)host_out)[q] = xm[q] * dm;
         return BF_OK;
+    }
+    case BF_DIAG_GAUSS: {
+        if (bytes < grid * 8) return fail(s, BF_EINVAL, "buffer too small");
+        return s->cfg.real_bytes == 4 ? gauss3_impl<float>(s, (double*)host_out)
+                                      : gauss3_impl<double>(s, (double*)host_out);
     }
     default:
         return fail(s, BF_EUNSUPPORTED, "diagnostic not available in 3D");
@@ -1879,6 +1964,10 @@ bf_status bf_batch_create(bf_sim* const* sims, int n, void* work, int64_t work_b
     if (work_bytes < bf_batch_work_bytes(n)) return BF_EINVAL;
     for (int q = 0; q < n; q++) {
         if (!sims[q] || sims[q]->cfg.real_bytes != 4 || sims[q]->d3) return BF_EUNSUPPORTED;
+        // the batched filter phase runs the stride-1 tile filter
+        if (sims[q]->cfg.filter_strides > 1) return BF_EUNSUPPORTED;
+        // the batched filter phase runs the stride-1 tile filter
+        if (sims[q]->cfg.filter_strides > 1) return BF_EUNSUPPORTED;
         if (sims[q]->err != BF_OK) return BF_ESTATE;
         for (int p = 0; p < q; p++)
             if (sims[p] == sims[q]) return BF_EINVAL;
@@ -2081,12 +2170,14 @@ static bf_status gauss_impl(bf_sim* s, double* out)
                   s->w<double>(L.w_ant), na, 0.5, za, s->aw, inv_cell, rho, s->stream);
     double* res = rho;
     if (s->cfg.filter_npass > 0) {
-        double* in[3] = {rho, rho, rho};
-        double* o3[3] = {rhof, rhof, rhof};
+        // the step's filter on the nodal charge density: rho -> rhof along x, back along z
+        bf3::FiltSeq fs;
+        bf3::filter_seq(s->cfg.filter_npass, s->cfg.filter_compensate, s->cfg.filter_strides, &fs);
+        double* in[3] = {rho, nullptr, nullptr};
+        double* tmp[3] = {rhof, nullptr, nullptr};
+        double* o3[3] = {rho, nullptr, nullptr};
         const int hx[3] = {0, 0, 0}, hz[3] = {0, 0, 0};
-        launch_filter<double>(g0, in, o3, hx, hz, 1, s->cfg.filter_npass, s->cfg.filter_compensate,
-                              s->stream);
-        res = rhof;
+        bf3::launch_filter_xz<double>(g3_of(g0, s->cfg), in, tmp, o3, hx, hz, 1, fs, s->stream);
     }
     ck(hipStreamSynchronize(s->stream));
     std::vector<double> r(grid), ex(grid), ez(grid);

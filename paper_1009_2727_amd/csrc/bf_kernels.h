@@ -175,9 +175,6 @@ template <typename R>
 void launch_ampere(const Geo& g, const FieldSet<R>& f, const PmlTab<R>& pm, const SolverCoef& c,
                    hipStream_t s);
 template <typename R>
-void launch_filter(const Geo& g, R* const in[3], R* const out[3], const int hx[3],
-                   const int hz[3], int ncomp, int npass, int compensate, hipStream_t s);
-template <typename R>
 struct PtrList {
     R* p[32];
     int n;

@@ -107,12 +107,39 @@ void launch3_faraday(const G3& g, const F3<R>& f, const Pml3& pml, const double 
                      hipStream_t s);
 template <typename R>
 void launch3_ampere(const G3& g, const F3<R>& f, const R* const J[3], const Pml3& pml, double dt, hipStream_t s);
-// n bilinear passes (+ compensation) per axis on J; returns in out[] where each component's
-// result lies.  Up to FILTER_FUSED passes per axis run as one launch per axis (Jf <- J, Jg <- Jf,
-// Jf <- Jg); more run pass by pass, ping-ponging between Jf and Jg after the first.
-constexpr int FILTER_FUSED = 8;
+// The passes of the current filter along one axis (Sec. 4.1, Eqs. 3ptfilter and
+// 3ptfilter_stride): for each stride of the mask in ascending order, npass passes with
+// alpha = 1/2 and, when asked, one compensation pass with alpha = npass/2 + 1.  reach is the sum
+// of the strides: a cell's result depends on the input within reach cells along the axis.
+constexpr int FSEQ_MAX = 48;       // passes per axis
+constexpr int FREACH_MAX = 128;    // reach per axis
+struct FiltSeq {
+    int n, reach;
+    double alpha[FSEQ_MAX];
+    int stride[FSEQ_MAX];
+};
+// builds the sequence; false when it exceeds FSEQ_MAX passes or FREACH_MAX cells of reach
+bool filter_seq(int npass, int comp, int stride_mask, FiltSeq* fs);
+// the whole filter on J (FP64 accumulators) into the run's type, one launch per axis for the
+// three components (Jf <- J along x, Jg <- Jf along y, Jf <- Jg along z); out[] receives each
+// component's result.  Without passes J is copied into Jf.
 template <typename R>
-void launch3_filter(const G3& g, const F3<R>& f, int npass, int comp, const R* out[3], hipStream_t s);
+void launch3_filter(const G3& g, const F3<R>& f, const FiltSeq& fs, const R* out[3], hipStream_t s);
+// the filter on up to three arrays of a grid with a single y plane (the 2-1/2D layout: S[1] = 1,
+// plane = the row pitch, the ring on z): in -> tmp along x, tmp -> out along z.  hx, hz: each
+// array's staggers.  Without passes in is copied into out.
+template <typename T>
+void launch_filter_xz(const G3& g, const T* const in[3], T* const tmp[3], T* const out[3], const int hx[3],
+                      const int hz[3], int ncomp, const FiltSeq& fs, hipStream_t s);
+// the same filter on one FP64 array of nodal stagger (the charge density of the Gauss
+// diagnostic): a -> b along x, b -> c along y, c -> b along z; returns b
+double* launch3_filter_nodal(const G3& g, double* a, double* b, double* c, const FiltSeq& fs, hipStream_t s);
+// charge density on the nodes (FP64, cubic shape) of the electrons, rigid ions (at z0 - zsh) and
+// antenna sheets (plane at za cells; + at home, - at its moving coordinate along pol) into rho
+// (cleared here); vol_inv = 1 / cell volume
+template <typename R>
+void launch3_rho(const G3& g, const E3<R>& e, int ne, const I3<R>& ion, int ni, double zsh, const double* ant,
+                 int na, int pol, double za, double aw, double vol_inv, double* rho, hipStream_t s);
 template <typename R> void launch3_zero_j(const G3& g, const F3<R>& f, hipStream_t s);
 // gather, push and deposit of the electrons of nseg segments (one workgroup each); bin holds
 // each segment's cell box at the start of the step, bout receives the box after the push (in

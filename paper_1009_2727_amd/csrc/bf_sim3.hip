@@ -255,68 +255,108 @@ __global__ void __launch_bounds__(NT) k3_ampere(G3 g, F3<R> f, const R* J0, cons
     ampere_comp<2>(g, f, J, pml, q, dt);
 }
 
-// one 3-point pass along AX over the stored range of a component with stagger h there;
-// neighbours beyond the range read 0, cells beyond it are copied
-// all np passes along AX at once (np <= FH): the result at a cell depends only on the 2 np + 1
-// values around it along AX, so the passes run on that window in registers, neighbours beyond
-// the component's range reading 0 after every pass (cells beyond it are copied)
-constexpr int FH = FILTER_FUSED;
+// ---- current filter: all passes along one axis in LDS ------------------------------------------
+// A workgroup holds a segment of tseg cells along AX plus the reach on both sides, for BC lines
+// (AX = x: BC whole x lines; AX = y, z: BC consecutive x columns, so every load and store is a
+// contiguous run of x).  It runs the pass sequence in LDS, ping-ponging between two buffers:
+// each pass is phi_j <- alpha phi_j + (1 - alpha)(phi_{j-s} + phi_{j+s}) / 2, positions beyond
+// the component's stored range held at 0 after every pass (zero padding; periodic axes wrap).
+// Positions beyond the segment's halo read 0; the error that causes moves inwards by at most
+// one stride per pass, so the tseg central cells are exact.  Cells beyond the component's range
+// (its last half node on a non-periodic axis) are copied.
+template <typename TI, typename TO>
+struct Lines3 {
+    const TI* in[3];
+    TO* out[3];
+    int h[3];                          // stagger of each component along the launch's axis
+};
 
-template <int AX, typename TI, typename R>
-__global__ void __launch_bounds__(NT) k3_ffused(G3 g, const TI* __restrict__ in, R* __restrict__ out, int h, int np,
-                                                int npass, double ac)
+template <int AX> constexpr int fline_bc() { return AX == 0 ? 8 : 32; }
+
+template <int AX, typename TI, typename TO, typename T>
+__global__ void __launch_bounds__(NT) k3_fline(G3 g, Lines3<TI, TO> L, FiltSeq fs, int tseg, int nseg, int ncolb)
 {
-    int q[3];
-    if (!cell_of(g, q)) return;
-    const long o = o3(g, q[0], q[1], q[2]);
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    constexpr int BC = fline_bc<AX>();
+    constexpr int TPC = NT / BC;                  // threads per line (x) or per column (y, z)
+    const int R = fs.reach;
+    const int A = tseg + 2 * R;
+    const int ld = AX == 0 ? A + 1 : BC + 1;
+    T* src = reinterpret_cast<T*>(smem_raw);
+    T* dst = src + (AX == 0 ? BC * ld : A * ld);
+    // block -> (component, segment, column block, plane or row across)
+    int bid = (int)blockIdx.x;
+    const int nother = AX == 0 ? 1 : g.S[AX == 1 ? 2 : 1];
+    const int per_comp = nseg * ncolb * nother;
+    const int c = bid / per_comp;
+    bid -= c * per_comp;
+    const int seg = bid % nseg;
+    bid /= nseg;
+    const int cb = bid % ncolb;
+    const int other = bid / ncolb;
+    const TI* __restrict__ in = L.in[c];
+    TO* __restrict__ out = L.out[c];
     const int S = g.S[AX], per = g.per[AX];
-    const int hi = per ? S - 1 : S - 1 - h;
-    if (q[AX] > hi) { out[o] = (R)in[o]; return; }
-    double w[2 * FH + 1];
-    bool m[2 * FH + 1];
-    int p[3] = {q[0], q[1], q[2]};
-#pragma unroll
-    for (int d = -FH; d <= FH; d++) {
-        w[d + FH] = 0.0;
-        m[d + FH] = false;
-        if (d < -np || d > np) continue;
-        int j = q[AX] + d;
-        if (per) {
-            j %= S;
-            if (j < 0) j += S;
+    const int hi = per ? S - 1 : S - 1 - L.h[c];
+    const int seg0 = seg * tseg;
+    // this thread's line / column and first row; the HBM offset of position jj along AX is
+    // base + jj * step, with the z ring applied to whichever index runs along z
+    const int col = AX == 0 ? (int)threadIdx.x / TPC : (int)threadIdx.x % BC;
+    const int a0 = AX == 0 ? (int)threadIdx.x % TPC : (int)threadIdx.x / BC;
+    bool ok;
+    long base = 0;
+    if (AX == 0) {
+        const int l = cb * BC + col;
+        ok = l < g.S[1] * g.S[2];
+        const int jy = ok ? l % g.S[1] : 0, k = ok ? l / g.S[1] : 0;
+        base = o3(g, 0, jy, k);
+    } else {
+        const int x = cb * BC + col;
+        ok = x < g.S[0];
+        base = AX == 1 ? o3(g, ok ? x : 0, 0, other) : (long)other * g.pitch + (ok ? x : 0);
+    }
+    auto at = [&](int jj) -> long {           // 0 <= jj < S
+        if (AX == 0) return base + jj;
+        if (AX == 1) return base + (long)jj * g.pitch;
+        int kk = jj + g.zoff;
+        if (kk >= g.S[2]) kk -= g.S[2];
+        return base + (long)kk * g.plane;
+    };
+    auto wrap = [&](int j) {
+        if (j >= 0 && j < S) return j;
+        int jj = j % S;
+        return jj < 0 ? jj + S : jj;
+    };
+    auto idx = [&](int a) { return AX == 0 ? col * ld + a : a * ld + col; };
+    for (int a = a0; a < A; a += TPC) {
+        const int j = seg0 - R + a;
+        T v = T(0);
+        if (ok && (per || (j >= 0 && j <= hi))) v = (T)in[at(per ? wrap(j) : j)];
+        src[idx(a)] = v;
+    }
+    __syncthreads();
+    for (int p = 0; p < fs.n; p++) {
+        const T al = (T)fs.alpha[p], be = (T(1) - al) * T(0.5);
+        const int st = fs.stride[p];
+        for (int a = a0; a < A; a += TPC) {
+            const int j = seg0 - R + a;
+            const T l = a >= st ? src[idx(a - st)] : T(0);
+            const T r = a + st < A ? src[idx(a + st)] : T(0);
+            const T v = al * src[idx(a)] + be * (l + r);
+            dst[idx(a)] = (per || (j >= 0 && j <= hi)) ? v : T(0);
         }
-        if (j < 0 || j > hi) continue;
-        p[AX] = j;
-        w[d + FH] = (double)in[o3(g, p[0], p[1], p[2])];
-        m[d + FH] = true;
+        __syncthreads();
+        T* t = src;
+        src = dst;
+        dst = t;
     }
-#pragma unroll
-    for (int s = 0; s < FH; s++) {
-        if (s >= np) break;
-        const double a = s < npass ? 0.5 : ac, b = 0.5 * (1.0 - a);
-        double t[2 * FH + 1];
-#pragma unroll
-        for (int d = 1; d < 2 * FH; d++) t[d] = m[d] ? a * w[d] + b * (w[d - 1] + w[d + 1]) : 0.0;
-#pragma unroll
-        for (int d = 1; d < 2 * FH; d++) w[d] = t[d];
+    if (!ok) return;
+    for (int a = a0; a < tseg; a += TPC) {
+        const int j = seg0 + a;
+        if (j >= S) break;
+        const long o = at(j);
+        out[o] = (per || j <= hi) ? (TO)src[idx(a + R)] : (TO)in[o];
     }
-    out[o] = (R)w[FH];
-}
-
-template <int AX, typename TI, typename R>
-__global__ void __launch_bounds__(NT) k3_fpass(G3 g, const TI* __restrict__ in, R* __restrict__ out, int h, R alpha)
-{
-    int q[3];
-    if (!cell_of(g, q)) return;
-    const long o = o3(g, q[0], q[1], q[2]);
-    const int hi = g.per[AX] ? g.S[AX] - 1 : g.S[AX] - 1 - h;
-    if (q[AX] > hi) { out[o] = (R)in[o]; return; }
-    int p[3] = {q[0], q[1], q[2]};
-    const int l = nb(q[AX], -1, g.S[AX], g.per[AX]), r = nb(q[AX], 1, g.S[AX], g.per[AX]);
-    TI vl = TI(0), vr = TI(0);
-    if (l >= 0 && l <= hi) { p[AX] = l; vl = in[o3(g, p[0], p[1], p[2])]; }
-    if (r >= 0 && r <= hi) { p[AX] = r; vr = in[o3(g, p[0], p[1], p[2])]; }
-    out[o] = (R)((TI)alpha * in[o] + (TI(1) - (TI)alpha) * TI(0.5) * (vl + vr));
 }
 
 __global__ void __launch_bounds__(NT) k3_zero3(G3 g, double* a, double* b, double* c)
@@ -1010,6 +1050,59 @@ __global__ void __launch_bounds__(64) k3_antenna(G3 g, F3<R> f, double* xm, cons
     xm[q] = x1;
 }
 
+// ---- charge density (Gauss diagnostic) ---------------------------------------------------------
+// rho on the nodes with the cubic shape of the gather and deposit, FP64 atomics
+__device__ __forceinline__ void rho3_add(const G3& g, double* rho, double qw, double x, double y, double z)
+{
+    const double r[3] = {x, y, z};
+    int j0[3];
+    double S[3][4];
+    for (int a = 0; a < 3; a++) {
+        j0[a] = (int)floor(r[a]);
+        bspline4<double>(r[a] - j0[a], S[a]);
+    }
+    for (int c = 0; c < 4; c++) {
+        const int k = sidx(g, 2, j0[2] - 1 + c);
+        if (k < 0) continue;
+        for (int b = 0; b < 4; b++) {
+            const int j = sidx(g, 1, j0[1] - 1 + b);
+            if (j < 0) continue;
+            for (int a = 0; a < 4; a++) {
+                const int i = sidx(g, 0, j0[0] - 1 + a);
+                if (i < 0) continue;
+                atomicAdd(&rho[o3(g, i, j, k)], qw * S[0][a] * S[1][b] * S[2][c]);
+            }
+        }
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NT) k3_rho(G3 g, E3<R> e, int ne, I3<R> ion, int ni, double zsh, const double* ant,
+                                             int na, int pol, double za, double aw, double vol_inv, double* rho)
+{
+    const long p = (long)blockIdx.x * NT + threadIdx.x;
+    if (p < ne) {
+        const double w = (double)e.w[p];
+        if (w != 0.0) rho3_add(g, rho, -w * vol_inv, e.x[p], e.y[p], e.z[p]);
+    } else if (p < (long)ne + ni) {
+        const long q = p - ne;
+        const double w = (double)ion.w[q];
+        if (w != 0.0) rho3_add(g, rho, w * vol_inv, ion.x[q], ion.y[q], ion.z0[q] - zsh);
+    } else if (p < (long)ne + ni + na) {
+        const long q = p - ne - ni;
+        const double xh = ant[na + q], yh = ant[2 * (long)na + q], m = ant[q];
+        rho3_add(g, rho, aw * vol_inv, xh, yh, za);
+        rho3_add(g, rho, -aw * vol_inv, pol == 0 ? m : xh, pol == 0 ? yh : m, za);
+    }
+}
+
+__global__ void __launch_bounds__(NT) k3_zero1(G3 g, double* a)
+{
+    int q[3];
+    if (!cell_of(g, q)) return;
+    a[o3(g, q[0], q[1], q[2])] = 0.0;
+}
+
 // SplitMix64 (Steele, Lea, Flood 2014): output number k of the generator started at seed
 __device__ __forceinline__ double u01(uint64_t seed, uint64_t k)
 {
@@ -1596,62 +1689,117 @@ void launch3_ampere(const G3& g, const F3<R>& f, const R* const J[3], const Pml3
     hipLaunchKernelGGL((k3_ampere<R>), cells_grid(g), cells_block(), 0, s, g, f, J[0], J[1], J[2], pml, (R)dt);
 }
 
-template <int AX, typename TI, typename R>
-void fpass(const G3& g, const TI* in, R* out, int h, R alpha, hipStream_t s)
+bool filter_seq(int npass, int comp, int stride_mask, FiltSeq* fs)
 {
-    hipLaunchKernelGGL((k3_fpass<AX, TI, R>), cells_grid(g), cells_block(), 0, s, g, in, out, h, alpha);
+    fs->n = 0;
+    fs->reach = 0;
+    if (npass <= 0) return true;
+    const int mask = stride_mask ? stride_mask : 1;
+    for (int st = 1; st <= 16; st++) {
+        if (!(mask & (1 << (st - 1)))) continue;
+        const int k = npass + (comp ? 1 : 0);
+        if (fs->n + k > FSEQ_MAX || fs->reach + k * st > FREACH_MAX) return false;
+        for (int p = 0; p < k; p++) {
+            fs->alpha[fs->n] = p < npass ? 0.5 : 0.5 * npass + 1.0;
+            fs->stride[fs->n] = st;
+            fs->n++;
+            fs->reach += st;
+        }
+    }
+    return true;
 }
 
-template <int AX, typename TI, typename R>
-void ffused(const G3& g, const TI* in, R* out, int h, int np, int npass, hipStream_t s)
+// one launch of k3_fline along AX for ncomp components
+template <int AX, typename TI, typename TO, typename T>
+void fline(const G3& g, const Lines3<TI, TO>& L, int ncomp, const FiltSeq& fs, hipStream_t s)
 {
-    hipLaunchKernelGGL((k3_ffused<AX, TI, R>), cells_grid(g), cells_block(), 0, s, g, in, out, h, np, npass,
-                       0.5 * npass + 1.0);
+    constexpr int BC = fline_bc<AX>();
+    constexpr size_t LDS_MAX = 144 * 1024;
+    const int S = g.S[AX];
+    int tseg;
+    if (AX == 0) tseg = S + 2 * fs.reach <= 1024 ? S : 512;
+    else tseg = std::min(S, sizeof(T) == 4 ? 128 : 64);
+    auto lds_of = [&](int t) {
+        const int A = t + 2 * fs.reach;
+        return 2 * (size_t)(AX == 0 ? BC * (A + 1) : A * (BC + 1)) * sizeof(T);
+    };
+    while (tseg > 16 && lds_of(tseg) > LDS_MAX) tseg /= 2;       // long reaches: shorter segments
+    const size_t lds = lds_of(tseg);
+    const int nseg = (S + tseg - 1) / tseg;
+    const int ncolb = AX == 0 ? (g.S[1] * g.S[2] + BC - 1) / BC : (g.S[0] + BC - 1) / BC;
+    const int nother = AX == 0 ? 1 : g.S[AX == 1 ? 2 : 1];
+    const long blocks = (long)ncomp * nseg * ncolb * nother;
+    (void)hipFuncSetAttribute((const void*)k3_fline<AX, TI, TO, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    hipLaunchKernelGGL((k3_fline<AX, TI, TO, T>), dim3((unsigned)blocks), dim3(NT), lds, s, g, L, fs, tseg, nseg,
+                       ncolb);
 }
 
 template <typename R>
-void launch3_filter(const G3& g, const F3<R>& f, int npass, int comp, const R* out[3], hipStream_t s)
+void launch3_filter(const G3& g, const F3<R>& f, const FiltSeq& fs, const R* out[3], hipStream_t s)
 {
-    const int np = npass + (comp ? 1 : 0);
-    if (np > 0 && np <= FH) {
-        // one launch per axis: Jf <- J (FP64), Jg <- Jf, Jf <- Jg
-        for (int c = 0; c < 3; c++) {
-            const int h[3] = {c == 0, c == 1, c == 2};
-            ffused<0>(g, (const double*)f.J[c], f.Jf[c], h[0], np, npass, s);
-            ffused<1>(g, (const R*)f.Jf[c], f.Jg[c], h[1], np, npass, s);
-            ffused<2>(g, (const R*)f.Jg[c], f.Jf[c], h[2], np, npass, s);
-            out[c] = f.Jf[c];
-        }
-        return;
-    }
+    Lines3<double, R> lx;
+    Lines3<R, R> ly, lz;
     for (int c = 0; c < 3; c++) {
-        const int h[3] = {c == 0, c == 1, c == 2};
-        const int np = npass + (comp ? 1 : 0);
-        R* cur = f.Jf[c];
-        R* oth = f.Jg[c];
-        bool first = true;
-        for (int ax = 0; ax < 3 && np > 0; ax++) {
-            for (int p = 0; p < np; p++) {
-                const R alpha = p < npass ? R(0.5) : (R)(0.5 * npass + 1.0);
-                if (first) {
-                    // the first pass reads the FP64 deposit
-                    if (ax == 0) fpass<0>(g, (const double*)f.J[c], cur, h[0], alpha, s);
-                    else if (ax == 1) fpass<1>(g, (const double*)f.J[c], cur, h[1], alpha, s);
-                    else fpass<2>(g, (const double*)f.J[c], cur, h[2], alpha, s);
-                    first = false;
-                    continue;
-                }
-                if (ax == 0) fpass<0>(g, (const R*)cur, oth, h[0], alpha, s);
-                else if (ax == 1) fpass<1>(g, (const R*)cur, oth, h[1], alpha, s);
-                else fpass<2>(g, (const R*)cur, oth, h[2], alpha, s);
-                R* t = cur;
-                cur = oth;
-                oth = t;
-            }
-        }
-        if (first) fpass<0>(g, (const double*)f.J[c], cur, 0, R(1), s);   // no filter: a copy in the run's type
-        out[c] = cur;
+        lx.in[c] = f.J[c];
+        lx.out[c] = f.Jf[c];
+        ly.in[c] = f.Jf[c];
+        ly.out[c] = f.Jg[c];
+        lz.in[c] = f.Jg[c];
+        lz.out[c] = f.Jf[c];
+        lx.h[c] = c == 0;
+        ly.h[c] = c == 1;
+        lz.h[c] = c == 2;
+        out[c] = f.Jf[c];
     }
+    fline<0, double, R, R>(g, lx, 3, fs, s);     // without passes: the copy into the run's type
+    if (fs.n == 0) return;
+    fline<1, R, R, R>(g, ly, 3, fs, s);
+    fline<2, R, R, R>(g, lz, 3, fs, s);
+}
+
+template <typename T>
+void launch_filter_xz(const G3& g, const T* const in[3], T* const tmp[3], T* const out[3], const int hx[3],
+                      const int hz[3], int ncomp, const FiltSeq& fs, hipStream_t s)
+{
+    Lines3<T, T> lx{}, lz{};
+    for (int c = 0; c < ncomp; c++) {
+        lx.in[c] = in[c];
+        lx.out[c] = fs.n ? tmp[c] : out[c];
+        lx.h[c] = hx[c];
+        lz.in[c] = tmp[c];
+        lz.out[c] = out[c];
+        lz.h[c] = hz[c];
+    }
+    fline<0, T, T, T>(g, lx, ncomp, fs, s);
+    if (fs.n) fline<2, T, T, T>(g, lz, ncomp, fs, s);
+}
+template void launch_filter_xz<float>(const G3&, const float* const*, float* const*, float* const*, const int*,
+                                      const int*, int, const FiltSeq&, hipStream_t);
+template void launch_filter_xz<double>(const G3&, const double* const*, double* const*, double* const*,
+                                       const int*, const int*, int, const FiltSeq&, hipStream_t);
+
+double* launch3_filter_nodal(const G3& g, double* a, double* b, double* c, const FiltSeq& fs, hipStream_t s)
+{
+    if (fs.n == 0) return a;
+    Lines3<double, double> l0{{a, nullptr, nullptr}, {b, nullptr, nullptr}, {0, 0, 0}};
+    Lines3<double, double> l1{{b, nullptr, nullptr}, {c, nullptr, nullptr}, {0, 0, 0}};
+    Lines3<double, double> l2{{c, nullptr, nullptr}, {b, nullptr, nullptr}, {0, 0, 0}};
+    fline<0, double, double, double>(g, l0, 1, fs, s);
+    fline<1, double, double, double>(g, l1, 1, fs, s);
+    fline<2, double, double, double>(g, l2, 1, fs, s);
+    return b;
+}
+
+template <typename R>
+void launch3_rho(const G3& g, const E3<R>& e, int ne, const I3<R>& ion, int ni, double zsh, const double* ant,
+                 int na, int pol, double za, double aw, double vol_inv, double* rho, hipStream_t s)
+{
+    hipLaunchKernelGGL(k3_zero1, cells_grid(g), cells_block(), 0, s, g, rho);
+    const long n = (long)ne + ni + na;
+    if (n > 0)
+        hipLaunchKernelGGL((k3_rho<R>), dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, g, e, ne, ion, ni, zsh,
+                           ant, na, pol, za, aw, vol_inv, rho);
 }
 
 template <typename R>
@@ -1762,8 +1910,10 @@ void launch3_stations(const G3& g, const F3<R>& f, const double* zlab, int nst, 
                                      hipStream_t);                                                          \
     template void launch3_ampere<R>(const G3&, const F3<R>&, const R* const*, const Pml3&, double,          \
                                     hipStream_t);                                                           \
-    template void launch3_filter<R>(const G3&, const F3<R>&, int, int, const R**, hipStream_t);             \
+    template void launch3_filter<R>(const G3&, const F3<R>&, const FiltSeq&, const R**, hipStream_t);        \
     template void launch3_zero_j<R>(const G3&, const F3<R>&, hipStream_t);                                  \
+    template void launch3_rho<R>(const G3&, const E3<R>&, int, const I3<R>&, int, double, const double*, int,   \
+                                 int, double, double, double, double*, hipStream_t);                       \
     template void launch3_count_live<R>(const R*, int, int*, hipStream_t);                                  \
     template void launch3_gpd<R>(const G3&, const F3<R>&, const E3<R>&, const Seg3*, const Box3*, Box3*, int,  \
                                  const Push3&, int, int*, int*, int2*, hipStream_t);                        \

@@ -203,3 +203,73 @@ def test_3d_full_size_faraday_and_sampled_electrons_match_oracle():
     for k in ("ux", "uy", "uz"):
         scale = max(np.abs(got[k]).max(), 1.0)
         assert np.abs(after[k][ia] - got[k][ib]).max() <= 1e-5 * scale, k
+
+
+# ---------------------------------------------------------------------------------------
+# diagnostics and options of the 3D path against the oracle
+# ---------------------------------------------------------------------------------------
+
+@gpu
+def test_3d_gauss_residual_matches_oracle_and_holds():
+    # div E - F[rho] with the deposit's shape and the step's filter (Sec. 4.2.2): the GPU's
+    # residual equals the oracle's, and the charge-conserving deposit keeps it constant
+    w = pi.small_boosted3(real="f64", nx=12, ny=10, nz=48, ppc=2)
+    sim, ref = _sim(w, sort_every=5), Oracle3.from_workload(w)
+    # scale: the charge density of one antenna sheet (the neutral pairs cancel at t = 0)
+    rho = ref.info()["antenna_weight"] / w["config"]["dx_um"] ** 3
+    g0 = sim.gauss_residual()
+    np.testing.assert_allclose(g0, ref.gauss_residual(), rtol=0, atol=1e-11 * rho)
+    sim.step(20)
+    ref.step(20)
+    assert ref.info()["shift"] > 5
+    g1, r1 = sim.gauss_residual(), ref.gauss_residual()
+    np.testing.assert_allclose(g1, r1, rtol=0, atol=1e-10 * rho)
+    P = 10      # nodes clear of the non-periodic edges by the shape and filter reach
+    inner = (slice(P + 10, P + 48 - 10), slice(P + 3, P + 10 - 3), slice(P + 3, P + 12 - 3))
+    assert np.abs(g1 - g0)[inner].max() <= 1e-11 * rho
+    assert np.abs(sim.field("Ez")).max() > 0
+
+
+@gpu
+def test_3d_gauss_fp32():
+    w = pi.small_boosted3(real="f32", nx=12, ny=10, nz=48, ppc=2)
+    ref = Oracle3.from_workload(pi.small_boosted3(real="f64", nx=12, ny=10, nz=48, ppc=2))
+    sim = _sim(w, sort_every=5)
+    g0 = sim.gauss_residual()
+    sim.step(24)
+    ref.step(24)
+    g1 = sim.gauss_residual()
+    rho = ref.info()["antenna_weight"] / w["config"]["dx_um"] ** 3
+    P = 10
+    inner = (slice(P + 10, P + 48 - 10), slice(P + 3, P + 10 - 3), slice(P + 3, P + 12 - 3))
+    assert np.abs(g1 - g0)[inner].max() <= 1e-5 * rho
+
+
+@gpu
+def test_3d_stations_and_energy_match_oracle():
+    w = pi.small_boosted3(real="f64", nx=12, ny=10, nz=48, ppc=2)
+    g, d = w["config"]["gamma_boost"], w["config"]["dz_um"]
+    zs = [g * 20 * d, g * 30 * d]
+    sim = _sim(w, stations=zs)
+    ref = Oracle3.from_workload(w, stations=zs)
+    sim.step(24)
+    ref.step(24)
+    for q in range(2):
+        a, b = sim.station(q), ref.station(q)
+        assert a.shape == b.shape and a.shape[0] > 5
+        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12 * max(np.abs(b).max(), 1))
+    np.testing.assert_allclose(sim.energy(), ref.energy(), rtol=1e-10)
+
+
+@gpu
+@pytest.mark.parametrize("real,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_3d_stride_filter_and_y_polarisation(real, tol):
+    w = pi.small_boosted3(real=real, nx=12, ny=10, nz=48, ppc=2)
+    w["config"]["filter_strides"] = 0b11                         # S(1:2)
+    w["laser"]["pol"] = 1
+    sim, ref = _sim(w, sort_every=7), Oracle3.from_workload(w)
+    sim.step(20)
+    ref.step(20)
+    assert np.abs(ref.field("Ey")).max() > np.abs(ref.field("Ex")).max()
+    compare_fields3(sim, ref, tol)
+    np.testing.assert_allclose(sim.antenna(), ref.antenna(), atol=1e-12)
