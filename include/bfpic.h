@@ -335,6 +335,17 @@ bf_status bf_lf_train_step(void* work, int64_t work_bytes, float* params, float*
                            float beta1, float beta2, float eps, int64_t step, float* grad_out,
                            double* loss_out, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+   loops, harnesses that forbid it): bf_lf_apply without a work buffer.  Same arguments and
+   results as bf_lf_apply; the packed BF16 weights go to a 64 KiB device array inside the
+   library (one per device, held until the process ends, its address looked up once per
+   device on the first call made with that device current).  Allocates nothing.  All calls on
+   one device share that array: calls that overlap on one device (other streams or host
+   threads) race.  BF_EINVAL: null pointer or bad sizes (as bf_lf_apply; the scratch need does
+   not grow with the images); BF_EDEVICE: the array's address could not be obtained. */
+bf_status bf_lf_apply_noalloc(const float* params, const float* in, float* out, int nimg, int ny, int nx,
+                              int periodic_x, int periodic_y, void* hip_stream);
+
 /* Host-side: the learned-filter parameters (n = BF_LF_PARAMS floats into host_params) that
    reproduce the n-pass bilinear filter with or without the compensation pass alpha_c = n/2 + 1
    of Sec. 4.1 (Eq. 3ptfilter) exactly: along each axis the composed stencil is cut into three

@@ -100,7 +100,7 @@ EXPORTS = ["bf_query_buffers", "bf_create", "bf_init_plasma", "bf_init_laser", "
            "bf_load_electrons", "bf_load_electrons3", "bf_step", "bf_diagnose", "bf_set_field", "bf_sync_status",
            "bf_get_state", "bf_set_state", "bf_status_string", "bf_last_error", "bf_destroy",
            "bf_set_learned_filter", "bf_lf_work_bytes", "bf_lf_apply", "bf_lf_train_step",
-           "bf_lf_bilinear_params",
+           "bf_lf_bilinear_params", "bf_lf_apply_noalloc",
            "bf_batch_work_bytes", "bf_batch_create", "bf_batch_step", "bf_batch_destroy"]
 FILTER_BILINEAR, FILTER_LEARNED = 0, 1
 LF_PARAMS = 7200
@@ -148,6 +148,7 @@ def lib(path: str = LIB_PATH):
                                    C.c_int, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float,
                                    C.c_int64, P, P, P]
     L.bf_lf_bilinear_params.argtypes = [C.c_int, C.c_int, F, C.c_int64]
+    L.bf_lf_apply_noalloc.argtypes = [P, P, P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P]
     L.bf_batch_work_bytes.argtypes = [C.c_int]
     L.bf_batch_work_bytes.restype = C.c_int64
     L.bf_batch_create.argtypes = [C.POINTER(P), C.c_int, P, C.c_int64, P, C.POINTER(P)]
@@ -490,6 +491,16 @@ class LearnedFilter:
         _ck(lib().bf_lf_apply(C.c_void_p(w.data_ptr()), w.numel(), C.c_void_p(self.params.data_ptr()),
                               C.c_void_p(images.data_ptr()), C.c_void_p(out.data_ptr()), nimg, ny, nx,
                               int(periodic[0]), int(periodic[1]), self._stream_ptr()))
+        return out
+
+    def apply_noalloc(self, images, out, periodic=(False, False)):
+        """The same as apply() through bf_lf_apply_noalloc: no work buffer, out supplied."""
+        self._check(images)
+        self._check(out)
+        nimg, ny, nx = images.shape
+        _ck(lib().bf_lf_apply_noalloc(C.c_void_p(self.params.data_ptr()), C.c_void_p(images.data_ptr()),
+                                      C.c_void_p(out.data_ptr()), nimg, ny, nx, int(periodic[0]),
+                                      int(periodic[1]), self._stream_ptr()))
         return out
 
     def train_step(self, images, targets, margin, lr, beta1=0.9, beta2=0.999, eps=1e-8,

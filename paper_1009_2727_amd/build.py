@@ -6,7 +6,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["bf_fields.hip", "bf_particles.hip", "bf_host.hip", "bf_lfilter.hip", "bf_sim3.hip"]
+SOURCES = ["bf_fields.hip", "bf_particles.hip", "bf_host.hip", "bf_lfilter.hip", "bf_sim3.hip",
+           "bf_lf_noalloc.hip"]
 LIB = os.path.join(HERE, "libbfpic.so")
 
 FLAGS = [
