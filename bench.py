@@ -1,22 +1,27 @@
 #!/usr/bin/env python
 """Throughput of the boosted-frame laser-wakefield PIC step on one MI355X.
 
-Workload (default): 2D boosted frame gamma = 13, 256 x 4096 cells, 16 macro-electrons per
-cell at 1e18 cm^-3 (lab) with rigid ions, window pre-loaded with plasma (steady state of the
-moving window), laser a0 = 2 w0 = 20 um through the lab-fixed antenna, CK2 solver with
-Friedman theta = 0.1, 4 bilinear passes + compensation, 10-cell PML on every face, moving
-window, FP32 fields/momenta with FP64 positions.  Inputs are synthetic and seeded.
+Headline workload (default): 3D boosted frame gamma = 30, 128 x 128 x 1024 cells of
+(1+beta) gamma lambda / 16, 8 macro-electrons per cell at 1e17 cm^-3 (lab) with rigid ions,
+window pre-loaded with plasma (134 M electrons + 134 M ions), laser a0 = 2 w0 = 50 um 30 fs
+through the lab-fixed antenna, CK2 solver with Friedman theta = 0.1, 4 bilinear passes +
+compensation, 10-cell PML on every face, moving window, FP32 fields/momenta with FP64
+positions and FP64 current sums.  Inputs are synthetic and seeded.
 
 One step = the whole PIC step of the library (Faraday, push, ions, antenna, filter, Ampere,
-window/injection, periodic tile sort).  Launch configuration: the library's default 26 x 8
-particle tile and a sort every 80 steps (the sort's amortised cost is inside the timed steps).
-Prints ONE JSON line with the metric, the roofline of
-the dominant kernel (gather/push/deposit, timed with HIP events on the library's stream) and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+window/injection, periodic tile sort).  The K timed steps are bracketed by HIP events on the
+library's stream; the tile sort runs every sort_every steps, so its cost is measured on a sort
+after the timed window (phase timers) and added as sort_ms / sort_every per step
+(ms_per_step and value include it; the raw window figure is reported beside it).
 
-Other workloads: --workload c3 (3D boosted frame gamma = 30, 128 x 128 x 1024, 8 ppc, 134 M
-electrons + 134 M rigid ions, window pre-loaded, 8 x 8 x 10 tiles), c4 (the batched scan),
-c5 (learned vs plain current filter).
+The JSON line also carries the 2D workload (gamma = 13, 256 x 4096, 16 ppc, 16.8 M electrons) as
+"c2", the roofline of the dominant kernel (gather/push/deposit, timed with HIP events on the
+library's stream, HBM bytes from rocprofv3 counters when they match the kernel's sources) and
+the FP64 CPU oracle timed on a bounded sample of the headline workload, on one host core and on
+all of them (at most 16).
+
+Other workloads: --workload c2 (the 2D run as the headline), c4 (the batched scan), c5
+(learned vs plain current filter).
 """
 from __future__ import annotations
 
@@ -35,18 +40,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
-PMC_FILE = os.path.join(ROOT, "profiles", "gpd_c2_pmc.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1009_2727_amd", "csrc", "bf_particles.hip")
+# counter summaries of the gather/push/deposit kernels: (file, kernel name, sources it is built from)
+PMC = {
+    "c2": (os.path.join(ROOT, "profiles", "gpd_c2_pmc.json"), "k_gpd",
+           ("bf_particles.hip", "bf_device.h", "bf_kernels.h")),
+    "c3": (os.path.join(ROOT, "profiles", "gpd3_c3_pmc.json"), "k3_gpd<",
+           ("bf_sim3.hip", "bf_device.h", "bf_kernels3.h")),
+}
 
 
-GPD_SOURCES = ("bf_particles.hip", "bf_device.h", "bf_kernels.h")
-
-
-def src_hash() -> str:
-    """Hash of the sources the gather/push/deposit kernel is compiled from: stored counter
-    totals are used only while it matches."""
+def src_hash(workload: str) -> str:
+    """Hash of the sources the workload's gather/push/deposit kernel is compiled from: stored
+    counter totals are used only while it matches."""
     h = hashlib.sha256()
-    for f in GPD_SOURCES:
+    for f in PMC[workload][2]:
         h.update(open(os.path.join(ROOT, "paper_1009_2727_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -77,36 +84,59 @@ def bytes_model3(ne: int, ni: int, nx: int, ny: int, nz: int, real: int = 4):
     return gpd, step
 
 
+def _oracle_rate(make, steps, threads):
+    """FP64 oracle electron pushes/s on a bounded sample: one untimed step, then `steps`."""
+    import oracle
+    oracle.set_threads(threads)
+    o = make()
+    o.step(1)
+    ne = o.num_particles(0)
+    t0 = time.perf_counter()
+    o.step(steps)
+    return ne * steps / (time.perf_counter() - t0), ne
+
+
+def cpu_baseline_of(make, steps, sample):
+    """The oracle as it stands on one host core and on all of them (at most 16)."""
+    import oracle
+    cores = oracle.host_threads()
+    v1, ne = _oracle_rate(make, steps, 1)
+    vn, _ = _oracle_rate(make, steps, cores) if cores > 1 else (v1, ne)
+    oracle.set_threads(1)
+    return {"value": vn, "unit": "electron pushes/s", "cores": cores, "kind": "oracle",
+            "sample": f"{sample} ({ne} electrons), {steps} steps after one untimed step, FP64",
+            "one_core": {"value": v1, "cores": 1}}
+
+
 def cpu_baseline3(args):
-    """FP64 3D oracle on a bounded sample: a 32 x 32 x 64 slab of the same physics (8 ppc,
-    pre-loaded, gamma = 30), a few steps, single thread."""
+    """FP64 3D oracle on a 32 x 32 x 64 slab of the headline physics (8 ppc, pre-loaded)."""
     import pic_inputs as pi
     from oracle.pic3 import Oracle3
-    w = pi.c3(real="f64", nx=32, ny=32, nz=64, ppc=8, preload=True)
-    o = Oracle3.from_workload(w)
-    ne = len(o.particles(0)["id"])
-    o.step(1)
-    t0 = time.perf_counter()
-    o.step(args.cpu_steps3)
-    dt = time.perf_counter() - t0
-    return {"value": ne * args.cpu_steps3 / dt, "unit": "electron pushes/s", "cores": 1, "kind": "oracle",
-            "sample": f"32x32x64 slab of the same 3D workload, 8 ppc pre-loaded ({ne} electrons), "
-                      f"{args.cpu_steps3} steps after one untimed step, FP64, single thread"}
+    return cpu_baseline_of(lambda: Oracle3.from_workload(pi.c3(real="f64", nx=32, ny=32, nz=64, ppc=8,
+                                                                 preload=True)),
+                           args.cpu_steps3, "32x32x64 slab of the 3D workload, 8 ppc pre-loaded")
 
 
-def bench_3d(args):
-    """The 3D boosted run (gamma = 30, 128 x 128 x 1024, 8 ppc, window pre-loaded) timed over
-    the whole step; the roofline is that of the 3D gather/push/deposit kernel."""
-    import torch
+def cpu_baseline2(args):
+    """FP64 oracle on a 256 x 256 slab of the 2D workload (16 ppc, pre-loaded)."""
     import pic_inputs as pi
+    from oracle import Oracle
+    return cpu_baseline_of(lambda: Oracle.from_workload(pi.c2(real="f64", nx=256, nz=256, ppc=16, preload=True)),
+                           args.cpu_steps, "256x256 slab of the 2D workload, 16 ppc pre-loaded")
+
+
+def timed_run(args, w, kernel_bytes, pmc_key, kernel_name):
+    """Warm-up, K timed steps (HIP events on the library's stream), then steps until a tile
+    sort has run, for its cost; returns the measurements of the K steps with the sort's cost
+    amortised over its cadence."""
+    import torch
     from paper_1009_2727_amd import Sim
-    w = pi.c3(real="f32", preload=True)
-    cfg = w["config"]
     sim = Sim.from_workload(w, sort_every=args.sort_every, timers=True)
     stream = sim.stream
     sim.step(args.warmup)
     torch.cuda.synchronize()
     c0 = sim.counts()
+    since0 = sim.get_state().since_sort
     sim.timers(reset=True)
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
@@ -119,52 +149,83 @@ def bench_3d(args):
     status = sim.sync_status()
     c1 = sim.counts()
     timers = sim.timers(reset=True)
+    info = sim.info()
+    every = info["sort_every"]
+    in_window = (since0 + args.steps) // every        # scheduled sorts inside the timed steps
+    # the tile sort's cost: step on (untimed) to the next scheduled sort; the sort phase of that
+    # step less the phase's empty bracket (the mean of the steps without a sort)
+    sort_each = 0.0
+    if not args.no_sort_cost:
+        idle = []
+        for _ in range(every + 1):
+            sim.step(1)
+            tm = sim.timers(reset=True)
+            if sim.get_state().since_sort == 0:
+                sort_each = tm["sort"][0] - (float(np.mean(idle)) if idle else 0.0)
+                break
+            idle.append(tm["sort"][0])
+    ms_amort = ms + sort_each * (args.steps / every - in_window)
     ne = 0.5 * (c0[0] + c1[0])
     ni = 0.5 * (c0[1] + c1[1])
-    ms_step = ms / args.steps
-    gpd_bytes, step_bytes = bytes_model3(int(ne), int(ni), cfg["nx"], cfg["ny"], cfg["nz"])
     push_ms, push_n = timers["push"]
     gpd_ms = push_ms / max(push_n, 1)
+    gpd_bytes, step_bytes = kernel_bytes(int(ne), int(ni))
     achieved = gpd_bytes / (gpd_ms / 1e3) / 1e9
-    out = {
-        "metric": "particle pushes/s",
-        "value": ne * args.steps / (ms / 1e3),
-        "unit": "electron pushes/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": w["name"], "grid": f"{cfg['nx']}x{cfg['ny']}x{cfg['nz']}", "ppc": 8,
-                   "gamma_boost": cfg["gamma_boost"], "electrons": int(ne), "rigid_ions": int(ni),
-                   "positions": "f64", "current_accumulation": "f64", "compact_every": sim.info()["sort_every"],
-                   "status": status},
-        "hbm_gbps_per_step": step_bytes / (ms_step / 1e3) / 1e9,
+    pmc = read_pmc(pmc_key)
+    del sim
+    torch.cuda.empty_cache()
+    return {
+        "value": ne * args.steps / (ms_amort / 1e3), "ms_per_step": ms_amort / args.steps,
+        "window_ms_per_step": ms / args.steps, "sort_ms": sort_each, "sort_every": every,
+        "sorts_in_window": int(in_window), "electrons": int(ne), "rigid_ions": int(ni), "status": status,
+        "hbm_gbps_per_step": step_bytes / (ms_amort / args.steps / 1e3) / 1e9,
         "phases_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in timers.items()},
-        "roofline": {"bound": "hbm", "kernel": "k3_gpd (gather + push + deposit)", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": gpd_bytes, "avg_launch_ms": gpd_ms,
-                     "limiter": "LDS: 8-byte current adds and gather reads, with bank conflicts "
-                                "(rocprofv3 counters in profiles/)"},
+        "roofline": {"bound": "hbm", "kernel": kernel_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": pmc["traffic_bytes_per_launch"] if pmc else None,
+                     "algorithmic_bytes_per_launch": gpd_bytes, "avg_launch_ms": gpd_ms},
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline3(args)
-    return out
 
 
-def cpu_baseline(args):
-    """FP64 oracle on a bounded sample of the workload: a 256 x 256 slab of the same
-    physics (16 ppc, pre-loaded), a few steps, single thread."""
+def _line(args, w, r, grid, ppc, extra_cfg):
+    cfg = w["config"]
+    return {
+        "metric": "particle pushes/s", "value": r["value"], "unit": "electron pushes/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": dict({"workload": w["name"], "grid": grid, "ppc": ppc, "gamma_boost": cfg["gamma_boost"],
+                        "electrons": r["electrons"], "rigid_ions": r["rigid_ions"], "positions": "f64",
+                        "sort_every": r["sort_every"], "status": r["status"]}, **extra_cfg),
+        "window_ms_per_step": r["window_ms_per_step"], "sort_ms": r["sort_ms"],
+        "sorts_in_window": r["sorts_in_window"],
+        "hbm_gbps_per_step": r["hbm_gbps_per_step"], "phases_ms_per_step": r["phases_ms_per_step"],
+        "roofline": r["roofline"],
+    }
+
+
+def bench_3d(args):
+    """The headline: 3D boosted run (gamma = 30, 128 x 128 x 1024, 8 ppc, window pre-loaded)."""
     import pic_inputs as pi
-    from oracle import Oracle
-    w = pi.c2(real="f64", nx=256, nz=256, ppc=16, preload=True)
-    o = Oracle.from_workload(w)
-    ne = o.num_particles(0)
-    o.step(1)       # first step outside the timing (allocations)
-    t0 = time.perf_counter()
-    o.step(args.cpu_steps)
-    dt = time.perf_counter() - t0
-    return {"value": ne * args.cpu_steps / dt, "unit": "particle pushes/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"256x256 slab of the same workload, 16 ppc pre-loaded ({ne} electrons), "
-                      f"{args.cpu_steps} steps after one untimed step, FP64, single thread"}
+    w = pi.c3(real="f32", preload=True)
+    cfg = w["config"]
+    r = timed_run(args, w, lambda ne, ni: bytes_model3(ne, ni, cfg["nx"], cfg["ny"], cfg["nz"]), "c3",
+                  "k3_gpd (gather + push + deposit)")
+    r["roofline"]["limiter"] = ("LDS: 8-byte fixed-point current adds and gather reads, with bank "
+                                "conflicts (rocprofv3 counters in profiles/)")
+    return _line(args, w, r, f"{cfg['nx']}x{cfg['ny']}x{cfg['nz']}", 8, {"current_accumulation": "f64"})
+
+
+def bench_2d(args, learned=True):
+    """The 2D boosted run (gamma = 13, 256 x 4096, 16 ppc, window pre-loaded)."""
+    import pic_inputs as pi
+    w = pi.c2(real="f32", preload=True)
+    cfg = w["config"]
+    r = timed_run(args, w, lambda ne, ni: bytes_model(ne, ni, cfg["nx"], cfg["nz"]), "c2",
+                  "k_gpd (gather + push + deposit)")
+    out = _line(args, w, r, f"{cfg['nx']}x{cfg['nz']}", 16, {})
+    if learned:
+        out["learned_filter"] = learned_filter_leg(args, w, r["phases_ms_per_step"]["filter"])
+    return out
 
 
 def learned_filter_leg(args, w, plain_filter_ms):
@@ -337,22 +398,24 @@ def bench_learned_filter_study(args):
     }
 
 
-def read_pmc():
-    if not os.path.exists(PMC_FILE):
+def read_pmc(workload: str):
+    path = PMC[workload][0]
+    if not os.path.exists(path):
         return None
     try:
-        d = json.load(open(PMC_FILE))
+        d = json.load(open(path))
     except Exception:
         return None
-    if d.get("source_hash") != src_hash():
+    if d.get("source_hash") != src_hash(workload):
         return None          # kernels changed since the counters were taken
     return d
 
 
-def summarize_pmc(fetch_dir: str, write_dir: str, copy_bytes: int, out: str):
+def summarize_pmc(fetch_dir: str, write_dir: str, copy_bytes: int, workload: str):
     """Reduces two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) to per-launch HBM bytes
-    of the gather/push/deposit kernel, scaled by what the counters read for a plain device
-    copy of copy_bytes in the same process."""
+    of the workload's gather/push/deposit kernel, scaled by what the counters read for a plain
+    device copy of copy_bytes in the same process."""
+    out, kname = PMC[workload][0], PMC[workload][1]
     import csv
 
     def load(d, counter):
@@ -367,15 +430,16 @@ def summarize_pmc(fetch_dir: str, write_dir: str, copy_bytes: int, out: str):
     res = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = load(d, counter)
-        gpd = [v for k, v in rows if "k_gpd" in k]
+        gpd = [v for k, v in rows if kname in k]
         copies = [v for k, v in rows if ("copy" in k.lower() or "elementwise" in k.lower()) and v > 0]
         if not gpd or not copies:
-            raise SystemExit(f"no {counter} rows for k_gpd / copy in {d}")
+            raise SystemExit(f"no {counter} rows for {kname} / copy in {d}")
         cal = max(copies) * 1024.0 / copy_bytes     # counter KiB vs true bytes
         res[counter] = {"gpd_kib_per_launch": sum(gpd) / len(gpd), "copy_kib": max(copies),
                         "calibration": cal,
                         "gpd_bytes_per_launch": sum(gpd) / len(gpd) * 1024.0 / cal}
-    res["source_hash"] = src_hash()
+    res["source_hash"] = src_hash(workload)
+    res["kernel"] = kname
     res["traffic_bytes_per_launch"] = (res["FETCH_SIZE"]["gpd_bytes_per_launch"]
                                        + res["WRITE_SIZE"]["gpd_bytes_per_launch"])
     json.dump(res, open(out, "w"), indent=1)
@@ -385,21 +449,24 @@ def summarize_pmc(fetch_dir: str, write_dir: str, copy_bytes: int, out: str):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--sort-every", type=int, default=80,
                     help="steps between particle sorts (the particle order lasts: the plasma drifts rigidly)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned-filter", action="store_true",
-                    help="skip the second run with the learned (MFMA) current filter")
+                    help="skip the 2D run with the learned (MFMA) current filter")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 2D workload beside the 3D headline")
+    ap.add_argument("--no-sort-cost", action="store_true",
+                    help="skip stepping on to a tile sort after the timed window (counter runs)")
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
-    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_GIB"))
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
-                    help="c2: the 256x4096 boosted run (default); c3: the 3D 128x128x1024 boosted run; "
-                         "c4: the batched scan of independent boosted runs (persistent batched launch "
-                         "vs one run at a time); c5: learned vs plain current filter")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("WORKLOAD", "FETCH_DIR", "WRITE_DIR", "COPY_GIB"))
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5"], default="c3",
+                    help="c3: the 3D 128x128x1024 boosted run (default, with c2 beside it); c2: the 256x4096 "
+                         "boosted run; c4: the batched scan of independent boosted runs (persistent batched "
+                         "launch vs one run at a time); c5: learned vs plain current filter")
     ap.add_argument("--cpu-steps3", type=int, default=8)
     ap.add_argument("--c4-runs", type=int, default=64)
     ap.add_argument("--c4-scale", type=float, default=1.0, help="grid scale of the scan's runs")
@@ -408,8 +475,8 @@ def main():
     args = ap.parse_args()
 
     if args.summarize_pmc:
-        f, wdir, gib = args.summarize_pmc
-        summarize_pmc(f, wdir, int(float(gib) * 2 ** 30), PMC_FILE)
+        wl, f, wdir, gib = args.summarize_pmc
+        summarize_pmc(f, wdir, int(float(gib) * 2 ** 30), wl)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -420,14 +487,9 @@ def main():
         sys.exit(2)
 
     import torch
-    import pic_inputs as pi
-    from paper_1009_2727_amd import Sim
 
     if args.workload == "c4":
         print(json.dumps(bench_scan(args)), flush=True)
-        return
-    if args.workload == "c3":
-        print(json.dumps(bench_3d(args)), flush=True)
         return
     if args.workload == "c5":
         print(json.dumps(bench_learned_filter_study(args)), flush=True)
@@ -441,66 +503,18 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    w = pi.c2(real="f32", preload=True)
-    cfg = w["config"]
-    sim = Sim.from_workload(w, sort_every=args.sort_every, timers=True)
-    stream = sim.stream
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-    c0 = sim.counts()
-    sim.timers(reset=True)
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    sim.step(args.steps)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    ms = t_start.elapsed_time(t_end)
-    status = sim.sync_status()
-    c1 = sim.counts()
-    timers = sim.timers(reset=True)
-    ne = 0.5 * (c0[0] + c1[0])
-    ni = 0.5 * (c0[1] + c1[1])
-    ms_step = ms / args.steps
-    value = ne * args.steps / (ms / 1e3)
-    gpd_bytes, step_bytes = bytes_model(int(ne), int(ni), cfg["nx"], cfg["nz"])
-    push_ms, push_n = timers["push"]
-    gpd_ms = push_ms / max(push_n, 1)
-    achieved = gpd_bytes / (gpd_ms / 1e3) / 1e9
-    pmc = read_pmc()
-    traffic = pmc["traffic_bytes_per_launch"] if pmc else None
+    if args.workload == "c2":
+        out = bench_2d(args, learned=not args.no_learned_filter)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline2(args)
+        print(json.dumps(out), flush=True)
+        return
 
-    out = {
-        "metric": "particle pushes/s",
-        "value": value,
-        "unit": "electron pushes/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": w["name"], "grid": f"{cfg['nx']}x{cfg['nz']}", "ppc": 16,
-                   "gamma_boost": cfg["gamma_boost"], "electrons": int(ne), "rigid_ions": int(ni),
-                   "positions": "f64", "sort_every": sim.info()["sort_every"],
-                   "status": status},
-        "hbm_gbps_per_step": step_bytes / (ms_step / 1e3) / 1e9,
-        "phases_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in timers.items()},
-        "roofline": {"bound": "hbm", "kernel": "k_gpd (gather + push + deposit)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": gpd_bytes, "avg_launch_ms": gpd_ms},
-    }
-    if not args.no_learned_filter:
-        del sim
-        torch.cuda.empty_cache()
-        out["learned_filter"] = learned_filter_leg(args, w, timers["filter"][0] / max(args.steps, 1))
+    out = bench_3d(args)
+    if not args.no_c2:
+        out["c2"] = bench_2d(args, learned=not args.no_learned_filter)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args)
+        out["cpu_baseline"] = cpu_baseline3(args)
     print(json.dumps(out), flush=True)
 
 

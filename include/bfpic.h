@@ -204,7 +204,7 @@ enum {
 
 /* phases of one bf_step (BF_DIAG_TIMERS rows) */
 enum {
-    BF_PHASE_FARADAY = 0,  /* Faraday + Friedman + PML, stations                            */
+    BF_PHASE_FARADAY = 0,  /* Faraday + Friedman + PML, stations, clearing the current      */
     BF_PHASE_PUSH,         /* electrons: gather, push, deposit                              */
     BF_PHASE_IONS,         /* rigid-ion current                                             */
     BF_PHASE_ANTENNA,      /* laser antenna current                                         */

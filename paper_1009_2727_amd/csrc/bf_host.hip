@@ -1151,6 +1151,7 @@ bf_status step3(bf_sim* s, int nsteps)
         bf3::launch3_faraday<R>(g, f, pml, ck, s->theta, s->dt, s->stream);
         bf3::launch3_stations<R>(g, f, w3<double>(s, L.w_st_z), s->nst, s->gamma, s->beta, s->t, (double)s->shift,
                                  w3<double>(s, L.w_st_rec), w3<int>(s, L.w_st_cnt), L.stcap, s->stream);
+        bf3::launch3_zero_j<R>(g, f, s->stream);        // the current of this step starts at zero
         s->tock(ev, BF_PHASE_FARADAY);
         // the window shift at the end of this step (particles are rebased in the push)
         const double t1 = (double)(s->step + 1) * s->dt;
@@ -1165,7 +1166,6 @@ bf_status step3(bf_sim* s, int nsteps)
         }
         pp.shift = (double)dsh;
         ev = s->tick();
-        bf3::launch3_zero_j<R>(g, f, s->stream);
         bf3::launch3_gpd<R>(g, f, electrons3<R>(s, L.p_cur), seg3<R>(s, 0), box3(s, 0, L.bb_cur),
                             box3(s, 0, 1 - L.bb_cur), L.nseg, pp, L.pz, w3<int>(s, L.w_status), w3<int>(s, L.w_lists),
                             w3<int2>(s, L.w_mis), s->stream);

@@ -7,9 +7,10 @@ physical scale of the field group (E, B: the emitted laser amplitude; J: the pla
 antenna-sheet current density), the measure of the other parity tests.
 
   * 64 x 512 lab-frame run (Yee, 4 ppc at 1e19 cm^-3, a0 = 1, one bilinear pass), 200 steps.
-    FP64 GPU: relative L2 <= 1e-12 on every component but the wake field E_z, <= 1e-10 on E_z
-    (the a0 = 1 electron motion amplifies the summation-order round-off of the deposit; E_z is
-    the smallest field, a second-order one), positions <= 1e-10 cells.  FP32 GPU: relative L2
+    FP64 GPU: relative L2 <= 1e-12 on the laser field and the transverse current, <= 1e-10 on
+    the wake field E_z and the longitudinal current J_z (second order in a0, the smallest
+    fields: the a0 = 1 electron motion amplifies the summation-order round-off of the deposit
+    there), positions <= 1e-10 cells.  FP32 GPU: relative L2
     <= 1e-5 on every component but E_z, <= 5e-5 on E_z (the wake is driven by the slow part
     of u_z, which the FP32 storage of the momenta rounds every step), and <= 1e-5 of the
     field-group scale everywhere; Gauss drift within the FP32 rounding of E.
@@ -120,8 +121,9 @@ def test_lab_64x512_200_steps_fp64_and_fp32():
                               "fp32_gauss_drift_over_max_rho": drift / rho,
                               "fp32_gauss_drift_over_E_rounding": drift / escale}
     _say(json.dumps(_LOG["lab_64x512_200"]))
-    assert max(v for n, v in e64.items() if n != "Ez") <= 1e-12, e64
-    assert e64["Ez"] <= 1e-10, e64
+    second = ("Ez", "Jz")          # the wake field and the longitudinal current: second order in a0
+    assert max(v for n, v in e64.items() if n not in second) <= 1e-12, e64
+    assert max(e64[n] for n in second) <= 1e-10, e64
     assert dx64 <= 1e-10
     assert max(v for n, v in e32.items() if n != "Ez") <= 1e-5, e32
     assert e32["Ez"] <= 5e-5, e32
