@@ -45,7 +45,8 @@ class _Cfg(C.Structure):
                 ("ck_alpha", C.c_double), ("ck_beta", C.c_double), ("ck_gamma", C.c_double),
                 ("theta", C.c_double), ("cfl_fraction", C.c_double), ("filter_npass", C.c_int),
                 ("filter_compensate", C.c_int), ("gamma_boost", C.c_double),
-                ("moving_window", C.c_int), ("seed", C.c_uint64), ("filter_strides", C.c_int)]
+                ("moving_window", C.c_int), ("seed", C.c_uint64), ("filter_strides", C.c_int),
+                ("gather_kind", C.c_int), ("pusher", C.c_int)]
 
 
 class _Plasma(C.Structure):
@@ -111,6 +112,7 @@ def lib():
         _lib.orc_shape3.restype = C.c_double
         _lib.orc_shape3.argtypes = [C.c_double]
         _lib.orc_boris.argtypes = [C.c_double, C.c_double, D, D, D]
+        _lib.orc_vay.argtypes = [C.c_double, C.c_double, D, D, D]
         _lib.orc_gather_at.argtypes = [P, C.c_double, C.c_double, D]
         _lib.orc_deposit_one.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_double,
                                          C.c_double, C.c_double, C.c_double]
@@ -134,7 +136,7 @@ class Oracle:
 
     def __init__(self, config: dict):
         L = lib()
-        c = _Cfg(**{k: config.get(k, 1) if k == "filter_strides" else config[k] for k, _ in _Cfg._fields_})
+        c = _Cfg(**{k: config.get(k, {"filter_strides": 1, "gather_kind": 0, "pusher": 0}[k]) if k in ("filter_strides", "gather_kind", "pusher") else config[k] for k, _ in _Cfg._fields_})
         self._h = L.orc_create(C.byref(c))
         if not self._h:
             raise ValueError("oracle rejected the configuration")
@@ -277,6 +279,14 @@ def boris(qm, dt, E, B, u):
     B = np.ascontiguousarray(B, dtype=np.float64)
     u = np.array(u, dtype=np.float64)
     lib().orc_boris(qm, dt, _dp(E), _dp(B), _dp(u))
+    return u
+
+
+def vay(qm, dt, E, B, u):
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    u = np.array(u, dtype=np.float64)
+    lib().orc_vay(qm, dt, _dp(E), _dp(B), _dp(u))
     return u
 
 

@@ -576,17 +576,104 @@ static double gather(const orc_sim* s, const double* F, int hx, int hz, double x
     return sum;
 }
 
-void orc_gather_at(const orc_sim* s, double x, double z, double out[6])
+/* stagger of each gathered component (Ex, Ey, Ez, Bx, By, Bz) on the Yee mesh, 2D (x, z) */
+static const int STAG2[6][2] = {{1, 0}, {0, 0}, {0, 1}, {0, 1}, {1, 1}, {1, 0}};
+
+/* value of F at stored (i, k), 0 beyond the stored range on a non-periodic axis */
+static double at2(const orc_sim* s, const double* F, long i, long k)
 {
-    /* the gather of the particle stage at one position (um, interior-relative): E^n and
-       B^n = (B^{n-1/2} + B^{n+1/2}) / 2, each component from its own staggered location */
-    double xc = x / s->ax.d, zc = z / s->az.d;
-    out[0] = gather(s, s->f[ORC_EX], 1, 0, xc, zc);
-    out[1] = gather(s, s->f[ORC_EY], 0, 0, xc, zc);
-    out[2] = gather(s, s->f[ORC_EZ], 0, 1, xc, zc);
-    out[3] = 0.5 * (gather(s, s->f[ORC_BXO], 0, 1, xc, zc) + gather(s, s->f[ORC_BX], 0, 1, xc, zc));
-    out[4] = 0.5 * (gather(s, s->f[ORC_BYO], 1, 1, xc, zc) + gather(s, s->f[ORC_BY], 1, 1, xc, zc));
-    out[5] = 0.5 * (gather(s, s->f[ORC_BZO], 1, 0, xc, zc) + gather(s, s->f[ORC_BZ], 1, 0, xc, zc));
+    return (i < 0 || k < 0) ? 0.0 : F[ID(s, i, k)];
+}
+
+/* Momentum-conserving gather, first step (Sec. 5.3): every component interpolated to the
+   nodes, the mean of its values at the two (or four) Yee locations around the node along
+   its staggered axes.  E^n and B^n = (B^{n-1/2} + B^{n+1/2}) / 2 into G[0..5] (n values each). */
+static void node_fields(orc_sim* s, double* G[6])
+{
+    const double* src[6] = {s->f[ORC_EX], s->f[ORC_EY], s->f[ORC_EZ], s->f[ORC_BX], s->f[ORC_BY], s->f[ORC_BZ]};
+    const double* old[6] = {NULL, NULL, NULL, s->f[ORC_BXO], s->f[ORC_BYO], s->f[ORC_BZO]};
+    for (int c = 0; c < 6; c++)
+        for (long k = 0; k < s->az.S; k++)
+            for (long i = 0; i < s->ax.S; i++) {
+                long il = STAG2[c][0] ? snb(&s->ax, i, -1) : i;
+                long kl = STAG2[c][1] ? snb(&s->az, k, -1) : k;
+                long is[2] = {il, i}, ks[2] = {kl, k};
+                double sum = 0.0;
+                int n = 0;
+                for (int a = 0; a < (STAG2[c][0] ? 2 : 1); a++)
+                    for (int b = 0; b < (STAG2[c][1] ? 2 : 1); b++) {
+                        long ii = STAG2[c][0] ? is[a] : i, kk = STAG2[c][1] ? ks[b] : k;
+                        double v = at2(s, src[c], ii, kk);
+                        if (old[c]) v = 0.5 * (v + at2(s, old[c], ii, kk));
+                        sum += v;
+                        n++;
+                    }
+                G[c][ID(s, i, k)] = sum / (double)n;
+            }
+}
+
+/* E^n, B^n at (xc, zc) (cells): from the staggered locations, or from the node values G */
+static void gather_fields(const orc_sim* s, double* const G[6], double xc, double zc, double E[3], double B[3])
+{
+    if (G) {
+        for (int c = 0; c < 3; c++) {
+            E[c] = gather(s, G[c], 0, 0, xc, zc);
+            B[c] = gather(s, G[3 + c], 0, 0, xc, zc);
+        }
+        return;
+    }
+    E[0] = gather(s, s->f[ORC_EX], 1, 0, xc, zc);
+    E[1] = gather(s, s->f[ORC_EY], 0, 0, xc, zc);
+    E[2] = gather(s, s->f[ORC_EZ], 0, 1, xc, zc);
+    /* B^n = (B^{n-1/2} + B^{n+1/2}) / 2 */
+    B[0] = 0.5 * (gather(s, s->f[ORC_BXO], 0, 1, xc, zc) + gather(s, s->f[ORC_BX], 0, 1, xc, zc));
+    B[1] = 0.5 * (gather(s, s->f[ORC_BYO], 1, 1, xc, zc) + gather(s, s->f[ORC_BY], 1, 1, xc, zc));
+    B[2] = 0.5 * (gather(s, s->f[ORC_BZO], 1, 0, xc, zc) + gather(s, s->f[ORC_BZ], 1, 0, xc, zc));
+}
+
+void orc_gather_at(const orc_sim* s_, double x, double z, double out[6])
+{
+    /* the gather of the particle stage at one position (um, interior-relative) */
+    orc_sim* s = (orc_sim*)s_;
+    const long n = (long)s->ax.S * s->az.S;
+    double* G[6] = {NULL};
+    int mc = s->cfg.gather_kind == 1;
+    if (mc) {
+        for (int c = 0; c < 6; c++) G[c] = (double*)malloc(n * sizeof(double));
+        node_fields(s, G);
+    }
+    gather_fields(s, mc ? G : NULL, x / s->ax.d, z / s->az.d, out, out + 3);
+    if (mc) for (int c = 0; c < 6; c++) free(G[c]);
+}
+
+/* Vay's pusher (Phys. Plasmas 15, 056701, 2008), from u^{n-1/2} to u^{n+1/2}:
+     u' = u + (q dt/m) (E + v x B / 2),  v = u / gamma(u),
+     tau = (q dt / 2m) B,  u* = u'.tau,  sigma = gamma'^2 - tau^2,
+     gamma_new^2 = (sigma + sqrt(sigma^2 + 4 (tau^2 + u*^2))) / 2,
+     t = tau / gamma_new,  s = 1 / (1 + t^2),
+     u_new = s (u' + (u'.t) t + u' x t).
+   A particle moving at the drift velocity of crossed fields (E + v x B = 0) keeps its
+   momentum exactly. */
+void orc_vay(double qm, double dt, const double E[3], const double B[3], double u[3])
+{
+    double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    double v[3] = {u[0] / g, u[1] / g, u[2] / g};
+    double h = 0.5 * qm * dt;
+    double up[3] = {u[0] + qm * dt * E[0] + h * (v[1] * B[2] - v[2] * B[1]),
+                    u[1] + qm * dt * E[1] + h * (v[2] * B[0] - v[0] * B[2]),
+                    u[2] + qm * dt * E[2] + h * (v[0] * B[1] - v[1] * B[0])};
+    double tau[3] = {h * B[0], h * B[1], h * B[2]};
+    double ustar = up[0] * tau[0] + up[1] * tau[1] + up[2] * tau[2];
+    double tau2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
+    double gp2 = 1.0 + up[0] * up[0] + up[1] * up[1] + up[2] * up[2];
+    double sigma = gp2 - tau2;
+    double gn = sqrt(0.5 * (sigma + sqrt(sigma * sigma + 4.0 * (tau2 + ustar * ustar))));
+    double t[3] = {tau[0] / gn, tau[1] / gn, tau[2] / gn};
+    double sf = 1.0 / (1.0 + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    double ut = up[0] * t[0] + up[1] * t[1] + up[2] * t[2];
+    u[0] = sf * (up[0] + ut * t[0] + (up[1] * t[2] - up[2] * t[1]));
+    u[1] = sf * (up[1] + ut * t[1] + (up[2] * t[0] - up[0] * t[2]));
+    u[2] = sf * (up[2] + ut * t[2] + (up[0] * t[1] - up[1] * t[0]));
 }
 
 void orc_boris(double qm, double dt, const double E[3], const double B[3], double u[3])
@@ -691,9 +778,6 @@ void orc_stage_particles(orc_sim* s)
 {
     const double dx = s->ax.d, dz = s->az.d, dt = s->dt;
     const double Lx = s->ax.N * dx, Lz = s->az.N * dz;
-    double *Ex = FLD(s, ORC_EX), *Ey = FLD(s, ORC_EY), *Ez = FLD(s, ORC_EZ);
-    double *Bx = FLD(s, ORC_BX), *By = FLD(s, ORC_BY), *Bz = FLD(s, ORC_BZ);
-    double *Bxo = FLD(s, ORC_BXO), *Byo = FLD(s, ORC_BYO), *Bzo = FLD(s, ORC_BZO);
     const long n = (long)s->ax.S * s->az.S;
     memset(FLD(s, ORC_JX), 0, n * sizeof(double));
     memset(FLD(s, ORC_JY), 0, n * sizeof(double));
@@ -706,6 +790,12 @@ void orc_stage_particles(orc_sim* s)
     double* priv = (double*)calloc((size_t)nt * 3 * n, sizeof(double));
     double* nxz = (double*)malloc((size_t)(s->ne > 0 ? s->ne : 1) * 5 * sizeof(double));
     long keep = 0;
+    const int mc = s->cfg.gather_kind == 1;
+    double* G[6] = {NULL};
+    if (mc) {
+        for (int c = 0; c < 6; c++) G[c] = (double*)malloc(n * sizeof(double));
+        node_fields(s, G);
+    }
 #pragma omp parallel for schedule(static) num_threads(nt)
     for (long p = 0; p < s->ne; p++) {
         int th = 0;
@@ -714,13 +804,11 @@ void orc_stage_particles(orc_sim* s)
 #endif
         double* Jt = priv + (size_t)th * 3 * n;
         double xc = s->ex[p] / dx, zc = s->ez[p] / dz;
-        double E[3] = {gather(s, Ex, 1, 0, xc, zc), gather(s, Ey, 0, 0, xc, zc), gather(s, Ez, 0, 1, xc, zc)};
-        /* B^n = (B^{n-1/2} + B^{n+1/2}) / 2 */
-        double B[3] = {0.5 * (gather(s, Bxo, 0, 1, xc, zc) + gather(s, Bx, 0, 1, xc, zc)),
-                       0.5 * (gather(s, Byo, 1, 1, xc, zc) + gather(s, By, 1, 1, xc, zc)),
-                       0.5 * (gather(s, Bzo, 1, 0, xc, zc) + gather(s, Bz, 1, 0, xc, zc))};
+        double E[3], B[3];
+        gather_fields(s, mc ? G : NULL, xc, zc, E, B);
         double u[3] = {s->eux[p], s->euy[p], s->euz[p]};
-        orc_boris(-1.0, dt, E, B, u);
+        if (s->cfg.pusher == 1) orc_vay(-1.0, dt, E, B, u);
+        else orc_boris(-1.0, dt, E, B, u);
         double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
         double x1 = s->ex[p] + dt * u[0] / g, z1 = s->ez[p] + dt * u[2] / g;
         deposit_into(s, Jt, Jt + n, Jt + 2 * n, -1.0, s->ew[p], s->ex[p], s->ez[p], x1, z1, u[1] / g);
@@ -741,6 +829,7 @@ void orc_stage_particles(orc_sim* s)
     }
     s->ne = keep;
     free(nxz);
+    if (mc) for (int c = 0; c < 6; c++) free(G[c]);
 
     /* rigid ions: z(t) = z0 - beta c t in the boosted frame, deposit only */
     if (s->plasma.ion_mode == 1) {

@@ -38,6 +38,10 @@ typedef struct {
     int filter_strides;       /* bit s-1 set: the n passes (+ compensation) are applied
                                  with stride s (Eq. 3ptfilter_stride), strides ascending;
                                  0 is the same as 1 (stride 1 only)                        */
+    int gather_kind;          /* 0: energy conserving, each component from its own Yee
+                                 location; 1: momentum conserving, the fields interpolated
+                                 to the nodes first (Sec. 5.3)                              */
+    int pusher;               /* 0: Boris; 1: Vay (Phys. Plasmas 15, 056701, 2008)          */
 } orc_config;
 
 typedef struct {
@@ -126,6 +130,7 @@ long orc_station_samples(const orc_sim* s, int station, double* out /* 7 per sam
 void orc_gather_at(const orc_sim* s, double x, double z, double out[6]);
 double orc_shape3(double r);
 void orc_boris(double q_over_m, double dt, const double E[3], const double B[3], double u[3]);
+void orc_vay(double q_over_m, double dt, const double E[3], const double B[3], double u[3]);
 /* Esirkepov deposit of one particle into a zeroed J (logical layout), for pins */
 void orc_deposit_one(orc_sim* s, double q, double w, double x0, double z0, double x1, double z1,
                      double vy);

@@ -565,14 +565,71 @@ static double antenna_field(const orc3_sim* s, double x, double y, double t)
     return (s->e0 / s->gamma) * f * sin(s->omega * tau);
 }
 
-void orc3_gather_at(const orc3_sim* s, const double r[3], double out[6])
+static const int NODE3[3] = {0, 0, 0};
+
+/* Momentum-conserving gather, first step (Sec. 5.3): each component of E^n and B^n interpolated
+   to the nodes, the mean of its values at the Yee locations around the node along its
+   staggered axes (2 for E, 4 for B); values beyond the stored range read 0. */
+static void node_fields3(orc3_sim* s, double* G[6])
+{
+    for (int c = 0; c < 6; c++) {
+        const int* h = c < 3 ? STAG_E[c] : STAG_B[c - 3];
+        const double* F = c < 3 ? s->f[O3_EX + c] : s->f[O3_BX + c - 3];
+        const double* Fo = c < 3 ? NULL : s->f[O3_BXO + c - 3];
+        long q[3];
+        for (q[2] = 0; q[2] < s->a[2].S; q[2]++)
+            for (q[1] = 0; q[1] < s->a[1].S; q[1]++)
+                for (q[0] = 0; q[0] < s->a[0].S; q[0]++) {
+                    double sum = 0.0;
+                    int n = 0;
+                    for (int m = 0; m < 8; m++) {
+                        long p[3];
+                        int skip = 0, ok = 1;
+                        for (int d = 0; d < 3; d++) {
+                            int lower = (m >> d) & 1;
+                            if (lower && !h[d]) { skip = 1; break; }
+                            p[d] = lower ? snb(&s->a[d], q[d], -1) : q[d];
+                            if (p[d] < 0) ok = 0;
+                        }
+                        if (skip) continue;
+                        n++;
+                        if (!ok) continue;
+                        double v = F[IDq(s, p)];
+                        if (Fo) v = 0.5 * (v + Fo[IDq(s, p)]);
+                        sum += v;
+                    }
+                    G[c][IDq(s, q)] = sum / (double)n;
+                }
+    }
+}
+
+/* E^n, B^n at rc (cells): from the staggered locations, or from the node values G */
+static void gather_fields3(const orc3_sim* s, double* const G[6], const double rc[3], double E[3], double B[3])
+{
+    for (int c = 0; c < 3; c++) {
+        if (G) {
+            E[c] = gather3(s, G[c], NODE3, rc);
+            B[c] = gather3(s, G[3 + c], NODE3, rc);
+        } else {
+            E[c] = gather3(s, s->f[O3_EX + c], STAG_E[c], rc);
+            B[c] = 0.5 * (gather3(s, s->f[O3_BXO + c], STAG_B[c], rc) + gather3(s, s->f[O3_BX + c], STAG_B[c], rc));
+        }
+    }
+}
+
+void orc3_gather_at(const orc3_sim* s_, const double r[3], double out[6])
 {
     /* the gather of the particle stage at one position (um, interior-relative) */
+    orc3_sim* s = (orc3_sim*)s_;
     double rc[3] = {r[0] / s->a[0].d, r[1] / s->a[1].d, r[2] / s->a[2].d};
-    for (int c = 0; c < 3; c++) {
-        out[c] = gather3(s, s->f[O3_EX + c], STAG_E[c], rc);
-        out[3 + c] = 0.5 * (gather3(s, s->f[O3_BXO + c], STAG_B[c], rc) + gather3(s, s->f[O3_BX + c], STAG_B[c], rc));
+    double* G[6] = {NULL};
+    int mc = s->cfg.gather_kind == 1;
+    if (mc) {
+        for (int c = 0; c < 6; c++) G[c] = (double*)malloc(s->ncell * sizeof(double));
+        node_fields3(s, G);
     }
+    gather_fields3(s, mc ? G : NULL, rc, out, out + 3);
+    if (mc) for (int c = 0; c < 6; c++) free(G[c]);
 }
 
 void orc3_stage_particles(orc3_sim* s)
@@ -589,6 +646,12 @@ void orc3_stage_particles(orc3_sim* s)
     const size_t nc = (size_t)s->ncell;
     double* priv = (double*)calloc((size_t)nt * 3 * nc, sizeof(double));
     double* nst = (double*)malloc((size_t)(s->ne > 0 ? s->ne : 1) * 6 * sizeof(double));
+    const int mc = s->cfg.gather_kind == 1;
+    double* G[6] = {NULL};
+    if (mc) {
+        for (int c = 0; c < 6; c++) G[c] = (double*)malloc(nc * sizeof(double));
+        node_fields3(s, G);
+    }
 #pragma omp parallel for schedule(static) num_threads(nt)
     for (long p = 0; p < s->ne; p++) {
         int th = 0;
@@ -600,12 +663,10 @@ void orc3_stage_particles(orc3_sim* s)
         double r0[3] = {s->ex[p], s->ey[p], s->ez[p]};
         double rc[3] = {r0[0] / s->a[0].d, r0[1] / s->a[1].d, r0[2] / s->a[2].d};
         double E[3], B[3];
-        for (int c = 0; c < 3; c++) {
-            E[c] = gather3(s, s->f[O3_EX + c], STAG_E[c], rc);
-            B[c] = 0.5 * (gather3(s, s->f[O3_BXO + c], STAG_B[c], rc) + gather3(s, s->f[O3_BX + c], STAG_B[c], rc));
-        }
+        gather_fields3(s, mc ? G : NULL, rc, E, B);
         double u[3] = {s->eux[p], s->euy[p], s->euz[p]};
-        orc_boris(-1.0, dt, E, B, u);
+        if (s->cfg.pusher == 1) orc_vay(-1.0, dt, E, B, u);
+        else orc_boris(-1.0, dt, E, B, u);
         double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
         double r1[3];
         for (int d = 0; d < 3; d++) r1[d] = r0[d] + dt * u[d] / g;
@@ -630,6 +691,7 @@ void orc3_stage_particles(orc3_sim* s)
     }
     s->ne = keep;
     free(nst);
+    if (mc) for (int c = 0; c < 6; c++) free(G[c]);
 
     if (s->plasma.ion_mode == 1) {
         double t0 = s->t, t1 = (double)(s->step + 1) * dt;

@@ -34,6 +34,7 @@ typedef struct {
     int moving_window;
     uint64_t seed;
     int filter_strides;                  /* stride mask, as in orc_config                    */
+    int gather_kind, pusher;             /* as in orc_config                                 */
 } orc3_config;
 
 /* field component ids; the split arrays S hold the PML part along the cyclic-next axis of the

@@ -391,3 +391,31 @@ def test_gather3_each_component_at_its_own_stagger():
             c = coef[name]
             want = c[0] + c[1] * p[0] + c[2] * p[1] + c[3] * p[2] - (0.25 if name[0] == "B" else 0.0)
             assert got[q] == pytest.approx(want, abs=1e-12), (name, p)
+
+
+def test_gather3_momentum_conserving_quadratic_closed_form():
+    # the node mean along each staggered axis adds a/4 for a (x/dx)^2 (see the 2D pin); linear
+    # fields stay exact
+    n, P = (9, 8, 10), 3
+    a = 0.9
+    ec = Oracle3(pi.make_config3(*n, *D3, pml_cells=P, gather_kind=0))
+    mc = Oracle3(pi.make_config3(*n, *D3, pml_cells=P, gather_kind=1))
+    nz, ny, nx = ec.shape
+    for o in (ec, mc):
+        for name in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+            h = STAG[name]
+            Z, Y, X = np.meshgrid(np.arange(nz) - P + 0.5 * h[2], np.arange(ny) - P + 0.5 * h[1],
+                                  np.arange(nx) - P + 0.5 * h[0], indexing="ij")
+            f = a * Y ** 2 + 0.3 * X - 0.2 * Z
+            o.set_field(name, f)
+            if name[0] == "B":
+                o.set_field(name + "o", f)
+    r = np.random.default_rng(8)
+    for _ in range(40):
+        c = np.array([2.0 + r.random() * (n[k] - 4.0) for k in range(3)])
+        p = c * np.array(D3)
+        g0, g1 = ec.gather_at(p), mc.gather_at(p)
+        for q, name in enumerate(("Ex", "Ey", "Ez", "Bx", "By", "Bz")):
+            want = a * (c[1] ** 2 + 1.0 / 3.0) + 0.3 * c[0] - 0.2 * c[2]
+            assert g0[q] == pytest.approx(want, abs=1e-12)
+            assert g1[q] - g0[q] == pytest.approx(a / 4.0 if STAG[name][1] else 0.0, abs=1e-12), name

@@ -921,3 +921,113 @@ def test_gauss_invariant_with_stride_filter():
     aw = o.info()["antenna_weight"] / (0.05 * 0.05)
     assert np.abs(g1 - g0)[inner].max() < 1e-13 * max(aw, rho0)
     assert np.abs(o.field("Ez")).max() > 1e-6
+
+
+# ---------------------------------------------------------------------------------------
+# Momentum-conserving gather (Sec. 5.3: the fields interpolated to the grid nodes first, then
+# gathered).  Linear fields still come back exactly (the mean of two points about a node is
+# the value at the node).  A quadratic a (x/dx)^2 separates the two procedures by a closed
+# form: the cubic B-spline gather gives a (x^2 + 1/3) (its second moment is 1/3), and the node
+# mean along a staggered axis adds (a/4) -- so the difference is a/4 exactly for components
+# staggered along x and 0 for components with nodes along x.
+# ---------------------------------------------------------------------------------------
+
+def _gather_box(kind, nx=14, nz=12, P=4):
+    return Oracle(pi.make_config(nx, nz, 0.1, 0.13, pml_cells=P, gather_kind=kind))
+
+
+def _set_profile(o, fn, P=4, d=(0.1, 0.13)):
+    Sz, Sx = o.shape
+    for name in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+        hx, hz = STAG2[name]
+        X = (np.arange(Sx) - P + 0.5 * hx)[None, :] + np.zeros((Sz, 1))
+        Z = (np.arange(Sz) - P + 0.5 * hz)[:, None] + np.zeros((1, Sx))
+        f = fn(name, X, Z)
+        o.set_field(name, f)
+        if name[0] == "B":
+            o.set_field(name + "o", f)
+
+
+def test_momentum_conserving_gather_linear_exact():
+    coef = {n: np.random.default_rng(hash(n) % 1000).standard_normal(3) for n in STAG2}
+    o = _gather_box(1)
+    _set_profile(o, lambda n, X, Z: coef[n][0] + coef[n][1] * X + coef[n][2] * Z)
+    r = np.random.default_rng(5)
+    for _ in range(100):
+        x, z = 2.0 + r.random() * 10.0, 2.0 + r.random() * 8.0     # cells
+        got = o.gather_at(x * 0.1, z * 0.13)
+        for c, n in enumerate(("Ex", "Ey", "Ez", "Bx", "By", "Bz")):
+            assert got[c] == pytest.approx(coef[n][0] + coef[n][1] * x + coef[n][2] * z, abs=1e-12)
+
+
+@pytest.mark.parametrize("axis", ["x", "z"])
+def test_momentum_conserving_gather_quadratic_closed_form(axis):
+    a = 0.7
+    ec, mc = _gather_box(0), _gather_box(1)
+    prof = (lambda n, X, Z: a * X ** 2) if axis == "x" else (lambda n, X, Z: a * Z ** 2)
+    _set_profile(ec, prof)
+    _set_profile(mc, prof)
+    r = np.random.default_rng(6)
+    ax = 0 if axis == "x" else 1
+    for _ in range(50):
+        x, z = 2.0 + r.random() * 10.0, 2.0 + r.random() * 8.0
+        pos = (x, z)[ax]
+        g0, g1 = ec.gather_at(x * 0.1, z * 0.13), mc.gather_at(x * 0.1, z * 0.13)
+        for c, n in enumerate(("Ex", "Ey", "Ez", "Bx", "By", "Bz")):
+            assert g0[c] == pytest.approx(a * (pos ** 2 + 1.0 / 3.0), abs=1e-12)
+            staggered = STAG2[n][ax] == 1
+            assert g1[c] - g0[c] == pytest.approx(a / 4.0 if staggered else 0.0, abs=1e-12), (n, axis)
+
+
+# ---------------------------------------------------------------------------------------
+# Vay's pusher (the pusher the paper's group built for relativistic beams, Sec. 1; Phys.
+# Plasmas 15, 056701): in crossed fields a particle at the drift velocity v_d (E = -v_d x B)
+# feels no force and keeps its momentum exactly, where Boris rotates it; a pure electric
+# impulse is q E dt; a pure magnetic field keeps |u|.
+# ---------------------------------------------------------------------------------------
+
+def test_vay_pusher_exb_drift_exact_and_boris_is_not():
+    from oracle import vay
+    vd = np.array([0.0, 0.0, 0.95])
+    g = 1.0 / math.sqrt(1.0 - vd @ vd)
+    B = np.array([0.0, 2.0, 0.0])
+    E = -np.cross(vd, B)
+    u = g * vd
+    for _ in range(500):
+        u = vay(-1.0, 0.2, E, B, u)
+    np.testing.assert_allclose(u, g * vd, rtol=0, atol=1e-13)
+    ub = g * vd
+    for _ in range(200):
+        ub = boris(-1.0, 0.2, E, B, ub)
+    assert np.abs(ub - g * vd).max() > 1e-2           # Boris drifts off at 0.95 c
+
+
+def test_vay_pusher_pure_fields():
+    from oracle import vay
+    E = np.array([0.2, -0.4, 1.3])
+    u = np.array([0.1, 0.0, -3.0])
+    np.testing.assert_allclose(vay(-1.0, 0.25, E, [0, 0, 0], u), u - 0.25 * E, atol=1e-15)
+    B = np.array([0.4, 0.7, -1.1])
+    u = np.array([0.3, -1.2, 2.0])
+    n0 = np.linalg.norm(u)
+    for _ in range(2000):
+        u = vay(-1.0, 0.3, [0, 0, 0], B, u)
+    assert np.linalg.norm(u) == pytest.approx(n0, rel=1e-13)
+    # the component along B is untouched by the rotation
+    assert u @ B == pytest.approx(np.array([0.3, -1.2, 2.0]) @ B, rel=1e-12)
+
+
+def test_gauss_invariant_with_momentum_conserving_gather_and_vay():
+    # the deposit alone carries charge conservation (Sec. 4.2.2): other gather and pusher keep it
+    w = pi.small_lab(nx=16, nz=80, ppc=2, npass=4, comp=1, ck="ck2", theta=0.1)
+    w["config"]["gather_kind"] = 1
+    w["config"]["pusher"] = 1
+    o = Oracle.from_workload(w)
+    g0 = o.gauss_residual()
+    rho0 = np.abs(o.charge_density()).max()
+    o.step(60)
+    g1 = o.gauss_residual()
+    P = 10
+    inner = slice(P + 12, P + 80 - 12)
+    aw = o.info()["antenna_weight"] / (0.05 * 0.05)
+    assert np.abs(g1 - g0)[inner].max() < 1e-13 * max(aw, rho0)
