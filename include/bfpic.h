@@ -74,6 +74,10 @@ typedef struct {
                                   ascending order of s, e.g. 0x3 = S(1:2), 0x7 = S(1:2:3),
                                   0xB = S(1:2:4); 0 means stride 1 only.  BF_EINVAL beyond
                                   stride 16, 48 passes or a reach of 128 cells per axis       */
+    int gather_kind;           /* 0: energy conserving, each field component gathered from its
+                                  own Yee location (Sec. 5.1); 1: momentum conserving, the
+                                  fields interpolated to the nodes first (Sec. 5.3)           */
+    int pusher;                /* 0: Boris; 1: Vay (Phys. Plasmas 15, 056701, 2008)            */
     int pml_cells;             /* PML depth on non-periodic faces (Appendix II)                */
     int periodic_mask;         /* bit 0: x, bit 1: y (3D), bit 2: z periodic (no moving window) */
     double gamma_boost;        /* Lorentz factor of the calculation frame (>= 1)              */
@@ -274,8 +278,8 @@ int64_t bf_batch_work_bytes(int nsims);
 /* Creates a batch over n distinct handles (not owned).  work: device buffer of at least
    bf_batch_work_bytes(n) bytes, 256-byte aligned, owned by the caller.  hip_stream: the stream
    of the batched launches (NULL: default).  BF_EINVAL: bad arguments or a repeated handle;
-   BF_EUNSUPPORTED: an FP64 or 3D handle, or one with filter strides other than 1; BF_ESTATE: a
-   handle with a sticky error;
+   BF_EUNSUPPORTED: an FP64 or 3D handle, or one with filter strides other than 1, the
+   momentum-conserving gather or Vay's pusher; BF_ESTATE: a handle with a sticky error;
    BF_EDEVICE: pinned staging memory could not be allocated. */
 bf_status bf_batch_create(bf_sim* const* sims, int n, void* work, int64_t work_bytes,
                           void* hip_stream, bf_batch** out);

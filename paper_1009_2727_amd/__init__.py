@@ -43,7 +43,7 @@ class bf_config(C.Structure):
                 ("ck_gamma", C.c_double), ("friedman_theta", C.c_double),
                 ("cfl_fraction", C.c_double), ("filter_npass", C.c_int),
                 ("filter_compensate", C.c_int), ("filter_kind", C.c_int), ("filter_strides", C.c_int),
-                ("pml_cells", C.c_int),
+                ("gather_kind", C.c_int), ("pusher", C.c_int), ("pml_cells", C.c_int),
                 ("periodic_mask", C.c_int), ("gamma_boost", C.c_double),
                 ("moving_window", C.c_int), ("particle_capacity", C.c_int64),
                 ("sort_every", C.c_int), ("tile_x", C.c_int), ("tile_z", C.c_int),
@@ -215,6 +215,8 @@ def make_config(cfg: dict, capacity: int, stations: int = 0, station_capacity: i
     c.filter_compensate = cfg["filter_compensate"]
     c.filter_kind = cfg.get("filter_kind", FILTER_BILINEAR)
     c.filter_strides = cfg.get("filter_strides", 1)
+    c.gather_kind = cfg.get("gather_kind", 0)
+    c.pusher = cfg.get("pusher", 0)
     c.pml_cells = cfg["pml_cells"]
     c.periodic_mask = ((1 if cfg.get("periodic_x") else 0) | (2 if cfg.get("periodic_y") else 0)
                        | (4 if cfg.get("periodic_z") else 0))

@@ -306,6 +306,36 @@ __device__ __forceinline__ void filter_tile(const Geo& g, const R* __restrict__ 
     }
 }
 
+// ---- momentum-conserving gather: fields to the nodes -------------------------------------
+// Each component of E^n and of B^n = (B^{n-1/2} + B^{n+1/2}) / 2 becomes, at node (i, k), the
+// mean of its values at the Yee locations around the node along its staggered axes: E_x (i -+
+// 1/2, k), E_z (i, k -+ 1/2), B_x (i, k -+ 1/2), B_y the four (i -+ 1/2, k -+ 1/2), B_z (i -+ 1/2,
+// k); E_y sits on the node.  Locations beyond a non-periodic edge read 0.
+template <typename R>
+__global__ void __launch_bounds__(256) k_nodes(Geo g, FieldSet<R> f)
+{
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int k = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= g.Sx || k >= g.Sz) return;
+    const int il = swrap(i - 1, g.Sx, g.perx), kl = swrap(k - 1, g.Sz, g.perz);
+    auto at = [&](const R* a, int ii, int kk) { return (ii < 0 || kk < 0) ? R(0) : a[gofs(g, ii, kk)]; };
+    auto bn = [&](int c, int ii, int kk) { return R(0.5) * (at(f.B[c], ii, kk) + at(f.Bn[c], ii, kk)); };
+    const long o = gofs(g, i, k);
+    f.G[0][o] = R(0.5) * (at(f.E[0], il, k) + at(f.E[0], i, k));
+    f.G[1][o] = f.E[1][o];
+    f.G[2][o] = R(0.5) * (at(f.E[2], i, kl) + at(f.E[2], i, k));
+    f.G[3][o] = R(0.5) * (bn(0, i, kl) + bn(0, i, k));
+    f.G[4][o] = R(0.25) * ((bn(1, il, kl) + bn(1, i, kl)) + (bn(1, il, k) + bn(1, i, k)));
+    f.G[5][o] = R(0.5) * (bn(2, il, k) + bn(2, i, k));
+}
+
+template <typename R>
+void launch_nodes(const Geo& g, const FieldSet<R>& f, hipStream_t s)
+{
+    dim3 grid((g.Sx + 63) / 64, (g.Sz + 3) / 4);
+    hipLaunchKernelGGL((k_nodes<R>), grid, dim3(256), 0, s, g, f);
+}
+
 // ---- batched runs: one persistent launch per phase over a device work queue ----------------
 template <typename R>
 __global__ void __launch_bounds__(256) k_faraday_batch(const FaradayDesc<R>* __restrict__ d, QueueRef q)
@@ -563,6 +593,7 @@ void launch_fill_int(int* p, int n, int v, hipStream_t s)
 #define BF_INST(R)                                                                                 \
     template void launch_faraday<R>(const Geo&, const FieldSet<R>&, const PmlTab<R>&,              \
                                     const SolverCoef&, hipStream_t);                               \
+    template void launch_nodes<R>(const Geo&, const FieldSet<R>&, hipStream_t);                       \
     template void launch_ampere<R>(const Geo&, const FieldSet<R>&, const PmlTab<R>&,               \
                                    const SolverCoef&, hipStream_t);                                \
     template void launch_faraday_batch<R>(const FaradayDesc<R>*, const QueueRef&, int, hipStream_t); \

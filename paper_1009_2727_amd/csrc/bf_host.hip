@@ -45,7 +45,8 @@ enum {
     A_BYX = 24,
     A_EYX = 25,
     A_JT = 26,  // the filter's intermediate (after the x passes)
-    A_COUNT = 29
+    A_G = 29,   // momentum-conserving gather: E^n, B^n at the nodes (6 arrays)
+    A_COUNT = 35
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -173,6 +174,7 @@ bf_status validate(const bf_config* c)
     if (c->friedman_theta < 0 || c->friedman_theta > 1) return BF_EINVAL;
     if (c->filter_npass < 0 || c->filter_npass > 10) return BF_EINVAL;
     if (c->filter_strides < 0 || c->filter_strides > 0xFFFF) return BF_EINVAL;
+    if (c->gather_kind < 0 || c->gather_kind > 1 || c->pusher < 0 || c->pusher > 1) return BF_EINVAL;
     {
         bf3::FiltSeq fs;
         if (!bf3::filter_seq(c->filter_npass, c->filter_compensate, c->filter_strides, &fs)) return BF_EINVAL;
@@ -334,6 +336,7 @@ FieldSet<R> field_set(const bf_sim* s)
     }
     f.Byx = s->arr<R>(A_BYX);
     f.Eyx = s->arr<R>(A_EYX);
+    for (int c = 0; c < 6; c++) f.G[c] = s->arr<R>(A_G + c);
     return f;
 }
 
@@ -561,12 +564,17 @@ void inject(bf_sim* s, int64_t nrows)
     s->next_row += nrows;
 }
 
+// the arrays whose rows move with the window (the filter's intermediate and the node values of
+// the momentum-conserving gather are rewritten every step before they are read)
+constexpr int A_PERSISTENT = A_JT;
+static_assert(A_PERSISTENT <= 32, "PtrList holds 32 arrays");
+
 template <typename R>
 PtrList<R> all_arrays(const bf_sim* s)
 {
     PtrList<R> p;
-    p.n = A_COUNT;
-    for (int a = 0; a < A_COUNT; a++) p.p[a] = s->arr<R>(a);
+    p.n = A_PERSISTENT;
+    for (int a = 0; a < A_PERSISTENT; a++) p.p[a] = s->arr<R>(a);
     return p;
 }
 
@@ -656,8 +664,10 @@ bf_status step_impl(bf_sim* s, int nsteps)
         pp.fjz = (R)(1.0 / (c.dx_um * s->dt));
         pp.fjy = (R)(-1.0 / (c.dx_um * c.dz_um));
         pp.shift = d;
+        pp.vay = c.pusher;
         s->slot = SLOT_PUSH;
         t_ph = s->tick();
+        if (c.gather_kind == 1) launch_nodes<R>(g, f, s->stream);      // single runs only (not batched)
         {
             const ElectronArrays<R> e = electrons<R>(s, s->p_cur);
             const Segment* sg = seg_e(s, s->sg_cur);
@@ -669,7 +679,7 @@ bf_status step_impl(bf_sim* s, int nsteps)
                     rb->n_gpd.push_back(s->nseg_e);
                 }
             }
-            if (!rb) launch_gpd<R>(g, f, e, sg, bi, bo, s->nseg_e, pp, status_word(s), s->stream);
+            if (!rb) launch_gpd<R>(g, f, e, sg, bi, bo, s->nseg_e, pp, status_word(s), c.gather_kind == 1, s->stream);
         }
         s->tock(t_ph, BF_PHASE_PUSH);
         // rigid ions: deposit-only J_z
@@ -861,6 +871,7 @@ void layout3(const bf_config* c, Sim3* L)
     L->fa = align_up((size_t)L->g.plane * L->g.S[2] * real, 256);
     L->fa8 = align_up((size_t)L->g.plane * L->g.S[2] * 8, 256);
     L->fields_bytes = L->fa * A3_COUNT + 3 * L->fa8;
+    if (c->gather_kind == 1) L->fields_bytes += 6 * L->fa;       // node values of E^n, B^n
     L->cap = std::max<int64_t>(c->particle_capacity, 1);
     size_t o = 0;
     const size_t esz[8] = {8, 8, 8, real, real, real, real, 4};
@@ -938,6 +949,10 @@ bf3::F3<R> fields3(const bf_sim* s)
         f.SE[c] = arr3<R>(s, A3_SE + c); f.SB[c] = arr3<R>(s, A3_SB + c);
         f.T[c] = arr3<R>(s, A3_T + c);
     }
+    for (int c = 0; c < 6; c++)
+        f.G[c] = s->cfg.gather_kind == 1
+                     ? reinterpret_cast<R*>((char*)s->buf[0] + s->d3->fa * A3_COUNT + 3 * s->d3->fa8 + s->d3->fa * c)
+                     : nullptr;
     return f;
 }
 
@@ -1165,10 +1180,13 @@ bf_status step3(bf_sim* s, int nsteps)
             pp.jk[a] = 1.0 / (d[(a + 1) % 3] * d[(a + 2) % 3] * s->dt);
         }
         pp.shift = (double)dsh;
+        pp.vay = s->cfg.pusher;
         ev = s->tick();
+        const bool mc = s->cfg.gather_kind == 1;
+        if (mc) bf3::launch3_nodes<R>(g, f, s->stream);
         bf3::launch3_gpd<R>(g, f, electrons3<R>(s, L.p_cur), seg3<R>(s, 0), box3(s, 0, L.bb_cur),
                             box3(s, 0, 1 - L.bb_cur), L.nseg, pp, L.pz, w3<int>(s, L.w_status), w3<int>(s, L.w_lists),
-                            w3<int2>(s, L.w_mis), s->stream);
+                            w3<int2>(s, L.w_mis), mc, s->stream);
         s->tock(ev, BF_PHASE_PUSH);
         ev = s->tick();
         if (s->have_plasma && s->plasma.ion_mode == 1)
@@ -1965,9 +1983,9 @@ bf_status bf_batch_create(bf_sim* const* sims, int n, void* work, int64_t work_b
     for (int q = 0; q < n; q++) {
         if (!sims[q] || sims[q]->cfg.real_bytes != 4 || sims[q]->d3) return BF_EUNSUPPORTED;
         // the batched filter phase runs the stride-1 tile filter
-        if (sims[q]->cfg.filter_strides > 1) return BF_EUNSUPPORTED;
+        if (sims[q]->cfg.filter_strides > 1 || sims[q]->cfg.gather_kind || sims[q]->cfg.pusher) return BF_EUNSUPPORTED;
         // the batched filter phase runs the stride-1 tile filter
-        if (sims[q]->cfg.filter_strides > 1) return BF_EUNSUPPORTED;
+        if (sims[q]->cfg.filter_strides > 1 || sims[q]->cfg.gather_kind || sims[q]->cfg.pusher) return BF_EUNSUPPORTED;
         if (sims[q]->err != BF_OK) return BF_ESTATE;
         for (int p = 0; p < q; p++)
             if (sims[p] == sims[q]) return BF_EINVAL;

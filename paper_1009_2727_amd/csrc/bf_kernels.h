@@ -25,6 +25,7 @@ struct FieldSet {
     R* Jf[3];
     R* Byx;
     R* Eyx;
+    R* G[6];    // momentum-conserving gather: E^n and B^n interpolated to the nodes (else unused)
 };
 
 // PML coefficient tables indexed [axis 0 x / 1 z][stagger 0 node / 1 half]; x tables by
@@ -72,6 +73,7 @@ struct PushParams {
     R dtdx, dtdz;      // dt / dx, dt / dz  (cell units per unit velocity)
     R fjx, fjz, fjy;   // -q/(dz dt), -q/(dx dt), q/(dx dz)   (times w, v_y)
     int shift;         // window shift (cells) applied after this step
+    int vay;           // 1: Vay's pusher, 0: Boris
 };
 
 struct InjectParams {
@@ -189,10 +191,15 @@ void launch_window_rows(const Geo& g, const PtrList<R>& arrays, int d, const Ent
 template <typename R>
 void launch_stations(const Geo& g, const FieldSet<R>& f, const StationParams& sp,
                      double* rec, int* counts, hipStream_t s);
+// momentum-conserving gather, first step: E^n and B^n = (B^{n-1/2} + B^{n+1/2})/2 interpolated to
+// the nodes (the mean over the Yee locations around each node along the staggered axes) into f.G
+template <typename R>
+void launch_nodes(const Geo& g, const FieldSet<R>& f, hipStream_t s);
+// gather, push and deposit; mc: the gather reads f.G with nodal weights for every component
 template <typename R>
 void launch_gpd(const Geo& g, const FieldSet<R>& f, const ElectronArrays<R>& e,
                 const Segment* seg, const int4* bbox_in, int4* bbox_out, int nseg,
-                const PushParams<R>& pp, int* status, hipStream_t s);
+                const PushParams<R>& pp, int* status, bool mc, hipStream_t s);
 template <typename R>
 void launch_ions(const Geo& g, const FieldSet<R>& f, const IonArrays<R>& ion, const Segment* seg,
                  const int4* bbox_in, int4* bbox_out, int nseg, double zsh_a, double zsh_b,

@@ -40,6 +40,7 @@ struct F3 {
     R* SE[3];   // PML split parts of E (part along the cyclic-next axis)
     R* SB[3];   // PML split parts of B
     R* T[3];    // E-tilde of the Friedman step
+    R* G[6];    // momentum-conserving gather: E^n and B^n interpolated to the nodes (else null)
 };
 
 template <typename R>
@@ -61,6 +62,7 @@ struct Push3 {
     double dtd[3];      // dt / d (cells per unit velocity)
     double jk[3];       // -q w factor of J_c: 1 / (d_a1 d_a2 dt) (times q w per particle)
     double shift;       // whole cells the window moves at the end of this step
+    int vay;            // 1: Vay's pusher, 0: Boris
 };
 
 // particle segment: a contiguous index range whose particles share a cell box
@@ -148,7 +150,10 @@ template <typename R> void launch3_zero_j(const G3& g, const F3<R>& f, hipStream
 // segment's box and segments too large for LDS are pushed in a second pass, on HBM)
 template <typename R>
 void launch3_gpd(const G3& g, const F3<R>& f, const E3<R>& e, const Seg3* seg, const Box3* bin, Box3* bout,
-                 int nseg, const Push3& pp, int pz, int* status, int* lists, int2* mis, hipStream_t s);
+                 int nseg, const Push3& pp, int pz, int* status, int* lists, int2* mis, bool mc, hipStream_t s);
+// momentum-conserving gather, first step: E^n and B^n = (B^{n-1/2} + B^{n+1/2})/2 interpolated to
+// the nodes (the mean over the Yee locations around each node along the staggered axes) into f.G
+template <typename R> void launch3_nodes(const G3& g, const F3<R>& f, hipStream_t s);
 // rigid-ion J_z of nseg segments: z = z0 - zsa at t_n, z0 - zsb at t_{n+1}, z0 - zsn in the
 // next window frame (for the boxes)
 template <typename R>

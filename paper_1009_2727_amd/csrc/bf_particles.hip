@@ -106,6 +106,7 @@ struct GlobAcc {
     const R* E[3];
     const R* B[3];
     const R* Bn[3];
+    const R* G[6];     // node values (momentum-conserving gather), or null
     R* J[3];
     __device__ __forceinline__ bool inside(int, int, int, int) const { return true; }
     __device__ __forceinline__ int2 handle(int jx, int jz) const { return make_int2(jx, jz); }
@@ -114,6 +115,7 @@ struct GlobAcc {
         int i = swrap(h.x + a + g.Px, g.Sx, g.perx), k = swrap(h.y + b + g.Pz, g.Sz, g.perz);
         if (i < 0 || k < 0) return R(0);
         long o = gofs(g, i, k);
+        if (G[0]) return G[c][o];
         if (c < 3) return E[c][o];
         return R(0.5) * (B[c - 3][o] + Bn[c - 3][o]);
     }
@@ -130,7 +132,7 @@ struct GlobAcc {
     }
 };
 
-template <typename R>
+template <bool MC, typename R>
 __device__ __forceinline__ GlobAcc<R> make_glob(const Geo& g, const FieldSet<R>& f)
 {
     GlobAcc<R> a;
@@ -141,6 +143,7 @@ __device__ __forceinline__ GlobAcc<R> make_glob(const Geo& g, const FieldSet<R>&
         a.Bn[c] = f.Bn[c];
         a.J[c] = f.J[c];
     }
+    for (int c = 0; c < 6; c++) a.G[c] = MC ? f.G[c] : nullptr;
     return a;
 }
 
@@ -227,12 +230,14 @@ __device__ __forceinline__ void esirkepov(const A& acc, int ix, double fx, int i
     }
 }
 
-// gather E^n, B^n at (x, z) (cells) with cubic weights at each component's stagger
-template <typename R, typename A>
+// gather E^n, B^n at (x, z) (cells) with cubic weights at each component's stagger (energy
+// conserving), or from the node values with nodal weights for every component (MC: momentum
+// conserving, the accessor then serves the node arrays)
+template <bool MC, typename R, typename A>
 __device__ __forceinline__ void gather(const A& acc, double x, double z, R E[3], R B[3])
 {
     const int ix = (int)floor(x), iz = (int)floor(z);
-    const double xh = x - 0.5, zh = z - 0.5;
+    const double xh = MC ? x : x - 0.5, zh = MC ? z : z - 0.5;
     const int ixh = (int)floor(xh), izh = (int)floor(zh);
     R wxn[4], wxh[4], wzn[4], wzh[4];
     bspline3((R)(x - ix), wxn);
@@ -282,6 +287,31 @@ __device__ __forceinline__ void boris(R h, const R E[3], const R B[3], R& ux, R&
     uz = uqz + h * E[2];
 }
 
+// Vay's pusher (Phys. Plasmas 15, 056701, 2008): u' = u + (q dt/m)(E + v x B/2), tau = (q dt/2m) B,
+// u* = u'.tau, sigma = gamma'^2 - tau^2, gamma^2 = (sigma + sqrt(sigma^2 + 4(tau^2 + u*^2)))/2,
+// t = tau/gamma, u = (u' + (u'.t) t + u' x t) / (1 + t^2); h = q dt / 2m
+template <typename R>
+__device__ __forceinline__ void vay(R h, const R E[3], const R B[3], R& ux, R& uy, R& uz)
+{
+    const R ig = rsqrt_(R(1) + ux * ux + uy * uy + uz * uz);
+    const R vx = ux * ig, vy = uy * ig, vz = uz * ig;
+    const R tx0 = h * B[0], ty0 = h * B[1], tz0 = h * B[2];
+    const R upx = ux + R(2) * h * E[0] + (vy * tz0 - vz * ty0);
+    const R upy = uy + R(2) * h * E[1] + (vz * tx0 - vx * tz0);
+    const R upz = uz + R(2) * h * E[2] + (vx * ty0 - vy * tx0);
+    const R us = upx * tx0 + upy * ty0 + upz * tz0;
+    const R tau2 = tx0 * tx0 + ty0 * ty0 + tz0 * tz0;
+    const R sigma = R(1) + upx * upx + upy * upy + upz * upz - tau2;
+    const R gn2 = R(0.5) * (sigma + sqrt(sigma * sigma + R(4) * (tau2 + us * us)));
+    const R ign = rsqrt_(gn2);
+    const R tx = tx0 * ign, ty = ty0 * ign, tz = tz0 * ign;
+    const R sf = rcp_(R(1) + tx * tx + ty * ty + tz * tz);
+    const R ut = upx * tx + upy * ty + upz * tz;
+    ux = sf * (upx + ut * tx + (upy * tz - upz * ty));
+    uy = sf * (upy + ut * ty + (upz * tx - upx * tz));
+    uz = sf * (upz + ut * tz + (upx * ty - upy * tx));
+}
+
 // the state of one electron as read from HBM
 template <typename R>
 struct EState {
@@ -311,7 +341,7 @@ __device__ __forceinline__ void store_electron(const ElectronArrays<R>& e, int p
 // in place (the caller writes it back) and the box is updated.  The caller guarantees the
 // gather window [ix-2, ix+2] and the deposit window [ix-2, ix+3] (one-cell move) are
 // addressable through A.  js scales the current into A's units.
-template <typename R, typename A>
+template <bool MC, typename R, typename A>
 __device__ __forceinline__ void advance_electron(const A& acc, const Geo& g, const PushParams<R>& pp,
                                                  EState<R>& st, double js, int* status, int& x0,
                                                  int& x1, int& z0, int& z1)
@@ -321,8 +351,9 @@ __device__ __forceinline__ void advance_electron(const A& acc, const Geo& g, con
     R ux = st.ux, uy = st.uy, uz = st.uz;
     const int ix = (int)floor(x), iz = (int)floor(z);
     R E[3], B[3];
-    gather(acc, x, z, E, B);
-    boris(pp.qdt2, E, B, ux, uy, uz);
+    gather<MC>(acc, x, z, E, B);
+    if (pp.vay) vay(pp.qdt2, E, B, ux, uy, uz);
+    else boris(pp.qdt2, E, B, ux, uy, uz);
     const R ig = rsqrt_(R(1) + ux * ux + uy * uy + uz * uz);
     const R vx = ux * ig, vy = uy * ig, vz = uz * ig;
     const double xn = x + (double)(pp.dtdx * vx), zn = z + (double)(pp.dtdz * vz);
@@ -356,7 +387,7 @@ __device__ __forceinline__ void advance_electron(const A& acc, const Geo& g, con
 constexpr int MISFIT_CAP = 256;
 
 // gather, push and deposit of particle segment s by one workgroup
-template <typename R>
+template <typename R, bool MC = false>
 __device__ __forceinline__ void gpd_segment(const Geo& g, const FieldSet<R>& f, const ElectronArrays<R>& e,
                                             const Segment* __restrict__ seg, const int4* __restrict__ bbin,
                                             int4* __restrict__ bbout, const PushParams<R>& pp, int* status,
@@ -404,10 +435,15 @@ __device__ __forceinline__ void gpd_segment(const Geo& g, const FieldSet<R>& f, 
             R v[6] = {0, 0, 0, 0, 0, 0};
             if (i >= 0 && k >= 0) {
                 const long o = gofs(g, i, k);
+                if constexpr (MC) {
 #pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    v[c] = f.E[c][o];
-                    v[3 + c] = R(0.5) * (f.B[c][o] + f.Bn[c][o]);
+                    for (int c = 0; c < 6; c++) v[c] = f.G[c][o];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        v[c] = f.E[c][o];
+                        v[3 + c] = R(0.5) * (f.B[c][o] + f.Bn[c][o]);
+                    }
                 }
             }
             const int t = b * TPX + a;
@@ -443,7 +479,7 @@ __device__ __forceinline__ void gpd_segment(const Geo& g, const FieldSet<R>& f, 
                 else atomicOr(status, ST_SEGMENTS);
                 continue;
             }
-            advance_electron(lds, g, pp, cur, js, status, x0, x1, z0, z1);
+            advance_electron<MC>(lds, g, pp, cur, js, status, x0, x1, z0, z1);
             done = cur;
             pdone = p;
         }
@@ -467,20 +503,20 @@ __device__ __forceinline__ void gpd_segment(const Geo& g, const FieldSet<R>& f, 
         // particles outside the staged box (none for a consistent box): global accessors
         const int nm = min(nmisfit, MISFIT_CAP);
         if (nm > 0) {
-            const GlobAcc<R> glb = make_glob(g, f);
+            const GlobAcc<R> glb = make_glob<MC>(g, f);
             for (int q = threadIdx.x; q < nm; q += NTHR) {
                 const int p = misfit[q];
                 EState<R> st = load_electron(e, p);
-                advance_electron(glb, g, pp, st, 1.0, status, x0, x1, z0, z1);
+                advance_electron<MC>(glb, g, pp, st, 1.0, status, x0, x1, z0, z1);
                 store_electron(e, p, st);
             }
         }
     } else {
-        const GlobAcc<R> glb = make_glob(g, f);
+        const GlobAcc<R> glb = make_glob<MC>(g, f);
         for (int p = sg.start + threadIdx.x; p < end; p += NTHR) {
             EState<R> st = load_electron(e, p);
             if (st.w == R(0)) continue;
-            advance_electron(glb, g, pp, st, 1.0, status, x0, x1, z0, z1);
+            advance_electron<MC>(glb, g, pp, st, 1.0, status, x0, x1, z0, z1);
             store_electron(e, p, st);
         }
     }
@@ -488,13 +524,13 @@ __device__ __forceinline__ void gpd_segment(const Geo& g, const FieldSet<R>& f, 
     if (threadIdx.x == 0) bbout[s] = make_int4(x0, x1, z0, z1);
 }
 
-template <typename R>
+template <typename R, bool MC>
 __global__ void __launch_bounds__(NTHR, sizeof(R) == 4 ? 3 : 1) k_gpd(Geo g, FieldSet<R> f, ElectronArrays<R> e,
                                               const Segment* __restrict__ seg,
                                               const int4* __restrict__ bbin, int4* __restrict__ bbout,
                                               PushParams<R> pp, int* status)
 {
-    gpd_segment<R>(g, f, e, seg, bbin, bbout, pp, status, blockIdx.x);
+    gpd_segment<R, MC>(g, f, e, seg, bbin, bbout, pp, status, blockIdx.x);
 }
 
 template <typename R>
@@ -554,7 +590,7 @@ __device__ __forceinline__ void ion_segment(const Geo& g, const FieldSet<R>& f, 
         return;
     }
     using JT = typename LdsAcc<R>::JT;
-    GlobAcc<R> glb = make_glob(g, f);
+    GlobAcc<R> glb = make_glob<false>(g, f);
     LdsAcc<R> lds;
     lds.xb = bb.x - 2;
     lds.zb = bb.z - 2;
@@ -1180,12 +1216,16 @@ __global__ void __launch_bounds__(SORT_THREADS) k_sort_disperse_i(Geo g, IonArra
 template <typename R>
 void launch_gpd(const Geo& g, const FieldSet<R>& f, const ElectronArrays<R>& e, const Segment* seg,
                 const int4* bbox_in, int4* bbox_out, int nseg, const PushParams<R>& pp, int* status,
-                hipStream_t s)
+                bool mc, hipStream_t s)
 {
     if (nseg <= 0) return;
     const size_t lds = (size_t)tcells<R>() * (6 * sizeof(R) + 3 * sizeof(typename LdsAcc<R>::JT));
-    hipLaunchKernelGGL((k_gpd<R>), dim3(nseg), dim3(NTHR), lds, s, g, f, e, seg, bbox_in, bbox_out,
-                       pp, status);
+    if (mc)
+        hipLaunchKernelGGL((k_gpd<R, true>), dim3(nseg), dim3(NTHR), lds, s, g, f, e, seg, bbox_in, bbox_out,
+                           pp, status);
+    else
+        hipLaunchKernelGGL((k_gpd<R, false>), dim3(nseg), dim3(NTHR), lds, s, g, f, e, seg, bbox_in, bbox_out,
+                           pp, status);
 }
 
 template <typename R>
@@ -1279,7 +1319,7 @@ void launch_sort_ions(const Geo& g, int tile_x, int tile_z, int ntx, int ntiles,
 #define BF_INST(R)                                                                                    \
     template void launch_gpd<R>(const Geo&, const FieldSet<R>&, const ElectronArrays<R>&,             \
                                 const Segment*, const int4*, int4*, int, const PushParams<R>&, int*,  \
-                                hipStream_t);                                                         \
+                                bool, hipStream_t);                                                   \
     template void launch_ions<R>(const Geo&, const FieldSet<R>&, const IonArrays<R>&,                 \
                                  const Segment*, const int4*, int4*, int, double, double, int, R,     \
                                  hipStream_t);                                                        \

@@ -398,7 +398,7 @@ __device__ __forceinline__ void window5(double f, bool hi, double s[5])
 
 // gather of E^n and B^n = (B^{n-1/2} + B^{n+1/2}) / 2 at r (cells), cubic weights at each
 // component's stagger
-template <typename R>
+template <bool MC, typename R>
 __device__ void gather3(const G3& g, const F3<R>& f, const double r[3], R E[3], R B[3])
 {
     R w[3][2][4];
@@ -415,9 +415,10 @@ __device__ void gather3(const G3& g, const F3<R>& f, const double r[3], R E[3], 
         }
 #pragma unroll
     for (int c = 0; c < 6; c++) {
-        const int hx = c < 3 ? (c == 0) : (c != 3), hy = c < 3 ? (c == 1) : (c != 4), hz = c < 3 ? (c == 2) : (c != 5);
+        int hx = c < 3 ? (c == 0) : (c != 3), hy = c < 3 ? (c == 1) : (c != 4), hz = c < 3 ? (c == 2) : (c != 5);
+        if (MC) hx = hy = hz = 0;
         R acc = R(0), acc2 = R(0);
-        const R* F = c < 3 ? f.E[c] : f.B[c - 3];
+        const R* F = MC ? f.G[c] : (c < 3 ? f.E[c] : f.B[c - 3]);
         const R* Fo = c < 3 ? f.E[c] : f.Bo[c - 3];
         for (int k = 0; k < 4; k++) {
             const int sk = id[2][hz][k];
@@ -432,12 +433,12 @@ __device__ void gather3(const G3& g, const F3<R>& f, const double r[3], R E[3], 
                     if (si < 0) continue;
                     const long o = o3(g, si, sj, sk);
                     acc += w[0][hx][i] * wjk * F[o];
-                    if (c >= 3) acc2 += w[0][hx][i] * wjk * Fo[o];
+                    if (!MC && c >= 3) acc2 += w[0][hx][i] * wjk * Fo[o];
                 }
             }
         }
         if (c < 3) E[c] = acc;
-        else B[c - 3] = R(0.5) * (acc + acc2);
+        else B[c - 3] = MC ? acc : R(0.5) * (acc + acc2);
     }
 }
 
@@ -569,7 +570,7 @@ __device__ __forceinline__ bool in_box(const BoxL<R>& bx, const double r[3])
 }
 
 // gather of E^n, B^n at r from the staged box, cubic weights at each component's stagger
-template <typename R>
+template <bool MC, typename R>
 __device__ __forceinline__ void gather_box(const BoxL<R>& bx, const double r[3], R E[3], R B[3])
 {
     R w[3][2][4];
@@ -585,7 +586,8 @@ __device__ __forceinline__ void gather_box(const BoxL<R>& bx, const double r[3],
         }
 #pragma unroll
     for (int c = 0; c < 6; c++) {
-        const int hx = c < 3 ? (c == 0) : (c != 3), hy = c < 3 ? (c == 1) : (c != 4), hz = c < 3 ? (c == 2) : (c != 5);
+        const int hx = MC ? 0 : (c < 3 ? (c == 0) : (c != 3)), hy = MC ? 0 : (c < 3 ? (c == 1) : (c != 4)),
+                  hz = MC ? 0 : (c < 3 ? (c == 2) : (c != 5));
         const R* F = bx.f + c * bx.n + ob[0][hx] + ob[1][hy] + ob[2][hz];
         R acc = R(0);
 #pragma unroll
@@ -690,7 +692,7 @@ __device__ __forceinline__ void deposit_box_z(const BoxL<R>& bx, double x, doubl
 }
 
 // stage the box: fields (electrons) and zeroed accumulators (nj planes)
-template <int NTH, typename R, bool FIELDS>
+template <int NTH, typename R, bool FIELDS, bool MC = false>
 __device__ void stage_box(const G3& g, const F3<R>& f, const BoxL<R>& bx, int nj)
 {
     const int L = bx.ext[0] * bx.ext[1] * bx.ext[2];
@@ -702,10 +704,15 @@ __device__ void stage_box(const G3& g, const F3<R>& f, const BoxL<R>& bx, int nj
             R v[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
             if (si >= 0 && sj >= 0 && sk >= 0) {
                 const long o = o3(g, si, sj, sk);
+                if constexpr (MC) {
 #pragma unroll
-                for (int cc = 0; cc < 3; cc++) {
-                    v[cc] = f.E[cc][o];
-                    v[3 + cc] = R(0.5) * (f.B[cc][o] + f.Bo[cc][o]);
+                    for (int cc = 0; cc < 6; cc++) v[cc] = f.G[cc][o];
+                } else {
+#pragma unroll
+                    for (int cc = 0; cc < 3; cc++) {
+                        v[cc] = f.E[cc][o];
+                        v[3 + cc] = R(0.5) * (f.B[cc][o] + f.Bo[cc][o]);
+                    }
                 }
             }
 #pragma unroll
@@ -783,7 +790,7 @@ __device__ __forceinline__ void grow(int nb[6], int a, int c)
 // one electron: gather, Boris push (q/m = -1), deposit, absorption, window rebase; on the
 // staged box (LDS) or on the fields and current in HBM.  The staged form returns false,
 // leaving the particle untouched, when its cell lies outside the box.
-template <bool LDS, typename R>
+template <bool LDS, bool MC, typename R>
 __device__ __forceinline__ bool electron3(const G3& g, const F3<R>& f, const BoxL<R>& bx, const E3<R>& e, int p,
                                           const Push3& pp, double js, int* status, int nb[6])
 {
@@ -792,19 +799,41 @@ __device__ __forceinline__ bool electron3(const G3& g, const F3<R>& f, const Box
     const double r0[3] = {e.x[p], e.y[p], e.z[p]};
     if (LDS && !in_box(bx, r0)) return false;
     R E[3], B[3];
-    if constexpr (LDS) gather_box(bx, r0, E, B);
-    else gather3(g, f, r0, E, B);
+    if constexpr (LDS) gather_box<MC>(bx, r0, E, B);
+    else gather3<MC>(g, f, r0, E, B);
     const R h = (R)(-0.5 * pp.dt);
     R ux = e.ux[p], uy = e.uy[p], uz = e.uz[p];
-    const R umx = ux + h * E[0], umy = uy + h * E[1], umz = uz + h * E[2];
-    const R ig = rsq(R(1) + umx * umx + umy * umy + umz * umz);
-    const R tx = h * B[0] * ig, ty = h * B[1] * ig, tz = h * B[2] * ig;
-    const R sf = R(2) / (R(1) + tx * tx + ty * ty + tz * tz);
-    const R sx = sf * tx, sy = sf * ty, sz = sf * tz;
-    const R upx = umx + (umy * tz - umz * ty), upy = umy + (umz * tx - umx * tz), upz = umz + (umx * ty - umy * tx);
-    ux = umx + (upy * sz - upz * sy) + h * E[0];
-    uy = umy + (upz * sx - upx * sz) + h * E[1];
-    uz = umz + (upx * sy - upy * sx) + h * E[2];
+    if (pp.vay) {
+        // Vay (Phys. Plasmas 15, 056701): u' = u + (q dt/m)(E + v x B/2), tau = (q dt/2m) B,
+        // gamma^2 = (sigma + sqrt(sigma^2 + 4 (tau^2 + (u'.tau)^2)))/2 with sigma = gamma'^2 - tau^2,
+        // t = tau/gamma, u = (u' + (u'.t) t + u' x t)/(1 + t^2)
+        const R ig0 = rsq(R(1) + ux * ux + uy * uy + uz * uz);
+        const R vx = ux * ig0, vy = uy * ig0, vz = uz * ig0;
+        const R t0x = h * B[0], t0y = h * B[1], t0z = h * B[2];
+        const R upx = ux + R(2) * h * E[0] + (vy * t0z - vz * t0y);
+        const R upy = uy + R(2) * h * E[1] + (vz * t0x - vx * t0z);
+        const R upz = uz + R(2) * h * E[2] + (vx * t0y - vy * t0x);
+        const R us = upx * t0x + upy * t0y + upz * t0z;
+        const R tau2 = t0x * t0x + t0y * t0y + t0z * t0z;
+        const R sig = R(1) + upx * upx + upy * upy + upz * upz - tau2;
+        const R ign = rsq(R(0.5) * (sig + sqrt(sig * sig + R(4) * (tau2 + us * us))));
+        const R tx = t0x * ign, ty = t0y * ign, tz = t0z * ign;
+        const R sf = R(1) / (R(1) + tx * tx + ty * ty + tz * tz);
+        const R ut = upx * tx + upy * ty + upz * tz;
+        ux = sf * (upx + ut * tx + (upy * tz - upz * ty));
+        uy = sf * (upy + ut * ty + (upz * tx - upx * tz));
+        uz = sf * (upz + ut * tz + (upx * ty - upy * tx));
+    } else {
+        const R umx = ux + h * E[0], umy = uy + h * E[1], umz = uz + h * E[2];
+        const R ig = rsq(R(1) + umx * umx + umy * umy + umz * umz);
+        const R tx = h * B[0] * ig, ty = h * B[1] * ig, tz = h * B[2] * ig;
+        const R sf = R(2) / (R(1) + tx * tx + ty * ty + tz * tz);
+        const R sx = sf * tx, sy = sf * ty, sz = sf * tz;
+        const R upx = umx + (umy * tz - umz * ty), upy = umy + (umz * tx - umx * tz), upz = umz + (umx * ty - umy * tx);
+        ux = umx + (upy * sz - upz * sy) + h * E[0];
+        uy = umy + (upz * sx - upx * sz) + h * E[1];
+        uz = umz + (upx * sy - upy * sx) + h * E[2];
+    }
     const R gi = rsq(R(1) + ux * ux + uy * uy + uz * uz);
     double r1[3] = {r0[0] + pp.dtd[0] * (double)(ux * gi), r0[1] + pp.dtd[1] * (double)(uy * gi),
                     r0[2] + pp.dtd[2] * (double)(uz * gi)};
@@ -865,7 +894,7 @@ __device__ __forceinline__ void box_of(const Box3& bb, int pz, BoxL<R>& bx, bool
 
 // Staged segments.  A segment whose box exceeds the LDS pitches goes to the list big, a particle
 // outside its segment's box to the list mis (segment, particle); k3_gpd_hbm pushes both.
-template <typename R>
+template <typename R, bool MC>
 __global__ void __launch_bounds__(GT) k3_gpd(G3 g, F3<R> f, E3<R> e, const Seg3* __restrict__ seg,
                                              const Box3* __restrict__ bin, Box3* __restrict__ bout, Push3 pp, int pz,
                                              int* status, int* big, int* nbig, int2* mis, int* nmis)
@@ -892,10 +921,10 @@ __global__ void __launch_bounds__(GT) k3_gpd(G3 g, F3<R> f, E3<R> e, const Seg3*
                 const double bound = fmax(fabs(pp.jk[0]), fmax(fabs(pp.jk[1]), fabs(pp.jk[2]))) * sw;
                 if (bound > 0.0) { js = FX_RANGE / bound; jq = bound / FX_RANGE; }
             }
-            stage_box<GT, R, true>(g, f, bx, 3);
+            stage_box<GT, R, true, MC>(g, f, bx, 3);
             __syncthreads();
             for (int p = sg.start + threadIdx.x; p < end; p += GT)
-                if (!electron3<true>(g, f, bx, e, p, pp, js, status, nb)) mis[atomicAdd(nmis, 1)] = make_int2(blockIdx.x, p);
+                if (!electron3<true, MC>(g, f, bx, e, p, pp, js, status, nb)) mis[atomicAdd(nmis, 1)] = make_int2(blockIdx.x, p);
             __syncthreads();
             flush_box<GT>(g, f, bx, 0, 3, jq);
         } else if (threadIdx.x == 0) {
@@ -926,7 +955,7 @@ __device__ __forceinline__ void wave_grow(int nb[6], Box3* out)
 // the particles k3_gpd left: whole segments of list big (one workgroup each, in turn) and
 // single particles of list mis, on the fields and current in HBM; their cells widen the
 // segments' next boxes
-template <typename R>
+template <typename R, bool MC>
 __global__ void __launch_bounds__(NT) k3_gpd_hbm(G3 g, F3<R> f, E3<R> e, const Seg3* __restrict__ seg,
                                                  Box3* __restrict__ bout, Push3 pp, int* status, const int* big,
                                                  const int* nbig, const int2* mis, const int* nmis)
@@ -940,7 +969,7 @@ __global__ void __launch_bounds__(NT) k3_gpd_hbm(G3 g, F3<R> f, E3<R> e, const S
         for (int base = sg.start; base < end; base += NT) {
             int nb[6] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN};
             const int p = base + threadIdx.x;
-            if (p < end) electron3<false>(g, f, none, e, p, pp, 1.0, status, nb);
+            if (p < end) electron3<false, MC>(g, f, none, e, p, pp, 1.0, status, nb);
             wave_grow(nb, &bout[q]);
         }
     }
@@ -952,7 +981,7 @@ __global__ void __launch_bounds__(NT) k3_gpd_hbm(G3 g, F3<R> f, E3<R> e, const S
         if (i < nm) {
             const int2 m = mis[i];
             q = m.x;
-            electron3<false>(g, f, none, e, m.y, pp, 1.0, status, nb);
+            electron3<false, MC>(g, f, none, e, m.y, pp, 1.0, status, nb);
         }
         // lanes may belong to different segments: one atomic set per lane
         if (i < nm && nb[0] <= nb[1]) {
@@ -1808,19 +1837,61 @@ void launch3_zero_j(const G3& g, const F3<R>& f, hipStream_t s)
     hipLaunchKernelGGL(k3_zero3, cells_grid(g), cells_block(), 0, s, g, f.J[0], f.J[1], f.J[2]);
 }
 
-template <typename R>
-void launch3_gpd(const G3& g, const F3<R>& f, const E3<R>& e, const Seg3* seg, const Box3* bin, Box3* bout,
-                 int nseg, const Push3& pp, int pz, int* status, int* lists, int2* mis, hipStream_t s)
+template <typename R, bool MC>
+void gpd_launch(const G3& g, const F3<R>& f, const E3<R>& e, const Seg3* seg, const Box3* bin, Box3* bout,
+                int nseg, const Push3& pp, int pz, int* status, int* lists, int2* mis, hipStream_t s)
 {
-    if (nseg <= 0) return;
     const size_t lds = (size_t)BPL * pz * box_cell_bytes<R>();
     int *nbig = lists, *nmis = lists + 1, *big = lists + 2;
     (void)hipMemsetAsync(lists, 0, 2 * sizeof(int), s);
-    (void)hipFuncSetAttribute((const void*)k3_gpd<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k3_gpd<R>), dim3(nseg), dim3(GT), lds, s, g, f, e, seg, bin, bout, pp, pz, status, big,
+    (void)hipFuncSetAttribute((const void*)k3_gpd<R, MC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k3_gpd<R, MC>), dim3(nseg), dim3(GT), lds, s, g, f, e, seg, bin, bout, pp, pz, status, big,
                        nbig, mis, nmis);
-    hipLaunchKernelGGL((k3_gpd_hbm<R>), dim3(std::min(HBM_GRID, nseg)), dim3(NT), 0, s, g, f, e, seg, bout, pp,
+    hipLaunchKernelGGL((k3_gpd_hbm<R, MC>), dim3(std::min(HBM_GRID, nseg)), dim3(NT), 0, s, g, f, e, seg, bout, pp,
                        status, big, nbig, mis, nmis);
+}
+
+template <typename R>
+void launch3_gpd(const G3& g, const F3<R>& f, const E3<R>& e, const Seg3* seg, const Box3* bin, Box3* bout,
+                 int nseg, const Push3& pp, int pz, int* status, int* lists, int2* mis, bool mc, hipStream_t s)
+{
+    if (nseg <= 0) return;
+    if (mc) gpd_launch<R, true>(g, f, e, seg, bin, bout, nseg, pp, pz, status, lists, mis, s);
+    else gpd_launch<R, false>(g, f, e, seg, bin, bout, nseg, pp, pz, status, lists, mis, s);
+}
+
+// ---- momentum-conserving gather: fields to the nodes ---------------------------------------------
+// E_c at a node is the mean of its two values at -1/2 and +1/2 along c; B_c the mean of its four
+// values at -+1/2 along the two other axes (B^n = (B^{n-1/2} + B^{n+1/2}) / 2); locations beyond a
+// non-periodic edge read 0
+template <typename R>
+__global__ void __launch_bounds__(NT) k3_nodes(G3 g, F3<R> f)
+{
+    int q[3];
+    if (!cell_of(g, q)) return;
+    int lo[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) lo[a] = nb(q[a], -1, g.S[a], g.per[a]);
+    auto at = [&](const R* A, int i, int j, int k) {
+        return (i < 0 || j < 0 || k < 0) ? R(0) : A[o3(g, i, j, k)];
+    };
+    auto bn = [&](int c, int i, int j, int k) { return R(0.5) * (at(f.B[c], i, j, k) + at(f.Bo[c], i, j, k)); };
+    const long o = o3(g, q[0], q[1], q[2]);
+    f.G[0][o] = R(0.5) * (at(f.E[0], lo[0], q[1], q[2]) + at(f.E[0], q[0], q[1], q[2]));
+    f.G[1][o] = R(0.5) * (at(f.E[1], q[0], lo[1], q[2]) + at(f.E[1], q[0], q[1], q[2]));
+    f.G[2][o] = R(0.5) * (at(f.E[2], q[0], q[1], lo[2]) + at(f.E[2], q[0], q[1], q[2]));
+    f.G[3][o] = R(0.25) * ((bn(0, q[0], lo[1], lo[2]) + bn(0, q[0], q[1], lo[2])) +
+                           (bn(0, q[0], lo[1], q[2]) + bn(0, q[0], q[1], q[2])));
+    f.G[4][o] = R(0.25) * ((bn(1, lo[0], q[1], lo[2]) + bn(1, q[0], q[1], lo[2])) +
+                           (bn(1, lo[0], q[1], q[2]) + bn(1, q[0], q[1], q[2])));
+    f.G[5][o] = R(0.25) * ((bn(2, lo[0], lo[1], q[2]) + bn(2, q[0], lo[1], q[2])) +
+                           (bn(2, lo[0], q[1], q[2]) + bn(2, q[0], q[1], q[2])));
+}
+
+template <typename R>
+void launch3_nodes(const G3& g, const F3<R>& f, hipStream_t s)
+{
+    hipLaunchKernelGGL((k3_nodes<R>), cells_grid(g), cells_block(), 0, s, g, f);
 }
 
 template <typename R>
@@ -1916,7 +1987,8 @@ void launch3_stations(const G3& g, const F3<R>& f, const double* zlab, int nst, 
                                  int, double, double, double, double*, hipStream_t);                       \
     template void launch3_count_live<R>(const R*, int, int*, hipStream_t);                                  \
     template void launch3_gpd<R>(const G3&, const F3<R>&, const E3<R>&, const Seg3*, const Box3*, Box3*, int,  \
-                                 const Push3&, int, int*, int*, int2*, hipStream_t);                        \
+                                 const Push3&, int, int*, int*, int2*, bool, hipStream_t);                  \
+    template void launch3_nodes<R>(const G3&, const F3<R>&, hipStream_t);                                   \
     template void launch3_gpi<R>(const G3&, const F3<R>&, const I3<R>&, const Seg3*, const Box3*, Box3*, int,  \
                                  double, double, double, const Push3&, int, hipStream_t);                   \
     template void launch3_antenna<R>(const G3&, const F3<R>&, double*, const double*, const double*,        \

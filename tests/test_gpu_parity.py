@@ -430,3 +430,45 @@ def test_gauss_law_fp32_long_run():
     _LOG.append(("gauss fp32 200 steps", {"drift_over_max_rho": drift / rho,
                                            "drift_over_E_rounding_scale": drift / escale}))
     assert drift <= 2.0 ** -22 * escale
+
+
+# ---------------------------------------------------------------------------------------
+# gather and pusher variants: momentum-conserving gather (fields to the nodes first, Sec.
+# 5.3) and Vay's pusher, against the oracle
+# ---------------------------------------------------------------------------------------
+
+@gpu
+@pytest.mark.parametrize("real,gather,pusher,tol", [("f64", 1, 0, 1e-11), ("f64", 0, 1, 1e-11),
+                                                     ("f32", 1, 1, 1e-5)])
+def test_gather_and_pusher_variants_match_oracle(real, gather, pusher, tol):
+    w = pi.small_boosted(real=real, nx=40, nz=120, ppc=2)
+    w["config"]["gather_kind"] = gather
+    w["config"]["pusher"] = pusher
+    sim, ref = _sim(w), Oracle.from_workload(w)
+    for n in (10, 30):
+        sim.step(n)
+        ref.step(n)
+    compare_fields(sim, ref, tol, tag=f"variant g{gather} p{pusher} {real}")
+    if real == "f64":
+        compare_particles(sim, ref, 1e-9, 1e-9)
+
+
+@gpu
+def test_variants_random_state_single_step():
+    nx, nz = 37, 53
+    cfg = pi.make_config(nx, nz, 0.1, 0.13, periodic_x=1, periodic_z=1, pml_cells=0, ck="ck2", theta=0.3,
+                         filter_npass=2, filter_compensate=1, real="f64", seed=5, gather_kind=1, pusher=1)
+    from paper_1009_2727_amd import Sim
+    sim = Sim(cfg, capacity=20000)
+    ref = Oracle(cfg)
+    for k, name in enumerate(["Ex", "Ey", "Ez", "Bx", "By", "Bz", "Exo", "Eyo", "Ezo", "Exb", "Eyb", "Ezb"]):
+        f = pi.random_field(ref.shape, seed=300 + k, amp=0.5)
+        ref.set_field(name, f)
+        sim.set_field(name, f)
+    p = pi.random_electrons(5000, nx, nz, 0.1, 0.13, seed=13, umax=3.0, margin=0.0)
+    ref.set_electrons(p)
+    sim.load_electrons(p)
+    ref.step(1)
+    sim.step(1)
+    compare_fields(sim, ref, 1e-12, tag="variants random")
+    compare_particles(sim, ref, 1e-9, 1e-10)

@@ -273,3 +273,42 @@ def test_3d_stride_filter_and_y_polarisation(real, tol):
     assert np.abs(ref.field("Ey")).max() > np.abs(ref.field("Ex")).max()
     compare_fields3(sim, ref, tol)
     np.testing.assert_allclose(sim.antenna(), ref.antenna(), atol=1e-12)
+
+
+@gpu
+@pytest.mark.parametrize("real,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_3d_momentum_gather_and_vay_match_oracle(real, tol):
+    w = pi.small_boosted3(real=real, nx=12, ny=10, nz=48, ppc=2)
+    w["config"]["gather_kind"] = 1
+    w["config"]["pusher"] = 1
+    sim, ref = _sim(w, sort_every=7), Oracle3.from_workload(w)
+    sim.step(20)
+    ref.step(20)
+    compare_fields3(sim, ref, tol)
+    if real == "f64":
+        compare_particles3(sim, ref, 1e-9, 1e-9)
+
+
+@gpu
+def test_3d_variants_random_state_single_step():
+    nx, ny, nz = 11, 9, 13
+    d = (0.1, 0.12, 0.09)
+    cfg = pi.make_config3(nx, ny, nz, *d, periodic_x=1, periodic_y=1, periodic_z=1, pml_cells=0, ck="ck2",
+                          theta=0.3, filter_npass=2, filter_compensate=1, real="f64", seed=5, gather_kind=1,
+                          pusher=1)
+    from paper_1009_2727_amd import Sim
+    sim = Sim(cfg, capacity=4000)
+    ref = Oracle3(cfg)
+    for k, name in enumerate(["Ex", "Ey", "Ez", "Bx", "By", "Bz", "Exo", "Eyo", "Ezo", "Exb", "Eyb", "Ezb"]):
+        f = pi.random_field(ref.shape, seed=400 + k, amp=0.5)
+        ref.set_field(name, f)
+        sim.set_field(name, f)
+    p = pi.random_electrons3(3000, nx, ny, nz, d, seed=14, umax=3.0, margin=0.0)
+    ref.set_electrons(p)
+    sim.load_electrons(p)
+    ref.step(1)
+    sim.step(1)
+    for n in FIELDS:
+        a, b = sim.field(n), ref.field(n)
+        assert np.abs(a - b).max() <= 1e-12 * max(np.abs(b).max(), 1.0), n
+    compare_particles3(sim, ref, 1e-9, 1e-10)
