@@ -398,6 +398,75 @@ def bench_learned_filter_study(args):
     }
 
 
+def bench_dt_scan(args):
+    """Growth of the high-frequency instability against the time step (Sec. 5.3, "Effects of time
+    step"): the boosted instability family (gamma = 13, 1e19 cm^-3 pre-loaded, square cells of
+    lambda*/32, no laser, no filter, no damping) with the CK solver, c dt / dz from 0.5 to 0.99 of
+    the 2D CK limit (c dt = dz), for the energy-conserving and the momentum-conserving gather.
+    Growth rate: slope per step of ln(high-k E_z energy) over the second half of the run."""
+    import pic_inputs as pi
+    from paper_1009_2727_amd import filter_training as ft
+    ratios = [float(r) for r in args.dt_ratios.split(",")]
+    if args.dt_case == "stage":
+        return dt_scan_stage(args, ratios)
+    g, n0 = args.dt_gamma, args.dt_density
+    out = {"metric": "instability growth rate per step vs c dt / dz", "data": "synthetic",
+           "config": {"workload": f"boosted gamma={g:g}, {n0:g} cm^-3 pre-loaded, 64x512 cells of lambda*/32, "
+                                  "4 ppc, CK solver, theta = 0, no filter, no laser", "steps": args.dt_steps},
+           "dt_over_dz": ratios, "growth": {}, "growth_per_unit_time": {}}
+    t0 = time.perf_counter()
+    for name, kind in (("energy_conserving", 0), ("momentum_conserving", 1)):
+        rates = []
+        for r in ratios:
+            w = pi.c5_growth(npass=0, comp=0, gamma=g, n0=n0)
+            w["config"].update(pi.make_config(w["config"]["nx"], w["config"]["nz"], w["config"]["dx_um"],
+                                              w["config"]["dz_um"], pml_cells=10, ck="ck", theta=0.0,
+                                              cfl_fraction=r, gamma_boost=w["config"]["gamma_boost"],
+                                              moving_window=1, seed=w["config"]["seed"], real="f32",
+                                              gather_kind=kind))
+            rates.append(ft.growth_rate(w, None, steps=args.dt_steps, every=10)[0])
+            print(f"[dtscan] {name} c dt/dz = {r:.3f}: {rates[-1]:.4g}", file=sys.stderr, flush=True)
+        out["growth"][name] = rates
+        out["growth_per_unit_time"][name] = [rt / r for rt, r in zip(rates, ratios)]   # per dz / c
+        out[f"min_{name}"] = ratios[int(np.argmin(rates))]
+    out["seconds"] = time.perf_counter() - t0
+    return out
+
+
+def dt_scan_stage(args, ratios):
+    """The time-step scan on the full-scale 10 GeV stage in the wake frame (gamma = 130, 6.5 um
+    cells, plasma entering at the front, CK solver, no filter or damping): the level of the
+    high-frequency instability as the high-k part (|k| > k_max / 2) of the E_z spectrum at a fixed
+    boosted-frame time T (the same physical time for every time step), for both gathers."""
+    import pic_inputs as pi
+    from paper_1009_2727_amd import Sim
+    from paper_1009_2727_amd import filter_training as ft
+    T = args.dt_time_ps * 1e-12 * 2.99792458e14            # um / c
+    out = {"metric": "high-k E_z energy at fixed time vs c dt / dz", "data": "synthetic",
+           "config": {"workload": pi.stage_10gev()["name"].split(", c dt")[0] + ", CK, no filter or damping",
+                      "time_ps": args.dt_time_ps},
+           "dt_over_dz": ratios, "highk_energy": {}, "total_energy": {}}
+    t0 = time.perf_counter()
+    for name, kind in (("energy_conserving", 0), ("momentum_conserving", 1)):
+        hk, tot = [], []
+        for r in ratios:
+            w = pi.stage_10gev(cfl=r, gather_kind=kind)
+            sim = Sim.from_workload(w)
+            n = int(round(T / sim.info()["dt"]))
+            sim.step(n)
+            ez = sim.field("Ez")
+            hk.append(ft.highk_energy(ez))
+            tot.append(float((ez.astype(np.float64) ** 2).sum()))
+            print(f"[dtscan] {name} c dt/dz = {r:.4f}: {n} steps, high-k {hk[-1]:.4g}, total {tot[-1]:.4g}",
+                  file=sys.stderr, flush=True)
+            del sim
+        out["highk_energy"][name] = hk
+        out["total_energy"][name] = tot
+        out[f"min_{name}"] = ratios[int(np.argmin(hk))]
+    out["seconds"] = time.perf_counter() - t0
+    return out
+
+
 def read_pmc(workload: str):
     path = PMC[workload][0]
     if not os.path.exists(path):
@@ -463,15 +532,24 @@ def main():
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("WORKLOAD", "FETCH_DIR", "WRITE_DIR", "COPY_GIB"))
-    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "dtscan"], default="c3",
                     help="c3: the 3D 128x128x1024 boosted run (default, with c2 beside it); c2: the 256x4096 "
                          "boosted run; c4: the batched scan of independent boosted runs (persistent batched "
-                         "launch vs one run at a time); c5: learned vs plain current filter")
+                         "launch vs one run at a time); c5: learned vs plain current filter; dtscan: "
+                         "instability growth rate against the time step for both gathers")
     ap.add_argument("--cpu-steps3", type=int, default=8)
     ap.add_argument("--c4-runs", type=int, default=64)
     ap.add_argument("--c4-scale", type=float, default=1.0, help="grid scale of the scan's runs")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--c5-train-steps", type=int, default=3000)
+    ap.add_argument("--dt-ratios", default="0.5,0.55,0.6,0.65,0.7,0.7071,0.75,0.8,0.85,0.9,0.95,0.99")
+    ap.add_argument("--dt-steps", type=int, default=600)
+    ap.add_argument("--dt-gamma", type=float, default=13.0)
+    ap.add_argument("--dt-density", type=float, default=1e19)
+    ap.add_argument("--dt-case", choices=["growth", "stage"], default="stage",
+                    help="stage: the 10 GeV stage at gamma = 130 (instability level at fixed time); "
+                         "growth: the pre-loaded instability family (growth-rate slope)")
+    ap.add_argument("--dt-time-ps", type=float, default=40.0)
     args = ap.parse_args()
 
     if args.summarize_pmc:
@@ -493,6 +571,9 @@ def main():
         return
     if args.workload == "c5":
         print(json.dumps(bench_learned_filter_study(args)), flush=True)
+        return
+    if args.workload == "dtscan":
+        print(json.dumps(bench_dt_scan(args)), flush=True)
         return
 
     if args.calib_copy_gib > 0:

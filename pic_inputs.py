@@ -175,6 +175,28 @@ def c5_growth(real="f32", nx=64, nz=512, ppc=4, gamma=13.0, n0=1e19, npass=4, co
     )
 
 
+def stage_10gev(real="f32", nx=128, nz=2048, ppc=4, gamma=130.0, cfl=0.7071, ck="ck", gather_kind=0,
+                seed=1017):
+    """A full-scale 10 GeV class stage in the wake frame (Sec. 5.2, 5.3): lab density 1e17 cm^-3
+    (gamma_w ~ 132) with a 20 um up-ramp starting just ahead of the box, so the plasma enters at
+    the front and streams through; boosted frame gamma = 130 with square cells of 6.5 um (lambda*/32);
+    laser a0 = 1, waist 50 um, FWHM half a plasma wavelength (176 fs), the antenna at 60% of the box;
+    CK solver without damping or filter (the high-frequency instability of Sec. 4 left free), c dt /
+    dz = cfl (the 2D CK limit is c dt = dz); moving window; rigid ions."""
+    d = boosted_cell(gamma)
+    z_ant = gamma * 0.6 * nz * d
+    fwhm = 0.5 * 105.6 / 0.299792458
+    return dict(
+        name=f"10 GeV stage gamma={gamma:g} {nx}x{nz}, {ppc} ppc, 1e17 cm^-3, c dt/dz={cfl:.4g}",
+        config=make_config(nx, nz, d, d, pml_cells=10, ck=ck, theta=0.0, cfl_fraction=cfl, filter_npass=0,
+                           filter_compensate=0, gamma_boost=gamma, moving_window=1, seed=seed, real=real,
+                           gather_kind=gather_kind),
+        plasma=plasma(1e17, ppc, ramp_um=20.0, start_um=gamma * (nz + 2) * d, ion_mode=1),
+        laser=laser(1.0, 50.0, fwhm, z_ant),
+        steps=0,
+    )
+
+
 def small_lab(real="f64", nx=24, nz=96, ppc=4, seed=77, npass=1, comp=0, ck="yee", theta=0.0):
     """A C1-shaped lab-frame case the oracle finishes in seconds (several tiles + ragged tail)."""
     w = c1(real, nx=nx, nz=nz, ppc=ppc)
