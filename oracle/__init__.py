@@ -60,6 +60,10 @@ class _Laser(C.Structure):
                 ("pol", C.c_int)]
 
 
+class _Beam(C.Structure):
+    _fields_ = [("beta_b", C.c_double), ("z_inj_um", C.c_double), ("test_only", C.c_int)]
+
+
 class _Info(C.Structure):
     _fields_ = [("dt", C.c_double), ("dt_crit", C.c_double), ("beta", C.c_double),
                 ("gamma", C.c_double), ("v_window", C.c_double), ("n0_norm", C.c_double),
@@ -116,6 +120,13 @@ def lib():
         _lib.orc_gather_at.argtypes = [P, C.c_double, C.c_double, D]
         _lib.orc_deposit_one.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_double,
                                          C.c_double, C.c_double, C.c_double]
+        _lib.orc_add_beam.argtypes = [P, C.POINTER(_Beam), C.c_long, D, D, D, D, D, D, C.c_long]
+        _lib.orc_beam_state.restype = C.c_long
+        _lib.orc_beam_state.argtypes = [P, D]
+        _lib.orc_beam_history.restype = C.c_long
+        _lib.orc_beam_history.argtypes = [P, D, C.c_long]
+        _lib.orc_beam_transform.argtypes = [P, C.POINTER(_Beam), C.c_double, C.c_double, C.c_double,
+                                            C.c_double, C.c_double, D]
         _lib.orc_set_threads.argtypes = [C.c_int]
         _lib.orc_threads.restype = C.c_int
         _lib.orc_splitmix64.restype = C.c_uint64
@@ -264,6 +275,40 @@ class Oracle:
         """E^n and B^n at (x, z) (um) as the particle stage gathers them: Ex, Ey, Ez, Bx, By, Bz."""
         out = np.zeros(6)
         lib().orc_gather_at(self._h, x, z, _dp(out))
+        return out
+
+    def add_beam(self, beam: dict, parts: dict, history_cap: int = 100000):
+        """Particle beam through a lab-fixed plane (Sec. 3.1.1).  beam: beta_b, z_inj_um,
+        test_only; parts: x (um, interior-relative), z (lab um), ux, uy, uz (lab), w."""
+        b = _Beam(beta_b=beam["beta_b"], z_inj_um=beam["z_inj_um"], test_only=int(beam.get("test_only", 1)))
+        cols = [np.ascontiguousarray(parts[k], dtype=np.float64) for k in ("x", "z", "ux", "uy", "uz", "w")]
+        r = lib().orc_add_beam(self._h, C.byref(b), len(cols[0]), *[_dp(c) for c in cols], history_cap)
+        if r != 0:
+            raise ValueError("orc_add_beam rejected the beam")
+
+    def beam(self) -> dict:
+        """x, z (um, window frame), ux, uy, uz (calculation frame), w, t_act, state."""
+        n = lib().orc_beam_state(self._h, None)
+        out = np.zeros(8 * max(n, 0))
+        if n > 0:
+            lib().orc_beam_state(self._h, _dp(out))
+        cols = out.reshape(8, max(n, 0))
+        return {k: cols[q] for q, k in enumerate(("x", "z", "ux", "uy", "uz", "w", "t_act", "state"))}
+
+    def beam_history(self) -> np.ndarray:
+        """(records, 8): t', count, sum w, sum w z_lab, sum w t_lab, sum w gamma_lab,
+        sum w u_z,lab, sum w u_z,lab^2."""
+        n = lib().orc_beam_history(self._h, None, 0)
+        out = np.zeros((max(n, 0), 8))
+        if n > 0:
+            lib().orc_beam_history(self._h, _dp(out), n)
+        return out
+
+    def beam_transform(self, beam: dict, x, z, ux, uy, uz) -> np.ndarray:
+        """t'*, x*, z'(0), u'x, u'y, u'z of one lab particle."""
+        b = _Beam(beta_b=beam["beta_b"], z_inj_um=beam["z_inj_um"], test_only=int(beam.get("test_only", 1)))
+        out = np.zeros(6)
+        lib().orc_beam_transform(self._h, C.byref(b), x, z, ux, uy, uz, _dp(out))
         return out
 
     def deposit_one(self, q, w, x0, z0, x1, z1, vy):

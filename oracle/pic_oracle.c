@@ -75,6 +75,10 @@ struct orc_sim {
     int na, pol; double *ax_home, *ax_minus; double aw, az_lab, sig_t, t0, w0;
     /* stations */
     int nst; station_t st[16];
+    /* particle beam (Sec. 3.1.1) */
+    int have_beam; orc_beam beam; double vbar;   /* boosted mean velocity of the beam */
+    long nb; double *bx, *bz, *bux, *buy, *buz, *bw, *btact; int* bst;
+    long nh, hcap; double* hist;
 };
 
 /* ------------------------------------------------------------------ */
@@ -253,6 +257,8 @@ void orc_destroy(orc_sim* s)
     free(s->iid); free(s->ix); free(s->iz0); free(s->iw);
     free(s->ax_home); free(s->ax_minus);
     for (int i = 0; i < s->nst; i++) free(s->st[i].rec);
+    free(s->bx); free(s->bz); free(s->bux); free(s->buy); free(s->buz); free(s->bw); free(s->btact);
+    free(s->bst); free(s->hist);
     free(s);
 }
 
@@ -774,6 +780,166 @@ static double antenna_field(const orc_sim* s, double x, double t)
     return (s->e0 / s->gamma) * f * sin(s->omega * tau);
 }
 
+/* ------------------------------------------------------------------ */
+/* particle beam through a lab-fixed plane (Sec. 3.1.1)                */
+/* ------------------------------------------------------------------ */
+
+/* The boosted-frame state of one lab macro-particle, in the paper's three steps:
+   (1) ballistic projection onto the plane: the particle at z at t = 0 crosses the plane at
+       lab time -t* with t* = (z - z_inj)/v_z, at transverse position x* = x - v_x t*
+       (Eqs. t*, x*); momenta unchanged;
+   (2) Lorentz transformation of the crossing event (t = -t*, z = z_inj) and of the momentum:
+       t'* = gamma (-t* - beta z_inj), z'* = gamma (z_inj + beta t*) (Eqs. tp*, zp*, which
+       they reduce to when the plane is at the origin), u'_perp = u_perp,
+       u'_z = gamma (u_z - beta gamma_p)  (Eqs. vxp*, vzp* for each particle's own v_z);
+   (3) synchronisation at t' = 0: z'(0) = z'* - vbar' t'* (Eq. zp), vbar' the boosted mean
+       beam velocity (beta_b - beta)/(1 - beta beta_b).
+   out = t'*, x*, z'(0), u'_x, u'_y, u'_z. */
+static void beam_transform(double gamma, double beta, const orc_beam* b, double x, double z, double ux,
+                           double uy, double uz, double out[6])
+{
+    double gp = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+    double vx = ux / gp, vz = uz / gp;
+    double ts = (z - b->z_inj_um) / vz;
+    double xs = x - vx * ts;
+    double tp = gamma * (-ts - beta * b->z_inj_um);
+    double zp = gamma * (b->z_inj_um + beta * ts);
+    double vbar = (b->beta_b - beta) / (1.0 - beta * b->beta_b);
+    out[0] = tp;
+    out[1] = xs;
+    out[2] = zp - vbar * tp;
+    out[3] = ux;
+    out[4] = uy;
+    out[5] = gamma * (uz - beta * gp);
+}
+
+void orc_beam_transform(const orc_sim* s, const orc_beam* b, double x, double z, double ux, double uy,
+                        double uz, double out[6])
+{
+    beam_transform(s->gamma, s->beta, b, x, z, ux, uy, uz, out);
+}
+
+int orc_add_beam(orc_sim* s, const orc_beam* b, long n, const double* x, const double* z, const double* ux,
+                 const double* uy, const double* uz, const double* w, long history_cap)
+{
+    if (!s || !b || n < 0 || history_cap < 0 || !(b->beta_b > 0.0 && b->beta_b < 1.0)) return -1;
+    for (long p = 0; p < n; p++)
+        if (!(uz[p] > 0.0)) return -1;     /* every particle must reach the plane moving forward */
+    free(s->bx); free(s->bz); free(s->bux); free(s->buy); free(s->buz); free(s->bw); free(s->btact);
+    free(s->bst); free(s->hist);
+    long m = n > 0 ? n : 1;
+    s->bx = (double*)malloc(m * sizeof(double)); s->bz = (double*)malloc(m * sizeof(double));
+    s->bux = (double*)malloc(m * sizeof(double)); s->buy = (double*)malloc(m * sizeof(double));
+    s->buz = (double*)malloc(m * sizeof(double)); s->bw = (double*)malloc(m * sizeof(double));
+    s->btact = (double*)malloc(m * sizeof(double)); s->bst = (int*)malloc(m * sizeof(int));
+    s->hcap = history_cap;
+    s->hist = (double*)calloc((size_t)(history_cap > 0 ? history_cap : 1) * 8, sizeof(double));
+    s->nh = 0;
+    s->beam = *b;
+    s->vbar = (b->beta_b - s->beta) / (1.0 - s->beta * b->beta_b);
+    const double Lx = s->ax.N * s->ax.d, Lz = s->az.N * s->az.d;
+    for (long p = 0; p < n; p++) {
+        double q[6];
+        beam_transform(s->gamma, s->beta, b, x[p], z[p], ux[p], uy[p], uz[p], q);
+        s->btact[p] = q[0];
+        s->bx[p] = q[1];
+        /* frozen since t' = 0: at the current time it has moved vbar' t */
+        s->bz[p] = q[2] + s->vbar * s->t - (double)s->shift * s->az.d;
+        if (s->cfg.periodic_x) s->bx[p] -= Lx * floor(s->bx[p] / Lx);
+        if (s->cfg.periodic_z) s->bz[p] -= Lz * floor(s->bz[p] / Lz);
+        s->bux[p] = q[3]; s->buy[p] = q[4]; s->buz[p] = q[5];
+        s->bw[p] = w[p];
+        s->bst[p] = 0;
+    }
+    s->nb = n;
+    s->have_beam = 1;
+    return 0;
+}
+
+/* inside the interior on the non-periodic axes */
+static int beam_inside(const orc_sim* s, double x, double z)
+{
+    if (!s->cfg.periodic_x && (x < 0.0 || x >= s->ax.N * s->ax.d)) return 0;
+    if (!s->cfg.periodic_z && (z < 0.0 || z >= s->az.N * s->az.d)) return 0;
+    return 1;
+}
+
+static double wrap_len(double v, double L) { return v < 0.0 ? v + L : (v >= L ? v - L : v); }
+
+/* One step of the beam at t_n: a frozen particle whose crossing time has come (t'* <= t_n)
+   becomes active; frozen particles move along z at vbar', active ones are gathered, pushed
+   and absorbed like plasma electrons.  Frozen and active particles deposit their current
+   (unless test_only) when the step starts inside the interior.  A particle activated outside
+   the interior is lost.  Afterwards one history record of the active particles. */
+static void beam_stage(orc_sim* s, double* const G[6])
+{
+    const double dx = s->ax.d, dz = s->az.d, dt = s->dt;
+    const double Lx = s->ax.N * dx, Lz = s->az.N * dz;
+    const int dep = !s->beam.test_only;
+    double* Jx = FLD(s, ORC_JX); double* Jy = FLD(s, ORC_JY); double* Jz = FLD(s, ORC_JZ);
+    const double t1 = (double)(s->step + 1) * dt;
+    double acc[7] = {0};
+    for (long p = 0; p < s->nb; p++) {
+        if (s->bst[p] == 2) continue;
+        double x = s->bx[p], z = s->bz[p];
+        if (s->bst[p] == 0 && s->btact[p] <= s->t) {
+            s->bst[p] = 1;
+            if (!beam_inside(s, x, z)) { s->bst[p] = 2; continue; }
+        }
+        if (s->bst[p] == 0) {
+            double z1 = z + s->vbar * dt;
+            if (dep && beam_inside(s, x, z)) deposit_into(s, Jx, Jy, Jz, -1.0, s->bw[p], x, z, x, z1, 0.0);
+            if (s->cfg.periodic_z) z1 = wrap_len(z1, Lz);
+            s->bz[p] = z1;
+            continue;
+        }
+        double E[3], B[3];
+        gather_fields(s, G, x / dx, z / dz, E, B);
+        double u[3] = {s->bux[p], s->buy[p], s->buz[p]};
+        if (s->cfg.pusher == 1) orc_vay(-1.0, dt, E, B, u);
+        else orc_boris(-1.0, dt, E, B, u);
+        double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        double x1 = x + dt * u[0] / g, z1 = z + dt * u[2] / g;
+        if (dep) deposit_into(s, Jx, Jy, Jz, -1.0, s->bw[p], x, z, x1, z1, u[1] / g);
+        s->bux[p] = u[0]; s->buy[p] = u[1]; s->buz[p] = u[2];
+        if (!beam_inside(s, x1, z1)) { s->bst[p] = 2; s->bx[p] = x1; s->bz[p] = z1; continue; }
+        /* lab-frame record: z'_abs = window position + window offset, time t_{n+1} */
+        double za = z1 + (double)s->shift * dz;
+        double w = s->bw[p];
+        double zl = s->gamma * (za + s->beta * t1), tl = s->gamma * (t1 + s->beta * za);
+        double gl = s->gamma * (g + s->beta * u[2]), ul = s->gamma * (u[2] + s->beta * g);
+        acc[0] += 1.0; acc[1] += w; acc[2] += w * zl; acc[3] += w * tl; acc[4] += w * gl;
+        acc[5] += w * ul; acc[6] += w * ul * ul;
+        if (s->cfg.periodic_x) x1 = wrap_len(x1, Lx);
+        if (s->cfg.periodic_z) z1 = wrap_len(z1, Lz);
+        s->bx[p] = x1; s->bz[p] = z1;
+    }
+    if (s->nh < s->hcap) {
+        double* r = s->hist + 8 * s->nh++;
+        r[0] = t1;
+        for (int k = 0; k < 7; k++) r[1 + k] = acc[k];
+    }
+}
+
+long orc_beam_state(const orc_sim* s, double* out)
+{
+    long n = s->nb;
+    if (out)
+        for (long p = 0; p < n; p++) {
+            out[p] = s->bx[p]; out[n + p] = s->bz[p]; out[2 * n + p] = s->bux[p];
+            out[3 * n + p] = s->buy[p]; out[4 * n + p] = s->buz[p]; out[5 * n + p] = s->bw[p];
+            out[6 * n + p] = s->btact[p]; out[7 * n + p] = (double)s->bst[p];
+        }
+    return n;
+}
+
+long orc_beam_history(const orc_sim* s, double* out, long cap)
+{
+    long n = s->nh < cap ? s->nh : cap;
+    if (out && n > 0) memcpy(out, s->hist, (size_t)n * 8 * sizeof(double));
+    return s->nh;
+}
+
 void orc_stage_particles(orc_sim* s)
 {
     const double dx = s->ax.d, dz = s->az.d, dt = s->dt;
@@ -829,7 +995,6 @@ void orc_stage_particles(orc_sim* s)
     }
     s->ne = keep;
     free(nxz);
-    if (mc) for (int c = 0; c < 6; c++) free(G[c]);
 
     /* rigid ions: z(t) = z0 - beta c t in the boosted frame, deposit only */
     if (s->plasma.ion_mode == 1) {
@@ -862,6 +1027,9 @@ void orc_stage_particles(orc_sim* s)
         }
     }
     free(priv);
+
+    if (s->have_beam) beam_stage(s, mc ? G : NULL);
+    if (mc) for (int c = 0; c < 6; c++) free(G[c]);
 
     /* laser antenna: a + and a - sheet particle per transverse cell; the - particle moves
        along the polarisation with v = K dx / (q w), K = -2 E_perp the sheet current.  Along
@@ -1059,6 +1227,8 @@ void orc_stage_advance(orc_sim* s)
                 memset(s->f[tang[m]] + last * Sx, 0, Sx * sizeof(double));
             }
             for (long p = 0; p < s->ne; p++) s->ez[p] -= (double)d * s->az.d;
+            for (long p = 0; p < s->nb; p++)
+                if (s->bst[p] != 2) s->bz[p] -= (double)d * s->az.d;
             s->shift = sn;
         }
     }
@@ -1213,6 +1383,10 @@ int orc_charge_density(const orc_sim* s_, double* rho)
         for (long p = 0; p < s->ni; p++)
             deposit_rho(s, rho, 1.0, s->iw[p], s->ix[p],
                         s->iz0[p] - s->beta * s->t - (double)s->shift * s->az.d);
+    if (s->have_beam && !s->beam.test_only)
+        for (long p = 0; p < s->nb; p++)
+            if (s->bst[p] != 2 && beam_inside(s, s->bx[p], s->bz[p]))
+                deposit_rho(s, rho, -1.0, s->bw[p], s->bx[p], s->bz[p]);
     if (s->have_laser) {
         double za = antenna_z(s, s->t);
         if (za >= 0.0 && za < s->az.N * s->az.d)

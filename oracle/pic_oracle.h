@@ -124,6 +124,31 @@ int  orc_gauss_residual(const orc_sim* s, double* out);
 int  orc_charge_density(const orc_sim* s, double* out);
 long orc_station_samples(const orc_sim* s, int station, double* out /* 7 per sample */, long cap);
 
+/* Particle beam launched through a lab-fixed plane (Sec. 3.1.1): the caller gives each
+   macro-particle's lab state at t = 0; the beam is projected ballistically onto the plane,
+   Lorentz transformed, synchronised to t' = 0 and kept frozen (moving along z at the
+   boosted mean velocity, transverse position and momentum fixed) until it crosses the
+   plane, then pushed as an ordinary electron.  Beam particles have charge -1 and mass 1. */
+typedef struct {
+    double beta_b;            /* mean lab velocity of the beam (c = 1), 0 < beta_b < 1      */
+    double z_inj_um;          /* lab position of the injection plane                        */
+    int test_only;            /* 1: the beam deposits no current (test particles)          */
+} orc_beam;
+/* x: um relative to the interior origin; z: lab position (um); u = gamma v lab momenta;
+   w: weights in normalised units.  Replaces a previous beam.  history_cap: records kept. */
+int  orc_add_beam(orc_sim* s, const orc_beam* b, long n, const double* x, const double* z,
+                  const double* ux, const double* uy, const double* uz, const double* w,
+                  long history_cap);
+/* 8 arrays of n doubles: x, z (um, window frame), ux, uy, uz (calculation frame), w,
+   crossing time t'* (um/c), state (0 frozen, 1 active, 2 lost); returns n */
+long orc_beam_state(const orc_sim* s, double* out);
+/* one record per step of the active particles after the push, back-transformed to the lab
+   frame: t'_{n+1}, count, sum w, sum w z_lab, sum w t_lab, sum w gamma_lab, sum w u_z,lab,
+   sum w u_z,lab^2; returns the number of records */
+long orc_beam_history(const orc_sim* s, double* out, long cap);
+/* the boosted-frame quantities of one lab particle (pins): t'*, x*, z'(0), u'x, u'y, u'z */
+void orc_beam_transform(const orc_sim* s, const orc_beam* b, double x, double z, double ux,
+                        double uy, double uz, double out[6]);
 /* one-particle helpers for pins */
 /* E^n and B^n gathered at (x, z) (um, interior-relative) exactly as the particle stage does:
    out = Ex, Ey, Ez, Bx, By, Bz */

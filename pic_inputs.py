@@ -302,3 +302,28 @@ def random_electrons(n, nx, nz, dx, dz, seed, umax=1.0, margin=3.0):
 def random_field(shape, seed, amp=0.1):
     r = np.random.default_rng(seed)
     return amp * (2.0 * r.random(shape) - 1.0)
+
+
+# Beam of the scaled 10 GeV stages (Table "Tablephyspar2d"): radius R_b = 82.5 nm with the
+# transverse profile exp(-r^2 / 8 R_b^2) (a Gaussian of rms 2 R_b), length L_b = 85 nm with
+# exp(-z^2 / 2 L_b^2).  The table gives no energy or spread; they are parameters here.
+BEAM_RB_UM = 0.0825
+BEAM_LB_UM = 0.085
+
+
+def beam_lab(n, *, x_center_um, z_center_um, gamma_b, seed, rb_um=BEAM_RB_UM, lb_um=BEAM_LB_UM,
+             energy_spread=0.0, angle_rms=0.0, weight=1e-6):
+    """n test macro-particles of a lab-frame beam at t = 0: x (um), z (lab um), ux, uy, uz, w.
+    Momenta gamma_b (1 + energy_spread N(0,1)) along z with transverse angles N(0, angle_rms)."""
+    r = np.random.default_rng(seed)
+    g = gamma_b * (1.0 + energy_spread * r.standard_normal(n))
+    u = np.sqrt(g * g - 1.0)
+    tx = np.tan(angle_rms * r.standard_normal(n))
+    ty = np.tan(angle_rms * r.standard_normal(n))
+    norm = np.sqrt(1.0 + tx * tx + ty * ty)
+    return {
+        "x": x_center_um + 2.0 * rb_um * r.standard_normal(n),
+        "z": z_center_um + lb_um * r.standard_normal(n),
+        "ux": u * tx / norm, "uy": u * ty / norm, "uz": u / norm,
+        "w": np.full(n, weight),
+    }
