@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define BF_ABI_VERSION 4u
+#define BF_ABI_VERSION 5u
 
 typedef enum {
     BF_OK = 0,
@@ -89,6 +89,9 @@ typedef struct {
     int station_capacity;      /* samples kept per station                                     */
     int phase_timers;          /* 1: record HIP events around every phase of bf_step          */
     uint64_t seed;             /* counter-based RNG seed for plasma loading                    */
+    int64_t beam_capacity;     /* beam macro-particles bf_add_beam may load (2D runs; 0: none)  */
+    int32_t beam_history;      /* per-step beam records kept (BF_DIAG_BEAM, arg 1)             */
+    int32_t reserved0;
 } bf_config;
 
 /* Plasma given in the lab frame: zero density before start_um, linear up-ramp of ramp_um
@@ -135,6 +138,9 @@ typedef struct {
     int32_t nseg_e, nseg_i;    /* particle segments in use                                     */
     int32_t since_sort;
     int32_t have_plasma, have_laser, nstations;
+    int32_t have_beam, beam_test_only;  /* beam loaded; it deposits no current                 */
+    int64_t beam_n, beam_records;       /* beam macro-particles; history records written      */
+    double beam_vbar;                   /* boosted mean beam velocity (c = 1)                  */
 } bf_state;
 
 /* ---- set-up ---------------------------------------------------------------------------- */
@@ -173,6 +179,34 @@ bf_status bf_load_electrons3(bf_sim* sim, int64_t n, const uint32_t* id, const d
                              const double* y, const double* z, const double* ux, const double* uy,
                              const double* uz, const double* w);
 
+/* Particle beam launched through a lab-fixed plane (Sec. 3.1.1, steps 1-3): the caller gives
+   each macro-particle's LAB state at t = 0 (the standard synchronisation z = z' = 0 at
+   t = t' = 0); the library projects it ballistically onto the plane z = z_inj_um
+   (Eqs. t*, x*), Lorentz transforms the crossing event and the momentum (Eqs. tp*-vzp*, with
+   each particle's own v_z, which they equal at the mean velocity), and synchronises the beam
+   at t' = 0 (Eq. zp) at the boosted mean velocity vbar' = (beta_b - beta)/(1 - beta beta_b).
+   Until a step starts at t_n >= t'* (the particle has crossed the plane) it is frozen: it
+   moves along z at vbar' with transverse position and momentum fixed.  Then it is pushed as
+   an electron (charge -1, mass 1) with the run's gather and pusher, in FP64.  Frozen and
+   active particles deposit their current unless test_only (the beam of the paper's scaled
+   10 GeV stages is made of test particles); a frozen particle deposits only for steps that start inside the
+   interior, and one that is activated outside it, or an active one that leaves it, is lost.
+   No field solve sets the initial self-field of a depositing beam. */
+typedef struct {
+    double beta_b;             /* mean lab velocity of the beam (c = 1), 0 < beta_b < 1         */
+    double z_inj_um;           /* lab position of the injection plane                          */
+    int32_t test_only;         /* 1: test particles, no current                                */
+    int32_t reserved;
+} bf_beam;
+
+/* Loads a beam (replacing any previous one) from host arrays of n particles: x in um
+   relative to the interior origin, z the lab position (um), ux, uy, uz the lab momenta
+   gamma v / c (uz > 0), w the weights in the library's normalised units.  The history
+   restarts.  Synchronous.  BF_EINVAL: n above beam_capacity, beta_b outside (0, 1), uz <= 0 or a
+   non-finite value; BF_EUNSUPPORTED: a 3D run. */
+bf_status bf_add_beam(bf_sim* sim, const bf_beam* beam, int64_t n, const double* x, const double* z,
+                      const double* ux, const double* uy, const double* uz, const double* w);
+
 /* ---- stepping -------------------------------------------------------------------------- */
 
 /* Advances nsteps PIC steps (Faraday+Friedman+PML, stations, gather/push/deposit, antenna,
@@ -190,7 +224,8 @@ enum {
     BF_DIAG_COUNTS = 2,    /* 4 int64: live electrons, live ions, slots e-, slots ions     */
     BF_DIAG_STATION = 3,   /* arg = station: int64 count then count x 7 doubles (t_lab, Ex,
                               Ey, Ez, Bx, By, Bz in the lab frame)                           */
-    BF_DIAG_ENERGY = 4,    /* 3 doubles: field energy E, field energy B, kinetic energy     */
+    BF_DIAG_ENERGY = 4,    /* 3 doubles: field energy E, field energy B, kinetic energy of
+                              the plasma electrons (the beam is not included)               */
     BF_DIAG_GAUSS = 5,     /* div E - F[rho] on the nodes, doubles in the field layout; 3D
                               uses the FP64 current accumulators as scratch (J_xr .. J_zr of
                               the last step are gone afterwards)                            */
@@ -200,9 +235,18 @@ enum {
                               y; 2D y polarisation: x, which then stays at the home position) */
     BF_DIAG_TIMERS = 8,    /* BF_PHASE_COUNT x 2 doubles: accumulated ms and launches per
                               phase since the last call (phase_timers = 1); arg != 0 resets */
-    BF_DIAG_PARTICLE_BLOCK = 9 /* 3D only; arg = species + 2 b: the live particles of slots
+    BF_DIAG_PARTICLE_BLOCK = 9, /* 3D only; arg = species + 2 b: the live particles of slots
                               [b, b + 1) x BF_PARTICLE_BLOCK, as int64 n then 8 arrays of n
                               doubles (id, x, y, z, ux, uy, uz, w); a sample of a large run  */
+    BF_DIAG_BEAM = 10      /* arg 0: int64 n then 8 arrays of n doubles: x, z (um, window
+                              frame), ux, uy, uz (calculation frame), w, crossing time t'*
+                              (um/c), state (0 frozen, 1 active, 2 lost).  arg 1: int64 count
+                              then count records of 8 doubles, one per step, over the active
+                              particles after the push, back-transformed to the lab frame:
+                              t'_{n+1}, count, sum w, sum w z_lab, sum w t_lab, sum w gamma_lab,
+                              sum w u_z,lab, sum w u_z,lab^2 (z_lab = gamma (z' + beta t'),
+                              gamma_lab = gamma (gamma' + beta u'_z), the momentum taken at
+                              t_{n+1/2})                                                      */
 };
 #define BF_PARTICLE_BLOCK 65536
 
@@ -216,6 +260,7 @@ enum {
     BF_PHASE_AMPERE,       /* Ampere + PML                                                  */
     BF_PHASE_WINDOW,       /* window shift and plasma injection                             */
     BF_PHASE_SORT,         /* tile sort                                                     */
+    BF_PHASE_BEAM,         /* beam through the injection plane                              */
     BF_PHASE_COUNT
 };
 

@@ -16,15 +16,15 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbfpic.so")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 FIELDS = ["Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "Exo", "Eyo", "Ezo",
           "Exb", "Eyb", "Ezb", "Byx", "Eyx", "Bxo", "Byo", "Bzo", "Jxr", "Jyr", "Jzr",
           "Exs", "Eys", "Ezs", "Bxs", "Bys", "Bzs"]
 FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 DIAG_FIELD, DIAG_PARTICLES, DIAG_COUNTS, DIAG_STATION, DIAG_ENERGY, DIAG_GAUSS, DIAG_INFO, \
-    DIAG_ANTENNA, DIAG_TIMERS, DIAG_PARTICLE_BLOCK = range(10)
+    DIAG_ANTENNA, DIAG_TIMERS, DIAG_PARTICLE_BLOCK, DIAG_BEAM = range(11)
 PARTICLE_BLOCK = 65536
-PHASES = ["faraday", "push", "ions", "antenna", "filter", "ampere", "window", "sort"]
+PHASES = ["faraday", "push", "ions", "antenna", "filter", "ampere", "window", "sort", "beam"]
 STATUS = {0: "BF_OK", -1: "BF_EINVAL", -2: "BF_ECFL", -3: "BF_ECAPACITY", -4: "BF_ENONFINITE",
           -5: "BF_EDEVICE", -6: "BF_ESTATE", -7: "BF_EUNSUPPORTED"}
 
@@ -48,7 +48,8 @@ class bf_config(C.Structure):
                 ("moving_window", C.c_int), ("particle_capacity", C.c_int64),
                 ("sort_every", C.c_int), ("tile_x", C.c_int), ("tile_z", C.c_int),
                 ("max_stations", C.c_int), ("station_capacity", C.c_int), ("phase_timers", C.c_int),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("beam_capacity", C.c_int64), ("beam_history", C.c_int32),
+                ("reserved0", C.c_int32)]
 
 
 class bf_plasma(C.Structure):
@@ -66,6 +67,11 @@ class bf_station(C.Structure):
     _fields_ = [("z_lab_um", C.c_double)]
 
 
+class bf_beam(C.Structure):
+    _fields_ = [("beta_b", C.c_double), ("z_inj_um", C.c_double), ("test_only", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class bf_buffer_desc(C.Structure):
     _fields_ = [("name", C.c_char_p), ("bytes", C.c_size_t), ("align", C.c_size_t),
                 ("dtype", C.c_int)]
@@ -81,7 +87,8 @@ class bf_state(C.Structure):
                 ("zoff", C.c_int32), ("e_cur", C.c_int32), ("b_cur", C.c_int32),
                 ("p_cur", C.c_int32), ("nseg_e", C.c_int32), ("nseg_i", C.c_int32),
                 ("since_sort", C.c_int32), ("have_plasma", C.c_int32), ("have_laser", C.c_int32),
-                ("nstations", C.c_int32)]
+                ("nstations", C.c_int32), ("have_beam", C.c_int32), ("beam_test_only", C.c_int32),
+                ("beam_n", C.c_int64), ("beam_records", C.c_int64), ("beam_vbar", C.c_double)]
 
 
 class bf_info(C.Structure):
@@ -97,7 +104,7 @@ class bf_info(C.Structure):
 
 
 EXPORTS = ["bf_query_buffers", "bf_create", "bf_init_plasma", "bf_init_laser", "bf_add_station",
-           "bf_load_electrons", "bf_load_electrons3", "bf_step", "bf_diagnose", "bf_set_field", "bf_sync_status",
+           "bf_load_electrons", "bf_load_electrons3", "bf_add_beam", "bf_step", "bf_diagnose", "bf_set_field", "bf_sync_status",
            "bf_get_state", "bf_set_state", "bf_status_string", "bf_last_error", "bf_destroy",
            "bf_set_learned_filter", "bf_lf_work_bytes", "bf_lf_apply", "bf_lf_train_step",
            "bf_lf_bilinear_params", "bf_lf_apply_noalloc",
@@ -127,6 +134,7 @@ def lib(path: str = LIB_PATH):
     L.bf_add_station.argtypes = [P, C.POINTER(bf_station), C.POINTER(C.c_int)]
     L.bf_load_electrons.argtypes = [P, C.c_int64, C.POINTER(C.c_uint32), D, D, D, D, D, D]
     L.bf_load_electrons3.argtypes = [P, C.c_int64, C.POINTER(C.c_uint32), D, D, D, D, D, D, D]
+    L.bf_add_beam.argtypes = [P, C.POINTER(bf_beam), C.c_int64, D, D, D, D, D, D]
     L.bf_step.argtypes = [P, C.c_int]
     L.bf_diagnose.argtypes = [P, C.c_int, C.c_int, P, C.c_size_t]
     L.bf_set_field.argtypes = [P, C.c_int, D, C.c_size_t]
@@ -229,6 +237,8 @@ def make_config(cfg: dict, capacity: int, stations: int = 0, station_capacity: i
     c.station_capacity = station_capacity
     c.phase_timers = 1 if timers else 0
     c.seed = cfg["seed"]
+    c.beam_capacity = int(cfg.get("beam_capacity", 0))
+    c.beam_history = int(cfg.get("beam_history", 0))
     return c
 
 
@@ -319,6 +329,33 @@ class Sim:
         self._ck(lib().bf_load_electrons(self.handle, n, ids.ctypes.data_as(C.POINTER(C.c_uint32)),
                                          dp(arr["x"]), dp(arr["z"]), dp(arr["ux"]), dp(arr["uy"]),
                                          dp(arr["uz"]), dp(arr["w"])))
+
+    def add_beam(self, beam: dict, parts: dict):
+        """Beam through a lab-fixed plane (bf_add_beam).  beam: beta_b, z_inj_um, test_only;
+        parts: lab x (um, interior-relative), z (lab um), ux, uy, uz, w at t = 0.  The run's
+        config needs beam_capacity (and beam_history for the per-step records)."""
+        n = len(parts["x"])
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+        arr = {k: np.ascontiguousarray(parts[k], dtype=np.float64) for k in ("x", "z", "ux", "uy", "uz", "w")}
+        b = bf_beam(beta_b=float(beam["beta_b"]), z_inj_um=float(beam["z_inj_um"]),
+                    test_only=int(beam.get("test_only", 1)))
+        self._ck(lib().bf_add_beam(self.handle, C.byref(b), n, *[dp(arr[k]) for k in ("x", "z", "ux", "uy", "uz", "w")]))
+
+    def beam(self) -> dict:
+        """x, z (um, window frame), ux, uy, uz (calculation frame), w, t_act, state."""
+        cap = int(self.cfg.beam_capacity)
+        out = self._diag(DIAG_BEAM, 0, np.zeros(1 + 8 * max(cap, 1)))
+        n = int(out[:1].view(np.int64)[0])
+        cols = out[1:1 + 8 * n].reshape(8, n)
+        return {k: cols[q].copy() for q, k in enumerate(("x", "z", "ux", "uy", "uz", "w", "t_act", "state"))}
+
+    def beam_history(self) -> np.ndarray:
+        """(records, 8): t', count, sum w, sum w z_lab, sum w t_lab, sum w gamma_lab,
+        sum w u_z,lab, sum w u_z,lab^2."""
+        cap = int(self.cfg.beam_history)
+        out = self._diag(DIAG_BEAM, 1, np.zeros(1 + 8 * max(cap, 1)))
+        m = int(out[:1].view(np.int64)[0])
+        return out[1:1 + 8 * m].reshape(m, 8).copy()
 
     def set_field(self, name: str, a: np.ndarray):
         a = np.ascontiguousarray(a, dtype=np.float64).reshape(self.shape)

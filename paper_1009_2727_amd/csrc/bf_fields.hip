@@ -584,6 +584,22 @@ void launch_rho(const Geo& g, const ElectronArrays<R>& e, int ne, const IonArray
                        na, xa_home0, za, aw, inv_cell, rho);
 }
 
+__global__ void k_rho_beam(Geo g, BeamArrays b, int n, double inv_cell, double* rho)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n || b.state[p] == 2) return;
+    const double x = b.x[p], z = b.z[p];
+    if (!g.perx && (x < 0.0 || x >= (double)g.Nx)) return;
+    if (!g.perz && (z < 0.0 || z >= (double)g.Nz)) return;
+    rho_add(g, rho, -b.w[p] * inv_cell, x, z);
+}
+
+void launch_rho_beam(const Geo& g, const BeamArrays& b, int n, double inv_cell, double* rho, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_rho_beam, dim3((n + 255) / 256), dim3(256), 0, s, g, b, n, inv_cell, rho);
+}
+
 void launch_fill_int(int* p, int n, int v, hipStream_t s)
 {
     if (n <= 0) return;

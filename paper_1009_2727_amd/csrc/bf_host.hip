@@ -71,7 +71,8 @@ struct Layout {
     int tile_x, tile_z, ntx, ntz, ntiles, nchunks, seg_cap;
     // work buffer
     size_t w_seg[2], w_bbe[2], w_segi[2], w_bbi[2], w_counts, w_cursor, w_nused, w_status,
-        w_pml_r, w_pml_on, w_st_z, w_st_rec, w_st_cnt, w_ant, w_rho, w_lf_par, w_lf_pk[3], w_bytes;
+        w_pml_r, w_pml_on, w_st_z, w_st_rec, w_st_cnt, w_ant, w_rho, w_lf_par, w_lf_pk[3], w_beam[8],
+        w_bhist, w_bytes;
     int nst, stcap;
 };
 
@@ -136,6 +137,10 @@ bool layout_of(const bf_config* c, Layout* L)
     const int nq[3] = {lf::chunks(1), lf::chunks(lf::C), lf::chunks(lf::C)};
     L->w_lf_par = take(lfk ? sizeof(float) * lf::NPARAM : 0);
     for (int k = 0; k < 3; k++) L->w_lf_pk[k] = take(lfk ? (size_t)nq[k] * lf::CHUNK_BYTES : 0);
+    // beam: x, z, ux, uy, uz, w, t'* (FP64) and the state (int) of beam_capacity particles,
+    // then beam_history records of 8 doubles
+    for (int k = 0; k < 8; k++) L->w_beam[k] = take((k < 7 ? 8 : 4) * (size_t)c->beam_capacity);
+    L->w_bhist = take(8 * sizeof(double) * (size_t)c->beam_history);
     L->w_bytes = o;
     return true;
 }
@@ -189,6 +194,8 @@ bf_status validate(const bf_config* c)
     if (c->particle_capacity < 0 || c->particle_capacity > (int64_t)INT32_MAX - 65536) return BF_EINVAL;
     if (c->tile_x < 0 || c->tile_z < 0 || c->tile_x > 64 || c->tile_z > 64) return BF_EINVAL;
     if (c->max_stations < 0 || c->max_stations > 64 || c->station_capacity < 0) return BF_EINVAL;
+    if (c->beam_capacity < 0 || c->beam_capacity > (int64_t)INT32_MAX - 65536 || c->beam_history < 0)
+        return BF_EINVAL;
     const double a2 = c->ck_alpha + 2 * c->ck_beta;
     if (std::fabs(c->ck_alpha + 4 * c->ck_beta + 4 * c->ck_gamma - 1.0) > 1e-12) return BF_EINVAL;
     (void)a2;
@@ -222,6 +229,10 @@ struct bf_sim {
     double t = 0;
     int since_sort = 0, sort_every = 20;
     int nst = 0;
+    // particle beam (Sec. 3.1.1)
+    int have_beam = 0, beam_test = 1;
+    int64_t nbeam = 0, beam_rec = 0;
+    double vbar = 0;
     std::vector<double> st_z;
     int err = BF_OK;
     std::string msg;
@@ -458,6 +469,22 @@ Segment* seg_e(const bf_sim* s, int k) { return s->w<Segment>(s->L.w_seg[k]); }
 Segment* seg_i(const bf_sim* s, int k) { return s->w<Segment>(s->L.w_segi[k]); }
 int4* bb_e(const bf_sim* s, int k) { return s->w<int4>(s->L.w_bbe[k]); }
 int4* bb_i(const bf_sim* s, int k) { return s->w<int4>(s->L.w_bbi[k]); }
+
+BeamArrays beam_arrays(const bf_sim* s)
+{
+    const Layout& L = s->L;
+    BeamArrays b;
+    b.x = s->w<double>(L.w_beam[0]);
+    b.z = s->w<double>(L.w_beam[1]);
+    b.ux = s->w<double>(L.w_beam[2]);
+    b.uy = s->w<double>(L.w_beam[3]);
+    b.uz = s->w<double>(L.w_beam[4]);
+    b.w = s->w<double>(L.w_beam[5]);
+    b.tact = s->w<double>(L.w_beam[6]);
+    b.state = s->w<int>(L.w_beam[7]);
+    b.hist = s->w<double>(L.w_bhist);
+    return b;
+}
 
 double ion_shift(const bf_sim* s, double t)
 {
@@ -701,6 +728,30 @@ bf_status step_impl(bf_sim* s, int nsteps)
             if (!rb) launch_ions<R>(g, f, ion, sg, bi, bo, s->nseg_i, za, zb, d, fjz, s->stream);
         }
         s->tock(t_ph, BF_PHASE_IONS);
+        // beam through the injection plane (single runs only: a batch rejects beam runs)
+        if (s->have_beam) {
+            t_ph = s->tick();
+            BeamParams bp;
+            bp.n = (int)s->nbeam;
+            bp.deposit = s->beam_test ? 0 : 1;
+            bp.rec = s->beam_rec < c.beam_history ? (int)s->beam_rec : -1;
+            bp.t0 = s->t; bp.t1 = t1;
+            bp.vbar_cells = s->vbar * s->dt / c.dz_um;
+            bp.gamma = s->gamma; bp.beta = s->beta; bp.dz_um = c.dz_um;
+            bp.shift = (double)s->shift;
+            PushParams<double> pb;
+            pb.qdt2 = -0.5 * s->dt;
+            pb.dtdx = s->dt / c.dx_um;
+            pb.dtdz = s->dt / c.dz_um;
+            pb.fjx = 1.0 / (c.dz_um * s->dt);
+            pb.fjz = 1.0 / (c.dx_um * s->dt);
+            pb.fjy = -1.0 / (c.dx_um * c.dz_um);
+            pb.shift = d;
+            pb.vay = c.pusher;
+            launch_beam<R>(g, f, beam_arrays(s), bp, pb, status_word(s), c.gather_kind == 1, s->stream);
+            if (bp.rec >= 0) s->beam_rec++;
+            s->tock(t_ph, BF_PHASE_BEAM);
+        }
         // antenna
         s->slot = SLOT_ANTENNA;
         t_ph = s->tick();
@@ -1833,6 +1884,66 @@ bf_status bf_load_electrons3(bf_sim* s, int64_t n, const uint32_t* id, const dou
     return hip_check(s, e, "load_electrons3");
 }
 
+// Sec. 3.1.1: (1) ballistic projection onto the plane, t* = (z - z_inj)/v_z, x* = x - v_x t*;
+// (2) the crossing event (t = -t*, z = z_inj) and the momentum in the calculation frame,
+// t'* = gamma (-t* - beta z_inj), z'* = gamma (z_inj + beta t*), u'_z = gamma (u_z - beta gamma_p),
+// u'_perp = u_perp; (3) the synchronised position z'(0) = z'* - vbar' t'*, advanced to the
+// current time at vbar' since the beam is frozen until it crosses.
+bf_status bf_add_beam(bf_sim* s, const bf_beam* bm, int64_t n, const double* x, const double* z, const double* ux,
+                      const double* uy, const double* uz, const double* w)
+{
+    bf_status st = guard(s);
+    if (st != BF_OK) return st;
+    if (s->d3) return fail(s, BF_EUNSUPPORTED, "the beam is available in 2D runs");
+    if (!bm || n < 0 || n > s->cfg.beam_capacity || (n > 0 && (!x || !z || !ux || !uy || !uz || !w)))
+        return fail(s, BF_EINVAL, "bad beam arrays or n above beam_capacity");
+    if (!(bm->beta_b > 0.0 && bm->beta_b < 1.0) || !std::isfinite(bm->z_inj_um))
+        return fail(s, BF_EINVAL, "beta_b must lie in (0, 1)");
+    const double g = s->gamma, b = s->beta, zi = bm->z_inj_um;
+    const double vbar = (bm->beta_b - b) / (1.0 - b * bm->beta_b);
+    const double dx = s->cfg.dx_um, dz = s->cfg.dz_um;
+    const int perx = s->cfg.periodic_mask & 1, perz = (s->cfg.periodic_mask >> 2) & 1;
+    std::vector<double> col[7];
+    for (auto& v : col) v.resize((size_t)n);
+    for (int64_t p = 0; p < n; p++) {
+        const double vals[6] = {x[p], z[p], ux[p], uy[p], uz[p], w[p]};
+        for (double v : vals)
+            if (!std::isfinite(v)) return fail(s, BF_EINVAL, "non-finite beam value");
+        if (!(uz[p] > 0.0)) return fail(s, BF_EINVAL, "every beam particle must move forward (uz > 0)");
+        const double gp = std::sqrt(1.0 + ux[p] * ux[p] + uy[p] * uy[p] + uz[p] * uz[p]);
+        const double tstar = (z[p] - zi) * gp / uz[p];
+        const double xstar = x[p] - ux[p] / gp * tstar;
+        const double tcross = g * (-tstar - b * zi);
+        const double zcross = g * (zi + b * tstar);
+        double xc = xstar / dx;
+        double zc = (zcross - vbar * tcross + vbar * s->t) / dz - (double)s->shift;
+        if (perx) xc -= s->cfg.nx * std::floor(xc / s->cfg.nx);
+        if (perz) zc -= s->cfg.nz * std::floor(zc / s->cfg.nz);
+        col[0][p] = xc;
+        col[1][p] = zc;
+        col[2][p] = ux[p];
+        col[3][p] = uy[p];
+        col[4][p] = g * (uz[p] - b * gp);
+        col[5][p] = w[p];
+        col[6][p] = tcross;
+    }
+    const Layout& L = s->L;
+    hipError_t e = hipStreamSynchronize(s->stream);   // earlier steps may still use the arrays
+    for (int k = 0; k < 7 && e == hipSuccess && n > 0; k++)
+        e = hipMemcpy(s->w<double>(L.w_beam[k]), col[k].data(), 8 * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess && n > 0) e = hipMemset(s->w<int>(L.w_beam[7]), 0, 4 * (size_t)n);
+    if (e == hipSuccess && s->cfg.beam_history > 0)
+        e = hipMemset(s->w<double>(L.w_bhist), 0, 64 * (size_t)s->cfg.beam_history);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_check(s, e, "add_beam");
+    s->have_beam = 1;
+    s->beam_test = bm->test_only ? 1 : 0;
+    s->nbeam = n;
+    s->beam_rec = 0;
+    s->vbar = vbar;
+    return BF_OK;
+}
+
 bf_status bf_step(bf_sim* s, int nsteps)
 {
     bf_status st = guard(s);
@@ -1982,10 +2093,11 @@ bf_status bf_batch_create(bf_sim* const* sims, int n, void* work, int64_t work_b
     if (work_bytes < bf_batch_work_bytes(n)) return BF_EINVAL;
     for (int q = 0; q < n; q++) {
         if (!sims[q] || sims[q]->cfg.real_bytes != 4 || sims[q]->d3) return BF_EUNSUPPORTED;
-        // the batched filter phase runs the stride-1 tile filter
-        if (sims[q]->cfg.filter_strides > 1 || sims[q]->cfg.gather_kind || sims[q]->cfg.pusher) return BF_EUNSUPPORTED;
-        // the batched filter phase runs the stride-1 tile filter
-        if (sims[q]->cfg.filter_strides > 1 || sims[q]->cfg.gather_kind || sims[q]->cfg.pusher) return BF_EUNSUPPORTED;
+        // the batched filter phase runs the stride-1 tile filter, the batched push the
+        // energy-conserving gather and Boris; the beam has no batched phase
+        if (sims[q]->cfg.filter_strides > 1 || sims[q]->cfg.gather_kind || sims[q]->cfg.pusher ||
+            sims[q]->cfg.beam_capacity > 0)
+            return BF_EUNSUPPORTED;
         if (sims[q]->err != BF_OK) return BF_ESTATE;
         for (int p = 0; p < q; p++)
             if (sims[p] == sims[q]) return BF_EINVAL;
@@ -2186,6 +2298,7 @@ static bf_status gauss_impl(bf_sim* s, double* out)
     }
     launch_rho<R>(g0, electrons<R>(s, s->p_cur), nu[0], ions<R>(s, s->p_cur), ni, ion_shift(s, s->t),
                   s->w<double>(L.w_ant), na, 0.5, za, s->aw, inv_cell, rho, s->stream);
+    if (s->have_beam && !s->beam_test) launch_rho_beam(g0, beam_arrays(s), (int)s->nbeam, inv_cell, rho, s->stream);
     double* res = rho;
     if (s->cfg.filter_npass > 0) {
         // the step's filter on the nodal charge density: rho -> rhof along x, back along z
@@ -2342,6 +2455,40 @@ bf_status bf_diagnose(bf_sim* s, int kind, int arg, void* host_out, size_t bytes
         if (arg) for (int q = 0; q < BF_PHASE_COUNT; q++) { s->tacc[q] = 0.0; s->tcnt[q] = 0.0; }
         return BF_OK;
     }
+    case BF_DIAG_BEAM: {
+        if (arg != 0 && arg != 1) return fail(s, BF_EINVAL, "beam diagnostic: arg 0 or 1");
+        const BeamArrays b = beam_arrays(s);
+        const int64_t n = s->have_beam ? s->nbeam : 0;
+        int64_t* o64 = (int64_t*)host_out;
+        double* o = (double*)host_out + 1;
+        if (arg == 0) {
+            if (bytes < 8 + 64 * (size_t)n) return fail(s, BF_EINVAL, "buffer too small");
+            o64[0] = n;
+            if (n == 0) return BF_OK;
+            double* const src[7] = {b.x, b.z, b.ux, b.uy, b.uz, b.w, b.tact};
+            for (int k = 0; k < 7; k++) {
+                e = hipMemcpy(o + k * n, src[k], 8 * (size_t)n, hipMemcpyDeviceToHost);
+                if (e != hipSuccess) return hip_check(s, e, "beam");
+            }
+            std::vector<int> st((size_t)n);
+            e = hipMemcpy(st.data(), b.state, 4 * (size_t)n, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_check(s, e, "beam");
+            for (int64_t p = 0; p < n; p++) {
+                o[p] *= s->cfg.dx_um;
+                o[n + p] *= s->cfg.dz_um;
+                o[7 * n + p] = (double)st[p];
+            }
+            return BF_OK;
+        }
+        const int64_t m = s->have_beam ? s->beam_rec : 0;
+        if (bytes < 8 + 64 * (size_t)m) return fail(s, BF_EINVAL, "buffer too small");
+        o64[0] = m;
+        if (m > 0) {
+            e = hipMemcpy(o, b.hist, 64 * (size_t)m, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_check(s, e, "beam history");
+        }
+        return BF_OK;
+    }
     default:
         return fail(s, BF_EINVAL, "unknown diagnostic");
     }
@@ -2396,6 +2543,8 @@ bf_status bf_get_state(const bf_sim* s, bf_state* o)
     o->p_cur = s->p_cur;
     o->nseg_e = s->nseg_e; o->nseg_i = s->nseg_i; o->since_sort = s->since_sort;
     o->have_plasma = s->have_plasma; o->have_laser = s->have_laser; o->nstations = s->nst;
+    o->have_beam = s->have_beam; o->beam_test_only = s->beam_test; o->beam_n = s->nbeam;
+    o->beam_records = s->beam_rec; o->beam_vbar = s->vbar;
     if (s->d3) {   // 3D: one segment table per species, both of nseg segments
         o->zoff = s->d3->g.zoff; o->p_cur = s->d3->p_cur; o->since_sort = s->d3->since_sort;
         o->nseg_e = o->nseg_i = s->d3->nseg;
@@ -2418,6 +2567,12 @@ bf_status bf_set_state(bf_sim* s, const bf_state* in)
         return BF_OK;
     }
     if (in->zoff < 0 || in->zoff >= s->L.Sz || in->nseg_e < 0 || in->nseg_e > s->L.seg_cap) return BF_EINVAL;
+    if (in->have_beam && (in->beam_n < 0 || in->beam_n > s->cfg.beam_capacity || in->beam_records < 0 ||
+                          in->beam_records > s->cfg.beam_history))
+        return BF_EINVAL;
+    s->have_beam = in->have_beam ? 1 : 0; s->beam_test = in->beam_test_only ? 1 : 0;
+    s->nbeam = in->have_beam ? in->beam_n : 0; s->beam_rec = in->have_beam ? in->beam_records : 0;
+    s->vbar = in->beam_vbar;
     s->step = in->step; s->t = in->time; s->shift = in->shift; s->next_row = in->next_row;
     s->g.zoff = in->zoff;
     s->e_cur = in->e_cur & 1; s->eb_cur = (in->e_cur >> 1) & 1; s->bb_cur = (in->e_cur >> 2) & 1;

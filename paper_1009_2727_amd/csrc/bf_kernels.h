@@ -99,6 +99,25 @@ struct AntennaParams {
     int pol;           // 0: the - sheet moves along x (J_x); 1: along y, out of the plane (J_y)
 };
 
+// particle beam launched through a lab-fixed plane (Sec. 3.1.1): FP64 state in the work buffer
+struct BeamArrays {
+    double *x, *z;        // cells, current window frame
+    double *ux, *uy, *uz; // calculation-frame momenta gamma v / c
+    double* w;            // macro-weight
+    double* tact;         // boosted time t'* at which the particle crosses the plane (um/c)
+    int* state;           // 0 frozen, 1 active, 2 lost
+    double* hist;         // one record of 8 doubles per step (see BF_DIAG_BEAM)
+};
+struct BeamParams {
+    int n;
+    int deposit;          // 1: frozen and active particles deposit current
+    int rec;              // history record of this step (-1: the history is full)
+    double t0, t1;        // t_n, t_{n+1} (um/c)
+    double vbar_cells;    // frozen move per step: vbar' dt / dz
+    double gamma, beta, dz_um;
+    double shift;         // window cells moved before this step (lab back-transformation)
+};
+
 struct StationParams {
     int n;
     const double* zlab;
@@ -227,5 +246,16 @@ void launch_rho(const Geo& g, const ElectronArrays<R>& e, int ne, const IonArray
                 int ni, double zsh, const double* xm, int na, double xa_home0, double za,
                 double aw, double inv_cell, double* rho, hipStream_t s);
 void launch_fill_int(int* p, int n, int v, hipStream_t s);
+// one step of the beam at t_n: frozen particles whose crossing time has come become active;
+// frozen ones move along z at vbar', active ones are gathered (mc: from the node values f.G),
+// pushed in FP64 (pp.vay: Vay, else Boris) and absorbed outside the interior; both deposit
+// into f.J when bp.deposit; positions are rebased by pp.shift; the active particles' lab-frame
+// sums go to record bp.rec of the history
+template <typename R>
+void launch_beam(const Geo& g, const FieldSet<R>& f, const BeamArrays& b, const BeamParams& bp,
+                 const PushParams<double>& pp, int* status, bool mc, hipStream_t s);
+// charge density of the beam's frozen and active particles inside the interior into rho
+// (the layout of launch_rho)
+void launch_rho_beam(const Geo& g, const BeamArrays& b, int n, double inv_cell, double* rho, hipStream_t s);
 
 }  // namespace bf

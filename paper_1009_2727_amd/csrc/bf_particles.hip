@@ -767,6 +767,91 @@ __global__ void __launch_bounds__(64) k_antenna(Geo g, FieldSet<R> f, double* xm
     if (lane == 0) xm[i] = xb;
 }
 
+// ---- particle beam through a lab-fixed plane (Sec. 3.1.1) ---------------------------------
+
+__device__ __forceinline__ bool beam_inside(const Geo& g, double x, double z)
+{
+    if (!g.perx && (x < 0.0 || x >= (double)g.Nx)) return false;
+    if (!g.perz && (z < 0.0 || z >= (double)g.Nz)) return false;
+    return true;
+}
+
+__device__ __forceinline__ double beam_wrap(double v, int N, int per)
+{
+    if (!per) return v;
+    return v < 0.0 ? v + N : (v >= (double)N ? v - N : v);
+}
+
+// One thread per beam particle.  A frozen particle (transverse position and momentum fixed)
+// moves along z at the boosted mean velocity until a step starts at t_n >= t'*; it then
+// becomes an ordinary electron (energy-conserving or momentum-conserving gather, Boris or
+// Vay in FP64, Esirkepov deposit through global atomics).  Particles activated outside the
+// interior, or leaving it, are lost.  Each block adds its active particles' lab-frame sums
+// (gamma_lab = gamma (gamma' + beta u'_z), z_lab = gamma (z' + beta t'), ...) to the record.
+template <typename R, bool MC>
+__global__ void __launch_bounds__(NTHR) k_beam(Geo g, FieldSet<R> f, BeamArrays b, BeamParams bp,
+                                               PushParams<double> pp, int* status)
+{
+    __shared__ double red[NTHR / 64];
+    const int p = blockIdx.x * NTHR + threadIdx.x;
+    double a[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (p < bp.n && b.state[p] != 2) {
+        const GlobAcc<R> acc = make_glob<MC>(g, f);
+        int st = b.state[p];
+        const double x = b.x[p], z = b.z[p], w = b.w[p];
+        if (st == 0 && b.tact[p] <= bp.t0) st = beam_inside(g, x, z) ? 1 : 2;
+        const int ix = (int)floor(x), iz = (int)floor(z);
+        if (st == 0) {
+            const double zn = z + bp.vbar_cells;
+            if (bp.deposit && beam_inside(g, x, z)) {
+                const int iz1 = (int)floor(zn);
+                esirkepov(acc, ix, x - ix, iz, z - iz, ix, x - ix, iz1, zn - iz1, w * pp.fjx, w * pp.fjz, 0.0);
+            }
+            b.z[p] = beam_wrap(zn, g.Nz, g.perz) - (double)pp.shift;
+        } else if (st == 1) {
+            R Er[3], Br[3];
+            gather<MC>(acc, x, z, Er, Br);
+            const double E[3] = {(double)Er[0], (double)Er[1], (double)Er[2]};
+            const double B[3] = {(double)Br[0], (double)Br[1], (double)Br[2]};
+            double ux = b.ux[p], uy = b.uy[p], uz = b.uz[p];
+            if (pp.vay) vay(pp.qdt2, E, B, ux, uy, uz);
+            else boris(pp.qdt2, E, B, ux, uy, uz);
+            const double gp = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+            const double xn = x + pp.dtdx * ux / gp, zn = z + pp.dtdz * uz / gp;
+            const int ix1 = (int)floor(xn), iz1 = (int)floor(zn);
+            if (abs(ix1 - ix) <= 1 && abs(iz1 - iz) <= 1) {
+                if (bp.deposit)
+                    esirkepov(acc, ix, x - ix, iz, z - iz, ix1, xn - ix1, iz1, zn - iz1, w * pp.fjx, w * pp.fjz,
+                              w * pp.fjy * (uy / gp));
+            } else {
+                atomicOr(status, ST_NONFINITE);   // faster than light: only a non-finite state gets here
+            }
+            if (!isfinite(ux + uy + uz)) atomicOr(status, ST_NONFINITE);
+            b.ux[p] = ux; b.uy[p] = uy; b.uz[p] = uz;
+            if (!beam_inside(g, xn, zn)) {
+                st = 2;
+                b.x[p] = xn; b.z[p] = zn;
+            } else {
+                const double za = (zn + bp.shift) * bp.dz_um;   // window-independent boosted z'
+                const double zl = bp.gamma * (za + bp.beta * bp.t1), tl = bp.gamma * (bp.t1 + bp.beta * za);
+                const double gl = bp.gamma * (gp + bp.beta * uz), ul = bp.gamma * (uz + bp.beta * gp);
+                a[0] = 1.0; a[1] = w; a[2] = w * zl; a[3] = w * tl; a[4] = w * gl; a[5] = w * ul; a[6] = w * ul * ul;
+                b.x[p] = beam_wrap(xn, g.Nx, g.perx);
+                b.z[p] = beam_wrap(zn, g.Nz, g.perz) - (double)pp.shift;
+            }
+        }
+        b.state[p] = st;
+    }
+    if (bp.rec < 0) return;   // uniform over the launch
+    double* r = b.hist + 8 * (long)bp.rec;
+    for (int k = 0; k < 7; k++) {
+        const double v = block_sum(a[k], red);
+        __syncthreads();   // red is reused by the next sum
+        if (threadIdx.x == 0 && v != 0.0) atomicAdd(&r[1 + k], v);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) r[0] = bp.t1;
+}
+
 // ---- plasma injection --------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k)
 {
@@ -1264,6 +1349,16 @@ void launch_antenna(const Geo& g, const FieldSet<R>& f, double* xminus, const An
 }
 
 template <typename R>
+void launch_beam(const Geo& g, const FieldSet<R>& f, const BeamArrays& b, const BeamParams& bp,
+                 const PushParams<double>& pp, int* status, bool mc, hipStream_t s)
+{
+    if (bp.n <= 0) return;
+    const dim3 grid((bp.n + NTHR - 1) / NTHR);
+    if (mc) hipLaunchKernelGGL((k_beam<R, true>), grid, dim3(NTHR), 0, s, g, f, b, bp, pp, status);
+    else hipLaunchKernelGGL((k_beam<R, false>), grid, dim3(NTHR), 0, s, g, f, b, bp, pp, status);
+}
+
+template <typename R>
 void launch_inject(const Geo& g, const ElectronArrays<R>& e, const IonArrays<R>& ion, Segment* seg_e,
                    int4* bbox_e, Segment* seg_i, int4* bbox_i, int* nused_e, int* nused_i,
                    const InjectParams& ip, int* status, hipStream_t s)
@@ -1327,6 +1422,8 @@ void launch_sort_ions(const Geo& g, int tile_x, int tile_z, int ntx, int ntiles,
     template void launch_ions_batch<R>(const IonDesc<R>*, const QueueRef&, int, hipStream_t);         \
     template void launch_antenna<R>(const Geo&, const FieldSet<R>&, double*, const AntennaParams&,    \
                                     hipStream_t);                                                     \
+    template void launch_beam<R>(const Geo&, const FieldSet<R>&, const BeamArrays&, const BeamParams&, \
+                                 const PushParams<double>&, int*, bool, hipStream_t);                 \
     template void launch_inject<R>(const Geo&, const ElectronArrays<R>&, const IonArrays<R>&,         \
                                    Segment*, int4*, Segment*, int4*, int*, int*,                      \
                                    const InjectParams&, int*, hipStream_t);                           \
