@@ -123,6 +123,9 @@ def lib(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} not built: run __graft_entry__.build() "
                            "(hipcc --offload-arch=gfx950) first")
+    # torch brings its own copy of the HIP runtime; load it first so that the library's
+    # dependency resolves to that same runtime (device pointers and streams come from torch)
+    import torch  # noqa: F401
     L = C.CDLL(path)
     P = C.c_void_p
     D = C.POINTER(C.c_double)

@@ -878,6 +878,7 @@ struct Sim3 {
     int seg_cap = 0, nseg = 0, bb_cur = 0;   // segments (tiles of the last sort, then injected chunks)
     int pz = 0;                              // z planes of the LDS box
     int na = 0;
+    int eb_cur = 0;                          // which of A3_EB / A3_T holds the Friedman average
 };
 
 void sim3_free(Sim3* d) { delete d; }
@@ -994,11 +995,12 @@ bf3::F3<R> fields3(const bf_sim* s)
 {
     bf3::F3<R> f;
     for (int c = 0; c < 3; c++) {
-        f.E[c] = arr3<R>(s, A3_E + c); f.Eo[c] = arr3<R>(s, A3_EO + c); f.Eb[c] = arr3<R>(s, A3_EB + c);
+        f.E[c] = arr3<R>(s, A3_E + c); f.Eo[c] = arr3<R>(s, A3_EO + c);
+        f.Eb[c] = arr3<R>(s, (s->d3->eb_cur ? A3_T : A3_EB) + c);
+        f.T[c] = arr3<R>(s, (s->d3->eb_cur ? A3_EB : A3_T) + c);
         f.B[c] = arr3<R>(s, A3_B + c); f.Bo[c] = arr3<R>(s, A3_BO + c); f.J[c] = jacc3(s, c);
         f.Jf[c] = arr3<R>(s, A3_JF + c); f.Jg[c] = arr3<R>(s, A3_JG + c);
         f.SE[c] = arr3<R>(s, A3_SE + c); f.SB[c] = arr3<R>(s, A3_SB + c);
-        f.T[c] = arr3<R>(s, A3_T + c);
     }
     for (int c = 0; c < 6; c++)
         f.G[c] = s->cfg.gather_kind == 1
@@ -1210,11 +1212,14 @@ bf_status step3(bf_sim* s, int nsteps)
     const double ck[3] = {s->cfg.ck_alpha, s->cfg.ck_beta, s->cfg.ck_gamma};
     const bf3::Pml3 pml = pml3(s);
     for (int it = 0; it < nsteps; it++) {
-        const bf3::F3<R> f = fields3<R>(s);
+        bf3::F3<R> f = fields3<R>(s);
         const bf3::G3 g = L.g;
         hipEvent_t ev = s->tick();
-        if (s->theta > 0.0) bf3::launch3_friedman<R>(g, f, s->theta, s->stream);
         bf3::launch3_faraday<R>(g, f, pml, ck, s->theta, s->dt, s->stream);
+        if (s->theta > 0.0) {   // the new Friedman average is in the other buffer
+            L.eb_cur ^= 1;
+            f = fields3<R>(s);
+        }
         bf3::launch3_stations<R>(g, f, w3<double>(s, L.w_st_z), s->nst, s->gamma, s->beta, s->t, (double)s->shift,
                                  w3<double>(s, L.w_st_rec), w3<int>(s, L.w_st_cnt), L.stcap, s->stream);
         bf3::launch3_zero_j<R>(g, f, s->stream);        // the current of this step starts at zero
@@ -1327,12 +1332,12 @@ bf_status init_laser3(bf_sim* s)
 }
 
 // field id -> array (-1: none)
-int array3_of(int id)
+int array3_of(const Sim3& L, int id)
 {
     switch (id) {
     case BF_F_EX: case BF_F_EY: case BF_F_EZ: return A3_E + (id - BF_F_EX);
     case BF_F_EXO: case BF_F_EYO: case BF_F_EZO: return A3_EO + (id - BF_F_EXO);
-    case BF_F_EXB: case BF_F_EYB: case BF_F_EZB: return A3_EB + (id - BF_F_EXB);
+    case BF_F_EXB: case BF_F_EYB: case BF_F_EZB: return (L.eb_cur ? A3_T : A3_EB) + (id - BF_F_EXB);
     case BF_F_BX: case BF_F_BY: case BF_F_BZ: return A3_B + (id - BF_F_BX);
     case BF_F_BXO: case BF_F_BYO: case BF_F_BZO: return A3_BO + (id - BF_F_BXO);
     case BF_F_JXR: case BF_F_JYR: case BF_F_JZR: return A3_J + (id - BF_F_JXR);
@@ -1499,7 +1504,7 @@ bf_status diagnose3(bf_sim* s, int kind, int arg, void* host_out, size_t bytes)
     const size_t grid = (size_t)L.g.S[0] * L.g.S[1] * L.g.S[2];
     switch (kind) {
     case BF_DIAG_FIELD: {
-        int a = (arg == BF_F_JX || arg == BF_F_JY || arg == BF_F_JZ) ? filtered3(s->cfg, arg - BF_F_JX) : array3_of(arg);
+        int a = (arg == BF_F_JX || arg == BF_F_JY || arg == BF_F_JZ) ? filtered3(s->cfg, arg - BF_F_JX) : array3_of(*s->d3, arg);
         if (a < 0) return fail(s, BF_EINVAL, "bad field id");
         if (bytes < grid * 8) return fail(s, BF_EINVAL, "buffer too small");
         return read_field3(s, a, (double*)host_out);
@@ -2501,7 +2506,7 @@ bf_status bf_set_field(bf_sim* s, int field, const double* in, size_t bytes)
     if (s->d3) {
         const Sim3& L3 = *s->d3;
         const int a = (field == BF_F_JX || field == BF_F_JY || field == BF_F_JZ) ? filtered3(s->cfg, field - BF_F_JX)
-                                                                                : array3_of(field);
+                                                                                : array3_of(*s->d3, field);
         if (a < 0) return fail(s, BF_EINVAL, "bad field id");
         if (!in || bytes < (size_t)L3.g.S[0] * L3.g.S[1] * L3.g.S[2] * 8) return fail(s, BF_EINVAL, "buffer too small");
         hipError_t e3 = hipStreamSynchronize(s->stream);
@@ -2548,7 +2553,7 @@ bf_status bf_get_state(const bf_sim* s, bf_state* o)
     if (s->d3) {   // 3D: one segment table per species, both of nseg segments
         o->zoff = s->d3->g.zoff; o->p_cur = s->d3->p_cur; o->since_sort = s->d3->since_sort;
         o->nseg_e = o->nseg_i = s->d3->nseg;
-        o->e_cur = s->d3->bb_cur << 2;
+        o->e_cur = (s->d3->bb_cur << 2) | (s->d3->eb_cur << 1);
     }
     return BF_OK;
 }
@@ -2563,7 +2568,7 @@ bf_status bf_set_state(bf_sim* s, const bf_state* in)
             return BF_EINVAL;
         s->step = in->step; s->t = in->time; s->shift = in->shift; s->next_row = in->next_row;
         L3.g.zoff = in->zoff; L3.p_cur = in->p_cur & 1; L3.since_sort = in->since_sort;
-        L3.nseg = in->nseg_e; L3.bb_cur = (in->e_cur >> 2) & 1;
+        L3.nseg = in->nseg_e; L3.bb_cur = (in->e_cur >> 2) & 1; L3.eb_cur = (in->e_cur >> 1) & 1;
         return BF_OK;
     }
     if (in->zoff < 0 || in->zoff >= s->L.Sz || in->nseg_e < 0 || in->nseg_e > s->L.seg_cap) return BF_EINVAL;

@@ -39,7 +39,7 @@ struct F3 {
     R* Jg[3];
     R* SE[3];   // PML split parts of E (part along the cyclic-next axis)
     R* SB[3];   // PML split parts of B
-    R* T[3];    // E-tilde of the Friedman step
+    R* T[3];    // the other Ebar buffer: Faraday writes the new Friedman average here
     R* G[6];    // momentum-conserving gather: E^n and B^n interpolated to the nodes (else null)
 };
 
@@ -103,7 +103,8 @@ struct Antenna3 {
 // status bits (same meaning as the 2D path)
 constexpr int ST3_CAPACITY = 1, ST3_NONFINITE = 2;
 
-template <typename R> void launch3_friedman(const G3& g, const F3<R>& f, double theta, hipStream_t s);
+// Faraday + PML, with Friedman's E-tilde (theta > 0) made from E, E^{n-1} and Ebar on the fly;
+// the new Ebar is written to f.T (the caller swaps the two Ebar buffers after the step)
 template <typename R>
 void launch3_faraday(const G3& g, const F3<R>& f, const Pml3& pml, const double ck[3], double theta, double dt,
                      hipStream_t s);

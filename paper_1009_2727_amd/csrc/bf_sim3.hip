@@ -12,7 +12,8 @@
 //   * n-pass bilinear filter plus compensation along x, y and z (Sec. 4.1);
 //   * laser sheets on a lab-fixed plane with one +/- pair per transverse cell (Sec. 3.1.2);
 //   * moving window as a ring offset of the z planes, plane-wise plasma injection.
-// Field stages run one thread per cell on the arrays in HBM.  Particles are binned by tile
+// Faraday and Ampere march up z over (x, y) tiles with the planes they difference in LDS; the
+// other field stages run one thread per cell on the arrays in HBM.  Particles are binned by tile
 // (periodic counting sort) and pushed one segment per workgroup on an LDS-staged box; the
 // deposited current is summed in FP64 in HBM (fixed point or FP64 in LDS).
 #include "bf_kernels3.h"
@@ -75,73 +76,6 @@ static_assert(CBX * CBY == NT, "per-cell launches use NT threads");
 
 // ---- field solver ---------------------------------------------------------------------------
 
-// difference of G along AX towards a target with stagger ht there: right neighbour q + ht, left
-// q + ht - 1 (a neighbour beyond a non-periodic edge reads 0)
-template <int AX, typename R>
-__device__ __forceinline__ R dG(const R* __restrict__ G, const G3& g, const int q[3], int ht)
-{
-    int p[3] = {q[0], q[1], q[2]};
-    const int r = nb(q[AX], ht, g.S[AX], g.per[AX]), l = nb(q[AX], ht - 1, g.S[AX], g.per[AX]);
-    R gr = R(0), gl = R(0);
-    if (r >= 0) { p[AX] = r; gr = G[o3(g, p[0], p[1], p[2])]; }
-    if (l >= 0) { p[AX] = l; gl = G[o3(g, p[0], p[1], p[2])]; }
-    return (gr - gl) / (R)g.d[AX];
-}
-
-template <int AX, typename R>
-__device__ __forceinline__ R dstar(const R* __restrict__ G, const G3& g, const int q[3], int ht, R a, R b, R c)
-{
-    R v = a * dG<AX>(G, g, q, ht);
-    if (b == R(0) && c == R(0)) return v;
-    constexpr int T1 = (AX + 1) % 3, T2 = (AX + 2) % 3;
-#pragma unroll
-    for (int s = -1; s <= 1; s += 2) {
-        int p[3] = {q[0], q[1], q[2]};
-        p[T1] = nb(q[T1], s, g.S[T1], g.per[T1]);
-        if (p[T1] >= 0) v += b * dG<AX>(G, g, p, ht);
-        int r[3] = {q[0], q[1], q[2]};
-        r[T2] = nb(q[T2], s, g.S[T2], g.per[T2]);
-        if (r[T2] >= 0) v += b * dG<AX>(G, g, r, ht);
-    }
-    if (c != R(0)) {
-#pragma unroll
-        for (int s1 = -1; s1 <= 1; s1 += 2)
-#pragma unroll
-            for (int s2 = -1; s2 <= 1; s2 += 2) {
-                int p[3] = {q[0], q[1], q[2]};
-                p[T1] = nb(q[T1], s1, g.S[T1], g.per[T1]);
-                p[T2] = nb(q[T2], s2, g.S[T2], g.per[T2]);
-                if (p[T1] >= 0 && p[T2] >= 0) v += c * dG<AX>(G, g, p, ht);
-            }
-    }
-    return v;
-}
-
-// Delta*_AX G of a cell at least one cell from every non-periodic edge: off[a][s + 1] is the
-// offset of shift s in {-1, 0, 1} along axis a (the z entries carry the ring), so every
-// neighbour is one sum of three offsets
-template <int AX, typename R>
-__device__ __forceinline__ R dstar_in(const R* __restrict__ G, const long off[3][3], int ht, R a, R b, R c, R id)
-{
-    constexpr int T1 = (AX + 1) % 3, T2 = (AX + 2) % 3;
-    auto D = [&](int t1, int t2) {
-        int s[3];
-        s[T1] = t1;
-        s[T2] = t2;
-        s[AX] = ht;
-        const long hi = off[0][s[0] + 1] + off[1][s[1] + 1] + off[2][s[2] + 1];
-        s[AX] = ht - 1;
-        const long lo = off[0][s[0] + 1] + off[1][s[1] + 1] + off[2][s[2] + 1];
-        return G[hi] - G[lo];
-    };
-    R v = a * D(0, 0);
-    if (b != R(0) || c != R(0)) {
-        v += b * (D(1, 0) + D(-1, 0) + D(0, 1) + D(0, -1));
-        if (c != R(0)) v += c * (D(1, 1) + D(1, -1) + D(-1, 1) + D(-1, -1));
-    }
-    return v * id;
-}
-
 // split update of one component from its curl terms t1 (axis A1, the stored part) and t2
 template <int A1, int A2, typename R>
 __device__ __forceinline__ R split_update(R old, R* sp, long o, R t1, R t2, const Pml3& pml, const int q[3],
@@ -159,79 +93,162 @@ __device__ __forceinline__ R split_update(R old, R* sp, long o, R t1, R t2, cons
     return p1 + p2;
 }
 
-template <typename R>
-__global__ void __launch_bounds__(NT) k3_friedman(G3 g, F3<R> f, R th)
+// Faraday with Friedman's E-tilde made on the fly.  A workgroup owns a 32 x 8 tile of (x, y)
+// and FMZ planes along z; it marches up z keeping three planes (k - 1, k, k + 1) of E-tilde with
+// a one-cell (x, y) halo in LDS, so each E value is read from HBM once per tile instead of once
+// per stencil point.  Delta* (Sec. 4.2) reaches one cell along every axis.  With Friedman
+// damping (Sec. 4.3), E-tilde = (1 + theta/4) E^n - E^{n-1}/2 + (1/2 - theta/4) Ebar^n with the
+// recursion Ebar^n = (1 - theta/2) E^{n-1} + (theta/2) Ebar^{n-1}; the new Ebar goes to the
+// second Ebar buffer (f.T), written by the tile that owns the cell, so no workgroup reads a
+// value another one has already replaced.  Cells beyond a non-periodic edge read 0.
+constexpr int FMX = CBX, FMY = CBY, FMZ = 16;
+constexpr int FPX = FMX + 2, FPP = (FMX + 2) * (FMY + 2);
+
+// Delta*_AX of one E-tilde component from the three LDS planes pl[0..2] = k - 1, k, k + 1 at
+// padded tile position (cx, cy): alpha D + beta (the four S^1 shifts) + gamma (the four S^2
+// shifts), times 1/d
+template <int AX, typename R>
+__device__ __forceinline__ R dstar_lds(const R* const pl[3], int cx, int cy, int ht, R a, R b, R c, R id)
 {
-    int q[3];
-    if (!cell_of(g, q)) return;
-    const long o = o3(g, q[0], q[1], q[2]);
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-        const R eo = f.Eo[c][o];
-        const R eb = (R(1) - R(0.5) * th) * eo + R(0.5) * th * f.Eb[c][o];
-        f.Eb[c][o] = eb;
-        f.T[c][o] = (R(1) + R(0.25) * th) * f.E[c][o] - R(0.5) * eo + (R(0.5) - R(0.25) * th) * eb;
+    constexpr int T1 = (AX + 1) % 3, T2 = (AX + 2) % 3;
+    auto D = [&](int t1, int t2) {
+        int s[3];
+        s[T1] = t1;
+        s[T2] = t2;
+        s[AX] = ht;
+        const R hi = pl[s[2] + 1][(cy + s[1]) * FPX + cx + s[0]];
+        s[AX] = ht - 1;
+        const R lo = pl[s[2] + 1][(cy + s[1]) * FPX + cx + s[0]];
+        return hi - lo;
+    };
+    R v = a * D(0, 0);
+    if (b != R(0) || c != R(0)) {
+        v += b * (D(1, 0) + D(-1, 0) + D(0, 1) + D(0, -1));
+        if (c != R(0)) v += c * (D(1, 1) + D(1, -1) + D(-1, 1) + D(-1, -1));
     }
+    return v * id;
 }
 
 // dB_C/dt = -(Delta*_A1 E_A2 - Delta*_A2 E_A1), (C, A1, A2) cyclic; B_C sits on a node along C
 // and on half nodes along A1, A2
 template <int C, typename R>
-__device__ __forceinline__ void faraday_comp(const G3& g, const F3<R>& f, const R* const* Et, const Pml3& pml,
-                                             const int q[3], R a, R b, R cg, R dt, bool in, const long (&off)[3][3])
+__device__ __forceinline__ void faraday_cell(const G3& g, const F3<R>& f, const Pml3& pml, const R (*sT)[3][FPP],
+                                             const int sl[3], const int q[3], long o, int cx, int cy, R a, R b,
+                                             R cg, R dt)
 {
     constexpr int A1 = (C + 1) % 3, A2 = (C + 2) % 3;
     const int h[3] = {C == 0 ? 0 : 1, C == 1 ? 0 : 1, C == 2 ? 0 : 1};
-    const long o = o3(g, q[0], q[1], q[2]);
     const R old = f.B[C][o];
     f.Bo[C][o] = old;
 #pragma unroll
     for (int d = 0; d < 3; d++)
         if (!g.per[d] && q[d] > g.S[d] - 1 - h[d]) return;
-    R t1, t2;
-    if (in) {
-        t1 = -dstar_in<A1>(Et[A2], off, h[A1], a, b, cg, (R)(1.0 / g.d[A1]));
-        t2 = dstar_in<A2>(Et[A1], off, h[A2], a, b, cg, (R)(1.0 / g.d[A2]));
-    } else {
-        t1 = -dstar<A1>(Et[A2], g, q, h[A1], a, b, cg);
-        t2 = dstar<A2>(Et[A1], g, q, h[A2], a, b, cg);
-    }
+    const R* p2[3] = {sT[sl[0]][A2], sT[sl[1]][A2], sT[sl[2]][A2]};
+    const R* p1[3] = {sT[sl[0]][A1], sT[sl[1]][A1], sT[sl[2]][A1]};
+    const R t1 = -dstar_lds<A1>(p2, cx, cy, h[A1], a, b, cg, (R)(1.0 / g.d[A1]));
+    const R t2 = dstar_lds<A2>(p1, cx, cy, h[A2], a, b, cg, (R)(1.0 / g.d[A2]));
     f.B[C][o] = split_update<A1, A2>(old, f.SB[C], o, t1, t2, pml, q, h, dt);
 }
 
+// the E-tilde inputs of the padded-plane cells a thread loads (two at most: FPP <= 2 NT)
 template <typename R>
-__global__ void __launch_bounds__(NT) k3_faraday(G3 g, F3<R> f, Pml3 pml, R a, R b, R cg, R dt, int use_t)
+struct PlaneRegs {
+    R e[2][3], eo[2][3], eb[2][3];
+    long o[2];
+    bool ok[2], own[2];
+};
+
+template <typename R, bool FRIED>
+__global__ void __launch_bounds__(NT) k3_faraday(G3 g, F3<R> f, Pml3 pml, R a, R b, R cg, R dt, R th)
 {
-    int q[3];
-    if (!cell_of(g, q)) return;
-    const R* Et[3] = {use_t ? f.T[0] : f.E[0], use_t ? f.T[1] : f.E[1], use_t ? f.T[2] : f.E[2]};
-    bool in = true;
+    static_assert(FPP <= 2 * NT, "a thread loads at most two cells of a padded plane");
+    __shared__ R sT[3][3][FPP];   // [ring slot][component][padded plane cell]
+    const int tid = (int)(threadIdx.y * FMX + threadIdx.x);
+    const int x0 = (int)blockIdx.x * FMX, y0 = (int)blockIdx.y * FMY;
+    const int k0 = (int)blockIdx.z * FMZ, k1 = min(k0 + FMZ, g.S[2]);
+    // issue the loads of plane kk (stored z index, k0 - 1 .. k1); they complete while the
+    // previous plane is computed
+    auto fetch = [&](int kk, PlaneRegs<R>& r) {
+        const int kz = nb(kk, 0, g.S[2], g.per[2]);
 #pragma unroll
-    for (int d = 0; d < 3; d++) in = in && (g.per[d] || (q[d] >= 1 && q[d] <= g.S[d] - 2));
-    long off[3][3];
+        for (int m = 0; m < 2; m++) {
+            const int i = tid + m * NT;
+            const int lx = i % FPX, ly = i / FPX;
+            const int xr = x0 - 1 + lx, yr = y0 - 1 + ly;
+            const int x = nb(xr, 0, g.S[0], g.per[0]), y = nb(yr, 0, g.S[1], g.per[1]);
+            r.ok[m] = i < FPP && x >= 0 && y >= 0 && kz >= 0;
+            r.own[m] = lx >= 1 && lx <= FMX && ly >= 1 && ly <= FMY && xr < g.S[0] && yr < g.S[1] && kk >= k0 &&
+                       kk < k1;
+            r.o[m] = r.ok[m] ? o3(g, x, y, kz) : 0;
 #pragma unroll
-    for (int s = -1; s <= 1; s++) {
-        off[0][s + 1] = nb(q[0], s, g.S[0], g.per[0]);
-        off[1][s + 1] = (long)nb(q[1], s, g.S[1], g.per[1]) * g.pitch;
-        int kk = nb(q[2], s, g.S[2], g.per[2]) + g.zoff;
-        if (kk >= g.S[2]) kk -= g.S[2];
-        off[2][s + 1] = (long)kk * g.plane;
+            for (int c = 0; c < 3; c++) {
+                r.e[m][c] = r.ok[m] ? f.E[c][r.o[m]] : R(0);
+                if constexpr (FRIED) {
+                    r.eo[m][c] = r.ok[m] ? f.Eo[c][r.o[m]] : R(0);
+                    r.eb[m][c] = r.ok[m] ? f.Eb[c][r.o[m]] : R(0);
+                }
+            }
+        }
+    };
+    // E-tilde of the fetched plane into its ring slot (kk - k0 + 1) mod 3; the owner of each
+    // cell stores the new Ebar
+    auto store = [&](int kk, const PlaneRegs<R>& r) {
+        const int sl = (kk - k0 + 1) % 3;
+#pragma unroll
+        for (int m = 0; m < 2; m++) {
+            const int i = tid + m * NT;
+            if (i >= FPP) continue;
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                R v = r.e[m][c];
+                if constexpr (FRIED) {
+                    const R eo = r.eo[m][c];
+                    const R eb = (R(1) - R(0.5) * th) * eo + R(0.5) * th * r.eb[m][c];
+                    v = (R(1) + R(0.25) * th) * r.e[m][c] - R(0.5) * eo + (R(0.5) - R(0.25) * th) * eb;
+                    if (r.ok[m] && r.own[m]) f.T[c][r.o[m]] = eb;
+                }
+                sT[sl][c][i] = r.ok[m] ? v : R(0);
+            }
+        }
+    };
+    PlaneRegs<R> pr;
+    fetch(k0 - 1, pr);
+    store(k0 - 1, pr);
+    fetch(k0, pr);
+    store(k0, pr);
+    fetch(k0 + 1, pr);
+    const int q0 = x0 + (int)threadIdx.x, q1 = y0 + (int)threadIdx.y;
+    const int cx = (int)threadIdx.x + 1, cy = (int)threadIdx.y + 1;
+    for (int k = k0; k < k1; k++) {
+        store(k + 1, pr);
+        __syncthreads();
+        if (k + 2 <= k1) fetch(k + 2, pr);
+        if (q0 < g.S[0] && q1 < g.S[1]) {
+            const int q[3] = {q0, q1, k};
+            const long o = o3(g, q0, q1, k);
+            const int sl[3] = {(k - k0) % 3, (k - k0 + 1) % 3, (k - k0 + 2) % 3};
+            faraday_cell<0>(g, f, pml, sT, sl, q, o, cx, cy, a, b, cg, dt);
+            faraday_cell<1>(g, f, pml, sT, sl, q, o, cx, cy, a, b, cg, dt);
+            faraday_cell<2>(g, f, pml, sT, sl, q, o, cx, cy, a, b, cg, dt);
+        }
+        __syncthreads();
     }
-    faraday_comp<0>(g, f, Et, pml, q, a, b, cg, dt, in, off);
-    faraday_comp<1>(g, f, Et, pml, q, a, b, cg, dt, in, off);
-    faraday_comp<2>(g, f, Et, pml, q, a, b, cg, dt, in, off);
 }
 
 // dE_C/dt = Delta_A1 B_A2 - Delta_A2 B_A1 - J_C; E_C sits on a half node along C, nodes along
-// A1, A2; conducting walls keep the tangential components at 0 (nodes 0 and S-1 of a
-// non-periodic axis stay untouched)
+// A1, A2, so each difference takes B at the cell and one cell below; conducting walls keep the
+// tangential components at 0 (nodes 0 and S-1 of a non-periodic axis stay untouched).  A
+// workgroup owns a 32 x 8 (x, y) tile and FMZ planes and marches up z with planes k - 1 and k of
+// B (and the cells one below in x and y) in LDS, loading plane k + 1 while computing plane k.
+constexpr int APX = FMX + 1, APP = (FMX + 1) * (FMY + 1);
+
 template <int C, typename R>
-__device__ __forceinline__ void ampere_comp(const G3& g, const F3<R>& f, const R* const* J, const Pml3& pml,
-                                            const int q[3], R dt)
+__device__ __forceinline__ void ampere_cell(const G3& g, const F3<R>& f, const R* const* J, const Pml3& pml,
+                                            const R (*sB)[3][APP], int s0, int s1, const int q[3], long o, int cx,
+                                            int cy, R dt)
 {
     constexpr int A1 = (C + 1) % 3, A2 = (C + 2) % 3;
     const int h[3] = {C == 0 ? 1 : 0, C == 1 ? 1 : 0, C == 2 ? 1 : 0};
-    const long o = o3(g, q[0], q[1], q[2]);
     const R old = f.E[C][o];
     f.Eo[C][o] = old;
 #pragma unroll
@@ -239,20 +256,70 @@ __device__ __forceinline__ void ampere_comp(const G3& g, const F3<R>& f, const R
         if (g.per[d]) continue;
         if (q[d] < (h[d] ? 0 : 1) || q[d] > g.S[d] - 2) return;
     }
-    const R t1 = dG<A1>(f.B[A2], g, q, h[A1]) - J[C][o];
-    const R t2 = -dG<A2>(f.B[A1], g, q, h[A2]);
+    // B at the cell and one cell below along axis ax
+    auto diff = [&](int comp, int ax) {
+        const R hi = sB[s1][comp][cy * APX + cx];
+        const R lo = ax == 0 ? sB[s1][comp][cy * APX + cx - 1]
+                             : (ax == 1 ? sB[s1][comp][(cy - 1) * APX + cx] : sB[s0][comp][cy * APX + cx]);
+        return (hi - lo) / (R)g.d[ax];
+    };
+    const R t1 = diff(A2, A1) - J[C][o];
+    const R t2 = -diff(A1, A2);
     f.E[C][o] = split_update<A1, A2>(old, f.SE[C], o, t1, t2, pml, q, h, dt);
 }
 
 template <typename R>
 __global__ void __launch_bounds__(NT) k3_ampere(G3 g, F3<R> f, const R* J0, const R* J1, const R* J2, Pml3 pml, R dt)
 {
-    int q[3];
-    if (!cell_of(g, q)) return;
+    static_assert(APP <= 2 * NT, "a thread loads at most two cells of a padded plane");
+    __shared__ R sB[2][3][APP];
     const R* J[3] = {J0, J1, J2};
-    ampere_comp<0>(g, f, J, pml, q, dt);
-    ampere_comp<1>(g, f, J, pml, q, dt);
-    ampere_comp<2>(g, f, J, pml, q, dt);
+    const int tid = (int)(threadIdx.y * FMX + threadIdx.x);
+    const int x0 = (int)blockIdx.x * FMX, y0 = (int)blockIdx.y * FMY;
+    const int k0 = (int)blockIdx.z * FMZ, k1 = min(k0 + FMZ, g.S[2]);
+    R rv[2][3];
+    auto fetch = [&](int kk) {
+        const int kz = nb(kk, 0, g.S[2], g.per[2]);
+#pragma unroll
+        for (int m = 0; m < 2; m++) {
+            const int i = tid + m * NT;
+            const int lx = i % APX, ly = i / APX;
+            const int x = nb(x0 - 1 + lx, 0, g.S[0], g.per[0]), y = nb(y0 - 1 + ly, 0, g.S[1], g.per[1]);
+            const bool ok = i < APP && x >= 0 && y >= 0 && kz >= 0;
+            const long o = ok ? o3(g, x, y, kz) : 0;
+#pragma unroll
+            for (int c = 0; c < 3; c++) rv[m][c] = ok ? f.B[c][o] : R(0);
+        }
+    };
+    auto store = [&](int kk) {
+        const int sl = (kk - k0 + 1) & 1;
+#pragma unroll
+        for (int m = 0; m < 2; m++) {
+            const int i = tid + m * NT;
+            if (i >= APP) continue;
+#pragma unroll
+            for (int c = 0; c < 3; c++) sB[sl][c][i] = rv[m][c];
+        }
+    };
+    fetch(k0 - 1);
+    store(k0 - 1);
+    fetch(k0);
+    const int q0 = x0 + (int)threadIdx.x, q1 = y0 + (int)threadIdx.y;
+    const int cx = (int)threadIdx.x + 1, cy = (int)threadIdx.y + 1;
+    for (int k = k0; k < k1; k++) {
+        store(k);
+        __syncthreads();
+        if (k + 1 < k1) fetch(k + 1);
+        if (q0 < g.S[0] && q1 < g.S[1]) {
+            const int q[3] = {q0, q1, k};
+            const long o = o3(g, q0, q1, k);
+            const int s0 = (k - k0) & 1, s1 = (k - k0 + 1) & 1;
+            ampere_cell<0>(g, f, J, pml, sB, s0, s1, q, o, cx, cy, dt);
+            ampere_cell<1>(g, f, J, pml, sB, s0, s1, q, o, cx, cy, dt);
+            ampere_cell<2>(g, f, J, pml, sB, s0, s1, q, o, cx, cy, dt);
+        }
+        __syncthreads();
+    }
 }
 
 // ---- current filter: all passes along one axis in LDS ------------------------------------------
@@ -1699,23 +1766,25 @@ __global__ void k3_stations(G3 g, F3<R> f, const double* zlab, int nst, double g
 // ---- launchers ----------------------------------------------------------------------------------
 
 template <typename R>
-void launch3_friedman(const G3& g, const F3<R>& f, double theta, hipStream_t s)
-{
-    hipLaunchKernelGGL((k3_friedman<R>), cells_grid(g), cells_block(), 0, s, g, f, (R)theta);
-}
-
-template <typename R>
 void launch3_faraday(const G3& g, const F3<R>& f, const Pml3& pml, const double ck[3], double theta, double dt,
                      hipStream_t s)
 {
-    hipLaunchKernelGGL((k3_faraday<R>), cells_grid(g), cells_block(), 0, s, g, f, pml, (R)ck[0], (R)ck[1], (R)ck[2],
-                       (R)dt, theta > 0.0 ? 1 : 0);
+    const dim3 grid((unsigned)((g.S[0] + FMX - 1) / FMX), (unsigned)((g.S[1] + FMY - 1) / FMY),
+                    (unsigned)((g.S[2] + FMZ - 1) / FMZ));
+    if (theta > 0.0)
+        hipLaunchKernelGGL((k3_faraday<R, true>), grid, cells_block(), 0, s, g, f, pml, (R)ck[0], (R)ck[1], (R)ck[2],
+                           (R)dt, (R)theta);
+    else
+        hipLaunchKernelGGL((k3_faraday<R, false>), grid, cells_block(), 0, s, g, f, pml, (R)ck[0], (R)ck[1],
+                           (R)ck[2], (R)dt, (R)theta);
 }
 
 template <typename R>
 void launch3_ampere(const G3& g, const F3<R>& f, const R* const J[3], const Pml3& pml, double dt, hipStream_t s)
 {
-    hipLaunchKernelGGL((k3_ampere<R>), cells_grid(g), cells_block(), 0, s, g, f, J[0], J[1], J[2], pml, (R)dt);
+    const dim3 grid((unsigned)((g.S[0] + FMX - 1) / FMX), (unsigned)((g.S[1] + FMY - 1) / FMY),
+                    (unsigned)((g.S[2] + FMZ - 1) / FMZ));
+    hipLaunchKernelGGL((k3_ampere<R>), grid, cells_block(), 0, s, g, f, J[0], J[1], J[2], pml, (R)dt);
 }
 
 bool filter_seq(int npass, int comp, int stride_mask, FiltSeq* fs)
@@ -1745,13 +1814,21 @@ void fline(const G3& g, const Lines3<TI, TO>& L, int ncomp, const FiltSeq& fs, h
     constexpr int BC = fline_bc<AX>();
     constexpr size_t LDS_MAX = 144 * 1024;
     const int S = g.S[AX];
-    int tseg;
-    if (AX == 0) tseg = S + 2 * fs.reach <= 1024 ? S : 512;
-    else tseg = std::min(S, sizeof(T) == 4 ? 128 : 64);
     auto lds_of = [&](int t) {
         const int A = t + 2 * fs.reach;
         return 2 * (size_t)(AX == 0 ? BC * (A + 1) : A * (BC + 1)) * sizeof(T);
     };
+    // segments along AX: the whole line when its halo-padded copy fits a third of the LDS (three
+    // workgroups per CU), else equal segments of at most 128 (FP32) or 64 (FP64) cells, so that
+    // no segment is mostly halo
+    int tseg;
+    if (AX == 0) tseg = S + 2 * fs.reach <= 1024 ? S : 512;
+    else if (lds_of(S) <= 48 * 1024) tseg = S;
+    else {
+        const int cap = sizeof(T) == 4 ? 128 : 64;
+        const int n = (S + cap - 1) / cap;
+        tseg = (S + n - 1) / n;
+    }
     while (tseg > 16 && lds_of(tseg) > LDS_MAX) tseg /= 2;       // long reaches: shorter segments
     const size_t lds = lds_of(tseg);
     const int nseg = (S + tseg - 1) / tseg;
@@ -1976,7 +2053,6 @@ void launch3_stations(const G3& g, const F3<R>& f, const double* zlab, int nst, 
 }
 
 #define BF3_INST(R)                                                                                           \
-    template void launch3_friedman<R>(const G3&, const F3<R>&, double, hipStream_t);                        \
     template void launch3_faraday<R>(const G3&, const F3<R>&, const Pml3&, const double*, double, double,   \
                                      hipStream_t);                                                          \
     template void launch3_ampere<R>(const G3&, const F3<R>&, const R* const*, const Pml3&, double,          \
