@@ -46,7 +46,7 @@ class _Cfg(C.Structure):
                 ("theta", C.c_double), ("cfl_fraction", C.c_double), ("filter_npass", C.c_int),
                 ("filter_compensate", C.c_int), ("gamma_boost", C.c_double),
                 ("moving_window", C.c_int), ("seed", C.c_uint64), ("filter_strides", C.c_int),
-                ("gather_kind", C.c_int), ("pusher", C.c_int)]
+                ("gather_kind", C.c_int), ("pusher", C.c_int), ("pml_kind", C.c_int)]
 
 
 class _Plasma(C.Structure):
@@ -147,7 +147,7 @@ class Oracle:
 
     def __init__(self, config: dict):
         L = lib()
-        c = _Cfg(**{k: config.get(k, {"filter_strides": 1, "gather_kind": 0, "pusher": 0}[k]) if k in ("filter_strides", "gather_kind", "pusher") else config[k] for k, _ in _Cfg._fields_})
+        c = _Cfg(**{k: config.get(k, {"filter_strides": 1, "gather_kind": 0, "pusher": 0, "pml_kind": 0}[k]) if k in ("filter_strides", "gather_kind", "pusher", "pml_kind") else config[k] for k, _ in _Cfg._fields_})
         self._h = L.orc_create(C.byref(c))
         if not self._h:
             raise ValueError("oracle rejected the configuration")

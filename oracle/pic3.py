@@ -29,7 +29,7 @@ class _Cfg3(C.Structure):
                 ("theta", C.c_double), ("cfl_fraction", C.c_double), ("filter_npass", C.c_int),
                 ("filter_compensate", C.c_int), ("gamma_boost", C.c_double),
                 ("moving_window", C.c_int), ("seed", C.c_uint64), ("filter_strides", C.c_int),
-                ("gather_kind", C.c_int), ("pusher", C.c_int)]
+                ("gather_kind", C.c_int), ("pusher", C.c_int), ("pml_kind", C.c_int)]
 
 
 class _Info3(C.Structure):
@@ -85,7 +85,7 @@ class Oracle3:
     """One FP64 reference simulation in 3D (fields [z][y][x])."""
 
     def __init__(self, config: dict):
-        c = _Cfg3(**{k: config.get(k, {"filter_strides": 1, "gather_kind": 0, "pusher": 0}[k]) if k in ("filter_strides", "gather_kind", "pusher") else config[k] for k, _ in _Cfg3._fields_})
+        c = _Cfg3(**{k: config.get(k, {"filter_strides": 1, "gather_kind": 0, "pusher": 0, "pml_kind": 0}[k]) if k in ("filter_strides", "gather_kind", "pusher", "pml_kind") else config[k] for k, _ in _Cfg3._fields_})
         self._h = lib3().orc3_create(C.byref(c))
         if not self._h:
             raise ValueError("oracle rejected the configuration")

@@ -168,6 +168,31 @@ static void pml_coef(double sig, double dt, double* xi, double* c)
     *c = (1.0 - *xi) / sig;
 }
 
+/* Modified coefficients (Appendix II, sigma*; the printed formula is garbled, see the design
+   notes for this reading).  Along the layer's axis every field value sits on the half-cell grid
+   p = 0, 1/2, 1, ...; the update of the value at p is  F <- xi(p) F + dt kappa(p) (curl term).
+   A wave at normal incidence with c dt = d crosses each half cell without reflection when
+   kappa(p + 1/2) kappa(p) = xi(p), walking outwards from the inner edge where kappa = 1 (lower
+   layer: kappa(p - 1/2) kappa(p) = xi(p)). */
+static double kappa_at(const axis_t* a, double p, double dt)
+{
+    if (sigma_at(a, p) == 0.0) return 1.0;
+    double k = 1.0;
+    if (p > (double)a->N) {
+        for (double q = (double)a->N; q < p; q += 0.5) k = exp(-sigma_at(a, q) * dt) / k;
+    } else {
+        for (double q = 0.0; q > p; q -= 0.5) k = exp(-sigma_at(a, q) * dt) / k;
+    }
+    return k;
+}
+
+/* xi and the curl coefficient of the value at position p along axis a */
+static void pml_at(const orc_sim* s, const axis_t* a, double p, double dt, double* xi, double* c)
+{
+    pml_coef(sigma_at(a, p), dt, xi, c);
+    if (s->cfg.pml_kind == 1 && *xi != 1.0) *c = dt * kappa_at(a, p, dt);
+}
+
 static inline double* FLD(orc_sim* s, int c) { return s->f[c]; }
 static inline long ID(const orc_sim* s, long i, long k) { return k * s->ax.S + i; }
 
@@ -475,7 +500,7 @@ void orc_stage_faraday(orc_sim* s)
     for (long k = 0; k <= hi_b(&s->az, 1); k++)
         for (long i = 0; i <= hi_b(&s->ax, 0); i++) {
             double d = dzStar(s, Et[1], i, k, 1);
-            double xi, c; pml_coef(sigma_at(&s->az, spos(&s->az, k, 1)), dt, &xi, &c);
+            double xi, c; pml_at(s, &s->az, spos(&s->az, k, 1), dt, &xi, &c);
             long q = ID(s, i, k);
             Bx[q] = xi * Bx[q] + c * d;
         }
@@ -483,7 +508,7 @@ void orc_stage_faraday(orc_sim* s)
     for (long k = 0; k <= hi_b(&s->az, 0); k++)
         for (long i = 0; i <= hi_b(&s->ax, 1); i++) {
             double d = -dxStar(s, Et[1], i, k, 1);
-            double xi, c; pml_coef(sigma_at(&s->ax, spos(&s->ax, i, 1)), dt, &xi, &c);
+            double xi, c; pml_at(s, &s->ax, spos(&s->ax, i, 1), dt, &xi, &c);
             long q = ID(s, i, k);
             Bz[q] = xi * Bz[q] + c * d;
         }
@@ -495,7 +520,9 @@ void orc_stage_faraday(orc_sim* s)
             double sx = sigma_at(&s->ax, spos(&s->ax, i, 1)), sz = sigma_at(&s->az, spos(&s->az, k, 1));
             long q = ID(s, i, k);
             if (sx == 0.0 && sz == 0.0) { By[q] = By[q] + dt * (dX + dZ); continue; }
-            double xix, cx, xiz, cz; pml_coef(sx, dt, &xix, &cx); pml_coef(sz, dt, &xiz, &cz);
+            double xix, cx, xiz, cz;
+            pml_at(s, &s->ax, spos(&s->ax, i, 1), dt, &xix, &cx);
+            pml_at(s, &s->az, spos(&s->az, k, 1), dt, &xiz, &cz);
             double px = Byx[q], pz = By[q] - Byx[q];
             px = xix * px + cx * dX;
             pz = xiz * pz + cz * dZ;
@@ -528,7 +555,7 @@ void orc_stage_ampere(orc_sim* s)
         for (long i = lo_e(&s->ax, 1); i <= hi_e(&s->ax); i++) {
             long q = ID(s, i, k);
             double d = -dzG(s, By, i, k, 0) - Jx[q];
-            double xi, c; pml_coef(sigma_at(&s->az, spos(&s->az, k, 0)), dt, &xi, &c);
+            double xi, c; pml_at(s, &s->az, spos(&s->az, k, 0), dt, &xi, &c);
             Ex[q] = xi * Exo[q] + c * d;
         }
     /* E_z at (node x, half z): dE/dt = + Delta_x B_y - J_z */
@@ -536,7 +563,7 @@ void orc_stage_ampere(orc_sim* s)
         for (long i = lo_e(&s->ax, 0); i <= hi_e(&s->ax); i++) {
             long q = ID(s, i, k);
             double d = dxG(s, By, i, k, 0) - Jz[q];
-            double xi, c; pml_coef(sigma_at(&s->ax, spos(&s->ax, i, 0)), dt, &xi, &c);
+            double xi, c; pml_at(s, &s->ax, spos(&s->ax, i, 0), dt, &xi, &c);
             Ez[q] = xi * Ezo[q] + c * d;
         }
     /* E_y at (node x, node z): dE/dt = - Delta_x B_z + Delta_z B_x - J_y, split in the PML
@@ -548,7 +575,9 @@ void orc_stage_ampere(orc_sim* s)
             double dZ = dzG(s, Bx, i, k, 0);
             double sx = sigma_at(&s->ax, spos(&s->ax, i, 0)), sz = sigma_at(&s->az, spos(&s->az, k, 0));
             if (sx == 0.0 && sz == 0.0) { Ey[q] = Eyo[q] + dt * (dX + dZ); continue; }
-            double xix, cx, xiz, cz; pml_coef(sx, dt, &xix, &cx); pml_coef(sz, dt, &xiz, &cz);
+            double xix, cx, xiz, cz;
+            pml_at(s, &s->ax, spos(&s->ax, i, 0), dt, &xix, &cx);
+            pml_at(s, &s->az, spos(&s->az, k, 0), dt, &xiz, &cz);
             double px = Eyx[q], pz = Eyo[q] - Eyx[q];
             px = xix * px + cx * dX;
             pz = xiz * pz + cz * dZ;

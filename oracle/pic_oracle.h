@@ -42,6 +42,8 @@ typedef struct {
                                  location; 1: momentum conserving, the fields interpolated
                                  to the nodes first (Sec. 5.3)                              */
     int pusher;               /* 0: Boris; 1: Vay (Phys. Plasmas 15, 056701, 2008)          */
+    int pml_kind;             /* 0: c = (1 - xi)/sigma; 1: the modified coefficients (the
+                                 layer matched cell by cell, Appendix II's sigma*)           */
 } orc_config;
 
 typedef struct {

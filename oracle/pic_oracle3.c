@@ -139,6 +139,22 @@ static void pml_coef(double sig, double dt, double* xi, double* c)
     *c = (1.0 - *xi) / sig;
 }
 
+/* Modified coefficients (Appendix II, sigma*; reading as in the 2D oracle): the curl
+   coefficient of the value at half-grid position p along the layer's axis is dt kappa(p), with
+   kappa(p + 1/2) kappa(p) = xi(p) walking outwards from the inner edge (kappa = 1 inside), which
+   lets a normally incident wave with c dt = d cross every half cell without reflection. */
+static double kappa3_at(const ax3_t* a, double p, double dt)
+{
+    if (sigma_at(a, p) == 0.0) return 1.0;
+    double k = 1.0;
+    if (p > (double)a->N) {
+        for (double q = (double)a->N; q < p; q += 0.5) k = exp(-sigma_at(a, q) * dt) / k;
+    } else {
+        for (double q = 0.0; q > p; q -= 0.5) k = exp(-sigma_at(a, q) * dt) / k;
+    }
+    return k;
+}
+
 static inline long ID3(const orc3_sim* s, long i, long j, long k)
 {
     return (k * s->a[1].S + j) * s->a[0].S + i;
@@ -377,14 +393,20 @@ static long b_hi(const ax3_t* a, int h) { return a->periodic ? a->S - 1 : a->S -
 static long e_lo(const ax3_t* a, int h) { return (a->periodic || h) ? 0 : 1; }
 static long e_hi(const ax3_t* a) { return a->periodic ? a->S - 1 : a->S - 2; }
 
-/* split update of one component from its two curl terms t1 (axis a1, stored part) and t2 */
-static void split_update(double* F, double* Sp, const double* Fold, long q, double t1, double t2,
-                         double s1, double s2, double dt)
+/* split update of one component from its two curl terms t1 (axis a1 at position r1, the stored
+   part) and t2 (axis a2 at r2) */
+static void split_update(const orc3_sim* s, double* F, double* Sp, const double* Fold, long q, double t1,
+                         double t2, int a1, double r1, int a2, double r2, double dt)
 {
+    const double s1 = sigma_at(&s->a[a1], r1), s2 = sigma_at(&s->a[a2], r2);
     if (s1 == 0.0 && s2 == 0.0) { F[q] = Fold[q] + dt * (t1 + t2); return; }
     double xi1, c1, xi2, c2;
     pml_coef(s1, dt, &xi1, &c1);
     pml_coef(s2, dt, &xi2, &c2);
+    if (s->cfg.pml_kind == 1) {
+        if (s1 != 0.0) c1 = dt * kappa3_at(&s->a[a1], r1, dt);
+        if (s2 != 0.0) c2 = dt * kappa3_at(&s->a[a2], r2, dt);
+    }
     double p1 = Sp[q], p2 = Fold[q] - Sp[q];
     p1 = xi1 * p1 + c1 * t1;
     p2 = xi2 * p2 + c2 * t2;
@@ -424,9 +446,8 @@ void orc3_stage_faraday(orc3_sim* s)
                 for (q[0] = 0; q[0] <= b_hi(&s->a[0], h[0]); q[0]++) {
                     double t1 = -dStar(s, Et[a2], q, a1, h[a1]);
                     double t2 = dStar(s, Et[a1], q, a2, h[a2]);
-                    double s1 = sigma_at(&s->a[a1], spos(&s->a[a1], q[a1], h[a1]));
-                    double s2 = sigma_at(&s->a[a2], spos(&s->a[a2], q[a2], h[a2]));
-                    split_update(B, Sp, B, IDq(s, q), t1, t2, s1, s2, dt);
+                    split_update(s, B, Sp, B, IDq(s, q), t1, t2, a1, spos(&s->a[a1], q[a1], h[a1]), a2,
+                                 spos(&s->a[a2], q[a2], h[a2]), dt);
                 }
     }
     if (th > 0.0) for (int c = 0; c < 3; c++) free(Et[c]);
@@ -454,9 +475,8 @@ void orc3_stage_ampere(orc3_sim* s)
                     long id = IDq(s, q);
                     double t1 = dG(s, Ba2, q, a1, h[a1]) - J[id];
                     double t2 = -dG(s, Ba1, q, a2, h[a2]);
-                    double s1 = sigma_at(&s->a[a1], spos(&s->a[a1], q[a1], h[a1]));
-                    double s2 = sigma_at(&s->a[a2], spos(&s->a[a2], q[a2], h[a2]));
-                    split_update(Ef, Sp, Eold, id, t1, t2, s1, s2, dt);
+                    split_update(s, Ef, Sp, Eold, id, t1, t2, a1, spos(&s->a[a1], q[a1], h[a1]), a2,
+                                 spos(&s->a[a2], q[a2], h[a2]), dt);
                 }
     }
 }

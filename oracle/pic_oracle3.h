@@ -35,6 +35,7 @@ typedef struct {
     uint64_t seed;
     int filter_strides;                  /* stride mask, as in orc_config                    */
     int gather_kind, pusher;             /* as in orc_config                                 */
+    int pml_kind;                        /* as in orc_config                                 */
 } orc3_config;
 
 /* field component ids; the split arrays S hold the PML part along the cyclic-next axis of the

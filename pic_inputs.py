@@ -41,7 +41,7 @@ def boosted_cell(gamma: float, frac: float = 1.0 / 32.0, lam: float = LAMBDA_UM)
 def make_config(nx, nz, dx_um, dz_um, *, pml_cells=10, periodic_x=0, periodic_z=0, ck="yee",
                 theta=0.0, cfl_fraction=0.95, filter_npass=0, filter_compensate=0,
                 gamma_boost=1.0, moving_window=0, seed=1009, real="f64", filter_strides=1,
-                gather_kind=0, pusher=0):
+                gather_kind=0, pusher=0, pml_kind=0):
     """filter_strides: mask of the filter strides (bit s-1: stride s), e.g. 0b11 = S(1:2),
     0b111 = S(1:2:3), 0b1011 = S(1:2:4); gather_kind 0 energy conserving, 1 momentum
     conserving; pusher 0 Boris, 1 Vay."""
@@ -52,7 +52,8 @@ def make_config(nx, nz, dx_um, dz_um, *, pml_cells=10, periodic_x=0, periodic_z=
                 cfl_fraction=float(cfl_fraction), filter_npass=int(filter_npass),
                 filter_compensate=int(filter_compensate), gamma_boost=float(gamma_boost),
                 moving_window=int(moving_window), seed=int(seed), real=real,
-                filter_strides=int(filter_strides), gather_kind=int(gather_kind), pusher=int(pusher))
+                filter_strides=int(filter_strides), gather_kind=int(gather_kind), pusher=int(pusher),
+                pml_kind=int(pml_kind))
 
 
 def plasma(n0_cm3, ppc, *, ramp_um=0.0, start_um=0.0, ion_mode=0):
@@ -223,9 +224,10 @@ def small_boosted(real="f64", nx=40, nz=150, ppc=4, seed=78, gamma=13.0, preload
 def make_config3(nx, ny, nz, dx_um, dy_um, dz_um, *, pml_cells=10, periodic_x=0, periodic_y=0,
                  periodic_z=0, ck="yee", theta=0.0, cfl_fraction=0.95, filter_npass=0,
                  filter_compensate=0, gamma_boost=1.0, moving_window=0, seed=1009, real="f64",
-                 filter_strides=1, gather_kind=0, pusher=0):
+                 filter_strides=1, gather_kind=0, pusher=0, pml_kind=0):
     a, b, g = CK_SETS[ck] if isinstance(ck, str) else ck
-    return dict(dim=3, filter_strides=int(filter_strides), gather_kind=int(gather_kind), pusher=int(pusher), nx=int(nx), ny=int(ny), nz=int(nz), dx_um=float(dx_um), dy_um=float(dy_um),
+    return dict(dim=3, filter_strides=int(filter_strides), gather_kind=int(gather_kind), pusher=int(pusher),
+                pml_kind=int(pml_kind), nx=int(nx), ny=int(ny), nz=int(nz), dx_um=float(dx_um), dy_um=float(dy_um),
                 dz_um=float(dz_um), pml_cells=int(pml_cells), periodic_x=int(periodic_x),
                 periodic_y=int(periodic_y), periodic_z=int(periodic_z), ck_alpha=a, ck_beta=b,
                 ck_gamma=g, theta=float(theta), cfl_fraction=float(cfl_fraction),
