@@ -21,7 +21,8 @@ the FP64 CPU oracle timed on a bounded sample of the headline workload, on one h
 all of them (at most 16).
 
 Other workloads: --workload c2 (the 2D run as the headline), c4 (the batched scan), c5
-(learned vs plain current filter).
+(learned vs plain current filter), dtscan (the time-step scan of the high-frequency
+instability), pml (Appendix II's layer test, standard against modified coefficients).
 """
 from __future__ import annotations
 
@@ -398,6 +399,49 @@ def bench_learned_filter_study(args):
     }
 
 
+def bench_pml(args):
+    """Appendix II's layer test on the GPU at the paper's size: a pulse with the Harris profile
+    (diameter L = 50 cells) from the centre of a 400 x 400 box with an 8-cell layer (sigma =
+    (4/delta)(i/5)^2), Yee at 0.99 and CK at 0.95 of the Courant limit (the modified layer is
+    unstable with CK at 0.99), FP64.  The residue is the largest
+    difference, over the interior, from a 1000 x 1000 box whose layer the pulse has not reached,
+    after 560 steps; standard coefficients against the modified ones (sigma*)."""
+    import numpy as np
+    import pic_inputs as pi
+    from paper_1009_2727_amd import Sim
+    n, big, P, L, steps = 400, 1000, 8, 50.0, 560
+
+    cfls = {"yee": 0.99, "ck": 0.95}
+
+    def run(kind, ck, size):
+        cfg = pi.make_config(size, size, 1.0, 1.0, pml_cells=P, periodic_x=0, periodic_z=0, ck=ck,
+                             cfl_fraction=cfls[ck], pml_kind=kind, real="f64")
+        sim = Sim(cfg, capacity=1)
+        Sz, Sx = sim.shape
+        x = np.arange(Sx) - P
+        X, Z = np.meshgrid(x, x)
+        r = np.hypot(X - size / 2, Z - size / 2)
+        s = 0.5 + r / L
+        h = (10 - 15 * np.cos(2 * np.pi * s) + 6 * np.cos(4 * np.pi * s) - np.cos(6 * np.pi * s)) / 32
+        h[r >= L / 2] = 0.0
+        sim.set_field("Ey", h)
+        sim.step(steps)
+        out = sim.field("Ey")
+        sim.close()
+        return out
+
+    res = {}
+    for ck in ("yee", "ck"):
+        ref = run(0, ck, big)
+        off = (big - n) // 2
+        sub = ref[off:off + n + 2 * P + 1, off:off + n + 2 * P + 1][P:P + n, P:P + n]
+        r = [float(np.abs(run(k, ck, n)[P:P + n, P:P + n] - sub).max()) for k in (0, 1)]
+        res[ck] = {"cfl_fraction": cfls[ck], "residue_sigma": r[0], "residue_sigma_star": r[1],
+                   "ratio": r[0] / r[1]}
+    return {"workload": "PML test, Appendix II (400x400, 8-cell layer, Harris pulse L = 50 cells)",
+            "steps": steps, "results": res}
+
+
 def bench_dt_scan(args):
     """Growth of the high-frequency instability against the time step (Sec. 5.3, "Effects of time
     step"): the boosted instability family (gamma = 13, 1e19 cm^-3 pre-loaded, square cells of
@@ -532,7 +576,7 @@ def main():
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("WORKLOAD", "FETCH_DIR", "WRITE_DIR", "COPY_GIB"))
-    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "dtscan"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "dtscan", "pml"], default="c3",
                     help="c3: the 3D 128x128x1024 boosted run (default, with c2 beside it); c2: the 256x4096 "
                          "boosted run; c4: the batched scan of independent boosted runs (persistent batched "
                          "launch vs one run at a time); c5: learned vs plain current filter; dtscan: "
@@ -574,6 +618,9 @@ def main():
         return
     if args.workload == "dtscan":
         print(json.dumps(bench_dt_scan(args)), flush=True)
+        return
+    if args.workload == "pml":
+        print(json.dumps(bench_pml(args)), flush=True)
         return
 
     if args.calib_copy_gib > 0:

@@ -91,7 +91,13 @@ typedef struct {
     uint64_t seed;             /* counter-based RNG seed for plasma loading                    */
     int64_t beam_capacity;     /* beam macro-particles bf_add_beam may load (2D runs; 0: none)  */
     int32_t beam_history;      /* per-step beam records kept (BF_DIAG_BEAM, arg 1)             */
-    int32_t reserved0;
+    int32_t pml_kind;          /* 0: curl coefficient (1 - xi)/sigma; 1: the modified
+                                  coefficients (Appendix II, sigma*): dt kappa(p) with
+                                  kappa(p + 1/2) kappa(p) = xi(p) outwards from the layer's
+                                  inner edge (kappa = 1 inside), which lets a normally incident
+                                  wave at c dt = delta cross every half cell unreflected.
+                                  BF_EUNSUPPORTED with a CK solver above 0.95 of its Courant
+                                  limit, where this layer is unstable                          */
 } bf_config;
 
 /* Plasma given in the lab frame: zero density before start_um, linear up-ramp of ramp_um

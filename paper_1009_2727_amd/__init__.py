@@ -49,7 +49,7 @@ class bf_config(C.Structure):
                 ("sort_every", C.c_int), ("tile_x", C.c_int), ("tile_z", C.c_int),
                 ("max_stations", C.c_int), ("station_capacity", C.c_int), ("phase_timers", C.c_int),
                 ("seed", C.c_uint64), ("beam_capacity", C.c_int64), ("beam_history", C.c_int32),
-                ("reserved0", C.c_int32)]
+                ("pml_kind", C.c_int32)]
 
 
 class bf_plasma(C.Structure):
@@ -242,6 +242,7 @@ def make_config(cfg: dict, capacity: int, stations: int = 0, station_capacity: i
     c.seed = cfg["seed"]
     c.beam_capacity = int(cfg.get("beam_capacity", 0))
     c.beam_history = int(cfg.get("beam_history", 0))
+    c.pml_kind = int(cfg.get("pml_kind", 0))
     return c
 
 

@@ -196,6 +196,11 @@ bf_status validate(const bf_config* c)
     if (c->max_stations < 0 || c->max_stations > 64 || c->station_capacity < 0) return BF_EINVAL;
     if (c->beam_capacity < 0 || c->beam_capacity > (int64_t)INT32_MAX - 65536 || c->beam_history < 0)
         return BF_EINVAL;
+    if (c->pml_kind < 0 || c->pml_kind > 1) return BF_EINVAL;
+    // the modified coefficients with the extended CK stencil grow without bound near the CK
+    // Courant limit (measured at 0.99; bounded at 0.95)
+    if (c->pml_kind == 1 && (c->ck_beta != 0.0 || c->ck_gamma != 0.0) && c->cfl_fraction > 0.95)
+        return BF_EUNSUPPORTED;
     const double a2 = c->ck_alpha + 2 * c->ck_beta;
     if (std::fabs(c->ck_alpha + 4 * c->ck_beta + 4 * c->ck_gamma - 1.0) > 1e-12) return BF_EINVAL;
     (void)a2;
@@ -406,6 +411,20 @@ double sigma_at(double p, int N, int P, double d)
     return (4.0 / d) * (dep / 5.0) * (dep / 5.0);
 }
 
+// curl coefficient of the layer value at half-grid position p: dt (1 - xi)/(sigma dt) for the
+// standard layer; for the modified coefficients dt kappa(p), kappa walked outwards from the
+// inner edge with kappa(p +- 1/2) = xi(p) / kappa(p) (kappa = 1 where sigma = 0)
+double pml_c(int kind, double p, int N, int P, double d, double dt)
+{
+    const double sg = sigma_at(p, N, P, d);
+    if (sg == 0.0) return dt;
+    if (kind == 0) return (1.0 - std::exp(-sg * dt)) / sg;
+    const double step = p > (double)N ? 0.5 : -0.5;
+    double k = 1.0;
+    for (double q = p > (double)N ? (double)N : 0.0; q != p; q += step) k = std::exp(-sigma_at(q, N, P, d) * dt) / k;
+    return dt * k;
+}
+
 template <typename R>
 hipError_t upload_pml(bf_sim* s)
 {
@@ -422,7 +441,7 @@ hipError_t upload_pml(bf_sim* s)
                 const double p = (double)(i - P[ax]) + 0.5 * h;
                 const double sg = sigma_at(p, N[ax], P[ax], d[ax]);
                 double x = 1.0, cc = s->dt;
-                if (sg != 0.0) { x = std::exp(-sg * s->dt); cc = (1.0 - x) / sg; }
+                if (sg != 0.0) { x = std::exp(-sg * s->dt); cc = pml_c(s->cfg.pml_kind, p, N[ax], P[ax], d[ax], s->dt); }
                 xi[i] = (R)x;
                 c[i] = (R)cc;
                 on.push_back(sg != 0.0 ? 1 : 0);
@@ -1059,7 +1078,10 @@ hipError_t upload_pml3(bf_sim* s)
                 sg[i] = L.g.per[a] ? 0.0 : sigma_at(p, L.g.N[a], L.g.P[a], L.g.d[a]);
                 xi[i] = 1.0;
                 c[i] = s->dt;
-                if (sg[i] != 0.0) { xi[i] = std::exp(-sg[i] * s->dt); c[i] = (1.0 - xi[i]) / sg[i]; }
+                if (sg[i] != 0.0) {
+                    xi[i] = std::exp(-sg[i] * s->dt);
+                    c[i] = pml_c(s->cfg.pml_kind, p, L.g.N[a], L.g.P[a], L.g.d[a], s->dt);
+                }
             }
             t.insert(t.end(), sg.begin(), sg.end());
             t.insert(t.end(), xi.begin(), xi.end());

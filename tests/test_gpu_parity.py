@@ -472,3 +472,17 @@ def test_variants_random_state_single_step():
     sim.step(1)
     compare_fields(sim, ref, 1e-12, tag="variants random")
     compare_particles(sim, ref, 1e-9, 1e-10)
+
+
+@gpu
+@pytest.mark.parametrize("real,tol", [("f64", 1e-11), ("f32", 1e-5)])
+def test_modified_pml_coefficients_match_oracle(real, tol):
+    # the boosted case (layer on every face, window, laser) with the modified coefficients
+    w = pi.small_boosted(real=real, nx=40, nz=120, ppc=2)
+    w["config"]["pml_kind"] = 1
+    sim, ref = _sim(w), Oracle.from_workload(w)
+    for n in (10, 30):
+        sim.step(n)
+        ref.step(n)
+        compare_fields(sim, ref, tol, names=FIELDS + ["Byx", "Eyx"], tag=f"pml sigma* {real}")
+    compare_particles(sim, ref, 1e-9 if real == "f64" else 2e-5, 1e-9 if real == "f64" else 1e-4)

@@ -312,3 +312,21 @@ def test_3d_variants_random_state_single_step():
         a, b = sim.field(n), ref.field(n)
         assert np.abs(a - b).max() <= 1e-12 * max(np.abs(b).max(), 1.0), n
     compare_particles3(sim, ref, 1e-9, 1e-10)
+
+
+@gpu
+def test_3d_modified_pml_coefficients_match_oracle():
+    # the vacuum pulse through the layer with the modified coefficients (Appendix II sigma*)
+    w = pi.small_boosted3(real="f64", nx=10, ny=8, nz=30)
+    w["config"]["pml_kind"] = 1
+    sim, ref = _sim(w, plasma=False, laser=False), Oracle3.from_workload(w, plasma=False, laser=False)
+    Sz, Sy, Sx = ref.shape
+    Z, Y, X = np.meshgrid(np.arange(Sz), np.arange(Sy), np.arange(Sx), indexing="ij")
+    f = np.exp(-((X - Sx / 2) ** 2 + (Z - Sz / 2) ** 2) / 8.0)
+    for o in (sim, ref):
+        o.set_field("By", f)
+    sim.step(40)
+    ref.step(40)
+    for n in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+        a, b = sim.field(n), ref.field(n)
+        assert np.abs(a - b).max() <= 1e-11 * np.abs(f).max(), n

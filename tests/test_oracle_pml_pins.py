@@ -45,8 +45,8 @@ def test_matched_layer_reflects_nothing_at_normal_incidence():
     assert mod < 1e-10         # the matched one only round-off
 
 
-def _harris_run(kind, ck, n, steps=220, P=8, L=25.0):
-    cfg = pi.make_config(n, n, 1.0, 1.0, pml_cells=P, periodic_x=0, periodic_z=0, ck=ck, cfl_fraction=0.99,
+def _harris_run(kind, ck, n, cfl, steps=220, P=8, L=25.0):
+    cfg = pi.make_config(n, n, 1.0, 1.0, pml_cells=P, periodic_x=0, periodic_z=0, ck=ck, cfl_fraction=cfl,
                          pml_kind=kind)
     o = Oracle(cfg)
     Sz, Sx = o.shape
@@ -62,14 +62,16 @@ def _harris_run(kind, ck, n, steps=220, P=8, L=25.0):
     return o.field("Ey")
 
 
-@pytest.mark.parametrize("ck,gain", [("yee", 3.0), ("ck", 10.0)])
-def test_modified_coefficients_reflect_less_in_the_papers_pml_test(ck, gain):
-    # a 200 x 200 box against a 500 x 500 reference whose layer is still out of reach
+@pytest.mark.parametrize("ck,cfl,gain", [("yee", 0.99, 3.0), ("ck", 0.95, 10.0)])
+def test_modified_coefficients_reflect_less_in_the_papers_pml_test(ck, cfl, gain):
+    # a 200 x 200 box against a 500 x 500 reference whose layer is still out of reach.  CK runs at
+    # 0.95 of its Courant limit: at 0.99 the modified layer grows without bound after ~500 steps
+    # (the library rejects that combination)
     n, big, P = 200, 500, 8
-    ref = _harris_run(0, ck, big)
+    ref = _harris_run(0, ck, big, cfl)
     off = (big - n) // 2
     sub = ref[off:off + n + 2 * P + 1, off:off + n + 2 * P + 1][P:P + n, P:P + n]
-    res = [np.abs(_harris_run(k, ck, n)[P:P + n, P:P + n] - sub).max() for k in (0, 1)]
+    res = [np.abs(_harris_run(k, ck, n, cfl)[P:P + n, P:P + n] - sub).max() for k in (0, 1)]
     assert res[0] > 1e-5
     assert res[0] / res[1] >= gain, res
 
