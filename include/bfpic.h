@@ -315,10 +315,10 @@ void bf_destroy(bf_sim* sim);
 
 /* ---- batched independent runs -----------------------------------------------------------
    Several handles stepped together, e.g. a scan over boost factor, density, grid and time step
-   (each run follows Sec. 2-4 on its own).  Each heavy phase of a step -- Faraday, particle
-   push, rigid ions, bilinear filter, Ampere -- is one persistent launch over a device queue of
-   (run, work item) pairs; the light phases (stations, antenna, learned filter, window shift,
-   injection, sort) are each run's own launches, in phase order.  Results equal each run's
+   (each run follows Sec. 2-4 on its own).  Faraday, the electron push and Ampere are each one
+   persistent launch over a device queue of (run, work item) pairs; the other phases (stations,
+   rigid ions, antenna, current filter, window shift, injection, sort) are each run's own
+   launches, in phase order.  Results equal each run's
    bf_step up to the order of floating-point atomic additions.  Runs must be FP32 handles on
    the current device without a sticky error; phase timers are not recorded in batched steps. */
 typedef struct bf_batch bf_batch;
@@ -329,8 +329,8 @@ int64_t bf_batch_work_bytes(int nsims);
 /* Creates a batch over n distinct handles (not owned).  work: device buffer of at least
    bf_batch_work_bytes(n) bytes, 256-byte aligned, owned by the caller.  hip_stream: the stream
    of the batched launches (NULL: default).  BF_EINVAL: bad arguments or a repeated handle;
-   BF_EUNSUPPORTED: an FP64 or 3D handle, or one with filter strides other than 1, the
-   momentum-conserving gather or Vay's pusher; BF_ESTATE: a handle with a sticky error;
+   BF_EUNSUPPORTED: an FP64 or 3D handle, or one with the momentum-conserving gather, Vay's
+   pusher or a beam capacity; BF_ESTATE: a handle with a sticky error;
    BF_EDEVICE: pinned staging memory could not be allocated. */
 bf_status bf_batch_create(bf_sim* const* sims, int n, void* work, int64_t work_bytes,
                           void* hip_stream, bf_batch** out);

@@ -1,6 +1,6 @@
 // bf_batch.h -- launches of one step of several runs, gathered per phase, so that a batch of
-// independent runs executes each heavy phase as one persistent launch over a device work queue
-// (the light phases run as the runs' own launches, in phase order).
+// independent runs executes Faraday, the electron push and Ampere as one persistent launch each
+// over a device work queue (the other phases run as the runs' own launches, in phase order).
 #pragma once
 #include <functional>
 #include <vector>
@@ -17,19 +17,15 @@ enum {
 struct BatchRec {
     std::vector<FaradayDesc<float>> faraday;
     std::vector<AmpereDesc<float>> ampere;
-    std::vector<FilterDesc<float>> filter;
     std::vector<GpdDesc<float>> gpd;
-    std::vector<IonDesc<float>> ion;
-    // work items of each descriptor (blocks, tiles or particle segments)
-    std::vector<int> n_faraday, n_ampere, n_filter, n_gpd, n_ion;
-    int max_halo = 0;
+    // work items of each descriptor (cell blocks or particle segments)
+    std::vector<int> n_faraday, n_ampere, n_gpd;
     std::vector<std::function<void(hipStream_t)>> slots[SLOT_COUNT];
 
     void clear()
     {
-        faraday.clear(); ampere.clear(); filter.clear(); gpd.clear(); ion.clear();
-        n_faraday.clear(); n_ampere.clear(); n_filter.clear(); n_gpd.clear(); n_ion.clear();
-        max_halo = 0;
+        faraday.clear(); ampere.clear(); gpd.clear();
+        n_faraday.clear(); n_ampere.clear(); n_gpd.clear();
         for (auto& v : slots) v.clear();
     }
 };

@@ -113,7 +113,8 @@ __device__ __forceinline__ void block_bbox(int& x0, int& x1, int& z0, int& z1, i
 }
 
 // A device work queue over the items of several runs: run r owns items [off[r], off[r+1]);
-// workgroups take items in increasing order from an atomic counter (zero before the launch).
+// workgroups take items in increasing order, from an atomic counter (zero before the launch) or
+// in a static grid-stride share.
 struct QueueRef {
     const int* off;
     int nrun, total;
@@ -127,6 +128,16 @@ __device__ __forceinline__ int next_item(const QueueRef& q, int* slot)
     if (threadIdx.x == 0) *slot = atomicAdd(q.counter, 1);
     __syncthreads();
     const int it = __builtin_amdgcn_readfirstlane(*slot);
+    return it < q.total ? it : -1;
+}
+
+// the workgroup's k-th item of a static grid-stride share of the queue (blockIdx.x + k gridDim.x),
+// or -1 past the end; for phases whose items cost about the same, it spares the counter's atomic
+// round trip per item
+__device__ __forceinline__ int stride_item(const QueueRef& q, int k)
+{
+    __syncthreads();   // the previous item is done with the LDS
+    const int it = (int)blockIdx.x + k * (int)gridDim.x;
     return it < q.total ? it : -1;
 }
 

@@ -7,9 +7,8 @@
 //    Faraday_Friedman, indices shifted by one), split-field PML (Appendix II) on the borders.
 //  * k_ampere: Yee Ampere E^{n+1} = E^n + dt (curl B^{n+1/2} - J) with the PML split.
 //    k_faraday, first in the step, clears the raw current the deposit accumulates into.
-//  * k_filter_batch: n bilinear passes plus compensation per axis (Sec. 4.1) for the batched
-//    runs, all passes of both axes in LDS on a tile with an (n + 1)-cell halo.  Single runs
-//    use the line filter of bf_sim3.hip (any stride mask) on the grid seen with one y plane.
+//  * The current filter (Sec. 4.1) is the line filter of bf_sim3.hip (any stride mask) on the
+//    grid seen with one y plane.
 //  * k_window_rows: moving-window advance = ring offset change + clearing the new rows.
 //  * k_stations: lab-frame stations (Sec. 3.2).
 //  * k_rho: charge density for the Gauss diagnostic.
@@ -199,113 +198,6 @@ __global__ void __launch_bounds__(256) k_ampere(Geo g, FieldSet<R> f, PmlTab<R> 
     ampere_block<R>(g, f, pm, dt, idx, idz, blockIdx.x, blockIdx.y);
 }
 
-// ---- filter ------------------------------------------------------------------------------
-// Tile of FTX x FTZ output cells, halo H = number of passes per axis.  The n passes +
-// compensation along one axis are one (2H+1)-tap stencil (the passes' kernels convolved), so a
-// tile whose stencil support lies inside the component's domain is filtered with one x and one
-// z convolution.  A tile that reaches a non-periodic edge runs the passes one by one with the
-// cells outside the domain held at zero after every pass (zero padding per pass).
-constexpr int FTX = 64, FTZ = 16, FMAXH = 12;
-
-template <typename R>
-__device__ __forceinline__ void filter_tile(const Geo& g, const R* __restrict__ in, R* __restrict__ out,
-                                            int hx, int hz, int npass, int comp, int bx, int by)
-{
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];   // 16-byte aligned: FP64 DS ops
-    R* buf0 = reinterpret_cast<R*>(smem_raw);
-    const int H = npass + (comp ? 1 : 0);
-    const int LX = FTX + 2 * H, LZ = FTZ + 2 * H, L = LX * LZ;
-    R* buf1 = buf0 + L;
-    const int x0 = bx * FTX - H, z0 = by * FTZ - H;
-    const int xmax = smax(g.Sx, g.perx, hx), zmax = smax(g.Sz, g.perz, hz);
-    auto inx = [&](int gi) { return g.perx || (gi >= 0 && gi <= xmax); };
-    auto inz = [&](int gk) { return g.perz || (gk >= 0 && gk <= zmax); };
-    __shared__ R taps[2 * FMAXH + 1];
-    const R ac = R(0.5) * R(npass) + R(1);
-    if (threadIdx.x == 0) {
-        // the passes' 3-point kernels convolved: binomial / 4^n times the compensation stencil
-        R t[2 * FMAXH + 3];
-        for (int k = 0; k < 2 * H + 3; k++) t[k] = R(0);
-        t[H + 1] = R(1);
-        for (int p = 0; p < H; p++) {
-            const R al = (p < npass) ? R(0.5) : ac;
-            const R be = (R(1) - al) * R(0.5);
-            R prev = R(0);
-            for (int k = 1; k <= 2 * H + 1; k++) {
-                const R cur = t[k];
-                t[k] = al * cur + be * (prev + t[k + 1]);
-                prev = cur;
-            }
-        }
-        for (int k = 0; k <= 2 * H; k++) taps[k] = t[k + 1];
-    }
-    for (int q = threadIdx.x; q < L; q += blockDim.x) {
-        int a = q % LX, b = q / LX;
-        int gi = x0 + a, gk = z0 + b;
-        R v = R(0);
-        if (inx(gi) && inz(gk)) {
-            int si = swrap(gi, g.Sx, g.perx), sk = swrap(gk, g.Sz, g.perz);
-            v = in[gofs(g, si, sk)];
-        }
-        buf0[q] = v;
-    }
-    __syncthreads();
-    const bool inner = (g.perx || (x0 >= 0 && x0 + LX - 1 <= xmax)) && (g.perz || (z0 >= 0 && z0 + LZ - 1 <= zmax));
-    if (inner) {
-        for (int q = threadIdx.x; q < LZ * FTX; q += blockDim.x) {
-            const int a = q % FTX, b = q / FTX;
-            const R* row = buf0 + b * LX + a;
-            R s = R(0);
-            for (int k = 0; k <= 2 * H; k++) s += taps[k] * row[k];
-            buf1[b * FTX + a] = s;
-        }
-        __syncthreads();
-        for (int q = threadIdx.x; q < FTX * FTZ; q += blockDim.x) {
-            const int a = q % FTX, b = q / FTX;
-            const int gi = x0 + H + a, gk = z0 + H + b;
-            const R* col = buf1 + b * FTX + a;
-            R s = R(0);
-            for (int k = 0; k <= 2 * H; k++) s += taps[k] * col[k * FTX];
-            if (gi < g.Sx && gk < g.Sz) out[gofs(g, gi, gk)] = s;
-        }
-        return;
-    }
-    R* src = buf0;
-    R* dst = buf1;
-    for (int p = 0; p < H; p++) {
-        const R al = (p < npass) ? R(0.5) : ac;
-        const R be = (R(1) - al) * R(0.5);
-        for (int q = threadIdx.x; q < L; q += blockDim.x) {
-            int a = q % LX, b = q / LX;
-            R l = a > 0 ? src[q - 1] : R(0);
-            R r = a < LX - 1 ? src[q + 1] : R(0);
-            R v = al * src[q] + be * (l + r);
-            dst[q] = (inx(x0 + a) && inz(z0 + b)) ? v : R(0);
-        }
-        __syncthreads();
-        R* t = src; src = dst; dst = t;
-    }
-    for (int p = 0; p < H; p++) {
-        const R al = (p < npass) ? R(0.5) : ac;
-        const R be = (R(1) - al) * R(0.5);
-        for (int q = threadIdx.x; q < L; q += blockDim.x) {
-            int a = q % LX, b = q / LX;
-            R l = b > 0 ? src[q - LX] : R(0);
-            R r = b < LZ - 1 ? src[q + LX] : R(0);
-            R v = al * src[q] + be * (l + r);
-            dst[q] = (inx(x0 + a) && inz(z0 + b)) ? v : R(0);
-        }
-        __syncthreads();
-        R* t = src; src = dst; dst = t;
-    }
-    for (int q = threadIdx.x; q < FTX * FTZ; q += blockDim.x) {
-        int a = q % FTX, b = q / FTX;
-        int gi = x0 + H + a, gk = z0 + H + b;
-        if (gi >= g.Sx || gk >= g.Sz) continue;
-        out[gofs(g, gi, gk)] = src[(b + H) * LX + a + H];
-    }
-}
-
 // ---- momentum-conserving gather: fields to the nodes -------------------------------------
 // Each component of E^n and of B^n = (B^{n-1/2} + B^{n+1/2}) / 2 becomes, at node (i, k), the
 // mean of its values at the Yee locations around the node along its staggered axes: E_x (i -+
@@ -340,10 +232,9 @@ void launch_nodes(const Geo& g, const FieldSet<R>& f, hipStream_t s)
 template <typename R>
 __global__ void __launch_bounds__(256) k_faraday_batch(const FaradayDesc<R>* __restrict__ d, QueueRef q)
 {
-    __shared__ int slot;
     int r = 0;
-    for (;;) {
-        const int it = next_item(q, &slot);
+    for (int k = 0;; k++) {
+        const int it = stride_item(q, k);
         if (it < 0) return;
         r = run_of(q, it, r);
         const FaradayDesc<R>& D = d[r];
@@ -360,10 +251,9 @@ __global__ void __launch_bounds__(256) k_faraday_batch(const FaradayDesc<R>* __r
 template <typename R>
 __global__ void __launch_bounds__(256) k_ampere_batch(const AmpereDesc<R>* __restrict__ d, QueueRef q)
 {
-    __shared__ int slot;
     int r = 0;
-    for (;;) {
-        const int it = next_item(q, &slot);
+    for (int k = 0;; k++) {
+        const int it = stride_item(q, k);
         if (it < 0) return;
         r = run_of(q, it, r);
         const AmpereDesc<R>& D = d[r];
@@ -372,20 +262,6 @@ __global__ void __launch_bounds__(256) k_ampere_batch(const AmpereDesc<R>* __res
     }
 }
 
-template <typename R>
-__global__ void __launch_bounds__(256) k_filter_batch(const FilterDesc<R>* __restrict__ d, QueueRef q)
-{
-    __shared__ int slot;
-    int r = 0;
-    for (;;) {
-        const int it = next_item(q, &slot);
-        if (it < 0) return;
-        r = run_of(q, it, r);
-        const FilterDesc<R>& D = d[r];
-        const int local = it - q.off[r];
-        filter_tile<R>(D.g, D.in, D.out, D.hx, D.hz, D.npass, D.comp, local % D.gx, local / D.gx);
-    }
-}
 
 // ---- moving window -------------------------------------------------------------------------
 // After the ring offset has moved by d rows: clear the d new rows of every array, drop the
@@ -524,17 +400,7 @@ void launch_ampere_batch(const AmpereDesc<R>* d, const QueueRef& q, int nblocks,
         hipLaunchKernelGGL((k_ampere_batch<R>), dim3(nblocks), dim3(256), 0, s, d, q);
 }
 
-template <typename R>
-void launch_filter_batch(const FilterDesc<R>* d, const QueueRef& q, int max_halo, int nblocks,
-                         hipStream_t s)
-{
-    const size_t lds = 2 * (size_t)(FTX + 2 * max_halo) * (FTZ + 2 * max_halo) * sizeof(R);
-    if (q.total > 0)
-        hipLaunchKernelGGL((k_filter_batch<R>), dim3(nblocks), dim3(256), lds, s, d, q);
-}
 
-int filter_tiles(const Geo& g) { return ((g.Sx + FTX - 1) / FTX) * ((g.Sz + FTZ - 1) / FTZ); }
-int filter_tiles_x(const Geo& g) { return (g.Sx + FTX - 1) / FTX; }
 
 template <typename R>
 void launch_faraday(const Geo& g, const FieldSet<R>& f, const PmlTab<R>& pm, const SolverCoef& c,
@@ -614,7 +480,6 @@ void launch_fill_int(int* p, int n, int v, hipStream_t s)
                                    const SolverCoef&, hipStream_t);                                \
     template void launch_faraday_batch<R>(const FaradayDesc<R>*, const QueueRef&, int, hipStream_t); \
     template void launch_ampere_batch<R>(const AmpereDesc<R>*, const QueueRef&, int, hipStream_t);   \
-    template void launch_filter_batch<R>(const FilterDesc<R>*, const QueueRef&, int, int, hipStream_t); \
     template void launch_window_rows<R>(const Geo&, const PtrList<R>&, int, const EntryRows&,      \
                                         const FieldSet<R>&, const PmlTab<R>&, hipStream_t);        \
     template void launch_stations<R>(const Geo&, const FieldSet<R>&, const StationParams&,         \

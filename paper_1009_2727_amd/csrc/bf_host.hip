@@ -738,13 +738,11 @@ bf_status step_impl(bf_sim* s, int nsteps)
             int4* bo = bb_i(s, 1 - s->bb_cur);
             const double za = ion_shift(s, s->t), zb = ion_shift(s, t1);
             const R fjz = (R)(-1.0 / (c.dx_um * s->dt));
-            if constexpr (sizeof(R) == 4) {
-                if (rb && s->nseg_i > 0) {
-                    rb->ion.push_back(IonDesc<float>{g, f, ion, sg, bi, bo, za, zb, d, fjz});
-                    rb->n_ion.push_back(s->nseg_i);
-                }
-            }
-            if (!rb) launch_ions<R>(g, f, ion, sg, bi, bo, s->nseg_i, za, zb, d, fjz, s->stream);
+            // batched runs launch their ions one run at a time too: the hardware's dispatch of
+            // one workgroup per segment balances the uneven segments better than a persistent
+            // launch over all runs
+            const int nsi = s->nseg_i;
+            s->run([=](hipStream_t st) { launch_ions<R>(g, f, ion, sg, bi, bo, nsi, za, zb, d, fjz, st); });
         }
         s->tock(t_ph, BF_PHASE_IONS);
         // beam through the injection plane (single runs only: a batch rejects beam runs)
@@ -795,25 +793,22 @@ bf_status step_impl(bf_sim* s, int nsteps)
         if (c.filter_kind == BF_FILTER_LEARNED) {
             if constexpr (sizeof(R) == 4) learned_filter(s, f);
         } else if (c.filter_npass > 0) {
-            R* in[3] = {f.J[0], f.J[1], f.J[2]};
-            R* out[3] = {f.Jf[0], f.Jf[1], f.Jf[2]};
-            const int hx[3] = {1, 0, 0}, hz[3] = {0, 0, 1};
-            if constexpr (sizeof(R) == 4) {
-                if (rb) {
-                    for (int q = 0; q < 3; q++) {
-                        rb->filter.push_back(FilterDesc<float>{g, in[q], out[q], hx[q], hz[q], c.filter_npass,
-                                                               c.filter_compensate, filter_tiles_x(g)});
-                        rb->n_filter.push_back(filter_tiles(g));
-                    }
-                    rb->max_halo = std::max(rb->max_halo, c.filter_npass + (c.filter_compensate ? 1 : 0));
-                }
-            }
-            if (!rb) {
-                bf3::FiltSeq fs;
-                bf3::filter_seq(c.filter_npass, c.filter_compensate, c.filter_strides, &fs);
-                R* tmp[3] = {s->arr<R>(A_JT), s->arr<R>(A_JT + 1), s->arr<R>(A_JT + 2)};
-                bf3::launch_filter_xz<R>(g3_of(g, c), in, tmp, out, hx, hz, 3, fs, s->stream);
-            }
+            // the line filter, one run at a time also in a batch (per run it beats the batched
+            // tile filter)
+            bf3::FiltSeq fs;
+            bf3::filter_seq(c.filter_npass, c.filter_compensate, c.filter_strides, &fs);
+            const bf3::G3 g3 = g3_of(g, c);
+            const FieldSet<R> ff = f;
+            R* tmp0 = s->arr<R>(A_JT);
+            R* tmp1 = s->arr<R>(A_JT + 1);
+            R* tmp2 = s->arr<R>(A_JT + 2);
+            s->run([=](hipStream_t st) {
+                R* in[3] = {ff.J[0], ff.J[1], ff.J[2]};
+                R* out[3] = {ff.Jf[0], ff.Jf[1], ff.Jf[2]};
+                R* tmp[3] = {tmp0, tmp1, tmp2};
+                const int hx[3] = {1, 0, 0}, hz[3] = {0, 0, 1};
+                bf3::launch_filter_xz<R>(g3, in, tmp, out, hx, hz, 3, fs, st);
+            });
         }
         s->tock(t_ph, BF_PHASE_FILTER);
         // Ampere + PML (E^{n+1} into the E^{n-1} set)
@@ -2003,9 +1998,7 @@ size_t batch_table_bytes(int n)
     const size_t m = (size_t)n;
     return 256 + al256(m * sizeof(FaradayDesc<float>)) + al256((m + 1) * 4) +
            al256(m * sizeof(AmpereDesc<float>)) + al256((m + 1) * 4) +
-           al256(3 * m * sizeof(FilterDesc<float>)) + al256((3 * m + 1) * 4) +
-           al256(m * sizeof(GpdDesc<float>)) + al256((m + 1) * 4) +
-           al256(m * sizeof(IonDesc<float>)) + al256((m + 1) * 4);
+           al256(m * sizeof(GpdDesc<float>)) + al256((m + 1) * 4);
 }
 
 }  // namespace
@@ -2072,14 +2065,10 @@ bf_status batch_one_step(bf_batch* b)
     size_t o = 256;
     const FaradayDesc<float>* dfar;
     const AmpereDesc<float>* damp;
-    const FilterDesc<float>* dfil;
     const GpdDesc<float>* dgpd;
-    const IonDesc<float>* dion;
     const QueueRef qf = stage_phase(H, Dv, o, rec.faraday, rec.n_faraday, cnt + 0, &dfar);
     const QueueRef qa = stage_phase(H, Dv, o, rec.ampere, rec.n_ampere, cnt + 1, &damp);
-    const QueueRef ql = stage_phase(H, Dv, o, rec.filter, rec.n_filter, cnt + 2, &dfil);
-    const QueueRef qg = stage_phase(H, Dv, o, rec.gpd, rec.n_gpd, cnt + 3, &dgpd);
-    const QueueRef qi = stage_phase(H, Dv, o, rec.ion, rec.n_ion, cnt + 4, &dion);
+    const QueueRef qg = stage_phase(H, Dv, o, rec.gpd, rec.n_gpd, cnt + 2, &dgpd);
     hipStream_t st = b->stream;
     if (hipMemcpyAsync(Dv, H, o, hipMemcpyHostToDevice, st) != hipSuccess) return BF_EDEVICE;
     auto grid = [&](const QueueRef& q, int per_cu) { return std::max(1, std::min(q.total, per_cu * b->cus)); };
@@ -2089,10 +2078,8 @@ bf_status batch_one_step(bf_batch* b)
     closures(SLOT_STATIONS);
     launch_gpd_batch<float>(dgpd, qg, grid(qg, 3), st);
     closures(SLOT_PUSH);
-    launch_ions_batch<float>(dion, qi, grid(qi, 4), st);
     closures(SLOT_IONS);
     closures(SLOT_ANTENNA);
-    launch_filter_batch<float>(dfil, ql, rec.max_halo, grid(ql, 4), st);
     closures(SLOT_FILTER);
     launch_ampere_batch<float>(damp, qa, grid(qa, 8), st);
     closures(SLOT_AMPERE);
@@ -2120,10 +2107,9 @@ bf_status bf_batch_create(bf_sim* const* sims, int n, void* work, int64_t work_b
     if (work_bytes < bf_batch_work_bytes(n)) return BF_EINVAL;
     for (int q = 0; q < n; q++) {
         if (!sims[q] || sims[q]->cfg.real_bytes != 4 || sims[q]->d3) return BF_EUNSUPPORTED;
-        // the batched filter phase runs the stride-1 tile filter, the batched push the
-        // energy-conserving gather and Boris; the beam has no batched phase
-        if (sims[q]->cfg.filter_strides > 1 || sims[q]->cfg.gather_kind || sims[q]->cfg.pusher ||
-            sims[q]->cfg.beam_capacity > 0)
+        // the batched push runs the energy-conserving gather and Boris; the beam has no batched
+        // phase
+        if (sims[q]->cfg.gather_kind || sims[q]->cfg.pusher || sims[q]->cfg.beam_capacity > 0)
             return BF_EUNSUPPORTED;
         if (sims[q]->err != BF_OK) return BF_ESTATE;
         for (int p = 0; p < q; p++)

@@ -144,13 +144,6 @@ struct AmpereDesc {
     int gx;
 };
 template <typename R>
-struct FilterDesc {    // one per run and current component
-    Geo g;
-    const R* in;
-    R* out;
-    int hx, hz, npass, comp, gx;
-};
-template <typename R>
 struct GpdDesc {
     Geo g;
     FieldSet<R> f;
@@ -161,32 +154,13 @@ struct GpdDesc {
     PushParams<R> pp;
     int* status;
 };
-template <typename R>
-struct IonDesc {
-    Geo g;
-    FieldSet<R> f;
-    IonArrays<R> ion;
-    const Segment* seg;
-    const int4* bbin;
-    int4* bbout;
-    double zsh_a, zsh_b;
-    int shift;
-    R fjz;
-};
 
 template <typename R>
 void launch_faraday_batch(const FaradayDesc<R>* d, const QueueRef& q, int nblocks, hipStream_t s);
 template <typename R>
 void launch_ampere_batch(const AmpereDesc<R>* d, const QueueRef& q, int nblocks, hipStream_t s);
 template <typename R>
-void launch_filter_batch(const FilterDesc<R>* d, const QueueRef& q, int max_halo, int nblocks,
-                         hipStream_t s);
-template <typename R>
 void launch_gpd_batch(const GpdDesc<R>* d, const QueueRef& q, int nblocks, hipStream_t s);
-template <typename R>
-void launch_ions_batch(const IonDesc<R>* d, const QueueRef& q, int nblocks, hipStream_t s);
-int filter_tiles(const Geo& g);
-int filter_tiles_x(const Geo& g);
 
 // ---- launchers (stream-ordered) -------------------------------------------------------
 template <typename R>

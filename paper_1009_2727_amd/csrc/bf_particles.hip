@@ -672,20 +672,6 @@ __global__ void __launch_bounds__(NTHR) k_ions(Geo g, FieldSet<R> f, IonArrays<R
     ion_segment<R>(g, f, ion, seg, bbin, bbout, zsh_a, zsh_b, shift, fjz, blockIdx.x);
 }
 
-template <typename R>
-__global__ void __launch_bounds__(NTHR) k_ions_batch(const IonDesc<R>* __restrict__ d, QueueRef q)
-{
-    __shared__ int slot;
-    int r = 0;
-    for (;;) {
-        const int it = next_item(q, &slot);
-        if (it < 0) return;
-        r = run_of(q, it, r);
-        const IonDesc<R>& D = d[r];
-        ion_segment<R>(D.g, D.f, D.ion, D.seg, D.bbin, D.bbout, D.zsh_a, D.zsh_b, D.shift, D.fjz,
-                       it - q.off[r]);
-    }
-}
 
 // ---- antenna (FP64) ------------------------------------------------------------------------
 
@@ -1332,13 +1318,6 @@ void launch_gpd_batch(const GpdDesc<R>* d, const QueueRef& q, int nblocks, hipSt
         hipLaunchKernelGGL((k_gpd_batch<R>), dim3(nblocks), dim3(NTHR), lds, s, d, q);
 }
 
-template <typename R>
-void launch_ions_batch(const IonDesc<R>* d, const QueueRef& q, int nblocks, hipStream_t s)
-{
-    const size_t lds = (size_t)tcells<R>() * sizeof(typename LdsAcc<R>::JT);
-    if (q.total > 0)
-        hipLaunchKernelGGL((k_ions_batch<R>), dim3(nblocks), dim3(NTHR), lds, s, d, q);
-}
 
 template <typename R>
 void launch_antenna(const Geo& g, const FieldSet<R>& f, double* xminus, const AntennaParams& ap,
@@ -1419,7 +1398,6 @@ void launch_sort_ions(const Geo& g, int tile_x, int tile_z, int ntx, int ntiles,
                                  const Segment*, const int4*, int4*, int, double, double, int, R,     \
                                  hipStream_t);                                                        \
     template void launch_gpd_batch<R>(const GpdDesc<R>*, const QueueRef&, int, hipStream_t);          \
-    template void launch_ions_batch<R>(const IonDesc<R>*, const QueueRef&, int, hipStream_t);         \
     template void launch_antenna<R>(const Geo&, const FieldSet<R>&, double*, const AntennaParams&,    \
                                     hipStream_t);                                                     \
     template void launch_beam<R>(const Geo&, const FieldSet<R>&, const BeamArrays&, const BeamParams&, \

@@ -80,3 +80,20 @@ def test_batch_with_learned_filter_and_single_steps_between():
     for w, s1, s2 in zip(ws, single, batched):
         errs = _max_err(s1, s2, w)
         assert max(errs.values()) <= 1e-5, errs
+
+
+@gpu
+def test_batch_with_strided_filter_equals_single_runs():
+    # a batch now runs each run's own line filter, so strided filters batch too
+    from paper_1009_2727_amd import Batch, Sim
+    ws = _workloads()[:2]
+    ws[1]["config"]["filter_strides"] = 0x3      # S(1:2)
+    singles = [Sim.from_workload(w, sort_every=7) for w in ws]
+    batched = [Sim.from_workload(w, sort_every=7) for w in ws]
+    for s in singles:
+        s.step(30)
+    Batch(batched).step(30)
+    for w, s1, s2 in zip(ws, singles, batched):
+        assert s2.sync_status() == 0
+        errs = _max_err(s1, s2, w)
+        assert max(errs.values()) <= 2e-6, errs
