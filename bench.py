@@ -22,7 +22,9 @@ all of them (at most 16).
 
 Other workloads: --workload c2 (the 2D run as the headline), c4 (the batched scan), c5
 (learned vs plain current filter), dtscan (the time-step scan of the high-frequency
-instability), pml (Appendix II's layer test, standard against modified coefficients).
+instability), pml (Appendix II's layer test, standard against modified coefficients), beam
+(a test beam's lab-frame energy history in the scaled 10 GeV stage, lab frame against boosted
+frames).
 """
 from __future__ import annotations
 
@@ -442,6 +444,78 @@ def bench_pml(args):
             "steps": steps, "results": res}
 
 
+def bench_beam_stage(args):
+    """The scaled 10 GeV stage (Sec. 5.2) in several frames with a test beam launched through the
+    plasma entrance plane (Sec. 3.1.1): the beam's mean lab-frame energy against its mean lab
+    position from the per-step history, and each frame's difference from the lab-frame run (the
+    paper's check that the boosted runs recover the lab physics).  The beam (radius 82.5 nm,
+    length 85 nm, gamma_b = --beam-gamma) trails the laser peak by one plasma wavelength."""
+    import numpy as np
+    import pic_inputs as pi
+    from paper_1009_2727_amd import Sim
+    gammas = [float(g) for g in args.beam_gammas.split(",")]
+    gb, L = args.beam_gamma, args.beam_length_um
+    lam_p = 2.0 * math.pi * 2.99792458e14 / (5.64e4 * math.sqrt(1e19))     # um, 1e19 cm^-3
+    out = {"metric": "mean lab beam energy gain vs lab position", "data": "synthetic",
+           "config": {"workload": "scaled 10 GeV stage (1e19 cm^-3, a0 = 1), test beam", "gamma_b": gb,
+                      "length_um": L, "delay_um": lam_p}, "runs": {}}
+    curves = {}
+    for g in gammas:
+        w = pi.scaled_stage(g, real=args.beam_real)
+        cfg = dict(w["config"], beam_capacity=args.beam_particles, beam_history=200000)
+        w = dict(w, config=cfg)
+        sim = Sim.from_workload(w)
+        info = sim.info()
+        bb = math.sqrt(1.0 - 1.0 / (gb * gb))
+        z_ant = w["laser"]["z_antenna_um"]
+        z_inj = w["plasma"]["start_um"]
+        sig_t = w["laser"]["fwhm_fs"] * 0.299792458 / (2.0 * math.sqrt(math.log(2.0)))
+        # the antenna emits E(t'/gamma - 3 sigma_t) at the lab-fixed plane, and t'/gamma there is the
+        # lab time less beta z_ant: the peak crosses the antenna at lab time 3 sigma_t + beta z_ant
+        bt = math.sqrt(1.0 - 1.0 / (g * g))
+        t_peak = 3.0 * sig_t + bt * z_ant
+        t_c = t_peak + (z_inj - z_ant) + lam_p  # the beam centre crosses the plane lam_p behind it
+        parts = pi.beam_lab(args.beam_particles, x_center_um=0.5 * 75 * 0.65, z_center_um=z_inj - bb * t_c,
+                            gamma_b=gb, seed=21, weight=1e-6)
+        sim.add_beam(dict(beta_b=bb, z_inj_um=z_inj, test_only=1), parts)
+        import time
+        t_start = time.time()
+        steps = 0
+        while steps < args.beam_max_steps:
+            sim.step(100)
+            steps += 100
+            h = sim.beam_history()
+            act = h[h[:, 2] > 0]
+            if len(act) and act[-1, 3] / act[-1, 2] > z_inj + L:
+                break
+        import torch
+        torch.cuda.synchronize()
+        secs = time.time() - t_start
+        h = sim.beam_history()
+        act = h[h[:, 1] >= 0.9 * args.beam_particles]
+        z = act[:, 3] / act[:, 2] - z_inj
+        gain = act[:, 5] / act[:, 2] - gb
+        curves[g] = (z, gain)
+        out["runs"][f"{g:g}"] = {"steps": steps, "seconds": secs, "nz": cfg["nz"], "dt": info["dt"],
+                                 "final_z_um": float(z[-1]) if len(z) else None,
+                                 "final_gain": float(gain[-1]) if len(gain) else None,
+                                 "lost": int((sim.beam()["state"] == 2).sum())}
+        sim.close()
+    grid = np.linspace(0.0, L, 11)
+    out["lab_positions_um"] = grid.tolist()
+    for g, (z, gain) in curves.items():
+        out["runs"][f"{g:g}"]["gain_at_positions"] = (np.interp(grid, z, gain, left=np.nan, right=np.nan).tolist()
+                                                     if len(z) > 1 else None)
+    if 1.0 in curves and len(curves[1.0][0]) > 1:
+        ref = np.interp(grid, *curves[1.0], left=np.nan, right=np.nan)
+        scale = np.nanmax(np.abs(ref)) or 1.0
+        for g, (z, gain) in curves.items():
+            if len(z) > 1:
+                v = np.interp(grid, z, gain, left=np.nan, right=np.nan)
+                out["runs"][f"{g:g}"]["max_diff_vs_lab_over_max_gain"] = float(np.nanmax(np.abs(v - ref)) / scale)
+    return out
+
+
 def bench_dt_scan(args):
     """Growth of the high-frequency instability against the time step (Sec. 5.3, "Effects of time
     step"): the boosted instability family (gamma = 13, 1e19 cm^-3 pre-loaded, square cells of
@@ -576,7 +650,13 @@ def main():
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("WORKLOAD", "FETCH_DIR", "WRITE_DIR", "COPY_GIB"))
-    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "dtscan", "pml"], default="c3",
+    ap.add_argument("--beam-gammas", default="1,2,5")
+    ap.add_argument("--beam-gamma", type=float, default=100.0)
+    ap.add_argument("--beam-length-um", type=float, default=500.0)
+    ap.add_argument("--beam-particles", type=int, default=256)
+    ap.add_argument("--beam-max-steps", type=int, default=40000)
+    ap.add_argument("--beam-real", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "dtscan", "pml", "beam"], default="c3",
                     help="c3: the 3D 128x128x1024 boosted run (default, with c2 beside it); c2: the 256x4096 "
                          "boosted run; c4: the batched scan of independent boosted runs (persistent batched "
                          "launch vs one run at a time); c5: learned vs plain current filter; dtscan: "
@@ -621,6 +701,9 @@ def main():
         return
     if args.workload == "pml":
         print(json.dumps(bench_pml(args)), flush=True)
+        return
+    if args.workload == "beam":
+        print(json.dumps(bench_beam_stage(args)), flush=True)
         return
 
     if args.calib_copy_gib > 0:

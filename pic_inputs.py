@@ -329,3 +329,31 @@ def beam_lab(n, *, x_center_um, z_center_um, gamma_b, seed, rb_um=BEAM_RB_UM, lb
         "ux": u * tx / norm, "uy": u * ty / norm, "uz": u / norm,
         "w": np.full(n, weight),
     }
+
+
+def scaled_stage(gamma, real="f32", ppc=1, seed=1018):
+    """The scaled 10 GeV stage of Table "Tablephyspar2d" in the frame gamma: lab density 1e19 cm^-3,
+    flat after a 4 um linear entrance ramp (the table's half-sinus read as linear), laser 0.8 um,
+    a0 = 1, FWHM 10.08 um (33.6 fs; the table's sine profile replaced by the antenna's Gaussian),
+    waist 12.6 um (the table's commented size sigma = 8.91 um as exp(-r^2/2 sigma^2)); 75 cells of
+    0.65 um across and dz = lambda/32 in the lab (so (1 + beta) gamma lambda / 32 here); 1 electron +
+    1 rigid ion per cell; Yee at 0.99 of its Courant limit, 4 passes + compensation, 10-cell PML.
+    The window holds the emitted pulse and one plasma wavelength behind its peak, both stretched by
+    the boost, with 30% to spare, and at least the table's lab-frame 1691 cells; the antenna sits at
+    90% of it so the pulse, emitted while the lab-fixed plane sweeps backwards, stays inside."""
+    d = boosted_cell(gamma)
+    beta = _beta(gamma)
+    t0 = 3.0 * (10.08 / (2.0 * math.sqrt(math.log(2.0))))          # 3 sigma_t of the field envelope, um
+    lam_p = 2.0 * math.pi * 299792458e6 / (5.64e4 * math.sqrt(1e19))  # plasma wavelength at 1e19, um
+    span = beta * gamma * t0 + lam_p * gamma * (1.0 + beta) + 10.0
+    nz = max(1691, int(math.ceil(1.3 * span / d)))
+    z_ant = gamma * 0.9 * nz * d
+    return dict(
+        name=f"scaled 10 GeV stage gamma={gamma:g} 75x{nz}, {ppc} ppc, 1e19 cm^-3, a0=1, Yee",
+        config=make_config(75, nz, 0.65, d, pml_cells=10, periodic_x=1, ck="yee", theta=0.0, cfl_fraction=0.99,
+                           filter_npass=4, filter_compensate=1, gamma_boost=gamma, moving_window=1,
+                           seed=seed, real=real),
+        plasma=plasma(1e19, ppc, ramp_um=4.0, start_um=z_ant + 2.0, ion_mode=1),
+        laser=laser(1.0, 12.6, 10.08 / 0.299792458, z_ant),
+        steps=0,
+    )
