@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <type_traits>
 
 namespace bf3 {
 
@@ -423,6 +424,335 @@ __global__ void __launch_bounds__(NT) k3_fline(G3 g, Lines3<TI, TO> L, FiltSeq f
         if (j >= S) break;
         const long o = at(j);
         out[o] = (per || j <= hi) ? (TO)src[idx(a + R)] : (TO)in[o];
+    }
+}
+
+// ---- current filter: the three axes in one launch ---------------------------------------------
+// For a sequence of unit-stride passes the whole sequence along one axis is one symmetric stencil
+// of 2 reach + 1 taps (the product of the passes), c[m] weighting the values m cells to either
+// side.  Holding the positions just outside a component's range at zero after every pass is the
+// same as applying that stencil to the line continued oddly about those two positions (-1 and
+// hi + 1): a symmetric pass keeps an odd continuation odd, so the two pivots stay at zero and
+// nothing else outside is ever read.  The edges therefore need no coefficients of their own.
+// The filter is separable, so the three axes commute and are applied x, y, z as the line passes
+// do.  A workgroup owns an FT_TX x FT_TY tile of (x, y) columns of one component and a run of
+// z planes.  For each plane it stages the tile with its x and y reach in LDS (the odd
+// continuation is built by the loads), filters along x, then along y, and keeps its columns'
+// last 2 reach + 1 filtered planes in registers for the z stencil; the continuation along z is
+// made from the planes already in that ring.  A component's cells beyond its range (the last
+// half node of its own axis when that axis is not periodic) are copied along that axis: the x
+// copy column and the y copy row are staged beside the tile, the z copy plane is written as it
+// is filtered.  Consecutive work items (neighbouring y tiles at the same z run) go to the same
+// XCD so that the reach they share is read once from its L2.
+constexpr int FT_TX = 32, FT_TY = 32, FT_QY = 4, FT_NT = 256, FT_RMAX = 6;
+static_assert(FT_TX * FT_TY == FT_NT * FT_QY, "one thread per x column and FT_QY rows");
+
+struct FiltStencil {
+    double c[FT_RMAX + 1];
+};
+
+template <typename T> struct Vec16;
+template <> struct Vec16<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static constexpr int n = 4;
+};
+template <> struct Vec16<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+    static constexpr int n = 2;
+};
+
+// stored index of position p on an axis of S stored cells whose component range is [0, hi],
+// under the odd continuation about -1 and hi + 1 (periodic axes wrap); sg = 0 at the pivots and
+// where the continuation would leave the range (no output within the reach reads those)
+__device__ __forceinline__ int odd_pos(int p, int S, int hi, int per, int& sg)
+{
+    if (per) {
+        sg = 1;
+        int j = p % S;
+        return j < 0 ? j + S : j;
+    }
+    if (p >= 0 && p <= hi) {
+        sg = 1;
+        return p;
+    }
+    const int q = p < 0 ? -2 - p : 2 * (hi + 1) - p;
+    sg = (p == -1 || p == hi + 1 || q < 0 || q > hi) ? 0 : -1;
+    return sg ? q : 0;
+}
+
+// calls f(std::integral_constant<int, K>) for the K == k among 0 <= K < N (k uniform: the
+// choice is a scalar branch and every K is a compile-time constant in its body)
+template <int K, int N, typename F>
+__device__ __forceinline__ void static_switch(int k, F&& f)
+{
+    if constexpr (K < N) {
+        if (k == K) f(std::integral_constant<int, K>{});
+        else static_switch<K + 1, N>(k, f);
+    }
+}
+
+template <int RC, typename T>
+struct FtGeom {
+    static constexpr int VW = Vec16<T>::n;
+    static constexpr int RW = FT_TY + 2 * RC;                     // staged rows (+1 copy row)
+    static constexpr int NRD = (2 * RC + 4 + VW - 1) / VW;        // vector reads per x item
+    static constexpr int W0 = FT_TX + 2 * RC > FT_TX - 4 + NRD * VW ? FT_TX + 2 * RC : FT_TX - 4 + NRD * VW;
+    static constexpr int LA = (W0 + VW - 1) / VW * VW;            // staged columns = row pitch
+    static constexpr int NMAIN = (RW + 1) * LA;                   // tile + copy row
+    static constexpr int CXB = NMAIN;                             // copy column after them
+    static constexpr int NLOAD = NMAIN + RW;
+    static constexpr int NSLOT = (NLOAD + FT_NT - 1) / FT_NT;
+    static constexpr int DUMMY = NLOAD;                           // sink of unused slots
+    static constexpr int NA = DUMMY + 1;
+    static constexpr int NB = (RW + 1) * FT_TX;
+};
+
+template <int RC, typename T, typename TO>
+__global__ void __launch_bounds__(FT_NT) k3_filt3(G3 g, Lines3<double, TO> L, FiltStencil st, int seg, int nzs,
+                                                  int nwork, int nxt, int nyt)
+{
+    using Gm = FtGeom<RC, T>;
+    using V = typename Vec16<T>::type;
+    __shared__ __attribute__((aligned(16))) T sA[Gm::NA];
+    __shared__ __attribute__((aligned(16))) T sB[Gm::NB];
+    // work item w: y tile fastest, then x tile, z run, component; the grid is a multiple of 8
+    // and blocks are dealt to the XCDs in turn, so block b works on item (b % 8) n8 + b / 8
+    const int n8 = (int)gridDim.x / 8;
+    int w = ((int)blockIdx.x % 8) * n8 + (int)blockIdx.x / 8;
+    if (w >= nwork) return;
+    const int yt = w % nyt;
+    w /= nyt;
+    const int xt = w % nxt;
+    w /= nxt;
+    const int zs = w % nzs;
+    const int comp = w / nzs;
+    const double* __restrict__ in = L.in[comp];
+    TO* __restrict__ out = L.out[comp];
+    const int S0 = g.S[0], S1 = g.S[1], S2 = g.S[2];
+    const int hx = g.per[0] ? S0 - 1 : S0 - 1 - (comp == 0);
+    const int hy = g.per[1] ? S1 - 1 : S1 - 1 - (comp == 1);
+    const int hz = g.per[2] ? S2 - 1 : S2 - 1 - (comp == 2);
+    const int x0 = xt * FT_TX, y0 = yt * FT_TY;
+    const bool xcopy = comp == 0 && !g.per[0] && hx + 1 >= x0 && hx + 1 < x0 + FT_TX;
+    const bool ycopy = comp == 1 && !g.per[1] && hy + 1 >= y0 && hy + 1 < y0 + FT_TY;
+    const int k0 = zs * seg, k1 = min(S2, k0 + seg);
+    T c[RC + 1];
+#pragma unroll
+    for (int m = 0; m <= RC; m++) c[m] = (T)st.c[m];
+
+    // load slots: in-plane offset and sign of the continuation, fixed for the run; slot i lands
+    // at LDS index i (rows of LA staged columns, the copy row, the copy column), unused ones in
+    // the sink
+    unsigned soff[Gm::NSLOT];
+    T ssg[Gm::NSLOT];
+#pragma unroll
+    for (int m = 0; m < Gm::NSLOT; m++) {
+        const int i = (int)threadIdx.x + m * FT_NT;
+        int sx = 0, sy = 0, ix = 0, iy = 0;
+        if (i < Gm::NMAIN) {
+            const int r = i / Gm::LA, cc = i % Gm::LA;
+            ix = odd_pos(x0 - RC + cc, S0, hx, g.per[0], sx);
+            if (r < Gm::RW) iy = odd_pos(y0 - RC + r, S1, hy, g.per[1], sy);
+            else if (ycopy) {
+                iy = hy + 1;
+                sy = 1;
+            }
+        } else if (i < Gm::NLOAD) {
+            const int r = i - Gm::NMAIN;
+            if (xcopy) {
+                ix = hx + 1;
+                sx = 1;
+                iy = odd_pos(y0 - RC + r, S1, hy, g.per[1], sy);
+            }
+        }
+        soff[m] = (unsigned)(iy * (int)g.pitch + ix);
+        ssg[m] = (T)(sx * sy);
+    }
+    double pre[Gm::NSLOT];
+    auto fetch = [&](int p) {           // logical plane p, 0 <= p < S2 unless z is periodic
+        int kk = p % S2;
+        if (kk < 0) kk += S2;
+        kk += g.zoff;
+        if (kk >= S2) kk -= S2;
+        const double* src = in + (long)kk * g.plane;
+#pragma unroll
+        for (int m = 0; m < Gm::NSLOT; m++)
+            if (ssg[m] != T(0)) pre[m] = src[soff[m]];
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int m = 0; m < Gm::NSLOT; m++) {
+            const int i = (int)threadIdx.x + m * FT_NT;
+            sA[(m + 1) * FT_NT <= Gm::NLOAD || i < Gm::NLOAD ? i : Gm::DUMMY] =
+                ssg[m] != T(0) ? ssg[m] * (T)pre[m] : T(0);
+        }
+    };
+    // x stencil on every staged row (the copy row only when it is staged) into sB
+    auto xfilter = [&]() {
+        constexpr int NQ = FT_TX / 4;
+        const int nrow = ycopy ? Gm::RW + 1 : Gm::RW;
+        for (int it = (int)threadIdx.x; it < nrow * NQ; it += FT_NT) {
+            const int r = it / NQ, xq = it % NQ;
+            T a[Gm::NRD * Gm::VW];
+            const T* row = sA + r * Gm::LA + 4 * xq;
+#pragma unroll
+            for (int v = 0; v < Gm::NRD; v++) {
+                const V t = *reinterpret_cast<const V*>(row + v * Gm::VW);
+#pragma unroll
+                for (int e = 0; e < Gm::VW; e++) a[v * Gm::VW + e] = t[e];
+            }
+            T o[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                T s = c[0] * a[q + RC];
+#pragma unroll
+                for (int m = 1; m <= RC; m++) s += c[m] * (a[q + RC - m] + a[q + RC + m]);
+                o[q] = s;
+            }
+            if (xcopy) {
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+                    if (x0 + 4 * xq + q == hx + 1) o[q] = r < Gm::RW ? sA[Gm::CXB + r] : T(0);
+            }
+            T* dst = sB + r * FT_TX + 4 * xq;
+#pragma unroll
+            for (int v = 0; v < 4 / Gm::VW; v++) {
+                V t;
+#pragma unroll
+                for (int e = 0; e < Gm::VW; e++) t[e] = o[v * Gm::VW + e];
+                *reinterpret_cast<V*>(dst + v * Gm::VW) = t;
+            }
+        }
+    };
+    // y stencil for this thread's column x0 + tx, rows y0 + FT_QY ty + q
+    const int tx = (int)threadIdx.x % FT_TX, ty = (int)threadIdx.x / FT_TX;
+    auto yfilter = [&](T v[FT_QY]) {
+        T b[FT_QY + 2 * RC];
+#pragma unroll
+        for (int i = 0; i < FT_QY + 2 * RC; i++) b[i] = sB[(FT_QY * ty + i) * FT_TX + tx];
+#pragma unroll
+        for (int q = 0; q < FT_QY; q++) {
+            T s = c[0] * b[q + RC];
+#pragma unroll
+            for (int m = 1; m <= RC; m++) s += c[m] * (b[q + RC - m] + b[q + RC + m]);
+            v[q] = s;
+        }
+        if (ycopy) {
+#pragma unroll
+            for (int q = 0; q < FT_QY; q++)
+                if (y0 + FT_QY * ty + q == hy + 1) v[q] = sB[Gm::RW * FT_TX + tx];
+        }
+    };
+    // one plane through x and y; prefetches plane pn when pn is not -1 << 30
+    constexpr int NOPLANE = -(1 << 30);
+    auto plane = [&](T v[FT_QY], int pn) {
+        stage();
+        __syncthreads();
+        if (pn != NOPLANE) fetch(pn);
+        xfilter();
+        __syncthreads();
+        yfilter(v);
+    };
+    // the z ring: plane p sits in slot (p - p0) mod NR, p0 the run's first plane, so that a plane
+    // is written once and never moved; the slot is uniform and selected by a scalar branch
+    constexpr int NR = 2 * RC + 1;
+    T rg[FT_QY][NR];
+#pragma unroll
+    for (int q = 0; q < FT_QY; q++)
+#pragma unroll
+        for (int i = 0; i < NR; i++) rg[q][i] = T(0);
+    const int xg = x0 + tx;
+    unsigned coff[FT_QY];               // in-plane offsets of this thread's columns
+#pragma unroll
+    for (int q = 0; q < FT_QY; q++) coff[q] = (unsigned)((y0 + FT_QY * ty + q) * (int)g.pitch + xg);
+    auto store_out = [&](int j, int q, T v) {
+        const int yg = y0 + FT_QY * ty + q;
+        if (xg >= S0 || yg >= S1) return;
+        int kk = j + g.zoff;
+        if (kk >= S2) kk -= S2;
+        (out + (long)kk * g.plane)[coff[q]] = (TO)v;
+    };
+    // plane j from the ring, its centre in slot C
+    auto emit_at = [&](auto cc, int j) {
+        constexpr int C = decltype(cc)::value;
+        if (j < k0 || j >= k1 || j > hz) return;
+#pragma unroll
+        for (int q = 0; q < FT_QY; q++) {
+            T s = c[0] * rg[q][C];
+#pragma unroll
+            for (int m = 1; m <= RC; m++) s += c[m] * (rg[q][(C + NR - m) % NR] + rg[q][(C + m) % NR]);
+            store_out(j, q, s);
+        }
+    };
+    const bool per = g.per[2] != 0;
+    const bool first = !per && k0 == 0;
+    const int p0 = first ? 0 : k0 - RC;
+    const int plast = per ? k1 - 1 + RC : min(k1 - 1 + RC, hz);
+    T v[FT_QY];
+    int p = p0, slot = 0;
+    fetch(p);
+    for (; p <= plast; p++) {
+        plane(v, p < plast ? p + 1 : NOPLANE);
+        static_switch<0, NR>(slot, [&](auto kc) {
+            constexpr int K = decltype(kc)::value;
+#pragma unroll
+            for (int q = 0; q < FT_QY; q++) rg[q][K] = v[q];
+            if (K == RC && first && p == RC) {
+                // planes -1 .. -RC (slots NR - 1 .. NR - RC, not yet used): the pivot and the odd
+                // continuation of planes 0 .. RC - 2 (slots 0 .. RC - 2)
+#pragma unroll
+                for (int q = 0; q < FT_QY; q++) {
+                    rg[q][NR - 1] = T(0);
+#pragma unroll
+                    for (int i = 1; i < RC; i++) rg[q][(NR - 1 - i) % NR] = -rg[q][(i - 1 + NR) % NR];
+                }
+            }
+            emit_at(std::integral_constant<int, (K + NR - RC) % NR>{}, p - RC);
+        });
+        slot = slot + 1 == NR ? 0 : slot + 1;
+    }
+    if (!per && k1 - 1 + RC > hz) {
+        // the far end: put the ring in shift-register order (rg[q][NR - 1] the newest plane,
+        // hz), then push the pivot plane hz + 1 and the continuation hz + 1 + m = -(hz + 1 - m)
+        static_switch<0, NR>(slot, [&](auto kc) {
+            constexpr int K = decltype(kc)::value;      // the oldest plane's slot
+            T t[FT_QY][NR];
+#pragma unroll
+            for (int q = 0; q < FT_QY; q++)
+#pragma unroll
+                for (int i = 0; i < NR; i++) t[q][i] = rg[q][(K + i) % NR];
+#pragma unroll
+            for (int q = 0; q < FT_QY; q++)
+#pragma unroll
+                for (int i = 0; i < NR; i++) rg[q][i] = t[q][i];
+        });
+        auto push = [&](const T w[FT_QY]) {
+#pragma unroll
+            for (int q = 0; q < FT_QY; q++) {
+#pragma unroll
+                for (int i = 0; i < NR - 1; i++) rg[q][i] = rg[q][i + 1];
+                rg[q][NR - 1] = w[q];
+            }
+        };
+        if (comp == 2) {                // the copy plane of the z component
+            fetch(hz + 1);
+            plane(v, NOPLANE);
+            if (hz + 1 >= k0 && hz + 1 < k1) {
+#pragma unroll
+                for (int q = 0; q < FT_QY; q++) store_out(hz + 1, q, v[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < FT_QY; q++) v[q] = T(0);
+        push(v);
+        emit_at(std::integral_constant<int, RC>{}, hz + 1 - RC);
+#pragma unroll
+        for (int m = 1; m < RC; m++) {
+#pragma unroll
+            for (int q = 0; q < FT_QY; q++) v[q] = -rg[q][NR - 2 * m];
+            push(v);
+            emit_at(std::integral_constant<int, RC>{}, hz + 1 + m - RC);
+        }
     }
 }
 
@@ -1841,6 +2171,74 @@ void fline(const G3& g, const Lines3<TI, TO>& L, int ncomp, const FiltSeq& fs, h
                        ncolb);
 }
 
+// the stencil of a sequence of unit-stride passes (the product of its 3-point stencils); false
+// for strided passes and for reaches beyond FT_RMAX
+static bool unit_stencil(const FiltSeq& fs, FiltStencil& st)
+{
+    const int R = fs.reach;
+    if (fs.n < 1 || R < 1 || R > FT_RMAX) return false;
+    for (int p = 0; p < fs.n; p++)
+        if (fs.stride[p] != 1) return false;
+    double a[2 * FT_RMAX + 1] = {}, b[2 * FT_RMAX + 1];
+    const int L = 2 * R + 1;
+    a[R] = 1.0;
+    for (int p = 0; p < fs.n; p++) {
+        const double al = fs.alpha[p], be = 0.5 * (1.0 - al);
+        for (int j = 0; j < L; j++) b[j] = al * a[j] + be * ((j > 0 ? a[j - 1] : 0.0) + (j + 1 < L ? a[j + 1] : 0.0));
+        for (int j = 0; j < L; j++) a[j] = b[j];
+    }
+    for (int m = 0; m <= FT_RMAX; m++) st.c[m] = m <= R ? a[R + m] : 0.0;
+    return true;
+}
+
+// the three-axis filter of J into Jf in one launch; false where it does not apply (an axis
+// shorter than the stencil's continuation needs), leaving the line passes to do it
+template <int RC, typename R>
+bool filt3(const G3& g, const F3<R>& f, const FiltStencil& st, hipStream_t s)
+{
+    for (int a = 0; a < 3; a++)
+        if (!g.per[a] && g.S[a] < 2 * RC + 3) return false;
+    static int slots = 0;          // workgroups resident on the device at once
+    if (!slots) {
+        int dev = 0, cus = 0, occ = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k3_filt3<RC, R, R>, FT_NT, 0) !=
+                hipSuccess || occ < 1)
+            occ = 1;
+        slots = occ * cus;
+    }
+    const int nxt = (g.S[0] + FT_TX - 1) / FT_TX, nyt = (g.S[1] + FT_TY - 1) / FT_TY;
+    const long base = 3L * nxt * nyt;
+    // z runs: the count for which (rounds of resident workgroups) x (run length + its reach) is
+    // least; a run of a non-periodic axis after the first starts at least 2 reach + 2 planes in
+    const int S2 = g.S[2];
+    int seg = S2;
+    double best = 1e300;
+    for (int n = 1; n <= 512; n++) {
+        const int sg = (S2 + n - 1) / n;
+        if (n > 1 && sg < 2 * RC + 2) break;
+        const int nz = (S2 + sg - 1) / sg;
+        const double t = (double)((base * nz + slots - 1) / slots) * (sg + 2 * RC);
+        if (t < best * (1.0 - 1e-9)) {
+            best = t;
+            seg = sg;
+        }
+    }
+    const int nzs = (S2 + seg - 1) / seg;
+    const long nwork = base * nzs;
+    const long blocks = (nwork + 7) / 8 * 8;
+    Lines3<double, R> L{};
+    for (int c = 0; c < 3; c++) {
+        L.in[c] = f.J[c];
+        L.out[c] = f.Jf[c];
+    }
+    hipLaunchKernelGGL((k3_filt3<RC, R, R>), dim3((unsigned)blocks), dim3(FT_NT), 0, s, g, L, st, seg, nzs,
+                       (int)nwork, nxt, nyt);
+    return true;
+}
+
 template <typename R>
 void launch3_filter(const G3& g, const F3<R>& f, const FiltSeq& fs, const R* out[3], hipStream_t s)
 {
@@ -1857,6 +2255,22 @@ void launch3_filter(const G3& g, const F3<R>& f, const FiltSeq& fs, const R* out
         ly.h[c] = c == 1;
         lz.h[c] = c == 2;
         out[c] = f.Jf[c];
+    }
+    if (fs.n) {
+        FiltStencil st;
+        if (unit_stencil(fs, st)) {
+            bool done = false;
+            switch (fs.reach) {
+            case 1: done = filt3<1>(g, f, st, s); break;
+            case 2: done = filt3<2>(g, f, st, s); break;
+            case 3: done = filt3<3>(g, f, st, s); break;
+            case 4: done = filt3<4>(g, f, st, s); break;
+            case 5: done = filt3<5>(g, f, st, s); break;
+            case 6: done = filt3<6>(g, f, st, s); break;
+            default: break;
+            }
+            if (done) return;
+        }
     }
     fline<0, double, R, R>(g, lx, 3, fs, s);     // without passes: the copy into the run's type
     if (fs.n == 0) return;
