@@ -257,10 +257,26 @@ def learned_filter_leg(args, w, plain_filter_ms):
     c1 = sim.counts()
     tm = sim.timers(reset=True)
     ne = 0.5 * (c0[0] + c1[0])
+    # the network's arithmetic: 5x5 taps, 1 -> 16 -> 16 -> 1 channels, 2 FLOP per multiply-add,
+    # over each current component's stored range (the last half node of its own axis excluded on
+    # a non-periodic axis); the MFMAs do twice this (hi and lo BF16 parts of every activation)
+    info = sim.info()
+    sx, sz = info["stored_x"], info["stored_z"]
+    px, pz = cfg.get("periodic_x", 0), cfg.get("periodic_z", 0)
+    cells = (sx - (0 if px else 1)) * sz + sx * sz + sx * (sz - (0 if pz else 1))
+    flop_cell = 2 * 25 * (1 * 16 + 16 * 16 + 16 * 1)
+    fms = tm["filter"][0] / args.steps
+    achieved = cells * flop_cell / (fms * 1e-3) / 1e12
     return {"value": ne * args.steps / (ms / 1e3), "unit": "electron pushes/s",
-            "ms_per_step": ms / args.steps, "filter_ms_per_step": tm["filter"][0] / args.steps,
+            "ms_per_step": ms / args.steps, "filter_ms_per_step": fms,
             "plain_filter_ms_per_step": plain_filter_ms, "status": sim.sync_status(),
-            "weights": "exact factorisation of the 4-pass + compensation filter"}
+            "weights": "exact factorisation of the 4-pass + compensation filter",
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
+                         "frac": achieved / 2500.0, "frac_with_hi_lo": 2.0 * achieved / 2500.0,
+                         "flop_per_cell": flop_cell, "cells": cells,
+                         "note": "network FLOPs (14,400 per cell and component) over the filter phase "
+                                 "time; the BF16 MFMAs execute twice that for the hi and lo parts of "
+                                 "every activation (frac_with_hi_lo)"}}
 
 
 def bench_scan(args):

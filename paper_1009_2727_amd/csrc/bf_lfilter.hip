@@ -253,14 +253,18 @@ __global__ void k_lf_zero(float* p, int n)
 //    columns by one lane (DPP row_shr) before each row moves every partial to its next dy, and
 //    column 4 leaves complete;
 //  * layer 1 (1 -> 16) gathers its 25 taps x {hi, lo} from the input ring (two MFMAs).
+// Layers 1 and 2 take the weights as the MFMA's A operand and the pixels as B, so that a lane
+// ends with four consecutive channels of one pixel: their hi and lo BF16 parts are converted in
+// hardware and stored as two 8-byte words.  The input ring keeps every row twice (rows r and
+// r + SIR of a 2 SIR-row buffer), so the five rows a layer-1 tap set reads are contiguous.
 // Out-of-domain h1 and h2 pixels on non-periodic axes are written as zeros, as the separate
-// layers read them.  Four waves: wave w computes h1 strip w (wave 0 also strip 4), h2 strip w
-// and output strip w, strips of 16 columns.
-constexpr int SOW = 60;              // output columns per workgroup: [x0, x0 + 60)
-constexpr int SNS = 5;               // h1 strips: [x0 - 4, x0 + 76)
-constexpr int SH1W = 16 * SNS;       // 80 h1 columns
-constexpr int SH2W = 68;             // h2 columns read by layer 3: [x0 - 2, x0 + 66); 64 computed
-constexpr int SIW = SH1W + 4;        // input columns: [x0 - 6, x0 + 78)
+// layers read them.  Four waves: wave w computes h1 strip w, h2 strip w and output strip w,
+// strips of 16 columns; the last four columns of h1 and h2 are zero padding that only feeds
+// columns beyond the workgroup's outputs.
+constexpr int SOW = 56;              // output columns per workgroup: [x0, x0 + 56)
+constexpr int SH1W = 68;             // h1 columns [x0 - 4, x0 + 64): 64 computed, 4 of padding
+constexpr int SH2W = 68;             // h2 columns [x0 - 2, x0 + 66): 64 computed, 4 of padding
+constexpr int SIW = 68;              // input columns: [x0 - 6, x0 + 62)
 constexpr int SIR = 8;               // input ring rows
 
 // one image plane per blockIdx.z % n (up to 3: the current components), images blockIdx.z / n
@@ -270,11 +274,35 @@ struct Planes {
     int n, oh;                      // planes, output rows per workgroup
 };
 
-__device__ __forceinline__ void split_store(unsigned short* dst, int drow, int px, int py, int ch, float v)
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// hi and lo BF16 parts (round to nearest even, in hardware) of four consecutive channels of one
+// pixel, stored as two 8-byte words: hi at channel offset 4g, lo at 16 + 4g
+__device__ __forceinline__ unsigned pk_bf16(float a, float b)
 {
-    const unsigned short hi = bf16_rne(v);
-    dst[py * drow + px * 32 + ch] = hi;
-    dst[py * drow + px * 32 + 16 + ch] = bf16_rne(v - bf16_val(hi));
+    const bf16x2 p = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(unsigned, p);
+}
+
+// A row of h1 or h2 in LDS is four planes of W pixels x 8 BF16 words: the 32 words of a pixel
+// (hi parts of channels 0-7, 8-15, then lo parts of 0-7, 8-15) split into 16-byte chunks by k, so
+// the 16 lanes that read one k chunk of a fragment (consecutive pixels) touch 256 consecutive
+// bytes.  Channels 4g .. 4g + 3 of pixel c go to chunk g / 2 (hi) and 2 + g / 2 (lo), half g % 2.
+__device__ __forceinline__ void store_ch4(unsigned short* row, int W, int c, int g, f32x4 v)
+{
+    const unsigned h01 = pk_bf16(v[0], v[1]), h23 = pk_bf16(v[2], v[3]);
+    const unsigned l01 = pk_bf16(v[0] - __uint_as_float(h01 << 16), v[1] - __uint_as_float(h01 & 0xffff0000u));
+    const unsigned l23 = pk_bf16(v[2] - __uint_as_float(h23 << 16), v[3] - __uint_as_float(h23 & 0xffff0000u));
+    unsigned short* p = row + ((g >> 1) * W + c) * 8 + 4 * (g & 1);
+    *reinterpret_cast<uint2*>(p) = make_uint2(h01, h23);
+    *reinterpret_cast<uint2*>(p + 2 * W * 8) = make_uint2(l01, l23);
+}
+
+// hi | lo << 16 of one value
+__device__ __forceinline__ unsigned hilo(float v)
+{
+    const unsigned h = pk_bf16(v, 0.f) & 0xffffu;
+    return h | (pk_bf16(v - __uint_as_float(h << 16), 0.f) << 16);
 }
 
 __device__ __forceinline__ f32x4 shift_columns(f32x4 t)
@@ -290,8 +318,8 @@ __device__ __forceinline__ f32x4 shift_columns(f32x4 t)
 __global__ void __launch_bounds__(256) k_lf_stream(Planes P, const us8* __restrict__ w1, const us8* __restrict__ w2,
                                                    const us8* __restrict__ w3)
 {
-    __shared__ unsigned sin[SIR * SIW];                                   // hi | lo << 16
-    __shared__ __attribute__((aligned(16))) unsigned short sh1[2 * SH1W * 32];   // [row][col][hi 16 | lo 16]
+    __shared__ unsigned sin[2 * SIR * SIW];                               // hi | lo << 16
+    __shared__ __attribute__((aligned(16))) unsigned short sh1[2 * SH1W * 32];   // [row][k chunk][col][8]
     __shared__ __attribute__((aligned(16))) unsigned short sh2[2 * SH2W * 32];
     const int pl = blockIdx.z % P.n, img = blockIdx.z / P.n;
     const View in = P.in[pl], out = P.out[pl];
@@ -319,13 +347,36 @@ __global__ void __launch_bounds__(256) k_lf_stream(Planes P, const us8* __restri
     };
     auto put_in = [&](int r, float v) {
         if (threadIdx.x < SIW) {
-            const unsigned short hi = bf16_rne(v);
-            sin[(r & (SIR - 1)) * SIW + threadIdx.x] = (unsigned)hi | ((unsigned)bf16_rne(v - bf16_val(hi)) << 16);
+            const unsigned h = hilo(v);
+            sin[(r & (SIR - 1)) * SIW + threadIdx.x] = h;
+            sin[((r & (SIR - 1)) + SIR) * SIW + threadIdx.x] = h;
         }
     };
+    // layer 1's taps t = 16 q + 4 g + jj of this lane: offset from the first of its five input
+    // rows, and whether the tap exists (t < 25; the weights of the padding are zero)
+    int toff[2][4];
+    bool tok[2][4];
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+#pragma unroll
+        for (int jj = 0; jj < 4; jj++) {
+            const int t = 16 * q + 4 * g + jj;
+            tok[q][jj] = t < TAPS;
+            toff[q][jj] = t < TAPS ? (t / 5) * SIW + t % 5 + i : 0;
+        }
+    // this lane's h1 and h2 columns lie in the domain (or x is periodic)
+    const int xh1 = x0 - 4 + 16 * wave + i, xh2 = x0 - 2 + 16 * wave + i;
+    const bool ok1 = d.perx || (xh1 >= 0 && xh1 < d.nx), ok2 = d.perx || (xh2 >= 0 && xh2 < d.nx);
     const int s0 = y0 - 5;
     for (int r = s0 - 1; r <= s0 + 3; r++) put_in(r, load_in(r));
-    float next = load_in(s0 + 4);
+    // input rows in flight ten rows ahead: at row s = s5 + u, q0[u] holds row s + 4 (staged at
+    // the end of the row) and q1[u] row s + 9
+    float q0[5], q1[5];
+#pragma unroll
+    for (int u = 0; u < 5; u++) {
+        q0[u] = load_in(s0 + 4 + u);
+        q1[u] = load_in(s0 + 9 + u);
+    }
     __syncthreads();
 
     f32x4 acc[5], T = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -336,64 +387,65 @@ __global__ void __launch_bounds__(256) k_lf_stream(Planes P, const us8* __restri
 #pragma unroll
         for (int u = 0; u < 5; u++) {
             const int s = s5 + u;
+            // every LDS read of the row first: all of it was written before the last barrier,
+            // and the row's writes go to ring slots the row does not read (h1 row s + 1, h2 row
+            // s - 2, input row s + 4)
+            const unsigned* rows = sin + ((s - 1) & (SIR - 1)) * SIW + 16 * wave;
+            unsigned A1[2][4];
+#pragma unroll
+            for (int q = 0; q < 2; q++)
+#pragma unroll
+                for (int jj = 0; jj < 4; jj++) A1[q][jj] = rows[toff[q][jj]];
+            const unsigned short* src2 = sh1 + (s & 1) * SH1W * 32 + (g * SH1W + 16 * wave + i) * 8;
+            const unsigned short* src3 = sh2 + ((s - 3) & 1) * SH2W * 32 + (g * SH2W + 16 * wave + i) * 8;
+            us8 A2[5], A3[5];
+#pragma unroll
+            for (int dx = 0; dx < 5; dx++) {
+                A2[dx] = *reinterpret_cast<const us8*>(src2 + dx * 8);
+                A3[dx] = *reinterpret_cast<const us8*>(src3 + dx * 8);
+            }
             // layer 1: h1 row s + 1 from input rows s - 1 .. s + 3
+            f32x4 a = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+#pragma unroll
+                for (int jj = 0; jj < 4; jj++) A1[q][jj] = q == 0 || tok[q][jj] ? A1[q][jj] : 0u;   // taps 0 .. 15 exist
+                a = mfma(b1[q], __builtin_bit_cast(us8, A1[q]), a);
+            }
+            // layer 2: h1 row s into the h2 rows s - 2 .. s + 2; row s - 2 (tap row dy = 4)
+            // first, so that its conversion and store overlap the other 20 MFMAs
+#pragma unroll
+            for (int dx = 0; dx < 5; dx++) acc[(u + 3) % 5] = mfma(b2[20 + dx], A2[dx], acc[(u + 3) % 5]);
             {
                 unsigned short* h1 = sh1 + ((s + 1) & 1) * SH1W * 32;
                 const int yr = s + 1;
-                const bool rowok = d.pery || (yr >= 0 && yr < d.ny);
-                for (int st = wave; st < SNS; st += 4) {
-                    f32x4 a = f32x4{0.f, 0.f, 0.f, 0.f};
+                const bool ok = (d.pery || (yr >= 0 && yr < d.ny)) && ok1;
 #pragma unroll
-                    for (int q = 0; q < 2; q++) {
-                        us8 A;
-#pragma unroll
-                        for (int jj = 0; jj < 4; jj++) {
-                            const int t = 16 * q + 4 * g + jj;
-                            unsigned v = 0u;
-                            if (t < TAPS) v = sin[((yr + t / 5 - 2) & (SIR - 1)) * SIW + 16 * st + i + t % 5];
-                            A[2 * jj] = (unsigned short)(v & 0xffffu);
-                            A[2 * jj + 1] = (unsigned short)(v >> 16);
-                        }
-                        a = mfma(A, b1[q], a);
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        const int c = 16 * st + 4 * g + r, x = x0 - 4 + c;
-                        const bool ok = rowok && (d.perx || (x >= 0 && x < d.nx));
-                        split_store(h1, 0, c, 0, i, ok ? a[r] : 0.f);
-                    }
-                }
+                for (int r = 0; r < 4; r++) a[r] = ok ? a[r] : 0.f;
+                store_ch4(h1, SH1W, 16 * wave + i, g, a);
             }
-            // layer 2: h1 row s into the h2 rows s - 2 .. s + 2; row s - 2 completes
-            {
-                const unsigned short* src = sh1 + (s & 1) * SH1W * 32 + (16 * wave + i) * 32 + 8 * g;
 #pragma unroll
-                for (int dx = 0; dx < 5; dx++) {
-                    const us8 A = *reinterpret_cast<const us8*>(src + dx * 32);
+            for (int dx = 0; dx < 5; dx++)
 #pragma unroll
-                    for (int dy = 0; dy < 5; dy++) {
-                        const int k = (u + 7 - dy) % 5;
-                        acc[k] = mfma(A, b2[5 * dy + dx], acc[k]);
-                    }
+                for (int dy = 0; dy < 4; dy++) {
+                    const int k = (u + 7 - dy) % 5;
+                    acc[k] = mfma(b2[5 * dy + dx], A2[dx], acc[k]);
                 }
+            // layer 3: h2 row s - 3; output row s - 5 completes in column 4
+            T = shift_columns(T);
+#pragma unroll
+            for (int dx = 0; dx < 5; dx++) T = mfma(A3[dx], b3[dx], T);
+            {
                 f32x4& c2 = acc[(u + 3) % 5];
                 unsigned short* h2 = sh2 + ((s - 2) & 1) * SH2W * 32;
                 const int yr = s - 2;
-                const bool rowok = d.pery || (yr >= 0 && yr < d.ny);
+                const bool ok = (d.pery || (yr >= 0 && yr < d.ny)) && ok2;
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const int c = 16 * wave + 4 * g + r, x = x0 - 2 + c;
-                    const bool ok = rowok && (d.perx || (x >= 0 && x < d.nx));
-                    split_store(h2, 0, c, 0, i, ok ? c2[r] : 0.f);
-                }
+                for (int r = 0; r < 4; r++) c2[r] = ok ? c2[r] : 0.f;
+                store_ch4(h2, SH2W, 16 * wave + i, g, c2);
                 c2 = f32x4{0.f, 0.f, 0.f, 0.f};
             }
-            // layer 3: h2 row s - 3; output row s - 5 completes in column 4
             {
-                T = shift_columns(T);
-                const unsigned short* src = sh2 + ((s - 3) & 1) * SH2W * 32 + (16 * wave + i) * 32 + 8 * g;
-#pragma unroll
-                for (int dx = 0; dx < 5; dx++) T = mfma(*reinterpret_cast<const us8*>(src + dx * 32), b3[dx], T);
                 const int y = s - 5;
                 if (i == 4 && y >= y0 && y < yend) {
 #pragma unroll
@@ -403,8 +455,9 @@ __global__ void __launch_bounds__(256) k_lf_stream(Planes P, const us8* __restri
                     }
                 }
             }
-            put_in(s + 4, next);
-            next = load_in(s + 5);
+            put_in(s + 4, q0[u]);
+            q0[u] = q1[u];
+            q1[u] = load_in(s + 14);
             __syncthreads();
         }
     }
@@ -482,11 +535,30 @@ void forward_fused(const View* in, const View* out, const Domain* d, int nplanes
         ny = std::max(ny, d[k].ny);
         nimg = std::max(nimg, d[k].nimg);
     }
-    // rows per workgroup: the tallest strip that still gives about four workgroups per CU
+    // rows per workgroup: each workgroup also walks 10 rows of reach (rounded up to 5), so take
+    // the height for which (rounds of resident workgroups) x (rows walked) is least
+    static int slots = 0;
+    if (!slots) {
+        int dev = 0, cus = 0, occ = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_lf_stream, 256, 0) != hipSuccess ||
+            occ < 1)
+            occ = 1;
+        slots = occ * cus;
+    }
     const long cols = (long)((nx + SOW - 1) / SOW) * nimg * nplanes;
     int oh = 16;
-    for (int c : {128, 96, 64, 48, 32, 24}) {
-        if (cols * ((ny + c - 1) / c) >= 1024) { oh = c; break; }
+    double best = 1e300;
+    for (int c = 16; c <= 512; c += 8) {
+        const long wg = cols * ((ny + c - 1) / c);
+        const double t = (double)((wg + slots - 1) / slots) * ((c + 14) / 5 * 5);
+        if (t < best * (1.0 - 1e-9)) {
+            best = t;
+            oh = c;
+        }
+        if (c >= ny) break;
     }
     P.oh = oh;
     const dim3 grid((nx + SOW - 1) / SOW, (ny + oh - 1) / oh, nimg * nplanes);
