@@ -318,7 +318,9 @@ void bf_destroy(bf_sim* sim);
    (each run follows Sec. 2-4 on its own).  Faraday, the electron push and Ampere are each one
    persistent launch over a device queue of (run, work item) pairs; the other phases (stations,
    rigid ions, antenna, current filter, window shift, injection, sort) are each run's own
-   launches, in phase order.  Results equal each run's
+   launches, in phase order, spread over the batch stream and three side streams the batch
+   owns (run r on stream r % 4, joined back before each persistent launch).  Results equal each
+   run's
    bf_step up to the order of floating-point atomic additions.  Runs must be FP32 handles on
    the current device without a sticky error; phase timers are not recorded in batched steps. */
 typedef struct bf_batch bf_batch;
@@ -331,7 +333,7 @@ int64_t bf_batch_work_bytes(int nsims);
    of the batched launches (NULL: default).  BF_EINVAL: bad arguments or a repeated handle;
    BF_EUNSUPPORTED: an FP64 or 3D handle, or one with the momentum-conserving gather, Vay's
    pusher or a beam capacity; BF_ESTATE: a handle with a sticky error;
-   BF_EDEVICE: pinned staging memory could not be allocated. */
+   BF_EDEVICE: pinned staging memory, the side streams or their events could not be created. */
 bf_status bf_batch_create(bf_sim* const* sims, int n, void* work, int64_t work_bytes,
                           void* hip_stream, bf_batch** out);
 
@@ -340,7 +342,7 @@ bf_status bf_batch_create(bf_sim* const* sims, int n, void* work, int64_t work_b
    or lacks its learned-filter parameters. */
 bf_status bf_batch_step(bf_batch* batch, int nsteps);
 
-/* Frees the batch's host resources (not the runs, not the work buffer). */
+/* Frees the batch's host resources and side streams (not the runs, not the work buffer). */
 void bf_batch_destroy(bf_batch* batch);
 
 /* ---- learned current filter ---------------------------------------------------------------

@@ -3,6 +3,7 @@
 // over a device work queue (the other phases run as the runs' own launches, in phase order).
 #pragma once
 #include <functional>
+#include <utility>
 #include <vector>
 #include "bf_kernels.h"
 
@@ -20,7 +21,8 @@ struct BatchRec {
     std::vector<GpdDesc<float>> gpd;
     // work items of each descriptor (cell blocks or particle segments)
     std::vector<int> n_faraday, n_ampere, n_gpd;
-    std::vector<std::function<void(hipStream_t)>> slots[SLOT_COUNT];
+    // each run's own launches by phase slot, with the run's index in the batch
+    std::vector<std::pair<int, std::function<void(hipStream_t)>>> slots[SLOT_COUNT];
 
     void clear()
     {

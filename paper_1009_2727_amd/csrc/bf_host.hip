@@ -256,11 +256,11 @@ struct bf_sim {
     }
     // batched execution: while rec is set, launches are gathered into rec's phase slots
     BatchRec* rec = nullptr;
-    int slot = 0;
+    int slot = 0, rec_run = 0;
     template <class F>
     void run(F&& f)
     {
-        if (rec) rec->slots[slot].emplace_back(std::forward<F>(f));
+        if (rec) rec->slots[slot].emplace_back(rec_run, std::forward<F>(f));
         else f(stream);
     }
 
@@ -1988,6 +1988,7 @@ bf_status bf_step(bf_sim* s, int nsteps)
 namespace {
 
 constexpr int BATCH_RING = 4;   // descriptor tables in flight
+constexpr int BATCH_LANES = 4;  // streams the runs' own launches are spread over
 
 size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -2012,6 +2013,10 @@ struct bf_batch {
     hipEvent_t ev[BATCH_RING] = {};
     bool used[BATCH_RING] = {};
     hipEvent_t join = nullptr;
+    // the runs' own launches between two batched launches go to BATCH_LANES lanes (the batch
+    // stream and side streams at the default priority), run r on lane r % BATCH_LANES
+    hipStream_t side[BATCH_LANES - 1] = {};
+    hipEvent_t fork = nullptr, lane_done[BATCH_LANES - 1] = {};
     int ring = 0, cus = 256;
     BatchRec rec;
     ~bf_batch()
@@ -2021,6 +2026,11 @@ struct bf_batch {
             if (ev[r]) (void)hipEventDestroy(ev[r]);
         }
         if (join) (void)hipEventDestroy(join);
+        if (fork) (void)hipEventDestroy(fork);
+        for (int k = 0; k < BATCH_LANES - 1; k++) {
+            if (lane_done[k]) (void)hipEventDestroy(lane_done[k]);
+            if (side[k]) (void)hipStreamDestroy(side[k]);
+        }
     }
 };
 
@@ -2049,8 +2059,10 @@ bf_status batch_one_step(bf_batch* b)
 {
     BatchRec& rec = b->rec;
     rec.clear();
-    for (bf_sim* s : b->sims) {
+    for (size_t q = 0; q < b->sims.size(); q++) {
+        bf_sim* s = b->sims[q];
         s->rec = &rec;
+        s->rec_run = (int)q;
         const bf_status st = step_impl<float>(s, 1);
         s->rec = nullptr;
         if (st != BF_OK) return st;
@@ -2072,19 +2084,33 @@ bf_status batch_one_step(bf_batch* b)
     hipStream_t st = b->stream;
     if (hipMemcpyAsync(Dv, H, o, hipMemcpyHostToDevice, st) != hipSuccess) return BF_EDEVICE;
     auto grid = [&](const QueueRef& q, int per_cu) { return std::max(1, std::min(q.total, per_cu * b->cus)); };
-    auto closures = [&](int slot) { for (auto& fn : rec.slots[slot]) fn(st); };
+    // the runs' own launches of consecutive slots, run r on lane r % BATCH_LANES: the lanes
+    // start after the batch stream's last launch and the batch stream waits for all of them,
+    // so each run's launches keep their order and the runs overlap one another
+    bool ok = true;
+    auto closures = [&](std::initializer_list<int> slots) {
+        size_t n = 0;
+        for (int sl : slots) n += rec.slots[sl].size();
+        if (n == 0) return;
+        ok = ok && hipEventRecord(b->fork, st) == hipSuccess;
+        for (int k = 0; k < BATCH_LANES - 1; k++) ok = ok && hipStreamWaitEvent(b->side[k], b->fork, 0) == hipSuccess;
+        for (int sl : slots)
+            for (auto& rf : rec.slots[sl]) {
+                const int lane = rf.first % BATCH_LANES;
+                rf.second(lane == 0 ? st : b->side[lane - 1]);
+            }
+        for (int k = 0; k < BATCH_LANES - 1; k++) {
+            ok = ok && hipEventRecord(b->lane_done[k], b->side[k]) == hipSuccess;
+            ok = ok && hipStreamWaitEvent(st, b->lane_done[k], 0) == hipSuccess;
+        }
+    };
     launch_faraday_batch<float>(dfar, qf, grid(qf, 8), st);
-    closures(SLOT_FARADAY);
-    closures(SLOT_STATIONS);
+    closures({SLOT_FARADAY, SLOT_STATIONS});
     launch_gpd_batch<float>(dgpd, qg, grid(qg, 3), st);
-    closures(SLOT_PUSH);
-    closures(SLOT_IONS);
-    closures(SLOT_ANTENNA);
-    closures(SLOT_FILTER);
+    closures({SLOT_PUSH, SLOT_IONS, SLOT_ANTENNA, SLOT_FILTER});
     launch_ampere_batch<float>(damp, qa, grid(qa, 8), st);
-    closures(SLOT_AMPERE);
-    closures(SLOT_WINDOW);
-    closures(SLOT_SORT);
+    closures({SLOT_AMPERE, SLOT_WINDOW, SLOT_SORT});
+    if (!ok) return BF_EDEVICE;
     if (hipEventRecord(b->ev[r], st) != hipSuccess) return BF_EDEVICE;
     b->used[r] = true;
     return hipGetLastError() == hipSuccess ? BF_OK : BF_EDEVICE;
@@ -2124,7 +2150,11 @@ bf_status bf_batch_create(bf_sim* const* sims, int n, void* work, int64_t work_b
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
         b->cus = cus;
-    bool ok = hipEventCreateWithFlags(&b->join, hipEventDisableTiming) == hipSuccess;
+    bool ok = hipEventCreateWithFlags(&b->join, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; ok && k < BATCH_LANES - 1; k++)
+        ok = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&b->lane_done[k], hipEventDisableTiming) == hipSuccess;
     for (int r = 0; ok && r < BATCH_RING; r++) {
         ok = hipHostMalloc(reinterpret_cast<void**>(&b->host[r]), b->table, hipHostMallocDefault) == hipSuccess &&
              hipEventCreateWithFlags(&b->ev[r], hipEventDisableTiming) == hipSuccess;
