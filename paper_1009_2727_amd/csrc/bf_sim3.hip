@@ -1088,13 +1088,27 @@ __device__ __forceinline__ void deposit_box_z(const BoxL<R>& bx, double x, doubl
         }
 }
 
+// box cell (a, b, c) of linear index q = a + ext0 (b + ext1 c), by float reciprocals: q stays below
+// 2^16 and the quotients below 64, so (q + 1/2) / d is at least 1/(2 d) from an integer and the
+// float product lands on the right side of it
+template <typename R>
+__device__ __forceinline__ void box_cell(const BoxL<R>& bx, int q, int& a, int& b, int& c)
+{
+    const int e0 = bx.ext[0], e01 = bx.ext[0] * bx.ext[1];
+    c = (int)(((float)q + 0.5f) * (1.0f / (float)e01));
+    const int r = q - c * e01;
+    b = (int)(((float)r + 0.5f) * (1.0f / (float)e0));
+    a = r - b * e0;
+}
+
 // stage the box: fields (electrons) and zeroed accumulators (nj planes)
 template <int NTH, typename R, bool FIELDS, bool MC = false>
 __device__ void stage_box(const G3& g, const F3<R>& f, const BoxL<R>& bx, int nj)
 {
     const int L = bx.ext[0] * bx.ext[1] * bx.ext[2];
     for (int q = threadIdx.x; q < L; q += NTH) {
-        const int a = q % bx.ext[0], b = (q / bx.ext[0]) % bx.ext[1], c = q / (bx.ext[0] * bx.ext[1]);
+        int a, b, c;
+        box_cell(bx, q, a, b, c);
         const int t = a + BPX * b + BPL * c;
         if constexpr (FIELDS) {
             const int si = sidx(g, 0, bx.lo[0] + a), sj = sidx(g, 1, bx.lo[1] + b), sk = sidx(g, 2, bx.lo[2] + c);
@@ -1125,7 +1139,8 @@ __device__ void flush_box(const G3& g, const F3<R>& f, const BoxL<R>& bx, int c0
 {
     const int L = bx.ext[0] * bx.ext[1] * bx.ext[2];
     for (int q = threadIdx.x; q < L; q += NTH) {
-        const int a = q % bx.ext[0], b = (q / bx.ext[0]) % bx.ext[1], c = q / (bx.ext[0] * bx.ext[1]);
+        int a, b, c;
+        box_cell(bx, q, a, b, c);
         const int si = sidx(g, 0, bx.lo[0] + a), sj = sidx(g, 1, bx.lo[1] + b), sk = sidx(g, 2, bx.lo[2] + c);
         if (si < 0 || sj < 0 || sk < 0) continue;
         const long o = o3(g, si, sj, sk);
