@@ -949,11 +949,12 @@ void layout3(const bf_config* c, Sim3* L)
     L->i_bytes = std::max<size_t>(o, 256);
     L->nst_max = std::max(c->max_stations, 0);
     L->stcap = std::max(c->station_capacity, 1);
-    // particle tiles: t x t transverse (the LDS box pitch leaves room for the stencil reach and
+    // particle tiles: tx x ty transverse (the LDS box pitches leave room for the stencil reach and
     // one cell of spread) by tz cells along z
-    const int tt = std::min(std::max(c->tile_x > 0 ? c->tile_x : 8, 1), std::min(bf3::BOX_PX, bf3::BOX_PY) - 6);
+    const int tx = std::min(std::max(c->tile_x > 0 ? c->tile_x : 16, 1), bf3::BOX_PX - 8);
+    const int ty = std::max(1, std::min(4, bf3::BOX_PY - 6));
     const int tz = std::max(c->tile_z > 0 ? c->tile_z : (real == 4 ? 7 : 2), 1);
-    const int tv[3] = {tt, tt, tz};
+    const int tv[3] = {tx, ty, tz};
     L->tl.ntiles = 1;
     for (int a = 0; a < 3; a++) {
         L->tl.t[a] = tv[a];

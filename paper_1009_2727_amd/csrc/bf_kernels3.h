@@ -75,11 +75,11 @@ struct Tiles3 { int t[3]; int nt[3]; int ntiles; };
 // LDS box of the particle kernels: a segment's cell box widened by the stencil reach (2 cells
 // below, 3 above) must fit BOX_PX x BOX_PY cells transversely and the run's plane count in z.
 // Planes are BOX_PL cells apart.  The 8-byte LDS adds of the deposit are served 16 lanes at a
-// time, two lanes conflicting when their word indices agree mod 16: with an x pitch of 16 the
-// two 8-cell rows of a quarter-wave share their eight slots (a 2-way conflict, about a fifth
-// slower), and the plane stride of 8 (mod 16) moves a lane whose stencil starts one plane lower
-// (a z face crossed, or a z-staggered component's lower half cell) onto the other eight.
-constexpr int BOX_PX = 16, BOX_PY = 14, BOX_PL = BOX_PX * BOX_PY + 8;
+// time, two lanes conflicting when their word indices agree mod 16.  The particle tiles are 16
+// cells wide in x, so a quarter-wave (one row of 16 cells of a lattice-ordered wave) adds to 16
+// distinct slots, and the plane stride of 0 (mod 16) keeps a lane whose stencil starts one plane
+// lower (a z face crossed, or a z-staggered component's lower half cell) on its own slot.
+constexpr int BOX_PX = 24, BOX_PY = 10, BOX_PL = BOX_PX * BOX_PY;
 // LDS bytes per box cell of the electron kernel: 6 field components in the run's type and 3
 // current accumulators of 8 bytes
 template <typename R> constexpr int box_cell_bytes() { return 6 * (int)sizeof(R) + 24; }
