@@ -34,9 +34,11 @@ __device__ __forceinline__ double block_sum(double v, double* red)
 }
 
 // ---- accessors ---------------------------------------------------------------------------
-// The staged tile has a fixed odd row pitch, so every stencil offset is a compile-time
-// immediate of the LDS instruction and rows of one column fall in different banks.
-constexpr int TPX = 33;                 // row pitch of the staged tile (cells)
+// The staged tile has a fixed row pitch, so every stencil offset is a compile-time immediate of
+// the LDS instruction.  The 8-byte current adds are served 16 lanes at a time, two lanes
+// conflicting when their word indices agree mod 16; a pitch of 0 (mod 16) keeps a lane whose
+// stencil starts one row lower (a z face crossed in the step) on the slot of its column.
+constexpr int TPX = 32;                 // row pitch of the staged tile (cells)
 // rows of the staged tile: 6 field planes + 3 FP64 current planes stay under 64 KB
 template <typename R> constexpr int trows() { return sizeof(R) == 4 ? 31 : 21; }
 template <typename R> constexpr int tcells() { return TPX * trows<R>(); }
