@@ -912,7 +912,7 @@ __device__ __forceinline__ R rsq(R x)
 // in HBM.
 
 constexpr int GT = 768;        // threads of an electron segment workgroup
-constexpr int GTI = 512;       // threads of an ion segment workgroup
+constexpr int GTI = 256;       // threads of an ion segment workgroup
 constexpr int HBM_GRID = 1024; // workgroups of the pass over the particles left to HBM
 constexpr int BPX = BOX_PX, BPY = BOX_PY, BPL = BOX_PL;
 
