@@ -2,9 +2,10 @@
 
 * Pairs (raw current, current after the 4-pass + compensation bilinear filter of Sec. 4.1) come
   from the method itself: GPU runs read back J_r (deposited) and J (filtered) after a step.
-* A spectral term: band-limited random patches whose spectrum lies in the high-k band where the
-  numerical instabilities of Sec. 4 grow; their targets are the bilinear filter's output, and
-  their weight sets how strongly the learned gain is held to the plain one in that band.
+* A spectral term: random patches whose power spectrum is the growth spectrum measured in
+  unfiltered unstable runs (the band where the numerical instabilities of Sec. 4 grow), or a flat
+  high-k band; their targets are the bilinear filter's output, so the learned gain is held to the
+  plain one where the instabilities grow, weighted by how fast they grow there.
 * Training is Adam through the library's MFMA kernels (LearnedFilter.train_step).
 * Evaluation: the learned transfer function against the plain one, the growth rate of the
   high-k field energy in an unstable run, and the on-axis wake field against a reference.
@@ -49,14 +50,72 @@ def current_pairs(workload, steps, every, per_component=48, seed=0, patch=PATCH,
     return np.asarray(xs, np.float32), np.asarray(ys, np.float32)
 
 
-def band_probes(n, kmin_frac=0.5, seed=1, patch=PATCH):
-    """Random patches with all their energy at |k| > kmin_frac * pi (grid units), and the
-    bilinear filter's output on them (computed with the exact factorisation on the device)."""
+def training_set(runs, n_total, seed=0, patch=PATCH):
+    """Patch pairs from several runs: `runs` is a list of (workload, steps, every); each run is
+    asked for about n_total / len(runs) pairs from its non-zero current components (patches with
+    no current at all are dropped, so a short harvest is cut again with more patches per frame),
+    and the union is cut to exactly n_total pairs at random (seeded).  Returns (inputs, targets,
+    pairs per run)."""
+    scale = 1.05
+    for _ in range(4):
+        xs, ys, per_run = [], [], []
+        for r, (w, steps, every) in enumerate(runs):
+            frames = steps // every
+            comps = 3 - sum(1 for c in "xyz" if _zero_component(w, c))
+            per = int(np.ceil(scale * n_total / (len(runs) * frames * comps)))
+            x, y = current_pairs(w, steps, every, per_component=per, seed=seed + 7919 * r, patch=patch)
+            xs.append(x)
+            ys.append(y)
+            per_run.append(len(x))
+        X, Y = np.concatenate(xs), np.concatenate(ys)
+        if len(X) >= n_total:
+            break
+        scale *= 1.1 * n_total / max(len(X), 1)
+    if len(X) < n_total:
+        raise RuntimeError(f"{len(X)} pairs from the runs, fewer than {n_total}")
+    keep = np.sort(np.random.default_rng(seed).choice(len(X), n_total, replace=False))
+    return X[keep], Y[keep], per_run
+
+
+def _zero_component(workload, c):
+    """True for the current component a 2D run never deposits: J_y without a y-polarised laser
+    (no force along y acts on particles that start with u_y = 0)."""
+    las = workload.get("laser")
+    return c == "y" and (las is None or las.get("pol", 0) == 0)
+
+
+def patch_spectrum(field, patch=PATCH):
+    """Mean power spectrum |F(k)|^2 of the non-overlapping patch x patch windows of a 2D field,
+    on the patch's own frequency grid (numpy FFT order)."""
+    nz, nx = field.shape
+    w = field[:nz - nz % patch, :nx - nx % patch].reshape(nz // patch, patch, nx // patch, patch)
+    return (np.abs(np.fft.fft2(w.transpose(0, 2, 1, 3))) ** 2).mean(axis=(0, 1))
+
+
+def growth_spectrum(workload, steps, early, field="Ez", patch=PATCH):
+    """Per-step growth rate of each patch mode of `field` in an unfiltered copy of `workload`:
+    ln(P_end(k) / P_early(k)) / (steps - early), negative rates clipped to zero."""
+    w = copy.deepcopy(workload)
+    w["config"]["filter_npass"], w["config"]["filter_compensate"] = 0, 0
+    sim = Sim.from_workload(w)
+    sim.step(early)
+    p0 = patch_spectrum(sim.field(field), patch)
+    sim.step(steps - early)
+    p1 = patch_spectrum(sim.field(field), patch)
+    tiny = 1e-300
+    return np.maximum(np.log((p1 + tiny) / (p0 + tiny)), 0.0) / (steps - early)
+
+
+def band_probes(n, kmin_frac=0.5, seed=1, patch=PATCH, weight=None):
+    """Random patches and the bilinear filter's output on them (computed with the exact
+    factorisation on the device).  weight None: all their energy at |k| > kmin_frac * pi (grid
+    units); else their power spectrum is `weight` (patch x patch, numpy FFT order)."""
     import torch
     rng = np.random.default_rng(seed)
     k = 2 * np.pi * np.fft.fftfreq(patch)
     kk = np.sqrt(k[:, None] ** 2 + k[None, :] ** 2)
-    x = np.fft.ifft2(np.fft.fft2(rng.normal(size=(n, patch, patch))) * (kk > kmin_frac * np.pi)).real
+    shape = (kk > kmin_frac * np.pi).astype(float) if weight is None else np.sqrt(np.asarray(weight, float))
+    x = np.fft.ifft2(np.fft.fft2(rng.normal(size=(n, patch, patch))) * shape).real
     x /= np.sqrt(np.mean(x * x, axis=(1, 2), keepdims=True))
     x = x.astype(np.float32)
     plain = LearnedFilter(bilinear_factor_params(4, True))
@@ -65,9 +124,10 @@ def band_probes(n, kmin_frac=0.5, seed=1, patch=PATCH):
 
 
 def train(inputs, targets, probes=None, probe_weight=1.0, params0=None, steps=2000, lr=2e-3,
-          batch=64, seed=2, log_every=0):
-    """Adam on the mean squared error of the patch pairs (plus the weighted probe pairs).
-    Returns (LearnedFilter, loss history)."""
+          batch=64, seed=2, log_every=0, lr_final=None):
+    """Adam on the mean squared error of the patch pairs (plus the weighted probe pairs); with
+    lr_final the step size falls from lr to lr_final along a half cosine.  Returns
+    (LearnedFilter, loss history)."""
     import torch
     rng = np.random.default_rng(seed)
     if params0 is None:
@@ -83,7 +143,8 @@ def train(inputs, targets, probes=None, probe_weight=1.0, params0=None, steps=20
     hist = []
     for it in range(steps):
         idx = torch.tensor(rng.integers(0, len(X), batch), device=lf.device)
-        loss, _ = lf.train_step(Xd[idx].contiguous(), Yd[idx].contiguous(), MARGIN, lr)
+        a = lr if lr_final is None else lr_final + 0.5 * (lr - lr_final) * (1 + np.cos(np.pi * it / steps))
+        loss, _ = lf.train_step(Xd[idx].contiguous(), Yd[idx].contiguous(), MARGIN, float(a))
         if log_every and it % log_every == 0:
             hist.append((it, float(loss.cpu())))
     return lf, hist
@@ -133,10 +194,10 @@ def highk_energy(field, frac=0.5):
     return float((np.abs(f[band]) ** 2).sum())
 
 
-def growth_rate(workload, params=None, steps=400, every=10, field="Ez"):
-    """Growth rate (per step) of the high-k energy of `field`: the slope of its logarithm over
-    the stretch where it grows steadily (least squares over the second half of the samples
-    above the noise floor).  params None: the workload's own filter."""
+def growth_rate(workload, params=None, steps=400, every=10, field="Ez", window=None):
+    """Growth rate (per step) of the high-k energy of `field`: the least-squares slope of its
+    logarithm over the samples at steps in `window` = (first, last), or over the second half of
+    the samples when no window is given.  params None: the workload's own filter."""
     w = copy.deepcopy(workload)
     if params is not None:
         w["config"]["filter_kind"] = FILTER_LEARNED
@@ -149,6 +210,16 @@ def growth_rate(workload, params=None, steps=400, every=10, field="Ez"):
         t.append(s)
         e.append(highk_energy(sim.field(field)))
     t, le = np.asarray(t, float), np.log(np.maximum(np.asarray(e), 1e-300))
-    h = len(t) // 2
-    slope = np.polyfit(t[h:], le[h:], 1)[0]
+    sel = (t >= window[0]) & (t <= window[1]) if window is not None else np.arange(len(t)) >= len(t) // 2
+    slope = np.polyfit(t[sel], le[sel], 1)[0]
     return float(slope), t, le
+
+
+def linear_phase(t, le, frac=0.8):
+    """The stretch of an unfiltered run's log high-k energy where the instability grows: from
+    the second sample (the first holds the start-up transient) to the first sample that has
+    covered `frac` of the rise from the minimum to the maximum (where saturation begins)."""
+    lo, hi = le.min(), le.max()
+    k1 = int(np.argmax(le >= lo + frac * (hi - lo)))
+    k1 = max(k1, 3)
+    return float(t[1]), float(t[k1])

@@ -176,6 +176,20 @@ def c5_growth(real="f32", nx=64, nz=512, ppc=4, gamma=13.0, n0=1e19, npass=4, co
     )
 
 
+def c5_growth_lab(real="f32", nx=64, nz=512, ppc=4, npass=4, comp=1, seed=1018):
+    """Lab-frame instability family: the wake family's laser-plasma run (0.05 um cells, 4 ppc at
+    1e19 cm^-3, a0 = 1, 10 fs) with the Cole-Karkkainen solver at 0.95 of its Courant limit
+    (c dt = 0.95 dz, where its Nyquist modes are nearly stationary, App. I) instead of Yee, 600
+    steps.  npass = 0: no filter."""
+    w = c1(real, nx=nx, nz=nz, ppc=ppc)
+    w["config"].update(make_config(nx, nz, 0.05, 0.05, pml_cells=10, periodic_x=1, ck="ck",
+                                   cfl_fraction=0.95, filter_npass=npass, filter_compensate=comp,
+                                   seed=seed, real=real))
+    w["name"] = f"lab-frame CK instability family {nx}x{nz}, {ppc} ppc"
+    w["steps"] = 600
+    return w
+
+
 def stage_10gev(real="f32", nx=128, nz=2048, ppc=4, gamma=130.0, cfl=0.7071, ck="ck", gather_kind=0,
                 seed=1017):
     """A full-scale 10 GeV class stage in the wake frame (Sec. 5.2, 5.3): lab density 1e17 cm^-3
