@@ -415,7 +415,24 @@ __device__ __forceinline__ void gpd_segment(const Geo& g, const FieldSet<R>& f, 
     constexpr int TCELLS = tcells<R>();
     using JT = typename LdsAcc<R>::JT;
     lds.j = reinterpret_cast<JT*>(lds.f + 6 * TCELLS);   // 6 TCELLS elements: 8-byte aligned
-    const bool use_lds = lds.lx <= TPX && lds.lz <= trows<R>();
+    // A box larger than the staged tile (particles spread since the last sort, as in a heated
+    // plasma) still stages the largest window, centred on the box, while each thread can
+    // remember which of its particles fall outside (at most 64 per thread); those are pushed with
+    // the global accessors after the tile is flushed.  Larger segments take the global accessors
+    // throughout.
+    const bool fits = lds.lx <= TPX && lds.lz <= trows<R>();
+    const bool use_lds = fits || sg.count <= 64 * NTHR;
+    if (!fits && use_lds) {
+        // a particle in cell ix fits while xb + 2 <= ix <= xb + lx - 4
+        if (lds.lx > TPX) {
+            lds.xb = ((bb.x + bb.y) >> 1) - 2 - (TPX - 6) / 2;
+            lds.lx = TPX;
+        }
+        if (lds.lz > trows<R>()) {
+            lds.zb = ((bb.z + bb.w) >> 1) - 2 - (trows<R>() - 6) / 2;
+            lds.lz = trows<R>();
+        }
+    }
     int x0 = INT_MAX, x1 = INT_MIN, z0 = INT_MAX, z1 = INT_MIN;
     const int end = sg.start + sg.count;
     const int L = lds.lx * lds.lz;
@@ -462,8 +479,9 @@ __device__ __forceinline__ void gpd_segment(const Geo& g, const FieldSet<R>& f, 
         int p = sg.start + threadIdx.x;
         EState<R> nxt{}, done{};
         int pdone = -1;
+        uint64_t late = 0;   // bit k: this thread's k-th particle lies outside the staged window
         if (p < end) nxt = load_electron(e, p);
-        for (; p < end; p += NTHR) {
+        for (int k = 0; p < end; p += NTHR, k++) {
             EState<R> cur = nxt;
             // the prefetched registers are taken here, before this iteration's stores and
             // loads are issued, so the wait for them covers only memory operations issued one
@@ -476,9 +494,13 @@ __device__ __forceinline__ void gpd_segment(const Geo& g, const FieldSet<R>& f, 
             if (cur.w == R(0)) continue;
             const int ix = (int)floor(cur.x), iz = (int)floor(cur.z);
             if (!lds.inside(ix - 2, ix + 3, iz - 2, iz + 3)) {
-                const int slot = atomicAdd(&nmisfit, 1);
-                if (slot < MISFIT_CAP) misfit[slot] = p;
-                else atomicOr(status, ST_SEGMENTS);
+                if (k < 64) {
+                    late |= 1ull << k;
+                } else {
+                    const int slot = atomicAdd(&nmisfit, 1);
+                    if (slot < MISFIT_CAP) misfit[slot] = p;
+                    else atomicOr(status, ST_SEGMENTS);
+                }
                 continue;
             }
             advance_electron<MC>(lds, g, pp, cur, js, status, x0, x1, z0, z1);
@@ -502,10 +524,18 @@ __device__ __forceinline__ void gpd_segment(const Geo& g, const FieldSet<R>& f, 
                 if (v != R(0)) atomicAdd(&f.J[c][o], v);
             }
         }
-        // particles outside the staged box (none for a consistent box): global accessors
+        // particles outside the staged window: global accessors
         const int nm = min(nmisfit, MISFIT_CAP);
-        if (nm > 0) {
+        if (nm > 0 || late) {
             const GlobAcc<R> glb = make_glob<MC>(g, f);
+            while (late) {
+                const int b = __builtin_ctzll(late);
+                late &= late - 1;
+                const int q = sg.start + threadIdx.x + b * NTHR;
+                EState<R> st = load_electron(e, q);
+                advance_electron<MC>(glb, g, pp, st, 1.0, status, x0, x1, z0, z1);
+                store_electron(e, q, st);
+            }
             for (int q = threadIdx.x; q < nm; q += NTHR) {
                 const int p = misfit[q];
                 EState<R> st = load_electron(e, p);

@@ -213,11 +213,15 @@ def test_random_state_single_step(real, tol):
 
 
 @gpu
-def test_global_memory_path_matches_oracle():
-    # tiles too large for the LDS budget: every segment takes the global-memory accessors
-    w = pi.small_lab(real="f64", nx=40, nz=100, ppc=4)
+@pytest.mark.parametrize("nx,ppc", [(40, 4), (64, 8)])
+def test_global_memory_path_matches_oracle(nx, ppc):
+    # tiles too large for the LDS budget.  40 x 64 cells at 4 ppc (10,240 particles, at most 64
+    # per thread): the largest window is staged and the particles outside it take the global
+    # accessors after the flush; 64 x 64 cells at 8 ppc (32,768): every particle of the segment
+    # takes the global accessors
+    w = pi.small_lab(real="f64", nx=nx, nz=100, ppc=ppc)
     from paper_1009_2727_amd import Sim
-    sim = Sim(w["config"], ppc=4, tile=(64, 64))
+    sim = Sim(w["config"], ppc=ppc, tile=(64, 64))
     sim.init_plasma(w["plasma"])
     sim.init_laser(w["laser"])
     ref = Oracle.from_workload(w)
@@ -225,6 +229,33 @@ def test_global_memory_path_matches_oracle():
     ref.step(25)
     compare_fields(sim, ref, 1e-11)
     compare_particles(sim, ref, 1e-9, 1e-9)
+
+
+@gpu
+@pytest.mark.parametrize("real,tol,xtol,utol", [("f64", 1e-11, 1e-9, 1e-9), ("f32", 1e-5, 2e-5, 1e-4)])
+def test_spread_segments_match_oracle(real, tol, xtol, utol):
+    # fast random electrons stepped 12 times with no sort after the load: each 26 x 24 tile's
+    # particles spread over more columns and rows than the staged tile holds, so the segments
+    # stage a window centred on their box and push the particles outside it with the global
+    # accessors
+    nx, nz = 37, 53
+    cfg = pi.make_config(nx, nz, 0.1, 0.13, periodic_x=1, periodic_z=1, pml_cells=0, ck="ck2",
+                         theta=0.3, filter_npass=2, filter_compensate=1, real=real, seed=6)
+    from paper_1009_2727_amd import Sim
+    sim = Sim(cfg, capacity=20000, tile=(26, 24), sort_every=1000)
+    ref = Oracle(cfg)
+    for k, name in enumerate(["Ex", "Ey", "Ez", "Bx", "By", "Bz", "Exo", "Eyo", "Ezo", "Exb", "Eyb", "Ezb"]):
+        f = pi.random_field(ref.shape, seed=300 + k, amp=0.2)
+        ref.set_field(name, f)
+        sim.set_field(name, f)
+    p = pi.random_electrons(6000, nx, nz, 0.1, 0.13, seed=12, umax=6.0, margin=0.0)
+    ref.set_electrons(p)
+    sim.load_electrons(p)
+    ref.step(12)
+    sim.step(12)
+    assert sim.sync_status() == 0
+    compare_fields(sim, ref, tol, tag=f"spread{real}")
+    compare_particles(sim, ref, xtol, utol)
 
 
 @gpu
