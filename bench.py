@@ -160,11 +160,18 @@ def timed_run(args, w, kernel_bytes, pmc_key, kernel_name):
     # the tile sort's cost: step on (untimed) to the next scheduled sort; the sort phase of that
     # step less the phase's empty bracket (the mean of the steps without a sort)
     sort_each = 0.0
+    # phase device time of the timed steps and of the steps after them up to and including the
+    # sort: the mean over (most of) a sort cycle, beside the window's figure
+    cyc_ms = sum(v[0] for v in timers.values())
+    cyc_push, cyc_n = timers["push"][0], args.steps
     if not args.no_sort_cost:
         idle = []
         for _ in range(every + 1):
             sim.step(1)
             tm = sim.timers(reset=True)
+            cyc_ms += sum(v[0] for v in tm.values())
+            cyc_push += tm["push"][0]
+            cyc_n += 1
             if sim.get_state().since_sort == 0:
                 sort_each = tm["sort"][0] - (float(np.mean(idle)) if idle else 0.0)
                 break
@@ -183,6 +190,9 @@ def timed_run(args, w, kernel_bytes, pmc_key, kernel_name):
         "value": ne * args.steps / (ms_amort / 1e3), "ms_per_step": ms_amort / args.steps,
         "window_ms_per_step": ms / args.steps, "sort_ms": sort_each, "sort_every": every,
         "sorts_in_window": int(in_window), "electrons": int(ne), "rigid_ions": int(ni), "status": status,
+        "sort_cycle": {"steps": cyc_n, "first_step_after_sort": int(since0) + 1,
+                       "phase_ms_per_step": cyc_ms / cyc_n, "push_ms_per_step": cyc_push / cyc_n,
+                       "window_phase_ms_per_step": sum(v[0] for v in timers.values()) / max(args.steps, 1)},
         "hbm_gbps_per_step": step_bytes / (ms_amort / args.steps / 1e3) / 1e9,
         "phases_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in timers.items()},
         "roofline": {"bound": "hbm", "kernel": kernel_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -202,7 +212,7 @@ def _line(args, w, r, grid, ppc, extra_cfg):
                         "electrons": r["electrons"], "rigid_ions": r["rigid_ions"], "positions": "f64",
                         "sort_every": r["sort_every"], "status": r["status"]}, **extra_cfg),
         "window_ms_per_step": r["window_ms_per_step"], "sort_ms": r["sort_ms"],
-        "sorts_in_window": r["sorts_in_window"],
+        "sorts_in_window": r["sorts_in_window"], "sort_cycle": r["sort_cycle"],
         "hbm_gbps_per_step": r["hbm_gbps_per_step"], "phases_ms_per_step": r["phases_ms_per_step"],
         "roofline": r["roofline"],
     }
