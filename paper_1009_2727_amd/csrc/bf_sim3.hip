@@ -1436,10 +1436,27 @@ __global__ void __launch_bounds__(GTI) k3_gpi(G3 g, F3<R> f, I3<R> ion, const Se
             stage_box<GTI, R, false>(g, f, bx, 1);
             __syncthreads();
         }
-        for (int p = sg.start + threadIdx.x; p < end; p += GTI) {
-            const R w = ion.w[p];
+        // the next ion's state is loaded while the current one deposits, so each iteration
+        // waits only for loads issued an iteration earlier
+        int p = sg.start + threadIdx.x;
+        R wq = R(0);
+        double xq = 0.0, yq = 0.0, zq = 0.0;
+        if (p < end) {
+            wq = ion.w[p];
+            xq = ion.x[p];
+            yq = ion.y[p];
+            zq = ion.z0[p];
+        }
+        for (; p < end; p += GTI) {
+            const R w = wq;
+            const double x = xq, y = yq, z0 = zq;
+            if (p + GTI < end) {
+                wq = ion.w[p + GTI];
+                xq = ion.x[p + GTI];
+                yq = ion.y[p + GTI];
+                zq = ion.z0[p + GTI];
+            }
             if (w == R(0)) continue;
-            const double x = ion.x[p], y = ion.y[p], z0 = ion.z0[p];
             const double r0[3] = {x, y, z0 - zsa}, r1[3] = {x, y, z0 - zsb};
             const double kz = -pp.jk[2] * (double)w;
             if (lds && in_box(bx, r0)) {
