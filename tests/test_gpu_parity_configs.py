@@ -21,6 +21,9 @@ antenna-sheet current density), the measure of the other parity tests.
     of the streaming plasma's currents covers the whole box while the signal (the laser still
     entering, the wake starting) is local, so the L2 ratio measures the box size, not the
     error per cell.
+  * the same physics on a 32 x 4096 window at 1 ppc for 2000 steps: the largest on-axis E_z
+    and the field and kinetic energies every 100 steps (FP64 within 1e-6 throughout; FP32
+    within 1% and 2% over the first 1000 steps).
   * a 128 x 128 x 128 slab of the 3D boosted run (gamma = 30, 8 ppc pre-loaded, 16.8 M
     electrons + rigid ions, default tiles and sort cadence): after a full step from the shared
     loading, the raw current, the filtered current, E after Ampere and B, FP32, <= 1e-5 of the
@@ -162,6 +165,65 @@ def test_boosted_256x4096_100_steps():
     _say(json.dumps(_LOG["boosted_256x4096_100"]))
     assert max(e64.values()) <= 1e-6, e64
     assert max(m32.values()) <= 1e-4, m32
+
+
+# ---------------------------------------------------------------------------------------
+# 2D boosted, long horizon: integral quantities over 2000 steps
+# ---------------------------------------------------------------------------------------
+
+def _highk(f):
+    """sum of |E(k)|^2 over |k| > half the grid's Nyquist wavenumber"""
+    F = np.fft.fft2(f)
+    kz = np.fft.fftfreq(f.shape[0])[:, None]
+    kx = np.fft.fftfreq(f.shape[1])[None, :]
+    return float((np.abs(F[np.sqrt(kx ** 2 + kz ** 2) > 0.25]) ** 2).sum())
+
+
+@gpu
+@pytest.mark.timeout(900)
+def test_boosted_long_horizon_peak_wake_and_energy():
+    """The 2D boosted run's physics (gamma = 13, 1e18 cm^-3 pre-loaded, a0 = 2, CK2 + Friedman
+    0.1, 4 passes + compensation, PML on every face, moving window) on a 32 x 4096 window at 1
+    ppc (131 k electrons + rigid ions), 2000 steps, against the FP64 oracle on the largest
+    on-axis |E_z| so far and the field (E, B) and kinetic energies, every 100 steps.
+      * FP64 GPU: within 1e-6 over all 2000 steps (summation order only).
+      * FP32 GPU: the peak within 1% and the energies within 2% over the first 1000 steps.  Past
+        about 1100 steps the high-k part of E_z, which grows in both runs from its rounding
+        floor, is larger in FP32 (its floor is higher) and carries a growing share of the field
+        energy, so the energies part by tens of percent; those steps are logged, not bounded.
+    Pointwise fields are not compared (the nonlinear a0 = 2 wake amplifies rounding)."""
+    steps, every, fp32_until = 2000, 100, 1000
+    runs = {r: _sim(pi.c2(real=r, nx=32, nz=4096, ppc=1, preload=True), sort_every=80)
+            for r in ("f32", "f64")}
+    oracle.set_threads(oracle.host_threads())
+    ref = Oracle.from_workload(pi.c2(real="f64", nx=32, nz=4096, ppc=1, preload=True))
+    axis = 16 + ref.info()["pml_x"]
+    peak = {"f32": 0.0, "f64": 0.0, "oracle": 0.0}
+    rows = []
+    for k in range(steps // every):
+        ref.step(every)
+        b = ref.field("Ez")
+        peak["oracle"] = max(peak["oracle"], float(np.abs(b[:, axis]).max()))
+        eb = ref.energy()
+        row = {"step": (k + 1) * every, "oracle_energy": [float(x) for x in eb], "oracle_highk_ez": _highk(b)}
+        for r, sim in runs.items():
+            sim.step(every)
+            a = sim.field("Ez")
+            peak[r] = max(peak[r], float(np.abs(a[:, axis]).max()))
+            ea = sim.energy()
+            row[r] = {"energy_rel_diff": [float(abs(x - y) / abs(y)) for x, y in zip(ea, eb)],
+                      "peak_ez_rel_diff": abs(peak[r] - peak["oracle"]) / peak["oracle"],
+                      "highk_ez": _highk(a)}
+        rows.append(row)
+        _say(json.dumps(row))
+    for sim in runs.values():
+        assert sim.sync_status() == 0
+    _LOG["boosted_32x4096_2000_steps"] = rows
+    early = [r for r in rows if r["step"] <= fp32_until]
+    assert max(r["f64"]["peak_ez_rel_diff"] for r in rows) <= 1e-6
+    assert max(max(r["f64"]["energy_rel_diff"]) for r in rows) <= 1e-6
+    assert max(r["f32"]["peak_ez_rel_diff"] for r in early) <= 0.01
+    assert max(max(r["f32"]["energy_rel_diff"]) for r in early) <= 0.02
 
 
 # ---------------------------------------------------------------------------------------
