@@ -70,7 +70,9 @@ def training_set(runs, n_total, seed=0, patch=PATCH):
         X, Y = np.concatenate(xs), np.concatenate(ys)
         if len(X) >= n_total:
             break
-        scale *= 1.1 * n_total / max(len(X), 1)
+        if len(X) == 0:
+            raise RuntimeError("the runs deposited no current: no patch pairs to cut")
+        scale *= 1.1 * n_total / len(X)
     if len(X) < n_total:
         raise RuntimeError(f"{len(X)} pairs from the runs, fewer than {n_total}")
     keep = np.sort(np.random.default_rng(seed).choice(len(X), n_total, replace=False))
