@@ -1405,9 +1405,11 @@ __global__ void __launch_bounds__(NT) k3_gpd_hbm(G3 g, F3<R> f, E3<R> e, const S
     }
 }
 
-// rigid ions (q = +1): z(t) = z0 - (beta t / dz + shift), J_z only
+// rigid ions (q = +1): z(t) = z0 - (beta t / dz + shift), J_z only.  Bounded to four waves per
+// SIMD (four 256-thread workgroups per CU, at most 128 VGPRs): the extra workgroup hides more of
+// the HBM latency of the ion loads than the few spilled registers cost.
 template <typename R>
-__global__ void __launch_bounds__(GTI) k3_gpi(G3 g, F3<R> f, I3<R> ion, const Seg3* __restrict__ seg,
+__global__ void __launch_bounds__(GTI, 4) k3_gpi(G3 g, F3<R> f, I3<R> ion, const Seg3* __restrict__ seg,
                                              const Box3* __restrict__ bin, Box3* __restrict__ bout, double zsa,
                                              double zsb, double zsn, Push3 pp, int pz)
 {
