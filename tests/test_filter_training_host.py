@@ -44,3 +44,23 @@ def test_lab_growth_family_is_the_wake_run_on_the_ck_solver():
     for k in ("nx", "nz", "dx_um", "dz_um", "cfl_fraction", "gamma_boost", "filter_npass"):
         assert g["config"][k] == w["config"][k], k
     assert g["plasma"] == w["plasma"] and g["laser"] == w["laser"] and g["steps"] == 600
+
+
+def test_linear_phase_ends_where_the_log_rise_saturates():
+    # exponential growth at 0.08 per step from step 20 to 320, then flat: the window starts at the
+    # second sample and ends at the first sample past 80% of the rise
+    t = np.arange(20.0, 601.0, 20.0)
+    le = np.where(t <= 320, -9.0 + 0.08 * (t - 20), -9.0 + 0.08 * 300)
+    lo, hi = ft.linear_phase(t, le)
+    assert lo == t[1]
+    rise = 0.08 * 300
+    first = t[np.argmax(le >= le.min() + 0.8 * rise)]
+    assert hi == first and 240.0 <= hi <= 320.0
+    sel = (t >= lo) & (t <= hi)
+    np.testing.assert_allclose(np.polyfit(t[sel], le[sel], 1)[0], 0.08, rtol=1e-12)
+
+
+def test_linear_phase_of_a_flat_record_keeps_a_minimal_window():
+    t = np.arange(20.0, 201.0, 20.0)
+    lo, hi = ft.linear_phase(t, np.full(t.shape, 3.0))
+    assert lo == t[1] and hi == t[3]
