@@ -24,6 +24,8 @@ antenna-sheet current density), the measure of the other parity tests.
   * the same physics on a 32 x 4096 window at 1 ppc for 2000 steps: the largest on-axis E_z
     and the field and kinetic energies every 100 steps (FP64 within 1e-6 throughout; FP32
     within 1% and 2% over the first 1000 steps).
+  * the 3D boosted physics on a 16 x 16 x 128 box at 2 ppc for 400 steps: FP64 within 1e-6 on
+    the peak on-axis E_z and the energies, FP32 within 1e-4 on the kinetic energy.
   * a 128 x 128 x 128 slab of the 3D boosted run (gamma = 30, 8 ppc pre-loaded, 16.8 M
     electrons + rigid ions, default tiles and sort cadence): after a full step from the shared
     loading, the raw current, the filtered current, E after Ampere and B, FP32, <= 1e-5 of the
@@ -224,6 +226,46 @@ def test_boosted_long_horizon_peak_wake_and_energy():
     assert max(max(r["f64"]["energy_rel_diff"]) for r in rows) <= 1e-6
     assert max(r["f32"]["peak_ez_rel_diff"] for r in early) <= 0.01
     assert max(max(r["f32"]["energy_rel_diff"]) for r in early) <= 0.02
+
+
+@gpu
+@pytest.mark.timeout(900)
+def test_3d_boosted_long_horizon_peak_wake_and_energy():
+    """The 3D boosted run's physics (gamma = 30, window pre-loaded, a0 = 2 with the waist scaled to
+    the box, CK2 + Friedman 0.1, 4 passes + compensation, PML on every face, rigid ions) on a
+    16 x 16 x 128 box at 2 ppc, 400 steps, against the FP64 oracle every 50 steps: the largest
+    on-axis |E_z| so far and the E, B and kinetic energies.
+      * FP64 GPU: everything within 1e-6.
+      * FP32 GPU: the kinetic energy within 1e-4.  In a box this small the field energy is about
+        1e-6 of the kinetic one, the particle noise of the streaming plasma, and FP32 rounding
+        changes it by a few percent (logged, not bounded), as it does the on-axis peak."""
+    from oracle.pic3 import Oracle3
+    steps, every = 400, 50
+    runs = {r: _sim(pi.small_boosted3(real=r, nx=16, ny=16, nz=128, ppc=2, preload=True)) for r in ("f32", "f64")}
+    oracle.set_threads(oracle.host_threads())
+    ref = Oracle3.from_workload(pi.small_boosted3(real="f64", nx=16, ny=16, nz=128, ppc=2, preload=True))
+    p = ref.info()["pml_x"]
+    peak = {"f32": 0.0, "f64": 0.0, "oracle": 0.0}
+    rows = []
+    for k in range(steps // every):
+        ref.step(every)
+        peak["oracle"] = max(peak["oracle"], float(np.abs(ref.field("Ez")[:, p + 8, p + 8]).max()))
+        eb = ref.energy()
+        row = {"step": (k + 1) * every, "oracle_energy": [float(x) for x in eb]}
+        for r, sim in runs.items():
+            sim.step(every)
+            peak[r] = max(peak[r], float(np.abs(sim.field("Ez")[:, p + 8, p + 8]).max()))
+            ea = sim.energy()
+            row[r] = {"energy_rel_diff": [float(abs(x - y) / abs(y)) for x, y in zip(ea, eb)],
+                      "peak_ez_rel_diff": abs(peak[r] - peak["oracle"]) / peak["oracle"]}
+        rows.append(row)
+        _say(json.dumps(row))
+    for sim in runs.values():
+        assert sim.sync_status() == 0
+    _LOG["boosted3d_16x16x128_400_steps"] = rows
+    assert max(r["f64"]["peak_ez_rel_diff"] for r in rows) <= 1e-6
+    assert max(max(r["f64"]["energy_rel_diff"]) for r in rows) <= 1e-6
+    assert max(r["f32"]["energy_rel_diff"][2] for r in rows) <= 1e-4
 
 
 # ---------------------------------------------------------------------------------------
